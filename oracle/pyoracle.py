@@ -1,0 +1,158 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+Wraps oracle/liboracle.so (plain C, FP64) and adds the closed-form checks
+written directly from their mathematical definitions.  Nothing here imports
+or calls the product library.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class OrGrid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("npml", C.c_int32), ("nt", C.c_int32),
+                ("dx", C.c_double), ("dt", C.c_double), ("pml_R", C.c_double),
+                ("pml_vmax", C.c_double), ("f0_pml", C.c_double)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        _LIB = C.CDLL(path)
+    return _LIB
+
+
+def grid(ndim=2, nx=1, ny=1, nz=1, npml=0, nt=1, dx=10.0, dt=1e-3,
+         pml_R=1e-3, pml_vmax=3000.0, f0_pml=10.0):
+    return OrGrid(ndim, nx, ny, nz, npml, nt, dx, dt, pml_R, pml_vmax, f0_pml)
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def ricker(f0, t0, dt, nt):
+    out = np.zeros(nt)
+    lib().or_ricker(C.c_double(f0), C.c_double(t0), C.c_double(dt), C.c_int32(nt), _d(out))
+    return out
+
+
+def stencil_weights():
+    l8, d8, s4 = np.zeros(5), np.zeros(5), np.zeros(2)
+    lib().or_stencil_weights(_d(l8), _d(d8), _d(s4))
+    return l8, d8, s4
+
+
+# ---------------------------------------------------------------- acoustic 2-D
+def ac2_pad(g, c):
+    P = g.npml
+    NX, NZ = g.nx + 2 * P, g.nz + 2 * P
+    cp, zx, zz = np.zeros((NZ, NX)), np.zeros(NX), np.zeros(NZ)
+    lib().or_ac2_pad(C.byref(g), _d(_f64(c)), _d(cp), _d(zx), _d(zz))
+    return cp, zx, zz
+
+
+def ac2_step(g, c_pad, X, src_idx=-1, src_val=0.0):
+    """X = (u, um, px, pz) padded arrays -> (Y tuple, w)."""
+    X = [_f64(x) for x in X]
+    Y = [np.zeros_like(X[0]) for _ in range(4)]
+    w = np.zeros_like(X[0])
+    lib().or_ac2_step(C.byref(g), _d(_f64(c_pad)), _d(X[0]), _d(X[1]), _d(X[2]), _d(X[3]),
+                      C.c_int64(src_idx), C.c_double(src_val),
+                      _d(Y[0]), _d(Y[1]), _d(Y[2]), _d(Y[3]), _d(w))
+    return Y, w
+
+
+def ac2_step_T(g, c_pad, X, aY, src_idx=-1):
+    X = [_f64(x) for x in X]
+    aY = [_f64(x) for x in aY]
+    aX = [np.zeros_like(X[0]) for _ in range(4)]
+    gC = np.zeros_like(X[0])
+    sb = C.c_double(0.0)
+    lib().or_ac2_step_T(C.byref(g), _d(_f64(c_pad)), _d(X[0]), _d(X[2]), _d(X[3]),
+                        _d(aY[0]), _d(aY[1]), _d(aY[2]), _d(aY[3]),
+                        _d(aX[0]), _d(aX[1]), _d(aX[2]), _d(aX[3]), _d(gC),
+                        C.c_int64(src_idx), C.byref(sb))
+    return aX, gC, sb.value
+
+
+def ac2_forward(g, c, src, wav, rec):
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    ns, nrec = src.shape[0], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    rc = lib().or_ac2_forward(C.byref(g), _d(_f64(c)), C.c_int32(ns), _i(src), _d(wav),
+                              C.c_int32(nrec), _i(rec), _d(seis))
+    if rc:
+        raise ValueError("oracle: invalid geometry or grid")
+    return seis
+
+
+def ac2_gradient(g, c, src, wav, rec, dJdd, ckpt=0, want_wav=False):
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    ns, nrec = src.shape[0], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    grad = np.zeros((g.nz, g.nx))
+    gw = np.zeros((ns, g.nt)) if want_wav else None
+    rc = lib().or_ac2_gradient(C.byref(g), _d(_f64(c)), C.c_int32(ns), _i(src), _d(wav),
+                               C.c_int32(nrec), _i(rec), _d(_f64(dJdd)), C.c_int32(ckpt),
+                               _d(grad), _d(seis), _d(gw) if want_wav else None)
+    if rc:
+        raise ValueError("oracle: invalid geometry or grid")
+    return (grad, seis, gw) if want_wav else (grad, seis)
+
+
+def misfit(pred, obs):
+    pred, obs = _f64(pred), _f64(obs)
+    r = np.zeros_like(pred)
+    lib().or_misfit.restype = C.c_double
+    J = lib().or_misfit(_d(pred), _d(obs), C.c_int64(pred.size), _d(r))
+    return J, r
+
+
+# ------------------------------------------------- closed-form 2-D Green's function
+def greens2d_ricker(r, c, t, f0, t0, nq=4000):
+    """Pressure of u_tt = c^2 lap u + delta(x) s(t) in an infinite 2-D medium
+    at distance r, for s = Ricker(f0, t0):
+
+        u(r, t) = 1/(2 pi c^2) * int_0^{acosh(ct/r)} s(t - (r/c) cosh(eta)) d eta
+
+    (the 2-D Green's function H(ct - r) / (2 pi c sqrt(c^2 t^2 - r^2))
+    convolved with s, after the substitution c(t - tau) = r cosh(eta)).
+    Evaluated with nq-point Gauss-Legendre quadrature per time sample."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.zeros_like(t)
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    for i, ti in enumerate(t):
+        if c * ti <= r:
+            continue
+        top = np.arccosh(c * ti / r)
+        eta = 0.5 * top * (xg + 1.0)
+        tau = ti - (r / c) * np.cosh(eta)
+        a = (np.pi * f0 * (tau - t0)) ** 2
+        s = (1.0 - 2.0 * a) * np.exp(-a)
+        out[i] = 0.5 * top * np.dot(wg, s) / (2.0 * np.pi * c * c)
+    return out
