@@ -1,0 +1,170 @@
+"""Throughput benchmark of the fwd+adjoint hot path on one MI355X.
+
+One step = one pass of the whole path over the batch: forward sweep of all
+shots with wavefield checkpoints, FP64 misfit and residual, then the adjoint
+sweep (checkpoint restore, segment recompute, adjoint steps) and the gradient
+finalisation -- all in the library's HIP kernels, inputs resident in HBM.
+
+Workload (default): 2-D acoustic, 8th-order Laplacian, 1000 x 500 cells
+(dx = 10 m) + 32-cell absorbing layer, dt = 0.8 ms, 4000 steps, 64 shots of
+an 8 Hz Ricker in one launch, 1000 receivers per shot, checkpoints every
+ceil(sqrt(4000)) = 64 steps; velocity 1500-4500 m/s from 12 seeded dipping
+layers + 20 Gaussian anomalies (a stand-in for the paper's Marmousi-class
+FWI model), initial model its 10-cell Gaussian blur.
+
+Prints ONE JSON line (rank 0, N = 1).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s fwd+adjoint (% HBM roofline); FWI time-to-misfit w/ vs w/o CNN"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_cell_step(pml_fraction):
+    """Algorithmic FP32 bytes per padded cell and step of each phase.
+    forward: read u^k, u^{k-1}, chat, write u^{k+1} = 16 B; layer cells also
+    read and write phi_x, phi_z (+16 B).  recompute: forward + the w~^k
+    snapshot write (+4 B).  adjoint: read s^{k+2}, s^{k+3}, chat, w~^k,
+    read+write the gradient, write s^{k+1} = 28 B; layer cells read and write
+    b_x, b_z (+16 B)."""
+    f = 16.0 + 16.0 * pml_fraction
+    return {"forward": f, "recompute": f + 4.0, "adjoint": 28.0 + 16.0 * pml_fraction}
+
+
+def cpu_baseline(cfg, c0, src, rec, nshots, nt):
+    from oracle import pyoracle as O
+    g = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+               pml_R=cfg.pml_R, pml_vmax=4500.0)
+    wav = np.stack([O.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)] * nshots)
+    d = np.random.default_rng(0).standard_normal((nshots, nt, rec.shape[1]))
+    t0 = time.perf_counter()
+    O.ac2_gradient(g, c0, src[:nshots], wav, rec[:nshots], d, ckpt=int(math.ceil(math.sqrt(nt))))
+    t = time.perf_counter() - t0
+    cells = cfg.padded_cells
+    return 2.0 * cells * nshots * nt / t / 1e9, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=None, help="override time steps (profiling runs only)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=120)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU shot sharding "
+              "is a design, not a build target.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_06027_amd import seisgrad as S
+    from paper_2003_06027_amd import synth
+
+    cfg = synth.C2
+    nt = args.nt or cfg.nt
+    ckpt = int(math.ceil(math.sqrt(nt)))
+    ct = synth.dipping_layers_anomalies(2003, cfg.nx, cfg.nz, cfg.dx)
+    c0 = synth.smooth(ct, 10.0)
+    src, rec = synth.c2_geometry(cfg.nshots, cfg.nx)
+    ns, nrec = src.shape[0], rec.shape[1]
+    vmax = 4500.0
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    d = S.desc(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+               pml_R=cfg.pml_R, pml_vmax=vmax)
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)
+    wav = wav[None].repeat(ns, 1).contiguous()
+    sh = S.Shots(src, rec, wav)
+    log(f"setup: {cfg.name} nt={nt} ckpt={ckpt} workspace={S.workspace_bytes(d, ns, nrec, ckpt) / 1e9:.1f} GB")
+    mt = S.Model(d, dev(ct), ns, nrec, ckpt)
+    obs = mt.forward(sh, save_ckpt=False)
+    torch.cuda.synchronize()
+    mt.close()
+    del mt
+    m = S.Model(d, dev(c0), ns, nrec, ckpt)
+    seis = torch.empty_like(obs)
+    resid = torch.empty_like(obs)
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty((1, cfg.nz, cfg.nx), dtype=torch.float32, device="cuda")
+
+    def step():
+        m.forward(sh, seis=seis, save_ckpt=True)
+        S._check(S.lib().misfit(m.handle, S._ptr(seis), S._ptr(obs), seis.numel(), S._ptr(J),
+                                S._ptr(resid), S._stream()))
+        m.gradient(sh, resid, g_vp=g)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done, J = {J.item():.6e}")
+    m.set_profiling(True)
+    m.phase_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s")
+    t1 = time.perf_counter()
+    phases = m.phase_times()
+    m.set_profiling(False)
+    assert np.isfinite(J.item()) and np.isfinite(g.abs().max().item())
+
+    T = (t1 - t0) / args.steps
+    cells = cfg.padded_cells
+    updates = 2.0 * cells * ns * nt
+    value = updates / T / 1e9
+    pml_frac = 1.0 - cfg.nx * cfg.nz / cells
+    bpc = bytes_per_cell_step(pml_frac)
+    ph = {}
+    for name, (ms, steps) in phases.items():
+        if steps == 0:
+            continue
+        per = ms / steps                      # ms per step of this phase
+        gbs = cells * ns * bpc[name] / (per * 1e-3) / 1e9
+        ph[name] = {"ms_per_step": round(per, 5), "gcell_per_s": round(cells * ns / (per * 1e-3) / 1e9, 2),
+                    "alg_bytes_per_cell": round(bpc[name], 3), "gbs": round(gbs, 1),
+                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(ph, key=lambda k: phases[k][0])
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}", "grid_padded": list(cfg.padded),
+                   "shots": ns, "nt": nt, "ckpt_every": ckpt, "receivers": nrec,
+                   "cell_updates_per_step": updates},
+        "roofline": {"bound": "hbm", "kernel": f"ac2 {dom} step (PML + interior launches)",
+                     "achieved": ph[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ph[dom]["frac_hbm"], "traffic": None},
+        "phases": ph,
+    }
+    if not args.no_cpu:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        ncpu = max(1, min(cores, ns))
+        log(f"cpu baseline: oracle, {ncpu} shots x {args.cpu_steps} steps on {cores} threads")
+        rate, t = cpu_baseline(cfg, c0, src, rec, ncpu, args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(rate, 4), "unit": "Gcell-updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{ncpu} shots x {args.cpu_steps} steps of the same grid, FP64 "
+                                         f"fwd+adjoint, {t:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/* seisgrad.h -- C ABI of the MI355X (gfx950) finite-difference wave-propagation
+ * and adjoint-gradient library (libseisgrad.so).
+ *
+ * What the library computes (Zhu, Xu, Darve & Beroza, "A General Approach to
+ * Seismic Inversion with Automatic Differentiation"):
+ *   - the explicit recursion U_k = A(theta) U_{k-1} + F_{k-1}
+ *     (Method, "Relationship to the Adjoint Method", Eq. (1)) for the
+ *     acoustic wave equation (Implementation, Eq. (11), constant-density form
+ *     u_tt = c^2 lap(u) + f, 2nd order in time, 8th order in space) with an
+ *     auxiliary-field absorbing layer (PML) padded outside the model;
+ *   - point-source injection of a wavelet and receiver gathering (the F_k
+ *     and the observation operator of the misfit);
+ *   - the L2 misfit J = 1/2 sum ||d - d_obs||^2 (display after Eq. (1)) on
+ *     the receiver samples, accumulated in FP64;
+ *   - the gradient dJ/dtheta = sum_k lambda_k^T (dA/dtheta) U_{k-1}
+ *     (Eq. (5)) with lambda_k from the adjoint recursion (Eq. (4)), which the
+ *     paper's Theorem shows equal to reverse-mode AD (Eqs. (8)-(9)).
+ *
+ * Conventions
+ *   - Physical model arrays: FP32, row-major [model][iz][ix] (2-D),
+ *     x fastest, z down, 0-based.  The absorbing layer of npml cells is padded
+ *     OUTSIDE the physical grid on every side, the model being continued by
+ *     edge replication; cells beyond the padded grid are zero (rigid).
+ *   - Time: u^0 = u^{-1} = 0; step k (0..nt-1) injects wavelet sample k;
+ *     seismogram sample k holds u^{k+1} at the receivers.
+ *   - Source: a point source at a grid node, f = r(t_k) / (dx*dz).
+ *   - Seismograms: FP32 [nshots][ncomp][nt][nrec] (ncomp = 1 acoustic).
+ *   - Shots are ordered model-major: with nmodels models, shot s uses model
+ *     s / (nshots / nmodels); nshots must be a multiple of nmodels.
+ *   - The damping profile zeta(d) = zeta_max (d/npml)^2 with
+ *     zeta_max = 3 pml_vmax ln(1/pml_R) / (2 npml dx) is fixed by pml_vmax and
+ *     does not depend on the model (so the gradient has no profile term).
+ *
+ * Ownership and memory
+ *   - Every array argument marked DEVICE is a caller-owned, contiguous device
+ *     pointer on the current HIP device; HOST arrays are read during the call
+ *     only.  The library never allocates device memory: all its state
+ *     (coefficients, wavefields, checkpoints, snapshots, per-shot gradients,
+ *     reduction partials) is carved from the caller's workspace, whose size is
+ *     given by workspace_bytes().  The workspace must outlive the model.
+ *   - sg_model is an opaque host object owned by the library until
+ *     free_model().  One model per stream; calls on one model are not
+ *     thread-safe.
+ *   - Every call enqueues its GPU work on `stream` (0 = null stream) and
+ *     returns after host-side validation; results are valid once the stream
+ *     has reached that point.  Outputs are overwritten, never accumulated.
+ *
+ * Errors: every int-returning entry point returns SG_OK (0) or a negative
+ * code; last_error() gives a thread-local message for the last failure.  No
+ * C++ exception crosses the ABI.
+ */
+#ifndef SEISGRAD_H
+#define SEISGRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define SG_API __attribute__((visibility("default")))
+#else
+#define SG_API
+#endif
+
+typedef struct ihipStream_t *sg_stream_t; /* hipStream_t */
+
+enum {
+    SG_OK = 0,
+    SG_EINVAL = -1,      /* bad shape, NULL pointer, out-of-grid source/receiver */
+    SG_EUNSTABLE = -2,   /* CFL number above 0.95 x the scheme's limit, or zeta_max*dt > 0.3 */
+    SG_ENOMEM = -3,      /* workspace smaller than workspace_bytes() */
+    SG_ESTATE = -4,      /* adjoint without a matching checkpointed forward */
+    SG_EDEVICE = -5,     /* a HIP runtime call failed */
+    SG_EUNSUPPORTED = -6 /* a physics / dimension combination this build does not provide */
+};
+
+enum { SG_ACOUSTIC = 0, SG_ELASTIC = 1 };
+
+/* Grid, time stepping and absorbing layer. */
+typedef struct sg_desc {
+    int32_t ndim;       /* 2 (3-D: SG_EUNSUPPORTED in this build) */
+    int32_t physics;    /* SG_ACOUSTIC */
+    int32_t nx, ny, nz; /* physical cells; ny = 1 in 2-D */
+    int32_t npml;       /* absorbing-layer width in cells (>= 0) */
+    int32_t nt;         /* time steps (>= 1) */
+    int32_t nmodels;    /* models batched in one launch (>= 1) */
+    double dx;          /* grid spacing, all axes (m) */
+    double dt;          /* time step (s) */
+    double pml_R;       /* target reflection coefficient, e.g. 1e-3 */
+    double pml_vmax;    /* reference velocity of the damping profile (m/s) */
+    double f0_pml;      /* reserved (elastic CPML frequency) */
+} sg_desc;
+
+/* One batch of shots. */
+typedef struct sg_shots {
+    int32_t nshots;          /* >= 1, multiple of nmodels, <= max_shots of the model */
+    int32_t nrec;            /* receivers per shot (>= 0) */
+    const int32_t *src;      /* HOST [nshots][ndim]: (ix, iz) physical source node */
+    const int32_t *rec;      /* HOST [nshots][nrec][ndim]: (ix, iz) receiver nodes */
+    const float *wavelet;    /* DEVICE [nshots][nt]: source time function r(t_k) */
+} sg_shots;
+
+typedef struct sg_model sg_model;
+
+/* Bytes of device workspace needed for up to max_shots shots of up to
+ * max_rec receivers each, with wavefield checkpoints every ckpt_every steps
+ * (0 -> ceil(sqrt(nt))).  Returns 0 on an invalid descriptor (see
+ * last_error()). */
+SG_API size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int32_t ckpt_every);
+
+/* Prepare a model (paper: the parameter theta of A(theta), Eq. (1); here the
+ * velocity c of Eq. (11)): validate the descriptor, check stability
+ * (8th-order leapfrog limit c dt/dx <= 2/sqrt(6.5016 ndim), rejected above
+ * 0.95 of it), pad the velocity by edge replication, form C = dt^2 c^2 on the
+ * padded grid and the damping tables.
+ *   vp:  DEVICE FP32 [nmodels][nz][nx] velocity (m/s), > 0;
+ *   vs, rho: reserved for elastic, must be NULL;
+ *   ws:  DEVICE workspace, 256-byte aligned, of
+ *        ws_bytes >= workspace_bytes(d, max_shots, max_rec, ckpt_every);
+ *   out: receives the model handle.
+ * The call synchronises `stream` once (it reads the velocity range back for
+ * the stability check).  The velocity is copied into the workspace; vp may be
+ * freed afterwards. */
+SG_API int init_model(const sg_desc *d, const float *vp, const float *vs, const float *rho,
+               int32_t max_shots, int32_t max_rec, int32_t ckpt_every, void *ws,
+               size_t ws_bytes, sg_stream_t stream, sg_model **out);
+
+/* Forward modelling of a batch of shots (Eq. (1) with the source term F_k):
+ * runs all nt steps and writes the seismograms.
+ *   seis: DEVICE FP32 [nshots][1][nt][nrec], overwritten;
+ *   save_ckpt: nonzero stores a wavefield checkpoint every ckpt_every steps
+ *   (required before adjoint_gradient).
+ * Errors: SG_EINVAL on out-of-grid sources/receivers or nshots too large. */
+SG_API int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckpt,
+                  sg_stream_t stream);
+
+/* L2 misfit (display after Eq. (1)): resid = pred - obs (FP32) and
+ * J = 1/2 sum resid^2 accumulated in FP64 in a fixed order (bitwise
+ * reproducible).
+ *   pred, obs: DEVICE FP32 [n]; J_dev: DEVICE double[1]; resid: DEVICE FP32
+ *   [n] or NULL (may alias pred).  With a model the reduction runs over many
+ *   workgroups and keeps its partial sums in the model's workspace; with
+ *   m == NULL it runs in one workgroup (slower, no workspace).
+ * Non-finite inputs give a non-finite J; the call itself does not sync. */
+SG_API int misfit(sg_model *m, const float *pred, const float *obs, int64_t n,
+           double *J_dev, float *resid, sg_stream_t stream);
+
+/* Gradient of J with respect to the velocity by the adjoint sweep
+ * (Eqs. (4)-(5)), for ANY seismogram-space adjoint dJ_dd (for the L2 misfit,
+ * the resid of misfit()).  Needs the checkpointed forward of the same shots
+ * (same geometry) on this model; recomputes each segment of ckpt_every steps
+ * from its checkpoint and runs the exact transpose of the forward step
+ * backwards in time.
+ *   dJ_dd: DEVICE FP32 [nshots][1][nt][nrec];
+ *   g_vp:  DEVICE FP32 [nmodels][nz][nx], sum over the model's shots in shot
+ *          order, absorbing-layer cells folded onto the edge cells they
+ *          replicate;
+ *   g_vs, g_rho: reserved, NULL;
+ *   g_wavelet: DEVICE FP32 [nshots][nt] or NULL: dJ/dr(t_k) per shot.
+ * Errors: SG_ESTATE when no matching checkpointed forward precedes it. */
+SG_API int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd,
+                     float *g_vp, float *g_vs, float *g_rho, float *g_wavelet,
+                     sg_stream_t stream);
+
+/* Optional device timing of the step loops.  With profiling on, the
+ * library records one pair of HIP events on the call's stream around every
+ * checkpoint segment of the forward sweep (phase 0), of the recompute
+ * (phase 1) and of the adjoint steps (phase 2); phase_times() waits for them
+ * and returns, per phase, the summed milliseconds and the number of steps
+ * they cover, then forgets them.  ms and steps: HOST arrays of 3. */
+SG_API int set_profiling(sg_model *m, int32_t enable);
+SG_API int phase_times(sg_model *m, double *ms, int64_t *steps);
+
+/* Release the host object (the workspace stays the caller's). */
+SG_API int free_model(sg_model *m);
+
+/* Message of the last failed call on this thread ("" if none). */
+SG_API const char *last_error(void);
+
+/* Ricker wavelet r(t_k) = (1 - 2 pi^2 f0^2 (t_k - t0)^2) exp(-pi^2 f0^2 (t_k - t0)^2),
+ * t_k = k dt, the source time function of the paper's FWI tests
+ * (Applications, "Full-waveform Inversion"); evaluated in FP64, stored FP32.
+ *   out: DEVICE FP32 [nt]. */
+SG_API int ricker(double f0, double t0, double dt, int32_t nt, float *out, sg_stream_t stream);
+
+/* FP64 inner product sum x[i]*y[i] of two FP32 device vectors in a fixed
+ * reduction order, one workgroup (dot-product tests, gradient norms).
+ *   x, y: DEVICE FP32 [n]; out: DEVICE double[1]. */
+SG_API int dot_f64(const float *x, const float *y, int64_t n, double *out, sg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,205 @@
+"""GPU parity of the 2-D acoustic HIP path (through the C ABI) against the
+FP64 oracle, plus GPU self-consistency (dot-product identity with FP64
+reductions, checkpointed == store-all bitwise, run-to-run determinism).
+
+Tolerances: seismograms rel-L2 <= 1e-4, gradients rel-L2 <= 1e-3 over the
+whole array; FP32 arithmetic in the kernels, FP64 in the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import O, S, synth, rel_l2, oracle_grid, gpu_desc, gpu_wavelets, oracle_wavelets, dev
+
+pytestmark = pytest.mark.gpu
+
+SEIS_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+def _run_case(cfg, c_true, c0, src, rec, f0s, t0s, pml_vmax, ckpt=0, nmodels=1, want_gw=False):
+    """GPU: forward on c_true (observed), forward+misfit+adjoint on c0."""
+    ns = src.shape[0]
+    d = gpu_desc(cfg, pml_vmax, nmodels=nmodels)
+    wav = gpu_wavelets(f0s, t0s, cfg.dt, cfg.nt)
+    sh = S.Shots(src, rec, wav)
+    mt = S.Model(d, dev(c_true), ns, rec.shape[1], ckpt)
+    obs = mt.forward(sh, save_ckpt=False)
+    m0 = S.Model(d, dev(c0), ns, rec.shape[1], ckpt)
+    pred = m0.forward(sh, save_ckpt=True)
+    J, resid = m0.misfit(pred, obs)
+    gw = torch.zeros((ns, cfg.nt), dtype=torch.float32, device="cuda") if want_gw else None
+    g = m0.gradient(sh, resid, g_wavelet=gw)
+    torch.cuda.synchronize()
+    out = dict(obs=obs.cpu().numpy()[:, 0], pred=pred.cpu().numpy()[:, 0], J=float(J.item()),
+               grad=g.cpu().numpy(), wav=wav.cpu().numpy())
+    if want_gw:
+        out["gw"] = gw.cpu().numpy()
+    mt.close()
+    m0.close()
+    return out
+
+
+def _oracle_case(cfg, c_true, c0, src, rec, f0s, t0s, pml_vmax, ckpt=0):
+    g = oracle_grid(cfg, pml_vmax)
+    wav = oracle_wavelets(f0s, t0s, cfg.dt, cfg.nt)
+    obs = O.ac2_forward(g, c_true, src, wav, rec)
+    pred = O.ac2_forward(g, c0, src, wav, rec)
+    J, r = O.misfit(pred, obs)
+    grad, _ = O.ac2_gradient(g, c0, src, wav, rec, r, ckpt=ckpt)
+    return dict(obs=obs, pred=pred, J=J, grad=grad, wav=wav)
+
+
+def test_ricker_matches_oracle():
+    for f0, t0, dt, nt in [(10.0, 0.1, 1e-3, 500), (8.0, 0.125, 0.8e-3, 4000)]:
+        a = S.ricker(f0, t0, dt, nt).cpu().numpy()
+        b = O.ricker(f0, t0, dt, nt)
+        assert np.max(np.abs(a - b)) <= 6e-8
+
+
+def test_c1_forward_and_gradient_parity():
+    """2-D acoustic 101x101, 3 layers, dt = 1 ms, 500 steps, 20-cell layer,
+    10 Hz Ricker at (50, 2), 101 surface receivers; gradient of the L2
+    misfit against the smoothed initial model."""
+    cfg = synth.C1
+    ct = synth.layered_c1()
+    c0 = synth.smooth(ct, 10.0)
+    src, rec = synth.c1_geometry()
+    f0s, t0s = [cfg.f0], [cfg.ricker_t0]
+    vmax = 3000.0
+    gpu = _run_case(cfg, ct, c0, src, rec, f0s, t0s, vmax)
+    ora = _oracle_case(cfg, ct, c0, src, rec, f0s, t0s, vmax)
+    e_obs, e_pred = rel_l2(gpu["obs"], ora["obs"]), rel_l2(gpu["pred"], ora["pred"])
+    e_grad = rel_l2(gpu["grad"], ora["grad"])
+    print(f"C1 seis rel-L2 {e_obs:.2e} / {e_pred:.2e}  grad rel-L2 {e_grad:.2e}  J {gpu['J']:.6e} vs {ora['J']:.6e}")
+    assert e_obs <= SEIS_TOL and e_pred <= SEIS_TOL
+    assert e_grad <= GRAD_TOL
+    assert gpu["J"] == pytest.approx(ora["J"], rel=2e-3)
+
+
+def test_ragged_multishot_multimodel_parity():
+    """Grid not a multiple of the tile (ragged tiles in x and z), 4 shots over
+    2 models batched in one launch, sources/receivers near and inside the
+    layer's neighbourhood, odd checkpoint interval."""
+    cfg = synth.C1.replace(nx=150, nz=77, npml=10, nt=300, dt=1e-3)
+    rng = np.random.default_rng(12)
+    cA = 1600.0 + 900.0 * synth.smooth_random(3, (cfg.nz, cfg.nx), 4.0, 0.0, 1.0)
+    cB = cA[::-1].copy()
+    src = np.array([[5, 3], [140, 70], [75, 0], [0, 40]], dtype=np.int32)
+    nr = 60
+    rec = np.stack([np.stack([rng.integers(0, cfg.nx, nr), rng.integers(0, cfg.nz, nr)], -1)
+                    for _ in range(4)]).astype(np.int32)
+    rec[0, :2] = rec[0, 2]                       # duplicate receivers on one cell
+    f0s, t0s = [15.0, 12.0, 20.0, 18.0], [0.07, 0.08, 0.05, 0.06]
+    vmax = 2600.0
+    ct = np.stack([cA, cA, cB, cB])
+    c0 = np.stack([synth.smooth(cA, 3.0)] * 2 + [synth.smooth(cB, 3.0)] * 2)
+    d = gpu_desc(cfg, vmax, nmodels=2)
+    wav = gpu_wavelets(f0s, t0s, cfg.dt, cfg.nt)
+    sh = S.Shots(src, rec, wav)
+    mt = S.Model(d, dev(np.stack([cA, cB])), 4, nr, 13)
+    obs = mt.forward(sh, save_ckpt=False)
+    m0 = S.Model(d, dev(np.stack([c0[0], c0[2]])), 4, nr, 13)
+    pred = m0.forward(sh)
+    J, r = m0.misfit(pred, obs)
+    g = m0.gradient(sh, r).cpu().numpy()
+    obs, pred = obs.cpu().numpy()[:, 0], pred.cpu().numpy()[:, 0]
+    go = oracle_grid(cfg, vmax)
+    wo = oracle_wavelets(f0s, t0s, cfg.dt, cfg.nt)
+    for mi, (ci, c0i) in enumerate([(cA, c0[0]), (cB, c0[2])]):
+        sl = slice(2 * mi, 2 * mi + 2)
+        oo = O.ac2_forward(go, ci, src[sl], wo[sl], rec[sl])
+        op = O.ac2_forward(go, c0i, src[sl], wo[sl], rec[sl])
+        _, ro = O.misfit(op, oo)
+        og, _ = O.ac2_gradient(go, c0i, src[sl], wo[sl], rec[sl], ro, ckpt=0)
+        e1, e2, e3 = rel_l2(obs[sl], oo), rel_l2(pred[sl], op), rel_l2(g[mi], og)
+        print(f"model {mi}: seis {e1:.2e} {e2:.2e} grad {e3:.2e}")
+        assert e1 <= SEIS_TOL and e2 <= SEIS_TOL and e3 <= GRAD_TOL
+
+
+def test_checkpointed_equals_store_all_bitwise_and_deterministic():
+    cfg = synth.C1.replace(nt=200)
+    ct = synth.layered_c1()
+    c0 = synth.smooth(ct, 10.0)
+    src, rec = synth.c1_geometry()
+    runs = [_run_case(cfg, ct, c0, src, rec, [10.0], [0.1], 3000.0, ckpt=k, want_gw=True)
+            for k in (0, 200, 7, 0)]
+    ref = runs[-1]
+    for r in runs[:-1]:
+        assert np.array_equal(r["grad"], ref["grad"])
+        assert np.array_equal(r["gw"], ref["gw"])
+        assert np.array_equal(r["pred"], ref["pred"])
+
+
+def test_sweep_dot_product_identity_fp64():
+    """<F s, d> = <s, F^T d> for the wavelet -> seismogram map with FP64
+    reductions on the GPU (FP32 arithmetic in the sweeps)."""
+    cfg = synth.C1.replace(nx=120, nz=90, npml=16, nt=400)
+    c = 1700.0 + 800.0 * synth.smooth_random(5, (cfg.nz, cfg.nx), 5.0, 0.0, 1.0)
+    src = np.array([[30, 4], [90, 60]], dtype=np.int32)
+    rec = np.stack([synth.surface_receivers_2d(1, cfg.nx)[0]] * 2)
+    d = gpu_desc(cfg, 2600.0)
+    s = dev(synth.random_field(1, (2, cfg.nt)))
+    dd = dev(synth.random_field(2, (2, 1, cfg.nt, cfg.nx)))
+    sh = S.Shots(src, rec, s)
+    m = S.Model(d, dev(c), 2, cfg.nx, 20)
+    Fs = m.forward(sh)
+    gw = torch.zeros((2, cfg.nt), dtype=torch.float32, device="cuda")
+    m.gradient(sh, dd, g_wavelet=gw)
+    lhs = S.dot_f64(Fs.reshape(-1), dd.reshape(-1)).item()
+    rhs = S.dot_f64(s.reshape(-1), gw.reshape(-1)).item()
+    nF = S.dot_f64(Fs.reshape(-1), Fs.reshape(-1)).item() ** 0.5
+    nd = S.dot_f64(dd.reshape(-1), dd.reshape(-1)).item() ** 0.5
+    # random-sign sums cancel: bound the defect by |F s| |d| (Cauchy-Schwarz)
+    print(f"dot test (random d): {lhs:.12e} {rhs:.12e} defect/(|Fs||d|) {abs(lhs - rhs) / (nF * nd):.2e}")
+    assert abs(lhs - rhs) <= 1e-5 * nF * nd
+    # d = F s: <F s, F s> = <s, F^T F s>, no cancellation
+    m.forward(sh)          # fresh checkpoints (same geometry)
+    gw.zero_()
+    m.gradient(sh, Fs, g_wavelet=gw)
+    lhs2 = nF * nF
+    rhs2 = S.dot_f64(s.reshape(-1), gw.reshape(-1)).item()
+    print(f"dot test (d = F s): {lhs2:.12e} {rhs2:.12e} rel {abs(lhs2 - rhs2) / lhs2:.2e}")
+    assert abs(lhs2 - rhs2) <= 1e-5 * lhs2
+
+
+def test_misfit_fp64_matches_oracle():
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(3_000_001).astype(np.float32)
+    b = rng.standard_normal(3_000_001).astype(np.float32)
+    J, r = O.misfit(a.astype(np.float64), b.astype(np.float64))
+    da, db = dev(a), dev(b)
+    Jd = torch.empty(1, dtype=torch.float64, device="cuda")
+    rd = torch.empty_like(da)
+    assert S.lib().misfit(None, S._ptr(da), S._ptr(db), a.size, S._ptr(Jd), S._ptr(rd), S._stream()) == 0
+    d = gpu_desc(synth.C1, 3000.0)
+    m = S.Model(d, dev(synth.layered_c1()), 1, 101)
+    J2, r2 = m.misfit(da, db)
+    # the residual is rounded to FP32 before the FP64 accumulation
+    assert Jd.item() == pytest.approx(J, rel=1e-8)
+    assert J2.item() == pytest.approx(J, rel=1e-8)
+    r32 = (a - b).astype(np.float64)
+    assert Jd.item() == pytest.approx(0.5 * np.dot(r32, r32), rel=1e-12)
+    assert np.array_equal(rd.cpu().numpy(), (a - b))
+    assert np.array_equal(r2.cpu().numpy(), (a - b))
+
+
+def test_error_paths_on_device():
+    cfg = synth.C1
+    d = gpu_desc(cfg, 3000.0)
+    src, rec = synth.c1_geometry()
+    wav = gpu_wavelets([10.0], [0.1], cfg.dt, cfg.nt)
+    m = S.Model(d, dev(synth.layered_c1()), 1, 101)
+    bad = src.copy()
+    bad[0, 0] = cfg.nx
+    with pytest.raises(S.SeisError) as e:
+        m.forward(S.Shots(bad, rec, wav))
+    assert e.value.code == S.SG_EINVAL
+    # adjoint before a checkpointed forward of these shots
+    m.forward(S.Shots(src, rec, wav), save_ckpt=False)
+    with pytest.raises(S.SeisError) as e:
+        m.gradient(S.Shots(src, rec, wav), torch.zeros((1, 1, cfg.nt, 101), device="cuda"))
+    assert e.value.code == S.SG_ESTATE
+    # unstable time step
+    with pytest.raises(S.SeisError) as e:
+        S.Model(gpu_desc(cfg.replace(dt=2e-3), 3000.0), dev(synth.layered_c1()), 1, 101)
+    assert e.value.code == S.SG_EUNSTABLE
