@@ -4,23 +4,29 @@
 // in the constant-density form u_tt = c^2 lap(u) + f with an auxiliary-field
 // absorbing layer).  In scaled variables (chat = dt^2 c^2/dx^2, phi~ = dx*phi,
 // h = zeta dt/2, L~ and D~ the 8th-order stencils without the 1/dx factors):
-//     phi~_j^k = p_j phi~_j^{k-1} + q_j D~_j u^k,  p = (1-h_j)/(1+h_j),
-//                                                  q = 2(h_other - h_j)/(1+h_j)
-//     w~^k     = L~ u^k + D~_x phi~_x^k + D~_z phi~_z^k
-//     u^{k+1}  = alpha (beta u^k - gamma u^{k-1} + chat w~^k + dt^2 f^k)
-// with alpha = 1/(1+h_x+h_z), beta = 2 - 4 h_x h_z, gamma = 1 - h_x - h_z.
-// The stored state after step k is (u^{k+1}, u^k, phi~^k): phi is updated at
-// the start of the next step from the u it needs, so one launch per step does
-// the whole update.  A tile needs phi~^k on its cells +-4, hence u^k on +-8:
-// tiles near the layer ("PML tiles") load an 8-cell halo and recompute phi on
-// the 4-cell ring; interior tiles load a 4-cell halo and skip phi entirely.
+//   pass A (layer cells only):
+//     phi~_j^k = p_j phi~_j^{k-1} + q_j D~_j u^k,   p_j = (1-h_j)/(1+h_j),
+//                                                  q_j = 2(h_other - h_j)/(1+h_j)
+//   pass B (every cell):
+//     w~^k    = L~ u^k + D~_x phi~_x^k + D~_z phi~_z^k
+//     u^{k+1} = alpha (beta u^k - gamma u^{k-1} + chat w~^k + dt^2 f^k)
+// with alpha = 1/(1+h_x+h_z), beta = 2 - 4 h_x h_z, gamma = 1 - h_x - h_z
+// (1, 2, 1 in the interior).  The stored state after step k is
+// (u^{k+1}, u^k, phi~^k).  Pass A reads phi~^{k-1} only at its own cell, so
+// phi is updated in place; outside the layer phi~ stays exactly zero.
+// Pass B tiles more than 4 cells from the layer skip the phi terms and the
+// damping coefficients ("interior" tiles); the others ("near" tiles) add them.
 //
 // Adjoint step k (Eq. (4): lambda_k = A^T lambda_{k+1} + residual; Eq. (5)
-// for the gradient), in the alpha-scaled variable s = alpha * dJ/du:
-//     b_j^{k+1} = p_j b_j^{k+2} - D~_j(chat s^{k+2})
-//     a^{k+1}   = R^T dJ/dd^{k+1} - sum_j D~_j(q_j b_j^{k+1})
-//                 + beta s^{k+2} + L~(chat s^{k+2}) - gamma s^{k+3}
-//     s^{k+1}   = alpha a^{k+1};   dJ/dchat += s^{k+1} w~^k
+// for the gradient), in the alpha-scaled variable s = alpha * dJ/du and the
+// q-scaled layer adjoint c_j = q_j * dJ/dphi~_j (q is constant in time, so
+// c obeys the same recursion as dJ/dphi~ multiplied by q):
+//   pass A (layer cells):
+//     c_j^{k+1} = p_j c_j^{k+2} - q_j D~_j(chat s^{k+2})
+//   pass B (every cell):
+//     a^{k+1} = R^T dJ/dd^{k+1} - D~_x c_x^{k+1} - D~_z c_z^{k+1}
+//               + beta s^{k+2} + L~(chat s^{k+2}) - gamma s^{k+3}
+//     s^{k+1} = alpha a^{k+1};   dJ/dchat += s^{k+1} w~^k
 // using L~^T = L~ and D~^T = -D~ (zero cells beyond the grid).
 #include "sg_internal.h"
 
@@ -42,27 +48,51 @@ __device__ __forceinline__ long long fidx(const Grid2 &g, int iz, int ix)
     return (long long)(iz + OZ) * g.SX + (ix + OX);
 }
 
+// 8th-order Laplacian (x + z) of an LDS tile with row stride W.  The weights
+// sum to zero, so L~u = sum_m a_m ((u_{+m} - u_0) + (u_{-m} - u_0)) along each
+// axis: neighbour differences of a smooth field are exact or nearly so in
+// FP32, which keeps the rounding error proportional to L~u instead of u.
 __device__ __forceinline__ float lap8(const float *c, int W)
 {
-    return 2.f * A0 * c[0]
-         + A1 * ((c[1] + c[-1]) + (c[W] + c[-W]))
-         + A2 * ((c[2] + c[-2]) + (c[2 * W] + c[-2 * W]))
-         + A3 * ((c[3] + c[-3]) + (c[3 * W] + c[-3 * W]))
-         + A4 * ((c[4] + c[-4]) + (c[4 * W] + c[-4 * W]));
+    const float c0 = c[0];
+    auto pair = [&](int o) { return (c[o] - c0) + (c[-o] - c0); };
+    return A4 * (pair(4) + pair(4 * W)) + A3 * (pair(3) + pair(3 * W))
+         + A2 * (pair(2) + pair(2 * W)) + A1 * (pair(1) + pair(W));
 }
 
-__device__ __forceinline__ float d8(const float *c, int s)
+template <class T>
+__device__ __forceinline__ float d8(const T *c, long long s)
 {
     return D1 * (c[s] - c[-s]) + D2 * (c[2 * s] - c[-2 * s])
          + D3 * (c[3 * s] - c[-3 * s]) + D4 * (c[4 * s] - c[-4 * s]);
 }
 
-// Fill the (TZ+2H) x (TX+2H) LDS tile from `src` (one shot's frame) with
-// f(value, frame index) -- own cells are loaded by the caller.
-template <int H, class Fn>
+// Work id of this workgroup with consecutive ids on one XCD: the hardware
+// hands workgroups to the 8 XCDs round-robin, so id b runs on XCD b % 8; the
+// remap gives each XCD a contiguous range of (tile, shot) work, which keeps
+// neighbouring tiles -- and their shared halos -- in the same L2.
+__device__ __forceinline__ int xcd_work_id(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks / NXCD, rem = nblocks % NXCD;
+    const int x = b % NXCD, j = b / NXCD;
+    return x * per + min(x, rem) + j;
+}
+
+// Is a tile within 4 cells of the absorbing layer (its cells need the phi
+// terms or damping coefficients)?
+__device__ __forceinline__ bool near_layer(const Grid2 &g, int x0, int z0)
+{
+    return g.P > 0 && (x0 - 4 < g.P || x0 + TX + 4 > g.P + g.nx ||
+                       z0 - 4 < g.P || z0 + TZ + 4 > g.P + g.nz);
+}
+
+// Fill the (TZ+8) x (TX+8) LDS tile: own cells by the caller, the 4-cell
+// halo here (value f(frame index)).
+template <class Fn>
 __device__ __forceinline__ void load_halo(const Grid2 &g, float *lds, int x0, int z0, Fn f)
 {
-    constexpr int W = TX + 2 * H;
+    constexpr int H = 4, W = TX + 2 * H;
     constexpr int NH = 2 * H * W + 2 * TZ * H;
     for (int i = threadIdx.x; i < NH; i += NTH) {
         int r, c;
@@ -80,21 +110,53 @@ __device__ __forceinline__ void load_halo(const Grid2 &g, float *lds, int x0, in
     }
 }
 
-template <bool PML, bool SNAP, bool REC>
-__global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
+// Map linear index i over the layer cells of one shot to (iz, ix): the top
+// strip (P full rows), the bottom strip, then the left/right strips of the
+// physical rows, each traversed row by row.
+__device__ __forceinline__ void layer_cell(const Grid2 &g, long long i, int &iz, int &ix)
 {
-    constexpr int H = PML ? 8 : 4;
-    constexpr int W = TX + 2 * H;
-    constexpr int HH = TZ + 2 * H;
-    constexpr int WX = TX + 8;
-    __shared__ float su[HH * W];
-    __shared__ float spx[PML ? TZ * WX : 1];
-    __shared__ float spz[PML ? (TZ + 8) * TX : 1];
+    const long long strip = (long long)g.P * g.NX;
+    if (i < 2 * strip) {
+        const int top = i < strip;
+        const long long j = top ? i : i - strip;
+        iz = (int)(j / g.NX);
+        ix = (int)(j - (long long)iz * g.NX);
+        if (!top) iz += g.P + g.nz;
+    } else {
+        const long long j = i - 2 * strip;
+        const int row = (int)(j / (2 * g.P)), col = (int)(j - (long long)row * 2 * g.P);
+        iz = g.P + row;
+        ix = col < g.P ? col : col + g.nx;
+    }
+}
 
+// ------------------------------------------------------------ forward pass A
+__global__ __launch_bounds__(256) void ac2_phi_kernel(Ac2PhiArgs a)
+{
     const Grid2 &g = a.g;
-    const int2 t = a.tiles[blockIdx.x];
     const int shot = blockIdx.y;
-    const int x0 = t.x * TX, z0 = t.y * TZ;
+    const long long so = (long long)shot * g.plane;
+    const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
+    const float *u = a.u + so;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < ncell; i += (long long)gridDim.x * 256) {
+        int iz, ix;
+        layer_cell(g, i, iz, ix);
+        const long long f = fidx(g, iz, ix);
+        const float hx = a.hx[ix], hz = a.hz[iz];
+        const float qx = 2.f * (hz - hx) * a.ihx[ix], qz = 2.f * (hx - hz) * a.ihz[iz];
+        a.phx[so + f] = a.px[ix] * a.phx[so + f] + qx * d8(u + f, 1);
+        a.phz[so + f] = a.pz[iz] * a.phz[so + f] + qz * d8(u + f, (long long)g.SX);
+    }
+}
+
+// ------------------------------------------------------------ forward pass B
+template <bool NEAR, bool SNAP, bool REC>
+__device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int tile, int shot)
+{
+    constexpr int H = 4, W = TX + 2 * H;
+    const Grid2 &g = a.g;
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
     const long long so = (long long)shot * g.plane;
     const float *u = a.u + so;
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
@@ -107,38 +169,8 @@ __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
         uc[j] = u[fidx(g, z0 + r, ix)];
         su[(r + H) * W + lx + H] = uc[j];
     }
-    load_halo<H>(g, su, x0, z0, [&](long long f) { return u[f]; });
+    load_halo(g, su, x0, z0, [&](long long f) { return u[f]; });
     __syncthreads();
-
-    if constexpr (PML) {
-        // phi~_x^k on rows z0.., columns x0-4 .. x0+TX+3
-        for (int i = tid; i < TZ * WX; i += NTH) {
-            const int r = i / WX, c = i - r * WX;
-            const int iz = z0 + r, jx = x0 - 4 + c;
-            float v = 0.f;
-            if (iz < g.NZ && jx >= 0 && jx < g.NX) {
-                const float hx = a.hx[jx], hz = a.hz[iz];
-                const float inv = 1.f / (1.f + hx);
-                const float p = (1.f - hx) * inv, q = 2.f * (hz - hx) * inv;
-                v = p * a.phx_old[so + fidx(g, iz, jx)] + q * d8(su + (r + H) * W + (c - 4 + H), 1);
-            }
-            spx[i] = v;
-        }
-        // phi~_z^k on rows z0-4 .. z0+TZ+3, columns x0..
-        for (int i = tid; i < (TZ + 8) * TX; i += NTH) {
-            const int r = i / TX, c = i - r * TX;
-            const int iz = z0 - 4 + r, jx = x0 + c;
-            float v = 0.f;
-            if (iz >= 0 && iz < g.NZ && jx < g.NX) {
-                const float hx = a.hx[jx], hz = a.hz[iz];
-                const float inv = 1.f / (1.f + hz);
-                const float p = (1.f - hz) * inv, q = 2.f * (hx - hz) * inv;
-                v = p * a.phz_old[so + fidx(g, iz, jx)] + q * d8(su + (r - 4 + H) * W + (c + H), W);
-            }
-            spz[i] = v;
-        }
-        __syncthreads();
-    }
 
     const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
     float *um = a.um + so;
@@ -148,32 +180,26 @@ __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int r = ly * RPT + j, iz = z0 + r;
+        const long long f = fidx(g, iz, ix);
         float w = lap8(su + (r + H) * W + lx + H, W);
-        float pxc = 0.f, pzc = 0.f;
-        if constexpr (PML) {
-            const float *px = spx + r * WX + lx + 4;
-            const float *pz = spz + (r + 4) * TX + lx;
-            w += d8(px, 1) + d8(pz, TX);
-            pxc = px[0];
-            pzc = pz[0];
-        }
         un[j] = 0.f;
         if (iz < g.NZ && ix < g.NX) {
-            const long long f = fidx(g, iz, ix);
             float v;
-            if constexpr (PML) {
+            if constexpr (NEAR) {
+                w += d8(a.phx + so + f, 1) + d8(a.phz + so + f, (long long)g.SX);
                 const float hx = a.hx[ix], hz = a.hz[iz];
+                // alpha (beta u - gamma um + chat w + src) with
+                // beta u - gamma um = u + (u - um) + (hx + hz) um - 4 hx hz u
                 const float alpha = 1.f / (1.f + hx + hz);
-                const float beta = 2.f - 4.f * hx * hz, gamma = 1.f - hx - hz;
-                float acc = beta * uc[j] - gamma * um[f] + chat[f] * w;
-                if (f == src) acc += sval;
-                v = alpha * acc;
-                a.phx_new[so + f] = pxc;
-                a.phz_new[so + f] = pzc;
+                const float umf = um[f];
+                float inc = (uc[j] - umf) + ((hx + hz) * umf - 4.f * hx * hz * uc[j]) + chat[f] * w;
+                if (f == src) inc += sval;
+                v = alpha * (uc[j] + inc);
             } else {
-                float acc = 2.f * uc[j] - um[f] + chat[f] * w;
-                if (f == src) acc += sval;
-                v = acc;
+                // 2u - um + chat w = u + ((u - um) + chat w)
+                float inc = (uc[j] - um[f]) + chat[f] * w;
+                if (f == src) inc += sval;
+                v = uc[j] + inc;
             }
             um[f] = v;
             un[j] = v;
@@ -184,7 +210,6 @@ __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
     if constexpr (REC) {
         const int ntiles = g.ntx * g.ntz;
         const int *off = a.rec_off + (long long)shot * (ntiles + 1);
-        const int tile = t.y * g.ntx + t.x;
         const int b = off[tile], e = off[tile + 1];
         if (b < e) {                      // uniform over the block
             __syncthreads();
@@ -201,21 +226,54 @@ __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
     }
 }
 
-template <bool PML>
-__global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
+template <bool SNAP, bool REC>
+__global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
 {
-    constexpr int H = PML ? 8 : 4;
-    constexpr int W = TX + 2 * H;
-    constexpr int HH = TZ + 2 * H;
-    constexpr int WX = TX + 8;
-    __shared__ float sc[HH * W];                 // chat * s^{k+2}
-    __shared__ float sqx[PML ? TZ * WX : 1];     // q_x * b_x^{k+1}
-    __shared__ float sqz[PML ? (TZ + 8) * TX : 1];
+    __shared__ float su[(TZ + 8) * (TX + 8)];
+    const int ntiles = a.g.ntx * a.g.ntz;
+    const int w = xcd_work_id(ntiles * a.nshots);
+    const int shot = w / ntiles, tile = w - shot * ntiles;
+    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
+    if (near_layer(a.g, tx * TX, tz * TZ)) fwd_tile<true, SNAP, REC>(a, su, tile, shot);
+    else                                    fwd_tile<false, SNAP, REC>(a, su, tile, shot);
+}
 
+// ------------------------------------------------------------ adjoint pass A
+__global__ __launch_bounds__(256) void ac2_phi_adj_kernel(Ac2PhiAdjArgs a)
+{
     const Grid2 &g = a.g;
-    const int2 t = a.tiles[blockIdx.x];
     const int shot = blockIdx.y;
-    const int x0 = t.x * TX, z0 = t.y * TZ;
+    const long long so = (long long)shot * g.plane;
+    const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
+    const float *s2 = a.s2 + so;
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < ncell; i += (long long)gridDim.x * 256) {
+        int iz, ix;
+        layer_cell(g, i, iz, ix);
+        const long long f = fidx(g, iz, ix);
+        float dx = 0.f, dz = 0.f;
+#pragma unroll
+        for (int m = 1; m <= 4; ++m) {
+            const float dm = m == 1 ? D1 : m == 2 ? D2 : m == 3 ? D3 : D4;
+            const long long e = (long long)m * g.SX;
+            dx += dm * (chat[f + m] * s2[f + m] - chat[f - m] * s2[f - m]);
+            dz += dm * (chat[f + e] * s2[f + e] - chat[f - e] * s2[f - e]);
+        }
+        const float hx = a.hx[ix], hz = a.hz[iz];
+        const float qx = 2.f * (hz - hx) * a.ihx[ix], qz = 2.f * (hx - hz) * a.ihz[iz];
+        a.cx[so + f] = a.px[ix] * a.cx[so + f] - qx * dx;
+        a.cz[so + f] = a.pz[iz] * a.cz[so + f] - qz * dz;
+    }
+}
+
+// ------------------------------------------------------------ adjoint pass B
+template <bool NEAR>
+__device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int tile, int shot)
+{
+    constexpr int H = 4, W = TX + 2 * H;
+    const Grid2 &g = a.g;
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
     const long long so = (long long)shot * g.plane;
     const float *s2 = a.s2 + so;
     const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
@@ -230,42 +288,8 @@ __global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
         sc2[j] = s2[f];
         sc[(r + H) * W + lx + H] = chat[f] * sc2[j];
     }
-    load_halo<H>(g, sc, x0, z0, [&](long long f) { return chat[f] * s2[f]; });
+    load_halo(g, sc, x0, z0, [&](long long f) { return chat[f] * s2[f]; });
     __syncthreads();
-
-    if constexpr (PML) {
-        for (int i = tid; i < TZ * WX; i += NTH) {
-            const int r = i / WX, c = i - r * WX;
-            const int iz = z0 + r, jx = x0 - 4 + c;
-            float v = 0.f;
-            if (iz < g.NZ && jx >= 0 && jx < g.NX) {
-                const float hx = a.hx[jx], hz = a.hz[iz];
-                const float inv = 1.f / (1.f + hx);
-                const float p = (1.f - hx) * inv, q = 2.f * (hz - hx) * inv;
-                const long long f = so + fidx(g, iz, jx);
-                const float bn = p * a.bx_old[f] - d8(sc + (r + H) * W + (c - 4 + H), 1);
-                if (c >= 4 && c < TX + 4) a.bx_new[f] = bn;
-                v = q * bn;
-            }
-            sqx[i] = v;
-        }
-        for (int i = tid; i < (TZ + 8) * TX; i += NTH) {
-            const int r = i / TX, c = i - r * TX;
-            const int iz = z0 - 4 + r, jx = x0 + c;
-            float v = 0.f;
-            if (iz >= 0 && iz < g.NZ && jx < g.NX) {
-                const float hx = a.hx[jx], hz = a.hz[iz];
-                const float inv = 1.f / (1.f + hz);
-                const float p = (1.f - hz) * inv, q = 2.f * (hx - hz) * inv;
-                const long long f = so + fidx(g, iz, jx);
-                const float bn = p * a.bz_old[f] - d8(sc + (r - 4 + H) * W + (c + H), W);
-                if (r >= 4 && r < TZ + 4) a.bz_new[f] = bn;
-                v = q * bn;
-            }
-            sqz[i] = v;
-        }
-        __syncthreads();
-    }
 
     float *s3 = a.s3 + so;
     float av[RPT];
@@ -273,14 +297,15 @@ __global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
     for (int j = 0; j < RPT; ++j) {
         const int r = ly * RPT + j, iz = z0 + r;
         float v = lap8(sc + (r + H) * W + lx + H, W);
-        if constexpr (PML) v -= d8(sqx + r * WX + lx + 4, 1) + d8(sqz + (r + 4) * TX + lx, TX);
         if (iz < g.NZ && ix < g.NX) {
             const long long f = fidx(g, iz, ix);
-            if constexpr (PML) {
+            if constexpr (NEAR) {
+                v -= d8(a.cx + so + f, 1) + d8(a.cz + so + f, (long long)g.SX);
                 const float hx = a.hx[ix], hz = a.hz[iz];
-                v += (2.f - 4.f * hx * hz) * sc2[j] - (1.f - hx - hz) * s3[f];
+                const float s3f = s3[f];
+                v += sc2[j] + ((sc2[j] - s3f) + ((hx + hz) * s3f - 4.f * hx * hz * sc2[j]));
             } else {
-                v += 2.f * sc2[j] - s3[f];
+                v += sc2[j] + (sc2[j] - s3[f]);
             }
         }
         av[j] = v;
@@ -289,7 +314,6 @@ __global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
     {   // receiver residual injection R^T dJ/dd^{k+1}, deterministic per cell
         const int ntiles = g.ntx * g.ntz;
         const int *off = a.rec_off + (long long)shot * (ntiles + 1);
-        const int tile = t.y * g.ntx + t.x;
         const int b = off[tile], e = off[tile + 1];
         if (b < e) {
             __syncthreads();
@@ -318,7 +342,7 @@ __global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
         if (iz < g.NZ && ix < g.NX) {
             const long long f = fidx(g, iz, ix);
             float s1 = av[j];
-            if constexpr (PML) s1 = s1 / (1.f + a.hx[ix] + a.hz[iz]);
+            if constexpr (NEAR) s1 = s1 / (1.f + a.hx[ix] + a.hz[iz]);
             s3[f] = s1;
             a.grad[so + f] += s1 * a.snap[so + f];
             if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
@@ -326,26 +350,50 @@ __global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
     }
 }
 
-void launch_ac2_fwd(const Ac2FwdArgs &a, int ntiles, int nshots, bool pml, hipStream_t s)
+__global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
 {
-    if (ntiles == 0 || nshots == 0) return;
-    dim3 grid(ntiles, nshots), block(NTH);
-    const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
-    if (pml) {
-        if (snap) { if (rec) ac2_fwd_kernel<true, true, true><<<grid, block, 0, s>>>(a); else ac2_fwd_kernel<true, true, false><<<grid, block, 0, s>>>(a); }
-        else      { if (rec) ac2_fwd_kernel<true, false, true><<<grid, block, 0, s>>>(a); else ac2_fwd_kernel<true, false, false><<<grid, block, 0, s>>>(a); }
-    } else {
-        if (snap) { if (rec) ac2_fwd_kernel<false, true, true><<<grid, block, 0, s>>>(a); else ac2_fwd_kernel<false, true, false><<<grid, block, 0, s>>>(a); }
-        else      { if (rec) ac2_fwd_kernel<false, false, true><<<grid, block, 0, s>>>(a); else ac2_fwd_kernel<false, false, false><<<grid, block, 0, s>>>(a); }
-    }
+    __shared__ float sc[(TZ + 8) * (TX + 8)];
+    const int ntiles = a.g.ntx * a.g.ntz;
+    const int w = xcd_work_id(ntiles * a.nshots);
+    const int shot = w / ntiles, tile = w - shot * ntiles;
+    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
+    if (near_layer(a.g, tx * TX, tz * TZ)) adj_tile<true>(a, sc, tile, shot);
+    else                                    adj_tile<false>(a, sc, tile, shot);
 }
 
-void launch_ac2_adj(const Ac2AdjArgs &a, int ntiles, int nshots, bool pml, hipStream_t s)
+// ------------------------------------------------------------------ launchers
+static int layer_blocks(const Grid2 &g)
 {
-    if (ntiles == 0 || nshots == 0) return;
-    dim3 grid(ntiles, nshots), block(NTH);
-    if (pml) ac2_adj_kernel<true><<<grid, block, 0, s>>>(a);
-    else     ac2_adj_kernel<false><<<grid, block, 0, s>>>(a);
+    const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
+    return (int)std::min<long long>(std::max<long long>((ncell + 255) / 256, 1), 4096);
+}
+
+void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s)
+{
+    if (a.g.P == 0 || nshots == 0) return;
+    ac2_phi_kernel<<<dim3(layer_blocks(a.g), nshots), 256, 0, s>>>(a);
+}
+
+void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s)
+{
+    if (a.g.P == 0 || nshots == 0) return;
+    ac2_phi_adj_kernel<<<dim3(layer_blocks(a.g), nshots), 256, 0, s>>>(a);
+}
+
+void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s)
+{
+    const int nb = a.g.ntx * a.g.ntz * a.nshots;
+    if (nb == 0) return;
+    const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
+    if (snap) { if (rec) ac2_fwd_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
+    else      { if (rec) ac2_fwd_kernel<false, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<false, false><<<nb, NTH, 0, s>>>(a); }
+}
+
+void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s)
+{
+    const int nb = a.g.ntx * a.g.ntz * a.nshots;
+    if (nb == 0) return;
+    ac2_adj_kernel<<<nb, NTH, 0, s>>>(a);
 }
 
 // ---------------------------------------------------------------- model prep
@@ -381,10 +429,23 @@ void launch_ac2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, do
 }
 
 // ------------------------------------------------------------ grad finalize
-// dJ/dc(phys) = sum over the model's shots (in order) and over the padded
-// cells replicating the physical cell of 2 dt^2 c / dx^2 * dJ/dchat.
-__global__ void ac2_finalize_kernel(Grid2 g, int nmodels, int spm, const float *grad,
-                                    const float *cpad, double dt, double dx, float *g_vp)
+// Pass 1: per padded cell, sum dJ/dchat over the model's shots in shot order
+// (coalesced over cells).  Pass 2: per physical cell, sum the padded cells
+// that replicate it and apply the chain rule dchat/dc = 2 dt^2 c / dx^2.
+__global__ void ac2_sum_shots_kernel(Grid2 g, int nmodels, int spm, const float *grad, float *acc)
+{
+    const long long n = (long long)nmodels * g.plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / g.plane, f = i - m * g.plane;
+        float v = 0.f;
+        for (int s = 0; s < spm; ++s) v += grad[(m * spm + s) * g.plane + f];
+        acc[i] = v;
+    }
+}
+
+__global__ void ac2_finalize_kernel(Grid2 g, int nmodels, const float *acc, const float *cpad,
+                                    double dt, double dx, float *g_vp)
 {
     const long long n = (long long)nmodels * g.nz * g.nx;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -394,24 +455,25 @@ __global__ void ac2_finalize_kernel(Grid2 g, int nmodels, int spm, const float *
         const int iz = (int)(rem / g.nx), ix = (int)(rem - (long long)iz * g.nx);
         const int zlo = iz == 0 ? 0 : iz + g.P, zhi = iz == g.nz - 1 ? g.NZ - 1 : iz + g.P;
         const int xlo = ix == 0 ? 0 : ix + g.P, xhi = ix == g.nx - 1 ? g.NX - 1 : ix + g.P;
-        float acc = 0.f;
-        for (int s = 0; s < spm; ++s) {
-            const float *gs = grad + (m * spm + s) * g.plane;
-            for (int pz = zlo; pz <= zhi; ++pz)
-                for (int px = xlo; px <= xhi; ++px)
-                    acc += gs[(long long)(pz + OZ) * g.SX + px + OX];
-        }
+        const float *am = acc + m * g.plane;
+        float v = 0.f;
+        for (int pz = zlo; pz <= zhi; ++pz)
+            for (int px = xlo; px <= xhi; ++px)
+                v += am[(long long)(pz + OZ) * g.SX + px + OX];
         const double c = cpad[m * g.plane + (long long)(iz + g.P + OZ) * g.SX + ix + g.P + OX];
-        g_vp[i] = (float)(2.0 * dt * dt * c / (dx * dx)) * acc;
+        g_vp[i] = (float)(2.0 * dt * dt * c / (dx * dx)) * v;
     }
 }
 
-void launch_ac2_finalize(const Grid2 &g, int nmodels, int spm, const float *grad,
+void launch_ac2_finalize(const Grid2 &g, int nmodels, int spm, const float *grad, float *acc,
                          const float *cpad, double dt, double dx, float *g_vp, hipStream_t s)
 {
-    const long long n = (long long)nmodels * g.nz * g.nx;
-    const int blocks = (int)std::min<long long>((n + 255) / 256, 65536);
-    ac2_finalize_kernel<<<blocks, 256, 0, s>>>(g, nmodels, spm, grad, cpad, dt, dx, g_vp);
+    long long n = (long long)nmodels * g.plane;
+    int blocks = (int)std::min<long long>((n + 255) / 256, 65536);
+    ac2_sum_shots_kernel<<<blocks, 256, 0, s>>>(g, nmodels, spm, grad, acc);
+    n = (long long)nmodels * g.nz * g.nx;
+    blocks = (int)std::min<long long>((n + 255) / 256, 65536);
+    ac2_finalize_kernel<<<blocks, 256, 0, s>>>(g, nmodels, acc, cpad, dt, dx, g_vp);
 }
 
 } // namespace sg

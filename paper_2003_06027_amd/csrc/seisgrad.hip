@@ -50,8 +50,8 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     Grid2 g;
     int K, nseg;
-    size_t off_chat, off_cpad, off_hx, off_hz, off_fwd, off_adj, off_ckpt, off_snap,
-        off_grad, off_tiles, off_src, off_recoff, off_recent, off_part, total;
+    size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
+        off_grad, off_src, off_recoff, off_recent, off_part, total;
     int ntiles;
     long long field;   // floats per field over max_shots
 };
@@ -90,14 +90,12 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
     L.off_chat = take(sizeof(float) * d->nmodels * g.plane);
     L.off_cpad = take(sizeof(float) * d->nmodels * g.plane);
-    L.off_hx = take(sizeof(float) * g.NX);
-    L.off_hz = take(sizeof(float) * g.NZ);
-    L.off_fwd = take(sizeof(float) * 6 * L.field);        // u[2], phx[2], phz[2]
-    L.off_adj = take(sizeof(float) * 6 * L.field);        // s[2], bx[2], bz[2]
+    L.off_tab = take(sizeof(float) * 3 * (g.NX + g.NZ));  // h, (1-h)/(1+h), 1/(1+h) per axis
+    L.off_fwd = take(sizeof(float) * 4 * L.field);        // u[2], phx, phz
+    L.off_adj = take(sizeof(float) * 4 * L.field);        // s[2], cx, cz
     L.off_ckpt = take(sizeof(float) * (size_t)L.nseg * 4 * L.field);
     L.off_snap = take(sizeof(float) * (size_t)L.K * L.field);
     L.off_grad = take(sizeof(float) * L.field);
-    L.off_tiles = take(sizeof(int2) * L.ntiles);
     L.off_src = take(sizeof(int) * max_shots);
     L.off_recoff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_recent = take(sizeof(int) * std::max<size_t>(1, (size_t)max_shots * max_rec));
@@ -113,15 +111,12 @@ struct sg_model {
     Layout L;
     int max_shots, max_rec;
     char *ws;
-    float *chat, *cpad, *hx, *hz;
-    float *fwd[6], *adj[6];
+    float *chat, *cpad, *hx, *hz, *px, *pz, *ihx, *ihz;
+    float *fwd[4], *adj[4];
     float *ckpt, *snap, *grad;
-    int2 *tiles;
-    int n_pml, n_int;   // tiles [0, n_pml) are PML tiles, the rest interior
     int *src_cell, *rec_off, *rec_ent;
     double *partials;
-    std::vector<float> h_hx, h_hz;
-    std::vector<int2> h_tiles;
+    std::vector<float> h_tab;
     std::vector<int> h_src, h_off, h_ent;
     std::vector<int32_t> geom_src, geom_rec;  // geometry as uploaded
     int geom_nshots = -1, geom_nrec = -1;
@@ -216,30 +211,6 @@ int check_shots(const sg_model *m, const sg_shots *sh)
     return SG_OK;
 }
 
-Ac2FwdArgs fwd_args(const sg_model *m, int ns, const float *wav, int cu, int cp)
-{
-    Ac2FwdArgs a{};
-    a.g = m->L.g;
-    a.u = m->fwd[cu];
-    a.um = m->fwd[1 - cu];
-    a.chat = m->chat;
-    a.shots_per_model = ns / m->d.nmodels;
-    a.phx_old = m->fwd[2 + cp];
-    a.phx_new = m->fwd[3 - cp];
-    a.phz_old = m->fwd[4 + cp];
-    a.phz_new = m->fwd[5 - cp];
-    a.hx = m->hx;
-    a.hz = m->hz;
-    a.src_cell = m->src_cell;
-    a.wav = wav;
-    a.nt = m->d.nt;
-    a.src_scale = (float)(m->d.dt * m->d.dt / (m->d.dx * m->d.dx));
-    a.rec_off = m->rec_off;
-    a.rec_ent = m->rec_ent;
-    a.nrec = m->geom_nrec;
-    return a;
-}
-
 hipEvent_t take_event(sg_model *m)
 {
     if (!m->pool.empty()) {
@@ -269,15 +240,43 @@ void span_end(sg_model *m, int i, hipStream_t s)
     if (i >= 0) (void)hipEventRecord(m->spans[i].b, s);
 }
 
-void fwd_step(const sg_model *m, Ac2FwdArgs a, int ns, int k, float *seis, float *snap, hipStream_t s)
+Ac2FwdArgs fwd_args(const sg_model *m, int ns, const float *wav, int cu)
 {
+    Ac2FwdArgs a{};
+    a.g = m->L.g;
+    a.nshots = ns;
+    a.u = m->fwd[cu];
+    a.um = m->fwd[1 - cu];
+    a.chat = m->chat;
+    a.shots_per_model = ns / m->d.nmodels;
+    a.phx = m->fwd[2];
+    a.phz = m->fwd[3];
+    a.hx = m->hx;
+    a.hz = m->hz;
+    a.src_cell = m->src_cell;
+    a.wav = wav;
+    a.nt = m->d.nt;
+    a.src_scale = (float)(m->d.dt * m->d.dt / (m->d.dx * m->d.dx));
+    a.rec_off = m->rec_off;
+    a.rec_ent = m->rec_ent;
+    a.nrec = m->geom_nrec;
+    return a;
+}
+
+// One forward step: layer auxiliary fields from u^k, then the tile update.
+void fwd_step(const sg_model *m, Ac2FwdArgs a, int k, float *seis, float *snap, hipStream_t s)
+{
+    Ac2PhiArgs p{};
+    p.g = a.g;
+    p.u = a.u;
+    p.phx = m->fwd[2];
+    p.phz = m->fwd[3];
+    p.hx = m->hx; p.hz = m->hz; p.px = m->px; p.pz = m->pz; p.ihx = m->ihx; p.ihz = m->ihz;
+    launch_ac2_phi(p, a.nshots, s);
     a.k = k;
     a.seis = seis;
     a.snap = snap;
-    a.tiles = m->tiles;
-    launch_ac2_fwd(a, m->n_pml, ns, true, s);
-    a.tiles = m->tiles + m->n_pml;
-    launch_ac2_fwd(a, m->n_int, ns, false, s);
+    launch_ac2_fwd(a, s);
 }
 
 } // namespace
@@ -343,46 +342,42 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     m->ws = static_cast<char *>(ws);
     m->chat = reinterpret_cast<float *>(m->ws + L.off_chat);
     m->cpad = reinterpret_cast<float *>(m->ws + L.off_cpad);
-    m->hx = reinterpret_cast<float *>(m->ws + L.off_hx);
-    m->hz = reinterpret_cast<float *>(m->ws + L.off_hz);
-    for (int i = 0; i < 6; ++i) {
+    float *tab = reinterpret_cast<float *>(m->ws + L.off_tab);
+    m->hx = tab;
+    m->px = tab + g.NX;
+    m->ihx = tab + 2 * g.NX;
+    m->hz = tab + 3 * g.NX;
+    m->pz = m->hz + g.NZ;
+    m->ihz = m->hz + 2 * g.NZ;
+    for (int i = 0; i < 4; ++i) {
         m->fwd[i] = reinterpret_cast<float *>(m->ws + L.off_fwd) + i * L.field;
         m->adj[i] = reinterpret_cast<float *>(m->ws + L.off_adj) + i * L.field;
     }
     m->ckpt = reinterpret_cast<float *>(m->ws + L.off_ckpt);
     m->snap = reinterpret_cast<float *>(m->ws + L.off_snap);
     m->grad = reinterpret_cast<float *>(m->ws + L.off_grad);
-    m->tiles = reinterpret_cast<int2 *>(m->ws + L.off_tiles);
     m->src_cell = reinterpret_cast<int *>(m->ws + L.off_src);
     m->rec_off = reinterpret_cast<int *>(m->ws + L.off_recoff);
     m->rec_ent = reinterpret_cast<int *>(m->ws + L.off_recent);
     m->partials = reinterpret_cast<double *>(m->ws + L.off_part);
 
-    // damping tables h = zeta dt / 2 (FP64, rounded once)
-    auto profile = [&](int n, std::vector<float> &h) {
-        h.assign(n + 2 * d->npml, 0.f);
+    // damping tables per axis, FP64 rounded once: h = zeta dt / 2,
+    // p = (1-h)/(1+h), 1/(1+h)
+    auto profile = [&](int n, float *h, float *p, float *ih) {
         for (int i = 0; i < n + 2 * d->npml; ++i) {
             int depth = i < d->npml ? d->npml - i : (i >= d->npml + n ? i - (d->npml + n - 1) : 0);
             const double r = d->npml > 0 ? (double)depth / d->npml : 0.0;
-            h[i] = (float)(0.5 * d->dt * zmax * r * r);
+            const double hv = 0.5 * d->dt * zmax * r * r;
+            h[i] = (float)hv;
+            p[i] = (float)((1.0 - hv) / (1.0 + hv));
+            ih[i] = (float)(1.0 / (1.0 + hv));
         }
     };
-    profile(d->nx, m->h_hx);
-    profile(d->nz, m->h_hz);
-    // tiles: those within 4 cells of the layer first (PML kernel), then interior
-    for (int pass = 0; pass < 2; ++pass)
-        for (int tz = 0; tz < g.ntz; ++tz)
-            for (int tx = 0; tx < g.ntx; ++tx) {
-                const int x0 = tx * TX, z0 = tz * TZ;
-                const bool pml = g.P > 0 && (x0 - 4 < g.P || x0 + TX + 4 > g.P + g.nx ||
-                                             z0 - 4 < g.P || z0 + TZ + 4 > g.P + g.nz);
-                if (pml == (pass == 0)) m->h_tiles.push_back(make_int2(tx, tz));
-                if (pass == 0 && pml) ++m->n_pml;
-            }
-    m->n_int = L.ntiles - m->n_pml;
-    hipError_t e = hipMemcpyAsync(m->hx, m->h_hx.data(), sizeof(float) * g.NX, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(m->hz, m->h_hz.data(), sizeof(float) * g.NZ, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(m->tiles, m->h_tiles.data(), sizeof(int2) * L.ntiles, hipMemcpyHostToDevice, s);
+    m->h_tab.assign(3 * (g.NX + g.NZ), 0.f);
+    float *ht = m->h_tab.data();
+    profile(d->nx, ht, ht + g.NX, ht + 2 * g.NX);
+    profile(d->nz, ht + 3 * g.NX, ht + 3 * g.NX + g.NZ, ht + 3 * g.NX + 2 * g.NZ);
+    hipError_t e = hipMemcpyAsync(tab, ht, sizeof(float) * m->h_tab.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         delete m;
         return fail(SG_EDEVICE, "upload failed: %s", hipGetErrorString(e));
@@ -410,8 +405,8 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     const int ns = sh->nshots, nt = m->d.nt, K = m->L.K;
     const Grid2 &g = m->L.g;
     const long long fs = (long long)ns * g.plane;  // floats of one field over the batch
-    for (int i = 0; i < 6; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
-    int cu = 0, cp = 0;
+    for (int i = 0; i < 4; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
+    int cu = 0;
     int span = -1;
     for (int k = 0; k < nt; ++k) {
         if (k % K == 0) {
@@ -422,12 +417,11 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
             float *ck = m->ckpt + (size_t)(k / K) * 4 * m->L.field;
             HIPCHECK(hipMemcpyAsync(ck, m->fwd[cu], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
             HIPCHECK(hipMemcpyAsync(ck + m->L.field, m->fwd[1 - cu], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-            HIPCHECK(hipMemcpyAsync(ck + 2 * m->L.field, m->fwd[2 + cp], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-            HIPCHECK(hipMemcpyAsync(ck + 3 * m->L.field, m->fwd[4 + cp], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+            HIPCHECK(hipMemcpyAsync(ck + 2 * m->L.field, m->fwd[2], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+            HIPCHECK(hipMemcpyAsync(ck + 3 * m->L.field, m->fwd[3], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
         }
-        fwd_step(m, fwd_args(m, ns, sh->wavelet, cu, cp), ns, k, sh->nrec > 0 ? seis : nullptr, nullptr, s);
+        fwd_step(m, fwd_args(m, ns, sh->wavelet, cu), k, sh->nrec > 0 ? seis : nullptr, nullptr, s);
         cu = 1 - cu;
-        cp = 1 - cp;
     }
     span_end(m, span, s);
     HIPCHECK(hipGetLastError());
@@ -466,11 +460,14 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     const int nt = m->d.nt, K = m->L.K;
     const Grid2 &g = m->L.g;
     const long long fs = (long long)ns * g.plane;
-    for (int i = 0; i < 6; ++i) launch_fill(m->adj[i], fs, 0.f, s);
+    for (int i = 0; i < 4; ++i) launch_fill(m->adj[i], fs, 0.f, s);
     launch_fill(m->grad, fs, 0.f, s);
 
     Ac2AdjArgs b{};
     b.g = g;
+    b.nshots = ns;
+    b.cx = m->adj[2];
+    b.cz = m->adj[3];
     b.chat = m->chat;
     b.shots_per_model = ns / m->d.nmodels;
     b.hx = m->hx;
@@ -484,21 +481,27 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     b.dJdd = dJ_dd;
     b.nrec = sh->nrec;
     b.grad = m->grad;
-    int ca = 0, cb = 0;   // s^{k+2} = adj[ca], s^{k+3} = adj[1-ca]; b^{k+2} = adj[2+cb] / adj[4+cb]
+    Ac2PhiAdjArgs pa{};
+    pa.g = g;
+    pa.chat = m->chat;
+    pa.shots_per_model = b.shots_per_model;
+    pa.cx = m->adj[2];
+    pa.cz = m->adj[3];
+    pa.hx = m->hx; pa.hz = m->hz; pa.px = m->px; pa.pz = m->pz; pa.ihx = m->ihx; pa.ihz = m->ihz;
+    int ca = 0;   // s^{k+2} = adj[ca], s^{k+3} = adj[1-ca]
     for (int seg = m->L.nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * K, k1 = std::min(k0 + K, nt);
         const float *ck = m->ckpt + (size_t)seg * 4 * m->L.field;
         HIPCHECK(hipMemcpyAsync(m->fwd[0], ck, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
         HIPCHECK(hipMemcpyAsync(m->fwd[1], ck + m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
         HIPCHECK(hipMemcpyAsync(m->fwd[2], ck + 2 * m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        HIPCHECK(hipMemcpyAsync(m->fwd[4], ck + 3 * m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        int cu = 0, cp = 0;
+        HIPCHECK(hipMemcpyAsync(m->fwd[3], ck + 3 * m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+        int cu = 0;
         int span = span_begin(m, 1, k1 - k0, s);
         for (int k = k0; k < k1; ++k) {
             float *snap = m->snap + (size_t)(k - k0) * m->L.field;
-            fwd_step(m, fwd_args(m, ns, sh->wavelet, cu, cp), ns, k, nullptr, snap, s);
+            fwd_step(m, fwd_args(m, ns, sh->wavelet, cu), k, nullptr, snap, s);
             cu = 1 - cu;
-            cp = 1 - cp;
         }
         span_end(m, span, s);
         span = span_begin(m, 2, k1 - k0, s);
@@ -507,20 +510,15 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
             b.snap = m->snap + (size_t)(k - k0) * m->L.field;
             b.s2 = m->adj[ca];
             b.s3 = m->adj[1 - ca];
-            b.bx_old = m->adj[2 + cb];
-            b.bx_new = m->adj[3 - cb];
-            b.bz_old = m->adj[4 + cb];
-            b.bz_new = m->adj[5 - cb];
-            b.tiles = m->tiles;
-            launch_ac2_adj(b, m->n_pml, ns, true, s);
-            b.tiles = m->tiles + m->n_pml;
-            launch_ac2_adj(b, m->n_int, ns, false, s);
+            pa.s2 = b.s2;
+            launch_ac2_phi_adj(pa, ns, s);
+            launch_ac2_adj(b, s);
             ca = 1 - ca;
-            cb = 1 - cb;
         }
         span_end(m, span, s);
     }
-    launch_ac2_finalize(g, m->d.nmodels, ns / m->d.nmodels, m->grad, m->cpad, m->d.dt, m->d.dx, g_vp, s);
+    // the snapshot buffer (free now) holds the per-model shot sums
+    launch_ac2_finalize(g, m->d.nmodels, ns / m->d.nmodels, m->grad, m->snap, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }

@@ -19,6 +19,9 @@ constexpr int RPT = TZ / (NTH / TX);
 constexpr int OX = 32;
 constexpr int OZ = 8;
 
+// Accelerator complex dies of an MI355X (workgroups are dealt round-robin).
+constexpr int NXCD = 8;
+
 struct Grid2 {
     int NX, NZ;      // padded grid
     int P, nx, nz;   // layer width, physical extents
@@ -27,36 +30,54 @@ struct Grid2 {
     int ntx, ntz;    // tiles
 };
 
+// Forward pass A: phi~^k = p phi~^{k-1} + q D~ u^k on the layer cells.
+struct Ac2PhiArgs {
+    Grid2 g;
+    const float *u;                   // u^k [shot][plane]
+    float *phx, *phz;                 // phi~ in place
+    const float *hx, *hz;             // h = zeta dt / 2 on the padded grid
+    const float *px, *pz, *ihx, *ihz; // (1-h)/(1+h) and 1/(1+h)
+};
+
+// Forward pass B over (tile, shot) pairs.
 struct Ac2FwdArgs {
     Grid2 g;
-    const int2 *tiles;      // (tx, tz) of the tiles of this launch
+    int nshots;
     const float *u;         // u^k       [shot][plane]
     float *um;              // u^{k-1} in, u^{k+1} out (same cells)
     const float *chat;      // dt^2 c^2 / dx^2  [model][plane]
     int shots_per_model;
-    const float *phx_old, *phz_old; // scaled phi^{k-1} (dx * phi)
-    float *phx_new, *phz_new;       // scaled phi^k
-    const float *hx, *hz;   // zeta dt / 2 on the padded grid
+    const float *phx, *phz; // phi~^k
+    const float *hx, *hz;
     const int *src_cell;    // [shot] frame index of the source node
     const float *wav;       // [shot][nt]
     int nt, k;
     float src_scale;        // dt^2 / (dx dz)
     const int *rec_off;     // [shot][ntiles + 1] CSR over tiles
-    const int *rec_ent;     // packed (local cell << 20 | receiver id)... see host
+    const int *rec_ent;     // rec_pack(local cell, receiver id), sorted by cell per tile
     float *seis;            // [shot][nt][nrec] or null
     int nrec;
     float *snap;            // w~^k [shot][plane] of this step, or null
 };
 
+// Adjoint pass A: c^{k+1} = p c^{k+2} - q D~(chat s^{k+2}) on the layer cells.
+struct Ac2PhiAdjArgs {
+    Grid2 g;
+    const float *s2;        // s^{k+2}
+    const float *chat;
+    int shots_per_model;
+    float *cx, *cz;         // q-scaled adjoint of phi~, in place
+    const float *hx, *hz, *px, *pz, *ihx, *ihz;
+};
+
 struct Ac2AdjArgs {
     Grid2 g;
-    const int2 *tiles;
+    int nshots;
     const float *s2;        // s^{k+2}  (alpha-scaled adjoint), read with halo
     float *s3;              // s^{k+3} in, s^{k+1} out
     const float *chat;
     int shots_per_model;
-    const float *bx_old, *bz_old; // adjoint of scaled phi^{k+2}
-    float *bx_new, *bz_new;       // adjoint of scaled phi^{k+1}
+    const float *cx, *cz;   // c^{k+1}
     const float *hx, *hz;
     const int *src_cell;
     float *gwav;            // [shot][nt] or null
@@ -70,12 +91,15 @@ struct Ac2AdjArgs {
     float *grad;            // dJ/dchat per shot [shot][plane], accumulated
 };
 
-void launch_ac2_fwd(const Ac2FwdArgs &a, int ntiles, int nshots, bool pml, hipStream_t s);
-void launch_ac2_adj(const Ac2AdjArgs &a, int ntiles, int nshots, bool pml, hipStream_t s);
+void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s);
+void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s);
+void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s);
+void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s);
 void launch_ac2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx,
                      float *chat, float *cpad, hipStream_t s);
 void launch_ac2_finalize(const Grid2 &g, int nmodels, int shots_per_model, const float *grad,
-                         const float *cpad, double dt, double dx, float *g_vp, hipStream_t s);
+                         float *acc, const float *cpad, double dt, double dx, float *g_vp,
+                         hipStream_t s);
 void launch_fill(float *p, long long n, float v, hipStream_t s);
 void launch_misfit(const float *pred, const float *obs, long long n, float *resid,
                    double *partials, int nparts, double *J, hipStream_t s);
