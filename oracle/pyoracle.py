@@ -156,3 +156,71 @@ def greens2d_ricker(r, c, t, f0, t0, nq=4000):
         s = (1.0 - 2.0 * a) * np.exp(-a)
         out[i] = 0.5 * top * np.dot(wg, s) / (2.0 * np.pi * c * c)
     return out
+
+
+# ---------------------------------------------------------------- acoustic 3-D
+def _ptrs(arrs):
+    arr_t = _dp * len(arrs)
+    return arr_t(*[_d(a) for a in arrs])
+
+
+def ac3_pad(g, c):
+    P = g.npml
+    sh = (g.nz + 2 * P, g.ny + 2 * P, g.nx + 2 * P)
+    cp = np.zeros(sh)
+    zx, zy, zz = np.zeros(sh[2]), np.zeros(sh[1]), np.zeros(sh[0])
+    lib().or_ac3_pad(C.byref(g), _d(_f64(c)), _d(cp), _d(zx), _d(zy), _d(zz))
+    return cp, zx, zy, zz
+
+
+def ac3_step(g, c_pad, X, src_idx=-1, src_val=0.0):
+    """X = (u, um, phix, phiy, phiz, psi) padded arrays -> (Y list, w)."""
+    X = [_f64(x) for x in X]
+    Y = [np.zeros_like(X[0]) for _ in range(6)]
+    w = np.zeros_like(X[0])
+    lib().or_ac3_step(C.byref(g), _d(_f64(c_pad)), _ptrs(X), C.c_int64(src_idx), C.c_double(src_val),
+                      _ptrs(Y), _d(w))
+    return Y, w
+
+
+def ac3_step_T(g, c_pad, X, aY, src_idx=-1):
+    X = [_f64(x) for x in X]
+    aY = [_f64(x) for x in aY]
+    aX = [np.zeros_like(X[0]) for _ in range(6)]
+    gC = np.zeros_like(X[0])
+    sb = C.c_double(0.0)
+    lib().or_ac3_step_T(C.byref(g), _d(_f64(c_pad)), _ptrs(X), _ptrs(aY), _ptrs(aX), _d(gC),
+                        C.c_int64(src_idx), C.byref(sb))
+    return aX, gC, sb.value
+
+
+def ac3_forward(g, c, src, wav, rec):
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    ns, nrec = src.shape[0], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    if lib().or_ac3_forward(C.byref(g), _d(_f64(c)), C.c_int32(ns), _i(src), _d(wav),
+                            C.c_int32(nrec), _i(rec), _d(seis)):
+        raise ValueError("oracle: invalid geometry or grid")
+    return seis
+
+
+def ac3_gradient(g, c, src, wav, rec, dJdd, ckpt=0, want_wav=False):
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    ns, nrec = src.shape[0], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    grad = np.zeros((g.nz, g.ny, g.nx))
+    gw = np.zeros((ns, g.nt)) if want_wav else None
+    if lib().or_ac3_gradient(C.byref(g), _d(_f64(c)), C.c_int32(ns), _i(src), _d(wav),
+                             C.c_int32(nrec), _i(rec), _d(_f64(dJdd)), C.c_int32(ckpt),
+                             _d(grad), _d(seis), _d(gw) if want_wav else None):
+        raise ValueError("oracle: invalid geometry or grid")
+    return (grad, seis, gw) if want_wav else (grad, seis)
+
+
+def greens3d_ricker(r, c, t, f0, t0):
+    """u_tt = c^2 lap u + delta(x) s(t) in infinite 3-D space:
+    u(r, t) = s(t - r/c) / (4 pi c^2 r)."""
+    tau = np.asarray(t, dtype=np.float64) - r / c
+    a = (np.pi * f0 * (tau - t0)) ** 2
+    s = np.where(tau >= 0, (1.0 - 2.0 * a) * np.exp(-a), 0.0)
+    return s / (4.0 * np.pi * c * c * r)
