@@ -17,13 +17,16 @@
  *     paper's Theorem shows equal to reverse-mode AD (Eqs. (8)-(9)).
  *
  * Conventions
- *   - Physical model arrays: FP32, row-major [model][iz][ix] (2-D),
- *     x fastest, z down, 0-based.  The absorbing layer of npml cells is padded
+ *   - Physical model arrays: FP32, row-major [model][iz][ix] (2-D) or
+ *     [model][iz][iy][ix] (3-D), x fastest, z down, 0-based.  The absorbing layer of npml cells is padded
  *     OUTSIDE the physical grid on every side, the model being continued by
  *     edge replication; cells beyond the padded grid are zero (rigid).
  *   - Time: u^0 = u^{-1} = 0; step k (0..nt-1) injects wavelet sample k;
  *     seismogram sample k holds u^{k+1} at the receivers.
- *   - Source: a point source at a grid node, f = r(t_k) / (dx*dz).
+ *   - Source: a point source at a grid node, f = r(t_k) / (dx*dz) in 2-D,
+ *     r(t_k) / dx^3 in 3-D.
+ *   - 3-D absorbing layer: the auxiliary-field form of complex coordinate
+ *     stretching with psi = time integral of u (phi_x, phi_y, phi_z, psi).
  *   - Seismograms: FP32 [nshots][ncomp][nt][nrec] (ncomp = 1 acoustic).
  *   - Shots are ordered model-major: with nmodels models, shot s uses model
  *     s / (nshots / nmodels); nshots must be a multiple of nmodels.
@@ -81,7 +84,7 @@ enum { SG_ACOUSTIC = 0, SG_ELASTIC = 1 };
 
 /* Grid, time stepping and absorbing layer. */
 typedef struct sg_desc {
-    int32_t ndim;       /* 2 (3-D: SG_EUNSUPPORTED in this build) */
+    int32_t ndim;       /* 2 or 3 */
     int32_t physics;    /* SG_ACOUSTIC */
     int32_t nx, ny, nz; /* physical cells; ny = 1 in 2-D */
     int32_t npml;       /* absorbing-layer width in cells (>= 0) */
@@ -98,8 +101,8 @@ typedef struct sg_desc {
 typedef struct sg_shots {
     int32_t nshots;          /* >= 1, multiple of nmodels, <= max_shots of the model */
     int32_t nrec;            /* receivers per shot (>= 0) */
-    const int32_t *src;      /* HOST [nshots][ndim]: (ix, iz) physical source node */
-    const int32_t *rec;      /* HOST [nshots][nrec][ndim]: (ix, iz) receiver nodes */
+    const int32_t *src;      /* HOST [nshots][ndim]: (ix, iz) or (ix, iy, iz) source node */
+    const int32_t *rec;      /* HOST [nshots][nrec][ndim]: receiver nodes, same order */
     const float *wavelet;    /* DEVICE [nshots][nt]: source time function r(t_k) */
 } sg_shots;
 
@@ -116,7 +119,7 @@ SG_API size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_r
  * (8th-order leapfrog limit c dt/dx <= 2/sqrt(6.5016 ndim), rejected above
  * 0.95 of it), pad the velocity by edge replication, form C = dt^2 c^2 on the
  * padded grid and the damping tables.
- *   vp:  DEVICE FP32 [nmodels][nz][nx] velocity (m/s), > 0;
+ *   vp:  DEVICE FP32 [nmodels][nz]([ny])[nx] velocity (m/s), > 0;
  *   vs, rho: reserved for elastic, must be NULL;
  *   ws:  DEVICE workspace, 256-byte aligned, of
  *        ws_bytes >= workspace_bytes(d, max_shots, max_rec, ckpt_every);
@@ -155,7 +158,7 @@ SG_API int misfit(sg_model *m, const float *pred, const float *obs, int64_t n,
  * from its checkpoint and runs the exact transpose of the forward step
  * backwards in time.
  *   dJ_dd: DEVICE FP32 [nshots][1][nt][nrec];
- *   g_vp:  DEVICE FP32 [nmodels][nz][nx], sum over the model's shots in shot
+ *   g_vp:  DEVICE FP32 [nmodels][nz]([ny])[nx], sum over the model's shots in shot
  *          order, absorbing-layer cells folded onto the edge cells they
  *          replicate;
  *   g_vs, g_rho: reserved, NULL;

@@ -32,8 +32,9 @@
 
 namespace sg {
 
-// 8th-order centred weights: second derivative and first derivative.
-constexpr float A0 = (float)(-205.0 / 72.0);
+// 8th-order centred weights: second derivative (a_1..a_4; the centre weight
+// -205/72 = -2 sum a_m is folded into the difference form below) and first
+// derivative.
 constexpr float A1 = (float)(8.0 / 5.0);
 constexpr float A2 = (float)(-1.0 / 5.0);
 constexpr float A3 = (float)(8.0 / 315.0);
@@ -174,7 +175,7 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
 
     const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
     float *um = a.um + so;
-    const long long src = a.src_cell[shot];
+    const long long src = a.src_f[shot];
     const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
     float un[RPT];
 #pragma unroll
@@ -335,7 +336,7 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
         }
     }
 
-    const long long src = a.src_cell[shot];
+    const long long src = a.src_f[shot];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int r = ly * RPT + j, iz = z0 + r;

@@ -10,8 +10,8 @@
 #include "sg_internal.h"
 
 #include <algorithm>
-#include <cstdarg>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -44,61 +44,92 @@ int fail(int code, const char *fmt, ...)
 
 constexpr double L8_SYMBOL_MAX = 6.501587301587301; // max |1-D 8th-order symbol| * dx^2
 constexpr size_t ALIGN = 256;
+constexpr int TABPAD = 4;   // damping tables carry 4 neutral entries on each side
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    Grid2 g;
+    int ndim;
+    Grid2 g2;
+    Grid3 g3;
+    long long plane;   // floats per field per shot
+    int ntiles;        // 2-D tiles, or 3-D xy tiles
+    int nf;            // wavefield state fields (checkpointed)
     int K, nseg;
+    long long field;   // floats of one field over max_shots
+    int n[3];          // padded extents x, y, z (y = 1 in 2-D)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
         off_grad, off_src, off_recoff, off_recent, off_part, total;
-    int ntiles;
-    long long field;   // floats per field over max_shots
 };
 
 int check_desc(const sg_desc *d)
 {
     if (!d) return fail(SG_EINVAL, "descriptor is NULL");
     if (d->physics != SG_ACOUSTIC) return fail(SG_EUNSUPPORTED, "physics %d is not provided by this build", d->physics);
-    if (d->ndim != 2) return fail(SG_EUNSUPPORTED, "ndim %d is not provided by this build", d->ndim);
-    if (d->nx < 1 || d->nz < 1 || d->npml < 0 || d->nt < 1 || d->nmodels < 1)
-        return fail(SG_EINVAL, "bad grid: nx=%d nz=%d npml=%d nt=%d nmodels=%d", d->nx, d->nz, d->npml, d->nt, d->nmodels);
+    if (d->ndim != 2 && d->ndim != 3) return fail(SG_EUNSUPPORTED, "ndim %d is not provided by this build", d->ndim);
+    const int ny = d->ndim == 3 ? d->ny : 1;
+    if (d->nx < 1 || d->nz < 1 || ny < 1 || d->npml < 0 || d->nt < 1 || d->nmodels < 1)
+        return fail(SG_EINVAL, "bad grid: nx=%d ny=%d nz=%d npml=%d nt=%d nmodels=%d", d->nx, d->ny, d->nz,
+                    d->npml, d->nt, d->nmodels);
     if (!(d->dx > 0) || !(d->dt > 0)) return fail(SG_EINVAL, "dx and dt must be positive");
     if (d->npml > 0 && (!(d->pml_R > 0 && d->pml_R < 1) || !(d->pml_vmax > 0)))
         return fail(SG_EINVAL, "absorbing layer needs 0 < pml_R < 1 and pml_vmax > 0");
-    if ((long long)(d->nx + 2 * d->npml) * (d->nz + 2 * d->npml) > (1LL << 31))
-        return fail(SG_EINVAL, "grid too large");
+    const long long cells = (long long)(d->nx + 2 * d->npml) * (ny + (d->ndim == 3 ? 2 * d->npml : 0)) *
+                            (d->nz + 2 * d->npml);
+    if (cells > (1LL << 33)) return fail(SG_EINVAL, "grid too large");
     return SG_OK;
 }
 
 Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
 {
     Layout L{};
-    Grid2 &g = L.g;
-    g.P = d->npml; g.nx = d->nx; g.nz = d->nz;
-    g.NX = d->nx + 2 * d->npml; g.NZ = d->nz + 2 * d->npml;
-    g.ntx = (g.NX + TX - 1) / TX; g.ntz = (g.NZ + TZ - 1) / TZ;
-    g.SX = OX + g.ntx * TX + 32;
-    g.SZ = OZ + g.ntz * TZ + 8;
-    g.plane = (long long)g.SX * g.SZ;
-    L.ntiles = g.ntx * g.ntz;
+    L.ndim = d->ndim;
+    const int P = d->npml;
+    if (d->ndim == 2) {
+        Grid2 &g = L.g2;
+        g.P = P; g.nx = d->nx; g.nz = d->nz;
+        g.NX = d->nx + 2 * P; g.NZ = d->nz + 2 * P;
+        g.ntx = (g.NX + TX - 1) / TX; g.ntz = (g.NZ + TZ - 1) / TZ;
+        g.SX = OX + g.ntx * TX + 32;
+        g.SZ = OZ + g.ntz * TZ + 8;
+        g.plane = (long long)g.SX * g.SZ;
+        L.plane = g.plane;
+        L.ntiles = g.ntx * g.ntz;
+        L.nf = 4;
+        L.n[0] = g.NX; L.n[1] = 1; L.n[2] = g.NZ;
+    } else {
+        Grid3 &g = L.g3;
+        g.P = P; g.nx = d->nx; g.ny = d->ny; g.nz = d->nz;
+        g.NX = d->nx + 2 * P; g.NY = d->ny + 2 * P; g.NZ = d->nz + 2 * P;
+        g.ntx = (g.NX + TX3 - 1) / TX3; g.nty = (g.NY + TY3 - 1) / TY3; g.nzc = (g.NZ + TZC - 1) / TZC;
+        g.SX = OX3 + g.ntx * TX3 + 32;
+        g.SY = OY3 + g.nty * TY3 + 4;
+        g.SZ = OZ3 + g.NZ + 4;
+        g.sy = g.SX;
+        g.sz = (long long)g.SX * g.SY;
+        g.plane = g.sz * g.SZ;
+        L.plane = g.plane;
+        L.ntiles = g.ntx * g.nty;
+        L.nf = 6;
+        L.n[0] = g.NX; L.n[1] = g.NY; L.n[2] = g.NZ;
+    }
     L.K = ckpt > 0 ? ckpt : (int)std::ceil(std::sqrt((double)d->nt));
     if (L.K > d->nt) L.K = d->nt;
     L.nseg = (d->nt + L.K - 1) / L.K;
-    L.field = (long long)max_shots * g.plane;
+    L.field = (long long)max_shots * L.plane;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
-    L.off_chat = take(sizeof(float) * d->nmodels * g.plane);
-    L.off_cpad = take(sizeof(float) * d->nmodels * g.plane);
-    L.off_tab = take(sizeof(float) * 3 * (g.NX + g.NZ));  // h, (1-h)/(1+h), 1/(1+h) per axis
-    L.off_fwd = take(sizeof(float) * 4 * L.field);        // u[2], phx, phz
-    L.off_adj = take(sizeof(float) * 4 * L.field);        // s[2], cx, cz
-    L.off_ckpt = take(sizeof(float) * (size_t)L.nseg * 4 * L.field);
+    L.off_chat = take(sizeof(float) * d->nmodels * L.plane);
+    L.off_cpad = take(sizeof(float) * d->nmodels * L.plane);
+    L.off_tab = take(sizeof(float) * 3 * (L.n[0] + L.n[1] + L.n[2] + 6 * TABPAD));
+    L.off_fwd = take(sizeof(float) * L.nf * L.field);
+    L.off_adj = take(sizeof(float) * L.nf * L.field);
+    L.off_ckpt = take(sizeof(float) * (size_t)L.nseg * L.nf * L.field);
     L.off_snap = take(sizeof(float) * (size_t)L.K * L.field);
     L.off_grad = take(sizeof(float) * L.field);
-    L.off_src = take(sizeof(int) * max_shots);
+    L.off_src = take(sizeof(long long) * max_shots);
     L.off_recoff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
-    L.off_recent = take(sizeof(int) * std::max<size_t>(1, (size_t)max_shots * max_rec));
+    L.off_recent = take(sizeof(int2) * std::max<size_t>(1, (size_t)max_shots * max_rec));
     L.off_part = take(sizeof(double) * 4096);
     L.total = o;
     return L;
@@ -111,17 +142,21 @@ struct sg_model {
     Layout L;
     int max_shots, max_rec;
     char *ws;
-    float *chat, *cpad, *hx, *hz, *px, *pz, *ihx, *ihz;
-    float *fwd[4], *adj[4];
+    float *chat, *cpad;
+    float *h[3], *p[3], *ih[3];   // damping tables per axis (x, y, z)
+    float *fwd[6], *adj[6];
     float *ckpt, *snap, *grad;
-    int *src_cell, *rec_off, *rec_ent;
+    long long *src_f;
+    int *rec_off;
+    void *rec_ent;
     double *partials;
     std::vector<float> h_tab;
-    std::vector<int> h_src, h_off, h_ent;
+    std::vector<long long> h_src;
+    std::vector<int> h_off, h_ent;
+    std::vector<int2> h_ent3;
     std::vector<int32_t> geom_src, geom_rec;  // geometry as uploaded
     int geom_nshots = -1, geom_nrec = -1;
     bool have_ckpt = false;
-    int ckpt_nshots = 0;
     // optional device timing of the step loops: one event pair per segment
     struct Span { int phase; int steps; hipEvent_t a, b; };
     bool profiling = false;
@@ -136,62 +171,95 @@ struct sg_model {
 
 namespace {
 
+bool same_geometry(const sg_model *m, const sg_shots *sh)
+{
+    const int nd = m->d.ndim, ns = sh->nshots;
+    return m->geom_nshots == ns && m->geom_nrec == sh->nrec &&
+           std::equal(sh->src, sh->src + (size_t)nd * ns, m->geom_src.begin()) &&
+           (sh->nrec == 0 || std::equal(sh->rec, sh->rec + (size_t)nd * ns * sh->nrec, m->geom_rec.begin()));
+}
+
 int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
 {
-    const Grid2 &g = m->L.g;
-    const int ns = sh->nshots, nrec = sh->nrec;
+    const Layout &L = m->L;
+    const int nd = m->d.ndim, ns = sh->nshots, nrec = sh->nrec, P = m->d.npml;
+    const int phys[3] = {m->d.nx, nd == 3 ? m->d.ny : 1, m->d.nz};
     if (!sh->src || (nrec > 0 && !sh->rec)) return fail(SG_EINVAL, "source/receiver arrays are NULL");
-    for (int i = 0; i < ns; ++i) {
-        const int ix = sh->src[2 * i], iz = sh->src[2 * i + 1];
-        if (ix < 0 || ix >= g.nx || iz < 0 || iz >= g.nz)
-            return fail(SG_EINVAL, "shot %d: source (%d, %d) outside the %dx%d grid", i, ix, iz, g.nx, g.nz);
-        for (int r = 0; r < nrec; ++r) {
-            const int32_t *q = sh->rec + ((size_t)i * nrec + r) * 2;
-            if (q[0] < 0 || q[0] >= g.nx || q[1] < 0 || q[1] >= g.nz)
-                return fail(SG_EINVAL, "shot %d receiver %d: (%d, %d) outside the grid", i, r, q[0], q[1]);
+    auto inside = [&](const int32_t *q) {
+        for (int c = 0; c < nd; ++c) {
+            const int axis = nd == 2 && c == 1 ? 2 : c;   // 2-D points are (ix, iz)
+            if (q[c] < 0 || q[c] >= phys[axis]) return false;
         }
+        return true;
+    };
+    for (int i = 0; i < ns; ++i) {
+        if (!inside(sh->src + (size_t)nd * i))
+            return fail(SG_EINVAL, "shot %d: source outside the %dx%dx%d grid", i, phys[0], phys[1], phys[2]);
+        for (int r = 0; r < nrec; ++r)
+            if (!inside(sh->rec + ((size_t)i * nrec + r) * nd))
+                return fail(SG_EINVAL, "shot %d receiver %d outside the grid", i, r);
     }
-    const bool same = m->geom_nshots == ns && m->geom_nrec == nrec &&
-                      std::equal(sh->src, sh->src + 2 * ns, m->geom_src.begin()) &&
-                      (nrec == 0 || std::equal(sh->rec, sh->rec + (size_t)2 * ns * nrec, m->geom_rec.begin()));
-    if (same) return SG_OK;
+    if (same_geometry(m, sh)) return SG_OK;
     // the previous upload may still be reading the host vectors
     HIPCHECK(hipStreamSynchronize(s));
-    const int ntiles = m->L.ntiles;
+    const int ntiles = L.ntiles;
     m->h_src.assign(ns, 0);
     m->h_off.assign((size_t)ns * (ntiles + 1), 0);
     m->h_ent.clear();
+    m->h_ent3.clear();
     std::vector<std::pair<long long, int>> keyed;
     for (int i = 0; i < ns; ++i) {
-        const int ix = sh->src[2 * i] + g.P, iz = sh->src[2 * i + 1] + g.P;
-        m->h_src[i] = (iz + OZ) * g.SX + ix + OX;
+        const int32_t *q = sh->src + (size_t)nd * i;
+        if (nd == 2) {
+            const Grid2 &g = L.g2;
+            m->h_src[i] = (long long)(q[1] + P + OZ) * g.SX + q[0] + P + OX;
+        } else {
+            const Grid3 &g = L.g3;
+            m->h_src[i] = (long long)(q[2] + P + OZ3) * g.sz + (long long)(q[1] + P + OY3) * g.sy + q[0] + P + OX3;
+        }
         keyed.clear();
         for (int r = 0; r < nrec; ++r) {
-            const int32_t *q = sh->rec + ((size_t)i * nrec + r) * 2;
-            const int px = q[0] + g.P, pz = q[1] + g.P;
-            const int tile = (pz / TZ) * g.ntx + px / TX;
-            const int cell = (pz % TZ) * TX + px % TX;
-            keyed.push_back({(long long)tile << 32 | (long long)cell << 20 | r, rec_pack(cell, r)});
+            const int32_t *e = sh->rec + ((size_t)i * nrec + r) * nd;
+            if (nd == 2) {
+                const int px = e[0] + P, pz = e[1] + P;
+                const int tile = (pz / TZ) * L.g2.ntx + px / TX;
+                const int cell = (pz % TZ) * TX + px % TX;
+                keyed.push_back({(long long)tile << 42 | (long long)cell << 21 | r, rec_pack(cell, r)});
+            } else {
+                const int px = e[0] + P, py = e[1] + P, pz = e[2] + P;
+                const int tile = (py / TY3) * L.g3.ntx + px / TX3;
+                const int cell = (py % TY3) * TX3 + px % TX3;
+                keyed.push_back({(long long)tile << 42 | (long long)pz << 30 | (long long)cell << 21 | r, r});
+            }
         }
         std::sort(keyed.begin(), keyed.end());
         int *off = m->h_off.data() + (size_t)i * (ntiles + 1);
-        size_t base = m->h_ent.size();
-        int e = 0;
+        const size_t base = nd == 2 ? m->h_ent.size() : m->h_ent3.size();
+        size_t e = 0;
         for (int tl = 0; tl < ntiles; ++tl) {
             off[tl] = (int)(base + e);
-            while (e < (int)keyed.size() && (int)(keyed[e].first >> 32) == tl) {
-                m->h_ent.push_back(keyed[e].second);
+            while (e < keyed.size() && (int)(keyed[e].first >> 42) == tl) {
+                if (nd == 2) {
+                    m->h_ent.push_back(keyed[e].second);
+                } else {
+                    const long long k = keyed[e].first;
+                    const int pz = (int)((k >> 30) & 0xFFF), cell = (int)((k >> 21) & 0x1FF);
+                    m->h_ent3.push_back(make_int2((pz << CELL3_BITS) | cell, keyed[e].second));
+                }
                 ++e;
             }
         }
         off[ntiles] = (int)(base + e);
     }
-    HIPCHECK(hipMemcpyAsync(m->src_cell, m->h_src.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(m->src_f, m->h_src.data(), sizeof(long long) * ns, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(m->rec_off, m->h_off.data(), sizeof(int) * m->h_off.size(), hipMemcpyHostToDevice, s));
-    if (!m->h_ent.empty())
+    if (nd == 2 && !m->h_ent.empty())
         HIPCHECK(hipMemcpyAsync(m->rec_ent, m->h_ent.data(), sizeof(int) * m->h_ent.size(), hipMemcpyHostToDevice, s));
-    m->geom_src.assign(sh->src, sh->src + 2 * ns);
-    m->geom_rec.assign(sh->rec ? sh->rec : sh->src, sh->rec ? sh->rec + (size_t)2 * ns * nrec : sh->src);
+    if (nd == 3 && !m->h_ent3.empty())
+        HIPCHECK(hipMemcpyAsync(m->rec_ent, m->h_ent3.data(), sizeof(int2) * m->h_ent3.size(), hipMemcpyHostToDevice, s));
+    m->geom_src.assign(sh->src, sh->src + (size_t)nd * ns);
+    if (nrec > 0) m->geom_rec.assign(sh->rec, sh->rec + (size_t)nd * ns * nrec);
+    else m->geom_rec.clear();
     m->geom_nshots = ns;
     m->geom_nrec = nrec;
     m->have_ckpt = false;
@@ -240,43 +308,161 @@ void span_end(sg_model *m, int i, hipStream_t s)
     if (i >= 0) (void)hipEventRecord(m->spans[i].b, s);
 }
 
-Ac2FwdArgs fwd_args(const sg_model *m, int ns, const float *wav, int cu)
+float src_scale(const sg_model *m)
 {
-    Ac2FwdArgs a{};
-    a.g = m->L.g;
-    a.nshots = ns;
-    a.u = m->fwd[cu];
-    a.um = m->fwd[1 - cu];
-    a.chat = m->chat;
-    a.shots_per_model = ns / m->d.nmodels;
-    a.phx = m->fwd[2];
-    a.phz = m->fwd[3];
-    a.hx = m->hx;
-    a.hz = m->hz;
-    a.src_cell = m->src_cell;
-    a.wav = wav;
-    a.nt = m->d.nt;
-    a.src_scale = (float)(m->d.dt * m->d.dt / (m->d.dx * m->d.dx));
-    a.rec_off = m->rec_off;
-    a.rec_ent = m->rec_ent;
-    a.nrec = m->geom_nrec;
-    return a;
+    const double dx = m->d.dx;
+    return (float)(m->d.dt * m->d.dt / (m->d.ndim == 2 ? dx * dx : dx * dx * dx));
+}
+
+Ac3Tabs tabs3(const sg_model *m)
+{
+    Ac3Tabs t;
+    for (int j = 0; j < 3; ++j) { t.h[j] = m->h[j]; t.p[j] = m->p[j]; t.ih[j] = m->ih[j]; }
+    return t;
 }
 
 // One forward step: layer auxiliary fields from u^k, then the tile update.
-void fwd_step(const sg_model *m, Ac2FwdArgs a, int k, float *seis, float *snap, hipStream_t s)
+// cu selects u^k = fwd[cu], u^{k-1} = fwd[1-cu].
+void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float *seis, float *snap,
+              hipStream_t s)
 {
-    Ac2PhiArgs p{};
-    p.g = a.g;
-    p.u = a.u;
-    p.phx = m->fwd[2];
-    p.phz = m->fwd[3];
-    p.hx = m->hx; p.hz = m->hz; p.px = m->px; p.pz = m->pz; p.ihx = m->ihx; p.ihz = m->ihz;
-    launch_ac2_phi(p, a.nshots, s);
-    a.k = k;
-    a.seis = seis;
-    a.snap = snap;
-    launch_ac2_fwd(a, s);
+    if (m->d.ndim == 2) {
+        Ac2PhiArgs p{};
+        p.g = m->L.g2;
+        p.u = m->fwd[cu];
+        p.phx = m->fwd[2];
+        p.phz = m->fwd[3];
+        p.hx = m->h[0]; p.hz = m->h[2]; p.px = m->p[0]; p.pz = m->p[2]; p.ihx = m->ih[0]; p.ihz = m->ih[2];
+        launch_ac2_phi(p, ns, s);
+        Ac2FwdArgs a{};
+        a.g = m->L.g2;
+        a.nshots = ns;
+        a.u = m->fwd[cu];
+        a.um = m->fwd[1 - cu];
+        a.chat = m->chat;
+        a.shots_per_model = ns / m->d.nmodels;
+        a.phx = m->fwd[2];
+        a.phz = m->fwd[3];
+        a.hx = m->h[0];
+        a.hz = m->h[2];
+        a.src_f = m->src_f;
+        a.wav = wav;
+        a.nt = m->d.nt;
+        a.k = k;
+        a.src_scale = src_scale(m);
+        a.rec_off = m->rec_off;
+        a.rec_ent = static_cast<const int *>(m->rec_ent);
+        a.nrec = m->geom_nrec;
+        a.seis = seis;
+        a.snap = snap;
+        launch_ac2_fwd(a, s);
+    } else {
+        Ac3PhiArgs p{};
+        p.g = m->L.g3;
+        p.u = m->fwd[cu];
+        p.psi = m->fwd[5];
+        for (int j = 0; j < 3; ++j) p.ph[j] = m->fwd[2 + j];
+        p.t = tabs3(m);
+        p.inv_dt = (float)(1.0 / m->d.dt);
+        launch_ac3_phi(p, ns, s);
+        Ac3FwdArgs a{};
+        a.g = m->L.g3;
+        a.nshots = ns;
+        a.u = m->fwd[cu];
+        a.um = m->fwd[1 - cu];
+        a.chat = m->chat;
+        a.shots_per_model = ns / m->d.nmodels;
+        for (int j = 0; j < 3; ++j) a.ph[j] = m->fwd[2 + j];
+        a.psi = m->fwd[5];
+        a.t = tabs3(m);
+        a.dt = (float)m->d.dt;
+        a.inv_dt = (float)(1.0 / m->d.dt);
+        a.src_f = m->src_f;
+        a.wav = wav;
+        a.nt = m->d.nt;
+        a.k = k;
+        a.src_scale = src_scale(m);
+        a.rec_off = m->rec_off;
+        a.rec_ent = static_cast<const int2 *>(m->rec_ent);
+        a.nrec = m->geom_nrec;
+        a.seis = seis;
+        a.snap = snap;
+        launch_ac3_fwd(a, s);
+    }
+}
+
+// One adjoint step k: s^{k+2} = adj[ca], s^{k+3} = adj[1-ca] (in) / s^{k+1} (out).
+void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float *gwav,
+              const float *snap, hipStream_t s)
+{
+    const int spm = ns / m->d.nmodels;
+    if (m->d.ndim == 2) {
+        Ac2PhiAdjArgs pa{};
+        pa.g = m->L.g2;
+        pa.s2 = m->adj[ca];
+        pa.chat = m->chat;
+        pa.shots_per_model = spm;
+        pa.cx = m->adj[2];
+        pa.cz = m->adj[3];
+        pa.hx = m->h[0]; pa.hz = m->h[2]; pa.px = m->p[0]; pa.pz = m->p[2]; pa.ihx = m->ih[0]; pa.ihz = m->ih[2];
+        launch_ac2_phi_adj(pa, ns, s);
+        Ac2AdjArgs b{};
+        b.g = m->L.g2;
+        b.nshots = ns;
+        b.s2 = m->adj[ca];
+        b.s3 = m->adj[1 - ca];
+        b.chat = m->chat;
+        b.shots_per_model = spm;
+        b.cx = m->adj[2];
+        b.cz = m->adj[3];
+        b.hx = m->h[0];
+        b.hz = m->h[2];
+        b.src_f = m->src_f;
+        b.gwav = gwav;
+        b.nt = m->d.nt;
+        b.k = k;
+        b.src_scale = src_scale(m);
+        b.rec_off = m->rec_off;
+        b.rec_ent = static_cast<const int *>(m->rec_ent);
+        b.dJdd = dJdd;
+        b.nrec = m->geom_nrec;
+        b.snap = snap;
+        b.grad = m->grad;
+        launch_ac2_adj(b, s);
+    } else {
+        Ac3PhiAdjArgs pa{};
+        pa.g = m->L.g3;
+        pa.s2 = m->adj[ca];
+        pa.chat = m->chat;
+        pa.shots_per_model = spm;
+        for (int j = 0; j < 3; ++j) pa.b[j] = m->adj[2 + j];
+        pa.t = tabs3(m);
+        launch_ac3_phi_adj(pa, ns, s);
+        Ac3AdjArgs b{};
+        b.g = m->L.g3;
+        b.nshots = ns;
+        b.s2 = m->adj[ca];
+        b.s3 = m->adj[1 - ca];
+        b.chat = m->chat;
+        b.shots_per_model = spm;
+        for (int j = 0; j < 3; ++j) b.b[j] = m->adj[2 + j];
+        b.e = m->adj[5];
+        b.t = tabs3(m);
+        b.dt = (float)m->d.dt;
+        b.inv_dt = (float)(1.0 / m->d.dt);
+        b.src_f = m->src_f;
+        b.gwav = gwav;
+        b.nt = m->d.nt;
+        b.k = k;
+        b.src_scale = src_scale(m);
+        b.rec_off = m->rec_off;
+        b.rec_ent = static_cast<const int2 *>(m->rec_ent);
+        b.dJdd = dJdd;
+        b.nrec = m->geom_nrec;
+        b.snap = snap;
+        b.grad = m->grad;
+        launch_ac3_adj(b, s);
+    }
 }
 
 } // namespace
@@ -310,79 +496,83 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         return fail(SG_EINVAL, "max_shots >= 1, max_rec >= 0 and ckpt_every >= 0 required");
     if (max_shots % d->nmodels) return fail(SG_EINVAL, "max_shots must be a multiple of nmodels");
     if ((long long)max_rec >= (1LL << REC_ID_BITS)) return fail(SG_EINVAL, "at most %d receivers per shot", (1 << REC_ID_BITS) - 1);
+    if (d->ndim == 3 && d->nz + 2 * d->npml >= (1 << 12)) return fail(SG_EINVAL, "3-D grids are limited to 4095 padded planes in z");
     const Layout L = make_layout(d, max_shots, max_rec, ckpt_every);
     if (ws_bytes < L.total) return fail(SG_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     if ((uintptr_t)ws % ALIGN) return fail(SG_EINVAL, "workspace must be %zu-byte aligned", ALIGN);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     // stability: velocity range from the device copy
-    const size_t nphys = (size_t)d->nmodels * d->nx * d->nz;
+    const size_t nphys = (size_t)d->nmodels * d->nx * (d->ndim == 3 ? d->ny : 1) * d->nz;
     std::vector<float> hv(nphys);
     HIPCHECK(hipMemcpyAsync(hv.data(), vp, sizeof(float) * nphys, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    float vmin = hv[0], vmax = hv[0];
+    float vmax = hv[0];
     for (float v : hv) {
         if (!(v > 0) || !std::isfinite(v)) return fail(SG_EINVAL, "velocity must be positive and finite");
-        vmin = std::min(vmin, v);
         vmax = std::max(vmax, v);
     }
     const double limit = 2.0 / std::sqrt(L8_SYMBOL_MAX * d->ndim);
     const double cfl = vmax * d->dt / d->dx;
-    if (cfl > 0.95 * limit)
-        return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
-    const Grid2 &g = L.g;
+    if (cfl > 0.95 * limit) return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
     const double zmax = d->npml > 0 ? 3.0 * d->pml_vmax * std::log(1.0 / d->pml_R) / (2.0 * d->npml * d->dx) : 0.0;
     if (zmax * d->dt > 0.3) return fail(SG_EUNSTABLE, "zeta_max*dt = %.3f above 0.3", zmax * d->dt);
 
     sg_model *m = new sg_model();
     m->d = *d;
+    if (d->ndim == 2) m->d.ny = 1;
     m->L = L;
     m->max_shots = max_shots;
     m->max_rec = max_rec;
     m->ws = static_cast<char *>(ws);
     m->chat = reinterpret_cast<float *>(m->ws + L.off_chat);
     m->cpad = reinterpret_cast<float *>(m->ws + L.off_cpad);
-    float *tab = reinterpret_cast<float *>(m->ws + L.off_tab);
-    m->hx = tab;
-    m->px = tab + g.NX;
-    m->ihx = tab + 2 * g.NX;
-    m->hz = tab + 3 * g.NX;
-    m->pz = m->hz + g.NZ;
-    m->ihz = m->hz + 2 * g.NZ;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < L.nf; ++i) {
         m->fwd[i] = reinterpret_cast<float *>(m->ws + L.off_fwd) + i * L.field;
         m->adj[i] = reinterpret_cast<float *>(m->ws + L.off_adj) + i * L.field;
     }
     m->ckpt = reinterpret_cast<float *>(m->ws + L.off_ckpt);
     m->snap = reinterpret_cast<float *>(m->ws + L.off_snap);
     m->grad = reinterpret_cast<float *>(m->ws + L.off_grad);
-    m->src_cell = reinterpret_cast<int *>(m->ws + L.off_src);
+    m->src_f = reinterpret_cast<long long *>(m->ws + L.off_src);
     m->rec_off = reinterpret_cast<int *>(m->ws + L.off_recoff);
-    m->rec_ent = reinterpret_cast<int *>(m->ws + L.off_recent);
+    m->rec_ent = m->ws + L.off_recent;
     m->partials = reinterpret_cast<double *>(m->ws + L.off_part);
 
     // damping tables per axis, FP64 rounded once: h = zeta dt / 2,
-    // p = (1-h)/(1+h), 1/(1+h)
-    auto profile = [&](int n, float *h, float *p, float *ih) {
-        for (int i = 0; i < n + 2 * d->npml; ++i) {
-            int depth = i < d->npml ? d->npml - i : (i >= d->npml + n ? i - (d->npml + n - 1) : 0);
+    // p = (1-h)/(1+h), 1/(1+h); TABPAD neutral entries (h = 0) on each side
+    const int phys[3] = {d->nx, d->ndim == 3 ? d->ny : 1, d->nz};
+    size_t tot = 0;
+    for (int a = 0; a < 3; ++a) tot += 3 * (L.n[a] + 2 * TABPAD);
+    m->h_tab.assign(tot, 0.f);
+    float *dev_tab = reinterpret_cast<float *>(m->ws + L.off_tab);
+    size_t o = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int N = L.n[a] + 2 * TABPAD;
+        float *h = m->h_tab.data() + o, *p = h + N, *ih = p + N;
+        for (int i = 0; i < N; ++i) {
+            const int c = i - TABPAD;   // padded-grid index
+            int depth = 0;
+            if (c >= 0 && c < L.n[a] && !(d->ndim == 2 && a == 1))
+                depth = c < d->npml ? d->npml - c : (c >= d->npml + phys[a] ? c - (d->npml + phys[a] - 1) : 0);
             const double r = d->npml > 0 ? (double)depth / d->npml : 0.0;
             const double hv = 0.5 * d->dt * zmax * r * r;
             h[i] = (float)hv;
             p[i] = (float)((1.0 - hv) / (1.0 + hv));
             ih[i] = (float)(1.0 / (1.0 + hv));
         }
-    };
-    m->h_tab.assign(3 * (g.NX + g.NZ), 0.f);
-    float *ht = m->h_tab.data();
-    profile(d->nx, ht, ht + g.NX, ht + 2 * g.NX);
-    profile(d->nz, ht + 3 * g.NX, ht + 3 * g.NX + g.NZ, ht + 3 * g.NX + 2 * g.NZ);
-    hipError_t e = hipMemcpyAsync(tab, ht, sizeof(float) * m->h_tab.size(), hipMemcpyHostToDevice, s);
+        m->h[a] = dev_tab + o + TABPAD;
+        m->p[a] = dev_tab + o + N + TABPAD;
+        m->ih[a] = dev_tab + o + 2 * N + TABPAD;
+        o += 3 * N;
+    }
+    hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         delete m;
         return fail(SG_EDEVICE, "upload failed: %s", hipGetErrorString(e));
     }
-    launch_ac2_prep(g, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
+    if (d->ndim == 2) launch_ac2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
+    else launch_ac3_prep(L.g3, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
     e = hipGetLastError();
     if (e != hipSuccess) {
         delete m;
@@ -402,31 +592,30 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     rc = upload_geometry(m, sh, s);
     if (rc) return rc;
-    const int ns = sh->nshots, nt = m->d.nt, K = m->L.K;
-    const Grid2 &g = m->L.g;
-    const long long fs = (long long)ns * g.plane;  // floats of one field over the batch
-    for (int i = 0; i < 4; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
+    const Layout &L = m->L;
+    const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
+    const long long fs = (long long)ns * L.plane;  // floats of one field over the batch
+    for (int i = 0; i < nf; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
     int cu = 0;
     int span = -1;
     for (int k = 0; k < nt; ++k) {
         if (k % K == 0) {
             span_end(m, span, s);
+            if (save_ckpt) {
+                // state at the start of step k: u^k, u^{k-1}, then the layer fields
+                float *ck = m->ckpt + (size_t)(k / K) * nf * L.field;
+                const float *src[6] = {m->fwd[cu], m->fwd[1 - cu], m->fwd[2], m->fwd[3], m->fwd[4], m->fwd[5]};
+                for (int i = 0; i < nf; ++i)
+                    HIPCHECK(hipMemcpyAsync(ck + i * L.field, src[i], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+            }
             span = span_begin(m, 0, std::min(K, nt - k), s);
         }
-        if (save_ckpt && k % K == 0) {
-            float *ck = m->ckpt + (size_t)(k / K) * 4 * m->L.field;
-            HIPCHECK(hipMemcpyAsync(ck, m->fwd[cu], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-            HIPCHECK(hipMemcpyAsync(ck + m->L.field, m->fwd[1 - cu], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-            HIPCHECK(hipMemcpyAsync(ck + 2 * m->L.field, m->fwd[2], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-            HIPCHECK(hipMemcpyAsync(ck + 3 * m->L.field, m->fwd[3], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        }
-        fwd_step(m, fwd_args(m, ns, sh->wavelet, cu), k, sh->nrec > 0 ? seis : nullptr, nullptr, s);
+        fwd_step(m, ns, sh->wavelet, cu, k, sh->nrec > 0 ? seis : nullptr, nullptr, s);
         cu = 1 - cu;
     }
     span_end(m, span, s);
     HIPCHECK(hipGetLastError());
     m->have_ckpt = save_ckpt != 0;
-    m->ckpt_nshots = ns;
     return SG_OK;
 }
 
@@ -450,75 +639,40 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     if (rc) return rc;
     if (g_vs || g_rho) return fail(SG_EINVAL, "g_vs and g_rho must be NULL for acoustic models");
     if (!g_vp || (!dJ_dd && sh->nrec > 0)) return fail(SG_EINVAL, "g_vp / dJ_dd is NULL");
+    if (!sh->src || (sh->nrec > 0 && !sh->rec)) return fail(SG_EINVAL, "source/receiver arrays are NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // geometry must be the one of the checkpointed forward
-    const int ns = sh->nshots;
-    const bool same = m->have_ckpt && m->geom_nshots == ns && m->geom_nrec == sh->nrec &&
-                      std::equal(sh->src, sh->src + 2 * ns, m->geom_src.begin()) &&
-                      (sh->nrec == 0 || std::equal(sh->rec, sh->rec + (size_t)2 * ns * sh->nrec, m->geom_rec.begin()));
-    if (!same) return fail(SG_ESTATE, "no checkpointed forward of these shots precedes the adjoint");
-    const int nt = m->d.nt, K = m->L.K;
-    const Grid2 &g = m->L.g;
-    const long long fs = (long long)ns * g.plane;
-    for (int i = 0; i < 4; ++i) launch_fill(m->adj[i], fs, 0.f, s);
+    if (!m->have_ckpt || !same_geometry(m, sh))
+        return fail(SG_ESTATE, "no checkpointed forward of these shots precedes the adjoint");
+    const Layout &L = m->L;
+    const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
+    const long long fs = (long long)ns * L.plane;
+    for (int i = 0; i < nf; ++i) launch_fill(m->adj[i], fs, 0.f, s);
     launch_fill(m->grad, fs, 0.f, s);
-
-    Ac2AdjArgs b{};
-    b.g = g;
-    b.nshots = ns;
-    b.cx = m->adj[2];
-    b.cz = m->adj[3];
-    b.chat = m->chat;
-    b.shots_per_model = ns / m->d.nmodels;
-    b.hx = m->hx;
-    b.hz = m->hz;
-    b.src_cell = m->src_cell;
-    b.gwav = g_wavelet;
-    b.nt = nt;
-    b.src_scale = (float)(m->d.dt * m->d.dt / (m->d.dx * m->d.dx));
-    b.rec_off = m->rec_off;
-    b.rec_ent = m->rec_ent;
-    b.dJdd = dJ_dd;
-    b.nrec = sh->nrec;
-    b.grad = m->grad;
-    Ac2PhiAdjArgs pa{};
-    pa.g = g;
-    pa.chat = m->chat;
-    pa.shots_per_model = b.shots_per_model;
-    pa.cx = m->adj[2];
-    pa.cz = m->adj[3];
-    pa.hx = m->hx; pa.hz = m->hz; pa.px = m->px; pa.pz = m->pz; pa.ihx = m->ihx; pa.ihz = m->ihz;
-    int ca = 0;   // s^{k+2} = adj[ca], s^{k+3} = adj[1-ca]
-    for (int seg = m->L.nseg - 1; seg >= 0; --seg) {
+    int ca = 0;
+    for (int seg = L.nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * K, k1 = std::min(k0 + K, nt);
-        const float *ck = m->ckpt + (size_t)seg * 4 * m->L.field;
-        HIPCHECK(hipMemcpyAsync(m->fwd[0], ck, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        HIPCHECK(hipMemcpyAsync(m->fwd[1], ck + m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        HIPCHECK(hipMemcpyAsync(m->fwd[2], ck + 2 * m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        HIPCHECK(hipMemcpyAsync(m->fwd[3], ck + 3 * m->L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+        const float *ck = m->ckpt + (size_t)seg * nf * L.field;
+        for (int i = 0; i < nf; ++i)
+            HIPCHECK(hipMemcpyAsync(m->fwd[i], ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
         int cu = 0;
         int span = span_begin(m, 1, k1 - k0, s);
         for (int k = k0; k < k1; ++k) {
-            float *snap = m->snap + (size_t)(k - k0) * m->L.field;
-            fwd_step(m, fwd_args(m, ns, sh->wavelet, cu), k, nullptr, snap, s);
+            fwd_step(m, ns, sh->wavelet, cu, k, nullptr, m->snap + (size_t)(k - k0) * L.field, s);
             cu = 1 - cu;
         }
         span_end(m, span, s);
         span = span_begin(m, 2, k1 - k0, s);
         for (int k = k1 - 1; k >= k0; --k) {
-            b.k = k;
-            b.snap = m->snap + (size_t)(k - k0) * m->L.field;
-            b.s2 = m->adj[ca];
-            b.s3 = m->adj[1 - ca];
-            pa.s2 = b.s2;
-            launch_ac2_phi_adj(pa, ns, s);
-            launch_ac2_adj(b, s);
+            adj_step(m, ns, ca, k, dJ_dd, g_wavelet, m->snap + (size_t)(k - k0) * L.field, s);
             ca = 1 - ca;
         }
         span_end(m, span, s);
     }
     // the snapshot buffer (free now) holds the per-model shot sums
-    launch_ac2_finalize(g, m->d.nmodels, ns / m->d.nmodels, m->grad, m->snap, m->cpad, m->d.dt, m->d.dx, g_vp, s);
+    if (m->d.ndim == 2)
+        launch_ac2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->snap, m->cpad, m->d.dt, m->d.dx, g_vp, s);
+    else
+        launch_ac3_finalize(L.g3, m->d.nmodels, ns / m->d.nmodels, m->grad, m->snap, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }

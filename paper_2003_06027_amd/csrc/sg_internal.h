@@ -49,7 +49,7 @@ struct Ac2FwdArgs {
     int shots_per_model;
     const float *phx, *phz; // phi~^k
     const float *hx, *hz;
-    const int *src_cell;    // [shot] frame index of the source node
+    const long long *src_f; // [shot] frame index of the source node
     const float *wav;       // [shot][nt]
     int nt, k;
     float src_scale;        // dt^2 / (dx dz)
@@ -79,7 +79,7 @@ struct Ac2AdjArgs {
     int shots_per_model;
     const float *cx, *cz;   // c^{k+1}
     const float *hx, *hz;
-    const int *src_cell;
+    const long long *src_f;
     float *gwav;            // [shot][nt] or null
     int nt, k;
     float src_scale;
@@ -111,5 +111,101 @@ constexpr int REC_ID_BITS = 20;
 __host__ __device__ inline int rec_pack(int cell, int id) { return (cell << REC_ID_BITS) | id; }
 __host__ __device__ inline int rec_cell(int e) { return e >> REC_ID_BITS; }
 __host__ __device__ inline int rec_id(int e) { return e & ((1 << REC_ID_BITS) - 1); }
+
+
+// ---------------------------------------------------------------- 3-D
+// Tile of the 3-D kernels: TX3 x TY3 columns (one thread each), marching in
+// z over chunks of TZC planes with a register window of 9 planes.
+constexpr int TX3 = 64;
+constexpr int TY3 = 8;
+constexpr int NTH3 = TX3 * TY3;
+constexpr int TZC = 64;
+constexpr int OX3 = 32;  // x offset (128-byte aligned rows)
+constexpr int OY3 = 4;
+constexpr int OZ3 = 4;
+constexpr int CELL3_BITS = 9;   // local cell of a TX3 x TY3 plane tile
+
+struct Grid3 {
+    int NX, NY, NZ;
+    int P, nx, ny, nz;
+    int SX, SY, SZ;
+    long long sy, sz, plane;   // strides: sy = SX, sz = SX*SY, plane = sz*SZ
+    int ntx, nty, nzc;         // tiles in x, y; z chunks
+};
+
+struct Ac3Tabs {               // per-axis damping tables, h = zeta dt / 2
+    const float *h[3], *p[3], *ih[3];  // x, y, z: h, (1-h)/(1+h), 1/(1+h)
+};
+
+struct Ac3FwdArgs {
+    Grid3 g;
+    int nshots;
+    const float *u;            // u^k
+    float *um;                 // u^{k-1} in, u^{k+1} out
+    const float *chat;
+    int shots_per_model;
+    const float *ph[3];        // phi~_j^k
+    float *psi;                // psi^k in, psi^{k+1} out (layer cells)
+    Ac3Tabs t;
+    float dt, inv_dt;
+    const long long *src_f;    // [shot] frame index of the source node
+    const float *wav;
+    int nt, k;
+    float src_scale;           // dt^2 / dx^3
+    const int *rec_off;        // [shot][ntx*nty + 1]
+    const int2 *rec_ent;       // x: (iz << CELL3_BITS) | cell, y: receiver id
+    float *seis;
+    int nrec;
+    float *snap;
+};
+
+struct Ac3PhiArgs {
+    Grid3 g;
+    const float *u, *psi;      // u^k, psi^k
+    float *ph[3];              // in place
+    Ac3Tabs t;
+    float inv_dt;
+};
+
+struct Ac3PhiAdjArgs {
+    Grid3 g;
+    const float *s2;
+    const float *chat;
+    int shots_per_model;
+    float *b[3];               // adjoint of phi~_j, in place
+    Ac3Tabs t;
+};
+
+struct Ac3AdjArgs {
+    Grid3 g;
+    int nshots;
+    const float *s2;
+    float *s3;
+    const float *chat;
+    int shots_per_model;
+    const float *b[3];
+    float *e;                  // adjoint of psi, in place (layer cells)
+    Ac3Tabs t;
+    float dt, inv_dt;
+    const long long *src_f;
+    float *gwav;
+    int nt, k;
+    float src_scale;
+    const int *rec_off;
+    const int2 *rec_ent;
+    const float *dJdd;
+    int nrec;
+    const float *snap;
+    float *grad;
+};
+
+void launch_ac3_phi(const Ac3PhiArgs &a, int nshots, hipStream_t s);
+void launch_ac3_fwd(const Ac3FwdArgs &a, hipStream_t s);
+void launch_ac3_phi_adj(const Ac3PhiAdjArgs &a, int nshots, hipStream_t s);
+void launch_ac3_adj(const Ac3AdjArgs &a, hipStream_t s);
+void launch_ac3_prep(const Grid3 &g, int nmodels, const float *vp, double dt, double dx,
+                     float *chat, float *cpad, hipStream_t s);
+void launch_ac3_finalize(const Grid3 &g, int nmodels, int spm, const float *grad, float *acc,
+                         const float *cpad, double dt, double dx, float *g_vp, hipStream_t s);
 
 } // namespace sg

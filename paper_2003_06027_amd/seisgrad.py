@@ -157,7 +157,9 @@ class Model:
 
     def gradient(self, shots, dJdd, g_vp=None, g_wavelet=None, stream=None):
         if g_vp is None:
-            g_vp = torch.empty((self.d.nmodels, self.d.nz, self.d.nx), dtype=torch.float32, device=dJdd.device)
+            shape = (self.d.nmodels, self.d.nz, self.d.nx) if self.d.ndim == 2 else \
+                (self.d.nmodels, self.d.nz, self.d.ny, self.d.nx)
+            g_vp = torch.empty(shape, dtype=torch.float32, device=dJdd.device)
         st = shots.struct()
         _check(lib().adjoint_gradient(self.handle, C.byref(st), _ptr(dJdd.contiguous()), _ptr(g_vp), None, None,
                                       _ptr(g_wavelet), _stream(stream)))
