@@ -224,3 +224,62 @@ def greens3d_ricker(r, c, t, f0, t0):
     a = (np.pi * f0 * (tau - t0)) ** 2
     s = np.where(tau >= 0, (1.0 - 2.0 * a) * np.exp(-a), 0.0)
     return s / (4.0 * np.pi * c * c * r)
+
+
+# ---------------------------------------------------------------- elastic 2-D
+EL2_FIELDS = ("vx", "vz", "sxx", "szz", "sxz", "m_vx_x", "m_vx_z", "m_vz_x", "m_vz_z",
+              "m_sxx_x", "m_sxz_z", "m_sxz_x", "m_szz_z")
+
+
+def el2_pad(g, vp, vs, rho):
+    """-> (lam, mu, muxz, bx, bz) on the padded grid."""
+    P = g.npml
+    sh = (g.nz + 2 * P, g.nx + 2 * P)
+    out = [np.zeros(sh) for _ in range(5)]
+    lib().or_el2_pad(C.byref(g), _d(_f64(vp)), _d(_f64(vs)), _d(_f64(rho)), *[_d(o) for o in out])
+    return out
+
+
+def el2_step(g, model, X, src_idx=-1, mt=(0.0, 0.0, 0.0), src_val=0.0):
+    model = [_f64(m) for m in model]
+    X = [_f64(x) for x in X]
+    Y = [np.zeros_like(X[0]) for _ in range(13)]
+    mta = _f64(mt)
+    lib().or_el2_step(C.byref(g), _ptrs(model), _ptrs(X), C.c_int64(src_idx), _d(mta),
+                      C.c_double(src_val), _ptrs(Y))
+    return Y
+
+
+def el2_step_T(g, model, X, aY, src_idx=-1, mt=(0.0, 0.0, 0.0)):
+    model = [_f64(m) for m in model]
+    X = [_f64(x) for x in X]
+    aY = [_f64(x) for x in aY]
+    aX = [np.zeros_like(X[0]) for _ in range(13)]
+    gM = [np.zeros_like(X[0]) for _ in range(5)]
+    sb = C.c_double(0.0)
+    mta = _f64(mt)
+    lib().or_el2_step_T(C.byref(g), _ptrs(model), _ptrs(X), _ptrs(aY), _ptrs(aX), _ptrs(gM),
+                        C.c_int64(src_idx), _d(mta), C.byref(sb))
+    return aX, gM, sb.value
+
+
+def el2_forward(g, vp, vs, rho, src, mt, wav, rec):
+    src, rec, wav, mt = _i32(src), _i32(rec), _f64(wav), _f64(mt)
+    ns, nrec = src.shape[0], rec.shape[1]
+    seis = np.zeros((ns, 2, g.nt, nrec))
+    if lib().or_el2_forward(C.byref(g), _d(_f64(vp)), _d(_f64(vs)), _d(_f64(rho)), C.c_int32(ns),
+                            _i(src), _d(mt), _d(wav), C.c_int32(nrec), _i(rec), _d(seis)):
+        raise ValueError("oracle: invalid geometry or grid")
+    return seis
+
+
+def el2_gradient(g, vp, vs, rho, src, mt, wav, rec, dJdd, ckpt=0):
+    src, rec, wav, mt = _i32(src), _i32(rec), _f64(wav), _f64(mt)
+    ns, nrec = src.shape[0], rec.shape[1]
+    seis = np.zeros((ns, 2, g.nt, nrec))
+    gvp, gvs, grho = np.zeros((g.nz, g.nx)), np.zeros((g.nz, g.nx)), np.zeros((g.nz, g.nx))
+    if lib().or_el2_gradient(C.byref(g), _d(_f64(vp)), _d(_f64(vs)), _d(_f64(rho)), C.c_int32(ns),
+                             _i(src), _d(mt), _d(wav), C.c_int32(nrec), _i(rec), _d(_f64(dJdd)),
+                             C.c_int32(ckpt), _d(gvp), _d(gvs), _d(grho), _d(seis)):
+        raise ValueError("oracle: invalid geometry or grid")
+    return (gvp, gvs, grho), seis

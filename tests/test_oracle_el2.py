@@ -1,0 +1,247 @@
+"""Pins of the FP64 oracle for the 2-D elastic velocity-stress scheme and its
+adjoint: closed-form explosive-source solution, exact discrete energy
+conservation (rigid walls, no layer), the per-step dot-product identity with
+the CPML active, brute-force finite differences of J in vp, vs, rho,
+reverse-mode AD in torch, checkpointing and CPML absorption."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2003_06027_amd import synth
+
+
+def _model(n, seed=0, vp0=2200.0):
+    nz, nx = n
+    vp = vp0 + 400.0 * synth.smooth_random(seed, (nz, nx), 2.0, 0.0, 1.0)
+    vs = vp / 1.73 * (1.0 + 0.05 * synth.smooth_random(seed + 1, (nz, nx), 2.0, -1.0, 1.0))
+    rho = 310.0 * vp ** 0.25
+    return vp, vs, rho
+
+
+def test_explosive_source_matches_closed_form(oracle):
+    """Isotropic stress-rate source in a homogeneous medium: v = grad(Phi) with
+    Phi the 2-D acoustic Green's function at vp convolved with r/rho; sample n
+    of vx is at x + dx/2 and time n dt."""
+    vp0, vs0, rho0, dx, dt, f0 = 2000.0, 1155.0, 2000.0, 5.0, 0.5e-3, 15.0
+    n, T = 261, 0.26
+    nt = int(round(T / dt))
+    g = oracle.grid(ndim=2, nx=n, nz=n, npml=0, nt=nt, dx=dx, dt=dt, pml_vmax=vp0)
+    m = n // 2
+    vp, vs, rho = np.full((n, n), vp0), np.full((n, n), vs0), np.full((n, n), rho0)
+    src = np.array([[m, m]], dtype=np.int32)
+    offs = [40, 60]
+    rec = np.array([[[m + k, m] for k in offs]], dtype=np.int32)
+    s = oracle.el2_forward(g, vp, vs, rho, src, np.array([[1.0, 1.0, 0.0]]),
+                           oracle.ricker(f0, 1.0 / f0, dt, nt)[None], rec)[0]
+    errs, slip = [], []
+    for j, k in enumerate(offs):
+        R, h = (k + 0.5) * dx, 0.25
+        t = np.arange(nt) * dt
+        ref = (oracle.greens2d_ricker(R + h, vp0, t, f0, 1.0 / f0)
+               - oracle.greens2d_ricker(R - h, vp0, t, f0, 1.0 / f0)) / (2 * h) / rho0
+        msk = t < (2 * (n - 1 - m) - k) * dx / vp0
+        errs.append(np.linalg.norm(s[0, msk, j] - ref[msk]) / np.linalg.norm(ref[msk]))
+        slip.append(np.linalg.norm(s[0, msk, j][1:] - ref[msk][:-1]) / np.linalg.norm(ref[msk]))
+    assert max(errs) < 5e-3, errs
+    assert min(slip) > 1e-2, slip          # a one-sample slip is detected
+
+
+def _state(rng, shape):
+    return [rng.standard_normal(shape) for _ in range(13)]
+
+
+def test_energy_conservation_rigid_no_layer(oracle):
+    """E^n = 1/2 <v^{n-1/2}, M v^{n+1/2}> + 1/2 <sigma^n, C^{-1} sigma^n> is
+    exactly conserved by the staggered leapfrog when the stress-update
+    differences are the negative transposes of the velocity-update ones."""
+    n, dx, dt = (30, 34), 5.0, 0.4e-3
+    g = oracle.grid(ndim=2, nx=n[1], nz=n[0], npml=0, nt=1, dx=dx, dt=dt, pml_vmax=3000.0)
+    vp, vs, rho = _model(n, 4)
+    lam, mu, muxz, bx, bz = oracle.el2_pad(g, vp, vs, rho)
+    # independent check of the model fields
+    assert np.allclose(lam, rho * (vp ** 2 - 2 * vs ** 2)) and np.allclose(mu, rho * vs ** 2)
+    rng = np.random.default_rng(0)
+    X = [np.zeros(n) for _ in range(13)]
+    win = np.outer(np.hanning(n[0]), np.hanning(n[1]))
+    for f in range(5):
+        X[f] = synth.smooth_random(10 + f, n, 1.5, -1.0, 1.0) * win * (1e-3 if f < 2 else 1e4)
+    model = [lam, mu, muxz, bx, bz]
+    det = (lam + 2 * mu) ** 2 - lam ** 2
+
+    def stress_energy(Y):
+        sxx, szz, sxz = Y[2], Y[3], Y[4]
+        # compliance of [[lam+2mu, lam], [lam, lam+2mu]] and of muxz
+        return 0.5 * np.sum(((lam + 2 * mu) * (sxx ** 2 + szz ** 2) - 2 * lam * sxx * szz) / det + sxz ** 2 / muxz)
+
+    E = []
+    for k in range(400):
+        Y = oracle.el2_step(g, model, X)
+        # X holds v^{n-1/2}, sigma^n; Y holds v^{n+1/2}, sigma^{n+1}
+        E.append(0.5 * np.sum(X[0] * Y[0] / bx + X[1] * Y[1] / bz) + stress_energy(X))
+        X = Y
+    E = np.array(E)
+    assert np.max(np.abs(E - E[0])) / abs(E[0]) < 1e-11
+
+
+def test_step_dot_product_identity_elastic(oracle):
+    n = (13, 15)
+    g = oracle.grid(ndim=2, nx=n[1], nz=n[0], npml=8, nt=1, dx=5.0, dt=0.4e-3, pml_vmax=2800.0, f0_pml=20.0)
+    vp, vs, rho = _model(n, 1)
+    model = oracle.el2_pad(g, vp, vs, rho)
+    sh = model[0].shape
+    rng = np.random.default_rng(7)
+    X = _state(rng, sh)
+    aY = _state(rng, sh)
+    Y = oracle.el2_step(g, model, X)
+    aX, _, _ = oracle.el2_step_T(g, model, X, aY)
+    lhs = sum(np.vdot(a, b) for a, b in zip(Y, aY))
+    rhs = sum(np.vdot(a, b) for a, b in zip(X, aX))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), np.sqrt(sum(np.vdot(y, y) for y in Y)))
+
+
+def _case(oracle, nt=90):
+    n = (12, 14)
+    g = oracle.grid(ndim=2, nx=n[1], nz=n[0], npml=8, nt=nt, dx=5.0, dt=0.4e-3, pml_vmax=2800.0, f0_pml=20.0)
+    vp, vs, rho = _model(n, 2)
+    src = np.array([[7, 2], [3, 8]], dtype=np.int32)
+    mt = np.array([[1.0, 1.0, 0.0], [-0.6, 0.6, 0.8]])
+    rec = np.stack([np.stack([np.arange(1, 13), np.zeros(12)], -1)] * 2).astype(np.int32)
+    wav = np.stack([oracle.ricker(60.0, 0.02, 0.4e-3, nt), oracle.ricker(50.0, 0.02, 0.4e-3, nt)])
+    return g, vp, vs, rho, src, mt, wav, rec
+
+
+def test_gradient_fd_vp_vs_rho(oracle):
+    g, vp, vs, rho, src, mt, wav, rec = _case(oracle)
+    dobs = oracle.el2_forward(g, vp * 1.04, vs * 0.97, rho * 1.02, src, mt, wav, rec)
+    pred = oracle.el2_forward(g, vp, vs, rho, src, mt, wav, rec)
+    J, r = oracle.misfit(pred, dobs)
+    (gvp, gvs, grho), _ = oracle.el2_gradient(g, vp, vs, rho, src, mt, wav, rec, r)
+    (gvp2, gvs2, grho2), _ = oracle.el2_gradient(g, vp, vs, rho, src, mt, wav, rec, r, ckpt=13)
+    assert np.array_equal(gvp, gvp2) and np.array_equal(gvs, gvs2) and np.array_equal(grho, grho2)
+    rng = np.random.default_rng(3)
+    cells = [tuple(rng.integers(0, s) for s in vp.shape) for _ in range(6)] + [(0, 0), (11, 13), (0, 6)]
+    for which, field, grad in (("vp", vp, gvp), ("vs", vs, gvs), ("rho", rho, grho)):
+        for cell in cells:
+            h = 1e-4 * field[cell]
+
+            def Jat(dh):
+                a = {"vp": vp.copy(), "vs": vs.copy(), "rho": rho.copy()}
+                a[which][cell] += dh
+                return oracle.misfit(oracle.el2_forward(g, a["vp"], a["vs"], a["rho"], src, mt, wav, rec), dobs)[0]
+
+            fd = (8 * (Jat(h) - Jat(-h)) - (Jat(2 * h) - Jat(-2 * h))) / (12 * h)
+            assert fd == pytest.approx(grad[cell], rel=1e-6, abs=1e-8 * np.abs(grad).max()), (which, cell)
+
+
+def _torch_el2(vp, vs, rho, P, dx, dt, nt, sidx, mt, wav, ridx, cp):
+    """The same discrete scheme written in torch FP64 ops (for reverse-mode AD).
+    cp: CPML (a, b) per axis and staggering from the oracle's definition."""
+    NZ, NX = vp.shape[0] + 2 * P, vp.shape[1] + 2 * P
+    iz = np.clip(np.arange(NZ) - P, 0, vp.shape[0] - 1)
+    ix = np.clip(np.arange(NX) - P, 0, vp.shape[1] - 1)
+    Vp, Vs, Rh = vp[iz][:, ix], vs[iz][:, ix], rho[iz][:, ix]
+    lam, mu = Rh * (Vp ** 2 - 2 * Vs ** 2), Rh * Vs ** 2
+    ix1 = np.minimum(np.arange(NX) + 1, NX - 1)
+    iz1 = np.minimum(np.arange(NZ) + 1, NZ - 1)
+    muxz = 4.0 / (1 / mu + 1 / mu[:, ix1] + 1 / mu[iz1] + 1 / mu[iz1][:, ix1])
+    bx = 2.0 / (Rh + Rh[:, ix1])
+    bz = 2.0 / (Rh + Rh[iz1])
+    c1, c2 = 9.0 / 8.0, -1.0 / 24.0
+
+    def sh(f, dz_, dx_):
+        p = torch.nn.functional.pad(f, (4, 4, 4, 4))
+        return p[4 + dz_:4 + dz_ + NZ, 4 + dx_:4 + dx_ + NX]
+
+    def Dp(f, ax):
+        s = (lambda m: sh(f, 0, m)) if ax == 0 else (lambda m: sh(f, m, 0))
+        return (c1 * (s(1) - s(0)) + c2 * (s(2) - s(-1))) / dx
+
+    def Dm(f, ax):
+        s = (lambda m: sh(f, 0, m)) if ax == 0 else (lambda m: sh(f, m, 0))
+        return (c1 * (s(0) - s(-1)) + c2 * (s(1) - s(-2))) / dx
+
+    (ax0, bx0), (ax1, bx1), (az0, bz0), (az1, bz1) = [(torch.tensor(a), torch.tensor(b)) for a, b in cp]
+    ax0, bx0, ax1, bx1 = ax0[None], bx0[None], ax1[None], bx1[None]
+    az0, bz0, az1, bz1 = az0[:, None], bz0[:, None], az1[:, None], bz1[:, None]
+    z = torch.zeros(NZ, NX, dtype=torch.float64)
+    vx, vz, sxx, szz, sxz = z, z, z, z, z
+    m = {k: z for k in ("vxx", "vxz", "vzx", "vzz", "sxxx", "sxzz", "sxzx", "szzz")}
+    out = []
+    for k in range(nt):
+        d1, d2, d3, d4 = Dp(sxx, 0), Dm(sxz, 1), Dm(sxz, 0), Dp(szz, 1)
+        m["sxxx"] = bx1 * m["sxxx"] + ax1 * d1
+        m["sxzz"] = bz0 * m["sxzz"] + az0 * d2
+        m["sxzx"] = bx0 * m["sxzx"] + ax0 * d3
+        m["szzz"] = bz1 * m["szzz"] + az1 * d4
+        vx = vx + dt * bx * (d1 + d2 + m["sxxx"] + m["sxzz"])
+        vz = vz + dt * bz * (d3 + d4 + m["sxzx"] + m["szzz"])
+        e1, e2, e3, e4 = Dm(vx, 0), Dm(vz, 1), Dp(vx, 1), Dp(vz, 0)
+        m["vxx"] = bx0 * m["vxx"] + ax0 * e1
+        m["vzz"] = bz0 * m["vzz"] + az0 * e2
+        m["vxz"] = bz1 * m["vxz"] + az1 * e3
+        m["vzx"] = bx1 * m["vzx"] + ax1 * e4
+        exx, ezz, exz = e1 + m["vxx"], e2 + m["vzz"], e3 + m["vxz"] + e4 + m["vzx"]
+        src = torch.zeros(NZ, NX, dtype=torch.float64)
+        src[sidx] = dt * wav[k] / dx ** 2
+        sxx = sxx + dt * ((lam + 2 * mu) * exx + lam * ezz) + mt[0] * src
+        szz = szz + dt * (lam * exx + (lam + 2 * mu) * ezz) + mt[1] * src
+        sxz = sxz + dt * muxz * exz + mt[2] * src
+        out.append(torch.stack([torch.stack([vx[r] for r in ridx]), torch.stack([vz[r] for r in ridx])]))
+    return torch.stack(out, dim=1)
+
+
+def _cpml_tables(g, n_x, n_z):
+    """CPML a, b from the definition (independent of the oracle's C code)."""
+    P, L = g.npml, g.npml * g.dx
+    d0 = 3.0 * g.pml_vmax * np.log(1.0 / g.pml_R) / (2.0 * L)
+
+    def ab(n, h):
+        x = np.arange(n + 2 * P) + 0.5 * h
+        dist = np.where(x < P, P - x, np.where(x > P + n - 1, x - (P + n - 1), 0.0))
+        r = np.minimum(dist / P, 1.0)
+        d, al = d0 * r * r, np.pi * g.f0_pml * (1.0 - r)
+        b = np.where(dist > 0, np.exp(-(d + al) * g.dt), 1.0)
+        a = np.where(dist > 0, d * (b - 1.0) / (d + al), 0.0)
+        return a, b
+
+    return [ab(n_x, 0), ab(n_x, 1), ab(n_z, 0), ab(n_z, 1)]
+
+
+def test_adjoint_equals_reverse_mode_ad_elastic(oracle):
+    g, vp, vs, rho, src, mt, wav, rec = _case(oracle, nt=40)
+    P = g.npml
+    dobs = oracle.el2_forward(g, vp * 1.03, vs, rho, src[:1], mt[:1], wav[:1], rec[:1])
+    tv = [torch.tensor(a, requires_grad=True) for a in (vp, vs, rho)]
+    sidx = (int(src[0, 1]) + P, int(src[0, 0]) + P)
+    ridx = [(int(r[1]) + P, int(r[0]) + P) for r in rec[0]]
+    cp = _cpml_tables(g, g.nx, g.nz)
+    d = _torch_el2(*tv, P, g.dx, g.dt, g.nt, sidx, mt[0], torch.tensor(wav[0]), ridx, cp)
+    J = 0.5 * ((d - torch.tensor(dobs[0])) ** 2).sum()
+    J.backward()
+    pred = oracle.el2_forward(g, vp, vs, rho, src[:1], mt[:1], wav[:1], rec[:1])
+    Jo, r = oracle.misfit(pred, dobs)
+    assert float(J.detach()) == pytest.approx(Jo, rel=1e-12)
+    grads, _ = oracle.el2_gradient(g, vp, vs, rho, src[:1], mt[:1], wav[:1], rec[:1], r)
+    for t, go in zip(tv, grads):
+        ad = t.grad.numpy()
+        assert np.linalg.norm(ad - go) / np.linalg.norm(ad) < 1e-10
+
+
+def test_cpml_absorbs(oracle):
+    n, P, dx, dt, f0 = 70, 20, 5.0, 0.5e-3, 25.0
+    nt = 500
+    g = oracle.grid(ndim=2, nx=n, nz=n, npml=P, nt=nt, dx=dx, dt=dt, pml_vmax=2000.0, f0_pml=f0)
+    vp, vs, rho = np.full((n, n), 2000.0), np.full((n, n), 1150.0), np.full((n, n), 2000.0)
+    src = np.array([[n // 2, n // 2]], dtype=np.int32)
+    mt = np.array([[1.0, 1.0, 0.0]])
+    wav = oracle.ricker(f0, 1.0 / f0, dt, nt)[None]
+    rec = np.array([[[n // 2 + 25, n // 2], [n // 2, n // 2 - 28], [4, 4]]], dtype=np.int32)
+    small = oracle.el2_forward(g, vp, vs, rho, src, mt, wav, rec)[0]
+    N3 = 3 * n
+    g3 = oracle.grid(ndim=2, nx=N3, nz=N3, npml=0, nt=nt, dx=dx, dt=dt, pml_vmax=2000.0)
+    big = oracle.el2_forward(g3, np.full((N3, N3), 2000.0), np.full((N3, N3), 1150.0), np.full((N3, N3), 2000.0),
+                             src + n, mt, wav, rec + n)[0]
+    tmax = int((2 * n) * dx / 2000.0 / dt)
+    refl = small[:, :tmax] - big[:, :tmax]
+    ratio = np.sqrt(np.mean(refl ** 2)) / np.sqrt(np.mean(big[:, :tmax] ** 2))
+    assert ratio < 2e-2, ratio
