@@ -104,6 +104,9 @@ typedef struct sg_shots {
     const int32_t *src;      /* HOST [nshots][ndim]: (ix, iz) or (ix, iy, iz) source node */
     const int32_t *rec;      /* HOST [nshots][nrec][ndim]: receiver nodes, same order */
     const float *wavelet;    /* DEVICE [nshots][nt]: source time function r(t_k) */
+    const float *mt;         /* HOST [nshots][3]: moment tensor (Mxx, Mzz, Mxz) of elastic
+                                sources (stress-rate injection dt M r(t_n)/(dx dz)); NULL for
+                                acoustic shots */
 } sg_shots;
 
 typedef struct sg_model sg_model;

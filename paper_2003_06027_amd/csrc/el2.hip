@@ -1,0 +1,408 @@
+// el2.hip -- gfx950 kernels of the 2-D elastic velocity-stress scheme
+// (paper: Implementation, Eq. (12), with the explicit recursion Eq. (1)) and
+// its exact adjoint (Eqs. (4)-(5)), gradients with respect to vp, vs, rho.
+//
+// Staggered grid, all fields [iz][ix] on the padded grid, the index naming
+// the node below-left of the field's position: sxx, szz at (ix, iz); vx at
+// (ix+1/2, iz); vz at (ix, iz+1/2); sxz at (ix+1/2, iz+1/2).  4th-order
+// staggered differences without the 1/dx factor (kap = dt/dx carries it):
+//     Dp f[i] = 9/8 (f[i+1] - f[i]) - 1/24 (f[i+2] - f[i-1])
+//     Dm f[i] = 9/8 (f[i] - f[i-1]) - 1/24 (f[i+1] - f[i-2])
+// zero beyond the padded grid, so Dm^T = -Dp.  Forward step n:
+//   velocity:  m = b m + a D(sigma) on the CPML cells, then
+//     vx += kap bx (Dxp sxx + Dzm sxz + m_sxx_x + m_sxz_z)
+//     vz += kap bz (Dxm sxz + Dzp szz + m_sxz_x + m_szz_z)
+//   stress:    m = b m + a D(v), Exx = Dxm vx + m, Ezz = Dzm vz + m,
+//     Exz = Dzp vx + m + Dxp vz + m
+//     sxx += kap ((lam+2mu) Exx + lam Ezz), szz += kap (lam Exx + (lam+2mu) Ezz),
+//     sxz += kap muxz Exz, plus dt M r(t_n)/(dx dz) at the source node.
+// Adjoint step n (reverse): pass 1 forms the adjoints e1..e4 of the four
+// velocity differences from the stress adjoints (and the lam/mu/muxz
+// gradients from the stored strains); pass 2 applies their transposes to the
+// velocity adjoints, then forms the adjoints d1..d4 of the stress
+// differences (and the bx/bz gradients from the stored divergences); pass 3
+// applies those transposes to the stress adjoints.
+#include "sg_internal.h"
+
+namespace sg {
+namespace {
+
+constexpr float C1 = (float)(9.0 / 8.0);
+constexpr float C2 = (float)(-1.0 / 24.0);
+constexpr int EBX = 64, EBZ = 4;   // cell block
+
+__device__ __forceinline__ float Dp(const float *f, long long i, long long s)
+{
+    return C1 * (f[i + s] - f[i]) + C2 * (f[i + 2 * s] - f[i - s]);
+}
+__device__ __forceinline__ float Dm(const float *f, long long i, long long s)
+{
+    return C1 * (f[i] - f[i - s]) + C2 * (f[i + s] - f[i - 2 * s]);
+}
+
+struct Cell {
+    int ix, iz, shot;
+    bool valid, layer;
+    long long f, so, mo;   // frame index, shot and model offsets
+};
+
+__device__ __forceinline__ Cell cell_of(const Grid2 &g, int spm)
+{
+    Cell c;
+    const int ntxe = (g.NX + EBX - 1) / EBX;
+    const int bx = blockIdx.x % ntxe, bz = blockIdx.x / ntxe;
+    c.ix = bx * EBX + (int)(threadIdx.x % EBX);
+    c.iz = bz * EBZ + (int)(threadIdx.x / EBX);
+    c.shot = blockIdx.y;
+    c.valid = c.ix < g.NX && c.iz < g.NZ;
+    c.layer = g.P > 0 && (c.ix < g.P || c.ix >= g.P + g.nx - 1 || c.iz < g.P || c.iz >= g.P + g.nz - 1);
+    c.f = (long long)(c.iz + OZ) * g.SX + c.ix + OX;
+    c.so = (long long)c.shot * g.plane;
+    c.mo = (long long)(c.shot / spm) * g.plane;
+    return c;
+}
+
+dim3 cell_grid(const Grid2 &g, int nshots)
+{
+    return dim3(((g.NX + EBX - 1) / EBX) * ((g.NZ + EBZ - 1) / EBZ), nshots);
+}
+
+__global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of(g, a.shots_per_model);
+    if (!c.valid) return;
+    const long long f = c.so + c.f, SX = g.SX;
+    float d1 = Dp(a.f[E_SXX], f, 1), d2 = Dm(a.f[E_SXZ], f, SX);
+    float d3 = Dm(a.f[E_SXZ], f, 1), d4 = Dp(a.f[E_SZZ], f, SX);
+    if (c.layer) {
+        float m;
+        m = a.t.bx[1][c.ix] * a.f[E_MSXXX][f] + a.t.ax[1][c.ix] * d1; a.f[E_MSXXX][f] = m; d1 += m;
+        m = a.t.bz[0][c.iz] * a.f[E_MSXZZ][f] + a.t.az[0][c.iz] * d2; a.f[E_MSXZZ][f] = m; d2 += m;
+        m = a.t.bx[0][c.ix] * a.f[E_MSXZX][f] + a.t.ax[0][c.ix] * d3; a.f[E_MSXZX][f] = m; d3 += m;
+        m = a.t.bz[1][c.iz] * a.f[E_MSZZZ][f] + a.t.az[1][c.iz] * d4; a.f[E_MSZZZ][f] = m; d4 += m;
+    }
+    const float fx = d1 + d2, fz = d3 + d4;
+    a.f[E_VX][f] += a.kap * a.m[M_BX][c.mo + c.f] * fx;
+    a.f[E_VZ][f] += a.kap * a.m[M_BZ][c.mo + c.f] * fz;
+    if (a.snap) {
+        a.snap[3 * a.snap_stride + f] = fx;
+        a.snap[4 * a.snap_stride + f] = fz;
+    }
+}
+
+__global__ __launch_bounds__(256) void el2_str_kernel(El2Args a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of(g, a.shots_per_model);
+    if (!c.valid) return;
+    const long long f = c.so + c.f, SX = g.SX;
+    float e1 = Dm(a.f[E_VX], f, 1), e2 = Dm(a.f[E_VZ], f, SX);
+    float e3 = Dp(a.f[E_VX], f, SX), e4 = Dp(a.f[E_VZ], f, 1);
+    if (c.layer) {
+        float m;
+        m = a.t.bx[0][c.ix] * a.f[E_MVXX][f] + a.t.ax[0][c.ix] * e1; a.f[E_MVXX][f] = m; e1 += m;
+        m = a.t.bz[0][c.iz] * a.f[E_MVZZ][f] + a.t.az[0][c.iz] * e2; a.f[E_MVZZ][f] = m; e2 += m;
+        m = a.t.bz[1][c.iz] * a.f[E_MVXZ][f] + a.t.az[1][c.iz] * e3; a.f[E_MVXZ][f] = m; e3 += m;
+        m = a.t.bx[1][c.ix] * a.f[E_MVZX][f] + a.t.ax[1][c.ix] * e4; a.f[E_MVZX][f] = m; e4 += m;
+    }
+    const float exz = e3 + e4;
+    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f];
+    float sxx = a.f[E_SXX][f] + a.kap * ((lam + 2.f * mu) * e1 + lam * e2);
+    float szz = a.f[E_SZZ][f] + a.kap * (lam * e1 + (lam + 2.f * mu) * e2);
+    float sxz = a.f[E_SXZ][f] + a.kap * a.m[M_MUXZ][c.mo + c.f] * exz;
+    if (c.f == a.src_f[c.shot]) {
+        const float s = a.src_scale * a.wav[(long long)c.shot * a.nt + a.k];
+        sxx += s * a.mt[3 * c.shot];
+        szz += s * a.mt[3 * c.shot + 1];
+        sxz += s * a.mt[3 * c.shot + 2];
+    }
+    a.f[E_SXX][f] = sxx;
+    a.f[E_SZZ][f] = szz;
+    a.f[E_SXZ][f] = sxz;
+    if (a.snap) {
+        a.snap[f] = e1;
+        a.snap[a.snap_stride + f] = e2;
+        a.snap[2 * a.snap_stride + f] = exz;
+    }
+}
+
+__global__ void el2_record_kernel(El2RecArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nshots * a.nrec) return;
+    const int shot = i / a.nrec, r = i - shot * a.nrec;
+    const long long f = (long long)shot * a.plane + a.rec_f[i];
+    a.seis[((long long)(shot * 2) * a.nt + a.k) * a.nrec + r] = a.vx[f];
+    a.seis[((long long)(shot * 2 + 1) * a.nt + a.k) * a.nrec + r] = a.vz[f];
+}
+
+// R^T dJ/dd of sample k into the velocity adjoints: one thread per unique
+// receiver cell, summing its receivers in a fixed order.
+__global__ void el2_inject_kernel(El2RecArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nshots * a.nuniq_max) return;
+    const int shot = i / a.nuniq_max, u = i - shot * a.nuniq_max;
+    const int *off = a.uoff + (long long)shot * (a.nuniq_max + 1);
+    const int b = off[u], e = off[u + 1];
+    if (b >= e) return;
+    const float *dx = a.dJdd + ((long long)(shot * 2) * a.nt + a.k) * a.nrec;
+    const float *dz = a.dJdd + ((long long)(shot * 2 + 1) * a.nt + a.k) * a.nrec;
+    float sx = 0.f, sz = 0.f;
+    for (int j = b; j < e; ++j) {
+        sx += dx[a.uid[j]];
+        sz += dz[a.uid[j]];
+    }
+    const long long f = (long long)shot * a.plane + a.rec_f[(long long)shot * a.nrec + a.uid[b]];
+    a.ax[f] += sx;
+    a.az[f] += sz;
+}
+
+__global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of(g, a.shots_per_model);
+    if (!c.valid) return;
+    const long long f = c.so + c.f;
+    const float sxx = a.a[E_SXX][f], szz = a.a[E_SZZ][f], sxz = a.a[E_SXZ][f];
+    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f];
+    const float txx = a.kap * ((lam + 2.f * mu) * sxx + lam * szz);
+    const float tzz = a.kap * (lam * sxx + (lam + 2.f * mu) * szz);
+    const float txz = a.kap * a.m[M_MUXZ][c.mo + c.f] * sxz;
+    const float exx = a.snap[f], ezz = a.snap[a.snap_stride + f], exz = a.snap[2 * a.snap_stride + f];
+    a.grad[f] += a.kap * (exx + ezz) * (sxx + szz);
+    a.grad[a.grad_stride + f] += 2.f * a.kap * (exx * sxx + ezz * szz);
+    a.grad[2 * a.grad_stride + f] += a.kap * exz * sxz;
+    float e1 = txx, e2 = tzz, e3 = txz, e4 = txz;
+    if (c.layer) {
+        float q;
+        q = txx + a.a[E_MVXX][f]; a.a[E_MVXX][f] = a.t.bx[0][c.ix] * q; e1 = txx + a.t.ax[0][c.ix] * q;
+        q = tzz + a.a[E_MVZZ][f]; a.a[E_MVZZ][f] = a.t.bz[0][c.iz] * q; e2 = tzz + a.t.az[0][c.iz] * q;
+        q = txz + a.a[E_MVXZ][f]; a.a[E_MVXZ][f] = a.t.bz[1][c.iz] * q; e3 = txz + a.t.az[1][c.iz] * q;
+        q = txz + a.a[E_MVZX][f]; a.a[E_MVZX][f] = a.t.bx[1][c.ix] * q; e4 = txz + a.t.ax[1][c.ix] * q;
+    }
+    a.tmp[0][f] = e1;
+    a.tmp[1][f] = e2;
+    a.tmp[2][f] = e3;
+    a.tmp[3][f] = e4;
+    if (a.gwav && c.f == a.src_f[c.shot])
+        a.gwav[(long long)c.shot * a.nt + a.k] =
+            a.src_scale * (a.mt[3 * c.shot] * sxx + a.mt[3 * c.shot + 1] * szz + a.mt[3 * c.shot + 2] * sxz);
+}
+
+__global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of(g, a.shots_per_model);
+    if (!c.valid) return;
+    const long long f = c.so + c.f, SX = g.SX;
+    // transposes of the velocity differences: Dm^T = -Dp, Dp^T = -Dm
+    const float vx = a.a[E_VX][f] - (Dp(a.tmp[0], f, 1) + Dm(a.tmp[2], f, SX));
+    const float vz = a.a[E_VZ][f] - (Dp(a.tmp[1], f, SX) + Dm(a.tmp[3], f, 1));
+    a.a[E_VX][f] = vx;
+    a.a[E_VZ][f] = vz;
+    const float fxb = a.kap * a.m[M_BX][c.mo + c.f] * vx;
+    const float fzb = a.kap * a.m[M_BZ][c.mo + c.f] * vz;
+    a.grad[3 * a.grad_stride + f] += a.kap * a.snap[3 * a.snap_stride + f] * vx;
+    a.grad[4 * a.grad_stride + f] += a.kap * a.snap[4 * a.snap_stride + f] * vz;
+    float d1 = fxb, d2 = fxb, d3 = fzb, d4 = fzb;
+    if (c.layer) {
+        float q;
+        q = fxb + a.a[E_MSXXX][f]; a.a[E_MSXXX][f] = a.t.bx[1][c.ix] * q; d1 = fxb + a.t.ax[1][c.ix] * q;
+        q = fxb + a.a[E_MSXZZ][f]; a.a[E_MSXZZ][f] = a.t.bz[0][c.iz] * q; d2 = fxb + a.t.az[0][c.iz] * q;
+        q = fzb + a.a[E_MSXZX][f]; a.a[E_MSXZX][f] = a.t.bx[0][c.ix] * q; d3 = fzb + a.t.ax[0][c.ix] * q;
+        q = fzb + a.a[E_MSZZZ][f]; a.a[E_MSZZZ][f] = a.t.bz[1][c.iz] * q; d4 = fzb + a.t.az[1][c.iz] * q;
+    }
+    a.tmp[4][f] = d1;
+    a.tmp[5][f] = d2;
+    a.tmp[6][f] = d3;
+    a.tmp[7][f] = d4;
+}
+
+__global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of(g, a.shots_per_model);
+    if (!c.valid) return;
+    const long long f = c.so + c.f, SX = g.SX;
+    a.a[E_SXX][f] -= Dm(a.tmp[4], f, 1);
+    a.a[E_SXZ][f] -= Dp(a.tmp[5], f, SX) + Dp(a.tmp[6], f, 1);
+    a.a[E_SZZ][f] -= Dm(a.tmp[7], f, SX);
+}
+
+// Model fields on the frame (FP64 arithmetic, rounded once) and padded
+// copies of vp, vs, rho for the chain rule.
+__global__ void el2_prep_kernel(Grid2 g, int nmodels, const float *vp, const float *vs, const float *rho,
+                                float *lam, float *mu, float *muxz, float *bx, float *bz,
+                                float *pvp, float *pvs, float *prho)
+{
+    const long long n = (long long)nmodels * g.plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / g.plane, f = i - m * g.plane;
+        const int fz = (int)(f / g.SX), fx = (int)(f - (long long)fz * g.SX);
+        const int iz = fz - OZ, ix = fx - OX;
+        float o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX) {
+            auto at = [&](const float *p, int z, int x) -> double {
+                z = min(max(z, 0), g.NZ - 1);
+                x = min(max(x, 0), g.NX - 1);
+                const int pz = min(max(z - g.P, 0), g.nz - 1), px = min(max(x - g.P, 0), g.nx - 1);
+                return p[(m * g.nz + pz) * g.nx + px];
+            };
+            auto mu_at = [&](int z, int x) { const double b = at(vs, z, x); return at(rho, z, x) * b * b; };
+            const double a = at(vp, iz, ix), b = at(vs, iz, ix), r = at(rho, iz, ix);
+            o[0] = (float)(r * (a * a - 2.0 * b * b));
+            o[1] = (float)(r * b * b);
+            o[2] = (float)(4.0 / (1.0 / mu_at(iz, ix) + 1.0 / mu_at(iz, ix + 1) + 1.0 / mu_at(iz + 1, ix) +
+                                  1.0 / mu_at(iz + 1, ix + 1)));
+            o[3] = (float)(2.0 / (r + at(rho, iz, ix + 1)));
+            o[4] = (float)(2.0 / (r + at(rho, iz + 1, ix)));
+            o[5] = (float)a;
+            o[6] = (float)b;
+            o[7] = (float)r;
+        }
+        lam[i] = o[0]; mu[i] = o[1]; muxz[i] = o[2]; bx[i] = o[3]; bz[i] = o[4];
+        pvp[i] = o[5]; pvs[i] = o[6]; prho[i] = o[7];
+    }
+}
+
+__global__ void el2_sum_shots_kernel(Grid2 g, int nmodels, int spm, const float *grad, long long gs, float *acc)
+{
+    const long long n = (long long)nmodels * g.plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / g.plane, f = i - m * g.plane;
+        for (int q = 0; q < 5; ++q) {
+            float v = 0.f;
+            for (int s = 0; s < spm; ++s) v += grad[q * gs + (m * spm + s) * g.plane + f];
+            acc[q * n + i] = v;
+        }
+    }
+}
+
+// Per padded cell: dJ/d(vp, vs, rho) of the padded model through
+// lam = rho (vp^2 - 2 vs^2), mu = rho vs^2, the harmonic mu average and the
+// arithmetic density averages (neighbours clamped to the padded grid, the
+// clamped references counted with multiplicity).
+__global__ void el2_chain_kernel(Grid2 g, int nmodels, const float *acc, const float *muxz,
+                                 const float *mu, const float *bx, const float *bz,
+                                 const float *pvp, const float *pvs, const float *prho, float *out)
+{
+    const long long n = (long long)nmodels * g.plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / g.plane, f = i - m * g.plane;
+        const int fz = (int)(f / g.SX), fx = (int)(f - (long long)fz * g.SX);
+        const int iz = fz - OZ, ix = fx - OX;
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+        if (iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX) {
+            const long long mb = m * g.plane;
+            auto fr = [&](int z, int x) { return mb + (long long)(z + OZ) * g.SX + x + OX; };
+            double glam = acc[i], gmu = acc[n + i], grho = 0.0;
+            const double mui = mu[i];
+            for (int dz = 0; dz <= 1; ++dz)
+                for (int dx = 0; dx <= 1; ++dx) {
+                    const int jz = iz - dz, jx = ix - dx;
+                    if (jz < 0 || jx < 0) continue;
+                    int cnt = 0;
+                    for (int a2 = 0; a2 <= 1; ++a2)
+                        for (int b2 = 0; b2 <= 1; ++b2)
+                            cnt += (min(jz + a2, g.NZ - 1) == iz && min(jx + b2, g.NX - 1) == ix);
+                    if (!cnt) continue;
+                    const double mx = muxz[fr(jz, jx)];
+                    gmu += cnt * acc[2 * n + fr(jz, jx)] * mx * mx / (4.0 * mui * mui);
+                }
+            for (int d = 0; d <= 1; ++d) {
+                if (ix - d >= 0) {
+                    const int cnt = (ix - d == ix) + (min(ix - d + 1, g.NX - 1) == ix);
+                    const double b = bx[fr(iz, ix - d)];
+                    grho += cnt * acc[3 * n + fr(iz, ix - d)] * (-0.5 * b * b);
+                }
+                if (iz - d >= 0) {
+                    const int cnt = (iz - d == iz) + (min(iz - d + 1, g.NZ - 1) == iz);
+                    const double b = bz[fr(iz - d, ix)];
+                    grho += cnt * acc[4 * n + fr(iz - d, ix)] * (-0.5 * b * b);
+                }
+            }
+            const double a = pvp[i], b = pvs[i], r = prho[i];
+            r0 = (float)(glam * 2.0 * r * a);
+            r1 = (float)(2.0 * r * b * (gmu - 2.0 * glam));
+            r2 = (float)(grho + (a * a - 2.0 * b * b) * glam + b * b * gmu);
+        }
+        out[i] = r0;
+        out[n + i] = r1;
+        out[2 * n + i] = r2;
+    }
+}
+
+__global__ void el2_fold_kernel(Grid2 g, int nmodels, const float *pad, float *g_vp, float *g_vs, float *g_rho)
+{
+    const long long np = (long long)nmodels * g.plane;
+    const long long n = (long long)nmodels * g.nz * g.nx;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / ((long long)g.nz * g.nx);
+        const long long rem = i - m * g.nz * g.nx;
+        const int iz = (int)(rem / g.nx), ix = (int)(rem - (long long)iz * g.nx);
+        const int zlo = iz == 0 ? 0 : iz + g.P, zhi = iz == g.nz - 1 ? g.NZ - 1 : iz + g.P;
+        const int xlo = ix == 0 ? 0 : ix + g.P, xhi = ix == g.nx - 1 ? g.NX - 1 : ix + g.P;
+        float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+        for (int pz = zlo; pz <= zhi; ++pz)
+            for (int px = xlo; px <= xhi; ++px) {
+                const long long q = m * g.plane + (long long)(pz + OZ) * g.SX + px + OX;
+                v0 += pad[q];
+                v1 += pad[np + q];
+                v2 += pad[2 * np + q];
+            }
+        g_vp[i] = v0;
+        g_vs[i] = v1;
+        g_rho[i] = v2;
+    }
+}
+
+int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 65536); }
+
+} // namespace
+
+void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { el2_adj1_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { el2_adj2_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
+
+void launch_el2_record(const El2RecArgs &a, hipStream_t s)
+{
+    const int n = a.nshots * a.nrec;
+    if (n > 0) el2_record_kernel<<<(n + 255) / 256, 256, 0, s>>>(a);
+}
+
+void launch_el2_inject(const El2RecArgs &a, hipStream_t s)
+{
+    const int n = a.nshots * a.nuniq_max;
+    if (n > 0) el2_inject_kernel<<<(n + 255) / 256, 256, 0, s>>>(a);
+}
+
+void launch_el2_prep(const Grid2 &g, int nmodels, const float *vp, const float *vs, const float *rho,
+                     float *const *model, float *const *phys_pad, hipStream_t s)
+{
+    el2_prep_kernel<<<blocks_for((long long)nmodels * g.plane), 256, 0, s>>>(
+        g, nmodels, vp, vs, rho, model[0], model[1], model[2], model[3], model[4], phys_pad[0], phys_pad[1],
+        phys_pad[2]);
+}
+
+void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, const float *grad, long long grad_stride,
+                         float *acc, const float *const *model, const float *const *phys_pad,
+                         float *g_vp, float *g_vs, float *g_rho, hipStream_t s)
+{
+    const long long n = (long long)nmodels * g.plane;
+    float *pad = acc + 5 * n;
+    el2_sum_shots_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, spm, grad, grad_stride, acc);
+    el2_chain_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, acc, model[2], model[1], model[3], model[4],
+                                                    phys_pad[0], phys_pad[1], phys_pad[2], pad);
+    el2_fold_kernel<<<blocks_for((long long)nmodels * g.nz * g.nx), 256, 0, s>>>(g, nmodels, pad, g_vp, g_vs,
+                                                                                 g_rho);
+}
+
+} // namespace sg

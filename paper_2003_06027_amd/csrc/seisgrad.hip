@@ -58,15 +58,19 @@ struct Layout {
     int K, nseg;
     long long field;   // floats of one field over max_shots
     int n[3];          // padded extents x, y, z (y = 1 in 2-D)
+    bool elastic;
+    int nsnap, ngrad, nmod; // snapshot fields per step, gradient accumulators, model fields
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
-        off_grad, off_src, off_recoff, off_recent, off_part, total;
+        off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt, total;
 };
 
 int check_desc(const sg_desc *d)
 {
     if (!d) return fail(SG_EINVAL, "descriptor is NULL");
-    if (d->physics != SG_ACOUSTIC) return fail(SG_EUNSUPPORTED, "physics %d is not provided by this build", d->physics);
+    if (d->physics != SG_ACOUSTIC && d->physics != SG_ELASTIC)
+        return fail(SG_EUNSUPPORTED, "physics %d is not provided by this build", d->physics);
     if (d->ndim != 2 && d->ndim != 3) return fail(SG_EUNSUPPORTED, "ndim %d is not provided by this build", d->ndim);
+    if (d->physics == SG_ELASTIC && d->ndim != 2) return fail(SG_EUNSUPPORTED, "elastic modelling is 2-D in this build");
     const int ny = d->ndim == 3 ? d->ny : 1;
     if (d->nx < 1 || d->nz < 1 || ny < 1 || d->npml < 0 || d->nt < 1 || d->nmodels < 1)
         return fail(SG_EINVAL, "bad grid: nx=%d ny=%d nz=%d npml=%d nt=%d nmodels=%d", d->nx, d->ny, d->nz,
@@ -84,8 +88,27 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
 {
     Layout L{};
     L.ndim = d->ndim;
+    L.elastic = d->physics == SG_ELASTIC;
+    L.nsnap = 1;
+    L.ngrad = 1;
+    L.nmod = 2;            // chat, padded velocity
     const int P = d->npml;
-    if (d->ndim == 2) {
+    if (L.elastic) {
+        Grid2 &g = L.g2;
+        g.P = P; g.nx = d->nx; g.nz = d->nz;
+        g.NX = d->nx + 2 * P; g.NZ = d->nz + 2 * P;
+        g.ntx = g.ntz = 0;
+        g.SX = OX + (g.NX + 31) / 32 * 32 + 32;
+        g.SZ = OZ + g.NZ + 8;
+        g.plane = (long long)g.SX * g.SZ;
+        L.plane = g.plane;
+        L.ntiles = 0;
+        L.nf = EL_NS;
+        L.nsnap = 5;
+        L.ngrad = 5;
+        L.nmod = 8;        // lam, mu, muxz, bx, bz + padded vp, vs, rho
+        L.n[0] = g.NX; L.n[1] = 1; L.n[2] = g.NZ;
+    } else if (d->ndim == 2) {
         Grid2 &g = L.g2;
         g.P = P; g.nx = d->nx; g.nz = d->nz;
         g.NX = d->nx + 2 * P; g.NZ = d->nz + 2 * P;
@@ -119,18 +142,23 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.field = (long long)max_shots * L.plane;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
-    L.off_chat = take(sizeof(float) * d->nmodels * L.plane);
-    L.off_cpad = take(sizeof(float) * d->nmodels * L.plane);
-    L.off_tab = take(sizeof(float) * 3 * (L.n[0] + L.n[1] + L.n[2] + 6 * TABPAD));
+    L.off_chat = take(sizeof(float) * (size_t)L.nmod * d->nmodels * L.plane);   // model fields
+    L.off_cpad = L.off_chat + sizeof(float) * (size_t)d->nmodels * L.plane;
+    L.off_tab = take(sizeof(float) * 4 * (L.n[0] + L.n[1] + L.n[2] + 6 * TABPAD));
     L.off_fwd = take(sizeof(float) * L.nf * L.field);
     L.off_adj = take(sizeof(float) * L.nf * L.field);
     L.off_ckpt = take(sizeof(float) * (size_t)L.nseg * L.nf * L.field);
-    L.off_snap = take(sizeof(float) * (size_t)L.K * L.field);
-    L.off_grad = take(sizeof(float) * L.field);
+    L.off_snap = take(sizeof(float) * (size_t)L.K * L.nsnap * L.field);
+    L.off_grad = take(sizeof(float) * (size_t)L.ngrad * L.field);
     L.off_src = take(sizeof(long long) * max_shots);
     L.off_recoff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
-    L.off_recent = take(sizeof(int2) * std::max<size_t>(1, (size_t)max_shots * max_rec));
+    L.off_recent = take(std::max(sizeof(int2), sizeof(long long)) * std::max<size_t>(1, (size_t)max_shots * max_rec));
     L.off_part = take(sizeof(double) * 4096);
+    L.off_tmp = take(L.elastic ? sizeof(float) * 8 * L.field : 0);
+    L.off_acc = take(sizeof(float) * 8 * (size_t)d->nmodels * L.plane);
+    L.off_uoff = take(sizeof(int) * (size_t)max_shots * (max_rec + 1));
+    L.off_uid = take(sizeof(int) * std::max<size_t>(1, (size_t)max_shots * max_rec));
+    L.off_mt = take(sizeof(float) * 3 * max_shots);
     L.total = o;
     return L;
 }
@@ -144,8 +172,16 @@ struct sg_model {
     char *ws;
     float *chat, *cpad;
     float *h[3], *p[3], *ih[3];   // damping tables per axis (x, y, z)
-    float *fwd[6], *adj[6];
-    float *ckpt, *snap, *grad;
+    float *fwd[EL_NS], *adj[EL_NS], *tmp[8];
+    float *model[8];              // elastic: lam, mu, muxz, bx, bz, vp, vs, rho (padded)
+    float *ckpt, *snap, *grad, *acc;
+    int *uoff, *uid;
+    float *mt;
+    float *cpml[2][4];            // elastic CPML tables: [x|z][a0, b0, a1, b1]
+    int nuniq_max = 0;
+    std::vector<int> h_uoff, h_uid;
+    std::vector<long long> h_recf;
+    std::vector<float> h_mt;
     long long *src_f;
     int *rec_off;
     void *rec_ent;
@@ -174,6 +210,11 @@ namespace {
 bool same_geometry(const sg_model *m, const sg_shots *sh)
 {
     const int nd = m->d.ndim, ns = sh->nshots;
+    if (m->L.elastic) {
+        if (!sh->mt || m->h_mt.size() != (size_t)3 * ns) return false;
+        for (int i = 0; i < 3 * ns; ++i)
+            if (m->h_mt[i] != sh->mt[i]) return false;
+    }
     return m->geom_nshots == ns && m->geom_nrec == sh->nrec &&
            std::equal(sh->src, sh->src + (size_t)nd * ns, m->geom_src.begin()) &&
            (sh->nrec == 0 || std::equal(sh->rec, sh->rec + (size_t)nd * ns * sh->nrec, m->geom_rec.begin()));
@@ -202,6 +243,61 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
     if (same_geometry(m, sh)) return SG_OK;
     // the previous upload may still be reading the host vectors
     HIPCHECK(hipStreamSynchronize(s));
+    if (L.elastic) {
+        if (!sh->mt) return fail(SG_EINVAL, "elastic shots need moment tensors (mt)");
+        const Grid2 &g = L.g2;
+        auto frame = [&](const int32_t *q) { return (long long)(q[1] + P + OZ) * g.SX + q[0] + P + OX; };
+        m->h_src.assign(ns, 0);
+        m->h_recf.assign((size_t)std::max(1, ns * nrec), 0);
+        m->h_mt.assign(sh->mt, sh->mt + 3 * ns);
+        std::vector<std::vector<int>> groups(ns);
+        int nu = 0;
+        for (int i = 0; i < ns; ++i) {
+            m->h_src[i] = frame(sh->src + 2 * i);
+            std::vector<std::pair<long long, int>> byc;
+            for (int r = 0; r < nrec; ++r) {
+                const long long f = frame(sh->rec + ((size_t)i * nrec + r) * 2);
+                m->h_recf[(size_t)i * nrec + r] = f;
+                byc.push_back({f, r});
+            }
+            std::sort(byc.begin(), byc.end());
+            int cnt = 0;
+            for (size_t j = 0; j < byc.size(); ++j) cnt += (j == 0 || byc[j].first != byc[j - 1].first);
+            nu = std::max(nu, cnt);
+            for (auto &pr : byc) groups[i].push_back(pr.second);   // receiver ids by cell
+        }
+        m->nuniq_max = nu;
+        m->h_uoff.assign((size_t)ns * (nu + 1), 0);
+        m->h_uid.clear();
+        for (int i = 0; i < ns; ++i) {
+            int *off = m->h_uoff.data() + (size_t)i * (nu + 1);
+            int u = 0;
+            long long prev = -1;
+            const size_t base = m->h_uid.size();
+            for (size_t j = 0; j < groups[i].size(); ++j) {
+                const int r = groups[i][j];
+                const long long f = m->h_recf[(size_t)i * nrec + r];
+                if (j == 0 || f != prev) off[u++] = (int)(base + j);
+                prev = f;
+                m->h_uid.push_back(r);
+            }
+            for (; u <= nu; ++u) off[u] = (int)m->h_uid.size();
+        }
+        HIPCHECK(hipMemcpyAsync(m->src_f, m->h_src.data(), sizeof(long long) * ns, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(m->mt, m->h_mt.data(), sizeof(float) * 3 * ns, hipMemcpyHostToDevice, s));
+        if (nrec > 0) {
+            HIPCHECK(hipMemcpyAsync(m->rec_ent, m->h_recf.data(), sizeof(long long) * ns * nrec, hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemcpyAsync(m->uoff, m->h_uoff.data(), sizeof(int) * m->h_uoff.size(), hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemcpyAsync(m->uid, m->h_uid.data(), sizeof(int) * m->h_uid.size(), hipMemcpyHostToDevice, s));
+        }
+        m->geom_src.assign(sh->src, sh->src + (size_t)nd * ns);
+        if (nrec > 0) m->geom_rec.assign(sh->rec, sh->rec + (size_t)nd * ns * nrec);
+        else m->geom_rec.clear();
+        m->geom_nshots = ns;
+        m->geom_nrec = nrec;
+        m->have_ckpt = false;
+        return SG_OK;
+    }
     const int ntiles = L.ntiles;
     m->h_src.assign(ns, 0);
     m->h_off.assign((size_t)ns * (ntiles + 1), 0);
@@ -321,12 +417,94 @@ Ac3Tabs tabs3(const sg_model *m)
     return t;
 }
 
+El2Tabs el_tabs(const sg_model *m)
+{
+    El2Tabs t;
+    for (int h = 0; h < 2; ++h) {
+        t.ax[h] = m->cpml[0][2 * h];
+        t.bx[h] = m->cpml[0][2 * h + 1];
+        t.az[h] = m->cpml[1][2 * h];
+        t.bz[h] = m->cpml[1][2 * h + 1];
+    }
+    return t;
+}
+
+// One elastic step: velocity update, receiver record, stress update (+ source).
+void el_fwd_step(const sg_model *m, int ns, const float *wav, int k, float *seis, float *snap, hipStream_t s)
+{
+    El2Args a{};
+    a.g = m->L.g2;
+    a.nshots = ns;
+    a.shots_per_model = ns / m->d.nmodels;
+    for (int i = 0; i < EL_NS; ++i) a.f[i] = m->fwd[i];
+    for (int i = 0; i < 5; ++i) a.m[i] = m->model[i];
+    a.t = el_tabs(m);
+    a.kap = (float)(m->d.dt / m->d.dx);
+    a.snap = snap;
+    a.snap_stride = m->L.field;
+    a.src_f = m->src_f;
+    a.mt = m->mt;
+    a.wav = wav;
+    a.nt = m->d.nt;
+    a.k = k;
+    a.src_scale = (float)(m->d.dt / (m->d.dx * m->d.dx));
+    launch_el2_vel(a, s);
+    if (seis && m->geom_nrec > 0) {
+        El2RecArgs r{};
+        r.nshots = ns; r.nrec = m->geom_nrec; r.nt = m->d.nt; r.k = k;
+        r.rec_f = static_cast<const long long *>(m->rec_ent);
+        r.plane = m->L.plane;
+        r.vx = m->fwd[E_VX]; r.vz = m->fwd[E_VZ];
+        r.seis = seis;
+        launch_el2_record(r, s);
+    }
+    launch_el2_str(a, s);
+}
+
+void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwav, const float *snap, hipStream_t s)
+{
+    El2AdjArgs a{};
+    a.g = m->L.g2;
+    a.nshots = ns;
+    a.shots_per_model = ns / m->d.nmodels;
+    for (int i = 0; i < EL_NS; ++i) a.a[i] = m->adj[i];
+    for (int i = 0; i < 8; ++i) a.tmp[i] = m->tmp[i];
+    for (int i = 0; i < 5; ++i) a.m[i] = m->model[i];
+    a.t = el_tabs(m);
+    a.kap = (float)(m->d.dt / m->d.dx);
+    a.snap = snap;
+    a.snap_stride = m->L.field;
+    a.grad = m->grad;
+    a.grad_stride = m->L.field;
+    a.src_f = m->src_f;
+    a.mt = m->mt;
+    a.gwav = gwav;
+    a.nt = m->d.nt;
+    a.k = k;
+    a.src_scale = (float)(m->d.dt / (m->d.dx * m->d.dx));
+    launch_el2_adj1(a, s);
+    if (m->geom_nrec > 0) {
+        El2RecArgs r{};
+        r.nshots = ns; r.nrec = m->geom_nrec; r.nt = m->d.nt; r.k = k;
+        r.rec_f = static_cast<const long long *>(m->rec_ent);
+        r.plane = m->L.plane;
+        r.uoff = m->uoff; r.uid = m->uid; r.nuniq_max = m->nuniq_max;
+        r.dJdd = dJdd;
+        r.ax = m->adj[E_VX]; r.az = m->adj[E_VZ];
+        launch_el2_inject(r, s);
+    }
+    launch_el2_adj2(a, s);
+    launch_el2_adj3(a, s);
+}
+
 // One forward step: layer auxiliary fields from u^k, then the tile update.
 // cu selects u^k = fwd[cu], u^{k-1} = fwd[1-cu].
 void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float *seis, float *snap,
               hipStream_t s)
 {
-    if (m->d.ndim == 2) {
+    if (m->L.elastic) {
+        el_fwd_step(m, ns, wav, k, seis, snap, s);
+    } else if (m->d.ndim == 2) {
         Ac2PhiArgs p{};
         p.g = m->L.g2;
         p.u = m->fwd[cu];
@@ -396,7 +574,9 @@ void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float
               const float *snap, hipStream_t s)
 {
     const int spm = ns / m->d.nmodels;
-    if (m->d.ndim == 2) {
+    if (m->L.elastic) {
+        el_adj_step(m, ns, k, dJdd, gwav, snap, s);
+    } else if (m->d.ndim == 2) {
         Ac2PhiAdjArgs pa{};
         pa.g = m->L.g2;
         pa.s2 = m->adj[ca];
@@ -490,7 +670,9 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     *out = nullptr;
     int rc = check_desc(d);
     if (rc) return rc;
-    if (vs || rho) return fail(SG_EINVAL, "vs and rho must be NULL for acoustic models");
+    const bool elastic = d->physics == SG_ELASTIC;
+    if (!elastic && (vs || rho)) return fail(SG_EINVAL, "vs and rho must be NULL for acoustic models");
+    if (elastic && (!vs || !rho)) return fail(SG_EINVAL, "elastic models need vs and rho");
     if (!vp || !ws) return fail(SG_EINVAL, "vp and ws must be device pointers");
     if (max_shots < 1 || max_rec < 0 || ckpt_every < 0)
         return fail(SG_EINVAL, "max_shots >= 1, max_rec >= 0 and ckpt_every >= 0 required");
@@ -512,11 +694,25 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         if (!(v > 0) || !std::isfinite(v)) return fail(SG_EINVAL, "velocity must be positive and finite");
         vmax = std::max(vmax, v);
     }
-    const double limit = 2.0 / std::sqrt(L8_SYMBOL_MAX * d->ndim);
-    const double cfl = vmax * d->dt / d->dx;
-    if (cfl > 0.95 * limit) return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
+    if (elastic) {
+        std::vector<float> hs(nphys), hr(nphys);
+        HIPCHECK(hipMemcpyAsync(hs.data(), vs, sizeof(float) * nphys, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(hr.data(), rho, sizeof(float) * nphys, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < nphys; ++i)
+            if (!(hs[i] > 0) || !(hs[i] < hv[i]) || !(hr[i] > 0) || !std::isfinite(hr[i]))
+                return fail(SG_EINVAL, "elastic model needs 0 < vs < vp and rho > 0");
+        // 4th-order staggered leapfrog: vp dt/dx <= 1/(sqrt(ndim) (9/8 + 1/24))
+        const double limit = 1.0 / (std::sqrt((double)d->ndim) * (9.0 / 8.0 + 1.0 / 24.0));
+        const double cfl = vmax * d->dt / d->dx;
+        if (cfl > 0.95 * limit) return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
+    } else {
+        const double limit = 2.0 / std::sqrt(L8_SYMBOL_MAX * d->ndim);
+        const double cfl = vmax * d->dt / d->dx;
+        if (cfl > 0.95 * limit) return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
+    }
     const double zmax = d->npml > 0 ? 3.0 * d->pml_vmax * std::log(1.0 / d->pml_R) / (2.0 * d->npml * d->dx) : 0.0;
-    if (zmax * d->dt > 0.3) return fail(SG_EUNSTABLE, "zeta_max*dt = %.3f above 0.3", zmax * d->dt);
+    if (!elastic && zmax * d->dt > 0.3) return fail(SG_EUNSTABLE, "zeta_max*dt = %.3f above 0.3", zmax * d->dt);
 
     sg_model *m = new sg_model();
     m->d = *d;
@@ -538,16 +734,25 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     m->rec_off = reinterpret_cast<int *>(m->ws + L.off_recoff);
     m->rec_ent = m->ws + L.off_recent;
     m->partials = reinterpret_cast<double *>(m->ws + L.off_part);
+    for (int i = 0; i < 8; ++i) {
+        m->model[i] = reinterpret_cast<float *>(m->ws + L.off_chat) + (size_t)i * d->nmodels * L.plane;
+        m->tmp[i] = L.elastic ? reinterpret_cast<float *>(m->ws + L.off_tmp) + i * L.field : nullptr;
+    }
+    m->acc = reinterpret_cast<float *>(m->ws + L.off_acc);
+    m->uoff = reinterpret_cast<int *>(m->ws + L.off_uoff);
+    m->uid = reinterpret_cast<int *>(m->ws + L.off_uid);
+    m->mt = reinterpret_cast<float *>(m->ws + L.off_mt);
 
     // damping tables per axis, FP64 rounded once: h = zeta dt / 2,
     // p = (1-h)/(1+h), 1/(1+h); TABPAD neutral entries (h = 0) on each side
     const int phys[3] = {d->nx, d->ndim == 3 ? d->ny : 1, d->nz};
     size_t tot = 0;
-    for (int a = 0; a < 3; ++a) tot += 3 * (L.n[a] + 2 * TABPAD);
+    if (elastic) tot = 4 * (L.n[0] + L.n[2] + 4 * TABPAD);
+    else for (int a = 0; a < 3; ++a) tot += 3 * (L.n[a] + 2 * TABPAD);
     m->h_tab.assign(tot, 0.f);
     float *dev_tab = reinterpret_cast<float *>(m->ws + L.off_tab);
     size_t o = 0;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < (elastic ? 0 : 3); ++a) {
         const int N = L.n[a] + 2 * TABPAD;
         float *h = m->h_tab.data() + o, *p = h + N, *ih = p + N;
         for (int i = 0; i < N; ++i) {
@@ -566,12 +771,47 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         m->ih[a] = dev_tab + o + 2 * N + TABPAD;
         o += 3 * N;
     }
+    if (elastic) {
+        // CPML (kappa = 1): b = exp(-(d + al) dt), a = d (b - 1)/(d + al),
+        // d = d0 (x/L)^2, al = pi f0 (1 - x/L), d0 = 3 vmax ln(1/R)/(2L), at
+        // integer and half positions; x = distance into the layer
+        const double Lw = d->npml * d->dx;
+        const double d0 = d->npml > 0 ? 3.0 * d->pml_vmax * std::log(1.0 / d->pml_R) / (2.0 * Lw) : 0.0;
+        o = 0;
+        for (int ax = 0; ax < 2; ++ax) {
+            const int a = ax == 0 ? 0 : 2, N = L.n[a] + 2 * TABPAD, n = phys[a];
+            for (int h = 0; h < 2; ++h) {
+                float *ta = m->h_tab.data() + o, *tb = ta + N;
+                for (int i = 0; i < N; ++i) {
+                    const double x = (i - TABPAD) + 0.5 * h;
+                    double dist = 0.0;
+                    if (i - TABPAD >= 0 && i - TABPAD < L.n[a]) {
+                        if (x < d->npml) dist = d->npml - x;
+                        else if (x > d->npml + n - 1) dist = x - (d->npml + n - 1);
+                    }
+                    double av = 0.0, bv = 1.0;
+                    if (d->npml > 0 && dist > 0.0) {
+                        const double r = std::min(dist / d->npml, 1.0);
+                        const double dd = d0 * r * r, al = M_PI * d->f0_pml * (1.0 - r);
+                        bv = std::exp(-(dd + al) * d->dt);
+                        av = dd * (bv - 1.0) / (dd + al);
+                    }
+                    ta[i] = (float)av;
+                    tb[i] = (float)bv;
+                }
+                m->cpml[ax][2 * h] = dev_tab + o + TABPAD;
+                m->cpml[ax][2 * h + 1] = dev_tab + o + N + TABPAD;
+                o += 2 * N;
+            }
+        }
+    }
     hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         delete m;
         return fail(SG_EDEVICE, "upload failed: %s", hipGetErrorString(e));
     }
-    if (d->ndim == 2) launch_ac2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
+    if (elastic) launch_el2_prep(L.g2, d->nmodels, vp, vs, rho, m->model, m->model + 5, s);
+    else if (d->ndim == 2) launch_ac2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
     else launch_ac3_prep(L.g3, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
     e = hipGetLastError();
     if (e != hipSuccess) {
@@ -603,10 +843,12 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
             span_end(m, span, s);
             if (save_ckpt) {
                 // state at the start of step k: u^k, u^{k-1}, then the layer fields
+                // (acoustic: u^k, u^{k-1} first; elastic: the fields in order)
                 float *ck = m->ckpt + (size_t)(k / K) * nf * L.field;
-                const float *src[6] = {m->fwd[cu], m->fwd[1 - cu], m->fwd[2], m->fwd[3], m->fwd[4], m->fwd[5]};
-                for (int i = 0; i < nf; ++i)
-                    HIPCHECK(hipMemcpyAsync(ck + i * L.field, src[i], sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+                for (int i = 0; i < nf; ++i) {
+                    const float *src = L.elastic || i >= 2 ? m->fwd[i] : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
+                    HIPCHECK(hipMemcpyAsync(ck + i * L.field, src, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+                }
             }
             span = span_begin(m, 0, std::min(K, nt - k), s);
         }
@@ -637,7 +879,8 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     if (!m) return fail(SG_EINVAL, "model is NULL");
     int rc = check_shots(m, sh);
     if (rc) return rc;
-    if (g_vs || g_rho) return fail(SG_EINVAL, "g_vs and g_rho must be NULL for acoustic models");
+    if (!m->L.elastic && (g_vs || g_rho)) return fail(SG_EINVAL, "g_vs and g_rho must be NULL for acoustic models");
+    if (m->L.elastic && (!g_vs || !g_rho)) return fail(SG_EINVAL, "elastic gradients need g_vs and g_rho");
     if (!g_vp || (!dJ_dd && sh->nrec > 0)) return fail(SG_EINVAL, "g_vp / dJ_dd is NULL");
     if (!sh->src || (sh->nrec > 0 && !sh->rec)) return fail(SG_EINVAL, "source/receiver arrays are NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -647,7 +890,9 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
     const long long fs = (long long)ns * L.plane;
     for (int i = 0; i < nf; ++i) launch_fill(m->adj[i], fs, 0.f, s);
-    launch_fill(m->grad, fs, 0.f, s);
+    for (int q = 0; q < L.ngrad; ++q) launch_fill(m->grad + q * L.field, fs, 0.f, s);
+    if (L.elastic)
+        for (int i = 0; i < 8; ++i) launch_fill(m->tmp[i], fs, 0.f, s);
     int ca = 0;
     for (int seg = L.nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * K, k1 = std::min(k0 + K, nt);
@@ -657,22 +902,24 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         int cu = 0;
         int span = span_begin(m, 1, k1 - k0, s);
         for (int k = k0; k < k1; ++k) {
-            fwd_step(m, ns, sh->wavelet, cu, k, nullptr, m->snap + (size_t)(k - k0) * L.field, s);
+            fwd_step(m, ns, sh->wavelet, cu, k, nullptr, m->snap + (size_t)(k - k0) * L.nsnap * L.field, s);
             cu = 1 - cu;
         }
         span_end(m, span, s);
         span = span_begin(m, 2, k1 - k0, s);
         for (int k = k1 - 1; k >= k0; --k) {
-            adj_step(m, ns, ca, k, dJ_dd, g_wavelet, m->snap + (size_t)(k - k0) * L.field, s);
+            adj_step(m, ns, ca, k, dJ_dd, g_wavelet, m->snap + (size_t)(k - k0) * L.nsnap * L.field, s);
             ca = 1 - ca;
         }
         span_end(m, span, s);
     }
-    // the snapshot buffer (free now) holds the per-model shot sums
-    if (m->d.ndim == 2)
-        launch_ac2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->snap, m->cpad, m->d.dt, m->d.dx, g_vp, s);
+    if (L.elastic)
+        launch_el2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, L.field, m->acc, m->model,
+                            m->model + 5, g_vp, g_vs, g_rho, s);
+    else if (m->d.ndim == 2)
+        launch_ac2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     else
-        launch_ac3_finalize(L.g3, m->d.nmodels, ns / m->d.nmodels, m->grad, m->snap, m->cpad, m->d.dt, m->d.dx, g_vp, s);
+        launch_ac3_finalize(L.g3, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }

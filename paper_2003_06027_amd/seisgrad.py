@@ -40,7 +40,7 @@ class SgDesc(C.Structure):
 
 class SgShots(C.Structure):
     _fields_ = [("nshots", C.c_int32), ("nrec", C.c_int32), ("src", C.c_void_p),
-                ("rec", C.c_void_p), ("wavelet", C.c_void_p)]
+                ("rec", C.c_void_p), ("wavelet", C.c_void_p), ("mt", C.c_void_p)]
 
 
 _lib = None
@@ -114,18 +114,20 @@ def dot_f64(x, y, stream=None):
 
 
 class Shots:
-    """Host geometry (int32) + device wavelet for one batch of shots."""
+    """Host geometry (int32), host moment tensors (elastic) and the device
+    wavelet of one batch of shots."""
 
-    def __init__(self, src, rec, wavelet):
+    def __init__(self, src, rec, wavelet, mt=None):
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.rec = np.ascontiguousarray(rec, dtype=np.int32)
         assert self.src.ndim == 2 and self.rec.ndim == 3 and self.rec.shape[0] == self.src.shape[0]
         self.wavelet = wavelet.contiguous()
+        self.mt = None if mt is None else np.ascontiguousarray(mt, dtype=np.float32)
         self.nshots, self.nrec = self.rec.shape[0], self.rec.shape[1]
 
     def struct(self):
         return SgShots(self.nshots, self.nrec, self.src.ctypes.data, self.rec.ctypes.data,
-                       self.wavelet.data_ptr())
+                       self.wavelet.data_ptr(), None if self.mt is None else self.mt.ctypes.data)
 
 
 class Model:
@@ -134,16 +136,21 @@ class Model:
     def __init__(self, d, vp, max_shots, max_rec, ckpt_every=0, stream=None, vs=None, rho=None):
         self.d = d
         self.max_shots, self.max_rec = max_shots, max_rec
+        self.elastic = d.physics == SG_ELASTIC
         nbytes = workspace_bytes(d, max_shots, max_rec, ckpt_every)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=vp.device)
         self.handle = C.c_void_p()
         self.vp = vp.contiguous()
-        _check(lib().init_model(C.byref(d), _ptr(self.vp), _ptr(vs), _ptr(rho), max_shots, max_rec,
+        self.vs = None if vs is None else vs.contiguous()
+        self.rho = None if rho is None else rho.contiguous()
+        _check(lib().init_model(C.byref(d), _ptr(self.vp), _ptr(self.vs), _ptr(self.rho), max_shots, max_rec,
                                 ckpt_every, _ptr(self.ws), nbytes, _stream(stream), C.byref(self.handle)))
 
     def forward(self, shots, seis=None, save_ckpt=True, stream=None):
         if seis is None:
-            seis = torch.empty((shots.nshots, 1, self.d.nt, shots.nrec), dtype=torch.float32, device=self.ws.device)
+            ncomp = 2 if self.elastic else 1
+            seis = torch.empty((shots.nshots, ncomp, self.d.nt, shots.nrec), dtype=torch.float32,
+                               device=self.ws.device)
         self._shots = shots.struct()
         _check(lib().forward_shots(self.handle, C.byref(self._shots), _ptr(seis), int(save_ckpt), _stream(stream)))
         return seis
@@ -155,15 +162,20 @@ class Model:
         _check(lib().misfit(self.handle, _ptr(pred), _ptr(obs), pred.numel(), _ptr(J), _ptr(resid), _stream(stream)))
         return J, resid
 
-    def gradient(self, shots, dJdd, g_vp=None, g_wavelet=None, stream=None):
+    def gradient(self, shots, dJdd, g_vp=None, g_wavelet=None, stream=None, g_vs=None, g_rho=None):
+        """dJ/dvp (acoustic) or (dJ/dvp, dJ/dvs, dJ/drho) (elastic)."""
+        shape = (self.d.nmodels, self.d.nz, self.d.nx) if self.d.ndim == 2 else \
+            (self.d.nmodels, self.d.nz, self.d.ny, self.d.nx)
+        new = lambda: torch.empty(shape, dtype=torch.float32, device=dJdd.device)
         if g_vp is None:
-            shape = (self.d.nmodels, self.d.nz, self.d.nx) if self.d.ndim == 2 else \
-                (self.d.nmodels, self.d.nz, self.d.ny, self.d.nx)
-            g_vp = torch.empty(shape, dtype=torch.float32, device=dJdd.device)
+            g_vp = new()
+        if self.elastic:
+            g_vs = new() if g_vs is None else g_vs
+            g_rho = new() if g_rho is None else g_rho
         st = shots.struct()
-        _check(lib().adjoint_gradient(self.handle, C.byref(st), _ptr(dJdd.contiguous()), _ptr(g_vp), None, None,
-                                      _ptr(g_wavelet), _stream(stream)))
-        return g_vp
+        _check(lib().adjoint_gradient(self.handle, C.byref(st), _ptr(dJdd.contiguous()), _ptr(g_vp), _ptr(g_vs),
+                                      _ptr(g_rho), _ptr(g_wavelet), _stream(stream)))
+        return (g_vp, g_vs, g_rho) if self.elastic else g_vp
 
     def set_profiling(self, on=True):
         _check(lib().set_profiling(self.handle, int(on)))
