@@ -1,0 +1,211 @@
+"""Training-system forms around the plain method.
+
+* :class:`Propagator` -- a reusable workspace plus model handle for one grid
+  and acquisition: the velocity (and, elastic, vs and rho) can change between
+  calls without reallocating.
+* :class:`SeisForward` -- a ``torch.autograd.Function`` whose forward is the
+  library's forward sweep (with wavefield checkpoints) and whose backward is
+  the hand-written adjoint sweep: for any loss of the seismograms, autograd
+  passes dL/dd and receives dL/dvp (elastic: dL/dvp, dL/dvs, dL/drho).  This
+  is the paper's per-operator reverse rule (Method, the display after
+  Eq. (5): dU_k/dU_{k-1} = A^T, dU_k/dtheta = dA/dtheta U_{k-1}) applied to
+  the whole recursion at once.
+* :func:`batched_gd` -- plain gradient descent FWI on B models batched in one
+  launch (every model its own shots), with a normalised step and
+  backtracking, the baseline the learned preconditioner is compared with.
+
+All arithmetic of the forward, misfit and adjoint runs in the library's HIP
+kernels; this module only sequences calls and does per-model scalar
+bookkeeping.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+import torch
+
+from . import seisgrad as S
+
+
+class Propagator:
+    """Workspace + model for a fixed grid, shot batch and checkpoint interval."""
+
+    def __init__(self, desc, shots: "S.Shots", ckpt_every: int = 0, device="cuda"):
+        self.d = desc
+        self.shots = shots
+        self.ckpt = ckpt_every
+        self.elastic = desc.physics == S.SG_ELASTIC
+        self.nbytes = S.workspace_bytes(desc, shots.nshots, shots.nrec, ckpt_every)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.model = None
+        self.generation = 0
+
+    def set_model(self, vp, vs=None, rho=None):
+        """(Re)initialise the model on the same workspace."""
+        if self.model is not None:
+            self.model.close()
+        self.model = S.Model(self.d, vp.detach(), self.shots.nshots, self.shots.nrec, self.ckpt,
+                             vs=None if vs is None else vs.detach(), rho=None if rho is None else rho.detach(),
+                             ws=self.ws)
+        self.generation += 1
+        return self.model
+
+    def forward(self, vp, vs=None, rho=None, save_ckpt=True):
+        self.set_model(vp, vs, rho)
+        return self.model.forward(self.shots, save_ckpt=save_ckpt)
+
+    def close(self):
+        if self.model is not None:
+            self.model.close()
+            self.model = None
+
+
+class SeisForward(torch.autograd.Function):
+    """seis = F(vp[, vs, rho]); backward = the library's adjoint sweep."""
+
+    @staticmethod
+    def forward(ctx, prop: Propagator, vp, vs=None, rho=None):
+        seis = prop.forward(vp, vs, rho, save_ckpt=True)
+        ctx.prop = prop
+        ctx.generation = prop.generation
+        ctx.elastic = prop.elastic
+        return seis
+
+    @staticmethod
+    def backward(ctx, gseis):
+        prop = ctx.prop
+        if prop.generation != ctx.generation:
+            raise RuntimeError("the propagator ran another forward before this backward; "
+                               "its checkpoints belong to that call")
+        g = prop.model.gradient(prop.shots, gseis.contiguous())
+        if ctx.elastic:
+            return (None,) + tuple(g)
+        return None, g, None, None
+
+
+def seis_forward(prop, vp, vs=None, rho=None):
+    return SeisForward.apply(prop, vp, vs, rho)
+
+
+# --------------------------------------------------------------- batched GD
+@dataclasses.dataclass
+class GDConfig:
+    iters: int = 50
+    alpha0: float = 50.0      # m/s, maximum model change of the first trial step
+    shrink: float = 0.5       # backtracking factor
+    max_backtracks: int = 4
+    grow: float = 1.25        # step growth after a first-try success
+    vmin: float = 1000.0
+    vmax: float = 5000.0
+
+
+@dataclasses.dataclass
+class GDResult:
+    models: torch.Tensor              # [B, nz, nx]
+    J: np.ndarray                     # [iters + 1, B] misfit per iteration
+    times: np.ndarray                 # [iters + 1] wall seconds since start (after device sync)
+    accepted: np.ndarray              # [iters, B] step accepted
+    directions: list = dataclasses.field(default_factory=list)
+
+
+def per_model_misfit(prop, pred, obs, nmodels):
+    """J_b = 1/2 sum over model b's samples (FP64 on the device), and the
+    residual (FP32)."""
+    resid = torch.empty_like(pred)
+    J = torch.empty(nmodels, dtype=torch.float64, device=pred.device)
+    per = pred.numel() // nmodels
+    pv, ov, rv = pred.reshape(nmodels, per), obs.reshape(nmodels, per), resid.reshape(nmodels, per)
+    for b in range(nmodels):
+        S._check(S.lib().misfit(prop.model.handle, S._ptr(pv[b]), S._ptr(ov[b]), per, S._ptr(J[b:b + 1]),
+                                S._ptr(rv[b]), S._stream()))
+    return J, resid
+
+
+def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDConfig = GDConfig(),
+               direction=None, target=None, log=None) -> GDResult:
+    """Gradient descent on B models at once.  Per iteration and model: fwd +
+    misfit + adjoint gradient g_b; direction p_b = -g_b, or
+    direction(g, models, it) if given (which returns p and a mask of models
+    whose direction must pass the safeguard); normalised trial step
+    m + alpha p / max|p| with backtracking until J decreases.  A safeguarded
+    direction that is not a descent direction (<p, g> >= 0) or that fails to
+    decrease J is replaced by -g for that model and iteration.  Stops early
+    when every model reaches J/J0 <= target."""
+    B = prop.d.nmodels
+    m = m0.clone().contiguous()
+    alpha = torch.full((B,), cfg.alpha0, dtype=torch.float64)
+    Js, times, acc = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = prop.forward(m, save_ckpt=True)
+    J, r = per_model_misfit(prop, pred, obs, B)
+    J0 = J.cpu().numpy().copy()
+    Js.append(J0.copy())
+    torch.cuda.synchronize()
+    times.append(time.perf_counter() - t0)
+    for it in range(cfg.iters):
+        g = prop.model.gradient(prop.shots, r)
+        gflat = g.reshape(B, -1)
+        p = -g
+        guarded = torch.zeros(B, dtype=torch.bool)
+        if direction is not None:
+            p, guarded = direction(g, m, it)
+        pflat = p.reshape(B, -1)
+        # a guarded direction must be a descent direction
+        descent = (pflat.double() * gflat.double()).sum(1).cpu() < 0
+        fallback = guarded & ~descent
+        if fallback.any():
+            pflat[fallback.to(pflat.device)] = -gflat[fallback.to(pflat.device)]
+        scale = pflat.abs().amax(1).clamp_min(1e-30)
+        Jc = J.cpu().numpy()
+        best = Jc.copy()
+        done = np.zeros(B, dtype=bool)
+        newm = m.clone()
+        a = alpha.clone()
+        first = np.ones(B, dtype=bool)
+        for bt in range(cfg.max_backtracks + 1):
+            trial = (m.reshape(B, -1) + (a.to(m.device, torch.float32) / scale)[:, None] * pflat).reshape(m.shape)
+            trial = trial.clamp(cfg.vmin, cfg.vmax)
+            tp = prop.forward(trial, save_ckpt=False)
+            Jt, _ = per_model_misfit(prop, tp, obs, B)
+            Jt = Jt.cpu().numpy()
+            ok = (~done) & (Jt < Jc)
+            if ok.any():
+                idx = torch.as_tensor(np.nonzero(ok)[0], device=m.device)
+                newm[idx] = trial[idx]
+                best[ok] = Jt[ok]
+            # guarded directions that failed on the first trial fall back to -g
+            if bt == 0 and direction is not None:
+                bad = guarded.numpy() & ~ok
+                if bad.any():
+                    bi = torch.as_tensor(np.nonzero(bad)[0], device=m.device)
+                    pflat[bi] = -gflat[bi]
+                    scale[bi] = pflat[bi].abs().amax(1).clamp_min(1e-30)
+                    guarded[torch.as_tensor(bad)] = False
+                    first[bad] = True
+                    done |= ok
+                    continue
+            for b in np.nonzero(ok)[0]:
+                alpha[b] = a[b] * (cfg.grow if first[b] else 1.0)
+            done |= ok
+            if done.all():
+                break
+            not_ok = ~done
+            a[torch.as_tensor(not_ok)] *= cfg.shrink
+            first[not_ok] = False
+        for b in np.nonzero(~done)[0]:
+            alpha[b] = a[b]
+        acc.append(done.copy())
+        m = newm
+        pred = prop.forward(m, save_ckpt=True)
+        J, r = per_model_misfit(prop, pred, obs, B)
+        Js.append(J.cpu().numpy().copy())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if log:
+            log(it, Js[-1] / J0, done)
+        if target is not None and np.all(Js[-1] / J0 <= target):
+            break
+    return GDResult(models=m, J=np.array(Js), times=np.array(times), accepted=np.array(acc))

@@ -133,12 +133,15 @@ class Shots:
 class Model:
     """A model handle plus its workspace (a torch uint8 device tensor)."""
 
-    def __init__(self, d, vp, max_shots, max_rec, ckpt_every=0, stream=None, vs=None, rho=None):
+    def __init__(self, d, vp, max_shots, max_rec, ckpt_every=0, stream=None, vs=None, rho=None, ws=None):
+        """ws: an existing workspace (uint8 device tensor) to reuse."""
         self.d = d
         self.max_shots, self.max_rec = max_shots, max_rec
         self.elastic = d.physics == SG_ELASTIC
         nbytes = workspace_bytes(d, max_shots, max_rec, ckpt_every)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=vp.device)
+        if ws is not None and ws.numel() < nbytes:
+            raise SeisError(SG_ENOMEM, f"workspace of {ws.numel()} bytes, {nbytes} needed")
+        self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device=vp.device)
         self.handle = C.c_void_p()
         self.vp = vp.contiguous()
         self.vs = None if vs is None else vs.contiguous()
