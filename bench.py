@@ -18,6 +18,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -45,6 +46,27 @@ def bytes_per_cell_step(pml_fraction):
     return {"forward": f, "recompute": f + 4.0, "adjoint": 28.0 + 16.0 * pml_fraction}
 
 
+def measured_traffic(phase):
+    """HBM bytes per step of `phase` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (counters scaled by a plain copy of known size), or None when the
+    kernels' source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ac2_c2_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2003_06027_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256()
+        for f in ("ac2.hip", "sg_internal.h"):
+            h.update(open(os.path.join(src, f), "rb").read())
+    except OSError:
+        return None
+    m = re.search(r"^kernel_source_sha256 (\w+)", text, re.M)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    m = re.search(rf"^step_{phase} (\d+) bytes", text, re.M)
+    return int(m.group(1)) if m else None
+
+
 def cpu_baseline(cfg, c0, src, rec, nshots, nt):
     from oracle import pyoracle as O
     g = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
@@ -66,6 +88,8 @@ def main():
     ap.add_argument("--nt", type=int, default=None, help="override time steps (profiling runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU shot sharding "
@@ -123,6 +147,12 @@ def main():
     t1 = time.perf_counter()
     phases = m.phase_times()
     m.set_profiling(False)
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.ones_like(a)
+        a.copy_(b)
+        torch.cuda.synchronize()
+        del a, b
     assert np.isfinite(J.item()) and np.isfinite(g.abs().max().item())
 
     T = (t1 - t0) / args.steps
@@ -141,6 +171,7 @@ def main():
                     "alg_bytes_per_cell": round(bpc[name], 3), "gbs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     dom = max(ph, key=lambda k: phases[k][0])
+    traffic = measured_traffic(dom)          # HBM bytes per step (layer + tile launch)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
@@ -151,7 +182,7 @@ def main():
                    "cell_updates_per_step": updates},
         "roofline": {"bound": "hbm", "kernel": f"ac2 {dom} step (PML + interior launches)",
                      "achieved": ph[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ph[dom]["frac_hbm"], "traffic": None},
+                     "frac": ph[dom]["frac_hbm"], "traffic": traffic},
         "phases": ph,
     }
     if not args.no_cpu:
