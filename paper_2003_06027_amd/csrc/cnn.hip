@@ -1,0 +1,828 @@
+// cnn.hip -- kernels and C ABI of the learned gradient preconditioner
+// (include/sg_cnn.h).
+//
+// The 32 -> 32 channel 3x3 layers are implicit GEMMs on the matrix cores:
+// v_mfma_f32_16x16x32_bf16 with one 3x3 tap (32 input channels) per
+// K-block.  A workgroup of four wavefronts computes a 4 x 64 output tile,
+// one row per wavefront; the 6 x 66 input tile (one-pixel zero halo) is
+// staged once in LDS with an 80-byte pixel stride, which makes the 16-byte
+// fragment reads of 16 consecutive pixels bank-conflict free.  The weight
+// gradient uses the pixels as the K dimension and reduces per workgroup,
+// then over workgroups in a fixed order.  The thin layers c1 (1 -> 32) and
+// c6 (32 -> 1) are per-pixel FP32 kernels: as GEMMs they would have K = 9 or
+// N = 1, which matrix cores cannot fill.
+#include "../../include/seisgrad.h"
+#include "../../include/sg_cnn.h"
+#include "sg_error.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+using sg::fail;
+
+namespace {
+
+using u16 = unsigned short;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int CH = CNN_CHANNELS;
+constexpr int TH = 4, TW = 64;           // output tile: 4 rows x 64 columns
+constexpr int LH = TH + 2, LW = TW + 2;  // input tile with a one-pixel halo
+constexpr int PS = 40;                   // LDS pixel stride in u16 (32 channels + 8 pad)
+constexpr int NT = 256;                  // threads per workgroup (4 wavefronts)
+constexpr int WMID = CH * 9 * CH;        // weights of one 32 -> 32 layer
+constexpr int PMID = WMID + CH;          // ... with its biases
+constexpr int OFF_C1 = 0, OFF_C2 = 9 * CH + CH, OFF_C6 = OFF_C2 + 4 * PMID;
+constexpr int MAX_WG_WGRAD = 512;        // workgroups (partials) of the MFMA weight gradient
+constexpr int MAX_WG_THIN = 1024;        // ... of the thin-layer weight gradients
+constexpr int THIN_STRIDE = 320;         // partial row of a thin layer (289 or 320 used)
+constexpr int MAX_WG_LOSS = 1024;
+static_assert(OFF_C6 + 9 * CH + 1 == CNN_NPARAMS, "parameter layout");
+
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ u16 f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)                 // inf stays inf, NaN stays NaN
+        return (u16)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest, ties to even
+    return (u16)(u >> 16);
+}
+
+__device__ __forceinline__ unsigned pack2(float a, float b)
+{
+    return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Stage pixels (y0-1 .. y0+TH, x0-1 .. x0+TW) of image n (zero outside) into
+// LDS, 16 bytes (8 channels) per thread and step.
+__device__ __forceinline__ void stage_halo(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
+                                          u16 *lds)
+{
+    for (int i = threadIdx.x; i < LH * LW * 4; i += NT) {
+        const int pix = i >> 2, q = i & 3;
+        const int r = pix / LW, c = pix - r * LW;
+        const int y = y0 - 1 + r, xx = x0 - 1 + c;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (y >= 0 && y < H && xx >= 0 && xx < W)
+            v = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
+        *(u32x4 *)(lds + pix * PS + q * 8) = v;
+    }
+}
+
+// Stage pixels (y0 .. y0+TH-1, x0 .. x0+TW-1) without halo.
+__device__ __forceinline__ void stage_plain(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
+                                           u16 *lds)
+{
+    for (int i = threadIdx.x; i < TH * TW * 4; i += NT) {
+        const int pix = i >> 2, q = i & 3;
+        const int r = pix / TW, c = pix - r * TW;
+        const int y = y0 + r, xx = x0 + c;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (y < H && xx < W)
+            v = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
+        *(u32x4 *)(lds + pix * PS + q * 8) = v;
+    }
+}
+
+// ------------------------------------------------------------ 32 -> 32 layer
+struct ConvArgs {
+    const u16 *x, *w;
+    const float *bias;
+    const u16 *res, *gate;
+    u16 *y;
+    float *y32;
+    int N, H, W, relu;
+};
+
+// grid (ceil(W/64), ceil(H/4), N).  Lane l of a wavefront: r = l % 16 is the
+// fragment row (a pixel for A, an output channel for B), g = l / 16 selects
+// the 8 channels 8g .. 8g+7 of the K-block; the accumulator holds output
+// pixels 4g .. 4g+3 of each 16-pixel block for output channel r.
+__global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) u16 lds[LH * LW * PS];
+    const int n = blockIdx.z, y0 = blockIdx.y * TH, x0 = blockIdx.x * TW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+
+    bf16x8 bw[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+            bw[t][nb] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(a.w + ((16 * nb + r) * 9 + t) * CH + 8 * g));
+
+    stage_halo(a.x, n, a.H, a.W, y0, x0, lds);
+    __syncthreads();
+
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+        acc[mb][0] = acc[mb][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ky = t / 3, kx = t - 3 * (t / 3);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const u16 *p = lds + ((wv + ky) * LW + 16 * mb + r + kx) * PS + 8 * g;
+            const bf16x8 av = __builtin_bit_cast(bf16x8, *(const u32x4 *)p);
+            acc[mb][0] = mfma(av, bw[t][0], acc[mb][0]);
+            acc[mb][1] = mfma(av, bw[t][1], acc[mb][1]);
+        }
+    }
+
+    const int y = y0 + wv;
+    if (y >= a.H) return;
+    const long long rowbase = ((long long)n * a.H + y) * a.W;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int co = 16 * nb + r;
+            const float b = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int px = x0 + 16 * mb + 4 * g + j;
+                if (px >= a.W) continue;
+                const long long idx = (rowbase + px) * CH + co;
+                float v = acc[mb][nb][j] + b;
+                if (a.res) v += bf2f(a.res[idx]);
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.gate && !(bf2f(a.gate[idx]) > 0.f)) v = 0.f;
+                a.y[idx] = f2bf(v);
+                if (a.y32) a.y32[idx] = v;
+            }
+        }
+}
+
+// Weight gradient, K = pixels.  Each wavefront owns one tile row (two
+// K-blocks of 32 pixels); K index 8g + e of a lane maps to pixel 4e + g of
+// the block, the same for both operands, so that the eight 2-byte LDS reads
+// of a fragment hit distinct banks across the lane groups.
+struct WgradArgs {
+    const u16 *dy, *x;
+    float *part;  // [gridDim.x][PMID]
+    int N, H, W, tx, ty, ntiles;
+};
+
+__global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) u16 smem[LH * LW * PS + TH * TW * PS];
+    u16 *lx = smem, *lg = smem + LH * LW * PS;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, u16x8{0x3f80, 0x3f80, 0x3f80, 0x3f80,
+                                                         0x3f80, 0x3f80, 0x3f80, 0x3f80});
+    f32x4 acc[9][2][2];
+    f32x4 accb[2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+        acc[t][0][0] = acc[t][0][1] = acc[t][1][0] = acc[t][1][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accb[0] = accb[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int per = a.tx * a.ty;
+        const int n = tile / per, rem = tile - n * per;
+        const int y0 = (rem / a.tx) * TH, x0 = (rem - (rem / a.tx) * a.tx) * TW;
+        __syncthreads();
+        stage_halo(a.x, n, a.H, a.W, y0, x0, lx);
+        stage_plain(a.dy, n, a.H, a.W, y0, x0, lg);
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            u16x8 ga0, ga1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const u16 *p = lg + (wv * TW + kb * 32 + 4 * e + g) * PS + r;
+                ga0[e] = p[0];
+                ga1[e] = p[16];
+            }
+            const bf16x8 A0 = __builtin_bit_cast(bf16x8, ga0), A1 = __builtin_bit_cast(bf16x8, ga1);
+            accb[0] = mfma(A0, ones, accb[0]);
+            accb[1] = mfma(A1, ones, accb[1]);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int ky = t / 3, kx = t - 3 * (t / 3);
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    u16x8 xb;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        xb[e] = lx[((wv + ky) * LW + kb * 32 + 4 * e + g + kx) * PS + 16 * ib + r];
+                    const bf16x8 B = __builtin_bit_cast(bf16x8, xb);
+                    acc[t][0][ib] = mfma(A0, B, acc[t][0][ib]);
+                    acc[t][1][ib] = mfma(A1, B, acc[t][1][ib]);
+                }
+            }
+        }
+    }
+
+    // fixed-order sum over the four wavefronts in LDS, then one partial row
+    float *red = reinterpret_cast<float *>(smem);
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wv == w) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int co = 16 * cb + 4 * g + j, ci = 16 * ib + r;
+                            const int idx = (co * 9 + t) * CH + ci;
+                            red[idx] = (w == 0 ? 0.f : red[idx]) + acc[t][cb][ib][j];
+                        }
+            if (r == 0)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int idx = WMID + 16 * cb + 4 * g + j;
+                        red[idx] = (w == 0 ? 0.f : red[idx]) + accb[cb][j];
+                    }
+        }
+    }
+    __syncthreads();
+    float *out = a.part + (long long)blockIdx.x * PMID;
+    for (int i = threadIdx.x; i < PMID; i += NT) out[i] = red[i];
+}
+
+// out[i] = sum over b of part[b][i], b ascending, in FP64.
+__global__ void reduce_partials_kernel(const float *__restrict__ part, int nb, int stride, int count,
+                                       float *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += (double)part[(long long)b * stride + i];
+    out[i] = (float)s;
+}
+
+// BF16 copies of c2..c5: wf[L] as stored ([co][tap][ci]) and wt[L] flipped
+// and transposed ([ci][8 - tap][co]), the weights of the input gradient.
+__global__ void prep_weights_kernel(const float *__restrict__ params, u16 *__restrict__ wf, u16 *__restrict__ wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * WMID) return;
+    const int L = i / WMID, k = i - L * WMID;
+    const int co = k / (9 * CH), t = (k / CH) % 9, ci = k % CH;
+    const u16 b = f2bf(params[OFF_C2 + L * PMID + k]);
+    wf[i] = b;
+    wt[L * WMID + (ci * 9 + (8 - t)) * CH + co] = b;
+}
+
+// ------------------------------------------------------------- thin layers
+__device__ __forceinline__ void pixel_of(long long p, int H, int W, int &n, int &y, int &x)
+{
+    x = (int)(p % W);
+    const long long q = p / W;
+    y = (int)(q % H);
+    n = (int)(q / H);
+}
+
+// c1: x1 = relu(b + sum_t w[co][t] g[pix + off_t]) in FP32, stored BF16.
+__global__ __launch_bounds__(256) void conv_in_kernel(const float *__restrict__ g, const float *__restrict__ params,
+                                                      u16 *__restrict__ x1, int N, int H, int W)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)N * H * W) return;
+    int n, y, x;
+    pixel_of(p, H, W, n, y, x);
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        v[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? g[((long long)n * H + yy) * W + xx] : 0.f;
+    }
+    const float *w = params + OFF_C1, *b = params + OFF_C1 + 9 * CH;
+    u32x4 *out = (u32x4 *)(x1 + p * CH);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int co = 8 * q + e;
+            float s = b[co];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) s = fmaf(w[co * 9 + t], v[t], s);
+            o[e] = fmaxf(s, 0.f);
+        }
+        out[q] = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+    }
+}
+
+// c6 and the global residual: p = -g + b + sum_t sum_ci w[t][ci] x3[pix + off_t][ci].
+__global__ __launch_bounds__(256) void conv_out_kernel(const u16 *__restrict__ x3, const float *__restrict__ g,
+                                                       const float *__restrict__ params, float *__restrict__ p,
+                                                       int N, int H, int W)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * H * W) return;
+    int n, y, x;
+    pixel_of(i, H, W, n, y, x);
+    const float *w = params + OFF_C6;
+    float s = params[OFF_C6 + 9 * CH];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+        const u32x4 *src = (const u32x4 *)(x3 + (((long long)n * H + yy) * W + xx) * CH);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const u32x4 u = src[q];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                s = fmaf(w[t * CH + 8 * q + 2 * e], __uint_as_float(u[e] << 16), s);
+                s = fmaf(w[t * CH + 8 * q + 2 * e + 1], __uint_as_float(u[e] & 0xffff0000u), s);
+            }
+        }
+    }
+    p[i] = s - g[i];
+}
+
+// Input gradient of c6 gated by x3 > 0: G[pix][ci] = [x3 > 0] sum_t w[t][ci] dp[pix - off_t].
+__global__ __launch_bounds__(256) void dgrad_out_kernel(const float *__restrict__ dp, const u16 *__restrict__ x3,
+                                                        const float *__restrict__ params, u16 *__restrict__ G,
+                                                        int N, int H, int W)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * H * W) return;
+    int n, y, x;
+    pixel_of(i, H, W, n, y, x);
+    float d[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+        d[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? dp[((long long)n * H + yy) * W + xx] : 0.f;
+    }
+    const float *w = params + OFF_C6;
+    const u32x4 *gate = (const u32x4 *)(x3 + i * CH);
+    u32x4 *out = (u32x4 *)(G + i * CH);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const u32x4 gt = gate[q];
+        float o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int ci = 8 * q + e;
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) s = fmaf(w[t * CH + ci], d[t], s);
+            const unsigned gv = (e & 1) ? (gt[e >> 1] & 0xffff0000u) : (gt[e >> 1] << 16);
+            o[e] = __uint_as_float(gv) > 0.f ? s : 0.f;
+        }
+        out[q] = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+    }
+}
+
+// Weight gradients of the thin layers; 256 threads = 8 pixel lanes x 32
+// channels, each workgroup a contiguous pixel range, fixed-order reductions.
+// OUT = true: c6, dw[t][ci] = sum dp[p] x3[p + off_t][ci], db = sum dp.
+// OUT = false: c1, dw[co][t] = sum G[p][co] g[p + off_t], db[co] = sum G[p][co].
+template <bool OUT>
+__global__ __launch_bounds__(256) void wgrad_thin_kernel(const float *__restrict__ img, const u16 *__restrict__ act,
+                                                         float *__restrict__ part, int N, int H, int W,
+                                                         long long per_wg)
+{
+    __shared__ float red[8][CH * 10];
+    const int c = threadIdx.x & 31, pl = threadIdx.x >> 5;
+    const long long total = (long long)N * H * W;
+    const long long p0 = blockIdx.x * per_wg, p1 = p0 + per_wg < total ? p0 + per_wg : total;
+    float acc[9], sb = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.f;
+    for (long long p = p0 + pl; p < p1; p += 8) {
+        int n, y, x;
+        pixel_of(p, H, W, n, y, x);
+        const float own = OUT ? img[p] : bf2f(act[p * CH + c]);
+        sb += own;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            const long long q = ((long long)n * H + yy) * W + xx;
+            const float other = OUT ? bf2f(act[q * CH + c]) : img[q];
+            acc[t] = fmaf(own, other, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) red[pl][c * 10 + t] = acc[t];
+    red[pl][c * 10 + 9] = sb;
+    __syncthreads();
+    if (pl == 0) {
+        float s[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) s[k] = red[0][c * 10 + k];
+        for (int l = 1; l < 8; ++l)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) s[k] += red[l][c * 10 + k];
+        float *out = part + (long long)blockIdx.x * THIN_STRIDE;
+        if (OUT) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) out[t * CH + c] = s[t];
+            if (c == 0) out[9 * CH] = s[9];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) out[c * 9 + t] = s[t];
+            out[9 * CH + c] = s[9];
+        }
+    }
+}
+
+// --------------------------------------------------------- loss and Adam
+__device__ void block_sum2(double &a, double &b)
+{
+    __shared__ double sa[256], sb[256];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sa[threadIdx.x] += sa[threadIdx.x + s];
+            sb[threadIdx.x] += sb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+}
+
+__global__ __launch_bounds__(256) void loss_partial_kernel(const float *__restrict__ p, const float *__restrict__ t,
+                                                           const float *__restrict__ m, long long n, long long per_wg,
+                                                           double *__restrict__ part)
+{
+    const long long i0 = blockIdx.x * per_wg, i1 = i0 + per_wg < n ? i0 + per_wg : n;
+    double s = 0.0, c = 0.0;
+    for (long long i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double r = (double)p[i] - (double)t[i];
+        s += (double)m[i] * r * r;
+        c += (double)m[i];
+    }
+    block_sum2(s, c);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s;
+        part[2 * blockIdx.x + 1] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void loss_final_kernel(const double *__restrict__ part, int nb, double *L,
+                                                         double *count)
+{
+    double s = 0.0, c = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        s += part[2 * b];
+        c += part[2 * b + 1];
+    }
+    block_sum2(s, c);
+    if (threadIdx.x == 0) {
+        *L = c > 0 ? s / c : 0.0;
+        *count = c;
+    }
+}
+
+__global__ void loss_grad_kernel(const float *__restrict__ p, const float *__restrict__ t, const float *__restrict__ m,
+                                 long long n, const double *__restrict__ count, float *__restrict__ dp)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double c = *count;
+    dp[i] = c > 0 ? (float)(2.0 * (double)m[i] * ((double)p[i] - (double)t[i]) / c) : 0.f;
+}
+
+__global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, long long n, float lr, float b1, float b2, float eps,
+                            float c1, float c2)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// ----------------------------------------------------------------- packing
+__global__ __launch_bounds__(256) void field_inv_rms_kernel(const float *__restrict__ a, const float *__restrict__ b,
+                                                            int nsrc, const int *__restrict__ order, int fh, int fw,
+                                                            double *__restrict__ inv)
+{
+    const int s = blockIdx.x;
+    const int f = order ? order[s] : s;
+    const bool valid = f >= 0 && f < nsrc;
+    const long long n = (long long)fh * fw, base = (long long)f * n;
+    double acc = 0.0, dummy = 0.0;
+    for (long long i = threadIdx.x; valid && i < n; i += 256) {
+        const float v = b ? a[base + i] - b[base + i] : a[base + i];
+        acc += (double)v * (double)v;
+    }
+    block_sum2(acc, dummy);
+    if (threadIdx.x == 0) inv[s] = acc > 0 ? 1.0 / sqrt(acc / (double)n) : 0.0;
+}
+
+__global__ void pack_kernel(const float *__restrict__ a, const float *__restrict__ b, int nsrc,
+                            const int *__restrict__ order, int nfields, int fh, int fw, int frame, const double *__restrict__ inv,
+                            float *__restrict__ patches, float *__restrict__ mask, long long total)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int P = 2 * frame;
+    const int xx = (int)(i % P), yy = (int)((i / P) % P);
+    const long long q = i / ((long long)P * P);
+    const long long s = q * 4 + (yy / frame) * 2 + xx / frame;
+    const int ly = yy % frame, lx = xx % frame;
+    const long long f = s < nfields ? (order ? order[s] : s) : -1;
+    const bool inside = f >= 0 && f < nsrc && ly < fh && lx < fw;
+    float v = 0.f;
+    if (inside) {
+        const long long k = (f * fh + ly) * fw + lx;
+        v = b ? a[k] - b[k] : a[k];
+        if (inv) v *= (float)inv[s];
+    }
+    patches[i] = v;
+    if (mask) mask[i] = inside ? 1.f : 0.f;
+}
+
+__global__ void unpack_kernel(const float *__restrict__ patches, int nfields, int fh, int fw, int frame,
+                              float *__restrict__ fields)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)nfields * fh * fw) return;
+    const int lx = (int)(i % fw), ly = (int)((i / fw) % fh);
+    const long long s = i / ((long long)fh * fw);
+    const int P = 2 * frame;
+    const int k = (int)(s % 4);
+    const long long src = ((s / 4) * P + (k / 2) * frame + ly) * P + (k % 2) * frame + lx;
+    fields[i] = patches[src];
+}
+
+// --------------------------------------------------------------- host side
+#define HIPCHECK(x)                                                                  \
+    do {                                                                             \
+        hipError_t e_ = (x);                                                         \
+        if (e_ != hipSuccess)                                                        \
+            return fail(SG_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct CnnLayout {
+    size_t wf, wt, act[5], gbuf[3], part, loss, total;
+};
+
+CnnLayout cnn_layout(int n, int h, int w)
+{
+    CnnLayout L;
+    const size_t A = up((size_t)n * h * w * CH * sizeof(u16));
+    size_t o = 0;
+    L.wf = o; o += up(4 * WMID * sizeof(u16));
+    L.wt = o; o += up(4 * WMID * sizeof(u16));
+    for (auto &x : L.act) { x = o; o += A; }
+    for (auto &x : L.gbuf) { x = o; o += A; }
+    L.part = o;
+    const size_t pm = (size_t)MAX_WG_WGRAD * PMID, pt = (size_t)MAX_WG_THIN * THIN_STRIDE;
+    o += up((pm > pt ? pm : pt) * sizeof(float));
+    L.loss = o; o += up((2 * MAX_WG_LOSS + 2) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_dims(int n, int h, int w)
+{
+    if (n < 1 || h < 1 || w < 1) return fail(SG_EINVAL, "image extents must be positive (n=%d h=%d w=%d)", n, h, w);
+    if ((long long)n * h * w * CH >= (1LL << 40)) return fail(SG_EINVAL, "images too large");
+    return SG_OK;
+}
+
+int launch_conv(const u16 *x, int n, int h, int w, const u16 *wgt, const float *bias, const u16 *res,
+                const u16 *gate, int relu, u16 *y, float *y32, hipStream_t s)
+{
+    ConvArgs a{x, wgt, bias, res, gate, y, y32, n, h, w, relu};
+    dim3 grid((w + TW - 1) / TW, (h + TH - 1) / TH, n);
+    if (grid.y > 65535u || grid.z > 65535u) return fail(SG_EINVAL, "image batch too large for one launch");
+    conv3x3_mfma_kernel<<<grid, NT, 0, s>>>(a);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int launch_wgrad(const u16 *dy, const u16 *x, int n, int h, int w, float *part, float *out, hipStream_t s)
+{
+    WgradArgs a;
+    a.dy = dy;
+    a.x = x;
+    a.part = part;
+    a.N = n;
+    a.H = h;
+    a.W = w;
+    a.tx = (w + TW - 1) / TW;
+    a.ty = (h + TH - 1) / TH;
+    const long long nt = (long long)a.tx * a.ty * n;
+    if (nt > (1LL << 31) - 1) return fail(SG_EINVAL, "too many tiles");
+    a.ntiles = (int)nt;
+    const int nwg = a.ntiles < MAX_WG_WGRAD ? a.ntiles : MAX_WG_WGRAD;
+    wgrad3x3_mfma_kernel<<<nwg, NT, 0, s>>>(a);
+    HIPCHECK(hipGetLastError());
+    reduce_partials_kernel<<<(PMID + 255) / 256, 256, 0, s>>>(part, nwg, PMID, PMID, out);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+template <bool OUT>
+int launch_wgrad_thin(const float *img, const u16 *act, int n, int h, int w, float *part, float *out, hipStream_t s)
+{
+    const long long total = (long long)n * h * w;
+    long long nwg = (total + 2047) / 2048;
+    if (nwg > MAX_WG_THIN) nwg = MAX_WG_THIN;
+    const long long per = (total + nwg - 1) / nwg;
+    nwg = (total + per - 1) / per;
+    wgrad_thin_kernel<OUT><<<(unsigned)nwg, 256, 0, s>>>(img, act, part, n, h, w, per);
+    HIPCHECK(hipGetLastError());
+    reduce_partials_kernel<<<2, 256, 0, s>>>(part, (int)nwg, THIN_STRIDE, 9 * CH + (OUT ? 1 : CH), out);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+unsigned blocks(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+} // namespace
+
+extern "C" {
+
+size_t cnn_workspace_bytes(int32_t n, int32_t h, int32_t w)
+{
+    if (n < 1 || h < 1 || w < 1) return 0;
+    return cnn_layout(n, h, w).total;
+}
+
+int cnn_forward(const float *params, const float *g, int32_t n, int32_t h, int32_t w, float *p, void *ws,
+                size_t ws_bytes, sg_stream_t stream)
+{
+    if (int e = check_dims(n, h, w)) return e;
+    if (!params || !g || !p || !ws) return fail(SG_EINVAL, "NULL pointer argument");
+    const CnnLayout L = cnn_layout(n, h, w);
+    if (ws_bytes < L.total || !aligned16(ws))
+        return fail(SG_EINVAL, "workspace too small or misaligned (%zu < %zu bytes)", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    u16 *wf = (u16 *)(base + L.wf), *wt = (u16 *)(base + L.wt);
+    u16 *x1 = (u16 *)(base + L.act[0]), *a2 = (u16 *)(base + L.act[1]), *x2 = (u16 *)(base + L.act[2]);
+    u16 *a4 = (u16 *)(base + L.act[3]), *x3 = (u16 *)(base + L.act[4]);
+    const long long pix = (long long)n * h * w;
+    prep_weights_kernel<<<blocks(4 * WMID), 256, 0, s>>>(params, wf, wt);
+    HIPCHECK(hipGetLastError());
+    conv_in_kernel<<<blocks(pix), 256, 0, s>>>(g, params, x1, n, h, w);
+    HIPCHECK(hipGetLastError());
+    const float *bias = params + OFF_C2 + WMID;
+    if (int e = launch_conv(x1, n, h, w, wf + 0 * WMID, bias + 0 * PMID, nullptr, nullptr, 1, a2, nullptr, s)) return e;
+    if (int e = launch_conv(a2, n, h, w, wf + 1 * WMID, bias + 1 * PMID, x1, nullptr, 1, x2, nullptr, s)) return e;
+    if (int e = launch_conv(x2, n, h, w, wf + 2 * WMID, bias + 2 * PMID, nullptr, nullptr, 1, a4, nullptr, s)) return e;
+    if (int e = launch_conv(a4, n, h, w, wf + 3 * WMID, bias + 3 * PMID, x2, nullptr, 1, x3, nullptr, s)) return e;
+    conv_out_kernel<<<blocks(pix), 256, 0, s>>>(x3, g, params, p, n, h, w);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int cnn_backward(const float *params, const float *g, const float *dp, int32_t n, int32_t h, int32_t w, float *grad,
+                 void *ws, size_t ws_bytes, sg_stream_t stream)
+{
+    if (int e = check_dims(n, h, w)) return e;
+    if (!params || !g || !dp || !grad || !ws) return fail(SG_EINVAL, "NULL pointer argument");
+    const CnnLayout L = cnn_layout(n, h, w);
+    if (ws_bytes < L.total || !aligned16(ws))
+        return fail(SG_EINVAL, "workspace too small or misaligned (%zu < %zu bytes)", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const u16 *wt = (const u16 *)(base + L.wt);
+    const u16 *x1 = (u16 *)(base + L.act[0]), *a2 = (u16 *)(base + L.act[1]), *x2 = (u16 *)(base + L.act[2]);
+    const u16 *a4 = (u16 *)(base + L.act[3]), *x3 = (u16 *)(base + L.act[4]);
+    u16 *G0 = (u16 *)(base + L.gbuf[0]), *G1 = (u16 *)(base + L.gbuf[1]), *G2 = (u16 *)(base + L.gbuf[2]);
+    float *part = (float *)(base + L.part);
+    const long long pix = (long long)n * h * w;
+
+    if (int e = launch_wgrad_thin<true>(dp, x3, n, h, w, part, grad + OFF_C6, s)) return e;
+    dgrad_out_kernel<<<blocks(pix), 256, 0, s>>>(dp, x3, params, G0, n, h, w);           // G0 = d pre(x3)
+    HIPCHECK(hipGetLastError());
+    float *gm = grad + OFF_C2;
+    if (int e = launch_wgrad(G0, a4, n, h, w, part, gm + 3 * PMID, s)) return e;
+    if (int e = launch_conv(G0, n, h, w, wt + 3 * WMID, nullptr, nullptr, a4, 0, G1, nullptr, s)) return e; // d pre(a4)
+    if (int e = launch_wgrad(G1, x2, n, h, w, part, gm + 2 * PMID, s)) return e;
+    if (int e = launch_conv(G1, n, h, w, wt + 2 * WMID, nullptr, G0, x2, 0, G2, nullptr, s)) return e;     // d pre(x2)
+    if (int e = launch_wgrad(G2, a2, n, h, w, part, gm + 1 * PMID, s)) return e;
+    if (int e = launch_conv(G2, n, h, w, wt + 1 * WMID, nullptr, nullptr, a2, 0, G0, nullptr, s)) return e; // d pre(a2)
+    if (int e = launch_wgrad(G0, x1, n, h, w, part, gm + 0 * PMID, s)) return e;
+    if (int e = launch_conv(G0, n, h, w, wt + 0 * WMID, nullptr, G2, x1, 0, G1, nullptr, s)) return e;     // d pre(x1)
+    if (int e = launch_wgrad_thin<false>(g, G1, n, h, w, part, grad + OFF_C1, s)) return e;
+    return SG_OK;
+}
+
+int cnn_loss(const float *p, const float *t, const float *mask, int64_t count, double *L_dev, float *dp, void *ws,
+             size_t ws_bytes, sg_stream_t stream)
+{
+    if (!p || !t || !mask || !L_dev || !ws) return fail(SG_EINVAL, "NULL pointer argument");
+    if (count < 1) return fail(SG_EINVAL, "count must be positive");
+    const CnnLayout L = cnn_layout(1, 1, 1);
+    if (ws_bytes < L.total) return fail(SG_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, L.total);
+    // the reduction area sits at the end of every layout; use the last bytes
+    double *part = (double *)((char *)ws + ws_bytes / ALIGN * ALIGN - up((2 * MAX_WG_LOSS + 2) * sizeof(double)));
+    hipStream_t s = (hipStream_t)stream;
+    long long nwg = (count + 4095) / 4096;
+    if (nwg > MAX_WG_LOSS) nwg = MAX_WG_LOSS;
+    const long long per = (count + nwg - 1) / nwg;
+    nwg = (count + per - 1) / per;
+    loss_partial_kernel<<<(unsigned)nwg, 256, 0, s>>>(p, t, mask, count, per, part);
+    HIPCHECK(hipGetLastError());
+    double *cnt = part + 2 * MAX_WG_LOSS;
+    loss_final_kernel<<<1, 256, 0, s>>>(part, (int)nwg, L_dev, cnt);
+    HIPCHECK(hipGetLastError());
+    if (dp) {
+        loss_grad_kernel<<<blocks(count), 256, 0, s>>>(p, t, mask, count, cnt, dp);
+        HIPCHECK(hipGetLastError());
+    }
+    return SG_OK;
+}
+
+int cnn_adam(float *params, const float *grad, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+             float eps, int32_t step, sg_stream_t stream)
+{
+    if (!params || !grad || !m || !v) return fail(SG_EINVAL, "NULL pointer argument");
+    if (n < 1 || step < 1) return fail(SG_EINVAL, "n and step must be positive");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+        return fail(SG_EINVAL, "Adam needs 0 <= beta < 1 and eps > 0");
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+    adam_kernel<<<blocks(n), 256, 0, (hipStream_t)stream>>>(params, grad, m, v, n, lr, beta1, beta2, eps, c1, c2);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int cnn_pack(const float *a, const float *b, int32_t nsrc, const int32_t *order, int32_t nfields, int32_t fh,
+             int32_t fw, int32_t frame, int32_t normalise, double *inv_rms, float *patches, float *mask,
+             sg_stream_t stream)
+{
+    if (!a || !patches) return fail(SG_EINVAL, "NULL pointer argument");
+    if (nfields < 1 || nsrc < 1 || fh < 1 || fw < 1 || frame < fh || frame < fw)
+        return fail(SG_EINVAL, "need nfields, nsrc, fh, fw >= 1 and fh, fw <= frame");
+    if (normalise && !inv_rms) return fail(SG_EINVAL, "normalise needs inv_rms");
+    hipStream_t s = (hipStream_t)stream;
+    if (normalise) {
+        field_inv_rms_kernel<<<nfields, 256, 0, s>>>(a, b, nsrc, order, fh, fw, inv_rms);
+        HIPCHECK(hipGetLastError());
+    }
+    const long long total = (long long)((nfields + 3) / 4) * 4 * frame * frame;
+    pack_kernel<<<blocks(total), 256, 0, s>>>(a, b, nsrc, order, nfields, fh, fw, frame, normalise ? inv_rms : nullptr,
+                                               patches, mask, total);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int cnn_unpack(const float *patches, int32_t nfields, int32_t fh, int32_t fw, int32_t frame, float *fields,
+               sg_stream_t stream)
+{
+    if (!patches || !fields) return fail(SG_EINVAL, "NULL pointer argument");
+    if (nfields < 1 || fh < 1 || fw < 1 || frame < fh || frame < fw)
+        return fail(SG_EINVAL, "need nfields, fh, fw >= 1 and fh, fw <= frame");
+    unpack_kernel<<<blocks((long long)nfields * fh * fw), 256, 0, (hipStream_t)stream>>>(patches, nfields, fh, fw,
+                                                                                         frame, fields);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int cnn_conv3x3(const uint16_t *x, int32_t n, int32_t h, int32_t w, const uint16_t *wgt, const float *bias,
+                const uint16_t *res, const uint16_t *gate, int32_t relu, uint16_t *y, float *y32, sg_stream_t stream)
+{
+    if (int e = check_dims(n, h, w)) return e;
+    if (!x || !wgt || !y) return fail(SG_EINVAL, "NULL pointer argument");
+    if (!aligned16(x) || !aligned16(wgt)) return fail(SG_EINVAL, "x and wgt must be 16-byte aligned");
+    return launch_conv(x, n, h, w, wgt, bias, res, gate, relu, y, y32, (hipStream_t)stream);
+}
+
+int cnn_conv3x3_wgrad(const uint16_t *dy, const uint16_t *x, int32_t n, int32_t h, int32_t w, float *dw, void *ws,
+                      size_t ws_bytes, sg_stream_t stream)
+{
+    if (int e = check_dims(n, h, w)) return e;
+    if (!dy || !x || !dw || !ws) return fail(SG_EINVAL, "NULL pointer argument");
+    if (!aligned16(dy) || !aligned16(x)) return fail(SG_EINVAL, "dy and x must be 16-byte aligned");
+    const CnnLayout L = cnn_layout(1, 1, 1);
+    if (ws_bytes < L.total) return fail(SG_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, L.total);
+    return launch_wgrad(dy, x, n, h, w, (float *)((char *)ws + L.part), dw, (hipStream_t)stream);
+}
+
+} // extern "C"

@@ -8,6 +8,7 @@
 // (two-level checkpointing; memory O(nt/K + K) wavefields instead of O(nt)).
 #include "../../include/seisgrad.h"
 #include "sg_internal.h"
+#include "sg_error.h"
 
 #include <algorithm>
 #include <cmath>
@@ -19,11 +20,10 @@
 
 using namespace sg;
 
-namespace {
+namespace sg {
 
 thread_local std::string g_err;
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -34,6 +34,10 @@ int fail(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
+
+} // namespace sg
+
+namespace {
 
 #define HIPCHECK(x)                                                                  \
     do {                                                                             \

@@ -7,14 +7,19 @@ import re
 
 import pytest
 
+from paper_2003_06027_amd import cnn as N
 from paper_2003_06027_amd import seisgrad as S
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    hdr = open(os.path.join(ROOT, "include", "seisgrad.h")).read()
-    return sorted(set(re.findall(r"SG_API\s+[\w\s\*]+?\b(\w+)\s*\(", hdr)))
+    syms = set()
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if f.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", f)).read()
+            syms |= set(re.findall(r"SG_API\s+[\w\s\*]+?\b(\w+)\s*\(", hdr))
+    return sorted(syms)
 
 
 def test_header_declares_the_paper_calls():
@@ -27,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     lib = S.lib()
     for name in declared_symbols():
         assert hasattr(lib, name), name
-    assert set(declared_symbols()) == set(S.EXPORTS)
+    assert set(declared_symbols()) == set(S.EXPORTS) | set(N.EXPORTS)
 
 
 def test_workspace_bytes_validation_on_host():
@@ -61,3 +66,15 @@ def test_misfit_and_adjoint_reject_bad_arguments_without_gpu():
     assert S.lib().forward_shots(None, None, None, 1, None) == S.SG_EINVAL
     assert S.lib().adjoint_gradient(None, None, None, None, None, None, None, None) == S.SG_EINVAL
     assert S.lib().ricker(10.0, 0.1, 1e-3, 0, None, None) == S.SG_EINVAL
+
+
+def test_cnn_entry_points_validate_on_host():
+    L = N.lib()
+    assert L.cnn_workspace_bytes(0, 4, 4) == 0
+    assert L.cnn_workspace_bytes(2, 256, 256) > 8 * 2 * 256 * 256 * 64
+    assert L.cnn_forward(None, None, 1, 8, 8, None, None, 0, None) == S.SG_EINVAL
+    assert L.cnn_forward(None, None, 0, 8, 8, None, None, 0, None) == S.SG_EINVAL
+    assert b"positive" in L.last_error()
+    assert L.cnn_pack(None, None, 1, None, 1, 5, 5, 4, 1, None, None, None, None) == S.SG_EINVAL
+    assert L.cnn_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == S.SG_EINVAL
+    assert L.cnn_conv3x3(None, 1, 4, 4, None, None, None, None, 0, None, None, None) == S.SG_EINVAL

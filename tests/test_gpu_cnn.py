@@ -1,0 +1,166 @@
+"""GPU parity of the preconditioner kernels (through the C ABI) against the
+FP64 CNN oracle on the same BF16-rounded operands.
+
+Tolerances:
+* single layers and weight gradients: rel-L2 <= 1e-5 (only the FP32
+  accumulation order differs from the oracle's FP64 sums);
+* the whole network: the oracle mirrors every BF16 storage point, yet an
+  FP32-versus-FP64 difference occasionally lands a stored value on the other
+  side of a BF16 rounding boundary (measured: 4.5e-5 of x1's elements), and
+  each later layer spreads such flips to its 3x3x32 neighbourhood (8e-3 of
+  x3's elements, activations rel-L2 4e-4).  Bound: output p rel-L2 <= 1e-3,
+  parameter gradients rel-L2 <= 2e-2 per layer (measured 3e-3 to 1.2e-2 after
+  five backward layers; the BF16 mirror itself differs from the exact FP64
+  network by 7e-2 to 1.3e-1 on these random inputs, so the bound still
+  separates the two by an order of magnitude, and a wrong tap, transpose
+  or residual gives O(1));
+* loss, Adam and packing: FP32 rounding."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import rel_l2, dev
+from oracle import cnn as K
+from paper_2003_06027_amd import cnn as N
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    """Host FP64 copy of the BF16 rounding and the device BF16 tensor."""
+    r = K.round_bf16(a)
+    return r, torch.tensor(r, dtype=torch.float32).to(torch.bfloat16).cuda()
+
+
+def _oracle_layer(x, w, b, res, gate, relu):
+    """x [n,h,w,32] FP64 (NHWC), w [co][3][3][ci] -> NHWC FP64 result of cnn_conv3x3."""
+    xt = torch.tensor(x).permute(0, 3, 1, 2)
+    wt = torch.tensor(w).permute(0, 3, 1, 2).contiguous()
+    v = K.conv3x3(xt, wt, None if b is None else torch.tensor(b)).permute(0, 2, 3, 1).numpy()
+    if res is not None:
+        v = v + res
+    if relu:
+        v = np.maximum(v, 0)
+    if gate is not None:
+        v = np.where(gate > 0, v, 0)
+    return v
+
+
+@pytest.mark.parametrize("shape", [(2, 37, 70), (1, 256, 256), (1, 1, 1), (3, 4, 64)])
+def test_conv3x3_layer_matches_oracle(shape):
+    n, h, w = shape
+    rng = np.random.default_rng(sum(shape))
+    x, xd = _bf16(rng.standard_normal((n, h, w, 32)))
+    wf, wd = _bf16(rng.standard_normal((32, 3, 3, 32)) / 17.0)
+    b = rng.standard_normal(32).astype(np.float32).astype(np.float64)
+    res, rd = _bf16(rng.standard_normal((n, h, w, 32)))
+    gate, gd = _bf16(rng.standard_normal((n, h, w, 32)))
+    for args in [(None, None, None, False), (b, None, None, True), (b, res, None, True), (None, res, gate, False)]:
+        bb, rr, gg, relu = args
+        ref = _oracle_layer(x, wf, bb, rr, gg, relu)
+        y, y32 = N.conv3x3(xd, wd, None if bb is None else dev(bb), None if rr is None else rd,
+                           None if gg is None else gd, relu, want_fp32=True)
+        e = rel_l2(y32.cpu().numpy(), ref) if np.any(ref) else float(np.abs(y32.cpu().numpy()).max())
+        assert e <= 1e-5, (shape, args[3], e)
+        # the BF16 output is the FP32 result rounded to nearest even
+        assert torch.equal(y, y32.to(torch.bfloat16))
+
+
+@pytest.mark.parametrize("shape", [(2, 37, 70), (2, 256, 256), (1, 3, 5)])
+def test_conv3x3_weight_gradient_matches_oracle(shape):
+    n, h, w = shape
+    rng = np.random.default_rng(100 + sum(shape))
+    x, xd = _bf16(rng.standard_normal((n, h, w, 32)))
+    dy, dyd = _bf16(rng.standard_normal((n, h, w, 32)))
+    ws = N.new_workspace(1, 1, 1)
+    got = N.conv3x3_wgrad(dyd, xd, ws).cpu().numpy()
+    dw = K.conv3x3_weight_grad(torch.tensor(dy).permute(0, 3, 1, 2), torch.tensor(x).permute(0, 3, 1, 2))
+    ref_w = dw.permute(0, 2, 3, 1).reshape(-1).numpy()        # [co][ky][kx][ci]
+    ref_b = dy.sum(axis=(0, 1, 2))
+    assert rel_l2(got[:9216], ref_w) <= 1e-5
+    assert rel_l2(got[9216:], ref_b) <= 1e-5
+    # fixed-order reductions: bitwise reproducible
+    assert np.array_equal(got, N.conv3x3_wgrad(dyd, xd, ws).cpu().numpy())
+
+
+def _trained_like_params(seed):
+    rng = np.random.default_rng(seed)
+    p = N.init_params(seed).astype(np.float64)
+    wo, bo, _, cout = N.offsets()[5]
+    p[wo:bo] = rng.standard_normal(bo - wo) * 0.05          # a non-zero last layer
+    for wo, bo, cin, cout in N.offsets():
+        p[bo:bo + cout] = rng.standard_normal(cout) * 0.02
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("shape", [(2, 40, 70), (2, 256, 256)])
+def test_network_forward_backward_match_oracle(shape):
+    n, h, w = shape
+    rng = np.random.default_rng(7)
+    params = _trained_like_params(3)
+    g = rng.standard_normal((n, h, w)).astype(np.float32)
+    dp = rng.standard_normal((n, h, w)).astype(np.float32)
+    pd, gd = dev(params), dev(g)
+    ws = N.new_workspace(n, h, w)
+    p = N.forward(pd, gd, ws)
+    grad = N.backward(pd, gd, dev(dp), ws).cpu().numpy()
+    rp, acts = K.forward(params.astype(np.float64), g, bf16=True)
+    rg = K.backward(params.astype(np.float64), acts, dp, bf16=True)
+    ep = rel_l2(p.cpu().numpy(), rp)
+    # the network's own contribution N(g) = p + g, compared on its own
+    en = rel_l2(p.cpu().numpy() + g, rp + g)
+    print(f"net p rel-L2 {ep:.2e}, N(g) {en:.2e}")
+    assert ep <= 1e-3 and en <= 1e-3
+    errs = []
+    for li, (wo, bo, cin, cout) in enumerate(N.offsets()):
+        ew = rel_l2(grad[wo:bo], rg[wo:bo])
+        eb = rel_l2(grad[bo:bo + cout], rg[bo:bo + cout])
+        print(f"layer {li + 1}: dW {ew:.2e} db {eb:.2e}")
+        errs += [ew, eb]
+    assert max(errs) <= 2e-2
+    # bitwise reproducible
+    N.forward(pd, gd, ws)
+    assert np.array_equal(grad, N.backward(pd, gd, dev(dp), ws).cpu().numpy())
+
+
+def test_untrained_network_is_the_plain_direction():
+    rng = np.random.default_rng(9)
+    g = dev(rng.standard_normal((3, 64, 80)))
+    ws = N.new_workspace(3, 64, 80)
+    p = N.forward(dev(N.init_params(1)), g, ws)
+    assert torch.equal(p, -g)
+
+
+def test_loss_adam_pack_unpack_match_oracle():
+    rng = np.random.default_rng(11)
+    # loss
+    p = rng.standard_normal((3, 20, 30)).astype(np.float32)
+    t = rng.standard_normal((3, 20, 30)).astype(np.float32)
+    m = (rng.random((3, 20, 30)) < 0.6).astype(np.float32)
+    ws = N.new_workspace(1, 1, 1)
+    L, dp = N.loss(dev(p), dev(t), dev(m), ws)
+    rL, rdp = K.loss(p, t, m)
+    assert abs(L.item() - rL) <= 1e-12 * rL
+    assert rel_l2(dp.cpu().numpy(), rdp) <= 1e-6
+    L0, dp0 = N.loss(dev(p), dev(t), dev(np.zeros_like(m)), ws)
+    assert L0.item() == 0.0 and not dp0.any()
+    # Adam, three steps
+    w0 = rng.standard_normal(1000).astype(np.float32)
+    wd, md, vd = dev(w0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    rw, rm, rv = w0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in (1, 2, 3):
+        gr = rng.standard_normal(1000).astype(np.float32)
+        N.adam(wd, dev(gr), md, vd, step, 1e-2)
+        rw, rm, rv = K.adam(rw, gr.astype(np.float64), rm, rv, step, 1e-2)
+    assert rel_l2(wd.cpu().numpy() - w0, rw - w0) <= 1e-5
+    # packing with a difference, normalisation and a slot order
+    a = rng.standard_normal((7, 101, 101)).astype(np.float32) * 5 + 2
+    b = rng.standard_normal((7, 101, 101)).astype(np.float32)
+    order = rng.permutation(7).astype(np.int32)
+    pk, mk, inv = N.pack(dev(a), 128, b=dev(b), order=torch.tensor(order, device="cuda"))
+    rpk, rmk = K.pack(a.astype(np.float64) - b.astype(np.float64), 128, order=order)
+    assert pk.shape == (2, 256, 256)
+    assert rel_l2(pk.cpu().numpy(), rpk) <= 1e-6
+    assert np.array_equal(mk.cpu().numpy(), rmk)
+    back = N.unpack(pk, 7, 101, 101, 128).cpu().numpy()
+    assert np.array_equal(back, K.unpack(pk.cpu().numpy(), 7, 101, 101, 128))
