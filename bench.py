@@ -12,6 +12,12 @@ ceil(sqrt(4000)) = 64 steps; velocity 1500-4500 m/s from 12 seeded dipping
 layers + 20 Gaussian anomalies (a stand-in for the paper's Marmousi-class
 FWI model), initial model its 10-cell Gaussian blur.
 
+Second leg (the metric's "time-to-misfit w/ vs w/o CNN"): the learned
+preconditioner experiment -- training data from 200 batched plain
+inversions of random three-layer 101 x 101 models, CNN training with the
+library's BF16 matrix-core kernels, then plain and preconditioned descent on
+20 unseen models; reported under "time_to_misfit" (skip with --no-ttm).
+
 Prints ONE JSON line (rank 0, N = 1).
 """
 import argparse
@@ -88,6 +94,7 @@ def main():
     ap.add_argument("--nt", type=int, default=None, help="override time steps (profiling runs only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--no-ttm", action="store_true", help="skip the learned-preconditioner time-to-misfit leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -185,6 +192,28 @@ def main():
                      "frac": ph[dom]["frac_hbm"], "traffic": traffic},
         "phases": ph,
     }
+    if not args.no_ttm:
+        m.close()
+        del m, seis, resid, obs
+        torch.cuda.empty_cache()
+        from paper_2003_06027_amd import ttm
+        log("time-to-misfit: data generation, CNN training and evaluation")
+        r = ttm.run(ttm.TTMConfig(), log=log)
+        out["time_to_misfit"] = {
+            "metric": "seconds until J/J0 <= tau (median over 20 unseen 3-layer models batched in one launch)",
+            "tau": round(r["tau"], 4),
+            "median_seconds_gd": round(r["median_seconds_gd"], 3),
+            "median_seconds_cnn": round(r["median_seconds_cnn"], 3),
+            "speedup": round(r["median_seconds_gd"] / r["median_seconds_cnn"], 2),
+            "median_iters_gd": r["median_iters_gd"], "median_iters_cnn": r["median_iters_cnn"],
+            "reached_gd": r["reached_gd"], "reached_cnn": r["reached_cnn"], "models": r["models"],
+            "final_rel_misfit_median_gd": round(r["final_rel_misfit_median_gd"], 4),
+            "final_rel_misfit_median_cnn": round(r["final_rel_misfit_median_cnn"], 4),
+            "cnn_acceptance": round(r["cnn_acceptance"], 3),
+            "data_seconds": round(r["data_seconds"], 2), "train_seconds": round(r["train_seconds"], 2),
+            "break_even_batches": None if r["break_even_batches"] is None else round(r["break_even_batches"], 1),
+            "val_loss_untrained_trained": [round(v, 4) for v in r["val_loss_untrained_trained"]],
+        }
     if not args.no_cpu:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         ncpu = max(1, min(cores, ns))

@@ -107,7 +107,8 @@ class GDResult:
     J: np.ndarray                     # [iters + 1, B] misfit per iteration
     times: np.ndarray                 # [iters + 1] wall seconds since start (after device sync)
     accepted: np.ndarray              # [iters, B] step accepted
-    directions: list = dataclasses.field(default_factory=list)
+    guarded: np.ndarray = None        # [iters, B] a guarded (e.g. learned) direction was offered
+    rejected: np.ndarray = None       # [iters, B] ... and replaced by the plain direction
 
 
 def per_model_misfit(prop, pred, obs, nmodels):
@@ -131,12 +132,14 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
     whose direction must pass the safeguard); normalised trial step
     m + alpha p / max|p| with backtracking until J decreases.  A safeguarded
     direction that is not a descent direction (<p, g> >= 0) or that fails to
-    decrease J is replaced by -g for that model and iteration.  Stops early
-    when every model reaches J/J0 <= target."""
+    decrease J on its first trial is replaced by -g for that model and
+    iteration; a direction object with a ``report(it, rejected)`` method is
+    told which models that happened to.  Stops early when every model
+    reaches J/J0 <= target."""
     B = prop.d.nmodels
     m = m0.clone().contiguous()
     alpha = torch.full((B,), cfg.alpha0, dtype=torch.float64)
-    Js, times, acc = [], [], []
+    Js, times, acc, offered, rej = [], [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pred = prop.forward(m, save_ckpt=True)
@@ -152,10 +155,14 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
         guarded = torch.zeros(B, dtype=torch.bool)
         if direction is not None:
             p, guarded = direction(g, m, it)
+            guarded = guarded.clone()
+        offered.append(guarded.numpy().copy())
         pflat = p.reshape(B, -1)
         # a guarded direction must be a descent direction
         descent = (pflat.double() * gflat.double()).sum(1).cpu() < 0
         fallback = guarded & ~descent
+        rejected = fallback.numpy().copy()
+        guarded = guarded & descent
         if fallback.any():
             pflat[fallback.to(pflat.device)] = -gflat[fallback.to(pflat.device)]
         scale = pflat.abs().amax(1).clamp_min(1e-30)
@@ -176,28 +183,31 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
                 idx = torch.as_tensor(np.nonzero(ok)[0], device=m.device)
                 newm[idx] = trial[idx]
                 best[ok] = Jt[ok]
-            # guarded directions that failed on the first trial fall back to -g
-            if bt == 0 and direction is not None:
-                bad = guarded.numpy() & ~ok
-                if bad.any():
-                    bi = torch.as_tensor(np.nonzero(bad)[0], device=m.device)
-                    pflat[bi] = -gflat[bi]
-                    scale[bi] = pflat[bi].abs().amax(1).clamp_min(1e-30)
-                    guarded[torch.as_tensor(bad)] = False
-                    first[bad] = True
-                    done |= ok
-                    continue
             for b in np.nonzero(ok)[0]:
                 alpha[b] = a[b] * (cfg.grow if first[b] else 1.0)
             done |= ok
+            # guarded directions that fail their first trial fall back to -g,
+            # which then gets a first trial of its own at the same step
+            retry = np.zeros(B, dtype=bool)
+            if bt == 0:
+                retry = guarded.numpy() & ~ok
+                if retry.any():
+                    rejected |= retry
+                    bi = torch.as_tensor(np.nonzero(retry)[0], device=m.device)
+                    pflat[bi] = -gflat[bi]
+                    scale[bi] = pflat[bi].abs().amax(1).clamp_min(1e-30)
+                    guarded[torch.as_tensor(retry)] = False
             if done.all():
                 break
-            not_ok = ~done
-            a[torch.as_tensor(not_ok)] *= cfg.shrink
-            first[not_ok] = False
+            shrink = ~done & ~retry
+            a[torch.as_tensor(shrink)] *= cfg.shrink
+            first[shrink] = False
         for b in np.nonzero(~done)[0]:
             alpha[b] = a[b]
         acc.append(done.copy())
+        rej.append(rejected)
+        if direction is not None and hasattr(direction, "report"):
+            direction.report(it, rejected)
         m = newm
         pred = prop.forward(m, save_ckpt=True)
         J, r = per_model_misfit(prop, pred, obs, B)
@@ -208,4 +218,5 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
             log(it, Js[-1] / J0, done)
         if target is not None and np.all(Js[-1] / J0 <= target):
             break
-    return GDResult(models=m, J=np.array(Js), times=np.array(times), accepted=np.array(acc))
+    return GDResult(models=m, J=np.array(Js), times=np.array(times), accepted=np.array(acc),
+                    guarded=np.array(offered), rejected=np.array(rej))
