@@ -178,3 +178,40 @@ class Preconditioner:
             x, _, _ = pack(gb, self.frame, with_mask=False)
             out[s:s + gb.shape[0]] = unpack(self.forward(x), gb.shape[0], fh, fw, self.frame)
         return out
+
+
+def _main():
+    """Times training steps on seeded random patches (a profiling harness for
+    the network kernels): python -m paper_2003_06027_amd.cnn --steps 50."""
+    import argparse
+    import json
+    import time
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--size", type=int, default=256)
+    a = ap.parse_args()
+    rng = np.random.default_rng(0)
+    shp = (a.batch, a.size, a.size)
+    x = torch.tensor(rng.standard_normal(shp), dtype=torch.float32, device="cuda")
+    t = torch.tensor(rng.standard_normal(shp), dtype=torch.float32, device="cuda")
+    mask = torch.ones(shp, dtype=torch.float32, device="cuda")
+    pre = Preconditioner(a.batch, a.size, seed=0)
+    pre.params[N_LAST_W:] = torch.tensor(rng.standard_normal(NPARAMS - N_LAST_W) * 0.05, dtype=torch.float32,
+                                         device="cuda")
+    pre.train_step(x, t, mask, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        pre.train_step(x, t, mask, 1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    flop = 3 * 2 * a.batch * a.size * a.size * sum(9 * ci * co for ci, co in LAYERS)
+    print(json.dumps({"ms_per_train_step": round(dt * 1e3, 3), "patches": a.batch,
+                      "tflops_fwd_bwd": round(flop / dt / 1e12, 2)}))
+
+
+N_LAST_W = offsets()[5][0]
+
+if __name__ == "__main__":
+    _main()

@@ -261,15 +261,25 @@ __global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
     for (int i = threadIdx.x; i < PMID; i += NT) out[i] = red[i];
 }
 
-// out[i] = sum over b of part[b][i], b ascending, in FP64.
-__global__ void reduce_partials_kernel(const float *__restrict__ part, int nb, int stride, int count,
-                                       float *__restrict__ out)
+// out[i] = sum over b of part[b][i] in FP64, in a fixed order: lane l of
+// output i sums rows b = l, l + 16, ... in ascending order, then the 16 lane
+// sums are added in lane order.  256 threads = 16 outputs x 16 lanes.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float *__restrict__ part, int nb, int stride,
+                                                              int count, float *__restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    __shared__ double red[16][17];
+    const int o = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + o;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += (double)part[(long long)b * stride + i];
-    out[i] = (float)s;
+    if (i < count)
+        for (int b = l; b < nb; b += 16) s += (double)part[(long long)b * stride + i];
+    red[l][o] = s;
+    __syncthreads();
+    if (l == 0 && i < count) {
+        double t = red[0][o];
+        for (int k = 1; k < 16; ++k) t += red[k][o];
+        out[i] = (float)t;
+    }
 }
 
 // BF16 copies of c2..c5: wf[L] as stored ([co][tap][ci]) and wt[L] flipped
@@ -389,58 +399,71 @@ __global__ __launch_bounds__(256) void dgrad_out_kernel(const float *__restrict_
     }
 }
 
-// Weight gradients of the thin layers; 256 threads = 8 pixel lanes x 32
-// channels, each workgroup a contiguous pixel range, fixed-order reductions.
-// OUT = true: c6, dw[t][ci] = sum dp[p] x3[p + off_t][ci], db = sum dp.
-// OUT = false: c1, dw[co][t] = sum G[p][co] g[p + off_t], db[co] = sum G[p][co].
+// Weight gradients of the thin layers, on the 4 x 64 pixel tiles of the
+// 32 -> 32 layers (grid-stride over tiles, per-thread register sums, one
+// partial row per workgroup; the rows are reduced in a fixed order after).
+// c6: out[t * 32 + ci] = sum_p dp[p] x3[p + off_t][ci] (t < 9), out[288] = sum dp.
+// c1: out[co * 9 + t] = sum_p G[p][co] g[p + off_t], out[288 + co] = sum_p G[p][co].
 template <bool OUT>
-__global__ __launch_bounds__(256) void wgrad_thin_kernel(const float *__restrict__ img, const u16 *__restrict__ act,
-                                                         float *__restrict__ part, int N, int H, int W,
-                                                         long long per_wg)
+__global__ __launch_bounds__(NT) void wgrad_thin_kernel(const float *__restrict__ img, const u16 *__restrict__ act,
+                                                        float *__restrict__ part, int H, int W, int tx, int ty,
+                                                        int ntiles)
 {
-    __shared__ float red[8][CH * 10];
-    const int c = threadIdx.x & 31, pl = threadIdx.x >> 5;
-    const long long total = (long long)N * H * W;
-    const long long p0 = blockIdx.x * per_wg, p1 = p0 + per_wg < total ? p0 + per_wg : total;
-    float acc[9], sb = 0.f;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = 0.f;
-    for (long long p = p0 + pl; p < p1; p += 8) {
-        int n, y, x;
-        pixel_of(p, H, W, n, y, x);
-        const float own = OUT ? img[p] : bf2f(act[p * CH + c]);
-        sb += own;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            const long long q = ((long long)n * H + yy) * W + xx;
-            const float other = OUT ? bf2f(act[q * CH + c]) : img[q];
-            acc[t] = fmaf(own, other, acc[t]);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) red[pl][c * 10 + t] = acc[t];
-    red[pl][c * 10 + 9] = sb;
-    __syncthreads();
-    if (pl == 0) {
-        float s[10];
-#pragma unroll
-        for (int k = 0; k < 10; ++k) s[k] = red[0][c * 10 + k];
-        for (int l = 1; l < 8; ++l)
-#pragma unroll
-            for (int k = 0; k < 10; ++k) s[k] += red[l][c * 10 + k];
-        float *out = part + (long long)blockIdx.x * THIN_STRIDE;
+    __shared__ __attribute__((aligned(16))) u16 la[(OUT ? LH * LW : TH * TW) * PS];
+    __shared__ float li[OUT ? TH * TW : LH * LW];
+    constexpr int NOUT = OUT ? 9 * CH + 1 : 9 * CH + CH;
+    float acc0 = 0.f, acc1 = 0.f;
+    const int o0 = threadIdx.x, o1 = threadIdx.x + NT;   // o1 valid when < NOUT
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int per = tx * ty;
+        const int n = tile / per, rem = tile - n * per;
+        const int y0 = (rem / tx) * TH, x0 = (rem - (rem / tx) * tx) * TW;
+        __syncthreads();
         if (OUT) {
-#pragma unroll
-            for (int t = 0; t < 9; ++t) out[t * CH + c] = s[t];
-            if (c == 0) out[9 * CH] = s[9];
+            stage_halo(act, n, H, W, y0, x0, la);
+            for (int i = threadIdx.x; i < TH * TW; i += NT) {
+                const int y = y0 + i / TW, x = x0 + i % TW;
+                li[i] = (y < H && x < W) ? img[((long long)n * H + y) * W + x] : 0.f;
+            }
         } else {
+            stage_plain(act, n, H, W, y0, x0, la);
+            for (int i = threadIdx.x; i < LH * LW; i += NT) {
+                const int y = y0 - 1 + i / LW, x = x0 - 1 + i % LW;
+                li[i] = (y >= 0 && y < H && x >= 0 && x < W) ? img[((long long)n * H + y) * W + x] : 0.f;
+            }
+        }
+        __syncthreads();
 #pragma unroll
-            for (int t = 0; t < 9; ++t) out[c * 9 + t] = s[t];
-            out[9 * CH + c] = s[9];
+        for (int q = 0; q < 2; ++q) {
+            const int o = q ? o1 : o0;
+            if (o >= NOUT) continue;
+            float s = 0.f;
+            if (OUT) {
+                if (o < 9 * CH) {
+                    const int t = o / CH, ci = o % CH, ky = t / 3, kx = t % 3;
+                    for (int r = 0; r < TH; ++r)
+                        for (int c = 0; c < TW; ++c)
+                            s = fmaf(li[r * TW + c], bf2f(la[((r + ky) * LW + c + kx) * PS + ci]), s);
+                } else {
+                    for (int i = 0; i < TH * TW; ++i) s += li[i];
+                }
+            } else {
+                if (o < 9 * CH) {
+                    const int co = o / 9, t = o % 9, ky = t / 3, kx = t % 3;
+                    for (int r = 0; r < TH; ++r)
+                        for (int c = 0; c < TW; ++c)
+                            s = fmaf(bf2f(la[(r * TW + c) * PS + co]), li[(r + ky) * LW + c + kx], s);
+                } else {
+                    const int co = o - 9 * CH;
+                    for (int i = 0; i < TH * TW; ++i) s += bf2f(la[i * PS + co]);
+                }
+            }
+            if (q) acc1 += s; else acc0 += s;
         }
     }
+    float *out = part + (long long)blockIdx.x * THIN_STRIDE;
+    if (o0 < NOUT) out[o0] = acc0;
+    if (o1 < NOUT) out[o1] = acc1;
 }
 
 // --------------------------------------------------------- loss and Adam
@@ -640,7 +663,7 @@ int launch_wgrad(const u16 *dy, const u16 *x, int n, int h, int w, float *part, 
     const int nwg = a.ntiles < MAX_WG_WGRAD ? a.ntiles : MAX_WG_WGRAD;
     wgrad3x3_mfma_kernel<<<nwg, NT, 0, s>>>(a);
     HIPCHECK(hipGetLastError());
-    reduce_partials_kernel<<<(PMID + 255) / 256, 256, 0, s>>>(part, nwg, PMID, PMID, out);
+    reduce_partials_kernel<<<(PMID + 15) / 16, 256, 0, s>>>(part, nwg, PMID, PMID, out);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }
@@ -648,14 +671,14 @@ int launch_wgrad(const u16 *dy, const u16 *x, int n, int h, int w, float *part, 
 template <bool OUT>
 int launch_wgrad_thin(const float *img, const u16 *act, int n, int h, int w, float *part, float *out, hipStream_t s)
 {
-    const long long total = (long long)n * h * w;
-    long long nwg = (total + 2047) / 2048;
-    if (nwg > MAX_WG_THIN) nwg = MAX_WG_THIN;
-    const long long per = (total + nwg - 1) / nwg;
-    nwg = (total + per - 1) / per;
-    wgrad_thin_kernel<OUT><<<(unsigned)nwg, 256, 0, s>>>(img, act, part, n, h, w, per);
+    const int tx = (w + TW - 1) / TW, ty = (h + TH - 1) / TH;
+    const long long nt = (long long)tx * ty * n;
+    if (nt > (1LL << 31) - 1) return fail(SG_EINVAL, "too many tiles");
+    const int nwg = nt < MAX_WG_THIN ? (int)nt : MAX_WG_THIN;
+    wgrad_thin_kernel<OUT><<<nwg, NT, 0, s>>>(img, act, part, h, w, tx, ty, (int)nt);
     HIPCHECK(hipGetLastError());
-    reduce_partials_kernel<<<2, 256, 0, s>>>(part, (int)nwg, THIN_STRIDE, 9 * CH + (OUT ? 1 : CH), out);
+    const int count = OUT ? 9 * CH + 1 : 9 * CH + CH;
+    reduce_partials_kernel<<<(count + 15) / 16, 256, 0, s>>>(part, nwg, THIN_STRIDE, count, out);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }
