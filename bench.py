@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--no-ttm", action="store_true", help="skip the learned-preconditioner time-to-misfit leg")
+    ap.add_argument("--time-blocking", type=int, default=2, choices=(1, 2),
+                    help="time steps per launch on the blocked tiles (results are identical)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -128,6 +130,7 @@ def main():
     mt.close()
     del mt
     m = S.Model(d, dev(c0), ns, nrec, ckpt)
+    m.set_time_blocking(args.time_blocking)
     seis = torch.empty_like(obs)
     resid = torch.empty_like(obs)
     J = torch.empty(1, dtype=torch.float64, device="cuda")

@@ -180,6 +180,16 @@ SG_API int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd,
 SG_API int set_profiling(sg_model *m, int32_t enable);
 SG_API int phase_times(sg_model *m, double *ms, int64_t *steps);
 
+/* Time blocking of the 2-D acoustic sweeps (the recursion of Eq. (1), run
+ * unchanged): with steps = 2 (the default) tiles whose cells and 8-cell halo
+ * are all physical and hold no receiver within 4 cells advance two time steps
+ * per launch, the other tiles one; steps = 1 advances every tile one step
+ * per launch.  Every value is computed with the same operations either way,
+ * so seismograms and gradients are bitwise identical; only the memory
+ * traffic and the launch count change.  Other physics ignore the setting.
+ * Returns SG_EINVAL unless steps is 1 or 2. */
+SG_API int set_time_blocking(sg_model *m, int32_t steps);
+
 /* Release the host object (the workspace stays the caller's). */
 SG_API int free_model(sg_model *m);
 

@@ -53,12 +53,16 @@ __device__ __forceinline__ long long fidx(const Grid2 &g, int iz, int ix)
 // sum to zero, so L~u = sum_m a_m ((u_{+m} - u_0) + (u_{-m} - u_0)) along each
 // axis: neighbour differences of a smooth field are exact or nearly so in
 // FP32, which keeps the rounding error proportional to L~u instead of u.
+// The multiply-adds are explicit so that every kernel evaluating the
+// stencil rounds identically (the one- and two-step paths agree bitwise).
 __device__ __forceinline__ float lap8(const float *c, int W)
 {
     const float c0 = c[0];
     auto pair = [&](int o) { return (c[o] - c0) + (c[-o] - c0); };
-    return A4 * (pair(4) + pair(4 * W)) + A3 * (pair(3) + pair(3 * W))
-         + A2 * (pair(2) + pair(2 * W)) + A1 * (pair(1) + pair(W));
+    float t = A4 * (pair(4) + pair(4 * W));
+    t = fmaf(A3, pair(3) + pair(3 * W), t);
+    t = fmaf(A2, pair(2) + pair(2 * W), t);
+    return fmaf(A1, pair(1) + pair(W), t);
 }
 
 template <class T>
@@ -174,7 +178,8 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
     __syncthreads();
 
     const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    float *um = a.um + so;
+    const float *um = a.um + so;
+    float *uo = a.un + so;
     const long long src = a.src_f[shot];
     const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
     float un[RPT];
@@ -198,11 +203,11 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
                 v = alpha * (uc[j] + inc);
             } else {
                 // 2u - um + chat w = u + ((u - um) + chat w)
-                float inc = (uc[j] - um[f]) + chat[f] * w;
+                float inc = fmaf(chat[f], w, uc[j] - um[f]);
                 if (f == src) inc += sval;
                 v = uc[j] + inc;
             }
-            um[f] = v;
+            uo[f] = v;
             un[j] = v;
             if constexpr (SNAP) a.snap[so + f] = w;
         }
@@ -231,9 +236,10 @@ template <bool SNAP, bool REC>
 __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
 {
     __shared__ float su[(TZ + 8) * (TX + 8)];
-    const int ntiles = a.g.ntx * a.g.ntz;
-    const int w = xcd_work_id(ntiles * a.nshots);
-    const int shot = w / ntiles, tile = w - shot * ntiles;
+    const int ntl = a.tiles ? a.ntl : a.g.ntx * a.g.ntz;
+    const int w = xcd_work_id(ntl * a.nshots);
+    const int shot = w / ntl, ti = w - shot * ntl;
+    const int tile = a.tiles ? a.tiles[ti] : ti;
     const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
     if (near_layer(a.g, tx * TX, tz * TZ)) fwd_tile<true, SNAP, REC>(a, su, tile, shot);
     else                                    fwd_tile<false, SNAP, REC>(a, su, tile, shot);
@@ -292,7 +298,8 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
     load_halo(g, sc, x0, z0, [&](long long f) { return chat[f] * s2[f]; });
     __syncthreads();
 
-    float *s3 = a.s3 + so;
+    const float *s3 = a.s3 + so;
+    float *s1o = a.s1 + so;
     float av[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -344,8 +351,8 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
             const long long f = fidx(g, iz, ix);
             float s1 = av[j];
             if constexpr (NEAR) s1 = s1 / (1.f + a.hx[ix] + a.hz[iz]);
-            s3[f] = s1;
-            a.grad[so + f] += s1 * a.snap[so + f];
+            s1o[f] = s1;
+            a.grad[so + f] = fmaf(s1, a.snap[so + f], a.grad[so + f]);
             if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
         }
     }
@@ -354,15 +361,257 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
 __global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
 {
     __shared__ float sc[(TZ + 8) * (TX + 8)];
-    const int ntiles = a.g.ntx * a.g.ntz;
-    const int w = xcd_work_id(ntiles * a.nshots);
-    const int shot = w / ntiles, tile = w - shot * ntiles;
+    const int ntl = a.tiles ? a.ntl : a.g.ntx * a.g.ntz;
+    const int w = xcd_work_id(ntl * a.nshots);
+    const int shot = w / ntl, ti = w - shot * ntl;
+    const int tile = a.tiles ? a.tiles[ti] : ti;
     const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
     if (near_layer(a.g, tx * TX, tz * TZ)) adj_tile<true>(a, sc, tile, shot);
     else                                    adj_tile<false>(a, sc, tile, shot);
 }
 
+// ---------------------------------------------------------- two-step kernels
+// Blocked tiles: the tile and its 8-cell halo are physical cells, so pass A
+// and every layer term vanish there and the forward update reduces to
+// u^{k+1} = u^k + ((u^k - u^{k-1}) + chat w~^k) (+ source).  One launch
+// forms u^{k+1} on the tile + 4 in LDS from u^k on the tile + 8, then
+// u^{k+2} on the tile: two steps for one read of u^k, u^{k-1} and chat and
+// one write of u^{k+1}, u^{k+2}.  Each value is computed with exactly the
+// operations of the single-step kernel, so results agree bit for bit.
+constexpr int H2 = 8;                       // u^k halo of a blocked tile
+constexpr int W0 = TX + 2 * H2, R0 = TZ + 2 * H2;
+constexpr int W1 = TX + 8, R1 = TZ + 8;
+constexpr int NRING = R1 * W1 - TZ * TX;    // the 4-cell ring around the tile
+constexpr int RING_IT = (NRING + NTH - 1) / NTH;
+
+// Load the tile + 8 of a field into LDS with 16-byte loads (rows start
+// 32-byte aligned: x0 - 8 + OX is a multiple of 8), optionally multiplied
+// cell by cell by a second field.
+__device__ __forceinline__ void load_tile8(const Grid2 &g, const float *u, const float *mul, float *lds,
+                                           int x0, int z0)
+{
+    constexpr int Q = W0 / 4, N4 = R0 * Q;
+#pragma unroll
+    for (int it = 0; it < (N4 + NTH - 1) / NTH; ++it) {
+        const int q = threadIdx.x + it * NTH;
+        if (q < N4) {
+            const int r = q / Q, c = (q - r * Q) * 4;
+            const long long f = fidx(g, z0 - H2 + r, x0 - H2 + c);
+            float4 v = *reinterpret_cast<const float4 *>(u + f);
+            if (mul) {
+                const float4 m = *reinterpret_cast<const float4 *>(mul + f);
+                v.x = m.x * v.x; v.y = m.y * v.y; v.z = m.z * v.z; v.w = m.w * v.w;
+            }
+            float *d = lds + r * W0 + c;
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+    }
+}
+
+// Cell i of the ring (rows 0-3 and 36-39 of the tile + 4, then columns 0-3
+// and 68-71 of rows 4-35), as (row, column) of the tile + 4.
+__device__ __forceinline__ void ring_cell(int i, int &r, int &c)
+{
+    if (i < 8 * W1) {
+        const int rr = i / W1;
+        r = rr < 4 ? rr : rr + TZ;
+        c = i - rr * W1;
+    } else {
+        const int j = i - 8 * W1, cc = j & 7;
+        r = 4 + (j >> 3);
+        c = cc < 4 ? cc : cc + TX;
+    }
+}
+
+__global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
+{
+    __shared__ float s0[R0 * W0];   // u^k on the tile + 8
+    __shared__ float s1[R1 * W1];   // u^{k+1} on the tile + 4
+    const Grid2 &g = a.g;
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
+    const long long so = (long long)shot * g.plane;
+    const float *um = a.um + so;
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const long long src = a.src_f[shot];
+    const float sv0 = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
+    const float sv1 = a.src_scale * a.wav[(long long)shot * a.nt + a.k + 1];
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+
+    // own cells: column lx, rows ly*RPT .. +RPT-1; their chat and u^{k-1} first
+    float ch[RPT], pm[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const long long f = fidx(g, z0 + ly * RPT + j, x0 + lx);
+        ch[j] = chat[f];
+        pm[j] = um[f];
+    }
+    // ring cells of the tile + 4
+    float rch[RING_IT], rpm[RING_IT];
+    long long rf[RING_IT];
+#pragma unroll
+    for (int it = 0; it < RING_IT; ++it) {
+        const int i = threadIdx.x + it * NTH;
+        rf[it] = -1;
+        if (i < NRING) {
+            int r, c;
+            ring_cell(i, r, c);
+            rf[it] = fidx(g, z0 - 4 + r, x0 - 4 + c);
+            rch[it] = chat[rf[it]];
+            rpm[it] = um[rf[it]];
+        }
+    }
+    load_tile8(g, a.u0 + so, nullptr, s0, x0, z0);
+    __syncthreads();
+
+    // step k: u^{k+1} on the tile + 4 (own cells, then the ring)
+    float uk[RPT], u1[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        const long long f = fidx(g, z0 + r, x0 + lx);
+        const float *cc = s0 + (r + H2) * W0 + lx + H2;
+        const float wk = lap8(cc, W0);
+        uk[j] = cc[0];
+        float inc = fmaf(ch[j], wk, uk[j] - pm[j]);
+        if (f == src) inc += sv0;
+        u1[j] = uk[j] + inc;
+        s1[(r + 4) * W1 + lx + 4] = u1[j];
+        a.u1[so + f] = u1[j];
+        if (a.snap0) a.snap0[so + f] = wk;
+    }
+#pragma unroll
+    for (int it = 0; it < RING_IT; ++it) {
+        const int i = threadIdx.x + it * NTH;
+        if (i < NRING) {
+            int r, c;
+            ring_cell(i, r, c);
+            const float *cc = s0 + (r + 4) * W0 + c + 4;
+            const float wk = lap8(cc, W0);
+            const float u = cc[0];
+            float inc = fmaf(rch[it], wk, u - rpm[it]);
+            if (rf[it] == src) inc += sv0;
+            s1[r * W1 + c] = u + inc;
+        }
+    }
+    __syncthreads();
+
+    // step k+1 on the tile
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        const long long f = fidx(g, z0 + r, x0 + lx);
+        const float wk = lap8(s1 + (r + 4) * W1 + lx + 4, W1);
+        float inc = fmaf(ch[j], wk, u1[j] - uk[j]);
+        if (f == src) inc += sv1;
+        a.u2[so + f] = u1[j] + inc;
+        if (a.snap1) a.snap1[so + f] = wk;
+    }
+}
+
+// Adjoint steps k and k-1 on blocked tiles (no receivers within 4 cells):
+// s^{k+1} on the tile + 4 from chat s^{k+2} on the tile + 8, then s^k on
+// the tile; the gradient gets s^{k+1} w~^k, then s^k w~^{k-1}, as in two
+// single steps.
+__global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
+{
+    __shared__ float p0[R0 * W0];   // chat s^{k+2} on the tile + 8
+    __shared__ float p1[R1 * W1];   // chat s^{k+1} on the tile + 4
+    const Grid2 &g = a.g;
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
+    const long long so = (long long)shot * g.plane;
+    const float *s2 = a.s2 + so, *s3 = a.s3 + so;
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const long long src = a.src_f[shot];
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+
+    float ch[RPT], q2[RPT], q3[RPT], gr[RPT], w1[RPT], w0[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const long long f = fidx(g, z0 + ly * RPT + j, x0 + lx);
+        ch[j] = chat[f];
+        q2[j] = s2[f];
+        q3[j] = s3[f];
+        gr[j] = a.grad[so + f];
+        w1[j] = a.snap1[so + f];
+        w0[j] = a.snap0[so + f];
+    }
+    float rch[RING_IT], rq2[RING_IT], rq3[RING_IT];
+#pragma unroll
+    for (int it = 0; it < RING_IT; ++it) {
+        const int i = threadIdx.x + it * NTH;
+        if (i < NRING) {
+            int r, c;
+            ring_cell(i, r, c);
+            const long long f = fidx(g, z0 - 4 + r, x0 - 4 + c);
+            rch[it] = chat[f];
+            rq2[it] = s2[f];
+            rq3[it] = s3[f];
+        }
+    }
+    load_tile8(g, s2, chat, p0, x0, z0);
+    __syncthreads();
+
+    // step k: s^{k+1} on the tile + 4
+    float v1[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        const long long f = fidx(g, z0 + r, x0 + lx);
+        float v = lap8(p0 + (r + H2) * W0 + lx + H2, W0);
+        v += q2[j] + (q2[j] - q3[j]);
+        v1[j] = v;
+        p1[(r + 4) * W1 + lx + 4] = ch[j] * v;
+        a.o1[so + f] = v;
+        if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = v * a.src_scale;
+    }
+#pragma unroll
+    for (int it = 0; it < RING_IT; ++it) {
+        const int i = threadIdx.x + it * NTH;
+        if (i < NRING) {
+            int r, c;
+            ring_cell(i, r, c);
+            float v = lap8(p0 + (r + 4) * W0 + c + 4, W0);
+            v += rq2[it] + (rq2[it] - rq3[it]);
+            p1[r * W1 + c] = rch[it] * v;
+        }
+    }
+    __syncthreads();
+
+    // step k-1 on the tile
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        const long long f = fidx(g, z0 + r, x0 + lx);
+        float v = lap8(p1 + (r + 4) * W1 + lx + 4, W1);
+        v += v1[j] + (v1[j] - q2[j]);
+        a.o0[so + f] = v;
+        float t = fmaf(v1[j], w1[j], gr[j]);
+        a.grad[so + f] = fmaf(v, w0[j], t);
+        if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k - 1] = v * a.src_scale;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
+void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s)
+{
+    const int nb = a.ntl * a.nshots;
+    if (nb == 0) return;
+    ac2_fwd2_kernel<<<nb, NTH, 0, s>>>(a);
+}
+
+void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s)
+{
+    const int nb = a.ntl * a.nshots;
+    if (nb == 0) return;
+    ac2_adj2_kernel<<<nb, NTH, 0, s>>>(a);
+}
+
 static int layer_blocks(const Grid2 &g)
 {
     const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
@@ -383,7 +632,7 @@ void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s)
 
 void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s)
 {
-    const int nb = a.g.ntx * a.g.ntz * a.nshots;
+    const int nb = (a.tiles ? a.ntl : a.g.ntx * a.g.ntz) * a.nshots;
     if (nb == 0) return;
     const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
     if (snap) { if (rec) ac2_fwd_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
@@ -392,7 +641,7 @@ void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s)
 
 void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s)
 {
-    const int nb = a.g.ntx * a.g.ntz * a.nshots;
+    const int nb = (a.tiles ? a.ntl : a.g.ntx * a.g.ntz) * a.nshots;
     if (nb == 0) return;
     ac2_adj_kernel<<<nb, NTH, 0, s>>>(a);
 }

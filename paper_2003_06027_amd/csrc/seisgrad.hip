@@ -64,8 +64,10 @@ struct Layout {
     int n[3];          // padded extents x, y, z (y = 1 in 2-D)
     bool elastic;
     int nsnap, ngrad, nmod; // snapshot fields per step, gradient accumulators, model fields
+    int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
-        off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt, total;
+        off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt,
+        off_tiles, total;
 };
 
 int check_desc(const sg_desc *d)
@@ -123,6 +125,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
         L.plane = g.plane;
         L.ntiles = g.ntx * g.ntz;
         L.nf = 4;
+        L.nxs = 2;
         L.n[0] = g.NX; L.n[1] = 1; L.n[2] = g.NZ;
     } else {
         Grid3 &g = L.g3;
@@ -149,8 +152,8 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_chat = take(sizeof(float) * (size_t)L.nmod * d->nmodels * L.plane);   // model fields
     L.off_cpad = L.off_chat + sizeof(float) * (size_t)d->nmodels * L.plane;
     L.off_tab = take(sizeof(float) * 4 * (L.n[0] + L.n[1] + L.n[2] + 6 * TABPAD));
-    L.off_fwd = take(sizeof(float) * L.nf * L.field);
-    L.off_adj = take(sizeof(float) * L.nf * L.field);
+    L.off_fwd = take(sizeof(float) * (L.nf + L.nxs) * L.field);
+    L.off_adj = take(sizeof(float) * (L.nf + L.nxs) * L.field);
     L.off_ckpt = take(sizeof(float) * (size_t)L.nseg * L.nf * L.field);
     L.off_snap = take(sizeof(float) * (size_t)L.K * L.nsnap * L.field);
     L.off_grad = take(sizeof(float) * (size_t)L.ngrad * L.field);
@@ -163,6 +166,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_uoff = take(sizeof(int) * (size_t)max_shots * (max_rec + 1));
     L.off_uid = take(sizeof(int) * std::max<size_t>(1, (size_t)max_shots * max_rec));
     L.off_mt = take(sizeof(float) * 3 * max_shots);
+    L.off_tiles = take(sizeof(int) * 2 * std::max(1, L.ntiles));
     L.total = o;
     return L;
 }
@@ -177,6 +181,14 @@ struct sg_model {
     float *chat, *cpad;
     float *h[3], *p[3], *ih[3];   // damping tables per axis (x, y, z)
     float *fwd[EL_NS], *adj[EL_NS], *tmp[8];
+    // 2-D acoustic: u^t lives in slot u4[t % 4], the adjoint s^t in s4[t % 4]
+    float *u4[4], *s4[4];
+    // 2-D acoustic tiles advanced one step per launch ("near": the layer within
+    // reach, or receivers within 4 cells) and two steps per launch ("blocked")
+    int *tiles_near = nullptr, *tiles_blk = nullptr;
+    int n_near = 0, n_blk = 0;
+    std::vector<int> h_tiles;
+    int steps_per_launch = 2;
     float *model[8];              // elastic: lam, mu, muxz, bx, bz, vp, vs, rho (padded)
     float *ckpt, *snap, *grad, *acc;
     int *uoff, *uid;
@@ -351,6 +363,34 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
         }
         off[ntiles] = (int)(base + e);
     }
+    if (nd == 2) {
+        // blocked tiles: the tile and its BLK_HALO-cell halo are physical cells,
+        // and no receiver of any shot lies within 4 cells of the tile
+        const Grid2 &g = L.g2;
+        std::vector<char> rec_near(ntiles, 0);
+        for (int i = 0; i < ns; ++i)
+            for (int r = 0; r < nrec; ++r) {
+                const int32_t *e = sh->rec + ((size_t)i * nrec + r) * nd;
+                const int px = e[0] + P, pz = e[1] + P;
+                for (int tz = std::max(0, (pz - 4) / TZ - 1); tz <= std::min(g.ntz - 1, (pz + 4) / TZ); ++tz)
+                    for (int tx = std::max(0, (px - 4) / TX - 1); tx <= std::min(g.ntx - 1, (px + 4) / TX); ++tx)
+                        if (px >= tx * TX - 4 && px < tx * TX + TX + 4 && pz >= tz * TZ - 4 && pz < tz * TZ + TZ + 4)
+                            rec_near[tz * g.ntx + tx] = 1;
+            }
+        std::vector<int> near, blk;
+        for (int t = 0; t < ntiles; ++t) {
+            const int x0 = (t % g.ntx) * TX, z0 = (t / g.ntx) * TZ;
+            const bool inner = x0 - BLK_HALO >= P && x0 + TX + BLK_HALO <= P + g.nx &&
+                               z0 - BLK_HALO >= P && z0 + TZ + BLK_HALO <= P + g.nz;
+            (inner && !rec_near[t] ? blk : near).push_back(t);
+        }
+        m->n_near = (int)near.size();
+        m->n_blk = (int)blk.size();
+        m->h_tiles = near;
+        m->h_tiles.insert(m->h_tiles.end(), blk.begin(), blk.end());
+        HIPCHECK(hipMemcpyAsync(m->tiles_near, m->h_tiles.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, s));
+        m->tiles_blk = m->tiles_near + m->n_near;
+    }
     HIPCHECK(hipMemcpyAsync(m->src_f, m->h_src.data(), sizeof(long long) * ns, hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(m->rec_off, m->h_off.data(), sizeof(int) * m->h_off.size(), hipMemcpyHostToDevice, s));
     if (nd == 2 && !m->h_ent.empty())
@@ -501,7 +541,89 @@ void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwa
     launch_el2_adj3(a, s);
 }
 
-// One forward step: layer auxiliary fields from u^k, then the tile update.
+// 2-D acoustic: u^t is slot u4[t % 4] and s^t is slot s4[t % 4], so one
+// launch can write u^{k+1} and u^{k+2} while another still reads u^k and
+// u^{k-1} (the one- and two-step launches of a double step never touch a
+// slot another one reads).
+void ac2_phi(const sg_model *m, int ns, int k, hipStream_t s)
+{
+    Ac2PhiArgs p{};
+    p.g = m->L.g2;
+    p.u = m->u4[k & 3];
+    p.phx = m->fwd[2];
+    p.phz = m->fwd[3];
+    p.hx = m->h[0]; p.hz = m->h[2]; p.px = m->p[0]; p.pz = m->p[2]; p.ihx = m->ih[0]; p.ihz = m->ih[2];
+    launch_ac2_phi(p, ns, s);
+}
+
+// Pass B of forward step k on a tile list (null: every tile).
+void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, const int *tiles, int ntl, float *seis,
+               float *snap, hipStream_t s)
+{
+    Ac2FwdArgs a{};
+    a.g = m->L.g2;
+    a.nshots = ns;
+    a.tiles = tiles;
+    a.ntl = ntl;
+    a.u = m->u4[k & 3];
+    a.um = m->u4[(k + 3) & 3];
+    a.un = m->u4[(k + 1) & 3];
+    a.chat = m->chat;
+    a.shots_per_model = ns / m->d.nmodels;
+    a.phx = m->fwd[2];
+    a.phz = m->fwd[3];
+    a.hx = m->h[0];
+    a.hz = m->h[2];
+    a.src_f = m->src_f;
+    a.wav = wav;
+    a.nt = m->d.nt;
+    a.k = k;
+    a.src_scale = src_scale(m);
+    a.rec_off = m->rec_off;
+    a.rec_ent = static_cast<const int *>(m->rec_ent);
+    a.nrec = m->geom_nrec;
+    a.seis = seis;
+    a.snap = snap;
+    launch_ac2_fwd(a, s);
+}
+
+// Forward step k, or steps k and k+1 when `two`: near tiles step by step,
+// blocked tiles both steps in one launch (between the two near launches,
+// whose second step reads the blocked tiles' u^{k+1} in its halo).
+void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, float *seis, float *snap0,
+                 float *snap1, hipStream_t s)
+{
+    if (!two) {
+        ac2_phi(m, ns, k, s);
+        ac2_tiles(m, ns, wav, k, nullptr, 0, seis, snap0, s);
+        return;
+    }
+    ac2_phi(m, ns, k, s);
+    ac2_tiles(m, ns, wav, k, m->tiles_near, m->n_near, seis, snap0, s);
+    Ac2Fwd2Args b{};
+    b.g = m->L.g2;
+    b.nshots = ns;
+    b.tiles = m->tiles_blk;
+    b.ntl = m->n_blk;
+    b.u0 = m->u4[k & 3];
+    b.um = m->u4[(k + 3) & 3];
+    b.u1 = m->u4[(k + 1) & 3];
+    b.u2 = m->u4[(k + 2) & 3];
+    b.chat = m->chat;
+    b.shots_per_model = ns / m->d.nmodels;
+    b.src_f = m->src_f;
+    b.wav = wav;
+    b.nt = m->d.nt;
+    b.k = k;
+    b.src_scale = src_scale(m);
+    b.snap0 = snap0;
+    b.snap1 = snap1;
+    launch_ac2_fwd2(b, s);
+    ac2_phi(m, ns, k + 1, s);
+    ac2_tiles(m, ns, wav, k + 1, m->tiles_near, m->n_near, seis, snap1, s);
+}
+
+// One forward step of the 3-D acoustic or 2-D elastic recursion.
 // cu selects u^k = fwd[cu], u^{k-1} = fwd[1-cu].
 void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float *seis, float *snap,
               hipStream_t s)
@@ -509,35 +631,7 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
     if (m->L.elastic) {
         el_fwd_step(m, ns, wav, k, seis, snap, s);
     } else if (m->d.ndim == 2) {
-        Ac2PhiArgs p{};
-        p.g = m->L.g2;
-        p.u = m->fwd[cu];
-        p.phx = m->fwd[2];
-        p.phz = m->fwd[3];
-        p.hx = m->h[0]; p.hz = m->h[2]; p.px = m->p[0]; p.pz = m->p[2]; p.ihx = m->ih[0]; p.ihz = m->ih[2];
-        launch_ac2_phi(p, ns, s);
-        Ac2FwdArgs a{};
-        a.g = m->L.g2;
-        a.nshots = ns;
-        a.u = m->fwd[cu];
-        a.um = m->fwd[1 - cu];
-        a.chat = m->chat;
-        a.shots_per_model = ns / m->d.nmodels;
-        a.phx = m->fwd[2];
-        a.phz = m->fwd[3];
-        a.hx = m->h[0];
-        a.hz = m->h[2];
-        a.src_f = m->src_f;
-        a.wav = wav;
-        a.nt = m->d.nt;
-        a.k = k;
-        a.src_scale = src_scale(m);
-        a.rec_off = m->rec_off;
-        a.rec_ent = static_cast<const int *>(m->rec_ent);
-        a.nrec = m->geom_nrec;
-        a.seis = seis;
-        a.snap = snap;
-        launch_ac2_fwd(a, s);
+        ac2_forward(m, ns, wav, k, false, seis, snap, nullptr, s);
     } else {
         Ac3PhiArgs p{};
         p.g = m->L.g3;
@@ -573,7 +667,88 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
     }
 }
 
-// One adjoint step k: s^{k+2} = adj[ca], s^{k+3} = adj[1-ca] (in) / s^{k+1} (out).
+void ac2_phi_adj(const sg_model *m, int ns, int k, hipStream_t s)
+{
+    Ac2PhiAdjArgs pa{};
+    pa.g = m->L.g2;
+    pa.s2 = m->s4[(k + 2) & 3];
+    pa.chat = m->chat;
+    pa.shots_per_model = ns / m->d.nmodels;
+    pa.cx = m->adj[2];
+    pa.cz = m->adj[3];
+    pa.hx = m->h[0]; pa.hz = m->h[2]; pa.px = m->p[0]; pa.pz = m->p[2]; pa.ihx = m->ih[0]; pa.ihz = m->ih[2];
+    launch_ac2_phi_adj(pa, ns, s);
+}
+
+// Pass B of adjoint step k (s^{k+1} from s^{k+2}, s^{k+3}) on a tile list.
+void ac2_adj_tiles(const sg_model *m, int ns, int k, const int *tiles, int ntl, const float *dJdd, float *gwav,
+                   const float *snap, hipStream_t s)
+{
+    Ac2AdjArgs b{};
+    b.g = m->L.g2;
+    b.nshots = ns;
+    b.tiles = tiles;
+    b.ntl = ntl;
+    b.s2 = m->s4[(k + 2) & 3];
+    b.s3 = m->s4[(k + 3) & 3];
+    b.s1 = m->s4[(k + 1) & 3];
+    b.chat = m->chat;
+    b.shots_per_model = ns / m->d.nmodels;
+    b.cx = m->adj[2];
+    b.cz = m->adj[3];
+    b.hx = m->h[0];
+    b.hz = m->h[2];
+    b.src_f = m->src_f;
+    b.gwav = gwav;
+    b.nt = m->d.nt;
+    b.k = k;
+    b.src_scale = src_scale(m);
+    b.rec_off = m->rec_off;
+    b.rec_ent = static_cast<const int *>(m->rec_ent);
+    b.dJdd = dJdd;
+    b.nrec = m->geom_nrec;
+    b.snap = snap;
+    b.grad = m->grad;
+    launch_ac2_adj(b, s);
+}
+
+// Adjoint step k, or steps k and k-1 when `two` (snap1 = w~^k, snap0 = w~^{k-1}).
+void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, float *gwav, const float *snap1,
+                 const float *snap0, hipStream_t s)
+{
+    if (!two) {
+        ac2_phi_adj(m, ns, k, s);
+        ac2_adj_tiles(m, ns, k, nullptr, 0, dJdd, gwav, snap1, s);
+        return;
+    }
+    ac2_phi_adj(m, ns, k, s);
+    ac2_adj_tiles(m, ns, k, m->tiles_near, m->n_near, dJdd, gwav, snap1, s);
+    Ac2Adj2Args b{};
+    b.g = m->L.g2;
+    b.nshots = ns;
+    b.tiles = m->tiles_blk;
+    b.ntl = m->n_blk;
+    b.s2 = m->s4[(k + 2) & 3];
+    b.s3 = m->s4[(k + 3) & 3];
+    b.o1 = m->s4[(k + 1) & 3];
+    b.o0 = m->s4[k & 3];
+    b.chat = m->chat;
+    b.shots_per_model = ns / m->d.nmodels;
+    b.src_f = m->src_f;
+    b.gwav = gwav;
+    b.nt = m->d.nt;
+    b.k = k;
+    b.src_scale = src_scale(m);
+    b.snap1 = snap1;
+    b.snap0 = snap0;
+    b.grad = m->grad;
+    launch_ac2_adj2(b, s);
+    ac2_phi_adj(m, ns, k - 1, s);
+    ac2_adj_tiles(m, ns, k - 1, m->tiles_near, m->n_near, dJdd, gwav, snap0, s);
+}
+
+// One adjoint step k of the 3-D acoustic or 2-D elastic recursion:
+// s^{k+2} = adj[ca], s^{k+3} = adj[1-ca] (in) / s^{k+1} (out).
 void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float *gwav,
               const float *snap, hipStream_t s)
 {
@@ -581,38 +756,7 @@ void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float
     if (m->L.elastic) {
         el_adj_step(m, ns, k, dJdd, gwav, snap, s);
     } else if (m->d.ndim == 2) {
-        Ac2PhiAdjArgs pa{};
-        pa.g = m->L.g2;
-        pa.s2 = m->adj[ca];
-        pa.chat = m->chat;
-        pa.shots_per_model = spm;
-        pa.cx = m->adj[2];
-        pa.cz = m->adj[3];
-        pa.hx = m->h[0]; pa.hz = m->h[2]; pa.px = m->p[0]; pa.pz = m->p[2]; pa.ihx = m->ih[0]; pa.ihz = m->ih[2];
-        launch_ac2_phi_adj(pa, ns, s);
-        Ac2AdjArgs b{};
-        b.g = m->L.g2;
-        b.nshots = ns;
-        b.s2 = m->adj[ca];
-        b.s3 = m->adj[1 - ca];
-        b.chat = m->chat;
-        b.shots_per_model = spm;
-        b.cx = m->adj[2];
-        b.cz = m->adj[3];
-        b.hx = m->h[0];
-        b.hz = m->h[2];
-        b.src_f = m->src_f;
-        b.gwav = gwav;
-        b.nt = m->d.nt;
-        b.k = k;
-        b.src_scale = src_scale(m);
-        b.rec_off = m->rec_off;
-        b.rec_ent = static_cast<const int *>(m->rec_ent);
-        b.dJdd = dJdd;
-        b.nrec = m->geom_nrec;
-        b.snap = snap;
-        b.grad = m->grad;
-        launch_ac2_adj(b, s);
+        ac2_adjoint(m, ns, k, false, dJdd, gwav, snap, nullptr, s);
     } else {
         Ac3PhiAdjArgs pa{};
         pa.g = m->L.g3;
@@ -731,6 +875,16 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         m->fwd[i] = reinterpret_cast<float *>(m->ws + L.off_fwd) + i * L.field;
         m->adj[i] = reinterpret_cast<float *>(m->ws + L.off_adj) + i * L.field;
     }
+    if (!L.elastic && d->ndim == 2) {
+        float *fb = reinterpret_cast<float *>(m->ws + L.off_fwd), *ab = reinterpret_cast<float *>(m->ws + L.off_adj);
+        const int slot[4] = {0, 1, 4, 5};   // fields 2, 3 hold the layer auxiliaries
+        for (int i = 0; i < 4; ++i) {
+            m->u4[i] = fb + slot[i] * L.field;
+            m->s4[i] = ab + slot[i] * L.field;
+        }
+        m->tiles_near = reinterpret_cast<int *>(m->ws + L.off_tiles);
+        m->tiles_blk = m->tiles_near + L.ntiles;
+    }
     m->ckpt = reinterpret_cast<float *>(m->ws + L.off_ckpt);
     m->snap = reinterpret_cast<float *>(m->ws + L.off_snap);
     m->grad = reinterpret_cast<float *>(m->ws + L.off_grad);
@@ -839,10 +993,13 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     const Layout &L = m->L;
     const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
     const long long fs = (long long)ns * L.plane;  // floats of one field over the batch
+    const bool ac2 = !L.elastic && m->d.ndim == 2;
     for (int i = 0; i < nf; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
+    if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->u4[i], fs, 0.f, s);
+    float *sp = sh->nrec > 0 ? seis : nullptr;
     int cu = 0;
     int span = -1;
-    for (int k = 0; k < nt; ++k) {
+    for (int k = 0; k < nt;) {
         if (k % K == 0) {
             span_end(m, span, s);
             if (save_ckpt) {
@@ -850,14 +1007,24 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
                 // (acoustic: u^k, u^{k-1} first; elastic: the fields in order)
                 float *ck = m->ckpt + (size_t)(k / K) * nf * L.field;
                 for (int i = 0; i < nf; ++i) {
-                    const float *src = L.elastic || i >= 2 ? m->fwd[i] : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
+                    const float *src = L.elastic || i >= 2 ? m->fwd[i]
+                                     : ac2 ? m->u4[(k + 4 - i) & 3]
+                                           : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
                     HIPCHECK(hipMemcpyAsync(ck + i * L.field, src, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
                 }
             }
             span = span_begin(m, 0, std::min(K, nt - k), s);
         }
-        fwd_step(m, ns, sh->wavelet, cu, k, sh->nrec > 0 ? seis : nullptr, nullptr, s);
-        cu = 1 - cu;
+        if (ac2) {
+            // two steps per launch on the blocked tiles, within one checkpoint segment
+            const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < std::min((k / K + 1) * K, nt);
+            ac2_forward(m, ns, sh->wavelet, k, two, sp, nullptr, nullptr, s);
+            k += two ? 2 : 1;
+        } else {
+            fwd_step(m, ns, sh->wavelet, cu, k, sp, nullptr, s);
+            cu = 1 - cu;
+            ++k;
+        }
     }
     span_end(m, span, s);
     HIPCHECK(hipGetLastError());
@@ -893,7 +1060,9 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     const Layout &L = m->L;
     const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
     const long long fs = (long long)ns * L.plane;
+    const bool ac2 = !L.elastic && m->d.ndim == 2;
     for (int i = 0; i < nf; ++i) launch_fill(m->adj[i], fs, 0.f, s);
+    if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->s4[i], fs, 0.f, s);
     for (int q = 0; q < L.ngrad; ++q) launch_fill(m->grad + q * L.field, fs, 0.f, s);
     if (L.elastic)
         for (int i = 0; i < 8; ++i) launch_fill(m->tmp[i], fs, 0.f, s);
@@ -901,19 +1070,37 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     for (int seg = L.nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * K, k1 = std::min(k0 + K, nt);
         const float *ck = m->ckpt + (size_t)seg * nf * L.field;
-        for (int i = 0; i < nf; ++i)
-            HIPCHECK(hipMemcpyAsync(m->fwd[i], ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i < nf; ++i) {
+            float *dst = ac2 && i < 2 ? m->u4[(k0 + 4 - i) & 3] : m->fwd[i];
+            HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+        }
+        auto snap = [&](int k) { return m->snap + (size_t)(k - k0) * L.nsnap * L.field; };
+        const bool blk = ac2 && m->steps_per_launch == 2 && m->n_blk > 0;
         int cu = 0;
         int span = span_begin(m, 1, k1 - k0, s);
-        for (int k = k0; k < k1; ++k) {
-            fwd_step(m, ns, sh->wavelet, cu, k, nullptr, m->snap + (size_t)(k - k0) * L.nsnap * L.field, s);
-            cu = 1 - cu;
+        for (int k = k0; k < k1;) {
+            if (ac2) {
+                const bool two = blk && k + 1 < k1;
+                ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
+                k += two ? 2 : 1;
+            } else {
+                fwd_step(m, ns, sh->wavelet, cu, k, nullptr, snap(k), s);
+                cu = 1 - cu;
+                ++k;
+            }
         }
         span_end(m, span, s);
         span = span_begin(m, 2, k1 - k0, s);
-        for (int k = k1 - 1; k >= k0; --k) {
-            adj_step(m, ns, ca, k, dJ_dd, g_wavelet, m->snap + (size_t)(k - k0) * L.nsnap * L.field, s);
-            ca = 1 - ca;
+        for (int k = k1 - 1; k >= k0;) {
+            if (ac2) {
+                const bool two = blk && k - 1 >= k0;
+                ac2_adjoint(m, ns, k, two, dJ_dd, g_wavelet, snap(k), two ? snap(k - 1) : nullptr, s);
+                k -= two ? 2 : 1;
+            } else {
+                adj_step(m, ns, ca, k, dJ_dd, g_wavelet, snap(k), s);
+                ca = 1 - ca;
+                --k;
+            }
         }
         span_end(m, span, s);
     }
@@ -925,6 +1112,15 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     else
         launch_ac3_finalize(L.g3, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int set_time_blocking(sg_model *m, int32_t steps)
+{
+    g_err.clear();
+    if (!m) return fail(SG_EINVAL, "model is NULL");
+    if (steps != 1 && steps != 2) return fail(SG_EINVAL, "steps per launch must be 1 or 2, got %d", steps);
+    m->steps_per_launch = steps;
     return SG_OK;
 }
 

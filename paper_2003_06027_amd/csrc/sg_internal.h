@@ -43,8 +43,11 @@ struct Ac2PhiArgs {
 struct Ac2FwdArgs {
     Grid2 g;
     int nshots;
+    const int *tiles;       // tile indices to update, or null for all tiles
+    int ntl;                // number of entries in tiles
     const float *u;         // u^k       [shot][plane]
-    float *um;              // u^{k-1} in, u^{k+1} out (same cells)
+    const float *um;        // u^{k-1}
+    float *un;              // u^{k+1} out (may alias um: each cell reads um before writing)
     const float *chat;      // dt^2 c^2 / dx^2  [model][plane]
     int shots_per_model;
     const float *phx, *phz; // phi~^k
@@ -73,8 +76,11 @@ struct Ac2PhiAdjArgs {
 struct Ac2AdjArgs {
     Grid2 g;
     int nshots;
+    const int *tiles;       // tile indices to update, or null for all tiles
+    int ntl;
     const float *s2;        // s^{k+2}  (alpha-scaled adjoint), read with halo
-    float *s3;              // s^{k+3} in, s^{k+1} out
+    const float *s3;        // s^{k+3}
+    float *s1;              // s^{k+1} out (may alias s3)
     const float *chat;
     int shots_per_model;
     const float *cx, *cz;   // c^{k+1}
@@ -91,7 +97,52 @@ struct Ac2AdjArgs {
     float *grad;            // dJ/dchat per shot [shot][plane], accumulated
 };
 
+// Two steps k, k+1 in one launch on "blocked" tiles: tiles whose cells and
+// 8-cell halo are all physical (no layer terms) and which hold no receiver
+// within 4 cells.  u^{k+1} is recomputed on the 4-cell halo in LDS; every
+// cell gets exactly the arithmetic of two single steps.
+struct Ac2Fwd2Args {
+    Grid2 g;
+    int nshots;
+    const int *tiles;
+    int ntl;
+    const float *u0;        // u^k, read on the tile + 8
+    const float *um;        // u^{k-1}, read on the tile + 4
+    float *u1, *u2;         // u^{k+1}, u^{k+2} out (slots distinct from u0, um)
+    const float *chat;
+    int shots_per_model;
+    const long long *src_f;
+    const float *wav;
+    int nt, k;
+    float src_scale;
+    float *snap0, *snap1;   // w~^k, w~^{k+1} [shot][plane], or null
+};
+
+// Two adjoint steps k, k-1 in one launch on blocked tiles.
+struct Ac2Adj2Args {
+    Grid2 g;
+    int nshots;
+    const int *tiles;
+    int ntl;
+    const float *s2;        // s^{k+2}, read on the tile + 8
+    const float *s3;        // s^{k+3}, read on the tile + 4
+    float *o1, *o0;         // s^{k+1}, s^k out (slots distinct from s2, s3)
+    const float *chat;
+    int shots_per_model;
+    const long long *src_f;
+    float *gwav;
+    int nt, k;
+    float src_scale;
+    const float *snap1, *snap0;  // w~^k, w~^{k-1}
+    float *grad;
+};
+
+// Halo of a blocked tile: its cells within BLK_HALO of the tile must be physical.
+constexpr int BLK_HALO = 8;
+
 void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s);
+void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s);
+void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s);
 void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s);
 void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s);
 void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s);

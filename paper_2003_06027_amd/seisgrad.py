@@ -22,7 +22,8 @@ _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_E
           SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED"}
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
-           "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times")
+           "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
+           "set_time_blocking")
 
 
 class SeisError(RuntimeError):
@@ -67,6 +68,7 @@ def lib():
         L.ricker.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
         L.dot_f64.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.set_profiling.argtypes = [C.c_void_p, C.c_int32]
+        L.set_time_blocking.argtypes = [C.c_void_p, C.c_int32]
         L.phase_times.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -179,6 +181,10 @@ class Model:
         _check(lib().adjoint_gradient(self.handle, C.byref(st), _ptr(dJdd.contiguous()), _ptr(g_vp), _ptr(g_vs),
                                       _ptr(g_rho), _ptr(g_wavelet), _stream(stream)))
         return (g_vp, g_vs, g_rho) if self.elastic else g_vp
+
+    def set_time_blocking(self, steps):
+        """Steps per launch of the 2-D acoustic blocked tiles (1 or 2)."""
+        _check(lib().set_time_blocking(self.handle, int(steps)))
 
     def set_profiling(self, on=True):
         _check(lib().set_profiling(self.handle, int(on)))
