@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--no-ttm", action="store_true", help="skip the learned-preconditioner time-to-misfit leg")
+    ap.add_argument("--store-segments", type=int, default=None,
+                    help="checkpoint segments whose adjoint snapshots the forward keeps "
+                         "(default: as many as fit in free HBM)")
     ap.add_argument("--time-blocking", type=int, default=2, choices=(1, 2),
                     help="time steps per launch on the blocked tiles (results are identical)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -129,7 +132,18 @@ def main():
     torch.cuda.synchronize()
     mt.close()
     del mt
-    m = S.Model(d, dev(c0), ns, nrec, ckpt)
+    # workspace beyond the minimum keeps the adjoint snapshots of the last
+    # checkpoint segments (their recomputation is skipped); leave a margin
+    # for the seismogram and residual buffers
+    nseg = -(-nt // ckpt)
+    if args.store_segments is None:
+        free = torch.cuda.mem_get_info()[0]
+        spare = free - S.workspace_bytes(d, ns, nrec, ckpt) - 16 * (1 << 30)
+        nstore = int(max(0, min(nseg, spare // S.snapshot_segment_bytes(d, ns, ckpt))))
+    else:
+        nstore = min(args.store_segments, nseg)
+    m = S.Model(d, dev(c0), ns, nrec, ckpt, store_segments=nstore)
+    log(f"workspace {m.ws.numel() / 1e9:.1f} GB: {nstore} of {nseg} segments keep their snapshots")
     m.set_time_blocking(args.time_blocking)
     seis = torch.empty_like(obs)
     resid = torch.empty_like(obs)
@@ -188,7 +202,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}", "grid_padded": list(cfg.padded),
-                   "shots": ns, "nt": nt, "ckpt_every": ckpt, "receivers": nrec,
+                   "shots": ns, "nt": nt, "ckpt_every": ckpt, "stored_segments": nstore, "segments": nseg,
+                   "time_blocking": args.time_blocking, "receivers": nrec,
                    "cell_updates_per_step": updates},
         "roofline": {"bound": "hbm", "kernel": f"ac2 {dom} step (PML + interior launches)",
                      "achieved": ph[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

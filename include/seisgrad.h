@@ -117,15 +117,27 @@ typedef struct sg_model sg_model;
  * last_error()). */
 SG_API size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int32_t ckpt_every);
 
+/* Bytes that one stored checkpoint segment of adjoint snapshots takes in the
+ * workspace beyond workspace_bytes() (see init_model's ws).  0 on an invalid
+ * descriptor. */
+SG_API size_t snapshot_segment_bytes(const sg_desc *d, int32_t max_shots, int32_t ckpt_every);
+
 /* Prepare a model (paper: the parameter theta of A(theta), Eq. (1); here the
  * velocity c of Eq. (11)): validate the descriptor, check stability
  * (8th-order leapfrog limit c dt/dx <= 2/sqrt(6.5016 ndim), rejected above
  * 0.95 of it), pad the velocity by edge replication, form C = dt^2 c^2 on the
  * padded grid and the damping tables.
  *   vp:  DEVICE FP32 [nmodels][nz]([ny])[nx] velocity (m/s), > 0;
- *   vs, rho: reserved for elastic, must be NULL;
+ *   vs, rho: elastic only, DEVICE FP32 like vp (0 < vs < vp, rho > 0);
+ *        NULL for acoustic models;
  *   ws:  DEVICE workspace, 256-byte aligned, of
- *        ws_bytes >= workspace_bytes(d, max_shots, max_rec, ckpt_every);
+ *        ws_bytes >= workspace_bytes(d, max_shots, max_rec, ckpt_every).
+ *        Bytes beyond that minimum hold the adjoint's snapshots of as many
+ *        of the LAST checkpoint segments as fit: a checkpointed forward
+ *        writes them directly, and adjoint_gradient then skips the restore
+ *        and recomputation of those segments (same results, bit for bit;
+ *        fewer recomputed steps).  Each stored segment takes
+ *        ckpt_every x (snapshot fields) x max_shots planes of FP32;
  *   out: receives the model handle.
  * The call synchronises `stream` once (it reads the velocity range back for
  * the stability check).  The velocity is copied into the workspace; vp may be

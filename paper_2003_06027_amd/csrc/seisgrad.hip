@@ -189,6 +189,11 @@ struct sg_model {
     int n_near = 0, n_blk = 0;
     std::vector<int> h_tiles;
     int steps_per_launch = 2;
+    // snapshots of the last n_store checkpoint segments, written by a
+    // checkpointed forward into the workspace beyond its minimum size
+    float *store = nullptr;
+    int n_store = 0;
+    bool have_store = false;
     float *model[8];              // elastic: lam, mu, muxz, bx, bz, vp, vs, rho (padded)
     float *ckpt, *snap, *grad, *acc;
     int *uoff, *uid;
@@ -809,6 +814,18 @@ size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int
     return make_layout(d, max_shots, max_rec, ckpt_every).total;
 }
 
+size_t snapshot_segment_bytes(const sg_desc *d, int32_t max_shots, int32_t ckpt_every)
+{
+    g_err.clear();
+    if (check_desc(d) != SG_OK) return 0;
+    if (max_shots < 1 || ckpt_every < 0) {
+        fail(SG_EINVAL, "max_shots >= 1 and ckpt_every >= 0 required");
+        return 0;
+    }
+    const Layout L = make_layout(d, max_shots, 0, ckpt_every);
+    return sizeof(float) * (size_t)L.K * L.nsnap * L.field;
+}
+
 int init_model(const sg_desc *d, const float *vp, const float *vs, const float *rho,
                int32_t max_shots, int32_t max_rec, int32_t ckpt_every, void *ws, size_t ws_bytes,
                sg_stream_t stream, sg_model **out)
@@ -884,6 +901,12 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         }
         m->tiles_near = reinterpret_cast<int *>(m->ws + L.off_tiles);
         m->tiles_blk = m->tiles_near + L.ntiles;
+    }
+    {
+        const size_t per = sizeof(float) * (size_t)L.K * L.nsnap * L.field;
+        const size_t extra = ws_bytes - L.total;
+        m->n_store = (int)std::min<size_t>(extra / per, (size_t)L.nseg);
+        m->store = m->n_store > 0 ? reinterpret_cast<float *>(m->ws + L.total) : nullptr;
     }
     m->ckpt = reinterpret_cast<float *>(m->ws + L.off_ckpt);
     m->snap = reinterpret_cast<float *>(m->ws + L.off_snap);
@@ -997,6 +1020,13 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     for (int i = 0; i < nf; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
     if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->u4[i], fs, 0.f, s);
     float *sp = sh->nrec > 0 ? seis : nullptr;
+    // segments >= seg0 keep their adjoint snapshots (checkpointed forwards only)
+    const int seg0 = save_ckpt ? L.nseg - m->n_store : L.nseg;
+    auto stored = [&](int k) -> float * {
+        const int seg = k / K;
+        if (seg < seg0) return nullptr;
+        return m->store + ((size_t)(seg - seg0) * K + (k - seg * K)) * L.nsnap * L.field;
+    };
     int cu = 0;
     int span = -1;
     for (int k = 0; k < nt;) {
@@ -1018,10 +1048,10 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
         if (ac2) {
             // two steps per launch on the blocked tiles, within one checkpoint segment
             const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < std::min((k / K + 1) * K, nt);
-            ac2_forward(m, ns, sh->wavelet, k, two, sp, nullptr, nullptr, s);
+            ac2_forward(m, ns, sh->wavelet, k, two, sp, stored(k), two ? stored(k + 1) : nullptr, s);
             k += two ? 2 : 1;
         } else {
-            fwd_step(m, ns, sh->wavelet, cu, k, sp, nullptr, s);
+            fwd_step(m, ns, sh->wavelet, cu, k, sp, stored(k), s);
             cu = 1 - cu;
             ++k;
         }
@@ -1029,6 +1059,7 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     span_end(m, span, s);
     HIPCHECK(hipGetLastError());
     m->have_ckpt = save_ckpt != 0;
+    m->have_store = save_ckpt != 0 && m->n_store > 0;
     return SG_OK;
 }
 
@@ -1067,29 +1098,35 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     if (L.elastic)
         for (int i = 0; i < 8; ++i) launch_fill(m->tmp[i], fs, 0.f, s);
     int ca = 0;
+    const int seg0 = m->have_store ? L.nseg - m->n_store : L.nseg;
     for (int seg = L.nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * K, k1 = std::min(k0 + K, nt);
-        const float *ck = m->ckpt + (size_t)seg * nf * L.field;
-        for (int i = 0; i < nf; ++i) {
-            float *dst = ac2 && i < 2 ? m->u4[(k0 + 4 - i) & 3] : m->fwd[i];
-            HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-        }
-        auto snap = [&](int k) { return m->snap + (size_t)(k - k0) * L.nsnap * L.field; };
+        const bool kept = seg >= seg0;   // snapshots written by the forward
+        float *sbase = kept ? m->store + (size_t)(seg - seg0) * K * L.nsnap * L.field : m->snap;
+        auto snap = [&](int k) { return sbase + (size_t)(k - k0) * L.nsnap * L.field; };
         const bool blk = ac2 && m->steps_per_launch == 2 && m->n_blk > 0;
-        int cu = 0;
-        int span = span_begin(m, 1, k1 - k0, s);
-        for (int k = k0; k < k1;) {
-            if (ac2) {
-                const bool two = blk && k + 1 < k1;
-                ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
-                k += two ? 2 : 1;
-            } else {
-                fwd_step(m, ns, sh->wavelet, cu, k, nullptr, snap(k), s);
-                cu = 1 - cu;
-                ++k;
+        int span = -1;
+        if (!kept) {
+            const float *ck = m->ckpt + (size_t)seg * nf * L.field;
+            for (int i = 0; i < nf; ++i) {
+                float *dst = ac2 && i < 2 ? m->u4[(k0 + 4 - i) & 3] : m->fwd[i];
+                HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
             }
+            int cu = 0;
+            span = span_begin(m, 1, k1 - k0, s);
+            for (int k = k0; k < k1;) {
+                if (ac2) {
+                    const bool two = blk && k + 1 < k1;
+                    ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
+                    k += two ? 2 : 1;
+                } else {
+                    fwd_step(m, ns, sh->wavelet, cu, k, nullptr, snap(k), s);
+                    cu = 1 - cu;
+                    ++k;
+                }
+            }
+            span_end(m, span, s);
         }
-        span_end(m, span, s);
         span = span_begin(m, 2, k1 - k0, s);
         for (int k = k1 - 1; k >= k0;) {
             if (ac2) {

@@ -32,12 +32,20 @@ from . import seisgrad as S
 class Propagator:
     """Workspace + model for a fixed grid, shot batch and checkpoint interval."""
 
-    def __init__(self, desc, shots: "S.Shots", ckpt_every: int = 0, device="cuda"):
+    def __init__(self, desc, shots: "S.Shots", ckpt_every: int = 0, device="cuda", store_segments: int = 0):
+        """store_segments: checkpoint segments whose adjoint snapshots the
+        checkpointed forward keeps in the workspace (-1: all of them), so the
+        adjoint does not recompute them."""
         self.d = desc
         self.shots = shots
         self.ckpt = ckpt_every
         self.elastic = desc.physics == S.SG_ELASTIC
         self.nbytes = S.workspace_bytes(desc, shots.nshots, shots.nrec, ckpt_every)
+        if store_segments:
+            K = ckpt_every if ckpt_every > 0 else int(np.ceil(np.sqrt(desc.nt)))
+            nseg = -(-desc.nt // min(K, desc.nt))
+            n = nseg if store_segments < 0 else min(store_segments, nseg)
+            self.nbytes += n * S.snapshot_segment_bytes(desc, shots.nshots, ckpt_every)
         self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         self.model = None
         self.generation = 0

@@ -23,7 +23,7 @@ _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_E
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
-           "set_time_blocking")
+           "set_time_blocking", "snapshot_segment_bytes")
 
 
 class SeisError(RuntimeError):
@@ -56,6 +56,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.workspace_bytes.restype = C.c_size_t
         L.workspace_bytes.argtypes = [C.POINTER(SgDesc), C.c_int32, C.c_int32, C.c_int32]
+        L.snapshot_segment_bytes.restype = C.c_size_t
+        L.snapshot_segment_bytes.argtypes = [C.POINTER(SgDesc), C.c_int32, C.c_int32]
         L.init_model.argtypes = [C.POINTER(SgDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                  C.POINTER(C.c_void_p)]
@@ -103,6 +105,15 @@ def workspace_bytes(d, max_shots, max_rec, ckpt_every=0):
     return n
 
 
+def snapshot_segment_bytes(d, max_shots, ckpt_every=0):
+    """Workspace bytes per checkpoint segment whose adjoint snapshots the
+    forward keeps (extra workspace beyond workspace_bytes)."""
+    n = lib().snapshot_segment_bytes(C.byref(d), max_shots, ckpt_every)
+    if n == 0:
+        raise SeisError(SG_EINVAL, lib().last_error().decode())
+    return n
+
+
 def ricker(f0, t0, dt, nt, out=None, stream=None):
     out = out if out is not None else torch.empty(nt, dtype=torch.float32, device="cuda")
     _check(lib().ricker(f0, t0, dt, nt, _ptr(out), _stream(stream)))
@@ -135,12 +146,18 @@ class Shots:
 class Model:
     """A model handle plus its workspace (a torch uint8 device tensor)."""
 
-    def __init__(self, d, vp, max_shots, max_rec, ckpt_every=0, stream=None, vs=None, rho=None, ws=None):
-        """ws: an existing workspace (uint8 device tensor) to reuse."""
+    def __init__(self, d, vp, max_shots, max_rec, ckpt_every=0, stream=None, vs=None, rho=None, ws=None,
+                 store_segments=0):
+        """ws: an existing workspace (uint8 device tensor) to reuse; all of it
+        is handed to the library.  store_segments: when ws is None, allocate
+        room for the adjoint snapshots of that many checkpoint segments, which
+        a checkpointed forward then keeps (no recomputation of them)."""
         self.d = d
         self.max_shots, self.max_rec = max_shots, max_rec
         self.elastic = d.physics == SG_ELASTIC
         nbytes = workspace_bytes(d, max_shots, max_rec, ckpt_every)
+        if ws is None and store_segments > 0:
+            nbytes += store_segments * snapshot_segment_bytes(d, max_shots, ckpt_every)
         if ws is not None and ws.numel() < nbytes:
             raise SeisError(SG_ENOMEM, f"workspace of {ws.numel()} bytes, {nbytes} needed")
         self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device=vp.device)
@@ -149,7 +166,7 @@ class Model:
         self.vs = None if vs is None else vs.contiguous()
         self.rho = None if rho is None else rho.contiguous()
         _check(lib().init_model(C.byref(d), _ptr(self.vp), _ptr(self.vs), _ptr(self.rho), max_shots, max_rec,
-                                ckpt_every, _ptr(self.ws), nbytes, _stream(stream), C.byref(self.handle)))
+                                ckpt_every, _ptr(self.ws), self.ws.numel(), _stream(stream), C.byref(self.handle)))
 
     def forward(self, shots, seis=None, save_ckpt=True, stream=None):
         if seis is None:

@@ -75,7 +75,7 @@ def c1_problem(seeds, nt=500) -> Problem:
     d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, nmodels=B, dx=cfg.dx, dt=cfg.dt,
                pml_R=cfg.pml_R, pml_vmax=3500.0)
     wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)[None].repeat(B, 1).contiguous()
-    prop = fwi.Propagator(d, S.Shots(src, rec, wav))
+    prop = fwi.Propagator(d, S.Shots(src, rec, wav), store_segments=-1)
     dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
     t_d, i_d = dev(true), dev(init)
     obs = prop.forward(t_d, save_ckpt=False).clone()
