@@ -98,8 +98,9 @@ def main():
     ap.add_argument("--store-segments", type=int, default=None,
                     help="checkpoint segments whose adjoint snapshots the forward keeps "
                          "(default: as many as fit in free HBM)")
-    ap.add_argument("--time-blocking", type=int, default=2, choices=(1, 2),
-                    help="time steps per launch on the blocked tiles (results are identical)")
+    ap.add_argument("--time-blocking", type=int, default=None, choices=(1, 2),
+                    help="time steps per launch on the blocked tiles (results are identical); "
+                         "default: the autotuner's choice")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -132,6 +133,14 @@ def main():
     torch.cuda.synchronize()
     mt.close()
     del mt
+    # strategy from the autotuner (timed on 4 checkpoint segments of this
+    # grid and shot batch, cached, outside the timed region)
+    strategy = None
+    if args.time_blocking is None:
+        from paper_2003_06027_amd import tune
+        strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log)
+        args.time_blocking = strategy.time_blocking
+        torch.cuda.empty_cache()
     # workspace beyond the minimum keeps the adjoint snapshots of the last
     # checkpoint segments (their recomputation is skipped); leave a margin
     # for the seismogram and residual buffers
@@ -203,7 +212,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}", "grid_padded": list(cfg.padded),
                    "shots": ns, "nt": nt, "ckpt_every": ckpt, "stored_segments": nstore, "segments": nseg,
-                   "time_blocking": args.time_blocking, "receivers": nrec,
+                   "time_blocking": args.time_blocking,
+                   "tuned": None if strategy is None else {"time_blocking": strategy.time_blocking,
+                                                           "graphs": strategy.graphs},
+                   "launch": "eager (per-phase HIP events need eager launches)",
+                   "receivers": nrec,
                    "cell_updates_per_step": updates},
         "roofline": {"bound": "hbm", "kernel": f"ac2 {dom} step (PML + interior launches)",
                      "achieved": ph[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -1,0 +1,158 @@
+"""Autotuner of the sweep strategy for one workload (grid, shot batch,
+physics), with a JSON cache.
+
+Candidates:
+* time blocking, 2-D acoustic only: 1 or 2 steps per launch on the blocked
+  tiles (results are bitwise identical, traffic and launch count differ);
+* launch mode: eager launches, or one hipGraph holding the whole
+  checkpointed forward, misfit and adjoint of the batch, replayed (useful
+  where per-launch overhead dominates: small grids, many short steps).
+
+Each candidate is timed on a shortened run of the same grid and shots (a
+few checkpoint segments; the cost per step does not depend on nt) and the
+fastest is cached (graph replay only if it beats the best eager candidate
+by more than 2%) under a key of the workload and the device, in
+``$SEISGRAD_TUNE_CACHE`` or ``~/.cache/seisgrad/tune.json``.  Tuning runs
+outside any timed region.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import seisgrad as S
+
+
+GRAPH_MARGIN = 0.02
+
+
+@dataclasses.dataclass(frozen=True)
+class Strategy:
+    time_blocking: int = 2
+    graphs: bool = False
+
+
+def cache_path():
+    return os.environ.get("SEISGRAD_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "seisgrad", "tune.json"))
+
+
+def workload_key(d, nshots, nrec):
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    lib = S.LIB_PATH
+    build = os.path.getmtime(lib) if os.path.exists(lib) else 0
+    fields = (d.ndim, d.physics, d.nx, d.ny, d.nz, d.npml, d.nmodels, nshots, nrec, dev, build)
+    return hashlib.sha1(repr(fields).encode()).hexdigest()[:16]
+
+
+def candidates(d):
+    tbs = (2, 1) if (d.ndim == 2 and d.physics == S.SG_ACOUSTIC) else (2,)
+    return [Strategy(tb, g) for tb in tbs for g in (False, True)]
+
+
+class Runner:
+    """One checkpointed forward + misfit + adjoint of a shot batch, launched
+    eagerly or replayed from a captured graph, with fixed buffers."""
+
+    def __init__(self, d, shots, vp, obs, strategy: Strategy, ckpt=0, vs=None, rho=None):
+        self.shots = shots
+        self.m = S.Model(d, vp, shots.nshots, shots.nrec, ckpt, vs=vs, rho=rho)
+        self.m.set_time_blocking(strategy.time_blocking)
+        self.obs = obs
+        self.seis = torch.empty_like(obs)
+        self.resid = torch.empty_like(obs)
+        self.graph = None
+        self.out = None
+        if strategy.graphs:
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                self._eager()                 # geometry upload and first touch outside the capture
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self._eager()
+
+    def _eager(self):
+        self.m.forward(self.shots, seis=self.seis, save_ckpt=True)
+        self.J, _ = self.m.misfit(self.seis, self.obs, resid=self.resid)
+        if self.out is None:
+            self.out = self.m.gradient(self.shots, self.resid)
+        else:
+            outs = self.out if isinstance(self.out, tuple) else (self.out,)
+            g = self.m.gradient(self.shots, self.resid, g_vp=outs[0],
+                                g_vs=outs[1] if len(outs) > 1 else None, g_rho=outs[2] if len(outs) > 2 else None)
+            self.out = g
+        return self.out
+
+    def step(self):
+        if self.graph is not None:
+            self.graph.replay()
+            return self.out
+        return self._eager()
+
+    def close(self):
+        self.graph = None
+        self.m.close()
+
+
+def measure(d, shots, vp, obs, strategy, reps=3, **kw):
+    """Median seconds of one fwd + misfit + adjoint of the batch."""
+    r = Runner(d, shots, vp, obs, strategy, **kw)
+    r.step()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r.step()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    r.close()
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(d, shots, vp, vs=None, rho=None, ckpt=0, segments=4, cache=None, log=None, force=False):
+    """Best Strategy for this workload (cached).  Times every candidate on a
+    run of `segments` checkpoint segments of the same grid and shots."""
+    cache = cache or cache_path()
+    key = workload_key(d, shots.nshots, shots.nrec)
+    table = {}
+    if os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+    if key in table and not force:
+        return Strategy(**table[key]["strategy"])
+    K = ckpt if ckpt > 0 else int(math.ceil(math.sqrt(d.nt)))
+    nt = min(d.nt, segments * K)
+    dt = S.desc(ndim=d.ndim, physics=d.physics, nx=d.nx, ny=d.ny, nz=d.nz, npml=d.npml, nt=nt,
+                nmodels=d.nmodels, dx=d.dx, dt=d.dt, pml_R=d.pml_R, pml_vmax=d.pml_vmax, f0_pml=d.f0_pml)
+    wav = shots.wavelet[:, :nt].contiguous()
+    sh = S.Shots(shots.src, shots.rec, wav, shots.mt)
+    ref = S.Model(dt, vp, sh.nshots, sh.nrec, K, vs=vs, rho=rho)
+    obs = (ref.forward(sh, save_ckpt=False) * 0.9).contiguous()   # any data of the right shape
+    ref.close()
+    times = {}
+    for c in candidates(d):
+        times[c] = measure(dt, sh, vp, obs, c, ckpt=K, vs=vs, rho=rho)
+        if log:
+            log(f"tune {key}: {c} {times[c] * 1e3:.2f} ms for {nt} steps")
+    # graph replay only where it beats the best eager candidate by more than 2%
+    eager = min((c for c in times if not c.graphs), key=times.get)
+    best = min(times, key=times.get)
+    if best.graphs and times[best] > (1.0 - GRAPH_MARGIN) * times[eager]:
+        best = eager
+    table[key] = {"strategy": dataclasses.asdict(best), "nt_measured": nt,
+                  "ms": {f"tb{c.time_blocking}_graphs{int(c.graphs)}": round(t * 1e3, 3) for c, t in times.items()}}
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    with open(cache + ".tmp", "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(cache + ".tmp", cache)
+    return best
