@@ -240,6 +240,9 @@ def main():
             "reached_gd": r["reached_gd"], "reached_cnn": r["reached_cnn"], "models": r["models"],
             "final_rel_misfit_median_gd": round(r["final_rel_misfit_median_gd"], 4),
             "final_rel_misfit_median_cnn": round(r["final_rel_misfit_median_cnn"], 4),
+            "median_seconds_lbfgs": round(r["median_seconds_lbfgs"], 3),
+            "median_iters_lbfgs": r["median_iters_lbfgs"], "reached_lbfgs": r["reached_lbfgs"],
+            "final_rel_misfit_median_lbfgs": round(r["final_rel_misfit_median_lbfgs"], 4),
             "cnn_acceptance": round(r["cnn_acceptance"], 3),
             "data_seconds": round(r["data_seconds"], 2), "train_seconds": round(r["train_seconds"], 2),
             "break_even_batches": None if r["break_even_batches"] is None else round(r["break_even_batches"], 1),

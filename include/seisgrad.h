@@ -202,6 +202,29 @@ SG_API int phase_times(sg_model *m, double *ms, int64_t *steps);
  * Returns SG_EINVAL unless steps is 1 or 2. */
 SG_API int set_time_blocking(sg_model *m, int32_t steps);
 
+/* Limited-memory BFGS helpers of the outer inversion loop (the paper's
+ * optimizer is L-BFGS-B, Applications, FWI; bounds are kept by clipping the
+ * model after each step).  Models of a batch keep separate histories in ring
+ * buffers S, Y: DEVICE FP32 [mem][nmodels][n]; ysyy: DEVICE FP64
+ * [mem][nmodels][2] holding (y.s, y.y) of each stored pair; 1 <= mem <= 64.
+ *
+ * lbfgs_push: for each model b with 0 <= slot[b] < mem, writes
+ *   s = m_new - m_old and y = g_new - g_old (all DEVICE FP32 [nmodels][n])
+ *   into ring slot slot[b] and their (y.s, y.y) in FP64 (fixed order); a
+ *   model with slot[b] outside [0, mem) is left unchanged.  slot: DEVICE
+ *   int32 [nmodels].  The caller keeps a pair only if y.s > 0.
+ * lbfgs_direction: p = -H g per model by the two-loop recursion (Nocedal &
+ *   Wright, Algorithm 7.4) over hist[2b] pairs ending at ring slot
+ *   hist[2b+1] (newest), with H0 = (y.s / y.y of the newest pair) I; no
+ *   pairs (or hist[2b+1] outside [0, mem)) gives p = -g.  hist: DEVICE int32
+ *   [nmodels][2]; g, p: DEVICE FP32 [nmodels][n], p must not alias g.
+ *   Inner products in FP64, fixed order: bitwise reproducible. */
+SG_API int lbfgs_push(int32_t nmodels, int64_t n, int32_t mem, const int32_t *slot, const float *m_new,
+                      const float *m_old, const float *g_new, const float *g_old, float *S, float *Y,
+                      double *ysyy, sg_stream_t stream);
+SG_API int lbfgs_direction(int32_t nmodels, int64_t n, int32_t mem, const int32_t *hist, const float *S,
+                           const float *Y, const double *ysyy, const float *g, float *p, sg_stream_t stream);
+
 /* Release the host object (the workspace stays the caller's). */
 SG_API int free_model(sg_model *m);
 

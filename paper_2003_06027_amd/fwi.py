@@ -228,3 +228,116 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
             break
     return GDResult(models=m, J=np.array(Js), times=np.array(times), accepted=np.array(acc),
                     guarded=np.array(offered), rejected=np.array(rej))
+
+
+# --------------------------------------------------------------- batched L-BFGS
+@dataclasses.dataclass
+class LBFGSConfig:
+    iters: int = 50
+    mem: int = 8
+    alpha0: float = 50.0      # m/s, maximum model change of the first steepest-descent step
+    shrink: float = 0.5
+    grow: float = 1.25        # steepest-descent step growth after a first-try success
+    max_backtracks: int = 6
+    vmin: float = 1000.0
+    vmax: float = 5000.0
+
+
+def batched_lbfgs(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: LBFGSConfig = LBFGSConfig(),
+                  target=None, log=None) -> GDResult:
+    """L-BFGS on B models at once, each with its own history (the paper's
+    optimizer family; bounds by clipping).  Per iteration and model: the
+    two-loop direction p = -H g (library kernel; -g with no history), the
+    natural step m + p, halved until the misfit decreases.  Without history
+    (the first step, and after a reset) the step is the normalised
+    steepest-descent step alpha p / max|p| whose alpha persists across
+    iterations as in plain descent (shrunk on failure, grown after a
+    first-try success).  A model whose search fails, or whose direction is
+    not a descent direction, drops its history.  Pairs (s, y) with y.s <= 0
+    are not stored."""
+    B = prop.d.nmodels
+    dev = m0.device
+    n = m0[0].numel()
+    S_ = torch.zeros((cfg.mem, B, n), dtype=torch.float32, device=dev)
+    Y_ = torch.zeros_like(S_)
+    ysyy = torch.zeros((cfg.mem, B, 2), dtype=torch.float64, device=dev)
+    count = np.zeros(B, dtype=np.int32)
+    newest = np.full(B, -1, dtype=np.int32)
+    alpha_sd = np.full(B, cfg.alpha0)
+    m = m0.clone().contiguous()
+    Js, times, acc = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = prop.forward(m, save_ckpt=True)
+    J, r = per_model_misfit(prop, pred, obs, B)
+    J0 = J.cpu().numpy().copy()
+    Js.append(J0.copy())
+    torch.cuda.synchronize()
+    times.append(time.perf_counter() - t0)
+    g = prop.model.gradient(prop.shots, r).contiguous()
+    p = torch.empty_like(g)
+    lib = S.lib()
+    for it in range(cfg.iters):
+        hist = torch.as_tensor(np.stack([count, newest], 1).astype(np.int32), device=dev)
+        S._check(lib.lbfgs_direction(B, n, cfg.mem, S._ptr(hist), S._ptr(S_), S._ptr(Y_), S._ptr(ysyy),
+                                     S._ptr(g), S._ptr(p), S._stream()))
+        pf, gf = p.reshape(B, -1), g.reshape(B, -1)
+        descent = (pf.double() * gf.double()).sum(1).cpu().numpy() < 0
+        for b in np.nonzero(~descent)[0]:
+            pf[b] = -gf[b]
+            count[b], newest[b] = 0, -1
+        # natural step with history; without, the normalised steepest-descent
+        # step whose length persists from iteration to iteration as in plain GD
+        sd = count == 0
+        scale = torch.where(torch.as_tensor(sd, device=dev), torch.as_tensor(alpha_sd, dtype=torch.float32, device=dev)
+                            / pf.abs().amax(1).clamp_min(1e-30), torch.ones(B, device=dev))
+        Jc = J.cpu().numpy()
+        done = np.zeros(B, dtype=bool)
+        newm = m.clone()
+        a = torch.ones(B, device=dev)
+        for bt in range(cfg.max_backtracks + 1):
+            trial = (m.reshape(B, -1) + (a * scale)[:, None] * pf).reshape(m.shape).clamp(cfg.vmin, cfg.vmax)
+            Jt, _ = per_model_misfit(prop, prop.forward(trial, save_ckpt=False), obs, B)
+            Jt = Jt.cpu().numpy()
+            ok = (~done) & (Jt < Jc)
+            if ok.any():
+                idx = torch.as_tensor(np.nonzero(ok)[0], device=dev)
+                newm[idx] = trial[idx]
+            done |= ok
+            if done.all():
+                break
+            a[torch.as_tensor(~done, device=dev)] *= cfg.shrink
+        ah = a.cpu().numpy().astype(np.float64)
+        for b in np.nonzero(sd)[0]:
+            if done[b]:
+                alpha_sd[b] *= ah[b] * (cfg.grow if ah[b] == 1.0 else 1.0)
+            else:
+                alpha_sd[b] *= ah[b] * cfg.shrink
+        for b in np.nonzero(~done)[0]:
+            count[b], newest[b] = 0, -1          # failed search: restart from steepest descent
+        acc.append(done.copy())
+        m_old, g_old = m, g
+        m = newm
+        pred = prop.forward(m, save_ckpt=True)
+        J, r = per_model_misfit(prop, pred, obs, B)
+        g = prop.model.gradient(prop.shots, r).contiguous()
+        # store (s, y) of the models that moved
+        slot = np.where(done, (newest + 1) % cfg.mem, -1).astype(np.int32)
+        slot_d = torch.as_tensor(slot, device=dev)
+        S._check(lib.lbfgs_push(B, n, cfg.mem, S._ptr(slot_d), S._ptr(m), S._ptr(m_old), S._ptr(g), S._ptr(g_old),
+                                S._ptr(S_), S._ptr(Y_), S._ptr(ysyy), S._stream()))
+        ys = ysyy.cpu().numpy()
+        for b in np.nonzero(done)[0]:
+            if ys[slot[b], b, 0] > 0:
+                newest[b] = slot[b]
+                count[b] = min(count[b] + 1, cfg.mem)
+            elif count[b] == cfg.mem:
+                count[b] = cfg.mem - 1           # the rejected pair overwrote the oldest one
+        Js.append(J.cpu().numpy().copy())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if log:
+            log(it, Js[-1] / J0, done)
+        if target is not None and np.all(Js[-1] / J0 <= target):
+            break
+    return GDResult(models=m, J=np.array(Js), times=np.array(times), accepted=np.array(acc))

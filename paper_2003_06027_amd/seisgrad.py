@@ -23,7 +23,7 @@ _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_E
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
-           "set_time_blocking", "snapshot_segment_bytes")
+           "set_time_blocking", "snapshot_segment_bytes", "lbfgs_push", "lbfgs_direction")
 
 
 class SeisError(RuntimeError):
@@ -71,6 +71,9 @@ def lib():
         L.dot_f64.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.set_profiling.argtypes = [C.c_void_p, C.c_int32]
         L.set_time_blocking.argtypes = [C.c_void_p, C.c_int32]
+        v = C.c_void_p
+        L.lbfgs_push.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v, v, v]
+        L.lbfgs_direction.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v]
         L.phase_times.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         _lib = L
     return _lib

@@ -16,6 +16,8 @@ training, and the time-to-misfit comparison with plain gradient descent.
 * Use: safeguarded descent (the learned direction must satisfy <p, g> < 0
   and lower the misfit on its first trial, else the plain step is taken;
   after two consecutive rejections a model stops asking the network).
+* Also timed: batched L-BFGS (the paper's optimizer family, two-loop
+  direction in library kernels) from the same start, same iteration cap.
 * Measure: tau = the upper median over the evaluation models of
   J_GD(50) / J(0) (the (B/2 + 1)-th smallest, so that more than half of the
   models reach it under plain descent and both median times are finite);
@@ -202,8 +204,10 @@ def run(cfg: TTMConfig = TTMConfig(), log=None) -> dict:
     tau = float(np.sort(gd.J[-1] / gd.J[0])[len(cfg.eval_seeds) // 2])
     ld = LearnedDirection(pre, cfg.max_rejects)
     pc = fwi.batched_gd(ev.prop, ev.init, ev.obs, fwi.GDConfig(iters=cfg.eval_iters), direction=ld)
+    lb = fwi.batched_lbfgs(ev.prop, ev.init, ev.obs, fwi.LBFGSConfig(iters=cfg.eval_iters))
     s_gd, i_gd = time_to_target(gd, tau)
     s_pc, i_pc = time_to_target(pc, tau)
+    s_lb, i_lb = time_to_target(lb, tau)
     offered = pc.guarded.sum()
     out.update({
         "tau": tau,
@@ -215,6 +219,10 @@ def run(cfg: TTMConfig = TTMConfig(), log=None) -> dict:
         "seconds_per_iter_cnn": float(pc.times[-1] / (len(pc.times) - 1)),
         "final_rel_misfit_median_gd": float(np.median(gd.J[-1] / gd.J[0])),
         "final_rel_misfit_median_cnn": float(np.median(pc.J[-1] / pc.J[0])),
+        "median_seconds_lbfgs": float(np.median(s_lb)), "median_iters_lbfgs": float(np.median(i_lb)),
+        "reached_lbfgs": int(np.isfinite(s_lb).sum()),
+        "final_rel_misfit_median_lbfgs": float(np.median(lb.J[-1] / lb.J[0])),
+        "lbfgs_misfit_never_increases": bool(np.all(np.diff(lb.J, axis=0) <= 0)),
         "cnn_acceptance": float(1.0 - pc.rejected.sum() / offered) if offered else 0.0,
         "cnn_misfit_never_increases": bool(np.all(np.diff(pc.J, axis=0) <= 0)),
         "cnn_offered_steps": int(offered),
