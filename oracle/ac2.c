@@ -162,10 +162,21 @@ void or_ac2_pad(const or_grid *g, const double *cphys, double *c_pad,
     if (zeta_z) or_zeta_profile(g, g->nz, zeta_z);
 }
 
-/* The step; cf is the velocity in framed storage, fields framed. */
+/* Several source cells of one shot (the Gaussian-footprint location source
+ * and the multi-point rupture of the Applications section): cell indices
+ * and their values at the current step; f = value / dx^2 at each cell. */
+typedef struct {
+    int n;
+    const long *cell;
+    const double *val;   /* this step's wavelet value per cell */
+} msrc_t;
+
+/* The step; cf is the velocity in framed storage, fields framed.  A point
+ * source (src >= 0) enters inside the update; the cells of ms (if any) are
+ * added to u^{k+1} (times alpha) before phi is formed from u^{k+1}. */
 static void step(const ac2_ctx *c, const double *cf,
                  const double *u, const double *um, const double *px, const double *pz,
-                 long src, double src_val,
+                 long src, double src_val, const msrc_t *ms,
                  double *un, double *unm, double *pxn, double *pzn, double *w_out)
 {
     const double dt = c->dt;
@@ -183,6 +194,12 @@ static void step(const ac2_ctx *c, const double *cf,
             un[i] = alpha * (beta * u[i] - gamma * um[i] + C * w + dt * dt * f);
             if (w_out) w_out[i] = w;
         }
+    for (int j = 0; ms && j < ms->n; ++j) {
+        const long i = ms->cell[j];
+        const int iz = (int)(i / c->SX) - G, ix = (int)(i % c->SX) - G;
+        const double alpha = 1.0 / (1.0 + 0.5 * (c->zx[ix] + c->zz[iz]) * dt);
+        un[i] += alpha * dt * dt * ms->val[j] / (c->dx * c->dx);
+    }
     #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < c->NZ; ++iz)
         for (int ix = 0; ix < c->NX; ++ix) {
@@ -203,7 +220,7 @@ static void step_T(const ac2_ctx *c, const double *cf,
                    const double *u, const double *px, const double *pz,
                    const double *au_n, const double *aum_n, const double *apx_n, const double *apz_n,
                    double *au, double *aum, double *apx, double *apz,
-                   double *gC, long src, double *src_bar)
+                   double *gC, long src, double *src_bar, const msrc_t *ms, double *ms_bar)
 {
     const double dt = c->dt;
     double *aun = c->aun, *qx = c->qx, *qz = c->qz, *t = c->t, *Ct = c->Ct;
@@ -241,6 +258,7 @@ static void step_T(const ac2_ctx *c, const double *cf,
             if (gC) gC[i] += t[i] * (lap(c, u, i) + d1(c, px, i, 0) + d1(c, pz, i, 1));
         }
     if (src_bar && src >= 0) *src_bar = t[src] * dt * dt / (c->dx * c->dx);
+    for (int j = 0; ms && ms_bar && j < ms->n; ++j) ms_bar[j] = t[ms->cell[j]] * dt * dt / (c->dx * c->dx);
     /* w^k = L u^k + D_x phix^k + D_z phiz^k */
     lap_T(c, Ct, au);
     d1_T(c, Ct, apx, 0);
@@ -263,7 +281,7 @@ void or_ac2_step(const or_grid *g, const double *c_pad,
     to_frame(&c, px, X + 2 * c.N); to_frame(&c, pz, X + 3 * c.N);
     long src = -1;
     if (src_idx >= 0) src = fi(&c, (int)(src_idx / c.NX), (int)(src_idx % c.NX));
-    step(&c, cf, X, X + c.N, X + 2 * c.N, X + 3 * c.N, src, src_val,
+    step(&c, cf, X, X + c.N, X + 2 * c.N, X + 3 * c.N, src, src_val, NULL,
          Y, Y + c.N, Y + 2 * c.N, Y + 3 * c.N, W);
     from_frame(&c, Y, un); from_frame(&c, Y + c.N, unm);
     from_frame(&c, Y + 2 * c.N, pxn); from_frame(&c, Y + 3 * c.N, pzn);
@@ -290,7 +308,7 @@ void or_ac2_step_T(const or_grid *g, const double *c_pad,
     long src = -1;
     if (src_idx >= 0) src = fi(&c, (int)(src_idx / c.NX), (int)(src_idx % c.NX));
     step_T(&c, cf, X, X + c.N, X + 2 * c.N, aY, aY + c.N, aY + 2 * c.N, aY + 3 * c.N,
-           aX, aX + c.N, aX + 2 * c.N, aX + 3 * c.N, gf, src, src_bar);
+           aX, aX + c.N, aX + 2 * c.N, aX + 3 * c.N, gf, src, src_bar, NULL, NULL);
     from_frame(&c, aX, au); from_frame(&c, aX + c.N, aum);
     from_frame(&c, aX + 2 * c.N, apx); from_frame(&c, aX + 3 * c.N, apz);
     if (gC) from_frame(&c, gf, gC);
@@ -298,12 +316,13 @@ void or_ac2_step_T(const or_grid *g, const double *c_pad,
     ctx_free(&c);
 }
 
-static int check_geom(const or_grid *g, int32_t nshots, const int32_t *src,
+static int check_geom(const or_grid *g, int32_t nshots, int32_t nsrc, const int32_t *src,
                       int32_t nrec, const int32_t *rec)
 {
-    if (g->ndim != 2 || g->nx < 1 || g->nz < 1 || g->npml < 0 || g->nt < 1) return -1;
+    if (g->ndim != 2 || g->nx < 1 || g->nz < 1 || g->npml < 0 || g->nt < 1 || nsrc < 1) return -1;
+    for (long j = 0; j < (long)nshots * nsrc; ++j)
+        if (src[2 * j] < 0 || src[2 * j] >= g->nx || src[2 * j + 1] < 0 || src[2 * j + 1] >= g->nz) return -1;
     for (int s = 0; s < nshots; ++s) {
-        if (src[2 * s] < 0 || src[2 * s] >= g->nx || src[2 * s + 1] < 0 || src[2 * s + 1] >= g->nz) return -1;
         for (int r = 0; r < nrec; ++r) {
             const int32_t *q = rec + ((long)s * nrec + r) * 2;
             if (q[0] < 0 || q[0] >= g->nx || q[1] < 0 || q[1] >= g->nz) return -1;
@@ -314,8 +333,10 @@ static int check_geom(const or_grid *g, int32_t nshots, const int32_t *src,
 
 /* One shot: forward, then optionally the two-level checkpointed reverse
  * sweep (checkpoints every K steps, each segment recomputed and stored
- * whole; K >= nt stores every state).  cf: framed velocity. */
-static void run_shot(const or_grid *g, const double *cf, const int32_t *src,
+ * whole; K >= nt stores every state).  cf: framed velocity.  nsrc = 1: a
+ * point source (src[2], wav[nt], gwav[nt]); nsrc > 1: source cells src[nsrc][2]
+ * with wavelets wav[nsrc][nt] and gradients gwav[nsrc][nt]. */
+static void run_shot(const or_grid *g, const double *cf, int32_t nsrc, const int32_t *src,
                      const double *wav, int32_t nrec, const int32_t *rec,
                      double *seis, const double *dJdd, int32_t ckpt,
                      double *gC, double *gwav)
@@ -324,7 +345,13 @@ static void run_shot(const or_grid *g, const double *cf, const int32_t *src,
     ctx_init(&c, g);
     const long N = c.N;
     const int nt = g->nt, P = g->npml;
-    const long sidx = fi(&c, src[1] + P, src[0] + P);
+    const long sidx = nsrc == 1 ? fi(&c, src[1] + P, src[0] + P) : -1;
+    long *mcell = malloc(sizeof(long) * nsrc);
+    double *mval = malloc(sizeof(double) * nsrc), *mbar = malloc(sizeof(double) * nsrc);
+    for (int j = 0; j < nsrc; ++j) mcell[j] = fi(&c, src[2 * j + 1] + P, src[2 * j] + P);
+    msrc_t msv = {nsrc, mcell, mval};
+    const msrc_t *ms = nsrc > 1 ? &msv : NULL;
+    #define SET_MS(k) do { for (int j_ = 0; ms && j_ < nsrc; ++j_) mval[j_] = wav[(long)j_ * nt + (k)]; } while (0)
     long *ridx = malloc(sizeof(long) * (nrec > 0 ? nrec : 1));
     for (int r = 0; r < nrec; ++r) ridx[r] = fi(&c, rec[2 * r + 1] + P, rec[2 * r] + P);
 
@@ -335,7 +362,8 @@ static void run_shot(const or_grid *g, const double *cf, const int32_t *src,
 
     for (int k = 0; k < nt; ++k) {
         if (ck && k % K == 0) memcpy(ck + (size_t)(k / K) * 4 * N, X, sizeof(double) * 4 * N);
-        step(&c, cf, X, X + N, X + 2 * N, X + 3 * N, sidx, wav[k],
+        SET_MS(k);
+        step(&c, cf, X, X + N, X + 2 * N, X + 3 * N, sidx, nsrc == 1 ? wav[k] : 0.0, ms,
              Y, Y + N, Y + 2 * N, Y + 3 * N, NULL);
         double *tmp = X; X = Y; Y = tmp;
         if (seis) for (int r = 0; r < nrec; ++r) seis[(long)k * nrec + r] = X[ridx[r]];
@@ -349,7 +377,8 @@ static void run_shot(const or_grid *g, const double *cf, const int32_t *src,
             memcpy(seg, ck + (size_t)s * 4 * N, sizeof(double) * 4 * N);
             for (int k = k0; k < k1 - 1; ++k) {
                 double *a = seg + (size_t)(k - k0) * 4 * N, *b = a + 4 * N;
-                step(&c, cf, a, a + N, a + 2 * N, a + 3 * N, sidx, wav[k],
+                SET_MS(k);
+                step(&c, cf, a, a + N, a + 2 * N, a + 3 * N, sidx, nsrc == 1 ? wav[k] : 0.0, ms,
                      b, b + N, b + 2 * N, b + 3 * N, NULL);
             }
             for (int k = k1 - 1; k >= k0; --k) {
@@ -359,14 +388,18 @@ static void run_shot(const or_grid *g, const double *cf, const int32_t *src,
                 for (int r = 0; r < nrec; ++r) L[ridx[r]] += dJdd[(long)k * nrec + r];
                 double sb = 0.0;
                 step_T(&c, cf, a, a + 2 * N, a + 3 * N, L, L + N, L + 2 * N, L + 3 * N,
-                       Ln, Ln + N, Ln + 2 * N, Ln + 3 * N, gC, sidx, &sb);
-                if (gwav) gwav[k] = sb;
+                       Ln, Ln + N, Ln + 2 * N, Ln + 3 * N, gC, sidx, &sb, ms, mbar);
+                if (gwav) {
+                    if (nsrc == 1) gwav[k] = sb;
+                    else for (int j = 0; j < nsrc; ++j) gwav[(long)j * nt + k] = mbar[j];
+                }
                 double *tmp = L; L = Ln; Ln = tmp;
             }
         }
         free(seg); free(L); free(Ln);
     }
-    free(ck); free(X); free(Y); free(ridx); ctx_free(&c);
+    #undef SET_MS
+    free(ck); free(X); free(Y); free(ridx); free(mcell); free(mval); free(mbar); ctx_free(&c);
 }
 
 static double *framed_velocity(const or_grid *g, const double *cphys, ac2_ctx *c)
@@ -379,21 +412,28 @@ static double *framed_velocity(const or_grid *g, const double *cphys, ac2_ctx *c
     return cf;
 }
 
-int or_ac2_forward(const or_grid *g, const double *cphys, int32_t nshots,
-                   const int32_t *src, const double *wav, int32_t nrec,
-                   const int32_t *rec, double *seis)
+int or_ac2_forward_ms(const or_grid *g, const double *cphys, int32_t nshots, int32_t nsrc,
+                      const int32_t *src, const double *wav, int32_t nrec,
+                      const int32_t *rec, double *seis)
 {
-    if (check_geom(g, nshots, src, nrec, rec)) return -1;
+    if (check_geom(g, nshots, nsrc, src, nrec, rec)) return -1;
     ac2_ctx c;
     ctx_init(&c, g);
     double *cf = framed_velocity(g, cphys, &c);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int s = 0; s < nshots; ++s)
-        run_shot(g, cf, src + 2 * s, wav + (long)s * g->nt, nrec, rec + (long)s * nrec * 2,
+        run_shot(g, cf, nsrc, src + 2L * nsrc * s, wav + (long)s * nsrc * g->nt, nrec, rec + (long)s * nrec * 2,
                  seis + (long)s * g->nt * nrec, NULL, 0, NULL, NULL);
     free(cf);
     ctx_free(&c);
     return 0;
+}
+
+int or_ac2_forward(const or_grid *g, const double *cphys, int32_t nshots,
+                   const int32_t *src, const double *wav, int32_t nrec,
+                   const int32_t *rec, double *seis)
+{
+    return or_ac2_forward_ms(g, cphys, nshots, 1, src, wav, nrec, rec, seis);
 }
 
 int or_ac2_gradient(const or_grid *g, const double *cphys, int32_t nshots,
@@ -401,7 +441,15 @@ int or_ac2_gradient(const or_grid *g, const double *cphys, int32_t nshots,
                     const int32_t *rec, const double *dJdd, int32_t ckpt,
                     double *grad_c, double *seis, double *grad_wav)
 {
-    if (check_geom(g, nshots, src, nrec, rec)) return -1;
+    return or_ac2_gradient_ms(g, cphys, nshots, 1, src, wav, nrec, rec, dJdd, ckpt, grad_c, seis, grad_wav);
+}
+
+int or_ac2_gradient_ms(const or_grid *g, const double *cphys, int32_t nshots, int32_t nsrc,
+                       const int32_t *src, const double *wav, int32_t nrec,
+                       const int32_t *rec, const double *dJdd, int32_t ckpt,
+                       double *grad_c, double *seis, double *grad_wav)
+{
+    if (check_geom(g, nshots, nsrc, src, nrec, rec)) return -1;
     ac2_ctx c;
     ctx_init(&c, g);
     const int P = g->npml;
@@ -409,10 +457,10 @@ int or_ac2_gradient(const or_grid *g, const double *cphys, int32_t nshots,
     double *gC = calloc((size_t)nshots * c.N, sizeof(double));
     #pragma omp parallel for schedule(dynamic, 1)
     for (int s = 0; s < nshots; ++s)
-        run_shot(g, cf, src + 2 * s, wav + (long)s * g->nt, nrec, rec + (long)s * nrec * 2,
+        run_shot(g, cf, nsrc, src + 2L * nsrc * s, wav + (long)s * nsrc * g->nt, nrec, rec + (long)s * nrec * 2,
                  seis ? seis + (long)s * g->nt * nrec : NULL,
                  dJdd + (long)s * g->nt * nrec, ckpt, gC + (size_t)s * c.N,
-                 grad_wav ? grad_wav + (long)s * g->nt : NULL);
+                 grad_wav ? grad_wav + (long)s * nsrc * g->nt : NULL);
     /* chain rule C = dt^2 c^2 -> dJ/dc = 2 dt^2 c dJ/dC, then fold the padded
      * cells back onto the physical cells they replicate; shots in order */
     memset(grad_c, 0, sizeof(double) * g->nx * g->nz);

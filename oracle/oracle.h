@@ -92,6 +92,19 @@ int or_ac2_forward(const or_grid *g, const double *c, int32_t nshots,
  * every state).  grad_c has nz*nx entries (sum over shots, fixed order).
  * seis (nullable) receives the forward seismograms, grad_wav (nullable)
  * receives dJ/dwavelet [nshots][nt]. */
+/* Several source cells per shot (Applications: the Gaussian-footprint
+ * earthquake location source and the multi-point rupture): src
+ * [nshots][nsrc][2], wav [nshots][nsrc][nt]; each cell j injects
+ * dt^2 wav_j(t_k)/dx^2 into u^{k+1} (times the layer's alpha);
+ * grad_wav [nshots][nsrc][nt] = dJ/dwav.  nsrc = 1 is the point source of
+ * or_ac2_forward / or_ac2_gradient. */
+int or_ac2_forward_ms(const or_grid *g, const double *c, int32_t nshots, int32_t nsrc,
+                      const int32_t *src, const double *wav, int32_t nrec,
+                      const int32_t *rec, double *seis);
+int or_ac2_gradient_ms(const or_grid *g, const double *c, int32_t nshots, int32_t nsrc,
+                       const int32_t *src, const double *wav, int32_t nrec,
+                       const int32_t *rec, const double *dJdd, int32_t ckpt,
+                       double *grad_c, double *seis, double *grad_wav);
 int or_ac2_gradient(const or_grid *g, const double *c, int32_t nshots,
                     const int32_t *src, const double *wav, int32_t nrec,
                     const int32_t *rec, const double *dJdd, int32_t ckpt,

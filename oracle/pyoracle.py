@@ -125,6 +125,33 @@ def ac2_gradient(g, c, src, wav, rec, dJdd, ckpt=0, want_wav=False):
     return (grad, seis, gw) if want_wav else (grad, seis)
 
 
+def ac2_forward_ms(g, c, src, wav, rec):
+    """Several source cells per shot: src [ns][nsrc][2], wav [ns][nsrc][nt]."""
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    ns, nsrc, nrec = src.shape[0], src.shape[1], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    rc = lib().or_ac2_forward_ms(C.byref(g), _d(_f64(c)), C.c_int32(ns), C.c_int32(nsrc), _i(src), _d(wav),
+                                 C.c_int32(nrec), _i(rec), _d(seis))
+    if rc:
+        raise ValueError("oracle: invalid geometry or grid")
+    return seis
+
+
+def ac2_gradient_ms(g, c, src, wav, rec, dJdd, ckpt=0):
+    """(dJ/dc, seismograms, dJ/dwav [ns][nsrc][nt]) for several source cells per shot."""
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    ns, nsrc, nrec = src.shape[0], src.shape[1], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    grad = np.zeros((g.nz, g.nx))
+    gw = np.zeros((ns, nsrc, g.nt))
+    rc = lib().or_ac2_gradient_ms(C.byref(g), _d(_f64(c)), C.c_int32(ns), C.c_int32(nsrc), _i(src), _d(wav),
+                                  C.c_int32(nrec), _i(rec), _d(_f64(dJdd)), C.c_int32(ckpt),
+                                  _d(grad), _d(seis), _d(gw))
+    if rc:
+        raise ValueError("oracle: invalid geometry or grid")
+    return grad, seis, gw
+
+
 def misfit(pred, obs):
     pred, obs = _f64(pred), _f64(obs)
     r = np.zeros_like(pred)
