@@ -98,15 +98,23 @@ typedef struct sg_desc {
 } sg_desc;
 
 /* One batch of shots. */
+#define SG_MAX_SRC 64    /* source cells per shot */
+
 typedef struct sg_shots {
     int32_t nshots;          /* >= 1, multiple of nmodels, <= max_shots of the model */
     int32_t nrec;            /* receivers per shot (>= 0) */
-    const int32_t *src;      /* HOST [nshots][ndim]: (ix, iz) or (ix, iy, iz) source node */
+    const int32_t *src;      /* HOST [nshots][nsrc][ndim]: (ix, iz) or (ix, iy, iz) source nodes */
     const int32_t *rec;      /* HOST [nshots][nrec][ndim]: receiver nodes, same order */
-    const float *wavelet;    /* DEVICE [nshots][nt]: source time function r(t_k) */
+    const float *wavelet;    /* DEVICE [nshots][nsrc][nt]: source time function r_j(t_k) of
+                                each source node (value r at a node: density r/(dx dz)) */
     const float *mt;         /* HOST [nshots][3]: moment tensor (Mxx, Mzz, Mxz) of elastic
                                 sources (stress-rate injection dt M r(t_n)/(dx dz)); NULL for
                                 acoustic shots */
+    int32_t nsrc;            /* source nodes per shot: 0 or 1 = one point source; up to
+                                SG_MAX_SRC nodes, each with its own wavelet, for the 2-D
+                                acoustic equation only (the Gaussian-footprint location
+                                source and the multi-point rupture of the paper's source
+                                applications); other physics return SG_EUNSUPPORTED */
 } sg_shots;
 
 typedef struct sg_model sg_model;
@@ -177,7 +185,8 @@ SG_API int misfit(sg_model *m, const float *pred, const float *obs, int64_t n,
  *          order, absorbing-layer cells folded onto the edge cells they
  *          replicate;
  *   g_vs, g_rho: reserved, NULL;
- *   g_wavelet: DEVICE FP32 [nshots][nt] or NULL: dJ/dr(t_k) per shot.
+ *   g_wavelet: DEVICE FP32 [nshots][nsrc][nt] or NULL: dJ/dr_j(t_k) per shot and
+ *            source node.
  * Errors: SG_ESTATE when no matching checkpointed forward precedes it. */
 SG_API int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd,
                      float *g_vp, float *g_vs, float *g_rho, float *g_wavelet,
@@ -224,6 +233,34 @@ SG_API int lbfgs_push(int32_t nmodels, int64_t n, int32_t mem, const int32_t *sl
                       double *ysyy, sg_stream_t stream);
 SG_API int lbfgs_direction(int32_t nmodels, int64_t n, int32_t mem, const int32_t *hist, const float *S,
                            const float *Y, const double *ysyy, const float *g, float *p, sg_stream_t stream);
+
+/* Source parameterisations of the paper's source applications (2-D; nodes
+ * are physical (ix, iz) indices, node (ix, iz) sits at (ix dx, iz dx)).
+ *
+ * Earthquake location (Applications, "Earthquake Location and Source Time
+ * Function Retrieval"): f(x, t) = g(t) exp(-|x - x0|^2/(2 sigma^2))/(2 pi
+ * sigma^2) sampled at nsrc footprint nodes (the caller picks the nodes, e.g.
+ * the 7 x 7 around the node nearest x0 for sigma = dx/2):
+ *   source_gaussian: wav[j][k] = g(t_k) w_j, w_j = dx^2 exp(-r_j^2/(2
+ *     sigma^2))/(2 pi sigma^2) -- the wavelets of one shot's nodes;
+ *   source_gaussian_grad: from gw = dJ/dwav [nsrc][nt] (adjoint_gradient's
+ *     g_wavelet), dg[k] = dJ/dg(t_k) and dxz = (dJ/dx0, dJ/dz0).
+ * Rupture (Applications, "Earthquake Rupture Imaging"): points j with
+ * f_j(t) = A0_j exp(-(t - t0_j)^2/(2 sigma_t^2)):
+ *   source_rupture: wav[j][k] = f_j(k dt);
+ *   source_rupture_grad: dA0[j] = dJ/dA0_j and dt0[j] = dJ/dt0_j from gw.
+ * cells: DEVICE int32 [nsrc][2]; g, A0, t0, wav, gw, dg: DEVICE FP32; dxz
+ * (2), dA0, dt0 (npt): DEVICE FP64.  Sums over steps and nodes in FP64, in a
+ * fixed order. */
+SG_API int source_gaussian(int32_t nsrc, int32_t nt, const int32_t *cells, double x0, double z0, double sigma,
+                           double dx, const float *g, float *wav, sg_stream_t stream);
+SG_API int source_gaussian_grad(int32_t nsrc, int32_t nt, const int32_t *cells, double x0, double z0,
+                                double sigma, double dx, const float *g, const float *gw, float *dg, double *dxz,
+                                sg_stream_t stream);
+SG_API int source_rupture(int32_t npt, int32_t nt, const float *A0, const float *t0, double sigma_t, double dt,
+                          float *wav, sg_stream_t stream);
+SG_API int source_rupture_grad(int32_t npt, int32_t nt, const float *A0, const float *t0, double sigma_t, double dt,
+                               const float *gw, double *dA0, double *dt0, sg_stream_t stream);
 
 /* Release the host object (the workspace stays the caller's). */
 SG_API int free_model(sg_model *m);

@@ -154,6 +154,38 @@ __global__ __launch_bounds__(256) void ac2_phi_kernel(Ac2PhiArgs a)
     }
 }
 
+// Sum of dt^2/(dx dz) r_j(t_k) over the source nodes j of this shot at
+// local tile cell `cell` (several source nodes per shot; a handful of
+// entries per tile, only in the tiles that hold them).
+__device__ __forceinline__ float node_sources(const Ac2FwdArgs &a, int tile, int shot, int cell)
+{
+    const int ntiles = a.g.ntx * a.g.ntz;
+    const int *off = a.src_off + (long long)shot * (ntiles + 1);
+    float v = 0.f;
+    for (int e = off[tile]; e < off[tile + 1]; ++e) {
+        const int ent = a.src_ent[e];
+        if ((ent >> 8) == cell)
+            v += a.src_scale * a.wav[((long long)shot * a.nsrc + (ent & 255)) * a.nt + a.k];
+    }
+    return v;
+}
+
+__global__ void ac2_src_gather_kernel(int nshots, int nsrc, long long plane, const long long *node_f,
+                                      const float *s1, float *gw, int nt, int k, float scale)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nshots * nsrc) return;
+    const int shot = i / nsrc;
+    gw[(long long)i * nt + k] = scale * s1[(long long)shot * plane + node_f[i]];
+}
+
+void launch_ac2_src_gather(int nshots, int nsrc, long long plane, const long long *node_f, const float *s1,
+                           float *gw, int nt, int k, float scale, hipStream_t s)
+{
+    const int n = nshots * nsrc;
+    ac2_src_gather_kernel<<<(n + 255) / 256, 256, 0, s>>>(nshots, nsrc, plane, node_f, s1, gw, nt, k, scale);
+}
+
 // ------------------------------------------------------------ forward pass B
 template <bool NEAR, bool SNAP, bool REC>
 __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int tile, int shot)
@@ -200,11 +232,13 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
                 const float umf = um[f];
                 float inc = (uc[j] - umf) + ((hx + hz) * umf - 4.f * hx * hz * uc[j]) + chat[f] * w;
                 if (f == src) inc += sval;
+                if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
                 v = alpha * (uc[j] + inc);
             } else {
                 // 2u - um + chat w = u + ((u - um) + chat w)
                 float inc = fmaf(chat[f], w, uc[j] - um[f]);
                 if (f == src) inc += sval;
+                if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
                 v = uc[j] + inc;
             }
             uo[f] = v;

@@ -67,7 +67,7 @@ struct Layout {
     int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
         off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt,
-        off_tiles, total;
+        off_tiles, off_soff, off_sent, off_nodef, total;
 };
 
 int check_desc(const sg_desc *d)
@@ -167,6 +167,9 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_uid = take(sizeof(int) * std::max<size_t>(1, (size_t)max_shots * max_rec));
     L.off_mt = take(sizeof(float) * 3 * max_shots);
     L.off_tiles = take(sizeof(int) * 2 * std::max(1, L.ntiles));
+    L.off_soff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
+    L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
+    L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
     L.total = o;
     return L;
 }
@@ -186,6 +189,12 @@ struct sg_model {
     // 2-D acoustic tiles advanced one step per launch ("near": the layer within
     // reach, or receivers within 4 cells) and two steps per launch ("blocked")
     int *tiles_near = nullptr, *tiles_blk = nullptr;
+    // several source nodes per shot (2-D acoustic): per-tile CSR and node frame indices
+    int *src_off = nullptr, *src_ent = nullptr;
+    long long *node_f = nullptr;
+    int geom_nsrc = 1;
+    std::vector<int> h_soff, h_sent;
+    std::vector<long long> h_nodef;
     int n_near = 0, n_blk = 0;
     std::vector<int> h_tiles;
     int steps_per_launch = 2;
@@ -236,8 +245,9 @@ bool same_geometry(const sg_model *m, const sg_shots *sh)
         for (int i = 0; i < 3 * ns; ++i)
             if (m->h_mt[i] != sh->mt[i]) return false;
     }
-    return m->geom_nshots == ns && m->geom_nrec == sh->nrec &&
-           std::equal(sh->src, sh->src + (size_t)nd * ns, m->geom_src.begin()) &&
+    const int nsrc = sh->nsrc < 1 ? 1 : sh->nsrc;
+    return m->geom_nshots == ns && m->geom_nrec == sh->nrec && m->geom_nsrc == nsrc &&
+           std::equal(sh->src, sh->src + (size_t)nd * ns * nsrc, m->geom_src.begin()) &&
            (sh->nrec == 0 || std::equal(sh->rec, sh->rec + (size_t)nd * ns * sh->nrec, m->geom_rec.begin()));
 }
 
@@ -254,9 +264,12 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
         }
         return true;
     };
+    const int nsrc = sh->nsrc < 1 ? 1 : sh->nsrc;
     for (int i = 0; i < ns; ++i) {
-        if (!inside(sh->src + (size_t)nd * i))
-            return fail(SG_EINVAL, "shot %d: source outside the %dx%dx%d grid", i, phys[0], phys[1], phys[2]);
+        for (int j = 0; j < nsrc; ++j)
+            if (!inside(sh->src + ((size_t)i * nsrc + j) * nd))
+                return fail(SG_EINVAL, "shot %d: source node %d outside the %dx%dx%d grid", i, j, phys[0], phys[1],
+                            phys[2]);
         for (int r = 0; r < nrec; ++r)
             if (!inside(sh->rec + ((size_t)i * nrec + r) * nd))
                 return fail(SG_EINVAL, "shot %d receiver %d outside the grid", i, r);
@@ -316,6 +329,7 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
         else m->geom_rec.clear();
         m->geom_nshots = ns;
         m->geom_nrec = nrec;
+        m->geom_nsrc = 1;
         m->have_ckpt = false;
         return SG_OK;
     }
@@ -325,9 +339,40 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
     m->h_ent.clear();
     m->h_ent3.clear();
     std::vector<std::pair<long long, int>> keyed;
+    if (nsrc > 1) {
+        // several source nodes per shot: no fused point source; per (shot, tile)
+        // lists of (local cell, node) and the frame index of every node
+        const Grid2 &g = L.g2;
+        m->h_soff.assign((size_t)ns * (ntiles + 1), 0);
+        m->h_sent.clear();
+        m->h_nodef.assign((size_t)ns * nsrc, 0);
+        for (int i = 0; i < ns; ++i) {
+            std::vector<std::pair<int, int>> byt;   // (tile, packed entry)
+            for (int j = 0; j < nsrc; ++j) {
+                const int32_t *q = sh->src + ((size_t)i * nsrc + j) * 2;
+                const int px = q[0] + P, pz = q[1] + P;
+                m->h_nodef[(size_t)i * nsrc + j] = (long long)(pz + OZ) * g.SX + px + OX;
+                byt.push_back({(pz / TZ) * g.ntx + px / TX, (((pz % TZ) * TX + px % TX) << 8) | j});
+            }
+            std::sort(byt.begin(), byt.end());
+            int *off = m->h_soff.data() + (size_t)i * (ntiles + 1);
+            size_t e = 0;
+            for (int tl = 0; tl < ntiles; ++tl) {
+                off[tl] = (int)m->h_sent.size();
+                while (e < byt.size() && byt[e].first == tl) m->h_sent.push_back(byt[e++].second);
+            }
+            off[ntiles] = (int)m->h_sent.size();
+        }
+        HIPCHECK(hipMemcpyAsync(m->src_off, m->h_soff.data(), sizeof(int) * m->h_soff.size(), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(m->src_ent, m->h_sent.data(), sizeof(int) * m->h_sent.size(), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(m->node_f, m->h_nodef.data(), sizeof(long long) * m->h_nodef.size(),
+                                hipMemcpyHostToDevice, s));
+    }
     for (int i = 0; i < ns; ++i) {
-        const int32_t *q = sh->src + (size_t)nd * i;
-        if (nd == 2) {
+        const int32_t *q = sh->src + (size_t)nd * nsrc * i;
+        if (nsrc > 1) {
+            m->h_src[i] = -1;
+        } else if (nd == 2) {
             const Grid2 &g = L.g2;
             m->h_src[i] = (long long)(q[1] + P + OZ) * g.SX + q[0] + P + OX;
         } else {
@@ -373,9 +418,11 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
         // and no receiver of any shot lies within 4 cells of the tile
         const Grid2 &g = L.g2;
         std::vector<char> rec_near(ntiles, 0);
+        const int nnode = nsrc > 1 ? nsrc : 0;     // source nodes handled by the one-step kernel
         for (int i = 0; i < ns; ++i)
-            for (int r = 0; r < nrec; ++r) {
-                const int32_t *e = sh->rec + ((size_t)i * nrec + r) * nd;
+            for (int r = 0; r < nrec + nnode; ++r) {
+                const int32_t *e = r < nrec ? sh->rec + ((size_t)i * nrec + r) * nd
+                                            : sh->src + ((size_t)i * nsrc + (r - nrec)) * nd;
                 const int px = e[0] + P, pz = e[1] + P;
                 for (int tz = std::max(0, (pz - 4) / TZ - 1); tz <= std::min(g.ntz - 1, (pz + 4) / TZ); ++tz)
                     for (int tx = std::max(0, (px - 4) / TX - 1); tx <= std::min(g.ntx - 1, (px + 4) / TX); ++tx)
@@ -402,11 +449,12 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
         HIPCHECK(hipMemcpyAsync(m->rec_ent, m->h_ent.data(), sizeof(int) * m->h_ent.size(), hipMemcpyHostToDevice, s));
     if (nd == 3 && !m->h_ent3.empty())
         HIPCHECK(hipMemcpyAsync(m->rec_ent, m->h_ent3.data(), sizeof(int2) * m->h_ent3.size(), hipMemcpyHostToDevice, s));
-    m->geom_src.assign(sh->src, sh->src + (size_t)nd * ns);
+    m->geom_src.assign(sh->src, sh->src + (size_t)nd * ns * nsrc);
     if (nrec > 0) m->geom_rec.assign(sh->rec, sh->rec + (size_t)nd * ns * nrec);
     else m->geom_rec.clear();
     m->geom_nshots = ns;
     m->geom_nrec = nrec;
+    m->geom_nsrc = nsrc;
     m->have_ckpt = false;
     return SG_OK;
 }
@@ -421,6 +469,9 @@ int check_shots(const sg_model *m, const sg_shots *sh)
     if (sh->nrec < 0 || sh->nrec > m->max_rec)
         return fail(SG_EINVAL, "nrec %d outside [0, %d]", sh->nrec, m->max_rec);
     if (!sh->wavelet) return fail(SG_EINVAL, "wavelet is NULL");
+    if (sh->nsrc < 0 || sh->nsrc > SG_MAX_SRC) return fail(SG_EINVAL, "nsrc %d outside [0, %d]", sh->nsrc, SG_MAX_SRC);
+    if (sh->nsrc > 1 && (m->L.elastic || m->d.ndim != 2))
+        return fail(SG_EUNSUPPORTED, "several source nodes per shot are provided for the 2-D acoustic equation only");
     return SG_OK;
 }
 
@@ -589,6 +640,9 @@ void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, const int *ti
     a.nrec = m->geom_nrec;
     a.seis = seis;
     a.snap = snap;
+    a.nsrc = m->geom_nsrc;
+    a.src_off = m->src_off;
+    a.src_ent = m->src_ent;
     launch_ac2_fwd(a, s);
 }
 
@@ -721,13 +775,20 @@ void ac2_adj_tiles(const sg_model *m, int ns, int k, const int *tiles, int ntl, 
 void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, float *gwav, const float *snap1,
                  const float *snap0, hipStream_t s)
 {
+    const bool nodes = gwav && m->geom_nsrc > 1;
+    auto gather = [&](int kk) {
+        launch_ac2_src_gather(ns, m->geom_nsrc, m->L.plane, m->node_f, m->s4[(kk + 1) & 3], gwav, m->d.nt, kk,
+                              src_scale(m), s);
+    };
     if (!two) {
         ac2_phi_adj(m, ns, k, s);
         ac2_adj_tiles(m, ns, k, nullptr, 0, dJdd, gwav, snap1, s);
+        if (nodes) gather(k);
         return;
     }
     ac2_phi_adj(m, ns, k, s);
     ac2_adj_tiles(m, ns, k, m->tiles_near, m->n_near, dJdd, gwav, snap1, s);
+    if (nodes) gather(k);
     Ac2Adj2Args b{};
     b.g = m->L.g2;
     b.nshots = ns;
@@ -750,6 +811,7 @@ void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, 
     launch_ac2_adj2(b, s);
     ac2_phi_adj(m, ns, k - 1, s);
     ac2_adj_tiles(m, ns, k - 1, m->tiles_near, m->n_near, dJdd, gwav, snap0, s);
+    if (nodes) gather(k - 1);
 }
 
 // One adjoint step k of the 3-D acoustic or 2-D elastic recursion:
@@ -908,6 +970,9 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         m->n_store = (int)std::min<size_t>(extra / per, (size_t)L.nseg);
         m->store = m->n_store > 0 ? reinterpret_cast<float *>(m->ws + L.total) : nullptr;
     }
+    m->src_off = reinterpret_cast<int *>(m->ws + L.off_soff);
+    m->src_ent = reinterpret_cast<int *>(m->ws + L.off_sent);
+    m->node_f = reinterpret_cast<long long *>(m->ws + L.off_nodef);
     m->ckpt = reinterpret_cast<float *>(m->ws + L.off_ckpt);
     m->snap = reinterpret_cast<float *>(m->ws + L.off_snap);
     m->grad = reinterpret_cast<float *>(m->ws + L.off_grad);

@@ -61,6 +61,11 @@ struct Ac2FwdArgs {
     float *seis;            // [shot][nt][nrec] or null
     int nrec;
     float *snap;            // w~^k [shot][plane] of this step, or null
+    // several source nodes per shot (nsrc > 1; src_f is then -1): CSR over
+    // tiles per shot of packed (local tile cell << 8 | node), wavelets [shot][nsrc][nt]
+    int nsrc;
+    const int *src_off;     // [shot][ntiles + 1]
+    const int *src_ent;
 };
 
 // Adjoint pass A: c^{k+1} = p c^{k+2} - q D~(chat s^{k+2}) on the layer cells.
@@ -140,6 +145,9 @@ struct Ac2Adj2Args {
 // Halo of a blocked tile: its cells within BLK_HALO of the tile must be physical.
 constexpr int BLK_HALO = 8;
 
+// Adjoint of several source nodes: gw[shot][j][k] = scale * s^{k+1}[node j].
+void launch_ac2_src_gather(int nshots, int nsrc, long long plane, const long long *node_f, const float *s1,
+                           float *gw, int nt, int k, float scale, hipStream_t s);
 void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s);
 void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s);
 void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s);

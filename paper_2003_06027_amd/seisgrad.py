@@ -23,7 +23,8 @@ _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_E
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
-           "set_time_blocking", "snapshot_segment_bytes", "lbfgs_push", "lbfgs_direction")
+           "set_time_blocking", "snapshot_segment_bytes", "lbfgs_push", "lbfgs_direction",
+           "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad")
 
 
 class SeisError(RuntimeError):
@@ -41,7 +42,7 @@ class SgDesc(C.Structure):
 
 class SgShots(C.Structure):
     _fields_ = [("nshots", C.c_int32), ("nrec", C.c_int32), ("src", C.c_void_p),
-                ("rec", C.c_void_p), ("wavelet", C.c_void_p), ("mt", C.c_void_p)]
+                ("rec", C.c_void_p), ("wavelet", C.c_void_p), ("mt", C.c_void_p), ("nsrc", C.c_int32)]
 
 
 _lib = None
@@ -74,6 +75,11 @@ def lib():
         v = C.c_void_p
         L.lbfgs_push.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v, v, v]
         L.lbfgs_direction.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v]
+        i32, d = C.c_int32, C.c_double
+        L.source_gaussian.argtypes = [i32, i32, v, d, d, d, d, v, v, v]
+        L.source_gaussian_grad.argtypes = [i32, i32, v, d, d, d, d, v, v, v, v, v]
+        L.source_rupture.argtypes = [i32, i32, v, v, d, d, v, v]
+        L.source_rupture_grad.argtypes = [i32, i32, v, v, d, d, v, v, v, v]
         L.phase_times.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         _lib = L
     return _lib
@@ -134,16 +140,19 @@ class Shots:
     wavelet of one batch of shots."""
 
     def __init__(self, src, rec, wavelet, mt=None):
+        """src [nshots][ndim] (one point source per shot) or [nshots][nsrc][ndim]
+        (several source nodes, 2-D acoustic; wavelet then [nshots][nsrc][nt])."""
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.rec = np.ascontiguousarray(rec, dtype=np.int32)
-        assert self.src.ndim == 2 and self.rec.ndim == 3 and self.rec.shape[0] == self.src.shape[0]
+        assert self.src.ndim in (2, 3) and self.rec.ndim == 3 and self.rec.shape[0] == self.src.shape[0]
+        self.nsrc = self.src.shape[1] if self.src.ndim == 3 else 1
         self.wavelet = wavelet.contiguous()
         self.mt = None if mt is None else np.ascontiguousarray(mt, dtype=np.float32)
         self.nshots, self.nrec = self.rec.shape[0], self.rec.shape[1]
 
     def struct(self):
         return SgShots(self.nshots, self.nrec, self.src.ctypes.data, self.rec.ctypes.data,
-                       self.wavelet.data_ptr(), None if self.mt is None else self.mt.ctypes.data)
+                       self.wavelet.data_ptr(), None if self.mt is None else self.mt.ctypes.data, self.nsrc)
 
 
 class Model:
