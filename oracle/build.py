@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["common.c", "ac2.c", "ac3.c", "el2.c"]
+SOURCES = ["common.c", "ac2.c", "ad2.c", "ac3.c", "el2.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

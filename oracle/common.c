@@ -51,6 +51,25 @@ void or_zeta_profile(const or_grid *g, int n, double *zeta)
     }
 }
 
+/* CPML profile at position x (in cells, padded coordinates) on an axis with
+ * n physical cells: distance into the layer measured from the physical edge
+ * nodes (index P and P+n-1). */
+void or_cpml_at(const or_grid *g, int n, double x, double *a, double *b)
+{
+    const int P = g->npml;
+    double dist = 0.0;
+    if (x < P) dist = P - x;
+    else if (x > P + n - 1) dist = x - (P + n - 1);
+    if (P == 0 || dist <= 0.0) { *a = 0.0; *b = 1.0; return; }
+    const double L = P * g->dx;
+    const double d0 = 3.0 * g->pml_vmax * log(1.0 / g->pml_R) / (2.0 * L);
+    double r = dist / P;
+    if (r > 1.0) r = 1.0;
+    const double d = d0 * r * r, al = M_PI * g->f0_pml * (1.0 - r);
+    *b = exp(-(d + al) * g->dt);
+    *a = d * (*b - 1.0) / (d + al);
+}
+
 int or_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 /* L2 misfit of the paper's Method section: J = 1/2 sum (pred - obs)^2. */

@@ -96,25 +96,6 @@ static void clear_ghosts(const el_ctx *c, double *a)
             if (iz < G || iz >= c->NZ + G || ix < G || ix >= c->NX + G) a[(long)iz * c->SX + ix] = 0.0;
 }
 
-/* CPML profile at position x (in cells, padded coordinates) on an axis with
- * n physical cells: distance into the layer measured from the physical edge
- * nodes (index P and P+n-1). */
-static void cpml_at(const or_grid *g, int n, double x, double *a, double *b)
-{
-    const int P = g->npml;
-    double dist = 0.0;
-    if (x < P) dist = P - x;
-    else if (x > P + n - 1) dist = x - (P + n - 1);
-    if (P == 0 || dist <= 0.0) { *a = 0.0; *b = 1.0; return; }
-    const double L = P * g->dx;
-    const double d0 = 3.0 * g->pml_vmax * log(1.0 / g->pml_R) / (2.0 * L);
-    double r = dist / P;
-    if (r > 1.0) r = 1.0;
-    const double d = d0 * r * r, al = M_PI * g->f0_pml * (1.0 - r);
-    *b = exp(-(d + al) * g->dt);
-    *a = d * (*b - 1.0) / (d + al);
-}
-
 static void ctx_init(el_ctx *c, const or_grid *g)
 {
     c->nx = g->nx; c->nz = g->nz; c->P = g->npml;
@@ -125,8 +106,8 @@ static void ctx_init(el_ctx *c, const or_grid *g)
     for (int h = 0; h < 2; ++h) {
         c->ax[h] = malloc(sizeof(double) * c->NX); c->bx[h] = malloc(sizeof(double) * c->NX);
         c->az[h] = malloc(sizeof(double) * c->NZ); c->bz[h] = malloc(sizeof(double) * c->NZ);
-        for (int i = 0; i < c->NX; ++i) cpml_at(g, g->nx, i + 0.5 * h, &c->ax[h][i], &c->bx[h][i]);
-        for (int i = 0; i < c->NZ; ++i) cpml_at(g, g->nz, i + 0.5 * h, &c->az[h][i], &c->bz[h][i]);
+        for (int i = 0; i < c->NX; ++i) or_cpml_at(g, g->nx, i + 0.5 * h, &c->ax[h][i], &c->bx[h][i]);
+        for (int i = 0; i < c->NZ; ++i) or_cpml_at(g, g->nz, i + 0.5 * h, &c->az[h][i], &c->bz[h][i]);
     }
 }
 

@@ -113,6 +113,29 @@ int or_ac2_gradient(const or_grid *g, const double *c, int32_t nshots,
 /* L2 misfit J = 1/2 sum (pred - obs)^2 and residual r = pred - obs. */
 double or_misfit(const double *pred, const double *obs, int64_t n, double *resid);
 
+/* ---------------- acoustic, 2-D, divergence form ---------------- */
+/* u_tt = div(c^2 grad u) + f on the staggered grid with CPML (see ad2.c for
+ * the scheme).  Padded NZ*NX arrays; state X = (u^k, u^{k-1}, psix, psiz,
+ * xix, xiz), 6 fields back to back.  kx, kz: the half-node coefficients
+ * (c_i^2 + c_{i+1}^2)/2 of the padded model. */
+void or_ad2_coefficients(const or_grid *g, const double *c, double *kx, double *kz);
+void or_ad2_step(const or_grid *g, const double *c, const double *X, int64_t src_idx, double src_val,
+                 double *Y);
+/* Exact transpose of the step's linear part (source excluded) at the state
+ * X: aX from aY; gkx, gkz receive this step's dJ/dkx, dJ/dkz. */
+void or_ad2_step_T(const or_grid *g, const double *c, const double *X, const double *aY, double *aX,
+                   double *gkx, double *gkz);
+/* nshots shots of nsrc source nodes each: src [nshots][nsrc][2], wav
+ * [nshots][nsrc][nt] (node j injects dt^2 wav_j(t_k)/(dx dz) into u^{k+1}),
+ * rec [nshots][nrec][2], seis [nshots][nt][nrec]. */
+int or_ad2_forward(const or_grid *g, const double *c, int32_t nshots, int32_t nsrc, const int32_t *src,
+                   const double *wav, int32_t nrec, const int32_t *rec, double *seis);
+/* dJ/dc (nz*nx), optional seismograms and dJ/dwav [nshots][nsrc][nt] for
+ * the seismogram adjoint dJdd [nshots][nt][nrec]; ckpt as for or_ac2_gradient. */
+int or_ad2_gradient(const or_grid *g, const double *c, int32_t nshots, int32_t nsrc, const int32_t *src,
+                    const double *wav, int32_t nrec, const int32_t *rec, const double *dJdd, int32_t ckpt,
+                    double *grad_c, double *seis, double *grad_wav);
+
 /* ---------------- acoustic, 3-D ---------------- */
 void or_ac3_pad(const or_grid *g, const double *c, double *c_pad,
                 double *zeta_x, double *zeta_y, double *zeta_z);

@@ -152,6 +152,66 @@ def ac2_gradient_ms(g, c, src, wav, rec, dJdd, ckpt=0):
     return grad, seis, gw
 
 
+# ------------------------------------------------ acoustic 2-D, divergence form
+def ad2_coefficients(g, c):
+    """Half-node coefficients (kx, kz) of the padded model, each (NZ, NX)."""
+    P = g.npml
+    kx, kz = np.zeros((g.nz + 2 * P, g.nx + 2 * P)), np.zeros((g.nz + 2 * P, g.nx + 2 * P))
+    lib().or_ad2_coefficients(C.byref(g), _d(_f64(c)), _d(kx), _d(kz))
+    return kx, kz
+
+
+def ad2_step(g, c, X, src_idx=-1, src_val=0.0):
+    """X: (6, NZ, NX) state (u, um, psix, psiz, xix, xiz) -> next state."""
+    X = _f64(X)
+    Y = np.zeros_like(X)
+    lib().or_ad2_step(C.byref(g), _d(_f64(c)), _d(X), C.c_int64(src_idx), C.c_double(src_val), _d(Y))
+    return Y
+
+
+def ad2_step_T(g, c, X, aY):
+    """Transpose of the step at state X: (aX, dJ/dkx, dJ/dkz)."""
+    X, aY = _f64(X), _f64(aY)
+    aX = np.zeros_like(X)
+    gkx, gkz = np.zeros_like(X[0]), np.zeros_like(X[0])
+    lib().or_ad2_step_T(C.byref(g), _d(_f64(c)), _d(X), _d(aY), _d(aX), _d(gkx), _d(gkz))
+    return aX, gkx, gkz
+
+
+def _ad2_geom(src, rec, wav):
+    src, rec, wav = _i32(src), _i32(rec), _f64(wav)
+    if src.ndim == 2:                       # one node per shot
+        src, wav = src[:, None], wav[:, None]
+    return src, rec, wav
+
+
+def ad2_forward(g, c, src, wav, rec):
+    """src [ns][nsrc][2] (or [ns][2]), wav [ns][nsrc][nt] (or [ns][nt]) -> seis [ns][nt][nrec]."""
+    src, rec, wav = _ad2_geom(src, rec, wav)
+    ns, nsrc, nrec = src.shape[0], src.shape[1], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    rc = lib().or_ad2_forward(C.byref(g), _d(_f64(c)), C.c_int32(ns), C.c_int32(nsrc), _i(src), _d(wav),
+                              C.c_int32(nrec), _i(rec), _d(seis))
+    if rc:
+        raise ValueError("oracle: invalid geometry or grid")
+    return seis
+
+
+def ad2_gradient(g, c, src, wav, rec, dJdd, ckpt=0):
+    """(dJ/dc, seismograms, dJ/dwav [ns][nsrc][nt])."""
+    src, rec, wav = _ad2_geom(src, rec, wav)
+    ns, nsrc, nrec = src.shape[0], src.shape[1], rec.shape[1]
+    seis = np.zeros((ns, g.nt, nrec))
+    grad = np.zeros((g.nz, g.nx))
+    gw = np.zeros((ns, nsrc, g.nt))
+    rc = lib().or_ad2_gradient(C.byref(g), _d(_f64(c)), C.c_int32(ns), C.c_int32(nsrc), _i(src), _d(wav),
+                               C.c_int32(nrec), _i(rec), _d(_f64(dJdd)), C.c_int32(ckpt),
+                               _d(grad), _d(seis), _d(gw))
+    if rc:
+        raise ValueError("oracle: invalid geometry or grid")
+    return grad, seis, gw
+
+
 def misfit(pred, obs):
     pred, obs = _f64(pred), _f64(obs)
     r = np.zeros_like(pred)

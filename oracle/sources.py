@@ -64,3 +64,19 @@ def rupture_grad(gw, A0, t0, sigma_t, dt):
     A0, t0 = np.asarray(A0, dtype=np.float64), np.asarray(t0, dtype=np.float64)
     e = np.exp(-(t[None, :] - t0[:, None]) ** 2 / (2 * sigma_t ** 2))
     return (gw * e).sum(1), (gw * A0[:, None] * e * (t[None, :] - t0[:, None]) / sigma_t ** 2).sum(1)
+
+
+def plane_wave_wavelets(xs, theta_deg, c, f0, t0, dt, nt):
+    """A row of source nodes at horizontal positions xs (metres) emitting a
+    plane wave at angle theta from the vertical (the bottom-incident plane
+    waves of the paper's layered-model inversion): node j fires the Ricker
+    r(t - tau_j), tau_j = (x_j - x_ref) sin(theta) / c, with x_ref the first
+    node to fire (all delays >= 0).  Positive theta: the front reaches small
+    x first and travels towards +x."""
+    xs = np.asarray(xs, dtype=np.float64)
+    s = np.sin(np.radians(theta_deg))
+    x_ref = xs.min() if s >= 0 else xs.max()
+    tau = (xs - x_ref) * s / c
+    t = np.arange(nt) * dt
+    a = (np.pi * f0 * (t[None, :] - t0 - tau[:, None])) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
