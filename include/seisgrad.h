@@ -7,7 +7,13 @@
  *     (Method, "Relationship to the Adjoint Method", Eq. (1)) for the
  *     acoustic wave equation (Implementation, Eq. (11), constant-density form
  *     u_tt = c^2 lap(u) + f, 2nd order in time, 8th order in space) with an
- *     auxiliary-field absorbing layer (PML) padded outside the model;
+ *     auxiliary-field absorbing layer (PML) padded outside the model; and the
+ *     same equation in the divergence form printed in Eq. (11),
+ *     u_tt = div(c^2 grad u) + f (physics SG_ACOUSTIC_DIV, 2-D): the
+ *     staggered grid with a convolutional PML of the Implementation section,
+ *     4th order in space, flux coefficients c^2 averaged onto the half nodes
+ *     ((c_i^2 + c_{i+1}^2)/2), a CPML memory variable on both the inner and
+ *     the outer derivative of each axis;
  *   - point-source injection of a wavelet and receiver gathering (the F_k
  *     and the observation operator of the misfit);
  *   - the L2 misfit J = 1/2 sum ||d - d_obs||^2 (display after Eq. (1)) on
@@ -80,12 +86,14 @@ enum {
     SG_EUNSUPPORTED = -6 /* a physics / dimension combination this build does not provide */
 };
 
-enum { SG_ACOUSTIC = 0, SG_ELASTIC = 1 };
+/* SG_ACOUSTIC: u_tt = c^2 lap(u) + f (2-D, 3-D); SG_ELASTIC: velocity-stress
+ * equations (2-D); SG_ACOUSTIC_DIV: u_tt = div(c^2 grad u) + f (2-D). */
+enum { SG_ACOUSTIC = 0, SG_ELASTIC = 1, SG_ACOUSTIC_DIV = 2 };
 
 /* Grid, time stepping and absorbing layer. */
 typedef struct sg_desc {
     int32_t ndim;       /* 2 or 3 */
-    int32_t physics;    /* SG_ACOUSTIC */
+    int32_t physics;    /* SG_ACOUSTIC, SG_ELASTIC or SG_ACOUSTIC_DIV */
     int32_t nx, ny, nz; /* physical cells; ny = 1 in 2-D */
     int32_t npml;       /* absorbing-layer width in cells (>= 0) */
     int32_t nt;         /* time steps (>= 1) */
@@ -94,11 +102,12 @@ typedef struct sg_desc {
     double dt;          /* time step (s) */
     double pml_R;       /* target reflection coefficient, e.g. 1e-3 */
     double pml_vmax;    /* reference velocity of the damping profile (m/s) */
-    double f0_pml;      /* reserved (elastic CPML frequency) */
+    double f0_pml;      /* CPML frequency of the staggered-grid forms (alpha = pi f0_pml (1 - x/L));
+                           unused by SG_ACOUSTIC */
 } sg_desc;
 
 /* One batch of shots. */
-#define SG_MAX_SRC 64    /* source cells per shot */
+#define SG_MAX_SRC 4096  /* source nodes per shot */
 
 typedef struct sg_shots {
     int32_t nshots;          /* >= 1, multiple of nmodels, <= max_shots of the model */
@@ -112,9 +121,11 @@ typedef struct sg_shots {
                                 acoustic shots */
     int32_t nsrc;            /* source nodes per shot: 0 or 1 = one point source; up to
                                 SG_MAX_SRC nodes, each with its own wavelet, for the 2-D
-                                acoustic equation only (the Gaussian-footprint location
+                                acoustic equations only (the Gaussian-footprint location
                                 source and the multi-point rupture of the paper's source
-                                applications); other physics return SG_EUNSUPPORTED */
+                                applications, a row of delayed wavelets for the
+                                bottom-incident plane waves of its layered-model
+                                inversion); other physics return SG_EUNSUPPORTED */
 } sg_shots;
 
 typedef struct sg_model sg_model;
@@ -132,9 +143,10 @@ SG_API size_t snapshot_segment_bytes(const sg_desc *d, int32_t max_shots, int32_
 
 /* Prepare a model (paper: the parameter theta of A(theta), Eq. (1); here the
  * velocity c of Eq. (11)): validate the descriptor, check stability
- * (8th-order leapfrog limit c dt/dx <= 2/sqrt(6.5016 ndim), rejected above
- * 0.95 of it), pad the velocity by edge replication, form C = dt^2 c^2 on the
- * padded grid and the damping tables.
+ * (8th-order leapfrog limit c dt/dx <= 2/sqrt(6.5016 ndim); staggered 4th
+ * order, elastic and SG_ACOUSTIC_DIV: c dt/dx <= 1/(sqrt(ndim) (9/8 + 1/24));
+ * rejected above 0.95 of the limit), pad the velocity by edge replication,
+ * form C = dt^2 c^2 on the padded grid and the damping tables.
  *   vp:  DEVICE FP32 [nmodels][nz]([ny])[nx] velocity (m/s), > 0;
  *   vs, rho: elastic only, DEVICE FP32 like vp (0 < vs < vp, rho > 0);
  *        NULL for acoustic models;
@@ -261,6 +273,20 @@ SG_API int source_rupture(int32_t npt, int32_t nt, const float *A0, const float 
                           float *wav, sg_stream_t stream);
 SG_API int source_rupture_grad(int32_t npt, int32_t nt, const float *A0, const float *t0, double sigma_t, double dt,
                                const float *gw, double *dA0, double *dt0, sg_stream_t stream);
+
+/* Bottom-incident plane wave (Applications, FWI: the layered model is probed
+ * by plane waves arriving from below at -30, -10, 10 and 30 degrees, with a
+ * Ricker source time function): a row of n source nodes at
+ * x_j = x_first + j spacing (metres) firing the Ricker wavelet
+ * r(t) = (1 - 2 a) exp(-a), a = (pi f0 (t - t0 - tau_j))^2, with delays
+ * tau_j = (x_j - x_ref) sin(theta)/c, x_ref the first node to fire, so that
+ * the row emits a front travelling at theta from the vertical through a
+ * medium of velocity c (positive theta: towards +x).
+ *   wav: DEVICE FP32 [n][nt] (a shot's wavelets for its n row nodes),
+ *   computed in FP64.  Errors: SG_EINVAL unless n, nt >= 1, c, f0, dt > 0
+ *   and |theta_deg| < 90. */
+SG_API int source_plane_wave(int32_t n, int32_t nt, double x_first, double spacing, double theta_deg, double c,
+                             double f0, double t0, double dt, float *wav, sg_stream_t stream);
 
 /* Release the host object (the workspace stays the caller's). */
 SG_API int free_model(sg_model *m);

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libseisgrad.so")
-SOURCES = ["seisgrad.hip", "ac2.hip", "ac3.hip", "el2.hip", "util.hip", "cnn.hip", "lbfgs.hip", "sources.hip"]
+SOURCES = ["seisgrad.hip", "ac2.hip", "ad2.hip", "ac3.hip", "el2.hip", "util.hip", "cnn.hip", "lbfgs.hip", "sources.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -164,8 +164,8 @@ __device__ __forceinline__ float node_sources(const Ac2FwdArgs &a, int tile, int
     float v = 0.f;
     for (int e = off[tile]; e < off[tile + 1]; ++e) {
         const int ent = a.src_ent[e];
-        if ((ent >> 8) == cell)
-            v += a.src_scale * a.wav[((long long)shot * a.nsrc + (ent & 255)) * a.nt + a.k];
+        if (src_cell(ent) == cell)
+            v += a.src_scale * a.wav[((long long)shot * a.nsrc + src_node(ent)) * a.nt + a.k];
     }
     return v;
 }

@@ -1,0 +1,458 @@
+// ad2.hip -- gfx950 kernels of the 2-D acoustic equation in divergence form,
+// u_tt = div(c^2 grad u) + f (Eq. (11) as printed), on a staggered grid with
+// a convolutional PML, and its adjoint (Eqs. (4)-(5)).
+//
+// Scaled variables: chat = dt^2 c^2 / dx^2 at the nodes, khat = (chat_i +
+// chat_{i+1}) / 2 at the half nodes (a neighbour beyond the padded grid takes
+// the edge value, so chat is replicated one node beyond it), differences
+// without the 1/dx factor,
+//   Dp' u (i + 1/2) = 9/8 (u_{i+1} - u_i) - 1/24 (u_{i+2} - u_{i-1}),
+//   Dm' q (i)       = 9/8 (q_i - q_{i-1}) - 1/24 (q_{i+1} - q_{i-2}),
+// psi' = dx psi and xi' = dt^2 xi for the layer memories.  Forward step k,
+// one launch over (tile, shot):
+//   G' = Dp' u^k;   psi'^{k+1} = bh psi'^k + ah G';   S' = G' + psi'^{k+1}
+//   q' = khat S';   H' = Dm' q';   xi'^{k+1} = b xi'^k + a H'
+//   u^{k+1} = 2 u^k - u^{k-1} + H'x + xi'x + H'z + xi'z + dt^2/(dx dz) sum_j r_j(t_k)
+// Half-node values exist on [0, NX) x [0, NZ) only (zero beyond), so that
+// Dm'^T = -Dp'.  psi' is read in the halo and written by its owner, so it
+// alternates between two buffers; xi' is read only at its own node and is
+// updated in place.
+//
+// Adjoint launch k computes lambda^k = dJ/du^k.  The layer adjoints are
+// kept multiplied by their constant coefficients, Y = a dJ/dxi' (nodes) and
+// Z = ah dJ/dpsi' (half nodes), so they vanish outside the layer:
+//   Y^{k+1} = a lambda^{k+1} + b Y^{k+2};   Hb = lambda^{k+1} + Y^{k+1}
+//   qb = -Dp' Hb;  Sb = khat qb;  Z^{k+1} = ah Sb + bh Z^{k+2};  Gb = Sb + Z^{k+1}
+//   lambda^k = 2 lambda^{k+1} - lambda^{k+2} - Dm' Gbx - Dm' Gbz + R^T dJ/dd_{k-1}
+//   dJ/dkhat += qb S' (S' of forward step k, a snapshot)
+// Y and Z alternate between two buffers like psi'.
+#include <algorithm>
+#include "ad2_internal.h"
+
+namespace sg {
+namespace {
+
+constexpr int AH = 3;              // halo of the composite stencil Dm' khat Dp'
+constexpr int AW = TX + 2 * AH;    // node tile with halo: AR rows of AW
+constexpr int AR = TZ + 2 * AH;
+constexpr int QXW = TX + 3;        // x half nodes x0-2 .. x0+TX on each row of the tile
+constexpr int QZR = TZ + 3;        // z half nodes z0-2 .. z0+TZ on each column
+constexpr float S1 = (float)(9.0 / 8.0);
+constexpr float S2 = (float)(-1.0 / 24.0);
+
+__device__ __forceinline__ long long fr(const Grid2 &g, int iz, int ix)
+{
+    return (long long)(iz + OZ) * g.SX + ix + OX;
+}
+
+// 9/8 (c - b) - 1/24 (d - a) of four consecutive values: Dp' at i + 1/2
+// from (u_{i-1}, u_i, u_{i+1}, u_{i+2}), Dm' at i from (q_{i-2}, .., q_{i+1}).
+__device__ __forceinline__ float d4(float a, float b, float c, float d)
+{
+    return fmaf(S1, c - b, S2 * (d - a));
+}
+
+// Consecutive work ids on one XCD (workgroups are dealt to the 8 XCDs
+// round-robin), so that neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_id(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks / NXCD, rem = nblocks % NXCD;
+    const int x = b % NXCD, j = b / NXCD;
+    return x * per + min(x, rem) + j;
+}
+
+// Does the tile or its 3-node halo reach the absorbing layer or the edge of
+// the grid (layer memories, masks of the half-node range)?
+__device__ __forceinline__ bool near_edge(const Grid2 &g, int x0, int z0)
+{
+    return x0 - AH < g.P || x0 + TX + AH > g.P + g.nx || z0 - AH < g.P || z0 + TZ + AH > g.P + g.nz;
+}
+
+// acc[cell] = sum of val(entry) over the tile's entries [b, e) of each local
+// cell (acc: TX*TZ floats, zeroed here).  Entries are sorted by cell; the
+// first entry of each cell sums its run in entry order, so duplicates add up
+// deterministically.  Every thread of the block must call this.
+template <class CellOf, class ValOf>
+__device__ __forceinline__ void gather_entries(float *acc, const int *ent, int b, int e, CellOf cell_of, ValOf val_of)
+{
+    for (int i = threadIdx.x; i < TX * TZ; i += NTH) acc[i] = 0.f;
+    __syncthreads();
+    for (int i = b + (int)threadIdx.x; i < e; i += NTH) {
+        const int c = cell_of(ent[i]);
+        if (i > b && cell_of(ent[i - 1]) == c) continue;
+        float v = 0.f;
+        for (int j = i; j < e && cell_of(ent[j]) == c; ++j) v += val_of(ent[j]);
+        acc[c] = v;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ forward
+template <bool NEAR, bool SNAP, bool REC>
+__device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *qx, float *qz, int tile, int shot)
+{
+    const Grid2 &g = a.g;
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
+    const long long so = (long long)shot * g.plane;
+    const float *u = a.u + so;
+    const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < AR * AW; i += NTH) {
+        const int r = i / AW, c = i - r * AW;
+        su[i] = u[fr(g, z0 - AH + r, x0 - AH + c)];
+    }
+    __syncthreads();
+
+    // x fluxes at the half nodes ix + 1/2, ix = x0-2 .. x0+TX, of the tile's rows
+    for (int i = tid; i < TZ * QXW; i += NTH) {
+        const int r = i / QXW, h = i - r * QXW;
+        const int iz = z0 + r, ix = x0 - 2 + h;
+        const float *s = su + (r + AH) * AW + h;
+        const float G = d4(s[0], s[1], s[2], s[3]);
+        float q = 0.f;
+        if (!NEAR || (ix >= 0 && ix < g.NX)) {
+            const long long f = fr(g, iz, ix);
+            const bool own = h >= 2 && h < TX + 2 && iz < g.NZ;
+            float S = G;
+            if constexpr (NEAR) {
+                const float p = fmaf(a.t.bhx[ix], a.psx[so + f], a.t.ahx[ix] * G);
+                S = G + p;
+                if (own) a.psxn[so + f] = p;
+            }
+            if constexpr (SNAP) {
+                if (own) a.snx[so + f] = S;
+            }
+            q = 0.5f * (ch[f] + ch[f + 1]) * S;
+        }
+        qx[i] = q;
+    }
+    // z fluxes at the half nodes iz + 1/2, iz = z0-2 .. z0+TZ, of the tile's columns
+    for (int i = tid; i < QZR * TX; i += NTH) {
+        const int h = i / TX, c = i - h * TX;
+        const int iz = z0 - 2 + h, ix = x0 + c;
+        const float *s = su + h * AW + c + AH;
+        const float G = d4(s[0], s[AW], s[2 * AW], s[3 * AW]);
+        float q = 0.f;
+        if (!NEAR || (iz >= 0 && iz < g.NZ)) {
+            const long long f = fr(g, iz, ix);
+            const bool own = h >= 2 && h < TZ + 2 && ix < g.NX;
+            float S = G;
+            if constexpr (NEAR) {
+                const float p = fmaf(a.t.bhz[iz], a.psz[so + f], a.t.ahz[iz] * G);
+                S = G + p;
+                if (own) a.pszn[so + f] = p;
+            }
+            if constexpr (SNAP) {
+                if (own) a.snz[so + f] = S;
+            }
+            q = 0.5f * (ch[f] + ch[f + g.SX]) * S;
+        }
+        qz[i] = q;
+    }
+    __syncthreads();
+
+    const int lx = tid % TX, ly = tid / TX, ix = x0 + lx;
+    float uc[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) uc[j] = su[(ly * RPT + j + AH) * AW + lx + AH];
+    const int ntiles = g.ntx * g.ntz;
+    const int *soff = a.src_off + (long long)shot * (ntiles + 1);
+    const int sb = soff[tile], se = soff[tile + 1];
+    if (sb < se) {                       // uniform over the block
+        __syncthreads();                 // every thread has read its u^k
+        const float *w = a.wav + (long long)shot * a.nsrc * a.nt + a.k;
+        gather_entries(su, a.src_ent, sb, se, [](int e) { return src_cell(e); },
+                       [&](int e) { return a.src_scale * w[(long long)src_node(e) * a.nt]; });
+    }
+    float un[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j, iz = z0 + r;
+        const float *qa = qx + r * QXW + lx;
+        const float *qb = qz + r * TX + lx;
+        const float Hx = d4(qa[0], qa[1], qa[2], qa[3]);
+        const float Hz = d4(qb[0], qb[TX], qb[2 * TX], qb[3 * TX]);
+        un[j] = 0.f;
+        if (iz < g.NZ && ix < g.NX) {
+            const long long f = fr(g, iz, ix);
+            float inc = Hx + Hz;
+            if constexpr (NEAR) {
+                const float xx = fmaf(a.t.b0x[ix], a.xix[so + f], a.t.a0x[ix] * Hx);
+                const float xz = fmaf(a.t.b0z[iz], a.xiz[so + f], a.t.a0z[iz] * Hz);
+                a.xix[so + f] = xx;
+                a.xiz[so + f] = xz;
+                inc += xx + xz;
+            }
+            inc += uc[j] - a.um[so + f];
+            if (sb < se) inc += su[r * TX + lx];
+            const float v = uc[j] + inc;
+            a.un[so + f] = v;
+            un[j] = v;
+        }
+    }
+    if constexpr (REC) {
+        const int *off = a.rec_off + (long long)shot * (ntiles + 1);
+        const int b = off[tile], e = off[tile + 1];
+        if (b < e) {                     // uniform over the block
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) su[(ly * RPT + j) * TX + lx] = un[j];
+            __syncthreads();
+            for (int i = b + tid; i < e; i += NTH) {
+                const int ent = a.rec_ent[i];
+                a.seis[((long long)shot * a.nt + a.k) * a.nrec + rec_id(ent)] = su[rec_cell(ent)];
+            }
+        }
+    }
+}
+
+template <bool SNAP, bool REC>
+__global__ __launch_bounds__(NTH) void ad2_fwd_kernel(Ad2FwdArgs a)
+{
+    __shared__ float su[AR * AW];
+    __shared__ float qx[TZ * QXW];
+    __shared__ float qz[QZR * TX];
+    const int ntl = a.g.ntx * a.g.ntz;
+    const int w = xcd_id(ntl * a.nshots);
+    const int shot = w / ntl, tile = w - shot * ntl;
+    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
+    if (near_edge(a.g, tx * TX, tz * TZ)) fwd_tile<true, SNAP, REC>(a, su, qx, qz, tile, shot);
+    else                                  fwd_tile<false, SNAP, REC>(a, su, qx, qz, tile, shot);
+}
+
+// ------------------------------------------------------------------ adjoint
+template <bool NEAR, bool GRAD>
+__device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *hz, float *qx, float *qz, int tile,
+                                         int shot)
+{
+    const Grid2 &g = a.g;
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
+    const long long so = (long long)shot * g.plane;
+    const float *l1 = a.l1 + so;
+    const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const int tid = threadIdx.x;
+
+    // Hb = lambda^{k+1} + Y^{k+1} per axis on the tile and its halo
+    for (int i = tid; i < AR * AW; i += NTH) {
+        const int r = i / AW, c = i - r * AW;
+        const int iz = z0 - AH + r, ix = x0 - AH + c;
+        const long long f = fr(g, iz, ix);
+        const float l = l1[f];
+        if constexpr (NEAR) {
+            float bx = l, bz = l;
+            if (iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX) {
+                const float yx = fmaf(a.t.a0x[ix], l, a.t.b0x[ix] * a.yx[so + f]);
+                const float yz = fmaf(a.t.a0z[iz], l, a.t.b0z[iz] * a.yz[so + f]);
+                if (r >= AH && r < AH + TZ && c >= AH && c < AH + TX) {
+                    a.yxn[so + f] = yx;
+                    a.yzn[so + f] = yz;
+                }
+                bx = l + yx;
+                bz = l + yz;
+            }
+            hx[i] = bx;
+            hz[i] = bz;
+        } else {
+            hx[i] = l;
+        }
+    }
+    __syncthreads();
+    const float *hzz = NEAR ? hz : hx;
+
+    for (int i = tid; i < TZ * QXW; i += NTH) {
+        const int r = i / QXW, h = i - r * QXW;
+        const int iz = z0 + r, ix = x0 - 2 + h;
+        const float *s = hx + (r + AH) * AW + h;
+        const float qb = -d4(s[0], s[1], s[2], s[3]);
+        float Gb = 0.f;
+        if (!NEAR || (ix >= 0 && ix < g.NX)) {
+            const long long f = fr(g, iz, ix);
+            const bool own = h >= 2 && h < TX + 2 && iz < g.NZ;
+            const float Sb = 0.5f * (ch[f] + ch[f + 1]) * qb;
+            Gb = Sb;
+            if constexpr (NEAR) {
+                const float z = fmaf(a.t.ahx[ix], Sb, a.t.bhx[ix] * a.zx[so + f]);
+                Gb = Sb + z;
+                if (own) a.zxn[so + f] = z;
+            }
+            if constexpr (GRAD) {
+                if (own) a.gkx[so + f] += qb * a.snx[so + f];
+            }
+        }
+        qx[i] = Gb;
+    }
+    for (int i = tid; i < QZR * TX; i += NTH) {
+        const int h = i / TX, c = i - h * TX;
+        const int iz = z0 - 2 + h, ix = x0 + c;
+        const float *s = hzz + h * AW + c + AH;
+        const float qb = -d4(s[0], s[AW], s[2 * AW], s[3 * AW]);
+        float Gb = 0.f;
+        if (!NEAR || (iz >= 0 && iz < g.NZ)) {
+            const long long f = fr(g, iz, ix);
+            const bool own = h >= 2 && h < TZ + 2 && ix < g.NX;
+            const float Sb = 0.5f * (ch[f] + ch[f + g.SX]) * qb;
+            Gb = Sb;
+            if constexpr (NEAR) {
+                const float z = fmaf(a.t.ahz[iz], Sb, a.t.bhz[iz] * a.zz[so + f]);
+                Gb = Sb + z;
+                if (own) a.zzn[so + f] = z;
+            }
+            if constexpr (GRAD) {
+                if (own) a.gkz[so + f] += qb * a.snz[so + f];
+            }
+        }
+        qz[i] = Gb;
+    }
+    __syncthreads();
+
+    const int ntiles = g.ntx * g.ntz;
+    const int *off = a.rec_off + (long long)shot * (ntiles + 1);
+    const int b = off[tile], e = off[tile + 1];
+    const bool inj = a.k >= 1 && b < e;  // uniform over the block
+    if (inj) {
+        const float *d = a.dJdd + ((long long)shot * a.nt + (a.k - 1)) * a.nrec;
+        gather_entries(hx, a.rec_ent, b, e, [](int en) { return rec_cell(en); },
+                       [&](int en) { return d[rec_id(en)]; });
+    }
+    const int lx = tid % TX, ly = tid / TX, ix = x0 + lx;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j, iz = z0 + r;
+        const float *ga = qx + r * QXW + lx;
+        const float *gb = qz + r * TX + lx;
+        const float Dx = d4(ga[0], ga[1], ga[2], ga[3]);
+        const float Dz = d4(gb[0], gb[TX], gb[2 * TX], gb[3 * TX]);
+        if (iz < g.NZ && ix < g.NX) {
+            const long long f = fr(g, iz, ix);
+            const float lc = l1[f];
+            float v = lc + ((lc - a.l2[so + f]) - (Dx + Dz));
+            if (inj) v += hx[r * TX + lx];
+            a.l0[so + f] = v;
+        }
+    }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(NTH) void ad2_adj_kernel(Ad2AdjArgs a)
+{
+    __shared__ float hx[AR * AW];
+    __shared__ float hz[AR * AW];
+    __shared__ float qx[TZ * QXW];
+    __shared__ float qz[QZR * TX];
+    const int ntl = a.g.ntx * a.g.ntz;
+    const int w = xcd_id(ntl * a.nshots);
+    const int shot = w / ntl, tile = w - shot * ntl;
+    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
+    if (near_edge(a.g, tx * TX, tz * TZ)) adj_tile<true, GRAD>(a, hx, hz, qx, qz, tile, shot);
+    else                                  adj_tile<false, GRAD>(a, hx, hz, qx, qz, tile, shot);
+}
+
+// ------------------------------------------------------------------ model and gradient
+__global__ void ad2_prep_kernel(Grid2 g, int nmodels, const float *vp, double dt, double dx, float *chat, float *cpad)
+{
+    const long long n = (long long)nmodels * g.plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / g.plane, f = i - m * g.plane;
+        const int iz = (int)(f / g.SX) - OZ, ix = (int)(f - (f / g.SX) * g.SX) - OX;
+        const bool in = iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX;
+        const bool rep = (ix == g.NX && iz >= 0 && iz < g.NZ) || (iz == g.NZ && ix >= 0 && ix < g.NX);
+        float c = 0.f, ch = 0.f;
+        if (in || rep) {
+            const int pz = min(max(min(iz, g.NZ - 1) - g.P, 0), g.nz - 1);
+            const int px = min(max(min(ix, g.NX - 1) - g.P, 0), g.nx - 1);
+            c = vp[(m * g.nz + pz) * g.nx + px];
+            const double cd = c;
+            ch = (float)(dt * dt * cd * cd / (dx * dx));
+        }
+        chat[i] = ch;
+        cpad[i] = in ? c : 0.f;
+    }
+}
+
+// dJ/dchat per padded node, summed over the model's shots in shot order:
+// khat_x(i) = (chat_i + chat_{i+1})/2 feeds nodes i and i+1 (node NX-1 twice,
+// its neighbour beyond the grid being its replica); z alike.
+__global__ void ad2_chat_grad_kernel(Grid2 g, int nmodels, int spm, const float *gkx, const float *gkz, float *acc)
+{
+    const long long n = (long long)nmodels * g.plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / g.plane, f = i - m * g.plane;
+        const int iz = (int)(f / g.SX) - OZ, ix = (int)(f - (f / g.SX) * g.SX) - OX;
+        float v = 0.f;
+        if (iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX) {
+            for (int s = 0; s < spm; ++s) {
+                const float *x = gkx + (m * spm + s) * g.plane, *z = gkz + (m * spm + s) * g.plane;
+                float t = (x[f] + x[f - 1]) + (z[f] + z[f - g.SX]);
+                if (ix == g.NX - 1) t += x[f];
+                if (iz == g.NZ - 1) t += z[f];
+                v += t;
+            }
+            v *= 0.5f;
+        }
+        acc[i] = v;
+    }
+}
+
+// dJ/dc per physical cell: the padded nodes replicating it, times
+// dchat/dc = 2 dt^2 c / dx^2.
+__global__ void ad2_fold_kernel(Grid2 g, int nmodels, const float *acc, const float *cpad, double dt, double dx,
+                                float *g_vp)
+{
+    const long long n = (long long)nmodels * g.nz * g.nx;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long m = i / ((long long)g.nz * g.nx);
+        const long long rem = i - m * g.nz * g.nx;
+        const int iz = (int)(rem / g.nx), ix = (int)(rem - (long long)iz * g.nx);
+        const int zlo = iz == 0 ? 0 : iz + g.P, zhi = iz == g.nz - 1 ? g.NZ - 1 : iz + g.P;
+        const int xlo = ix == 0 ? 0 : ix + g.P, xhi = ix == g.nx - 1 ? g.NX - 1 : ix + g.P;
+        const float *am = acc + m * g.plane;
+        float v = 0.f;
+        for (int pz = zlo; pz <= zhi; ++pz)
+            for (int px = xlo; px <= xhi; ++px) v += am[fr(g, pz, px)];
+        const double c = cpad[m * g.plane + fr(g, iz + g.P, ix + g.P)];
+        g_vp[i] = (float)(2.0 * dt * dt * c / (dx * dx)) * v;
+    }
+}
+
+int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 65536); }
+
+} // namespace
+
+void launch_ad2_fwd(const Ad2FwdArgs &a, hipStream_t s)
+{
+    const int n = a.g.ntx * a.g.ntz * a.nshots;
+    const bool rec = a.seis && a.nrec > 0;
+    if (a.snx) {
+        if (rec) ad2_fwd_kernel<true, true><<<n, NTH, 0, s>>>(a);
+        else     ad2_fwd_kernel<true, false><<<n, NTH, 0, s>>>(a);
+    } else {
+        if (rec) ad2_fwd_kernel<false, true><<<n, NTH, 0, s>>>(a);
+        else     ad2_fwd_kernel<false, false><<<n, NTH, 0, s>>>(a);
+    }
+}
+
+void launch_ad2_adj(const Ad2AdjArgs &a, hipStream_t s)
+{
+    const int n = a.g.ntx * a.g.ntz * a.nshots;
+    if (a.snx) ad2_adj_kernel<true><<<n, NTH, 0, s>>>(a);
+    else       ad2_adj_kernel<false><<<n, NTH, 0, s>>>(a);
+}
+
+void launch_ad2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx, float *chat, float *cpad,
+                     hipStream_t s)
+{
+    ad2_prep_kernel<<<blocks_for((long long)nmodels * g.plane), 256, 0, s>>>(g, nmodels, vp, dt, dx, chat, cpad);
+}
+
+void launch_ad2_finalize(const Grid2 &g, int nmodels, int spm, const float *gkx, const float *gkz, float *acc,
+                         const float *cpad, double dt, double dx, float *g_vp, hipStream_t s)
+{
+    ad2_chat_grad_kernel<<<blocks_for((long long)nmodels * g.plane), 256, 0, s>>>(g, nmodels, spm, gkx, gkz, acc);
+    ad2_fold_kernel<<<blocks_for((long long)nmodels * g.nz * g.nx), 256, 0, s>>>(g, nmodels, acc, cpad, dt, dx, g_vp);
+}
+
+} // namespace sg

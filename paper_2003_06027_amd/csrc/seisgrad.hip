@@ -8,6 +8,7 @@
 // (two-level checkpointing; memory O(nt/K + K) wavefields instead of O(nt)).
 #include "../../include/seisgrad.h"
 #include "sg_internal.h"
+#include "ad2_internal.h"
 #include "sg_error.h"
 
 #include <algorithm>
@@ -63,6 +64,7 @@ struct Layout {
     long long field;   // floats of one field over max_shots
     int n[3];          // padded extents x, y, z (y = 1 in 2-D)
     bool elastic;
+    bool ad2;          // 2-D acoustic in divergence form (staggered grid, CPML)
     int nsnap, ngrad, nmod; // snapshot fields per step, gradient accumulators, model fields
     int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
@@ -73,10 +75,12 @@ struct Layout {
 int check_desc(const sg_desc *d)
 {
     if (!d) return fail(SG_EINVAL, "descriptor is NULL");
-    if (d->physics != SG_ACOUSTIC && d->physics != SG_ELASTIC)
+    if (d->physics != SG_ACOUSTIC && d->physics != SG_ELASTIC && d->physics != SG_ACOUSTIC_DIV)
         return fail(SG_EUNSUPPORTED, "physics %d is not provided by this build", d->physics);
     if (d->ndim != 2 && d->ndim != 3) return fail(SG_EUNSUPPORTED, "ndim %d is not provided by this build", d->ndim);
     if (d->physics == SG_ELASTIC && d->ndim != 2) return fail(SG_EUNSUPPORTED, "elastic modelling is 2-D in this build");
+    if (d->physics == SG_ACOUSTIC_DIV && d->ndim != 2)
+        return fail(SG_EUNSUPPORTED, "the divergence-form acoustic equation is 2-D in this build");
     const int ny = d->ndim == 3 ? d->ny : 1;
     if (d->nx < 1 || d->nz < 1 || ny < 1 || d->npml < 0 || d->nt < 1 || d->nmodels < 1)
         return fail(SG_EINVAL, "bad grid: nx=%d ny=%d nz=%d npml=%d nt=%d nmodels=%d", d->nx, d->ny, d->nz,
@@ -95,6 +99,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     Layout L{};
     L.ndim = d->ndim;
     L.elastic = d->physics == SG_ELASTIC;
+    L.ad2 = d->physics == SG_ACOUSTIC_DIV;
     L.nsnap = 1;
     L.ngrad = 1;
     L.nmod = 2;            // chat, padded velocity
@@ -126,6 +131,14 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
         L.ntiles = g.ntx * g.ntz;
         L.nf = 4;
         L.nxs = 2;
+        if (L.ad2) {
+            // state u^k, u^{k-1}, psi'x, psi'z, xi'x, xi'z; the second psi' buffers
+            // (forward) and the adjoint's 10 fields use the extra slots
+            L.nf = 6;
+            L.nxs = 4;
+            L.nsnap = 2;   // S'x, S'z per step
+            L.ngrad = 2;   // dJ/dkhat at the x and z half nodes
+        }
         L.n[0] = g.NX; L.n[1] = 1; L.n[2] = g.NZ;
     } else {
         Grid3 &g = L.g3;
@@ -339,8 +352,9 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
     m->h_ent.clear();
     m->h_ent3.clear();
     std::vector<std::pair<long long, int>> keyed;
-    if (nsrc > 1) {
-        // several source nodes per shot: no fused point source; per (shot, tile)
+    if (nsrc > 1 || L.ad2) {
+        // several source nodes per shot (and every divergence-form shot): no
+        // fused point source; per (shot, tile)
         // lists of (local cell, node) and the frame index of every node
         const Grid2 &g = L.g2;
         m->h_soff.assign((size_t)ns * (ntiles + 1), 0);
@@ -352,7 +366,7 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
                 const int32_t *q = sh->src + ((size_t)i * nsrc + j) * 2;
                 const int px = q[0] + P, pz = q[1] + P;
                 m->h_nodef[(size_t)i * nsrc + j] = (long long)(pz + OZ) * g.SX + px + OX;
-                byt.push_back({(pz / TZ) * g.ntx + px / TX, (((pz % TZ) * TX + px % TX) << 8) | j});
+                byt.push_back({(pz / TZ) * g.ntx + px / TX, src_pack((pz % TZ) * TX + px % TX, j)});
             }
             std::sort(byt.begin(), byt.end());
             int *off = m->h_soff.data() + (size_t)i * (ntiles + 1);
@@ -370,7 +384,7 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
     }
     for (int i = 0; i < ns; ++i) {
         const int32_t *q = sh->src + (size_t)nd * nsrc * i;
-        if (nsrc > 1) {
+        if (nsrc > 1 || L.ad2) {
             m->h_src[i] = -1;
         } else if (nd == 2) {
             const Grid2 &g = L.g2;
@@ -595,6 +609,102 @@ void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwa
     }
     launch_el2_adj2(a, s);
     launch_el2_adj3(a, s);
+}
+
+// 2-D divergence form.  Forward: u^k in fwd[k & 1] (u^{k+1} overwrites
+// u^{k-1}), psi'x^k, psi'z^k in fwd[2 + (k & 1)], fwd[4 + (k & 1)], xi'x, xi'z
+// in fwd[6], fwd[7].  Adjoint: lambda^k in adj[k & 1], Y^k (x, z) in
+// adj[2 + (k & 1)], adj[4 + (k & 1)], Z^k in adj[6 + (k & 1)], adj[8 + (k & 1)].
+Ad2Cpml ad2_tabs(const sg_model *m)
+{
+    Ad2Cpml t;
+    t.a0x = m->cpml[0][0]; t.b0x = m->cpml[0][1]; t.ahx = m->cpml[0][2]; t.bhx = m->cpml[0][3];
+    t.a0z = m->cpml[1][0]; t.b0z = m->cpml[1][1]; t.ahz = m->cpml[1][2]; t.bhz = m->cpml[1][3];
+    return t;
+}
+
+// Field i of the checkpointed state at the start of step k:
+// (u^k, u^{k-1}, psi'x^k, psi'z^k, xi'x, xi'z).
+float *ad2_state(const sg_model *m, int k, int i)
+{
+    switch (i) {
+    case 0: return m->fwd[k & 1];
+    case 1: return m->fwd[(k + 1) & 1];
+    case 2: return m->fwd[2 + (k & 1)];
+    case 3: return m->fwd[4 + (k & 1)];
+    default: return m->fwd[i + 2];
+    }
+}
+
+void ad2_fwd_step(const sg_model *m, int ns, const float *wav, int k, float *seis, float *snap, hipStream_t s)
+{
+    Ad2FwdArgs a{};
+    a.g = m->L.g2;
+    a.nshots = ns;
+    a.shots_per_model = ns / m->d.nmodels;
+    a.u = m->fwd[k & 1];
+    a.um = m->fwd[(k + 1) & 1];
+    a.un = m->fwd[(k + 1) & 1];
+    a.psx = m->fwd[2 + (k & 1)];
+    a.psxn = m->fwd[2 + ((k + 1) & 1)];
+    a.psz = m->fwd[4 + (k & 1)];
+    a.pszn = m->fwd[4 + ((k + 1) & 1)];
+    a.xix = m->fwd[6];
+    a.xiz = m->fwd[7];
+    a.chat = m->chat;
+    a.t = ad2_tabs(m);
+    a.wav = wav;
+    a.nt = m->d.nt;
+    a.k = k;
+    a.nsrc = m->geom_nsrc;
+    a.src_scale = src_scale(m);
+    a.src_off = m->src_off;
+    a.src_ent = m->src_ent;
+    a.rec_off = m->rec_off;
+    a.rec_ent = static_cast<const int *>(m->rec_ent);
+    a.seis = seis;
+    a.nrec = m->geom_nrec;
+    a.snx = snap;
+    a.snz = snap ? snap + m->L.field : nullptr;
+    launch_ad2_fwd(a, s);
+}
+
+// Adjoint launch k (k = nt: lambda^nt from the last sample alone, no
+// gradient term); then dJ/dr_j(t_k) = dt^2/(dx dz) lambda^{k+1} at node j.
+void ad2_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwav, const float *snap,
+                  hipStream_t s)
+{
+    Ad2AdjArgs a{};
+    a.g = m->L.g2;
+    a.nshots = ns;
+    a.shots_per_model = ns / m->d.nmodels;
+    a.l1 = m->adj[(k + 1) & 1];
+    a.l2 = m->adj[k & 1];
+    a.l0 = m->adj[k & 1];
+    a.yx = m->adj[2 + (k & 1)];
+    a.yxn = m->adj[2 + ((k + 1) & 1)];
+    a.yz = m->adj[4 + (k & 1)];
+    a.yzn = m->adj[4 + ((k + 1) & 1)];
+    a.zx = m->adj[6 + (k & 1)];
+    a.zxn = m->adj[6 + ((k + 1) & 1)];
+    a.zz = m->adj[8 + (k & 1)];
+    a.zzn = m->adj[8 + ((k + 1) & 1)];
+    a.chat = m->chat;
+    a.t = ad2_tabs(m);
+    a.nt = m->d.nt;
+    a.k = k;
+    a.rec_off = m->rec_off;
+    a.rec_ent = static_cast<const int *>(m->rec_ent);
+    a.dJdd = dJdd;
+    a.nrec = m->geom_nrec;
+    a.snx = snap;
+    a.snz = snap ? snap + m->L.field : nullptr;
+    a.gkx = m->grad;
+    a.gkz = m->grad + m->L.field;
+    launch_ad2_adj(a, s);
+    if (gwav && k < m->d.nt)
+        launch_ac2_src_gather(ns, m->geom_nsrc, m->L.plane, m->node_f, m->adj[(k + 1) & 1], gwav, m->d.nt, k,
+                              src_scale(m), s);
 }
 
 // 2-D acoustic: u^t is slot u4[t % 4] and s^t is slot s4[t % 4], so one
@@ -929,7 +1039,10 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         for (size_t i = 0; i < nphys; ++i)
             if (!(hs[i] > 0) || !(hs[i] < hv[i]) || !(hr[i] > 0) || !std::isfinite(hr[i]))
                 return fail(SG_EINVAL, "elastic model needs 0 < vs < vp and rho > 0");
-        // 4th-order staggered leapfrog: vp dt/dx <= 1/(sqrt(ndim) (9/8 + 1/24))
+    }
+    if (elastic || L.ad2) {
+        // 4th-order staggered leapfrog: v dt/dx <= 1/(sqrt(ndim) (9/8 + 1/24))
+        // (divergence form: the half-node coefficient never exceeds vmax^2)
         const double limit = 1.0 / (std::sqrt((double)d->ndim) * (9.0 / 8.0 + 1.0 / 24.0));
         const double cfl = vmax * d->dt / d->dx;
         if (cfl > 0.95 * limit) return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
@@ -939,7 +1052,7 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         if (cfl > 0.95 * limit) return fail(SG_EUNSTABLE, "CFL number %.4f above 0.95 x %.4f", cfl, limit);
     }
     const double zmax = d->npml > 0 ? 3.0 * d->pml_vmax * std::log(1.0 / d->pml_R) / (2.0 * d->npml * d->dx) : 0.0;
-    if (!elastic && zmax * d->dt > 0.3) return fail(SG_EUNSTABLE, "zeta_max*dt = %.3f above 0.3", zmax * d->dt);
+    if (!elastic && !L.ad2 && zmax * d->dt > 0.3) return fail(SG_EUNSTABLE, "zeta_max*dt = %.3f above 0.3", zmax * d->dt);
 
     sg_model *m = new sg_model();
     m->d = *d;
@@ -950,16 +1063,18 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     m->ws = static_cast<char *>(ws);
     m->chat = reinterpret_cast<float *>(m->ws + L.off_chat);
     m->cpad = reinterpret_cast<float *>(m->ws + L.off_cpad);
-    for (int i = 0; i < L.nf; ++i) {
+    for (int i = 0; i < (L.ad2 ? L.nf + L.nxs : L.nf); ++i) {
         m->fwd[i] = reinterpret_cast<float *>(m->ws + L.off_fwd) + i * L.field;
         m->adj[i] = reinterpret_cast<float *>(m->ws + L.off_adj) + i * L.field;
     }
     if (!L.elastic && d->ndim == 2) {
-        float *fb = reinterpret_cast<float *>(m->ws + L.off_fwd), *ab = reinterpret_cast<float *>(m->ws + L.off_adj);
-        const int slot[4] = {0, 1, 4, 5};   // fields 2, 3 hold the layer auxiliaries
-        for (int i = 0; i < 4; ++i) {
-            m->u4[i] = fb + slot[i] * L.field;
-            m->s4[i] = ab + slot[i] * L.field;
+        if (!L.ad2) {
+            float *fb = reinterpret_cast<float *>(m->ws + L.off_fwd), *ab = reinterpret_cast<float *>(m->ws + L.off_adj);
+            const int slot[4] = {0, 1, 4, 5};   // fields 2, 3 hold the layer auxiliaries
+            for (int i = 0; i < 4; ++i) {
+                m->u4[i] = fb + slot[i] * L.field;
+                m->s4[i] = ab + slot[i] * L.field;
+            }
         }
         m->tiles_near = reinterpret_cast<int *>(m->ws + L.off_tiles);
         m->tiles_blk = m->tiles_near + L.ntiles;
@@ -992,13 +1107,14 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     // damping tables per axis, FP64 rounded once: h = zeta dt / 2,
     // p = (1-h)/(1+h), 1/(1+h); TABPAD neutral entries (h = 0) on each side
     const int phys[3] = {d->nx, d->ndim == 3 ? d->ny : 1, d->nz};
+    const bool cpml = elastic || L.ad2;   // the staggered-grid forms
     size_t tot = 0;
-    if (elastic) tot = 4 * (L.n[0] + L.n[2] + 4 * TABPAD);
+    if (cpml) tot = 4 * (L.n[0] + L.n[2] + 4 * TABPAD);
     else for (int a = 0; a < 3; ++a) tot += 3 * (L.n[a] + 2 * TABPAD);
     m->h_tab.assign(tot, 0.f);
     float *dev_tab = reinterpret_cast<float *>(m->ws + L.off_tab);
     size_t o = 0;
-    for (int a = 0; a < (elastic ? 0 : 3); ++a) {
+    for (int a = 0; a < (cpml ? 0 : 3); ++a) {
         const int N = L.n[a] + 2 * TABPAD;
         float *h = m->h_tab.data() + o, *p = h + N, *ih = p + N;
         for (int i = 0; i < N; ++i) {
@@ -1017,7 +1133,7 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         m->ih[a] = dev_tab + o + 2 * N + TABPAD;
         o += 3 * N;
     }
-    if (elastic) {
+    if (cpml) {
         // CPML (kappa = 1): b = exp(-(d + al) dt), a = d (b - 1)/(d + al),
         // d = d0 (x/L)^2, al = pi f0 (1 - x/L), d0 = 3 vmax ln(1/R)/(2L), at
         // integer and half positions; x = distance into the layer
@@ -1057,6 +1173,7 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         return fail(SG_EDEVICE, "upload failed: %s", hipGetErrorString(e));
     }
     if (elastic) launch_el2_prep(L.g2, d->nmodels, vp, vs, rho, m->model, m->model + 5, s);
+    else if (L.ad2) launch_ad2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
     else if (d->ndim == 2) launch_ac2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
     else launch_ac3_prep(L.g3, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
     e = hipGetLastError();
@@ -1081,8 +1198,9 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     const Layout &L = m->L;
     const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
     const long long fs = (long long)ns * L.plane;  // floats of one field over the batch
-    const bool ac2 = !L.elastic && m->d.ndim == 2;
-    for (int i = 0; i < nf; ++i) launch_fill(m->fwd[i], fs, 0.f, s);
+    const bool ad2 = L.ad2;
+    const bool ac2 = !L.elastic && !ad2 && m->d.ndim == 2;
+    for (int i = 0; i < (ad2 ? nf + L.nxs : nf); ++i) launch_fill(m->fwd[i], fs, 0.f, s);
     if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->u4[i], fs, 0.f, s);
     float *sp = sh->nrec > 0 ? seis : nullptr;
     // segments >= seg0 keep their adjoint snapshots (checkpointed forwards only)
@@ -1102,7 +1220,8 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
                 // (acoustic: u^k, u^{k-1} first; elastic: the fields in order)
                 float *ck = m->ckpt + (size_t)(k / K) * nf * L.field;
                 for (int i = 0; i < nf; ++i) {
-                    const float *src = L.elastic || i >= 2 ? m->fwd[i]
+                    const float *src = ad2 ? ad2_state(m, k, i)
+                                     : L.elastic || i >= 2 ? m->fwd[i]
                                      : ac2 ? m->u4[(k + 4 - i) & 3]
                                            : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
                     HIPCHECK(hipMemcpyAsync(ck + i * L.field, src, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
@@ -1115,6 +1234,9 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
             const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < std::min((k / K + 1) * K, nt);
             ac2_forward(m, ns, sh->wavelet, k, two, sp, stored(k), two ? stored(k + 1) : nullptr, s);
             k += two ? 2 : 1;
+        } else if (ad2) {
+            ad2_fwd_step(m, ns, sh->wavelet, k, sp, stored(k), s);
+            ++k;
         } else {
             fwd_step(m, ns, sh->wavelet, cu, k, sp, stored(k), s);
             cu = 1 - cu;
@@ -1156,12 +1278,14 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     const Layout &L = m->L;
     const int ns = sh->nshots, nt = m->d.nt, K = L.K, nf = L.nf;
     const long long fs = (long long)ns * L.plane;
-    const bool ac2 = !L.elastic && m->d.ndim == 2;
-    for (int i = 0; i < nf; ++i) launch_fill(m->adj[i], fs, 0.f, s);
+    const bool ad2 = L.ad2;
+    const bool ac2 = !L.elastic && !ad2 && m->d.ndim == 2;
+    for (int i = 0; i < (ad2 ? nf + L.nxs : nf); ++i) launch_fill(m->adj[i], fs, 0.f, s);
     if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->s4[i], fs, 0.f, s);
     for (int q = 0; q < L.ngrad; ++q) launch_fill(m->grad + q * L.field, fs, 0.f, s);
     if (L.elastic)
         for (int i = 0; i < 8; ++i) launch_fill(m->tmp[i], fs, 0.f, s);
+    if (ad2) ad2_adj_step(m, ns, nt, dJ_dd, nullptr, nullptr, s);   // lambda^nt
     int ca = 0;
     const int seg0 = m->have_store ? L.nseg - m->n_store : L.nseg;
     for (int seg = L.nseg - 1; seg >= 0; --seg) {
@@ -1174,7 +1298,7 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         if (!kept) {
             const float *ck = m->ckpt + (size_t)seg * nf * L.field;
             for (int i = 0; i < nf; ++i) {
-                float *dst = ac2 && i < 2 ? m->u4[(k0 + 4 - i) & 3] : m->fwd[i];
+                float *dst = ad2 ? ad2_state(m, k0, i) : ac2 && i < 2 ? m->u4[(k0 + 4 - i) & 3] : m->fwd[i];
                 HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
             }
             int cu = 0;
@@ -1184,6 +1308,9 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
                     const bool two = blk && k + 1 < k1;
                     ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
                     k += two ? 2 : 1;
+                } else if (ad2) {
+                    ad2_fwd_step(m, ns, sh->wavelet, k, nullptr, snap(k), s);
+                    ++k;
                 } else {
                     fwd_step(m, ns, sh->wavelet, cu, k, nullptr, snap(k), s);
                     cu = 1 - cu;
@@ -1198,6 +1325,9 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
                 const bool two = blk && k - 1 >= k0;
                 ac2_adjoint(m, ns, k, two, dJ_dd, g_wavelet, snap(k), two ? snap(k - 1) : nullptr, s);
                 k -= two ? 2 : 1;
+            } else if (ad2) {
+                ad2_adj_step(m, ns, k, dJ_dd, g_wavelet, snap(k), s);
+                --k;
             } else {
                 adj_step(m, ns, ca, k, dJ_dd, g_wavelet, snap(k), s);
                 ca = 1 - ca;
@@ -1209,6 +1339,9 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     if (L.elastic)
         launch_el2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, L.field, m->acc, m->model,
                             m->model + 5, g_vp, g_vs, g_rho, s);
+    else if (ad2)
+        launch_ad2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->grad + L.field, m->acc, m->cpad,
+                            m->d.dt, m->d.dx, g_vp, s);
     else if (m->d.ndim == 2)
         launch_ac2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     else

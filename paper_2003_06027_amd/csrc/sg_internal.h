@@ -62,7 +62,7 @@ struct Ac2FwdArgs {
     int nrec;
     float *snap;            // w~^k [shot][plane] of this step, or null
     // several source nodes per shot (nsrc > 1; src_f is then -1): CSR over
-    // tiles per shot of packed (local tile cell << 8 | node), wavelets [shot][nsrc][nt]
+    // tiles per shot of src_pack(local tile cell, node), wavelets [shot][nsrc][nt]
     int nsrc;
     const int *src_off;     // [shot][ntiles + 1]
     const int *src_ent;
@@ -170,6 +170,12 @@ constexpr int REC_ID_BITS = 20;
 __host__ __device__ inline int rec_pack(int cell, int id) { return (cell << REC_ID_BITS) | id; }
 __host__ __device__ inline int rec_cell(int e) { return e >> REC_ID_BITS; }
 __host__ __device__ inline int rec_id(int e) { return e & ((1 << REC_ID_BITS) - 1); }
+
+// source-node entry packing: local tile cell (< 2^11) and node index (< 2^12)
+constexpr int SRC_NODE_BITS = 12;
+__host__ __device__ inline int src_pack(int cell, int node) { return (cell << SRC_NODE_BITS) | node; }
+__host__ __device__ inline int src_cell(int e) { return e >> SRC_NODE_BITS; }
+__host__ __device__ inline int src_node(int e) { return e & ((1 << SRC_NODE_BITS) - 1); }
 
 
 // ---------------------------------------------------------------- 3-D

@@ -1,6 +1,7 @@
 // sources.hip -- the source parameterisations of the paper's source
 // applications (include/seisgrad.h: source_gaussian, source_gaussian_grad,
-// source_rupture, source_rupture_grad): wavelets of several source nodes from
+// source_rupture, source_rupture_grad) and the plane-wave row of the
+// layered-model inversion (source_plane_wave): wavelets of several source nodes from
 // a few parameters, and the chain rule from dJ/dwavelet (adjoint_gradient's
 // g_wavelet) back to those parameters.  Reductions over time steps and nodes
 // are FP64 in a fixed order.
@@ -112,9 +113,37 @@ __global__ __launch_bounds__(ST) void rupture_grad_kernel(int nt, const float *A
         if (e_ != hipSuccess) return fail(SG_EDEVICE, what ": %s", hipGetErrorString(e_)); \
     } while (0)
 
+// Row of nodes x_j = x_first + j spacing firing the Ricker wavelet with
+// delays tau_j = (x_j - x_ref) sin(theta) / c, x_ref the first node to fire.
+__global__ void plane_wave_kernel(int n, int nt, double x_first, double spacing, double s_over_c, double f0,
+                                  double t0, double dt, float *wav)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * nt) return;
+    const int j = (int)(i / nt), k = (int)(i - (long long)j * nt);
+    const double x_ref = s_over_c >= 0.0 ? x_first : x_first + (n - 1) * spacing;
+    const double tau = (x_first + j * spacing - x_ref) * s_over_c;
+    double a = M_PI * f0 * (k * dt - t0 - tau);
+    a *= a;
+    wav[i] = (float)((1.0 - 2.0 * a) * exp(-a));
+}
+
 } // namespace
 
 extern "C" {
+
+int source_plane_wave(int32_t n, int32_t nt, double x_first, double spacing, double theta_deg, double c, double f0,
+                      double t0, double dt, float *wav, sg_stream_t stream)
+{
+    if (n < 1 || nt < 1 || !(c > 0) || !(f0 > 0) || !(dt > 0) || !(std::fabs(theta_deg) < 90.0))
+        return fail(SG_EINVAL, "bad plane-wave arguments");
+    if (!wav) return fail(SG_EINVAL, "NULL pointer argument");
+    const long long m = (long long)n * nt;
+    plane_wave_kernel<<<(unsigned)((m + ST - 1) / ST), ST, 0, (hipStream_t)stream>>>(
+        n, nt, x_first, spacing, std::sin(theta_deg * M_PI / 180.0) / c, f0, t0, dt, wav);
+    LAUNCH_CHECK("source_plane_wave");
+    return SG_OK;
+}
 
 int source_gaussian(int32_t nsrc, int32_t nt, const int32_t *cells, double x0, double z0, double sigma, double dx,
                     const float *g, float *wav, sg_stream_t stream)

@@ -17,14 +17,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libseisgrad.so")
 
 SG_OK, SG_EINVAL, SG_EUNSTABLE, SG_ENOMEM, SG_ESTATE, SG_EDEVICE, SG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-SG_ACOUSTIC, SG_ELASTIC = 0, 1
+SG_ACOUSTIC, SG_ELASTIC, SG_ACOUSTIC_DIV = 0, 1, 2
 _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_ENOMEM",
           SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED"}
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
            "set_time_blocking", "snapshot_segment_bytes", "lbfgs_push", "lbfgs_direction",
-           "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad")
+           "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad",
+           "source_plane_wave")
 
 
 class SeisError(RuntimeError):
@@ -80,6 +81,7 @@ def lib():
         L.source_gaussian_grad.argtypes = [i32, i32, v, d, d, d, d, v, v, v, v, v]
         L.source_rupture.argtypes = [i32, i32, v, v, d, d, v, v]
         L.source_rupture_grad.argtypes = [i32, i32, v, v, d, d, v, v, v, v]
+        L.source_plane_wave.argtypes = [i32, i32, d, d, d, d, d, d, d, v, v]
         L.phase_times.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         _lib = L
     return _lib

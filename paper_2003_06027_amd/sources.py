@@ -1,5 +1,6 @@
 """Source applications of the paper (Applications: earthquake location with
-the source time function; rupture imaging) on the 2-D acoustic path.
+the source time function; rupture imaging) on the 2-D acoustic path, and
+the bottom-incident plane waves of its layered-model inversion.
 
 A shot may carry up to SG_MAX_SRC source nodes, each with its own wavelet;
 adjoint_gradient then returns dJ/dwavelet per node.  The two
@@ -59,6 +60,21 @@ def rupture_wavelets(A0, t0, sigma_t, dt, nt):
     wav = torch.empty((A0.numel(), nt), dtype=torch.float32, device=A0.device)
     S._check(S.lib().source_rupture(A0.numel(), nt, S._ptr(A0), S._ptr(t0), sigma_t, dt, S._ptr(wav), S._stream()))
     return wav
+
+
+def plane_wave(ix, iz, theta_deg, c, f0, t0, dx, dt, nt):
+    """Nodes and wavelets of one plane-wave shot: the row of nodes (ix[j], iz),
+    ix consecutive, firing the Ricker wavelet with delays
+    (x_j - x_ref) sin(theta)/c (library kernel source_plane_wave).
+    Returns (nodes int32 [n][2], wavelets DEVICE FP32 [n][nt])."""
+    ix = np.asarray(ix, dtype=np.int64)
+    if ix.ndim != 1 or len(ix) < 1 or np.any(np.diff(ix) != 1):
+        raise ValueError("plane-wave rows are consecutive nodes")
+    nodes = np.stack([ix, np.full_like(ix, iz)], 1).astype(np.int32)
+    wav = torch.empty((len(ix), nt), dtype=torch.float32, device="cuda")
+    S._check(S.lib().source_plane_wave(len(ix), nt, float(ix[0] * dx), float(dx), float(theta_deg), float(c),
+                                       float(f0), float(t0), float(dt), S._ptr(wav), S._stream()))
+    return nodes, wav
 
 
 def rupture_grad(A0, t0, sigma_t, dt, gw):

@@ -127,6 +127,31 @@ def dipping_layers_anomalies(seed: int = 2003, nx: int = 1000, nz: int = 500,
     return np.clip(v, 1500.0, 4500.0)
 
 
+def layered_ellipses(seed: int = 250, nx: int = 300, nz: int = 150, dx: float = 20.0, nlayers: int = 5,
+                     nellipses: int = 4) -> np.ndarray:
+    """A layered crust with embedded elliptical anomalies (stand-in for the
+    paper's second FWI model, whose parameters are not given): flat layers
+    with velocity increasing with depth (2500 -> 4500 m/s, random interface
+    depths), plus ellipses of +-8..15 % velocity contrast with random centres,
+    semi-axes and tilts, in the middle of the section."""
+    rng = np.random.default_rng(seed)
+    H, L = nz * dx, nx * dx
+    zi = np.sort(rng.uniform(0.15 * H, 0.9 * H, size=nlayers - 1))
+    vel = np.linspace(2500.0, 4500.0, nlayers) + rng.uniform(-100, 100, size=nlayers)
+    X = np.ones((nz, 1)) * (np.arange(nx) * dx)[None, :]
+    Z = (np.arange(nz) * dx)[:, None] * np.ones((1, nx))
+    v = vel[np.searchsorted(zi, Z)]
+    for _ in range(nellipses):
+        cx, cz = rng.uniform(0.2 * L, 0.8 * L), rng.uniform(0.3 * H, 0.75 * H)
+        a, b = rng.uniform(0.06 * L, 0.12 * L), rng.uniform(0.05 * H, 0.1 * H)
+        th = rng.uniform(-0.5, 0.5)
+        xr = (X - cx) * np.cos(th) + (Z - cz) * np.sin(th)
+        zr = -(X - cx) * np.sin(th) + (Z - cz) * np.cos(th)
+        inside = (xr / a) ** 2 + (zr / b) ** 2 <= 1.0
+        v = np.where(inside, v * (1.0 + rng.choice([-1.0, 1.0]) * rng.uniform(0.08, 0.15)), v)
+    return v
+
+
 def smooth_random(seed: int, shape, sigma: float, vmin: float, vmax: float) -> np.ndarray:
     """Gaussian-filtered N(0,1) noise mapped affinely onto [vmin, vmax]."""
     rng = np.random.default_rng(seed)
