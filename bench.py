@@ -52,6 +52,17 @@ def bytes_per_cell_step(pml_fraction):
     return {"forward": f, "recompute": f + 4.0, "adjoint": 28.0 + 16.0 * pml_fraction}
 
 
+def bytes_per_cell_step_div(pml_fraction):
+    """The same for the divergence form (staggered grid, CPML).  forward:
+    read u^k, u^{k-1}, chat, write u^{k+1} = 16 B; layer cells read and write
+    psi'x, psi'z, xi'x, xi'z (+32 B).  recompute: + the S'x, S'z snapshot
+    writes (+8 B).  adjoint: read lambda^{k+1}, lambda^{k+2}, chat, S'x, S'z,
+    read+write dJ/dchat, write lambda^k = 32 B; layer cells read and write
+    Yx, Yz, Zx, Zz (+32 B)."""
+    f = 16.0 + 32.0 * pml_fraction
+    return {"forward": f, "recompute": f + 8.0, "adjoint": 32.0 + 32.0 * pml_fraction}
+
+
 def measured_traffic(phase):
     """HBM bytes per step of `phase` from the committed FETCH_SIZE/WRITE_SIZE
     summary (counters scaled by a plain copy of known size), or None when the
@@ -73,14 +84,15 @@ def measured_traffic(phase):
     return int(m.group(1)) if m else None
 
 
-def cpu_baseline(cfg, c0, src, rec, nshots, nt):
+def cpu_baseline(cfg, c0, src, rec, nshots, nt, divergence=False):
     from oracle import pyoracle as O
     g = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
-               pml_R=cfg.pml_R, pml_vmax=4500.0)
+               pml_R=cfg.pml_R, pml_vmax=4500.0, f0_pml=cfg.f0)
     wav = np.stack([O.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)] * nshots)
     d = np.random.default_rng(0).standard_normal((nshots, nt, rec.shape[1]))
     t0 = time.perf_counter()
-    O.ac2_gradient(g, c0, src[:nshots], wav, rec[:nshots], d, ckpt=int(math.ceil(math.sqrt(nt))))
+    grad = O.ad2_gradient if divergence else O.ac2_gradient
+    grad(g, c0, src[:nshots], wav, rec[:nshots], d, ckpt=int(math.ceil(math.sqrt(nt))))
     t = time.perf_counter() - t0
     cells = cfg.padded_cells
     return 2.0 * cells * nshots * nt / t / 1e9, t
@@ -101,6 +113,9 @@ def main():
     ap.add_argument("--time-blocking", type=int, default=None, choices=(1, 2),
                     help="time steps per launch on the blocked tiles (results are identical); "
                          "default: the autotuner's choice")
+    ap.add_argument("--physics", choices=("constant-density", "divergence"), default="constant-density",
+                    help="acoustic form: u_tt = c^2 lap(u) (the headline kernels) or u_tt = div(c^2 grad u) "
+                         "(staggered grid, CPML; same grid, shots and steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -122,8 +137,11 @@ def main():
     ns, nrec = src.shape[0], rec.shape[1]
     vmax = 4500.0
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
-    d = S.desc(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
-               pml_R=cfg.pml_R, pml_vmax=vmax)
+    div = args.physics == "divergence"
+    if div:
+        args.no_ttm = True                    # the learned-preconditioner leg runs the headline form
+    d = S.desc(ndim=2, physics=S.SG_ACOUSTIC_DIV if div else S.SG_ACOUSTIC, nx=cfg.nx, nz=cfg.nz,
+               npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt, pml_R=cfg.pml_R, pml_vmax=vmax, f0_pml=cfg.f0)
     wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)
     wav = wav[None].repeat(ns, 1).contiguous()
     sh = S.Shots(src, rec, wav)
@@ -136,6 +154,8 @@ def main():
     # strategy from the autotuner (timed on 4 checkpoint segments of this
     # grid and shot batch, cached, outside the timed region)
     strategy = None
+    if div:
+        args.time_blocking = 1                # one step per launch (the setting applies to the other form)
     if args.time_blocking is None:
         from paper_2003_06027_amd import tune
         strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log)
@@ -193,7 +213,7 @@ def main():
     updates = 2.0 * cells * ns * nt
     value = updates / T / 1e9
     pml_frac = 1.0 - cfg.nx * cfg.nz / cells
-    bpc = bytes_per_cell_step(pml_frac)
+    bpc = bytes_per_cell_step_div(pml_frac) if div else bytes_per_cell_step(pml_frac)
     ph = {}
     for name, (ms, steps) in phases.items():
         if steps == 0:
@@ -204,13 +224,14 @@ def main():
                     "alg_bytes_per_cell": round(bpc[name], 3), "gbs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     dom = max(ph, key=lambda k: phases[k][0])
-    traffic = measured_traffic(dom)          # HBM bytes per step (layer + tile launch)
+    traffic = None if div else measured_traffic(dom)   # HBM bytes per step (layer + tile launch)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}", "grid_padded": list(cfg.padded),
+        "config": {"workload": (cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}") + ("_divergence" if div else ""),
+                   "grid_padded": list(cfg.padded),
                    "shots": ns, "nt": nt, "ckpt_every": ckpt, "stored_segments": nstore, "segments": nseg,
                    "time_blocking": args.time_blocking,
                    "tuned": None if strategy is None else {"time_blocking": strategy.time_blocking,
@@ -218,7 +239,8 @@ def main():
                    "launch": "eager (per-phase HIP events need eager launches)",
                    "receivers": nrec,
                    "cell_updates_per_step": updates},
-        "roofline": {"bound": "hbm", "kernel": f"ac2 {dom} step (PML + interior launches)",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"ad2 {dom} step (one fused launch)" if div else f"ac2 {dom} step (PML + interior launches)",
                      "achieved": ph[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ph[dom]["frac_hbm"], "traffic": traffic},
         "phases": ph,
@@ -252,7 +274,7 @@ def main():
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         ncpu = max(1, min(cores, ns))
         log(f"cpu baseline: oracle, {ncpu} shots x {args.cpu_steps} steps on {cores} threads")
-        rate, t = cpu_baseline(cfg, c0, src, rec, ncpu, args.cpu_steps)
+        rate, t = cpu_baseline(cfg, c0, src, rec, ncpu, args.cpu_steps, divergence=div)
         out["cpu_baseline"] = {"value": round(rate, 4), "unit": "Gcell-updates/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{ncpu} shots x {args.cpu_steps} steps of the same grid, FP64 "

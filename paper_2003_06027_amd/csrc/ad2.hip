@@ -24,7 +24,8 @@
 //   Y^{k+1} = a lambda^{k+1} + b Y^{k+2};   Hb = lambda^{k+1} + Y^{k+1}
 //   qb = -Dp' Hb;  Sb = khat qb;  Z^{k+1} = ah Sb + bh Z^{k+2};  Gb = Sb + Z^{k+1}
 //   lambda^k = 2 lambda^{k+1} - lambda^{k+2} - Dm' Gbx - Dm' Gbz + R^T dJ/dd_{k-1}
-//   dJ/dkhat += qb S' (S' of forward step k, a snapshot)
+//   dJ/dchat_i += 1/2 (qb S' at the two half nodes beside node i, per axis),
+//   S' of forward step k being a snapshot
 // Y and Z alternate between two buffers like psi'.
 #include <algorithm>
 #include "ad2_internal.h"
@@ -36,7 +37,6 @@ constexpr int AH = 3;              // halo of the composite stencil Dm' khat Dp'
 constexpr int AW = TX + 2 * AH;    // node tile with halo: AR rows of AW
 constexpr int AR = TZ + 2 * AH;
 constexpr int QXW = TX + 3;        // x half nodes x0-2 .. x0+TX on each row of the tile
-constexpr int QZR = TZ + 3;        // z half nodes z0-2 .. z0+TZ on each column
 constexpr float S1 = (float)(9.0 / 8.0);
 constexpr float S2 = (float)(-1.0 / 24.0);
 
@@ -89,8 +89,42 @@ __device__ __forceinline__ void gather_entries(float *acc, const int *ent, int b
 }
 
 // ------------------------------------------------------------------ forward
+// Work split of a tile: thread (lx, ly) owns column x0 + lx and rows
+// r0 = ly*RPT .. r0+RPT-1.  The z fluxes of its column (its own half rows and
+// the three around them that its Dm' needs) are computed in registers from
+// its column of the u tile; the x fluxes go through LDS (own half column by
+// every thread, the three extra columns x0-2, x0-1, x0+TX by the first 3*TZ
+// threads).  chat of the own column is read once per thread; the right
+// neighbour's comes from the next lane (one wavefront = one tile row).  The
+// z part runs first so that only Hz and u^k of the own rows stay live.
+template <bool NEAR, bool SNAP>
+__device__ __forceinline__ float fwd_xflux(const Ad2FwdArgs &a, const float *su, long long so, int x0, int z0, int r,
+                                           int h, float c0, float c1)
+{
+    const Grid2 &g = a.g;
+    const int iz = z0 + r, ix = x0 - 2 + h;
+    const float *s = su + (r + AH) * AW + h;
+    const float G = d4(s[0], s[1], s[2], s[3]);
+    float q = 0.f;
+    if (!NEAR || (ix >= 0 && ix < g.NX)) {
+        const long long f = fr(g, iz, ix);
+        const bool own = h >= 2 && h < TX + 2 && iz < g.NZ;
+        float S = G;
+        if constexpr (NEAR) {
+            const float p = fmaf(a.t.bhx[ix], a.psx[so + f], a.t.ahx[ix] * G);
+            S = G + p;
+            if (own) a.psxn[so + f] = p;
+        }
+        if constexpr (SNAP) {
+            if (own) a.snx[so + f] = S;
+        }
+        q = 0.5f * (c0 + c1) * S;
+    }
+    return q;
+}
+
 template <bool NEAR, bool SNAP, bool REC>
-__device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *qx, float *qz, int tile, int shot)
+__device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *qx, int tile, int shot)
 {
     const Grid2 &g = a.g;
     const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
@@ -98,71 +132,72 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     const long long so = (long long)shot * g.plane;
     const float *u = a.u + so;
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPT, ix = x0 + lx;
 
     for (int i = tid; i < AR * AW; i += NTH) {
         const int r = i / AW, c = i - r * AW;
         su[i] = u[fr(g, z0 - AH + r, x0 - AH + c)];
     }
-    __syncthreads();
-
-    // x fluxes at the half nodes ix + 1/2, ix = x0-2 .. x0+TX, of the tile's rows
-    for (int i = tid; i < TZ * QXW; i += NTH) {
-        const int r = i / QXW, h = i - r * QXW;
-        const int iz = z0 + r, ix = x0 - 2 + h;
-        const float *s = su + (r + AH) * AW + h;
-        const float G = d4(s[0], s[1], s[2], s[3]);
-        float q = 0.f;
-        if (!NEAR || (ix >= 0 && ix < g.NX)) {
-            const long long f = fr(g, iz, ix);
-            const bool own = h >= 2 && h < TX + 2 && iz < g.NZ;
-            float S = G;
-            if constexpr (NEAR) {
-                const float p = fmaf(a.t.bhx[ix], a.psx[so + f], a.t.ahx[ix] * G);
-                S = G + p;
-                if (own) a.psxn[so + f] = p;
-            }
-            if constexpr (SNAP) {
-                if (own) a.snx[so + f] = S;
-            }
-            q = 0.5f * (ch[f] + ch[f + 1]) * S;
-        }
-        qx[i] = q;
-    }
-    // z fluxes at the half nodes iz + 1/2, iz = z0-2 .. z0+TZ, of the tile's columns
-    for (int i = tid; i < QZR * TX; i += NTH) {
-        const int h = i / TX, c = i - h * TX;
-        const int iz = z0 - 2 + h, ix = x0 + c;
-        const float *s = su + h * AW + c + AH;
-        const float G = d4(s[0], s[AW], s[2 * AW], s[3 * AW]);
-        float q = 0.f;
-        if (!NEAR || (iz >= 0 && iz < g.NZ)) {
-            const long long f = fr(g, iz, ix);
-            const bool own = h >= 2 && h < TZ + 2 && ix < g.NX;
-            float S = G;
-            if constexpr (NEAR) {
-                const float p = fmaf(a.t.bhz[iz], a.psz[so + f], a.t.ahz[iz] * G);
-                S = G + p;
-                if (own) a.pszn[so + f] = p;
-            }
-            if constexpr (SNAP) {
-                if (own) a.snz[so + f] = S;
-            }
-            q = 0.5f * (ch[f] + ch[f + g.SX]) * S;
-        }
-        qz[i] = q;
-    }
-    __syncthreads();
-
-    const int lx = tid % TX, ly = tid / TX, ix = x0 + lx;
-    float uc[RPT];
+    float cz[RPT + 4];                    // chat of rows z0+r0-2 .. z0+r0+RPT+1
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) uc[j] = su[(ly * RPT + j + AH) * AW + lx + AH];
+    for (int m = 0; m < RPT + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
+    float um[RPT];                        // u^{k-1} of the own rows, loaded early
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) um[j] = a.um[so + fr(g, z0 + r0 + j, ix)];
+    __syncthreads();
+
+    // z fluxes of the own column at half rows z0+r0-2+m, m = 0 .. RPT+2
+    float uc[RPT], hz[RPT];
+    {
+        float uz[RPT + 6];
+#pragma unroll
+        for (int m = 0; m < RPT + 6; ++m) uz[m] = su[(r0 + m) * AW + lx + AH];
+        float qz[RPT + 3];
+#pragma unroll
+        for (int m = 0; m < RPT + 3; ++m) {
+            const int iz = z0 + r0 - 2 + m;
+            const float G = d4(uz[m], uz[m + 1], uz[m + 2], uz[m + 3]);
+            float q = 0.f;
+            if (!NEAR || (iz >= 0 && iz < g.NZ)) {
+                const long long f = fr(g, iz, ix);
+                const bool own = m >= 2 && m < RPT + 2 && ix < g.NX;
+                float S = G;
+                if constexpr (NEAR) {
+                    const float p = fmaf(a.t.bhz[iz], a.psz[so + f], a.t.ahz[iz] * G);
+                    S = G + p;
+                    if (own) a.pszn[so + f] = p;
+                }
+                if constexpr (SNAP) {
+                    if (own) a.snz[so + f] = S;
+                }
+                q = 0.5f * (cz[m] + cz[m + 1]) * S;
+            }
+            qz[m] = q;
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            uc[j] = uz[j + 3];
+            hz[j] = d4(qz[j], qz[j + 1], qz[j + 2], qz[j + 3]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const float c0 = cz[j + 2];
+        float c1 = __shfl_down(c0, 1, TX);
+        if (lx == TX - 1) c1 = ch[fr(g, z0 + r0 + j, ix + 1)];
+        qx[(r0 + j) * QXW + lx + 2] = fwd_xflux<NEAR, SNAP>(a, su, so, x0, z0, r0 + j, lx + 2, c0, c1);
+    }
+    if (tid < 3 * TZ) {
+        const int r = tid / 3, e = tid - 3 * r, h = e == 2 ? TX + 2 : e;
+        const long long f = fr(g, z0 + r, x0 - 2 + h);
+        qx[r * QXW + h] = fwd_xflux<NEAR, SNAP>(a, su, so, x0, z0, r, h, ch[f], ch[f + 1]);
+    }
+    __syncthreads();                      // qx complete; su no longer read
+
     const int ntiles = g.ntx * g.ntz;
     const int *soff = a.src_off + (long long)shot * (ntiles + 1);
     const int sb = soff[tile], se = soff[tile + 1];
-    if (sb < se) {                       // uniform over the block
-        __syncthreads();                 // every thread has read its u^k
+    if (sb < se) {                        // uniform over the block
         const float *w = a.wav + (long long)shot * a.nsrc * a.nt + a.k;
         gather_entries(su, a.src_ent, sb, se, [](int e) { return src_cell(e); },
                        [&](int e) { return a.src_scale * w[(long long)src_node(e) * a.nt]; });
@@ -170,23 +205,21 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     float un[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j, iz = z0 + r;
+        const int r = r0 + j, iz = z0 + r;
         const float *qa = qx + r * QXW + lx;
-        const float *qb = qz + r * TX + lx;
         const float Hx = d4(qa[0], qa[1], qa[2], qa[3]);
-        const float Hz = d4(qb[0], qb[TX], qb[2 * TX], qb[3 * TX]);
         un[j] = 0.f;
         if (iz < g.NZ && ix < g.NX) {
             const long long f = fr(g, iz, ix);
-            float inc = Hx + Hz;
+            float inc = Hx + hz[j];
             if constexpr (NEAR) {
                 const float xx = fmaf(a.t.b0x[ix], a.xix[so + f], a.t.a0x[ix] * Hx);
-                const float xz = fmaf(a.t.b0z[iz], a.xiz[so + f], a.t.a0z[iz] * Hz);
+                const float xz = fmaf(a.t.b0z[iz], a.xiz[so + f], a.t.a0z[iz] * hz[j]);
                 a.xix[so + f] = xx;
                 a.xiz[so + f] = xz;
                 inc += xx + xz;
             }
-            inc += uc[j] - a.um[so + f];
+            inc += uc[j] - um[j];
             if (sb < se) inc += su[r * TX + lx];
             const float v = uc[j] + inc;
             a.un[so + f] = v;
@@ -196,10 +229,10 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     if constexpr (REC) {
         const int *off = a.rec_off + (long long)shot * (ntiles + 1);
         const int b = off[tile], e = off[tile + 1];
-        if (b < e) {                     // uniform over the block
+        if (b < e) {                      // uniform over the block
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) su[(ly * RPT + j) * TX + lx] = un[j];
+            for (int j = 0; j < RPT; ++j) su[(r0 + j) * TX + lx] = un[j];
             __syncthreads();
             for (int i = b + tid; i < e; i += NTH) {
                 const int ent = a.rec_ent[i];
@@ -214,18 +247,50 @@ __global__ __launch_bounds__(NTH) void ad2_fwd_kernel(Ad2FwdArgs a)
 {
     __shared__ float su[AR * AW];
     __shared__ float qx[TZ * QXW];
-    __shared__ float qz[QZR * TX];
     const int ntl = a.g.ntx * a.g.ntz;
     const int w = xcd_id(ntl * a.nshots);
     const int shot = w / ntl, tile = w - shot * ntl;
     const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
-    if (near_edge(a.g, tx * TX, tz * TZ)) fwd_tile<true, SNAP, REC>(a, su, qx, qz, tile, shot);
-    else                                  fwd_tile<false, SNAP, REC>(a, su, qx, qz, tile, shot);
+    if (near_edge(a.g, tx * TX, tz * TZ)) fwd_tile<true, SNAP, REC>(a, su, qx, tile, shot);
+    else                                  fwd_tile<false, SNAP, REC>(a, su, qx, tile, shot);
 }
 
 // ------------------------------------------------------------------ adjoint
+// Gradient per node: khat at a half node feeds its two nodes with weight
+// 1/2 each, so dJ/dchat_i = 1/2 (p at i-1/2 + p at i+1/2) per axis, with
+// p = qb S' the half-node product; the node at the far edge of each axis
+// also takes the other half of its right half node (the chat beyond the
+// grid is its replica).  The x product of the half node left of a thread's
+// node comes from the neighbouring lane (lane 0: from the extra column).
 template <bool NEAR, bool GRAD>
-__device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *hz, float *qx, float *qz, int tile,
+__device__ __forceinline__ float adj_xflux(const Ad2AdjArgs &a, const float *hx, long long so, int x0, int z0, int r,
+                                           int h, float c0, float c1, bool want_p, float &p)
+{
+    const Grid2 &g = a.g;
+    const int iz = z0 + r, ix = x0 - 2 + h;
+    const float *s = hx + (r + AH) * AW + h;
+    const float qb = -d4(s[0], s[1], s[2], s[3]);
+    float Gb = 0.f;
+    p = 0.f;
+    if (!NEAR || (ix >= 0 && ix < g.NX)) {
+        const long long f = fr(g, iz, ix);
+        const bool own = h >= 2 && h < TX + 2 && iz < g.NZ;
+        const float Sb = 0.5f * (c0 + c1) * qb;
+        Gb = Sb;
+        if constexpr (NEAR) {
+            const float z = fmaf(a.t.ahx[ix], Sb, a.t.bhx[ix] * a.zx[so + f]);
+            Gb = Sb + z;
+            if (own) a.zxn[so + f] = z;
+        }
+        if constexpr (GRAD) {
+            if (want_p && iz < g.NZ) p = qb * a.snx[so + f];
+        }
+    }
+    return Gb;
+}
+
+template <bool NEAR, bool GRAD>
+__device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *hz, float *qx, float *pl, int tile,
                                          int shot)
 {
     const Grid2 &g = a.g;
@@ -234,18 +299,18 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
     const long long so = (long long)shot * g.plane;
     const float *l1 = a.l1 + so;
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPT, ix = x0 + lx;
 
     // Hb = lambda^{k+1} + Y^{k+1} per axis on the tile and its halo
     for (int i = tid; i < AR * AW; i += NTH) {
         const int r = i / AW, c = i - r * AW;
-        const int iz = z0 - AH + r, ix = x0 - AH + c;
-        const long long f = fr(g, iz, ix);
+        const int iz = z0 - AH + r, jx = x0 - AH + c;
+        const long long f = fr(g, iz, jx);
         const float l = l1[f];
         if constexpr (NEAR) {
             float bx = l, bz = l;
-            if (iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX) {
-                const float yx = fmaf(a.t.a0x[ix], l, a.t.b0x[ix] * a.yx[so + f]);
+            if (iz >= 0 && iz < g.NZ && jx >= 0 && jx < g.NX) {
+                const float yx = fmaf(a.t.a0x[jx], l, a.t.b0x[jx] * a.yx[so + f]);
                 const float yz = fmaf(a.t.a0z[iz], l, a.t.b0z[iz] * a.yz[so + f]);
                 if (r >= AH && r < AH + TZ && c >= AH && c < AH + TX) {
                     a.yxn[so + f] = yx;
@@ -260,78 +325,99 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             hx[i] = l;
         }
     }
+    float cz[RPT + 4];
+#pragma unroll
+    for (int m = 0; m < RPT + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
+    float l2[RPT];                        // lambda^{k+2} of the own rows, loaded early
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) l2[j] = a.l2[so + fr(g, z0 + r0 + j, ix)];
     __syncthreads();
     const float *hzz = NEAR ? hz : hx;
 
-    for (int i = tid; i < TZ * QXW; i += NTH) {
-        const int r = i / QXW, h = i - r * QXW;
-        const int iz = z0 + r, ix = x0 - 2 + h;
-        const float *s = hx + (r + AH) * AW + h;
-        const float qb = -d4(s[0], s[1], s[2], s[3]);
-        float Gb = 0.f;
-        if (!NEAR || (ix >= 0 && ix < g.NX)) {
-            const long long f = fr(g, iz, ix);
-            const bool own = h >= 2 && h < TX + 2 && iz < g.NZ;
-            const float Sb = 0.5f * (ch[f] + ch[f + 1]) * qb;
-            Gb = Sb;
-            if constexpr (NEAR) {
-                const float z = fmaf(a.t.ahx[ix], Sb, a.t.bhx[ix] * a.zx[so + f]);
-                Gb = Sb + z;
-                if (own) a.zxn[so + f] = z;
+    float lam[RPT], dz[RPT], gnz[RPT];   // lambda^{k+1}, Dm' Gb_z and the z gradient of the own rows
+    {
+        float hc[RPT + 6];
+#pragma unroll
+        for (int m = 0; m < RPT + 6; ++m) hc[m] = hzz[(r0 + m) * AW + lx + AH];
+        float gz[RPT + 3], pz[RPT + 3];
+#pragma unroll
+        for (int m = 0; m < RPT + 3; ++m) {
+            const int iz = z0 + r0 - 2 + m;
+            const float qb = -d4(hc[m], hc[m + 1], hc[m + 2], hc[m + 3]);
+            float Gb = 0.f;
+            pz[m] = 0.f;
+            if (!NEAR || (iz >= 0 && iz < g.NZ)) {
+                const long long f = fr(g, iz, ix);
+                const bool own = m >= 2 && m < RPT + 2 && ix < g.NX;
+                const float Sb = 0.5f * (cz[m] + cz[m + 1]) * qb;
+                Gb = Sb;
+                if constexpr (NEAR) {
+                    const float z = fmaf(a.t.ahz[iz], Sb, a.t.bhz[iz] * a.zz[so + f]);
+                    Gb = Sb + z;
+                    if (own) a.zzn[so + f] = z;
+                }
+                if constexpr (GRAD) {
+                    if (m >= 1 && m < RPT + 2) pz[m] = qb * a.snz[so + f];
+                }
             }
-            if constexpr (GRAD) {
-                if (own) a.gkx[so + f] += qb * a.snx[so + f];
-            }
+            gz[m] = Gb;
         }
-        qx[i] = Gb;
-    }
-    for (int i = tid; i < QZR * TX; i += NTH) {
-        const int h = i / TX, c = i - h * TX;
-        const int iz = z0 - 2 + h, ix = x0 + c;
-        const float *s = hzz + h * AW + c + AH;
-        const float qb = -d4(s[0], s[AW], s[2 * AW], s[3 * AW]);
-        float Gb = 0.f;
-        if (!NEAR || (iz >= 0 && iz < g.NZ)) {
-            const long long f = fr(g, iz, ix);
-            const bool own = h >= 2 && h < TZ + 2 && ix < g.NX;
-            const float Sb = 0.5f * (ch[f] + ch[f + g.SX]) * qb;
-            Gb = Sb;
-            if constexpr (NEAR) {
-                const float z = fmaf(a.t.ahz[iz], Sb, a.t.bhz[iz] * a.zz[so + f]);
-                Gb = Sb + z;
-                if (own) a.zzn[so + f] = z;
-            }
-            if constexpr (GRAD) {
-                if (own) a.gkz[so + f] += qb * a.snz[so + f];
-            }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int iz = z0 + r0 + j;
+            lam[j] = NEAR ? 0.f : hc[j + 3];
+            dz[j] = d4(gz[j], gz[j + 1], gz[j + 2], gz[j + 3]);
+            gnz[j] = 0.5f * (pz[j + 1] + pz[j + 2]);
+            if (iz == g.NZ - 1) gnz[j] += 0.5f * pz[j + 2];
         }
-        qz[i] = Gb;
     }
-    __syncthreads();
+    float px[RPT];                        // x products at the own half column
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const float c0 = cz[j + 2];
+        float c1 = __shfl_down(c0, 1, TX);
+        if (lx == TX - 1) c1 = ch[fr(g, z0 + r0 + j, ix + 1)];
+        float pj;
+        qx[(r0 + j) * QXW + lx + 2] = adj_xflux<NEAR, GRAD>(a, hx, so, x0, z0, r0 + j, lx + 2, c0, c1, true, pj);
+        px[j] = pj;
+    }
+    if (tid < 3 * TZ) {
+        const int r = tid / 3, e = tid - 3 * r, h = e == 2 ? TX + 2 : e;
+        const long long f = fr(g, z0 + r, x0 - 2 + h);
+        float p = 0.f;
+        qx[r * QXW + h] = adj_xflux<NEAR, GRAD>(a, hx, so, x0, z0, r, h, ch[f], ch[f + 1], h == 1, p);
+        if (GRAD && h == 1) pl[r] = p;    // the half node left of the tile's first column
+    }
+    __syncthreads();                      // qx, pl complete; hx, hz no longer read
 
     const int ntiles = g.ntx * g.ntz;
     const int *off = a.rec_off + (long long)shot * (ntiles + 1);
     const int b = off[tile], e = off[tile + 1];
-    const bool inj = a.k >= 1 && b < e;  // uniform over the block
+    const bool inj = a.k >= 1 && b < e;   // uniform over the block
     if (inj) {
         const float *d = a.dJdd + ((long long)shot * a.nt + (a.k - 1)) * a.nrec;
         gather_entries(hx, a.rec_ent, b, e, [](int en) { return rec_cell(en); },
                        [&](int en) { return d[rec_id(en)]; });
     }
-    const int lx = tid % TX, ly = tid / TX, ix = x0 + lx;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j, iz = z0 + r;
+        const int r = r0 + j, iz = z0 + r;
         const float *ga = qx + r * QXW + lx;
-        const float *gb = qz + r * TX + lx;
         const float Dx = d4(ga[0], ga[1], ga[2], ga[3]);
-        const float Dz = d4(gb[0], gb[TX], gb[2 * TX], gb[3 * TX]);
+        float gn = 0.f;
+        if constexpr (GRAD) {
+            float left = __shfl_up(px[j], 1, TX);
+            if (lx == 0) left = pl[r];
+            gn = 0.5f * (left + px[j]) + gnz[j];
+            if (ix == g.NX - 1) gn += 0.5f * px[j];
+        }
         if (iz < g.NZ && ix < g.NX) {
             const long long f = fr(g, iz, ix);
-            const float lc = l1[f];
-            float v = lc + ((lc - a.l2[so + f]) - (Dx + Dz));
+            const float lc = NEAR ? l1[f] : lam[j];
+            float v = lc + ((lc - l2[j]) - (Dx + dz[j]));
             if (inj) v += hx[r * TX + lx];
             a.l0[so + f] = v;
+            if constexpr (GRAD) a.gn[so + f] += gn;
         }
     }
 }
@@ -342,13 +428,13 @@ __global__ __launch_bounds__(NTH) void ad2_adj_kernel(Ad2AdjArgs a)
     __shared__ float hx[AR * AW];
     __shared__ float hz[AR * AW];
     __shared__ float qx[TZ * QXW];
-    __shared__ float qz[QZR * TX];
+    __shared__ float pl[TZ];
     const int ntl = a.g.ntx * a.g.ntz;
     const int w = xcd_id(ntl * a.nshots);
     const int shot = w / ntl, tile = w - shot * ntl;
     const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
-    if (near_edge(a.g, tx * TX, tz * TZ)) adj_tile<true, GRAD>(a, hx, hz, qx, qz, tile, shot);
-    else                                  adj_tile<false, GRAD>(a, hx, hz, qx, qz, tile, shot);
+    if (near_edge(a.g, tx * TX, tz * TZ)) adj_tile<true, GRAD>(a, hx, hz, qx, pl, tile, shot);
+    else                                  adj_tile<false, GRAD>(a, hx, hz, qx, pl, tile, shot);
 }
 
 // ------------------------------------------------------------------ model and gradient
@@ -373,26 +459,14 @@ __global__ void ad2_prep_kernel(Grid2 g, int nmodels, const float *vp, double dt
     }
 }
 
-// dJ/dchat per padded node, summed over the model's shots in shot order:
-// khat_x(i) = (chat_i + chat_{i+1})/2 feeds nodes i and i+1 (node NX-1 twice,
-// its neighbour beyond the grid being its replica); z alike.
-__global__ void ad2_chat_grad_kernel(Grid2 g, int nmodels, int spm, const float *gkx, const float *gkz, float *acc)
+// dJ/dchat per padded node, summed over the model's shots in shot order.
+__global__ void ad2_sum_shots_kernel(Grid2 g, int nmodels, int spm, const float *gn, float *acc)
 {
     const long long n = (long long)nmodels * g.plane;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const long long m = i / g.plane, f = i - m * g.plane;
-        const int iz = (int)(f / g.SX) - OZ, ix = (int)(f - (f / g.SX) * g.SX) - OX;
         float v = 0.f;
-        if (iz >= 0 && iz < g.NZ && ix >= 0 && ix < g.NX) {
-            for (int s = 0; s < spm; ++s) {
-                const float *x = gkx + (m * spm + s) * g.plane, *z = gkz + (m * spm + s) * g.plane;
-                float t = (x[f] + x[f - 1]) + (z[f] + z[f - g.SX]);
-                if (ix == g.NX - 1) t += x[f];
-                if (iz == g.NZ - 1) t += z[f];
-                v += t;
-            }
-            v *= 0.5f;
-        }
+        for (int s = 0; s < spm; ++s) v += gn[(m * spm + s) * g.plane + f];
         acc[i] = v;
     }
 }
@@ -448,10 +522,10 @@ void launch_ad2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, do
     ad2_prep_kernel<<<blocks_for((long long)nmodels * g.plane), 256, 0, s>>>(g, nmodels, vp, dt, dx, chat, cpad);
 }
 
-void launch_ad2_finalize(const Grid2 &g, int nmodels, int spm, const float *gkx, const float *gkz, float *acc,
-                         const float *cpad, double dt, double dx, float *g_vp, hipStream_t s)
+void launch_ad2_finalize(const Grid2 &g, int nmodels, int spm, const float *gn, float *acc, const float *cpad,
+                         double dt, double dx, float *g_vp, hipStream_t s)
 {
-    ad2_chat_grad_kernel<<<blocks_for((long long)nmodels * g.plane), 256, 0, s>>>(g, nmodels, spm, gkx, gkz, acc);
+    ad2_sum_shots_kernel<<<blocks_for((long long)nmodels * g.plane), 256, 0, s>>>(g, nmodels, spm, gn, acc);
     ad2_fold_kernel<<<blocks_for((long long)nmodels * g.nz * g.nx), 256, 0, s>>>(g, nmodels, acc, cpad, dt, dx, g_vp);
 }
 

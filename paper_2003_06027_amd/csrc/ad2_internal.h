@@ -55,14 +55,14 @@ struct Ad2AdjArgs {
     const float *dJdd;        // [shot][nt][nrec]; sample k-1 joins lambda^k
     int nrec;
     const float *snx, *snz;   // S' of forward step k, or null (no gradient term)
-    float *gkx, *gkz;         // dJ/dkhat at the half nodes [shot][plane], accumulated
+    float *gn;                // dJ/dchat at the nodes [shot][plane], accumulated
 };
 
 void launch_ad2_fwd(const Ad2FwdArgs &a, hipStream_t s);
 void launch_ad2_adj(const Ad2AdjArgs &a, hipStream_t s);
 void launch_ad2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx, float *chat,
                      float *cpad, hipStream_t s);
-void launch_ad2_finalize(const Grid2 &g, int nmodels, int shots_per_model, const float *gkx, const float *gkz,
-                         float *acc, const float *cpad, double dt, double dx, float *g_vp, hipStream_t s);
+void launch_ad2_finalize(const Grid2 &g, int nmodels, int shots_per_model, const float *gn, float *acc,
+                         const float *cpad, double dt, double dx, float *g_vp, hipStream_t s);
 
 } // namespace sg

@@ -137,7 +137,6 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
             L.nf = 6;
             L.nxs = 4;
             L.nsnap = 2;   // S'x, S'z per step
-            L.ngrad = 2;   // dJ/dkhat at the x and z half nodes
         }
         L.n[0] = g.NX; L.n[1] = 1; L.n[2] = g.NZ;
     } else {
@@ -699,8 +698,7 @@ void ad2_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gw
     a.nrec = m->geom_nrec;
     a.snx = snap;
     a.snz = snap ? snap + m->L.field : nullptr;
-    a.gkx = m->grad;
-    a.gkz = m->grad + m->L.field;
+    a.gn = m->grad;
     launch_ad2_adj(a, s);
     if (gwav && k < m->d.nt)
         launch_ac2_src_gather(ns, m->geom_nsrc, m->L.plane, m->node_f, m->adj[(k + 1) & 1], gwav, m->d.nt, k,
@@ -1340,8 +1338,8 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         launch_el2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, L.field, m->acc, m->model,
                             m->model + 5, g_vp, g_vs, g_rho, s);
     else if (ad2)
-        launch_ad2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->grad + L.field, m->acc, m->cpad,
-                            m->d.dt, m->d.dx, g_vp, s);
+        launch_ad2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx,
+                            g_vp, s);
     else if (m->d.ndim == 2)
         launch_ac2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     else
