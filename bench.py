@@ -63,17 +63,19 @@ def bytes_per_cell_step_div(pml_fraction):
     return {"forward": f, "recompute": f + 8.0, "adjoint": 32.0 + 32.0 * pml_fraction}
 
 
-def measured_traffic(phase):
+def measured_traffic(phase, divergence=False):
     """HBM bytes per step of `phase` from the committed FETCH_SIZE/WRITE_SIZE
     summary (counters scaled by a plain copy of known size), or None when the
     kernels' source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "ac2_c2_hbm_traffic.txt")
+    name, files = (("ad2_c2_hbm_traffic.txt", ("ad2.hip", "ad2_internal.h", "sg_internal.h")) if divergence
+                   else ("ac2_c2_hbm_traffic.txt", ("ac2.hip", "sg_internal.h")))
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2003_06027_amd", "csrc")
     try:
         text = open(path).read()
         h = hashlib.sha256()
-        for f in ("ac2.hip", "sg_internal.h"):
+        for f in files:
             h.update(open(os.path.join(src, f), "rb").read())
     except OSError:
         return None
@@ -224,7 +226,7 @@ def main():
                     "alg_bytes_per_cell": round(bpc[name], 3), "gbs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     dom = max(ph, key=lambda k: phases[k][0])
-    traffic = None if div else measured_traffic(dom)   # HBM bytes per step (layer + tile launch)
+    traffic = measured_traffic(dom, div)     # HBM bytes per step (all launches of the step)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
