@@ -183,6 +183,9 @@ def test_layered_model_plane_wave_inversion():
     m = res.models.cpu().numpy()[0]
     J = np.asarray(res.J)[:, 0]
     e0, e1 = rel_l2(c0, c_true), rel_l2(m, c_true)
-    print(f"J/J0 {J[-1] / J[0]:.3e}, model error {e0:.4f} -> {e1:.4f}")
+    # the update against the missing part of the model (cosine of the angle)
+    du, dt_ = (m - c0).ravel(), (c_true - c0).ravel()
+    cos = float(du @ dt_ / (np.linalg.norm(du) * np.linalg.norm(dt_)))
+    print(f"J/J0 {J[-1] / J[0]:.3e}, model error {e0:.4f} -> {e1:.4f}, cos(update, true update) {cos:.3f}")
     assert np.all(np.diff(J) <= 0) and J[-1] <= 0.2 * J[0]
-    assert e1 < e0
+    assert e1 < e0 and cos > 0.1
