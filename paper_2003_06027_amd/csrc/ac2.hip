@@ -136,6 +136,8 @@ __device__ __forceinline__ void layer_cell(const Grid2 &g, long long i, int &iz,
 }
 
 // ------------------------------------------------------------ forward pass A
+// Strip order over the layer cells, one thread per cell, stencil points read
+// directly (measured faster than staging tiles for this one-operand pass).
 __global__ __launch_bounds__(256) void ac2_phi_kernel(Ac2PhiArgs a)
 {
     const Grid2 &g = a.g;
@@ -152,6 +154,12 @@ __global__ __launch_bounds__(256) void ac2_phi_kernel(Ac2PhiArgs a)
         a.phx[so + f] = a.px[ix] * a.phx[so + f] + qx * d8(u + f, 1);
         a.phz[so + f] = a.pz[iz] * a.phz[so + f] + qz * d8(u + f, (long long)g.SX);
     }
+}
+
+// A layer cell of the padded grid.
+__device__ __forceinline__ bool layer_cell_at(const Grid2 &g, int iz, int ix)
+{
+    return iz < g.P || iz >= g.P + g.nz || ix < g.P || ix >= g.P + g.nx;
 }
 
 // Sum of dt^2/(dx dz) r_j(t_k) over the source nodes j of this shot at
@@ -280,30 +288,40 @@ __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
 }
 
 // ------------------------------------------------------------ adjoint pass A
-__global__ __launch_bounds__(256) void ac2_phi_adj_kernel(Ac2PhiAdjArgs a)
+// Over the tiles that hold layer cells: chat s^{k+2} with a 4-cell halo in
+// LDS (two operands per stencil point make direct reads twice as costly as
+// in the forward pass), then the layer adjoint at the tile's layer cells.
+__global__ __launch_bounds__(NTH) void ac2_phi_adj_kernel(Ac2PhiAdjArgs a)
 {
+    constexpr int H = 4, W = TX + 2 * H;
+    __shared__ float sc[(TZ + 8) * (TX + 8)];
     const Grid2 &g = a.g;
-    const int shot = blockIdx.y;
+    const int w = xcd_work_id((int)gridDim.x);
+    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
     const long long so = (long long)shot * g.plane;
-    const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
     const float *s2 = a.s2 + so;
     const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < ncell; i += (long long)gridDim.x * 256) {
-        int iz, ix;
-        layer_cell(g, i, iz, ix);
-        const long long f = fidx(g, iz, ix);
-        float dx = 0.f, dz = 0.f;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, ix = x0 + lx;
 #pragma unroll
-        for (int m = 1; m <= 4; ++m) {
-            const float dm = m == 1 ? D1 : m == 2 ? D2 : m == 3 ? D3 : D4;
-            const long long e = (long long)m * g.SX;
-            dx += dm * (chat[f + m] * s2[f + m] - chat[f - m] * s2[f - m]);
-            dz += dm * (chat[f + e] * s2[f + e] - chat[f - e] * s2[f - e]);
-        }
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        const long long f = fidx(g, z0 + r, ix);
+        sc[(r + H) * W + lx + H] = chat[f] * s2[f];
+    }
+    load_halo(g, sc, x0, z0, [&](long long f) { return chat[f] * s2[f]; });
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j, iz = z0 + r;
+        if (iz >= g.NZ || ix >= g.NX || !layer_cell_at(g, iz, ix)) continue;
+        const long long f = so + fidx(g, iz, ix);
+        const float *c = sc + (r + H) * W + lx + H;
         const float hx = a.hx[ix], hz = a.hz[iz];
         const float qx = 2.f * (hz - hx) * a.ihx[ix], qz = 2.f * (hx - hz) * a.ihz[iz];
-        a.cx[so + f] = a.px[ix] * a.cx[so + f] - qx * dx;
-        a.cz[so + f] = a.pz[iz] * a.cz[so + f] - qz * dz;
+        a.cx[f] = a.px[ix] * a.cx[f] - qx * d8(c, 1);
+        a.cz[f] = a.pz[iz] * a.cz[f] - qz * d8(c, (long long)W);
     }
 }
 
@@ -660,8 +678,8 @@ void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s)
 
 void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s)
 {
-    if (a.g.P == 0 || nshots == 0) return;
-    ac2_phi_adj_kernel<<<dim3(layer_blocks(a.g), nshots), 256, 0, s>>>(a);
+    if (a.g.P == 0 || nshots == 0 || a.ntl == 0) return;
+    ac2_phi_adj_kernel<<<a.ntl * nshots, NTH, 0, s>>>(a);
 }
 
 void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s)

@@ -209,6 +209,10 @@ struct sg_model {
     std::vector<long long> h_nodef;
     int n_near = 0, n_blk = 0;
     std::vector<int> h_tiles;
+    // tiles holding layer cells (the layer pass of the constant-density form)
+    int *tiles_layer = nullptr;
+    int n_layer = 0;
+    std::vector<int> h_layer;
     int steps_per_launch = 2;
     // snapshots of the last n_store checkpoint segments, written by a
     // checkpointed forward into the workspace beyond its minimum size
@@ -838,6 +842,8 @@ void ac2_phi_adj(const sg_model *m, int ns, int k, hipStream_t s)
 {
     Ac2PhiAdjArgs pa{};
     pa.g = m->L.g2;
+    pa.tiles = m->tiles_layer;
+    pa.ntl = m->n_layer;
     pa.s2 = m->s4[(k + 2) & 3];
     pa.chat = m->chat;
     pa.shots_per_model = ns / m->d.nmodels;
@@ -1076,6 +1082,13 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         }
         m->tiles_near = reinterpret_cast<int *>(m->ws + L.off_tiles);
         m->tiles_blk = m->tiles_near + L.ntiles;
+        m->tiles_layer = m->tiles_near + L.ntiles;   // the second half of the tile lists
+        const Grid2 &g = L.g2;
+        for (int t = 0; t < L.ntiles && d->npml > 0; ++t) {
+            const int x0 = (t % g.ntx) * TX, z0 = (t / g.ntx) * TZ;
+            if (x0 < g.P || x0 + TX > g.P + g.nx || z0 < g.P || z0 + TZ > g.P + g.nz) m->h_layer.push_back(t);
+        }
+        m->n_layer = (int)m->h_layer.size();
     }
     {
         const size_t per = sizeof(float) * (size_t)L.K * L.nsnap * L.field;
@@ -1166,6 +1179,8 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         }
     }
     hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && m->n_layer > 0)
+        e = hipMemcpyAsync(m->tiles_layer, m->h_layer.data(), sizeof(int) * m->n_layer, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         delete m;
         return fail(SG_EDEVICE, "upload failed: %s", hipGetErrorString(e));

@@ -71,6 +71,8 @@ struct Ac2FwdArgs {
 // Adjoint pass A: c^{k+1} = p c^{k+2} - q D~(chat s^{k+2}) on the layer cells.
 struct Ac2PhiAdjArgs {
     Grid2 g;
+    const int *tiles;       // tiles holding layer cells
+    int ntl;
     const float *s2;        // s^{k+2}
     const float *chat;
     int shots_per_model;
