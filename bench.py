@@ -18,6 +18,11 @@ inversions of random three-layer 101 x 101 models, CNN training with the
 library's BF16 matrix-core kernels, then plain and preconditioned descent on
 20 unseen models; reported under "time_to_misfit" (skip with --no-ttm).
 
+Other workloads (--workload c3 | c4, --physics divergence) print their own
+line with the same keys: the 2-D elastic (800 x 400, 16 shots) and 3-D
+acoustic (400^3) sweeps, and the divergence-form acoustic kernels on the C2
+workload.  The default run is the one above.
+
 Prints ONE JSON line (rank 0, N = 1).
 """
 import argparse
@@ -86,6 +91,66 @@ def measured_traffic(phase, divergence=False):
     return int(m.group(1)) if m else None
 
 
+def bytes_per_cell_step_el2(pml_fraction):
+    """2-D elastic: forward reads vx, vz, sxx, szz, sxz and the five model
+    fields (lam, mu, muxz, bx, bz) and writes the five fields = 60 B; layer
+    cells read and write the eight CPML memory variables (+64 B).  recompute:
+    + five snapshot fields (+20 B).  adjoint: read the five adjoint fields,
+    the model fields and the snapshots, read+write five gradient
+    accumulators, write five adjoint fields = 120 B (+64 B on layer cells)."""
+    return {"forward": 60.0 + 64.0 * pml_fraction, "recompute": 80.0 + 64.0 * pml_fraction,
+            "adjoint": 120.0 + 64.0 * pml_fraction}
+
+
+def bytes_per_cell_step_ac3(pml_fraction):
+    """3-D acoustic: as the 2-D form, with phi_x, phi_y, phi_z and psi on
+    layer cells (+32 B forward and adjoint)."""
+    f = 16.0 + 32.0 * pml_fraction
+    return {"forward": f, "recompute": f + 4.0, "adjoint": 28.0 + 32.0 * pml_fraction}
+
+
+def copy_bandwidth(torch):
+    """Best of five 1 GiB device-to-device copies (read + write bytes per
+    second, GB/s), timed with HIP events on the current stream."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        a.copy_(b)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    return best
+
+
+def cpu_baseline_el2(cfg, m0, src, mt, rec, nshots, nt):
+    from oracle import pyoracle as O
+    g = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+               pml_R=cfg.pml_R, pml_vmax=4000.0, f0_pml=cfg.f0_pml)
+    wav = np.stack([O.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)] * nshots)
+    d = np.random.default_rng(0).standard_normal((nshots, 2, nt, rec.shape[1]))
+    t0 = time.perf_counter()
+    O.el2_gradient(g, m0[0], m0[1], m0[2], src[:nshots], mt[:nshots], wav, rec[:nshots], d,
+                   ckpt=int(math.ceil(math.sqrt(nt))))
+    t = time.perf_counter() - t0
+    return 2.0 * cfg.padded_cells * nshots * nt / t / 1e9, t
+
+
+def cpu_baseline_ac3(cfg, c0, src, rec, nt):
+    from oracle import pyoracle as O
+    g = O.grid(ndim=3, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+               pml_R=cfg.pml_R, pml_vmax=4000.0)
+    wav = O.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)[None]
+    d = np.random.default_rng(0).standard_normal((1, nt, rec.shape[1]))
+    t0 = time.perf_counter()
+    O.ac3_gradient(g, c0, src, wav, rec, d, ckpt=int(math.ceil(math.sqrt(nt))))
+    t = time.perf_counter() - t0
+    return 2.0 * cfg.padded_cells * nt / t / 1e9, t
+
+
 def cpu_baseline(cfg, c0, src, rec, nshots, nt, divergence=False):
     from oracle import pyoracle as O
     g = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
@@ -115,6 +180,9 @@ def main():
     ap.add_argument("--time-blocking", type=int, default=None, choices=(1, 2),
                     help="time steps per launch on the blocked tiles (results are identical); "
                          "default: the autotuner's choice")
+    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
+                    help="c2: 2-D acoustic 1000x500, 64 shots (default); c3: 2-D elastic 800x400, 16 shots; "
+                         "c4: 3-D acoustic 400^3")
     ap.add_argument("--physics", choices=("constant-density", "divergence"), default="constant-density",
                     help="acoustic form: u_tt = c^2 lap(u) (the headline kernels) or u_tt = div(c^2 grad u) "
                          "(staggered grid, CPML; same grid, shots and steps)")
@@ -130,34 +198,58 @@ def main():
     from paper_2003_06027_amd import seisgrad as S
     from paper_2003_06027_amd import synth
 
-    cfg = synth.C2
+    wl = args.workload
+    cfg = {"c2": synth.C2, "c3": synth.C3, "c4": synth.C4}[wl]
     nt = args.nt or cfg.nt
     ckpt = int(math.ceil(math.sqrt(nt)))
-    ct = synth.dipping_layers_anomalies(2003, cfg.nx, cfg.nz, cfg.dx)
-    c0 = synth.smooth(ct, 10.0)
-    src, rec = synth.c2_geometry(cfg.nshots, cfg.nx)
-    ns, nrec = src.shape[0], rec.shape[1]
-    vmax = 4500.0
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
     div = args.physics == "divergence"
-    if div:
+    if div and wl != "c2":
+        log("--physics divergence applies to the c2 workload")
+        sys.exit(2)
+    if div or wl != "c2":
         args.no_ttm = True                    # the learned-preconditioner leg runs the headline form
-    d = S.desc(ndim=2, physics=S.SG_ACOUSTIC_DIV if div else S.SG_ACOUSTIC, nx=cfg.nx, nz=cfg.nz,
-               npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt, pml_R=cfg.pml_R, pml_vmax=vmax, f0_pml=cfg.f0)
+    mt_ = None
+    if wl == "c2":
+        true_m = [synth.dipping_layers_anomalies(2003, cfg.nx, cfg.nz, cfg.dx)]
+        src, rec = synth.c2_geometry(cfg.nshots, cfg.nx)
+        vmax = 4500.0
+        d = S.desc(ndim=2, physics=S.SG_ACOUSTIC_DIV if div else S.SG_ACOUSTIC, nx=cfg.nx, nz=cfg.nz,
+                   npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt, pml_R=cfg.pml_R, pml_vmax=vmax, f0_pml=cfg.f0)
+    elif wl == "c3":
+        true_m = list(synth.elastic_c3(6027, cfg.nx, cfg.nz))
+        src, mt_, rec = synth.c3_geometry(6027, cfg.nx)
+        vmax = 4000.0
+        d = S.desc(ndim=2, physics=S.SG_ELASTIC, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx,
+                   dt=cfg.dt, pml_R=cfg.pml_R, pml_vmax=vmax, f0_pml=cfg.f0_pml)
+    else:
+        true_m = [synth.smooth_3d(4, cfg.nx)]
+        src, rec = synth.c4_geometry(cfg.nx)
+        vmax = 4000.0
+        d = S.desc(ndim=3, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+                   pml_R=cfg.pml_R, pml_vmax=vmax)
+    init_m = [synth.smooth(m, 10.0) for m in true_m]
+    c0 = init_m[0]
+    ns, nrec = src.shape[0], rec.shape[1]
     wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)
     wav = wav[None].repeat(ns, 1).contiguous()
-    sh = S.Shots(src, rec, wav)
+    sh = S.Shots(src, rec, wav, mt=mt_)
     log(f"setup: {cfg.name} nt={nt} ckpt={ckpt} workspace={S.workspace_bytes(d, ns, nrec, ckpt) / 1e9:.1f} GB")
-    mt = S.Model(d, dev(ct), ns, nrec, ckpt)
-    obs = mt.forward(sh, save_ckpt=False)
+
+    def model(ms, **kw):
+        extra = {} if len(ms) == 1 else {"vs": dev(ms[1]), "rho": dev(ms[2])}
+        return S.Model(d, dev(ms[0]), ns, nrec, ckpt, **extra, **kw)
+
+    mtrue = model(true_m)
+    obs = mtrue.forward(sh, save_ckpt=False)
     torch.cuda.synchronize()
-    mt.close()
-    del mt
+    mtrue.close()
+    del mtrue
     # strategy from the autotuner (timed on 4 checkpoint segments of this
     # grid and shot batch, cached, outside the timed region)
     strategy = None
-    if div:
-        args.time_blocking = 1                # one step per launch (the setting applies to the other form)
+    if div or wl != "c2":
+        args.time_blocking = 1                # one step per launch (the setting is the 2-D acoustic form's)
     if args.time_blocking is None:
         from paper_2003_06027_amd import tune
         strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log)
@@ -173,19 +265,21 @@ def main():
         nstore = int(max(0, min(nseg, spare // S.snapshot_segment_bytes(d, ns, ckpt))))
     else:
         nstore = min(args.store_segments, nseg)
-    m = S.Model(d, dev(c0), ns, nrec, ckpt, store_segments=nstore)
+    m = model(init_m, store_segments=nstore)
     log(f"workspace {m.ws.numel() / 1e9:.1f} GB: {nstore} of {nseg} segments keep their snapshots")
     m.set_time_blocking(args.time_blocking)
     seis = torch.empty_like(obs)
     resid = torch.empty_like(obs)
     J = torch.empty(1, dtype=torch.float64, device="cuda")
-    g = torch.empty((1, cfg.nz, cfg.nx), dtype=torch.float32, device="cuda")
+    gshape = (1, cfg.nz, cfg.nx) if cfg.ndim == 2 else (1, cfg.nz, cfg.ny, cfg.nx)
+    g = torch.empty(gshape, dtype=torch.float32, device="cuda")
+    gx = [torch.empty_like(g), torch.empty_like(g)] if wl == "c3" else [None, None]
 
     def step():
         m.forward(sh, seis=seis, save_ckpt=True)
         S._check(S.lib().misfit(m.handle, S._ptr(seis), S._ptr(obs), seis.numel(), S._ptr(J),
                                 S._ptr(resid), S._stream()))
-        m.gradient(sh, resid, g_vp=g)
+        m.gradient(sh, resid, g_vp=g, g_vs=gx[0], g_rho=gx[1])
 
     for i in range(args.warmup):
         step()
@@ -209,13 +303,15 @@ def main():
         torch.cuda.synchronize()
         del a, b
     assert np.isfinite(J.item()) and np.isfinite(g.abs().max().item())
+    copy_gbs = None if args.copy_probe else copy_bandwidth(torch)
 
     T = (t1 - t0) / args.steps
     cells = cfg.padded_cells
     updates = 2.0 * cells * ns * nt
     value = updates / T / 1e9
-    pml_frac = 1.0 - cfg.nx * cfg.nz / cells
-    bpc = bytes_per_cell_step_div(pml_frac) if div else bytes_per_cell_step(pml_frac)
+    pml_frac = 1.0 - cfg.nx * cfg.ny * cfg.nz / cells
+    bpc = (bytes_per_cell_step_div if div else bytes_per_cell_step_el2 if wl == "c3"
+           else bytes_per_cell_step_ac3 if wl == "c4" else bytes_per_cell_step)(pml_frac)
     ph = {}
     for name, (ms, steps) in phases.items():
         if steps == 0:
@@ -226,7 +322,7 @@ def main():
                     "alg_bytes_per_cell": round(bpc[name], 3), "gbs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     dom = max(ph, key=lambda k: phases[k][0])
-    traffic = measured_traffic(dom, div)     # HBM bytes per step (all launches of the step)
+    traffic = measured_traffic(dom, div) if wl == "c2" else None   # HBM bytes per step (all launches)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
@@ -242,9 +338,14 @@ def main():
                    "receivers": nrec,
                    "cell_updates_per_step": updates},
         "roofline": {"bound": "hbm",
-                     "kernel": f"ad2 {dom} step (one fused launch)" if div else f"ac2 {dom} step (PML + interior launches)",
+                     "kernel": (f"ad2 {dom} step (one fused launch)" if div
+                                else f"el2 {dom} step (velocity and stress passes)" if wl == "c3"
+                                else f"ac3 {dom} step (layer and z-marching passes)" if wl == "c4"
+                                else f"ac2 {dom} step (PML + interior launches)"),
                      "achieved": ph[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ph[dom]["frac_hbm"], "traffic": traffic},
+                     "frac": ph[dom]["frac_hbm"], "traffic": traffic,
+                     "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+                     "frac_of_copy": None if copy_gbs is None else round(ph[dom]["gbs"] / copy_gbs, 4)},
         "phases": ph,
     }
     if not args.no_ttm:
@@ -274,12 +375,21 @@ def main():
         }
     if not args.no_cpu:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        ncpu = max(1, min(cores, ns))
-        log(f"cpu baseline: oracle, {ncpu} shots x {args.cpu_steps} steps on {cores} threads")
-        rate, t = cpu_baseline(cfg, c0, src, rec, ncpu, args.cpu_steps, divergence=div)
+        if wl == "c2":
+            ncpu, steps = max(1, min(cores, ns)), args.cpu_steps
+            log(f"cpu baseline: oracle, {ncpu} shots x {steps} steps on {cores} threads")
+            rate, t = cpu_baseline(cfg, c0, src, rec, ncpu, steps, divergence=div)
+        elif wl == "c3":
+            ncpu, steps = 2, min(args.cpu_steps, 300)
+            log(f"cpu baseline: oracle, {ncpu} shots x {steps} steps on {cores} threads")
+            rate, t = cpu_baseline_el2(cfg, init_m, src, mt_, rec, ncpu, steps)
+        else:
+            ncpu, steps = 1, 2
+            log(f"cpu baseline: oracle, 1 shot x {steps} steps on {cores} threads")
+            rate, t = cpu_baseline_ac3(cfg, c0, src, rec, steps)
         out["cpu_baseline"] = {"value": round(rate, 4), "unit": "Gcell-updates/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"{ncpu} shots x {args.cpu_steps} steps of the same grid, FP64 "
+                               "sample": f"{ncpu} shot(s) x {steps} steps of the same grid, FP64 "
                                          f"fwd+adjoint, {t:.1f} s"}
     print(json.dumps(out), flush=True)
 
