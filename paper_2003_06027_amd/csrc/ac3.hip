@@ -62,47 +62,6 @@ __device__ __forceinline__ int xcd_work_id(int nblocks)
     return x * per + min(x, rem) + j;
 }
 
-// Linear index over the layer cells of one shot -> (iz, iy, ix): the two
-// z slabs (P full planes each), then per interior plane its 2-D ring.
-__device__ __forceinline__ void layer_cell3(const Grid3 &g, long long i, int &iz, int &iy, int &ix)
-{
-    const long long pl = (long long)g.NX * g.NY;
-    const long long slab = (long long)g.P * pl;
-    if (i < 2 * slab) {
-        const int top = i < slab;
-        const long long j = top ? i : i - slab;
-        iz = (int)(j / pl);
-        const long long r = j - iz * pl;
-        iy = (int)(r / g.NX);
-        ix = (int)(r - (long long)iy * g.NX);
-        if (!top) iz += g.P + g.nz;
-    } else {
-        const long long j = i - 2 * slab;
-        const long long strip = (long long)g.P * g.NX;
-        const long long ring = 2 * strip + 2LL * g.P * g.ny;
-        const int pz = (int)(j / ring);
-        const long long r = j - pz * ring;
-        iz = g.P + pz;
-        if (r < 2 * strip) {
-            const int top = r < strip;
-            const long long q = top ? r : r - strip;
-            iy = (int)(q / g.NX);
-            ix = (int)(q - (long long)iy * g.NX);
-            if (!top) iy += g.P + g.ny;
-        } else {
-            const long long q = r - 2 * strip;
-            const int row = (int)(q / (2 * g.P)), col = (int)(q - (long long)row * 2 * g.P);
-            iy = g.P + row;
-            ix = col < g.P ? col : col + g.nx;
-        }
-    }
-}
-
-__device__ __forceinline__ long long layer_count3(const Grid3 &g)
-{
-    return (long long)g.NX * g.NY * g.NZ - (long long)g.nx * g.ny * g.nz;
-}
-
 __device__ __forceinline__ bool tile_near_xy(const Grid3 &g, int x0, int y0)
 {
     return g.P > 0 && (x0 - 4 < g.P || x0 + TX3 + 4 > g.P + g.nx || y0 - 4 < g.P || y0 + TY3 + 4 > g.P + g.ny);
@@ -132,28 +91,109 @@ __device__ __forceinline__ void ring_rc(int i, int &r, int &c)
 constexpr int RING3 = 8 * (TX3 + 8) + 8 * TY3;
 
 // ------------------------------------------------------------ forward pass A
-__global__ __launch_bounds__(256) void ac3_phi_kernel(Ac3PhiArgs a)
+// z-marching over the layer work items (every plane of the tiles that touch
+// the layer in x or y, the z slabs of the others), like pass B: u^k and
+// psi^k planes with a 4-cell ring in LDS, 9-plane register windows along z,
+// the next plane's values loaded one plane ahead.  phi is updated at the
+// layer cells only.
+__device__ __forceinline__ bool layer3(const Grid3 &g, int ix, int iy, int iz)
 {
+    return ix < g.P || ix >= g.P + g.nx || iy < g.P || iy >= g.P + g.ny || iz < g.P || iz >= g.P + g.nz;
+}
+
+__device__ __forceinline__ float d8w(const float *q)
+{
+    return D1 * (q[5] - q[3]) + D2 * (q[6] - q[2]) + D3 * (q[7] - q[1]) + D4 * (q[8] - q[0]);
+}
+
+__global__ __launch_bounds__(NTH3) void ac3_phi_kernel(Ac3PhiArgs a)
+{
+    constexpr int W = TX3 + 8;
+    __shared__ float pu[2][(TY3 + 8) * W];
+    __shared__ float pp[2][(TY3 + 8) * W];
     const Grid3 &g = a.g;
-    const long long so = (long long)blockIdx.y * g.plane;
-    const long long n = layer_count3(g);
+    const int w = xcd_work_id((int)gridDim.x);
+    const int shot = w / a.nitems;
+    const int4 it = a.items[w - shot * a.nitems];
+    const int ty = it.x / g.ntx, tx = it.x - ty * g.ntx;
+    const int x0 = tx * TX3, y0 = ty * TY3, z0 = it.y, z1 = it.z;
+    const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
+    const int ix = x0 + lx, iy = y0 + ly;
+    const bool valid_xy = ix < g.NX && iy < g.NY;
+    const long long so = (long long)shot * g.plane;
     const float *u = a.u + so, *psi = a.psi + so;
-    const long long st[3] = {1, g.sy, g.sz};
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
-        int iz, iy, ix;
-        layer_cell3(g, i, iz, iy, ix);
-        const long long f = f3(g, iz, iy, ix);
-        const int id[3] = {ix, iy, iz};
-        const float h[3] = {a.t.h[0][ix], a.t.h[1][iy], a.t.h[2][iz]};
-        const float hs = h[0] + h[1] + h[2];
+    const long long col = f3(g, 0, iy, ix);
+    float qu[9], qp[9];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const float ih = a.t.ih[j][id[j]];
-            const float q = 2.f * (hs - 2.f * h[j]) * ih;
-            const float r = 4.f * a.inv_dt * h[(j + 1) % 3] * h[(j + 2) % 3] * ih;
-            float *ph = a.ph[j] + so;
-            ph[f] = a.t.p[j][id[j]] * ph[f] + q * d8(u + f, st[j]) + r * d8(psi + f, st[j]);
+    for (int m = 0; m < 9; ++m) {
+        const long long o = col + (long long)(z0 - 4 + m) * g.sz;
+        qu[m] = u[o];
+        qp[m] = psi[o];
+    }
+    int rs[2];
+    long long ro[2];
+    float ru[2], rp[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int i = tid + e * NTH3;
+        int r = 0, c = 0;
+        if (i < RING3) ring_rc(i, r, c);
+        rs[e] = i < RING3 ? r * W + c : -1;
+        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
+        const long long o = ro[e] + (long long)z0 * g.sz;
+        ru[e] = rs[e] >= 0 ? u[o] : 0.f;
+        rp[e] = rs[e] >= 0 ? psi[o] : 0.f;
+    }
+    const float hx = valid_xy ? a.t.h[0][ix] : 0.f, hy = valid_xy ? a.t.h[1][iy] : 0.f;
+#pragma unroll 1
+    for (int z = z0; z < z1; ++z) {
+        float *P = pu[z & 1], *Q = pp[z & 1];
+        const int ctr = (ly + 4) * W + lx + 4;
+        P[ctr] = qu[4];
+        Q[ctr] = qp[4];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (rs[e] >= 0) {
+                P[rs[e]] = ru[e];
+                Q[rs[e]] = rp[e];
+            }
+        __syncthreads();
+        float nu = 0.f, np = 0.f;
+        if (z + 1 < z1) {
+            const long long o = col + (long long)(z + 5) * g.sz;
+            nu = u[o];
+            np = psi[o];
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (rs[e] >= 0) {
+                    const long long oe = ro[e] + (long long)(z + 1) * g.sz;
+                    ru[e] = u[oe];
+                    rp[e] = psi[oe];
+                }
         }
+        if (valid_xy && layer3(g, ix, iy, z)) {
+            const long long f = so + col + (long long)z * g.sz;
+            const float h[3] = {hx, hy, a.t.h[2][z]};
+            const int id[3] = {ix, iy, z};
+            const float hs = h[0] + h[1] + h[2];
+            const float du[3] = {d8(P + ctr, 1), d8(P + ctr, W), d8w(qu)};
+            const float dp[3] = {d8(Q + ctr, 1), d8(Q + ctr, W), d8w(qp)};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const float ih = a.t.ih[j][id[j]];
+                const float q = 2.f * (hs - 2.f * h[j]) * ih;
+                const float r = 4.f * a.inv_dt * h[(j + 1) % 3] * h[(j + 2) % 3] * ih;
+                float *ph = a.ph[j];
+                ph[f] = a.t.p[j][id[j]] * ph[f] + q * du[j] + r * dp[j];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            qu[m] = qu[m + 1];
+            qp[m] = qp[m + 1];
+        }
+        qu[8] = nu;
+        qp[8] = np;
     }
 }
 
@@ -194,33 +234,55 @@ __global__ __launch_bounds__(NTH3) void ac3_fwd_kernel(Ac3FwdArgs a)
     float q[9];
     const long long col = f3(g, 0, iy, ix);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) q[m] = u[col + (long long)(z0 - 4 + m) * g.sz];
+    for (int m = 0; m < 9; ++m) q[m] = u[col + (long long)(z0 - 4 + m) * g.sz];
+    // this thread's (at most two) halo-ring cells of every plane: LDS slot and
+    // plane-0 frame offset, and their values for the current plane, loaded
+    // one plane ahead so that the loads overlap the previous plane's work
+    int rs[2];
+    long long ro[2];
+    float rv[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int i = tid + e * NTH3;
+        int r = 0, c = 0;
+        if (i < RING3) ring_rc(i, r, c);
+        rs[e] = i < RING3 ? r * W + c : -1;
+        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
+        rv[e] = rs[e] >= 0 ? u[ro[e] + (long long)z0 * g.sz] : 0.f;
+    }
 
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        q[8] = u[col + (long long)(z + 4) * g.sz];
         float *P = pl[z & 1];
         P[(ly + 4) * W + lx + 4] = q[4];
-        for (int i = tid; i < RING3; i += NTH3) {
-            int r, c;
-            ring_rc(i, r, c);
-            P[r * W + c] = u[f3(g, z, y0 - 4 + r, x0 - 4 + c)];
-        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (rs[e] >= 0) P[rs[e]] = rv[e];
+        const long long f = col + (long long)z * g.sz;
+        const float umf = valid_xy ? um[f] : 0.f;
+        const float chf = valid_xy ? chat[f] : 0.f;
         __syncthreads();
+        // next plane: the window's new value and the ring
+        float qn = 0.f;
+        if (z + 1 < z1) {
+            qn = u[col + (long long)(z + 5) * g.sz];
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (rs[e] >= 0) rv[e] = u[ro[e] + (long long)(z + 1) * g.sz];
+        }
         const float *cc = P + (ly + 4) * W + lx + 4;
         const float c0 = q[4];
         float wv = A4 * (pair(cc, 4, c0) + pair(cc, 4 * W, c0) + ((q[8] - c0) + (q[0] - c0)))
                  + A3 * (pair(cc, 3, c0) + pair(cc, 3 * W, c0) + ((q[7] - c0) + (q[1] - c0)))
                  + A2 * (pair(cc, 2, c0) + pair(cc, 2 * W, c0) + ((q[6] - c0) + (q[2] - c0)))
                  + A1 * (pair(cc, 1, c0) + pair(cc, W, c0) + ((q[5] - c0) + (q[3] - c0)));
-        const long long f = col + (long long)z * g.sz;
         float un = 0.f;
         if (valid_xy) {
             if (near_xy || plane_near_z(g, z)) {
                 wv += d8(a.ph[0] + so + f, 1) + d8(a.ph[1] + so + f, g.sy) + d8(a.ph[2] + so + f, g.sz);
                 const float hx = a.t.h[0][ix], hy = a.t.h[1][iy], hz = a.t.h[2][z];
                 const float hs = hx + hy + hz;
-                const float umf = um[f];
-                float inc = (c0 - umf) + (hs * umf - 4.f * (hx * hy + hy * hz + hz * hx) * c0) + chat[f] * wv;
+                float inc = (c0 - umf) + (hs * umf - 4.f * (hx * hy + hy * hz + hz * hx) * c0) + chf * wv;
                 float ps = 0.f;
                 if (hs > 0.f) {
                     ps = a.psi[so + f];
@@ -230,7 +292,7 @@ __global__ __launch_bounds__(NTH3) void ac3_fwd_kernel(Ac3FwdArgs a)
                 un = (c0 + inc) / (1.f + hs);
                 if (hs > 0.f) a.psi[so + f] = ps + a.dt * un;
             } else {
-                float inc = (c0 - um[f]) + chat[f] * wv;
+                float inc = (c0 - umf) + chf * wv;
                 if (f == src) inc += sval;
                 un = c0 + inc;
             }
@@ -253,34 +315,81 @@ __global__ __launch_bounds__(NTH3) void ac3_fwd_kernel(Ac3FwdArgs a)
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) q[m] = q[m + 1];
+        q[8] = qn;
     }
 }
 
 // ------------------------------------------------------------ adjoint pass A
-__global__ __launch_bounds__(256) void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
+// Same work items and marching, on chat s^{k+2}.
+__global__ __launch_bounds__(NTH3) void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
 {
+    constexpr int W = TX3 + 8;
+    __shared__ float pc[2][(TY3 + 8) * W];
     const Grid3 &g = a.g;
-    const long long so = (long long)blockIdx.y * g.plane;
-    const long long n = layer_count3(g);
+    const int w = xcd_work_id((int)gridDim.x);
+    const int shot = w / a.nitems;
+    const int4 it = a.items[w - shot * a.nitems];
+    const int ty = it.x / g.ntx, tx = it.x - ty * g.ntx;
+    const int x0 = tx * TX3, y0 = ty * TY3, z0 = it.y, z1 = it.z;
+    const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
+    const int ix = x0 + lx, iy = y0 + ly;
+    const bool valid_xy = ix < g.NX && iy < g.NY;
+    const long long so = (long long)shot * g.plane;
     const float *s2 = a.s2 + so;
-    const float *chat = a.chat + (long long)(blockIdx.y / a.shots_per_model) * g.plane;
-    const long long st[3] = {1, g.sy, g.sz};
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
-        int iz, iy, ix;
-        layer_cell3(g, i, iz, iy, ix);
-        const long long f = f3(g, iz, iy, ix);
-        const int id[3] = {ix, iy, iz};
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const long long col = f3(g, 0, iy, ix);
+    float q[9];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            float d = 0.f;
+    for (int m = 0; m < 9; ++m) {
+        const long long o = col + (long long)(z0 - 4 + m) * g.sz;
+        q[m] = chat[o] * s2[o];
+    }
+    int rs[2];
+    long long ro[2];
+    float rv[2];
 #pragma unroll
-            for (int m = 1; m <= 4; ++m) {
-                const long long o = m * st[j];
-                d += dcoef(m) * (chat[f + o] * s2[f + o] - chat[f - o] * s2[f - o]);
-            }
-            float *b = a.b[j] + so;
-            b[f] = a.t.p[j][id[j]] * b[f] - d;
+    for (int e = 0; e < 2; ++e) {
+        const int i = tid + e * NTH3;
+        int r = 0, c = 0;
+        if (i < RING3) ring_rc(i, r, c);
+        rs[e] = i < RING3 ? r * W + c : -1;
+        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
+        const long long o = ro[e] + (long long)z0 * g.sz;
+        rv[e] = rs[e] >= 0 ? chat[o] * s2[o] : 0.f;
+    }
+#pragma unroll 1
+    for (int z = z0; z < z1; ++z) {
+        float *P = pc[z & 1];
+        const int ctr = (ly + 4) * W + lx + 4;
+        P[ctr] = q[4];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (rs[e] >= 0) P[rs[e]] = rv[e];
+        __syncthreads();
+        float nq = 0.f;
+        if (z + 1 < z1) {
+            const long long o = col + (long long)(z + 5) * g.sz;
+            nq = chat[o] * s2[o];
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (rs[e] >= 0) {
+                    const long long oe = ro[e] + (long long)(z + 1) * g.sz;
+                    rv[e] = chat[oe] * s2[oe];
+                }
         }
+        if (valid_xy && layer3(g, ix, iy, z)) {
+            const long long f = so + col + (long long)z * g.sz;
+            const int id[3] = {ix, iy, z};
+            const float d[3] = {d8(P + ctr, 1), d8(P + ctr, W), d8w(q)};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                float *b = a.b[j];
+                b[f] = a.t.p[j][id[j]] * b[f] - d[j];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) q[m] = q[m + 1];
+        q[8] = nq;
     }
 }
 
@@ -317,26 +426,47 @@ __global__ __launch_bounds__(NTH3) void ac3_adj_kernel(Ac3AdjArgs a)
     float sraw;        // s^{k+2} at (z, own column)
     const long long col = f3(g, 0, iy, ix);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
+    for (int m = 0; m < 9; ++m) {
         const long long o = col + (long long)(z0 - 4 + m) * g.sz;
         q[m] = chat[o] * s2[o];
     }
+    // halo-ring cells of this thread, loaded one plane ahead (as in the forward)
+    int rs[2];
+    long long ro[2];
+    float rv[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int i = tid + e * NTH3;
+        int r = 0, c = 0;
+        if (i < RING3) ring_rc(i, r, c);
+        rs[e] = i < RING3 ? r * W + c : -1;
+        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
+        const long long o = ro[e] + (long long)z0 * g.sz;
+        rv[e] = rs[e] >= 0 ? chat[o] * s2[o] : 0.f;
+    }
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        {
-            const long long o = col + (long long)(z + 4) * g.sz;
-            q[8] = chat[o] * s2[o];
-        }
         const long long f = col + (long long)z * g.sz;
         sraw = s2[f];
         float *P = pl[z & 1];
         P[(ly + 4) * W + lx + 4] = q[4];
-        for (int i = tid; i < RING3; i += NTH3) {
-            int r, c;
-            ring_rc(i, r, c);
-            const long long o = f3(g, z, y0 - 4 + r, x0 - 4 + c);
-            P[r * W + c] = chat[o] * s2[o];
-        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (rs[e] >= 0) P[rs[e]] = rv[e];
+        const float s3f = valid_xy ? s3[f] : 0.f;
+        const float snf = valid_xy ? a.snap[so + f] : 0.f;
         __syncthreads();
+        float qn = 0.f;
+        if (z + 1 < z1) {
+            const long long o = col + (long long)(z + 5) * g.sz;
+            qn = chat[o] * s2[o];
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (rs[e] >= 0) {
+                    const long long oe = ro[e] + (long long)(z + 1) * g.sz;
+                    rv[e] = chat[oe] * s2[oe];
+                }
+        }
         const float *cc = P + (ly + 4) * W + lx + 4;
         const float c0 = q[4];
         float v = A4 * (pair(cc, 4, c0) + pair(cc, 4 * W, c0) + ((q[8] - c0) + (q[0] - c0)))
@@ -376,10 +506,9 @@ __global__ __launch_bounds__(NTH3) void ac3_adj_kernel(Ac3AdjArgs a)
                     a.e[so + f] = en;
                     v += a.dt * en;
                 }
-                const float s3f = s3[f];
                 v += sraw + ((sraw - s3f) + (hs * s3f - 4.f * (h[0] * h[1] + h[1] * h[2] + h[2] * h[0]) * sraw));
             } else {
-                v += sraw + (sraw - s3[f]);
+                v += sraw + (sraw - s3f);
             }
         }
         // receiver residual injection (deterministic per cell)
@@ -404,11 +533,12 @@ __global__ __launch_bounds__(NTH3) void ac3_adj_kernel(Ac3AdjArgs a)
         if (valid_xy) {
             const float s1 = nearz ? v / (1.f + hs) : v;
             s3[f] = s1;
-            a.grad[so + f] += s1 * a.snap[so + f];
+            a.grad[so + f] += s1 * snf;
             if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) q[m] = q[m + 1];
+        q[8] = qn;
     }
 }
 
@@ -474,24 +604,18 @@ __global__ void ac3_finalize_kernel(Grid3 g, int nmodels, const float *acc, cons
     }
 }
 
-int layer_blocks3(const Grid3 &g)
-{
-    const long long n = (long long)g.NX * g.NY * g.NZ - (long long)g.nx * g.ny * g.nz;
-    return (int)std::min<long long>(std::max<long long>((n + 255) / 256, 1), 8192);
-}
-
 } // namespace
 
 void launch_ac3_phi(const Ac3PhiArgs &a, int nshots, hipStream_t s)
 {
-    if (a.g.P == 0 || nshots == 0) return;
-    ac3_phi_kernel<<<dim3(layer_blocks3(a.g), nshots), 256, 0, s>>>(a);
+    if (a.g.P == 0 || nshots == 0 || a.nitems == 0) return;
+    ac3_phi_kernel<<<a.nitems * nshots, NTH3, 0, s>>>(a);
 }
 
 void launch_ac3_phi_adj(const Ac3PhiAdjArgs &a, int nshots, hipStream_t s)
 {
-    if (a.g.P == 0 || nshots == 0) return;
-    ac3_phi_adj_kernel<<<dim3(layer_blocks3(a.g), nshots), 256, 0, s>>>(a);
+    if (a.g.P == 0 || nshots == 0 || a.nitems == 0) return;
+    ac3_phi_adj_kernel<<<a.nitems * nshots, NTH3, 0, s>>>(a);
 }
 
 void launch_ac3_fwd(const Ac3FwdArgs &a, hipStream_t s)

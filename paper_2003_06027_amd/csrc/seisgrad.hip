@@ -69,7 +69,7 @@ struct Layout {
     int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
         off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt,
-        off_tiles, off_soff, off_sent, off_nodef, total;
+        off_tiles, off_soff, off_sent, off_nodef, off_items, total;
 };
 
 int check_desc(const sg_desc *d)
@@ -182,6 +182,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_soff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
     L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
+    L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * (L.g3.nzc + 2) : 0);
     L.total = o;
     return L;
 }
@@ -213,6 +214,10 @@ struct sg_model {
     int *tiles_layer = nullptr;
     int n_layer = 0;
     std::vector<int> h_layer;
+    // 3-D acoustic layer pass: (xy tile, first plane, end plane) work items
+    int4 *items3 = nullptr;
+    int n_items3 = 0;
+    std::vector<int4> h_items3;
     int steps_per_launch = 2;
     // snapshots of the last n_store checkpoint segments, written by a
     // checkpointed forward into the workspace beyond its minimum size
@@ -806,6 +811,8 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
     } else {
         Ac3PhiArgs p{};
         p.g = m->L.g3;
+        p.items = m->items3;
+        p.nitems = m->n_items3;
         p.u = m->fwd[cu];
         p.psi = m->fwd[5];
         for (int j = 0; j < 3; ++j) p.ph[j] = m->fwd[2 + j];
@@ -941,6 +948,8 @@ void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float
     } else {
         Ac3PhiAdjArgs pa{};
         pa.g = m->L.g3;
+        pa.items = m->items3;
+        pa.nitems = m->n_items3;
         pa.s2 = m->adj[ca];
         pa.chat = m->chat;
         pa.shots_per_model = spm;
@@ -1178,7 +1187,25 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
             }
         }
     }
+    if (d->ndim == 3 && d->npml > 0) {
+        // every plane of the xy tiles that touch the layer in x or y; the two
+        // z slabs of the others
+        const Grid3 &g = L.g3;
+        m->items3 = reinterpret_cast<int4 *>(m->ws + L.off_items);
+        for (int t = 0; t < L.ntiles; ++t) {
+            const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
+            const bool xy = x0 < g.P || x0 + TX3 > g.P + g.nx || y0 < g.P || y0 + TY3 > g.P + g.ny;
+            auto add = [&](int za, int zb) {
+                for (int z = za; z < zb; z += TZC) m->h_items3.push_back(make_int4(t, z, std::min(z + TZC, zb), 0));
+            };
+            if (xy) add(0, g.NZ);
+            else { add(0, g.P); add(g.P + g.nz, g.NZ); }
+        }
+        m->n_items3 = (int)m->h_items3.size();
+    }
     hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && m->n_items3 > 0)
+        e = hipMemcpyAsync(m->items3, m->h_items3.data(), sizeof(int4) * m->n_items3, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m->n_layer > 0)
         e = hipMemcpyAsync(m->tiles_layer, m->h_layer.data(), sizeof(int) * m->n_layer, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {

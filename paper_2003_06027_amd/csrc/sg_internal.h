@@ -183,8 +183,8 @@ __host__ __device__ inline int src_node(int e) { return e & ((1 << SRC_NODE_BITS
 // ---------------------------------------------------------------- 3-D
 // Tile of the 3-D kernels: TX3 x TY3 columns (one thread each), marching in
 // z over chunks of TZC planes with a register window of 9 planes.
-constexpr int TX3 = 64;
-constexpr int TY3 = 8;
+constexpr int TX3 = 32;
+constexpr int TY3 = 16;
 constexpr int NTH3 = TX3 * TY3;
 constexpr int TZC = 64;
 constexpr int OX3 = 32;  // x offset (128-byte aligned rows)
@@ -228,6 +228,8 @@ struct Ac3FwdArgs {
 
 struct Ac3PhiArgs {
     Grid3 g;
+    const int4 *items;         // (xy tile, first plane, end plane) of the layer work
+    int nitems;
     const float *u, *psi;      // u^k, psi^k
     float *ph[3];              // in place
     Ac3Tabs t;
@@ -236,6 +238,8 @@ struct Ac3PhiArgs {
 
 struct Ac3PhiAdjArgs {
     Grid3 g;
+    const int4 *items;         // as in Ac3PhiArgs
+    int nitems;
     const float *s2;
     const float *chat;
     int shots_per_model;
