@@ -24,6 +24,9 @@
 //             s^{k+1} = alpha a^{k+1};  dJ/dchat += s^{k+1} w~^k
 #include "sg_internal.h"
 
+#include <climits>
+#include <type_traits>
+
 namespace sg {
 namespace {
 
@@ -105,9 +108,9 @@ constexpr int RING3 = 8 * (TX3 + 8) + 8 * TY3;
 // ------------------------------------------------------------ forward pass A
 // z-marching over the layer work items (every plane of the tiles that touch
 // the layer in x or y, the z slabs of the others), like pass B: u^k and
-// psi^k planes with a 4-cell ring in LDS, 9-plane register windows along z,
-// the next plane's values loaded one plane ahead.  phi is updated at the
-// layer cells only.
+// psi^k planes with a 4-cell ring in LDS, register windows along z, the
+// operands of the next plane loaded one plane ahead into rings (the scheme of
+// pass B below).  phi is updated at the layer cells only.
 __device__ __forceinline__ bool layer3(const Grid3 &g, int ix, int iy, int iz)
 {
     return ix < g.P || ix >= g.P + g.nx || iy < g.P || iy >= g.P + g.ny || iz < g.P || iz >= g.P + g.nz;
@@ -118,7 +121,68 @@ __device__ __forceinline__ float d8w(const float *q)
     return D1 * (q[5] - q[3]) + D2 * (q[6] - q[2]) + D3 * (q[7] - q[1]) + D4 * (q[8] - q[0]);
 }
 
-__global__ __launch_bounds__(NTH3) void ac3_phi_kernel(Ac3PhiArgs a)
+
+// ------------------------------------------------------------ forward pass B
+// Two launches over (xy tile, z chunk, shot): the tiles within 4 cells of the
+// layer in x or y (LAYER: every plane takes the layer terms) and the others
+// (only the z slabs do; their cells are interior in x and y, hx = hy = 0).
+// In LAYER tiles the layer auxiliaries are staged like u: phi_x with its x
+// halo and phi_y with its y halo in LDS planes, phi_z in a register window;
+// the other tiles read the few stencil points of their slab planes directly.
+//
+// Every per-plane operand is loaded PD planes ahead into registers that the
+// planes in between do not use: the z windows are rings of ZR registers (9
+// in use, the next PD receiving planes z + 5 ..), the other operands rings of
+// NB = PD + 1, and the z loop is unrolled by ZR so that ring positions are
+// compile-time constants.  The prefetch loads are unconditional (addresses
+// stay inside the frame; unused values are dropped) and so are the stores
+// that follow them, so that the memory counter waits are exact and do not
+// wait for the loads just issued; the conditional psi store of a plane is
+// issued at the start of the next one, before its prefetch.  Addresses are
+// 32-bit byte offsets from per-block bases at the chunk's first window plane
+// (the host bounds (TZC + 8) planes below 4 GiB).
+constexpr int PD = 1, NB = PD + 1, ZR = 10;
+static_assert(ZR % NB == 0 && 8 + PD < ZR, "ring sizes");
+static_assert(RING3 <= NTH3, "one halo-ring cell per thread");
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>)
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+__device__ __forceinline__ void tab_at(const float *h, const float *ih, int i, int n, float &hv, float &ihv)
+{
+    const bool in = i >= -4 && i < n + 4;     // the tables' extent
+    hv = in ? h[i] : 0.f;
+    ihv = in ? ih[i] : 1.f;
+}
+
+__device__ __forceinline__ float ldb(const float *b, unsigned o)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(b) + o);
+}
+__device__ __forceinline__ void stb(float *b, unsigned o, float v)
+{
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(b) + o) = v;
+}
+// d8 at byte offset o with byte stride sb
+__device__ __forceinline__ float d8b(const float *b, unsigned o, unsigned sb)
+{
+    return D1 * (ldb(b, o + sb) - ldb(b, o - sb)) + D2 * (ldb(b, o + 2 * sb) - ldb(b, o - 2 * sb))
+         + D3 * (ldb(b, o + 3 * sb) - ldb(b, o - 3 * sb)) + D4 * (ldb(b, o + 4 * sb) - ldb(b, o - 4 * sb));
+}
+
+// forward pass A (described above): phi~_j^k = p_j phi~_j^{k-1} + q_j D~_j u^k + r_j D~_j psi^k
+constexpr int LPD = 1, LNB = LPD + 1, LZR = 10;
+static_assert(LZR % LNB == 0 && 8 + LPD < LZR, "ring sizes");
+
+__global__ __launch_bounds__(NTH3) __attribute__((amdgpu_waves_per_eu(8)))
+void ac3_phi_kernel(Ac3PhiArgs a)
 {
     constexpr int W = TX3 + 8;
     __shared__ float pu[2][(TY3 + 8) * W];
@@ -132,206 +196,330 @@ __global__ __launch_bounds__(NTH3) void ac3_phi_kernel(Ac3PhiArgs a)
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
     const int ix = x0 + lx, iy = y0 + ly;
     const bool valid_xy = ix < g.NX && iy < g.NY;
-    const long long so = (long long)shot * g.plane;
-    const float *u = a.u + so, *psi = a.psi + so;
-    const long long col = f3(g, 0, iy, ix);
-    float qu[9], qp[9];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        const long long o = col + (long long)(z0 - 4 + m) * g.sz;
-        qu[m] = u[o];
-        qp[m] = psi[o];
-    }
-    int rs[2];
-    long long ro[2];
-    float ru[2], rp[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int i = tid + e * NTH3;
+    const bool layer_xy = ix < g.P || ix >= g.P + g.nx || iy < g.P || iy >= g.P + g.ny;
+    const long long zb0 = (long long)shot * g.plane + (long long)(z0 + OZ3 - 4) * g.sz;
+    const float *u = a.u + zb0, *psi = a.psi + zb0;
+    float *ph0 = a.ph[0] + zb0, *ph1 = a.ph[1] + zb0, *ph2 = a.ph[2] + zb0;
+    const unsigned SZB = (unsigned)g.sz * 4u;
+    auto pb = [&](int z) { return (unsigned)(z - z0 + 4) * SZB; };
+    auto pbc = [&](int z) { return pb(min(z, g.NZ + 3)); };
+    const unsigned colb = (unsigned)((iy + OY3) * g.sy + ix + OX3) * 4u;
+    int rs;
+    unsigned rob;
+    {
         int r = 0, c = 0;
-        if (i < RING3) ring_rc(i, r, c);
-        rs[e] = i < RING3 ? r * W + c : -1;
-        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
-        const long long o = ro[e] + (long long)z0 * g.sz;
-        ru[e] = rs[e] >= 0 ? u[o] : 0.f;
-        rp[e] = rs[e] >= 0 ? psi[o] : 0.f;
+        if (tid < RING3) ring_rc(tid, r, c);
+        rs = tid < RING3 ? r * W + c : -1;
+        rob = (unsigned)((y0 - 4 + r + OY3) * g.sy + x0 - 4 + c + OX3) * 4u;
     }
-    const float hx = valid_xy ? a.t.h[0][ix] : 0.f, hy = valid_xy ? a.t.h[1][iy] : 0.f;
+    float qu[LZR], qp[LZR], ru[LNB], rp[LNB], f0[LNB], f1[LNB], f2[LNB];
+#pragma unroll
+    for (int m = 0; m < 8 + LPD; ++m) {
+        const unsigned o = colb + pbc(z0 - 4 + m);
+        qu[m] = ldb(u, o);
+        qp[m] = ldb(psi, o);
+    }
+#pragma unroll
+    for (int d = 0; d < LPD; ++d) {
+        const unsigned o = pbc(z0 + d);
+        ru[d] = ldb(u, rob + o);
+        rp[d] = ldb(psi, rob + o);
+        f0[d] = ldb(ph0, colb + o);
+        f1[d] = ldb(ph1, colb + o);
+        f2[d] = ldb(ph2, colb + o);
+    }
+    // per-column coefficients of x and y
+    float hx = 0.f, hy = 0.f, ihx = 1.f, ihy = 1.f, px = 1.f, py = 1.f;
+    if (valid_xy) {
+        hx = a.t.h[0][ix]; ihx = a.t.ih[0][ix]; px = a.t.p[0][ix];
+        hy = a.t.h[1][iy]; ihy = a.t.ih[1][iy]; py = a.t.p[1][iy];
+    }
+    // phi of the previous plane, stored at the start of the next
+    bool fw = false;
+    float fn0 = 0.f, fn1 = 0.f, fn2 = 0.f;
+    unsigned ff = 0;
+
 #pragma unroll 1
-    for (int z = z0; z < z1; ++z) {
-        float *P = pu[z & 1], *Q = pp[z & 1];
-        const int ctr = (ly + 4) * W + lx + 4;
-        P[ctr] = qu[4];
-        Q[ctr] = qp[4];
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-            if (rs[e] >= 0) {
-                P[rs[e]] = ru[e];
-                Q[rs[e]] = rp[e];
+    for (int zb = z0; zb < z1; zb += LZR) {
+        const int zbo = __builtin_amdgcn_readfirstlane(zb);
+        static_for<LZR>([&](auto R) __attribute__((always_inline)) {
+            constexpr int r = decltype(R)::value;
+            constexpr int c = r % LNB, n = (r + LPD) % LNB;
+            const int z = zbo + r;
+            if (z >= z1) return;
+            if (fw) {
+                stb(ph0, ff, fn0);
+                stb(ph1, ff, fn1);
+                stb(ph2, ff, fn2);
             }
-        __syncthreads();
-        float nu = 0.f, np = 0.f;
-        if (z + 1 < z1) {
-            const long long o = col + (long long)(z + 5) * g.sz;
-            nu = u[o];
-            np = psi[o];
+            fw = false;
+            float *P = pu[z & 1], *Q = pp[z & 1];
+            const int ctr = (ly + 4) * W + lx + 4;
+            P[ctr] = qu[(r + 4) % LZR];
+            Q[ctr] = qp[(r + 4) % LZR];
+            if (rs >= 0) {
+                P[rs] = ru[c];
+                Q[rs] = rp[c];
+            }
+            const unsigned fb = colb + pb(z);
+            __syncthreads();
+            {
+                const unsigned d1 = pbc(z + LPD), dw = colb + pbc(z + 4 + LPD);
+                ru[n] = ldb(u, rob + d1);
+                rp[n] = ldb(psi, rob + d1);
+                qu[(r + 8 + LPD) % LZR] = ldb(u, dw);
+                qp[(r + 8 + LPD) % LZR] = ldb(psi, dw);
+                f0[n] = ldb(ph0, colb + d1);
+                f1[n] = ldb(ph1, colb + d1);
+                f2[n] = ldb(ph2, colb + d1);
+            }
+            if (valid_xy && (layer_xy || z < g.P || z >= g.P + g.nz)) {
+                float wu[9], wp[9];
 #pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (rs[e] >= 0) {
-                    const long long oe = ro[e] + (long long)(z + 1) * g.sz;
-                    ru[e] = u[oe];
-                    rp[e] = psi[oe];
+                for (int m = 0; m < 9; ++m) {
+                    wu[m] = qu[(r + m) % LZR];
+                    wp[m] = qp[(r + m) % LZR];
                 }
-        }
-        if (valid_xy && layer3(g, ix, iy, z)) {
-            const long long f = so + col + (long long)z * g.sz;
-            const float h[3] = {hx, hy, a.t.h[2][z]};
-            const int id[3] = {ix, iy, z};
-            const float hs = h[0] + h[1] + h[2];
-            const float du[3] = {d8(P + ctr, 1), d8(P + ctr, W), d8w(qu)};
-            const float dp[3] = {d8(Q + ctr, 1), d8(Q + ctr, W), d8w(qp)};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const float ih = a.t.ih[j][id[j]];
-                const float q = 2.f * (hs - 2.f * h[j]) * ih;
-                const float r = 4.f * a.inv_dt * h[(j + 1) % 3] * h[(j + 2) % 3] * ih;
-                float *ph = a.ph[j];
-                ph[f] = a.t.p[j][id[j]] * ph[f] + q * du[j] + r * dp[j];
+                const float hz = a.t.h[2][z], ihz = a.t.ih[2][z], pz = a.t.p[2][z];
+                const float hs = hx + hy + hz;
+                const float k4 = 4.f * a.inv_dt;
+                fn0 = px * f0[c] + 2.f * (hs - 2.f * hx) * ihx * d8(P + ctr, 1) + k4 * hy * hz * ihx * d8(Q + ctr, 1);
+                fn1 = py * f1[c] + 2.f * (hs - 2.f * hy) * ihy * d8(P + ctr, W) + k4 * hz * hx * ihy * d8(Q + ctr, W);
+                fn2 = pz * f2[c] + 2.f * (hs - 2.f * hz) * ihz * d8w(wu) + k4 * hx * hy * ihz * d8w(wp);
+                fw = true;
+                ff = fb;
             }
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            qu[m] = qu[m + 1];
-            qp[m] = qp[m + 1];
-        }
-        qu[8] = nu;
-        qp[8] = np;
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+    if (fw) {
+        stb(ph0, ff, fn0);
+        stb(ph1, ff, fn1);
+        stb(ph2, ff, fn2);
     }
 }
 
-// ------------------------------------------------------------ forward pass B
-template <bool SNAP, bool REC>
-__global__ __launch_bounds__(NTH3) void ac3_fwd_kernel(Ac3FwdArgs a)
+template <bool SNAP, bool REC, bool LAYER>
+__global__ __launch_bounds__(NTH3) __attribute__((amdgpu_waves_per_eu(LAYER ? 4 : 8)))
+void ac3_fwd_kernel(Ac3FwdArgs a)
 {
     constexpr int W = TX3 + 8;
+    constexpr int WX = TX3 + 8, WY = TX3;      // phi_x plane: TY3 rows of WX; phi_y: TY3 + 8 rows of WY
     __shared__ float pl[2][(TY3 + 8) * W];
+    __shared__ float sphx[LAYER ? 2 * TY3 * WX : 1];
+    __shared__ float sphy[LAYER ? 2 * (TY3 + 8) * WY : 1];
     __shared__ float xch[REC ? TX3 * TY3 : 1];
     const Grid3 &g = a.g;
+    const int w = xcd_work_id(a.ntl * g.nzc * a.nshots);
+    const int shot = w / (a.ntl * g.nzc);
+    const int rem = w - shot * a.ntl * g.nzc;
+    const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
     const int nxy = g.ntx * g.nty;
-    const int w = xcd_work_id(nxy * g.nzc * a.nshots);
-    const int shot = w / (nxy * g.nzc);
-    const int rem = w - shot * nxy * g.nzc;
-    const int zc = rem / nxy, tile = rem - zc * nxy;
     const int ty = tile / g.ntx, tx = tile - ty * g.ntx;
     const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * TZC, z1 = min(z0 + TZC, g.NZ);
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
     const int ix = x0 + lx, iy = y0 + ly;
     const bool valid_xy = ix < g.NX && iy < g.NY;
-    const bool near_xy = tile_near_xy(g, x0, y0);
-    const long long so = (long long)shot * g.plane;
-    const float *u = a.u + so;
-    float *um = a.um + so;
-    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    // bases at plane z0 - 4 of this shot; plane z at byte offset pb(z)
+    const long long zoff = (long long)(z0 + OZ3 - 4) * g.sz;
+    const long long zb0 = (long long)shot * g.plane + zoff;
+    const float *u = a.u + zb0;
+    float *um = a.um + zb0;
+    float *psi = a.psi + zb0;
+    float *snap = a.snap + zb0;
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane + zoff;
+    const float *phx = a.ph[0] + zb0, *phy = a.ph[1] + zb0, *phz = a.ph[2] + zb0;
+    const unsigned SZB = (unsigned)g.sz * 4u, SYB = (unsigned)g.sy * 4u;
+    auto pb = [&](int z) { return (unsigned)(z - z0 + 4) * SZB; };
+    auto pbc = [&](int z) { return pb(min(z, g.NZ + 3)); };
+    const unsigned colb = (unsigned)((iy + OY3) * g.sy + ix + OX3) * 4u;
+    // the source cell as (plane, in-plane byte offset)
     const long long src = a.src_f[shot];
+    const int srcp = (int)(src / g.sz) - OZ3;
+    const unsigned srcc = (unsigned)(src - (long long)(srcp + OZ3) * g.sz) * 4u;
     const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
 
-    int rb = 0, re = 0;
+    // receivers of this tile and chunk, by plane; zr = plane of the next one
+    int rb = 0, re = 0, zr = INT_MAX;
     if constexpr (REC) {
         const int *off = a.rec_off + (long long)shot * (nxy + 1);
         rb = off[tile];
         re = off[tile + 1];
         while (rb < re && (a.rec_ent[rb].x >> CELL3_BITS) < z0) ++rb;
+        if (rb < re) zr = a.rec_ent[rb].x >> CELL3_BITS;
     }
 
-    float q[9];
-    const long long col = f3(g, 0, iy, ix);
+    // window: planes z0 - 4 .. z0 + 3 + PD; the rings: planes z0 .. z0 + PD - 1
+    float q[ZR];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) q[m] = u[col + (long long)(z0 - 4 + m) * g.sz];
-    // this thread's (at most two) halo-ring cells of every plane: LDS slot and
-    // plane-0 frame offset, and their values for the current plane, loaded
-    // one plane ahead so that the loads overlap the previous plane's work
-    int rs[2];
-    long long ro[2];
-    float rv[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int i = tid + e * NTH3;
+    for (int m = 0; m < 8 + PD; ++m) q[m] = ldb(u, colb + pbc(z0 - 4 + m));
+    // this thread's halo-ring cell of every plane (if any): LDS slot and
+    // in-plane byte offset (a cell of the ring's row 0 for threads without)
+    int rs;
+    unsigned rob;
+    float rv[NB], umv[NB], chv[NB];
+    {
         int r = 0, c = 0;
-        if (i < RING3) ring_rc(i, r, c);
-        rs[e] = i < RING3 ? r * W + c : -1;
-        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
-        rv[e] = rs[e] >= 0 ? u[ro[e] + (long long)z0 * g.sz] : 0.f;
+        if (tid < RING3) ring_rc(tid, r, c);
+        rs = tid < RING3 ? r * W + c : -1;
+        rob = (unsigned)((y0 - 4 + r + OY3) * g.sy + x0 - 4 + c + OX3) * 4u;
     }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+        rv[d] = ldb(u, rob + pbc(z0 + d));
+        umv[d] = ldb(um, colb + pbc(z0 + d));
+        chv[d] = ldb(chat, colb + pbc(z0 + d));
+    }
+    // LAYER: the phi_z window, this column's phi_x, phi_y and psi, and one
+    // halo cell: of phi_x (the first 8 TY3 threads) or of phi_y (the next 8 TX3)
+    float pz[LAYER ? ZR : 1], pxv[NB], pyv[NB], hvv[NB], psv[NB];
+    int hslot = -1;
+    const float *hsrc = phx;
+    unsigned hob = colb;
+    float hx = 0.f, hy = 0.f;
+    if constexpr (LAYER) {
+#pragma unroll
+        for (int m = 0; m < 8 + PD; ++m) pz[m] = ldb(phz, colb + pbc(z0 - 4 + m));
+        if (tid < 8 * TY3) {
+            const int r = tid / 8, c = tid % 8, cx = c < 4 ? c : c + TX3;
+            hslot = r * WX + cx;
+            hob = (unsigned)((y0 + r + OY3) * g.sy + x0 - 4 + cx + OX3) * 4u;
+        } else if (tid < 8 * TY3 + 8 * TX3) {
+            const int i = tid - 8 * TY3, r = i / TX3, c = i % TX3, ry = r < 4 ? r : r + TY3;
+            hslot = TY3 * WX + ry * WY + c;    // past the phi_x plane: one index space for both
+            hsrc = phy;
+            hob = (unsigned)((y0 - 4 + ry + OY3) * g.sy + x0 + c + OX3) * 4u;
+        }
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+            const unsigned o = pbc(z0 + d);
+            pxv[d] = ldb(phx, colb + o);
+            pyv[d] = ldb(phy, colb + o);
+            psv[d] = ldb(psi, colb + o);
+            hvv[d] = ldb(hsrc, hob + o);
+        }
+        if (valid_xy) {
+            hx = a.t.h[0][ix];
+            hy = a.t.h[1][iy];
+        }
+    }
+    // psi^{k+1} of the previous plane, stored at the start of the next
+    bool psw = false;
+    float psn = 0.f;
+    unsigned psf = 0;
 
 #pragma unroll 1
-    for (int z = z0; z < z1; ++z) {
-        float *P = pl[z & 1];
-        P[(ly + 4) * W + lx + 4] = q[4];
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-            if (rs[e] >= 0) P[rs[e]] = rv[e];
-        const long long f = col + (long long)z * g.sz;
-        const float umf = valid_xy ? um[f] : 0.f;
-        const float chf = valid_xy ? chat[f] : 0.f;
-        __syncthreads();
-        // next plane: the window's new value and the ring
-        float qn = 0.f;
-        if (z + 1 < z1) {
-            qn = u[col + (long long)(z + 5) * g.sz];
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (rs[e] >= 0) rv[e] = u[ro[e] + (long long)(z + 1) * g.sz];
-        }
-        const float *cc = P + (ly + 4) * W + lx + 4;
-        const float c0 = q[4];
-        float wv = lap3(cc, W, q);
-        float un = 0.f;
-        if (valid_xy) {
-            if (near_xy || plane_near_z(g, z)) {
-                wv += d8(a.ph[0] + so + f, 1) + d8(a.ph[1] + so + f, g.sy) + d8(a.ph[2] + so + f, g.sz);
-                const float hx = a.t.h[0][ix], hy = a.t.h[1][iy], hz = a.t.h[2][z];
-                const float hs = hx + hy + hz;
-                float inc = (c0 - umf) + (hs * umf - 4.f * (hx * hy + hy * hz + hz * hx) * c0) + chf * wv;
-                float ps = 0.f;
-                if (hs > 0.f) {
-                    ps = a.psi[so + f];
-                    inc -= 8.f * hx * hy * hz * a.inv_dt * ps;
+    for (int zb = z0; zb < z1; zb += ZR) {
+        // an opaque copy of the chunk's plane: addresses are formed afresh in
+        // every pass rather than carried as strength-reduced pointers
+        const int zbo = __builtin_amdgcn_readfirstlane(zb);
+        static_for<ZR>([&](auto R) __attribute__((always_inline)) {
+            constexpr int r = decltype(R)::value;
+            constexpr int c = r % NB, n = (r + PD) % NB;
+            const int z = zbo + r;
+            if (z >= z1) return;
+            if (psw) stb(psi, psf, psn);
+            psw = false;
+            float *P = pl[z & 1];
+            P[(ly + 4) * W + lx + 4] = q[(r + 4) % ZR];
+            if (rs >= 0) P[rs] = rv[c];
+            float *PX = sphx + (LAYER ? (z & 1) * TY3 * WX : 0);
+            float *PY = sphy + (LAYER ? (z & 1) * (TY3 + 8) * WY : 0);
+            if constexpr (LAYER) {
+                PX[ly * WX + lx + 4] = pxv[c];
+                PY[(ly + 4) * WY + lx] = pyv[c];
+                if (hslot >= 0) {
+                    if (hslot < TY3 * WX) PX[hslot] = hvv[c];
+                    else PY[hslot - TY3 * WX] = hvv[c];
                 }
-                if (f == src) inc += sval;
-                un = (c0 + inc) / (1.f + hs);
-                if (hs > 0.f) a.psi[so + f] = ps + a.dt * un;
-            } else {
-                float inc = (c0 - umf) + chf * wv;
-                if (f == src) inc += sval;
-                un = c0 + inc;
             }
-            um[f] = un;
-            if constexpr (SNAP) a.snap[so + f] = wv;
-        }
-        if constexpr (REC) {
-            int pe = rb;
-            while (pe < re && (a.rec_ent[pe].x >> CELL3_BITS) == z) ++pe;
-            if (pe > rb) {                         // uniform over the block
-                xch[tid] = un;
-                __syncthreads();
-                for (int i = rb + tid; i < pe; i += NTH3) {
-                    const int2 en = a.rec_ent[i];
-                    a.seis[((long long)shot * a.nt + a.k) * a.nrec + en.y] = xch[en.x & ((1 << CELL3_BITS) - 1)];
+            const unsigned fb = colb + pb(z);
+            __syncthreads();
+            // plane z + PD (the windows: plane z + 4 + PD), kept inside the frame
+            {
+                const unsigned d1 = pbc(z + PD), dw = pbc(z + 4 + PD);
+                rv[n] = ldb(u, rob + d1);
+                if constexpr (LAYER) {
+                    pxv[n] = ldb(phx, colb + d1);
+                    pyv[n] = ldb(phy, colb + d1);
+                    hvv[n] = ldb(hsrc, hob + d1);
                 }
-                __syncthreads();
-                rb = pe;
+                q[(r + 8 + PD) % ZR] = ldb(u, colb + dw);
+                umv[n] = ldb(um, colb + d1);
+                chv[n] = ldb(chat, colb + d1);
+                if constexpr (LAYER) {
+                    pz[(r + 8 + PD) % ZR] = ldb(phz, colb + dw);
+                    psv[n] = ldb(psi, colb + d1);
+                }
             }
-        }
+            float qw[9];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) q[m] = q[m + 1];
-        q[8] = qn;
-        __builtin_amdgcn_sched_barrier(0);   // keep each plane's loads in its own iteration
+            for (int m = 0; m < 9; ++m) qw[m] = q[(r + m) % ZR];
+            const float *cc = P + (ly + 4) * W + lx + 4;
+            const float c0 = qw[4], umf = umv[c], chf = chv[c];
+            float wv = lap3(cc, W, qw);
+            float un = 0.f;
+            const bool at_src = z == srcp && colb == srcc;
+            if (valid_xy) {
+                if (LAYER || plane_near_z(g, z)) {
+                    float ps;
+                    if constexpr (LAYER) {
+                        float pw[9];
+#pragma unroll
+                        for (int m = 0; m < 9; ++m) pw[m] = pz[(r + m) % ZR];
+                        wv += d8(PX + ly * WX + lx + 4, 1) + d8(PY + (ly + 4) * WY + lx, (long long)WY) + d8w(pw);
+                        ps = psv[c];
+                    } else {
+                        // slab planes only: the offset comes from an opaque
+                        // copy of z (no strength-reduced stencil addresses)
+                        const unsigned fo = colb + pb(__builtin_amdgcn_readfirstlane(z));
+                        wv += d8b(phx, fo, 4u) + d8b(phy, fo, SYB) + d8b(phz, fo, SZB);
+                        ps = ldb(psi, fo);
+                    }
+                    const float hz = a.t.h[2][z];
+                    const float hs = hx + hy + hz;
+                    float inc = (c0 - umf) + (hs * umf - 4.f * (hx * hy + hy * hz + hz * hx) * c0) + chf * wv;
+                    if (hs > 0.f) inc -= 8.f * hx * hy * hz * a.inv_dt * ps;
+                    if (at_src) inc += sval;
+                    un = (c0 + inc) / (1.f + hs);
+                    if (hs > 0.f) {
+                        psw = true;
+                        psn = ps + a.dt * un;
+                        psf = fb;
+                    }
+                } else {
+                    float inc = (c0 - umf) + chf * wv;
+                    if (at_src) inc += sval;
+                    un = c0 + inc;
+                }
+            }
+            stb(um, fb, un);                       // 0 outside the grid, as the frame holds
+            if constexpr (SNAP) stb(snap, fb, valid_xy ? wv : 0.f);
+            if constexpr (REC) {
+                if (z == zr) {                     // uniform over the block
+                    int pe = rb;
+                    while (pe < re && (a.rec_ent[pe].x >> CELL3_BITS) == z) ++pe;
+                    xch[tid] = un;
+                    __syncthreads();
+                    for (int i = rb + tid; i < pe; i += NTH3) {
+                        const int2 en = a.rec_ent[i];
+                        a.seis[((long long)shot * a.nt + a.k) * a.nrec + en.y] = xch[en.x & ((1 << CELL3_BITS) - 1)];
+                    }
+                    __syncthreads();
+                    rb = pe;
+                    zr = rb < re ? a.rec_ent[rb].x >> CELL3_BITS : INT_MAX;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep each plane's loads in its own step
+        });
     }
+    if (psw) stb(psi, psf, psn);
 }
 
 // ------------------------------------------------------------ adjoint pass A
-// Same work items and marching, on chat s^{k+2}.
-__global__ __launch_bounds__(NTH3) void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
+// Same work items and marching, on chat s^{k+2} (its factors one plane ahead).
+__global__ __launch_bounds__(NTH3) __attribute__((amdgpu_waves_per_eu(8)))
+void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
 {
     constexpr int W = TX3 + 8;
     __shared__ float pc[2][(TY3 + 8) * W];
@@ -344,209 +532,354 @@ __global__ __launch_bounds__(NTH3) void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
     const int ix = x0 + lx, iy = y0 + ly;
     const bool valid_xy = ix < g.NX && iy < g.NY;
-    const long long so = (long long)shot * g.plane;
-    const float *s2 = a.s2 + so;
-    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const long long col = f3(g, 0, iy, ix);
-    float q[9];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        const long long o = col + (long long)(z0 - 4 + m) * g.sz;
-        q[m] = chat[o] * s2[o];
-    }
-    int rs[2];
-    long long ro[2];
-    float rv[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int i = tid + e * NTH3;
+    const bool layer_xy = ix < g.P || ix >= g.P + g.nx || iy < g.P || iy >= g.P + g.ny;
+    const long long zoff = (long long)(z0 + OZ3 - 4) * g.sz;
+    const long long zb0 = (long long)shot * g.plane + zoff;
+    const float *s2 = a.s2 + zb0;
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane + zoff;
+    float *b0 = a.b[0] + zb0, *b1 = a.b[1] + zb0, *b2 = a.b[2] + zb0;
+    const unsigned SZB = (unsigned)g.sz * 4u;
+    auto pb = [&](int z) { return (unsigned)(z - z0 + 4) * SZB; };
+    auto pbc = [&](int z) { return pb(min(z, g.NZ + 3)); };
+    const unsigned colb = (unsigned)((iy + OY3) * g.sy + ix + OX3) * 4u;
+    int rs;
+    unsigned rob;
+    {
         int r = 0, c = 0;
-        if (i < RING3) ring_rc(i, r, c);
-        rs[e] = i < RING3 ? r * W + c : -1;
-        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
-        const long long o = ro[e] + (long long)z0 * g.sz;
-        rv[e] = rs[e] >= 0 ? chat[o] * s2[o] : 0.f;
+        if (tid < RING3) ring_rc(tid, r, c);
+        rs = tid < RING3 ? r * W + c : -1;
+        rob = (unsigned)((y0 - 4 + r + OY3) * g.sy + x0 - 4 + c + OX3) * 4u;
     }
+    float q[LZR], wc[LNB], ws[LNB], rc[LNB], rsv[LNB], e0[LNB], e1[LNB], e2[LNB];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const unsigned o = colb + pbc(z0 - 4 + m);
+        q[m] = ldb(chat, o) * ldb(s2, o);
+    }
+#pragma unroll
+    for (int d = 0; d < LPD; ++d) {
+        const unsigned o = pbc(z0 + d), ow = colb + pbc(z0 + d + 4);
+        wc[d] = ldb(chat, ow);
+        ws[d] = ldb(s2, ow);
+        rc[d] = ldb(chat, rob + o);
+        rsv[d] = ldb(s2, rob + o);
+        e0[d] = ldb(b0, colb + o);
+        e1[d] = ldb(b1, colb + o);
+        e2[d] = ldb(b2, colb + o);
+    }
+    const float px = valid_xy ? a.t.p[0][ix] : 1.f, py = valid_xy ? a.t.p[1][iy] : 1.f;
+    bool fw = false;
+    float fn0 = 0.f, fn1 = 0.f, fn2 = 0.f;
+    unsigned ff = 0;
+
 #pragma unroll 1
-    for (int z = z0; z < z1; ++z) {
-        float *P = pc[z & 1];
-        const int ctr = (ly + 4) * W + lx + 4;
-        P[ctr] = q[4];
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-            if (rs[e] >= 0) P[rs[e]] = rv[e];
-        __syncthreads();
-        float nq = 0.f;
-        if (z + 1 < z1) {
-            const long long o = col + (long long)(z + 5) * g.sz;
-            nq = chat[o] * s2[o];
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (rs[e] >= 0) {
-                    const long long oe = ro[e] + (long long)(z + 1) * g.sz;
-                    rv[e] = chat[oe] * s2[oe];
-                }
-        }
-        if (valid_xy && layer3(g, ix, iy, z)) {
-            const long long f = so + col + (long long)z * g.sz;
-            const int id[3] = {ix, iy, z};
-            const float d[3] = {d8(P + ctr, 1), d8(P + ctr, W), d8w(q)};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                float *b = a.b[j];
-                b[f] = a.t.p[j][id[j]] * b[f] - d[j];
+    for (int zb = z0; zb < z1; zb += LZR) {
+        const int zbo = __builtin_amdgcn_readfirstlane(zb);
+        static_for<LZR>([&](auto R) __attribute__((always_inline)) {
+            constexpr int r = decltype(R)::value;
+            constexpr int c = r % LNB, n = (r + LPD) % LNB;
+            const int z = zbo + r;
+            if (z >= z1) return;
+            if (fw) {
+                stb(b0, ff, fn0);
+                stb(b1, ff, fn1);
+                stb(b2, ff, fn2);
             }
-        }
+            fw = false;
+            q[(r + 8) % LZR] = wc[c] * ws[c];
+            float *P = pc[z & 1];
+            const int ctr = (ly + 4) * W + lx + 4;
+            P[ctr] = q[(r + 4) % LZR];
+            if (rs >= 0) P[rs] = rc[c] * rsv[c];
+            const unsigned fb = colb + pb(z);
+            __syncthreads();
+            {
+                const unsigned d1 = pbc(z + LPD), dw = colb + pbc(z + 4 + LPD);
+                rc[n] = ldb(chat, rob + d1);
+                rsv[n] = ldb(s2, rob + d1);
+                wc[n] = ldb(chat, dw);
+                ws[n] = ldb(s2, dw);
+                e0[n] = ldb(b0, colb + d1);
+                e1[n] = ldb(b1, colb + d1);
+                e2[n] = ldb(b2, colb + d1);
+            }
+            if (valid_xy && (layer_xy || z < g.P || z >= g.P + g.nz)) {
+                float wq[9];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) q[m] = q[m + 1];
-        q[8] = nq;
+                for (int m = 0; m < 9; ++m) wq[m] = q[(r + m) % LZR];
+                fn0 = px * e0[c] - d8(P + ctr, 1);
+                fn1 = py * e1[c] - d8(P + ctr, W);
+                fn2 = a.t.p[2][z] * e2[c] - d8w(wq);
+                fw = true;
+                ff = fb;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+    if (fw) {
+        stb(b0, ff, fn0);
+        stb(b1, ff, fn1);
+        stb(b2, ff, fn2);
     }
 }
 
 // ------------------------------------------------------------ adjoint pass B
-__global__ __launch_bounds__(NTH3) void ac3_adj_kernel(Ac3AdjArgs a)
+// Two launches as in the forward: LAYER tiles take the layer terms on every
+// plane; in the others only the z slabs do, with hx = hy = 0 (their x and y
+// neighbours are interior too: h = 0, 1/(1+h) = 1), where e is constant.
+// The layer terms of axis j need D~_j of r_j = b_j / (1 + h_j) and of
+// t_j = h_j r_j:
+//   sum_m d_m (2 (ha + hb - h_j) r_j)|_{+m} - (..)|_{-m} = 2 (ha + hb) D~_j r_j - 2 D~_j t_j.
+// In LAYER tiles r and t of x (y) are staged in LDS planes with their x (y)
+// halo, b_z in a register window whose r and t are formed with the scalar z
+// tables.  Operands are prefetched one plane ahead into rings as in the
+// forward; chat s^{k+2} enters the window as a product formed one step after
+// its two factors arrive.  Addresses are 32-bit byte offsets from per-block
+// bases at the chunk's first window plane.
+constexpr int APD = 1, ANB = APD + 1, AZR = 10;
+static_assert(AZR % ANB == 0 && 8 + APD < AZR, "ring sizes");
+
+template <bool LAYER>
+__global__ __launch_bounds__(NTH3) __attribute__((amdgpu_waves_per_eu(LAYER ? 4 : 8)))
+void ac3_adj_kernel(Ac3AdjArgs a)
 {
     constexpr int W = TX3 + 8;
+    constexpr int WX = TX3 + 8, WY = TX3;
+    constexpr int NPX = TY3 * WX, NPY = (TY3 + 8) * WY;
     __shared__ float pl[2][(TY3 + 8) * W];
+    // per buffer: r_x, t_x (NPX each), r_y, t_y (NPY each)
+    __shared__ float sb[LAYER ? 2 * 2 * (NPX + NPY) : 1];
     __shared__ float xch[TX3 * TY3];
     const Grid3 &g = a.g;
     const int nxy = g.ntx * g.nty;
-    const int w = xcd_work_id(nxy * g.nzc * a.nshots);
-    const int shot = w / (nxy * g.nzc);
-    const int rem = w - shot * nxy * g.nzc;
-    const int zc = rem / nxy, tile = rem - zc * nxy;
+    const int w = xcd_work_id(a.ntl * g.nzc * a.nshots);
+    const int shot = w / (a.ntl * g.nzc);
+    const int rem = w - shot * a.ntl * g.nzc;
+    const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
     const int ty = tile / g.ntx, tx = tile - ty * g.ntx;
     const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * TZC, z1 = min(z0 + TZC, g.NZ);
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
     const int ix = x0 + lx, iy = y0 + ly;
     const bool valid_xy = ix < g.NX && iy < g.NY;
-    const bool near_xy = tile_near_xy(g, x0, y0);
-    const long long so = (long long)shot * g.plane;
-    const float *s2 = a.s2 + so;
-    float *s3 = a.s3 + so;
-    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    // bases at plane z0 - 4 of this shot; plane z at byte offset pb(z)
+    const long long zb0 = (long long)shot * g.plane + (long long)(z0 + OZ3 - 4) * g.sz;
+    const float *s2 = a.s2 + zb0;
+    float *s3 = a.s3 + zb0;
+    float *ee = a.e + zb0;
+    float *grad = a.grad + zb0;
+    const float *snap = a.snap + zb0;
+    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane + (long long)(z0 + OZ3 - 4) * g.sz;
+    const float *bxp = a.b[0] + zb0, *byp = a.b[1] + zb0, *bzp = a.b[2] + zb0;
+    const unsigned SZB = (unsigned)g.sz * 4u, SYB = (unsigned)g.sy * 4u;
+    auto pb = [&](int z) { return (unsigned)(z - z0 + 4) * SZB; };
+    auto pbc = [&](int z) { return pb(min(z, g.NZ + 3)); };
+    const unsigned colb = (unsigned)((iy + OY3) * g.sy + ix + OX3) * 4u;
+    // the source cell as (plane, in-plane byte offset)
     const long long src = a.src_f[shot];
+    const int srcp = (int)(src / g.sz) - OZ3;
+    const unsigned srcc = (unsigned)(src - (long long)(srcp + OZ3) * g.sz) * 4u;
 
     const int *off = a.rec_off + (long long)shot * (nxy + 1);
-    int rb = off[tile], re = off[tile + 1];
+    int rb = off[tile], re = off[tile + 1], zr = INT_MAX;
     while (rb < re && (a.rec_ent[rb].x >> CELL3_BITS) < z0) ++rb;
+    if (rb < re) zr = a.rec_ent[rb].x >> CELL3_BITS;
     const float *dd = a.dJdd + ((long long)shot * a.nt + a.k) * a.nrec;
 
-    float q[9];        // chat s^{k+2}, z-4 .. z+4 of the own column
-    float sraw;        // s^{k+2} at (z, own column)
-    const long long col = f3(g, 0, iy, ix);
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        const long long o = col + (long long)(z0 - 4 + m) * g.sz;
-        q[m] = chat[o] * s2[o];
-    }
-    // halo-ring cells of this thread, loaded one plane ahead (as in the forward)
-    int rs[2];
-    long long ro[2];
-    float rv[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int i = tid + e * NTH3;
+    int rs;
+    unsigned rob;
+    {
         int r = 0, c = 0;
-        if (i < RING3) ring_rc(i, r, c);
-        rs[e] = i < RING3 ? r * W + c : -1;
-        ro[e] = f3(g, 0, y0 - 4 + r, x0 - 4 + c);
-        const long long o = ro[e] + (long long)z0 * g.sz;
-        rv[e] = rs[e] >= 0 ? chat[o] * s2[o] : 0.f;
+        if (tid < RING3) ring_rc(tid, r, c);
+        rs = tid < RING3 ? r * W + c : -1;
+        rob = (unsigned)((y0 - 4 + r + OY3) * g.sy + x0 - 4 + c + OX3) * 4u;
     }
-#pragma unroll 1
-    for (int z = z0; z < z1; ++z) {
-        const long long f = col + (long long)z * g.sz;
-        sraw = s2[f];
-        float *P = pl[z & 1];
-        P[(ly + 4) * W + lx + 4] = q[4];
+    // q: chat s^{k+2} of planes z - 4 .. z + 4 (ring); wc, ws: the factors
+    // of plane z + 4 + APD; the other rings: planes z .. z + APD
+    float q[AZR], wc[ANB], ws[ANB], rc[ANB], rsv[ANB], srv[ANB], s3v[ANB], snv[ANB], gv[ANB];
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
-            if (rs[e] >= 0) P[rs[e]] = rv[e];
-        const float s3f = valid_xy ? s3[f] : 0.f;
-        const float snf = valid_xy ? a.snap[so + f] : 0.f;
-        __syncthreads();
-        float qn = 0.f;
-        if (z + 1 < z1) {
-            const long long o = col + (long long)(z + 5) * g.sz;
-            qn = chat[o] * s2[o];
+    for (int m = 0; m < 8; ++m) {
+        const unsigned o = colb + pbc(z0 - 4 + m);
+        q[m] = ldb(chat, o) * ldb(s2, o);
+    }
 #pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (rs[e] >= 0) {
-                    const long long oe = ro[e] + (long long)(z + 1) * g.sz;
-                    rv[e] = chat[oe] * s2[oe];
-                }
+    for (int d = 0; d < APD; ++d) {
+        const unsigned o = pbc(z0 + d), ow = colb + pbc(z0 + d + 4);
+        wc[d] = ldb(chat, ow);
+        ws[d] = ldb(s2, ow);
+        rc[d] = ldb(chat, rob + o);
+        rsv[d] = ldb(s2, rob + o);
+        srv[d] = ldb(s2, colb + o);
+        s3v[d] = ldb(s3, colb + o);
+        snv[d] = ldb(snap, colb + o);
+        gv[d] = ldb(grad, colb + o);
+    }
+    // LAYER: b_z window, own b_x, b_y, e, one halo cell of b_x or b_y, and
+    // the tables at the own column, row and halo cell
+    float bzw[LAYER ? AZR : 1], bxv[ANB], byv[ANB], hbv[ANB], ev[ANB];
+    float hxo = 0.f, ihxo = 1.f, hyo = 0.f, ihyo = 1.f, hho = 0.f, ihho = 1.f;
+    int hslot = -1;
+    const float *hsrc = bxp;
+    unsigned hob = colb;
+    if constexpr (LAYER) {
+#pragma unroll
+        for (int m = 0; m < 8 + APD; ++m) bzw[m] = ldb(bzp, colb + pbc(z0 - 4 + m));
+        if (tid < 8 * TY3) {
+            const int r = tid / 8, c = tid % 8, cx = c < 4 ? c : c + TX3;
+            hslot = r * WX + cx;
+            hob = (unsigned)((y0 + r + OY3) * g.sy + x0 - 4 + cx + OX3) * 4u;
+            tab_at(a.t.h[0], a.t.ih[0], x0 - 4 + cx, g.NX, hho, ihho);
+        } else if (tid < 8 * TY3 + 8 * TX3) {
+            const int i = tid - 8 * TY3, r = i / TX3, c = i % TX3, ry = r < 4 ? r : r + TY3;
+            hslot = 2 * NPX + ry * WY + c;     // r_y plane; t_y follows at + NPY
+            hsrc = byp;
+            hob = (unsigned)((y0 - 4 + ry + OY3) * g.sy + x0 + c + OX3) * 4u;
+            tab_at(a.t.h[1], a.t.ih[1], y0 - 4 + ry, g.NY, hho, ihho);
         }
-        const float *cc = P + (ly + 4) * W + lx + 4;
-        float v = lap3(cc, W, q);
-        bool nearz = false;
-        float hs = 0.f;
-        if (valid_xy) {
-            nearz = near_xy || plane_near_z(g, z);
-            if (nearz) {
-                const int id[3] = {ix, iy, z};
-                const float h[3] = {a.t.h[0][ix], a.t.h[1][iy], a.t.h[2][z]};
-                hs = h[0] + h[1] + h[2];
-                const long long st[3] = {1, g.sy, g.sz};
-                float de = 0.f;
+        tab_at(a.t.h[0], a.t.ih[0], ix, g.NX, hxo, ihxo);
+        tab_at(a.t.h[1], a.t.ih[1], iy, g.NY, hyo, ihyo);
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const float ha = h[(j + 1) % 3], hb = h[(j + 2) % 3];
-                    const float *tj = a.t.h[j], *ij = a.t.ih[j];
-                    const float *b = a.b[j] + so + f;
-                    float dq = 0.f, dr = 0.f;
+        for (int d = 0; d < APD; ++d) {
+            const unsigned o = pbc(z0 + d);
+            bxv[d] = ldb(bxp, colb + o);
+            byv[d] = ldb(byp, colb + o);
+            hbv[d] = ldb(hsrc, hob + o);
+            ev[d] = ldb(ee, colb + o);
+        }
+    }
+    const float *tz = a.t.h[2], *iz = a.t.ih[2];
+    // e^{k+1} of the previous plane, stored at the start of the next
+    bool esw = false;
+    float esn = 0.f;
+    unsigned esf = 0;
+
+#pragma unroll 1
+    for (int zb = z0; zb < z1; zb += AZR) {
+        const int zbo = __builtin_amdgcn_readfirstlane(zb);
+        static_for<AZR>([&](auto R) __attribute__((always_inline)) {
+            constexpr int r = decltype(R)::value;
+            constexpr int c = r % ANB, n = (r + APD) % ANB;
+            const int z = zbo + r;
+            if (z >= z1) return;
+            if (esw) stb(ee, esf, esn);
+            esw = false;
+            q[(r + 8) % AZR] = wc[c] * ws[c];
+            float *P = pl[z & 1];
+            P[(ly + 4) * W + lx + 4] = q[(r + 4) % AZR];
+            if (rs >= 0) P[rs] = rc[c] * rsv[c];
+            float *SB = sb + (LAYER ? (z & 1) * 2 * (NPX + NPY) : 0);
+            if constexpr (LAYER) {
+                const float rx = ihxo * bxv[c], ry = ihyo * byv[c], rh = ihho * hbv[c];
+                SB[ly * WX + lx + 4] = rx;
+                SB[NPX + ly * WX + lx + 4] = hxo * rx;
+                SB[2 * NPX + (ly + 4) * WY + lx] = ry;
+                SB[2 * NPX + NPY + (ly + 4) * WY + lx] = hyo * ry;
+                if (hslot >= 0) {
+                    const int o2 = hslot < NPX ? NPX : NPY;
+                    SB[hslot] = rh;
+                    SB[hslot + o2] = hho * rh;
+                }
+            }
+            const unsigned fb = colb + pb(z);
+            __syncthreads();
+            {
+                const unsigned d1 = pbc(z + APD), dw = pbc(z + 4 + APD);
+                rc[n] = ldb(chat, rob + d1);
+                rsv[n] = ldb(s2, rob + d1);
+                if constexpr (LAYER) {
+                    bxv[n] = ldb(bxp, colb + d1);
+                    byv[n] = ldb(byp, colb + d1);
+                    hbv[n] = ldb(hsrc, hob + d1);
+                }
+                wc[n] = ldb(chat, colb + dw);
+                ws[n] = ldb(s2, colb + dw);
+                srv[n] = ldb(s2, colb + d1);
+                s3v[n] = ldb(s3, colb + d1);
+                snv[n] = ldb(snap, colb + d1);
+                gv[n] = ldb(grad, colb + d1);
+                if constexpr (LAYER) {
+                    bzw[(r + 8 + APD) % AZR] = ldb(bzp, colb + dw);
+                    ev[n] = ldb(ee, colb + d1);
+                }
+            }
+            float qw[9];
+#pragma unroll
+            for (int m = 0; m < 9; ++m) qw[m] = q[(r + m) % AZR];
+            const float *cc = P + (ly + 4) * W + lx + 4;
+            const float sraw = srv[c], s3f = s3v[c];
+            float v = lap3(cc, W, qw);
+            bool nearz = false;
+            float hs = 0.f;
+            if (valid_xy) {
+                nearz = LAYER || plane_near_z(g, z);
+                if constexpr (LAYER) {
+                    const float hz = tz[z];
+                    hs = hxo + hyo + hz;
+                    const float drx = d8(SB + ly * WX + lx + 4, 1), dtx = d8(SB + NPX + ly * WX + lx + 4, 1);
+                    const float dry = d8(SB + 2 * NPX + (ly + 4) * WY + lx, (long long)WY);
+                    const float dty = d8(SB + 2 * NPX + NPY + (ly + 4) * WY + lx, (long long)WY);
+                    float drz = 0.f, dtz = 0.f;
 #pragma unroll
                     for (int m = 1; m <= 4; ++m) {
-                        const long long o = m * st[j];
-                        const float bp = b[o], bm = b[-o];
-                        const float ip = ij[id[j] + m], im = ij[id[j] - m];
-                        dq += dcoef(m) * (2.f * (ha + hb - tj[id[j] + m]) * ip * bp
-                                          - 2.f * (ha + hb - tj[id[j] - m]) * im * bm);
-                        dr += dcoef(m) * (ip * bp - im * bm);
+                        const float rp = iz[z + m] * bzw[(r + 4 + m) % AZR], rm = iz[z - m] * bzw[(r + 4 - m) % AZR];
+                        drz += dcoef(m) * (rp - rm);
+                        dtz += dcoef(m) * (tz[z + m] * rp - tz[z - m] * rm);
                     }
-                    v -= dq;
-                    de += 4.f * a.inv_dt * ha * hb * dr;
-                }
-                if (hs > 0.f) {
-                    const float en = a.e[so + f] - 8.f * h[0] * h[1] * h[2] * a.inv_dt * sraw - de;
-                    a.e[so + f] = en;
-                    v += a.dt * en;
-                }
-                v += sraw + ((sraw - s3f) + (hs * s3f - 4.f * (h[0] * h[1] + h[1] * h[2] + h[2] * h[0]) * sraw));
-            } else {
-                v += sraw + (sraw - s3f);
-            }
-        }
-        // receiver residual injection (deterministic per cell)
-        int pe = rb;
-        while (pe < re && (a.rec_ent[pe].x >> CELL3_BITS) == z) ++pe;
-        if (pe > rb) {                              // uniform over the block
-            xch[tid] = v;
-            __syncthreads();
-            for (int i = rb + tid; i < pe; i += NTH3) {
-                const int cell = a.rec_ent[i].x & ((1 << CELL3_BITS) - 1);
-                if (i > rb && (a.rec_ent[i - 1].x & ((1 << CELL3_BITS) - 1)) == cell) continue;
-                float sum = 0.f;
-                for (int m = i; m < pe && (a.rec_ent[m].x & ((1 << CELL3_BITS) - 1)) == cell; ++m)
-                    sum += dd[a.rec_ent[m].y];
-                xch[cell] += sum;
-            }
-            __syncthreads();
-            v = xch[tid];
-            __syncthreads();
-            rb = pe;
-        }
-        if (valid_xy) {
-            const float s1 = nearz ? v / (1.f + hs) : v;
-            s3[f] = s1;
-            a.grad[so + f] += s1 * snf;
-            if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
-        }
+                    v -= 2.f * ((hyo + hz) * drx + (hz + hxo) * dry + (hxo + hyo) * drz - (dtx + dty + dtz));
+                    const float de = 4.f * a.inv_dt * (hyo * hz * drx + hz * hxo * dry + hxo * hyo * drz);
+                    if (hs > 0.f) {
+                        const float en = ev[c] - 8.f * hxo * hyo * hz * a.inv_dt * sraw - de;
+                        esw = true;
+                        esn = en;
+                        esf = fb;
+                        v += a.dt * en;
+                    }
+                    v += sraw + ((sraw - s3f) + (hs * s3f - 4.f * (hxo * hyo + hyo * hz + hz * hxo) * sraw));
+                } else if (nearz) {
+                    // slab plane of an interior tile; the offset comes from
+                    // an opaque copy of z (no strength-reduced addresses)
+                    const int zz = __builtin_amdgcn_readfirstlane(z);
+                    const unsigned fo = colb + pb(zz);
+                    hs = tz[zz];
+                    float dq = 0.f;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) q[m] = q[m + 1];
-        q[8] = qn;
-        __builtin_amdgcn_sched_barrier(0);
+                    for (int m = 1; m <= 4; ++m)
+                        dq += dcoef(m) * (tz[zz - m] * iz[zz - m] * ldb(bzp, fo - m * SZB)
+                                          - tz[zz + m] * iz[zz + m] * ldb(bzp, fo + m * SZB));
+                    v -= 2.f * (hs * (d8b(bxp, fo, 4u) + d8b(byp, fo, SYB)) + dq);
+                    if (hs > 0.f) v += a.dt * ldb(ee, fo);
+                    v += sraw + ((sraw - s3f) + hs * s3f);
+                } else {
+                    v += sraw + (sraw - s3f);
+                }
+            }
+            // receiver residual injection (deterministic per cell)
+            if (z == zr) {                              // uniform over the block
+                int pe = rb;
+                while (pe < re && (a.rec_ent[pe].x >> CELL3_BITS) == z) ++pe;
+                xch[tid] = v;
+                __syncthreads();
+                for (int i = rb + tid; i < pe; i += NTH3) {
+                    const int cell = a.rec_ent[i].x & ((1 << CELL3_BITS) - 1);
+                    if (i > rb && (a.rec_ent[i - 1].x & ((1 << CELL3_BITS) - 1)) == cell) continue;
+                    float sum = 0.f;
+                    for (int m = i; m < pe && (a.rec_ent[m].x & ((1 << CELL3_BITS) - 1)) == cell; ++m)
+                        sum += dd[a.rec_ent[m].y];
+                    xch[cell] += sum;
+                }
+                __syncthreads();
+                v = xch[tid];
+                __syncthreads();
+                rb = pe;
+                zr = rb < re ? a.rec_ent[rb].x >> CELL3_BITS : INT_MAX;
+            }
+            const float s1 = valid_xy ? (nearz ? v / (1.f + hs) : v) : 0.f;
+            stb(s3, fb, s1);                            // 0 outside the grid, as the frame holds
+            stb(grad, fb, valid_xy ? gv[c] + s1 * snv[c] : gv[c]);
+            if (a.gwav && z == srcp && colb == srcc) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
+            __builtin_amdgcn_sched_barrier(0);
+        });
     }
+    if (esw) stb(ee, esf, esn);
 }
 
 __global__ void ac3_prep_kernel(Grid3 g, int nmodels, const float *vp, double dt, double dx,
@@ -625,20 +958,37 @@ void launch_ac3_phi_adj(const Ac3PhiAdjArgs &a, int nshots, hipStream_t s)
     ac3_phi_adj_kernel<<<a.nitems * nshots, NTH3, 0, s>>>(a);
 }
 
-void launch_ac3_fwd(const Ac3FwdArgs &a, hipStream_t s)
+template <bool LAYER>
+void launch_ac3_fwd_part(Ac3FwdArgs a, int t0, int ntl, hipStream_t s)
 {
-    const int nb = a.g.ntx * a.g.nty * a.g.nzc * a.nshots;
+    a.t0 = t0;
+    a.ntl = ntl;
+    const int nb = ntl * a.g.nzc * a.nshots;
     if (nb == 0) return;
     const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
-    if (snap) { if (rec) ac3_fwd_kernel<true, true><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<true, false><<<nb, NTH3, 0, s>>>(a); }
-    else      { if (rec) ac3_fwd_kernel<false, true><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<false, false><<<nb, NTH3, 0, s>>>(a); }
+    if (snap) { if (rec) ac3_fwd_kernel<true, true, LAYER><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<true, false, LAYER><<<nb, NTH3, 0, s>>>(a); }
+    else      { if (rec) ac3_fwd_kernel<false, true, LAYER><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<false, false, LAYER><<<nb, NTH3, 0, s>>>(a); }
+}
+
+void launch_ac3_fwd(const Ac3FwdArgs &a, hipStream_t s)
+{
+    const int nxy = a.g.ntx * a.g.nty;
+    launch_ac3_fwd_part<true>(a, 0, a.nnear, s);
+    launch_ac3_fwd_part<false>(a, a.nnear, nxy - a.nnear, s);
 }
 
 void launch_ac3_adj(const Ac3AdjArgs &a, hipStream_t s)
 {
-    const int nb = a.g.ntx * a.g.nty * a.g.nzc * a.nshots;
-    if (nb == 0) return;
-    ac3_adj_kernel<<<nb, NTH3, 0, s>>>(a);
+    const int nxy = a.g.ntx * a.g.nty;
+    for (int part = 0; part < 2; ++part) {
+        Ac3AdjArgs b = a;
+        b.t0 = part ? a.nnear : 0;
+        b.ntl = part ? nxy - a.nnear : a.nnear;
+        const int nb = b.ntl * a.g.nzc * a.nshots;
+        if (nb == 0) continue;
+        if (part) ac3_adj_kernel<false><<<nb, NTH3, 0, s>>>(b);
+        else ac3_adj_kernel<true><<<nb, NTH3, 0, s>>>(b);
+    }
 }
 
 void launch_ac3_prep(const Grid3 &g, int nmodels, const float *vp, double dt, double dx,

@@ -91,6 +91,14 @@ int check_desc(const sg_desc *d)
     const long long cells = (long long)(d->nx + 2 * d->npml) * (ny + (d->ndim == 3 ? 2 * d->npml : 0)) *
                             (d->nz + 2 * d->npml);
     if (cells > (1LL << 33)) return fail(SG_EINVAL, "grid too large");
+    if (d->ndim == 3) {
+        // the 3-D tile passes address a z chunk and its window planes with
+        // 32-bit byte offsets
+        const long long NX = d->nx + 2LL * d->npml, NY = d->ny + 2LL * d->npml;
+        const long long SX = OX3 + (NX + TX3 - 1) / TX3 * TX3 + 32, SY = OY3 + (NY + TY3 - 1) / TY3 * TY3 + 4;
+        if ((TZC + 12) * SX * SY * 4 >= (1LL << 32))
+            return fail(SG_EUNSUPPORTED, "3-D grid planes of %lld x %lld cells exceed this build's limit", NX, NY);
+    }
     return SG_OK;
 }
 
@@ -218,6 +226,10 @@ struct sg_model {
     int4 *items3 = nullptr;
     int n_items3 = 0;
     std::vector<int4> h_items3;
+    // 3-D xy tiles, those within the stencil reach of the layer in x or y first
+    int *tiles3 = nullptr;
+    int n_near3 = 0;
+    std::vector<int> h_tiles3;
     int steps_per_launch = 2;
     // snapshots of the last n_store checkpoint segments, written by a
     // checkpointed forward into the workspace beyond its minimum size
@@ -841,6 +853,8 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
         a.nrec = m->geom_nrec;
         a.seis = seis;
         a.snap = snap;
+        a.tiles = m->tiles3;
+        a.nnear = m->n_near3;
         launch_ac3_fwd(a, s);
     }
 }
@@ -979,6 +993,8 @@ void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float
         b.nrec = m->geom_nrec;
         b.snap = snap;
         b.grad = m->grad;
+        b.tiles = m->tiles3;
+        b.nnear = m->n_near3;
         launch_ac3_adj(b, s);
     }
 }
@@ -1187,6 +1203,19 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
             }
         }
     }
+    if (d->ndim == 3) {
+        const Grid3 &g = L.g3;
+        m->tiles3 = reinterpret_cast<int *>(m->ws + L.off_tiles);
+        std::vector<int> rest;
+        for (int t = 0; t < L.ntiles; ++t) {
+            const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
+            const bool near = g.P > 0 && (x0 - 4 < g.P || x0 + TX3 + 4 > g.P + g.nx ||
+                                          y0 - 4 < g.P || y0 + TY3 + 4 > g.P + g.ny);
+            (near ? m->h_tiles3 : rest).push_back(t);
+        }
+        m->n_near3 = (int)m->h_tiles3.size();
+        m->h_tiles3.insert(m->h_tiles3.end(), rest.begin(), rest.end());
+    }
     if (d->ndim == 3 && d->npml > 0) {
         // every plane of the xy tiles that touch the layer in x or y; the two
         // z slabs of the others
@@ -1208,6 +1237,8 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         e = hipMemcpyAsync(m->items3, m->h_items3.data(), sizeof(int4) * m->n_items3, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m->n_layer > 0)
         e = hipMemcpyAsync(m->tiles_layer, m->h_layer.data(), sizeof(int) * m->n_layer, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !m->h_tiles3.empty())
+        e = hipMemcpyAsync(m->tiles3, m->h_tiles3.data(), sizeof(int) * m->h_tiles3.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         delete m;
         return fail(SG_EDEVICE, "upload failed: %s", hipGetErrorString(e));

@@ -224,6 +224,9 @@ struct Ac3FwdArgs {
     float *seis;
     int nrec;
     float *snap;
+    const int *tiles;          // xy tiles, the nnear within 4 cells of the layer in x or y first
+    int nnear;
+    int t0, ntl;               // this launch's slice of tiles (set by the launcher)
 };
 
 struct Ac3PhiArgs {
@@ -268,6 +271,9 @@ struct Ac3AdjArgs {
     int nrec;
     const float *snap;
     float *grad;
+    const int *tiles;          // as in Ac3FwdArgs
+    int nnear;
+    int t0, ntl;
 };
 
 void launch_ac3_phi(const Ac3PhiArgs &a, int nshots, hipStream_t s);
