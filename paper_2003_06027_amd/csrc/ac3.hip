@@ -22,7 +22,7 @@
 //             a^{k+1} = R^T dJ/dd^{k+1} + dt e^{k+1} - sum_j D~_j(q_j b_j^{k+1})
 //                       + L~(chat s^{k+2}) + beta s^{k+2} - gamma s^{k+3}
 //             s^{k+1} = alpha a^{k+1};  dJ/dchat += s^{k+1} w~^k
-#include "sg_internal.h"
+#include "ac3_internal.h"
 
 #include <climits>
 #include <type_traits>

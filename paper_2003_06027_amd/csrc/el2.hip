@@ -22,7 +22,7 @@
 // velocity adjoints, then forms the adjoints d1..d4 of the stress
 // differences (and the bx/bz gradients from the stored divergences); pass 3
 // applies those transposes to the stress adjoints.
-#include "sg_internal.h"
+#include "el2_internal.h"
 
 namespace sg {
 namespace {

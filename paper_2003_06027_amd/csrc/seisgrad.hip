@@ -9,6 +9,8 @@
 #include "../../include/seisgrad.h"
 #include "sg_internal.h"
 #include "ad2_internal.h"
+#include "ac3_internal.h"
+#include "el2_internal.h"
 #include "sg_error.h"
 
 #include <algorithm>
