@@ -170,6 +170,16 @@ __device__ __forceinline__ void stb(float *b, unsigned o, float v)
 {
     *reinterpret_cast<float *>(reinterpret_cast<char *>(b) + o) = v;
 }
+// streaming operands (read or written once per step, no neighbour reuse):
+// non-temporal, so that they do not displace the reused planes from L2
+__device__ __forceinline__ float ldn(const float *b, unsigned o)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const float *>(reinterpret_cast<const char *>(b) + o));
+}
+__device__ __forceinline__ void stn(float *b, unsigned o, float v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<float *>(reinterpret_cast<char *>(b) + o));
+}
 // d8 at byte offset o with byte stride sb
 __device__ __forceinline__ float d8b(const float *b, unsigned o, unsigned sb)
 {
@@ -367,8 +377,8 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
 #pragma unroll
     for (int d = 0; d < PD; ++d) {
         rv[d] = ldb(u, rob + pbc(z0 + d));
-        umv[d] = ldb(um, colb + pbc(z0 + d));
-        chv[d] = ldb(chat, colb + pbc(z0 + d));
+        umv[d] = ldn(um, colb + pbc(z0 + d));
+        chv[d] = ldn(chat, colb + pbc(z0 + d));
     }
     // LAYER: the phi_z window, this column's phi_x, phi_y and psi, and one
     // halo cell: of phi_x (the first 8 TY3 threads) or of phi_y (the next 8 TX3)
@@ -445,8 +455,8 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
                     hvv[n] = ldb(hsrc, hob + d1);
                 }
                 q[(r + 8 + PD) % ZR] = ldb(u, colb + dw);
-                umv[n] = ldb(um, colb + d1);
-                chv[n] = ldb(chat, colb + d1);
+                umv[n] = ldn(um, colb + d1);
+                chv[n] = ldn(chat, colb + d1);
                 if constexpr (LAYER) {
                     pz[(r + 8 + PD) % ZR] = ldb(phz, colb + dw);
                     psv[n] = ldb(psi, colb + d1);
@@ -493,8 +503,8 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
                     un = c0 + inc;
                 }
             }
-            stb(um, fb, un);                       // 0 outside the grid, as the frame holds
-            if constexpr (SNAP) stb(snap, fb, valid_xy ? wv : 0.f);
+            stn(um, fb, un);                       // 0 outside the grid, as the frame holds
+            if constexpr (SNAP) stn(snap, fb, valid_xy ? wv : 0.f);
             if constexpr (REC) {
                 if (z == zr) {                     // uniform over the block
                     int pe = rb;
@@ -709,9 +719,9 @@ void ac3_adj_kernel(Ac3AdjArgs a)
         rc[d] = ldb(chat, rob + o);
         rsv[d] = ldb(s2, rob + o);
         srv[d] = ldb(s2, colb + o);
-        s3v[d] = ldb(s3, colb + o);
-        snv[d] = ldb(snap, colb + o);
-        gv[d] = ldb(grad, colb + o);
+        s3v[d] = ldn(s3, colb + o);
+        snv[d] = ldn(snap, colb + o);
+        gv[d] = ldn(grad, colb + o);
     }
     // LAYER: b_z window, own b_x, b_y, e, one halo cell of b_x or b_y, and
     // the tables at the own column, row and halo cell
@@ -793,9 +803,9 @@ void ac3_adj_kernel(Ac3AdjArgs a)
                 wc[n] = ldb(chat, colb + dw);
                 ws[n] = ldb(s2, colb + dw);
                 srv[n] = ldb(s2, colb + d1);
-                s3v[n] = ldb(s3, colb + d1);
-                snv[n] = ldb(snap, colb + d1);
-                gv[n] = ldb(grad, colb + d1);
+                s3v[n] = ldn(s3, colb + d1);
+                snv[n] = ldn(snap, colb + d1);
+                gv[n] = ldn(grad, colb + d1);
                 if constexpr (LAYER) {
                     bzw[(r + 8 + APD) % AZR] = ldb(bzp, colb + dw);
                     ev[n] = ldb(ee, colb + d1);
@@ -873,8 +883,8 @@ void ac3_adj_kernel(Ac3AdjArgs a)
                 zr = rb < re ? a.rec_ent[rb].x >> CELL3_BITS : INT_MAX;
             }
             const float s1 = valid_xy ? (nearz ? v / (1.f + hs) : v) : 0.f;
-            stb(s3, fb, s1);                            // 0 outside the grid, as the frame holds
-            stb(grad, fb, valid_xy ? gv[c] + s1 * snv[c] : gv[c]);
+            stn(s3, fb, s1);                            // 0 outside the grid, as the frame holds
+            stn(grad, fb, valid_xy ? gv[c] + s1 * snv[c] : gv[c]);
             if (a.gwav && z == srcp && colb == srcc) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
             __builtin_amdgcn_sched_barrier(0);
         });

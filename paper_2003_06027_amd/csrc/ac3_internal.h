@@ -16,6 +16,7 @@ constexpr int OX3 = 32;  // x offset (128-byte aligned rows)
 constexpr int OY3 = 4;
 constexpr int OZ3 = 4;
 constexpr int CELL3_BITS = 9;   // local cell of a TX3 x TY3 plane tile
+static_assert(TX3 * TY3 <= (1 << CELL3_BITS) && CELL3_BITS <= 11, "tile cells fit the receiver entries");
 
 struct Grid3 {
     int NX, NY, NZ;

@@ -100,6 +100,9 @@ int check_desc(const sg_desc *d)
         const long long SX = OX3 + (NX + TX3 - 1) / TX3 * TX3 + 32, SY = OY3 + (NY + TY3 - 1) / TY3 * TY3 + 4;
         if ((TZC + 12) * SX * SY * 4 >= (1LL << 32))
             return fail(SG_EUNSUPPORTED, "3-D grid planes of %lld x %lld cells exceed this build's limit", NX, NY);
+        // receiver entries are sorted by (tile, plane) with a 12-bit plane field
+        if (d->nz + 2LL * d->npml >= 4096)
+            return fail(SG_EUNSUPPORTED, "3-D grids are limited to %d padded planes in z", 4095);
     }
     return SG_OK;
 }
@@ -427,7 +430,8 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
                 const int px = e[0] + P, py = e[1] + P, pz = e[2] + P;
                 const int tile = (py / TY3) * L.g3.ntx + px / TX3;
                 const int cell = (py % TY3) * TX3 + px % TX3;
-                keyed.push_back({(long long)tile << 42 | (long long)pz << 30 | (long long)cell << 21 | r, r});
+                // key: tile (bits 44..), plane (32..43), cell (21..31), receiver (0..20)
+                keyed.push_back({(long long)tile << 44 | (long long)pz << 32 | (long long)cell << 21 | r, r});
             }
         }
         std::sort(keyed.begin(), keyed.end());
@@ -436,12 +440,12 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
         size_t e = 0;
         for (int tl = 0; tl < ntiles; ++tl) {
             off[tl] = (int)(base + e);
-            while (e < keyed.size() && (int)(keyed[e].first >> 42) == tl) {
+            while (e < keyed.size() && (int)(keyed[e].first >> (nd == 2 ? 42 : 44)) == tl) {
                 if (nd == 2) {
                     m->h_ent.push_back(keyed[e].second);
                 } else {
                     const long long k = keyed[e].first;
-                    const int pz = (int)((k >> 30) & 0xFFF), cell = (int)((k >> 21) & 0x1FF);
+                    const int pz = (int)((k >> 32) & 0xFFF), cell = (int)((k >> 21) & 0x7FF);
                     m->h_ent3.push_back(make_int2((pz << CELL3_BITS) | cell, keyed[e].second));
                 }
                 ++e;
