@@ -1,6 +1,6 @@
-"""The learned preconditioner end to end on the GPU (the full training data,
-half the epochs, 8 evaluation models x 30 iterations): training data from
-the plain batched inversion, training with the
+"""The learned preconditioner end to end on the GPU, in the configuration the
+benchmark reports (200 training inversions, 20 epochs, 20 evaluation models
+x 50 iterations): training data from the plain batched inversion, training with the
 library's BF16 kernels, then safeguarded preconditioned descent against
 plain descent on unseen models.
 
@@ -20,7 +20,10 @@ pytestmark = pytest.mark.gpu
 
 
 def test_learned_preconditioner_gains_over_plain_descent():
-    cfg = ttm.TTMConfig(eval_seeds=tuple(range(10000, 10008)), eval_iters=30, epochs=10)
+    # A smaller evaluation (8 models x 30 iterations after 10 epochs) left the
+    # two medians within 0.2 % of each other, where a change in the rounding
+    # of the training data decides the order; the full evaluation separates them.
+    cfg = ttm.TTMConfig()
     out = ttm.run(cfg, log=print)
     print({k: v for k, v in out.items()})
     v0, v1 = out["val_loss_untrained_trained"]
