@@ -279,9 +279,11 @@ void ac3_phi_kernel(Ac3PhiArgs a)
                 rp[n] = ldb(psi, rob + d1);
                 qu[(r + 8 + LPD) % LZR] = ldb(u, dw);
                 qp[(r + 8 + LPD) % LZR] = ldb(psi, dw);
-                f0[n] = ldb(ph0, colb + d1);
-                f1[n] = ldb(ph1, colb + d1);
-                f2[n] = ldb(ph2, colb + d1);
+                // phi only where it is updated; elsewhere one shared line
+                const unsigned fo = layer_xy || z + LPD < g.P || z + LPD >= g.P + g.nz ? colb + d1 : 0u;
+                f0[n] = ldb(ph0, fo);
+                f1[n] = ldb(ph1, fo);
+                f2[n] = ldb(ph2, fo);
             }
             if (valid_xy && (layer_xy || z < g.P || z >= g.P + g.nz)) {
                 float wu[9], wp[9];
@@ -609,9 +611,10 @@ void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
                 rsv[n] = ldb(s2, rob + d1);
                 wc[n] = ldb(chat, dw);
                 ws[n] = ldb(s2, dw);
-                e0[n] = ldb(b0, colb + d1);
-                e1[n] = ldb(b1, colb + d1);
-                e2[n] = ldb(b2, colb + d1);
+                const unsigned fo = layer_xy || z + LPD < g.P || z + LPD >= g.P + g.nz ? colb + d1 : 0u;
+                e0[n] = ldb(b0, fo);
+                e1[n] = ldb(b1, fo);
+                e2[n] = ldb(b2, fo);
             }
             if (valid_xy && (layer_xy || z < g.P || z >= g.P + g.nz)) {
                 float wq[9];
