@@ -28,6 +28,14 @@
 //               + beta s^{k+2} + L~(chat s^{k+2}) - gamma s^{k+3}
 //     s^{k+1} = alpha a^{k+1};   dJ/dchat += s^{k+1} w~^k
 // using L~^T = L~ and D~^T = -D~ (zero cells beyond the grid).
+//
+// Cache policy: an operand that only its own cell reads or writes in a step
+// (u^{k-1} and s^{k+3} in the one-step kernels, the new wavefields, the
+// snapshots, the gradient accumulators) is loaded and stored non-temporally,
+// so that it does not displace what neighbouring tiles share (u^k, chat s,
+// chat, the layer auxiliaries).  A load that the ring of a neighbouring tile
+// repeats (u^{k-1}, s^{k+3} in the blocked kernels) stays cached: streaming
+// it made the blocked adjoint 2 % slower.
 #include "sg_internal.h"
 
 namespace sg {
@@ -237,21 +245,21 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
                 // alpha (beta u - gamma um + chat w + src) with
                 // beta u - gamma um = u + (u - um) + (hx + hz) um - 4 hx hz u
                 const float alpha = 1.f / (1.f + hx + hz);
-                const float umf = um[f];
+                const float umf = __builtin_nontemporal_load(um + f);
                 float inc = (uc[j] - umf) + ((hx + hz) * umf - 4.f * hx * hz * uc[j]) + chat[f] * w;
                 if (f == src) inc += sval;
                 if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
                 v = alpha * (uc[j] + inc);
             } else {
                 // 2u - um + chat w = u + ((u - um) + chat w)
-                float inc = fmaf(chat[f], w, uc[j] - um[f]);
+                float inc = fmaf(chat[f], w, uc[j] - __builtin_nontemporal_load(um + f));
                 if (f == src) inc += sval;
                 if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
                 v = uc[j] + inc;
             }
-            uo[f] = v;
+            __builtin_nontemporal_store(v, uo + f);
             un[j] = v;
-            if constexpr (SNAP) a.snap[so + f] = w;
+            if constexpr (SNAP) __builtin_nontemporal_store(w, a.snap + so + f);
         }
     }
 
@@ -362,10 +370,10 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
             if constexpr (NEAR) {
                 v -= d8(a.cx + so + f, 1) + d8(a.cz + so + f, (long long)g.SX);
                 const float hx = a.hx[ix], hz = a.hz[iz];
-                const float s3f = s3[f];
+                const float s3f = __builtin_nontemporal_load(s3 + f);
                 v += sc2[j] + ((sc2[j] - s3f) + ((hx + hz) * s3f - 4.f * hx * hz * sc2[j]));
             } else {
-                v += sc2[j] + (sc2[j] - s3[f]);
+                v += sc2[j] + (sc2[j] - __builtin_nontemporal_load(s3 + f));
             }
         }
         av[j] = v;
@@ -403,8 +411,8 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
             const long long f = fidx(g, iz, ix);
             float s1 = av[j];
             if constexpr (NEAR) s1 = s1 / (1.f + a.hx[ix] + a.hz[iz]);
-            s1o[f] = s1;
-            a.grad[so + f] = fmaf(s1, a.snap[so + f], a.grad[so + f]);
+            __builtin_nontemporal_store(s1, s1o + f);
+            __builtin_nontemporal_store(fmaf(s1, __builtin_nontemporal_load(a.snap + so + f), __builtin_nontemporal_load(a.grad + so + f)), a.grad + so + f);
             if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
         }
     }
@@ -531,8 +539,8 @@ __global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
         if (f == src) inc += sv0;
         u1[j] = uk[j] + inc;
         s1[(r + 4) * W1 + lx + 4] = u1[j];
-        a.u1[so + f] = u1[j];
-        if (a.snap0) a.snap0[so + f] = wk;
+        __builtin_nontemporal_store(u1[j], a.u1 + so + f);
+        if (a.snap0) __builtin_nontemporal_store(wk, a.snap0 + so + f);
     }
 #pragma unroll
     for (int it = 0; it < RING_IT; ++it) {
@@ -558,8 +566,8 @@ __global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
         const float wk = lap8(s1 + (r + 4) * W1 + lx + 4, W1);
         float inc = fmaf(ch[j], wk, u1[j] - uk[j]);
         if (f == src) inc += sv1;
-        a.u2[so + f] = u1[j] + inc;
-        if (a.snap1) a.snap1[so + f] = wk;
+        __builtin_nontemporal_store(u1[j] + inc, a.u2 + so + f);
+        if (a.snap1) __builtin_nontemporal_store(wk, a.snap1 + so + f);
     }
 }
 
@@ -589,9 +597,9 @@ __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
         ch[j] = chat[f];
         q2[j] = s2[f];
         q3[j] = s3[f];
-        gr[j] = a.grad[so + f];
-        w1[j] = a.snap1[so + f];
-        w0[j] = a.snap0[so + f];
+        gr[j] = __builtin_nontemporal_load(a.grad + so + f);
+        w1[j] = __builtin_nontemporal_load(a.snap1 + so + f);
+        w0[j] = __builtin_nontemporal_load(a.snap0 + so + f);
     }
     float rch[RING_IT], rq2[RING_IT], rq3[RING_IT];
 #pragma unroll
@@ -619,7 +627,7 @@ __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
         v += q2[j] + (q2[j] - q3[j]);
         v1[j] = v;
         p1[(r + 4) * W1 + lx + 4] = ch[j] * v;
-        a.o1[so + f] = v;
+        __builtin_nontemporal_store(v, a.o1 + so + f);
         if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = v * a.src_scale;
     }
 #pragma unroll
@@ -642,9 +650,9 @@ __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
         const long long f = fidx(g, z0 + r, x0 + lx);
         float v = lap8(p1 + (r + 4) * W1 + lx + 4, W1);
         v += v1[j] + (v1[j] - q2[j]);
-        a.o0[so + f] = v;
+        __builtin_nontemporal_store(v, a.o0 + so + f);
         float t = fmaf(v1[j], w1[j], gr[j]);
-        a.grad[so + f] = fmaf(v, w0[j], t);
+        __builtin_nontemporal_store(fmaf(v, w0[j], t), a.grad + so + f);
         if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k - 1] = v * a.src_scale;
     }
 }

@@ -27,6 +27,10 @@
 //   dJ/dchat_i += 1/2 (qb S' at the two half nodes beside node i, per axis),
 //   S' of forward step k being a snapshot
 // Y and Z alternate between two buffers like psi'.
+// Cache policy: u^{k-1} (lambda^{k+2}) and its overwrite, the snapshot
+// stores and the gradient accumulator are streamed (non-temporal); the
+// snapshot loads of the adjoint stay cached, since the half-node averages
+// read each of them from two rows (streaming them cost 16 % of the adjoint).
 #include <algorithm>
 #include "ad2_internal.h"
 
@@ -116,7 +120,7 @@ __device__ __forceinline__ float fwd_xflux(const Ad2FwdArgs &a, const float *su,
             if (own) a.psxn[so + f] = p;
         }
         if constexpr (SNAP) {
-            if (own) a.snx[so + f] = S;
+            if (own) __builtin_nontemporal_store(S, a.snx + so + f);
         }
         q = 0.5f * (c0 + c1) * S;
     }
@@ -143,7 +147,7 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     for (int m = 0; m < RPT + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
     float um[RPT];                        // u^{k-1} of the own rows, loaded early
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) um[j] = a.um[so + fr(g, z0 + r0 + j, ix)];
+    for (int j = 0; j < RPT; ++j) um[j] = __builtin_nontemporal_load(a.um + so + fr(g, z0 + r0 + j, ix));
     __syncthreads();
 
     // z fluxes of the own column at half rows z0+r0-2+m, m = 0 .. RPT+2
@@ -168,7 +172,7 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
                     if (own) a.pszn[so + f] = p;
                 }
                 if constexpr (SNAP) {
-                    if (own) a.snz[so + f] = S;
+                    if (own) __builtin_nontemporal_store(S, a.snz + so + f);
                 }
                 q = 0.5f * (cz[m] + cz[m + 1]) * S;
             }
@@ -222,7 +226,7 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
             inc += uc[j] - um[j];
             if (sb < se) inc += su[r * TX + lx];
             const float v = uc[j] + inc;
-            a.un[so + f] = v;
+            __builtin_nontemporal_store(v, a.un + so + f);
             un[j] = v;
         }
     }
@@ -330,7 +334,7 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
     for (int m = 0; m < RPT + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
     float l2[RPT];                        // lambda^{k+2} of the own rows, loaded early
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) l2[j] = a.l2[so + fr(g, z0 + r0 + j, ix)];
+    for (int j = 0; j < RPT; ++j) l2[j] = __builtin_nontemporal_load(a.l2 + so + fr(g, z0 + r0 + j, ix));
     __syncthreads();
     const float *hzz = NEAR ? hz : hx;
 
@@ -416,8 +420,8 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             const float lc = NEAR ? l1[f] : lam[j];
             float v = lc + ((lc - l2[j]) - (Dx + dz[j]));
             if (inj) v += hx[r * TX + lx];
-            a.l0[so + f] = v;
-            if constexpr (GRAD) a.gn[so + f] += gn;
+            __builtin_nontemporal_store(v, a.l0 + so + f);
+            if constexpr (GRAD) __builtin_nontemporal_store(__builtin_nontemporal_load(a.gn + so + f) + gn, a.gn + so + f);
         }
     }
 }

@@ -22,6 +22,9 @@
 // velocity adjoints, then forms the adjoints d1..d4 of the stress
 // differences (and the bx/bz gradients from the stored divergences); pass 3
 // applies those transposes to the stress adjoints.
+// Cache policy: the snapshots and the gradient accumulators, which only their
+// own cell touches, are loaded and stored non-temporally; the fields that the
+// stencils share stay cached.
 #include "el2_internal.h"
 
 namespace sg {
@@ -38,6 +41,12 @@ __device__ __forceinline__ float Dp(const float *f, long long i, long long s)
 __device__ __forceinline__ float Dm(const float *f, long long i, long long s)
 {
     return C1 * (f[i] - f[i - s]) + C2 * (f[i + s] - f[i - 2 * s]);
+}
+
+// gradient accumulator += v, streamed (non-temporal): read and written once per step
+__device__ __forceinline__ void gacc(float *p, float v)
+{
+    __builtin_nontemporal_store(__builtin_nontemporal_load(p) + v, p);
 }
 
 struct Cell {
@@ -86,8 +95,8 @@ __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
     a.f[E_VX][f] += a.kap * a.m[M_BX][c.mo + c.f] * fx;
     a.f[E_VZ][f] += a.kap * a.m[M_BZ][c.mo + c.f] * fz;
     if (a.snap) {
-        a.snap[3 * a.snap_stride + f] = fx;
-        a.snap[4 * a.snap_stride + f] = fz;
+        __builtin_nontemporal_store(fx, a.snap + 3 * a.snap_stride + f);
+        __builtin_nontemporal_store(fz, a.snap + 4 * a.snap_stride + f);
     }
 }
 
@@ -121,9 +130,9 @@ __global__ __launch_bounds__(256) void el2_str_kernel(El2Args a)
     a.f[E_SZZ][f] = szz;
     a.f[E_SXZ][f] = sxz;
     if (a.snap) {
-        a.snap[f] = e1;
-        a.snap[a.snap_stride + f] = e2;
-        a.snap[2 * a.snap_stride + f] = exz;
+        __builtin_nontemporal_store(e1, a.snap + f);
+        __builtin_nontemporal_store(e2, a.snap + a.snap_stride + f);
+        __builtin_nontemporal_store(exz, a.snap + 2 * a.snap_stride + f);
     }
 }
 
@@ -170,10 +179,11 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
     const float txx = a.kap * ((lam + 2.f * mu) * sxx + lam * szz);
     const float tzz = a.kap * (lam * sxx + (lam + 2.f * mu) * szz);
     const float txz = a.kap * a.m[M_MUXZ][c.mo + c.f] * sxz;
-    const float exx = a.snap[f], ezz = a.snap[a.snap_stride + f], exz = a.snap[2 * a.snap_stride + f];
-    a.grad[f] += a.kap * (exx + ezz) * (sxx + szz);
-    a.grad[a.grad_stride + f] += 2.f * a.kap * (exx * sxx + ezz * szz);
-    a.grad[2 * a.grad_stride + f] += a.kap * exz * sxz;
+    const float exx = __builtin_nontemporal_load(a.snap + f), ezz = __builtin_nontemporal_load(a.snap + a.snap_stride + f),
+                exz = __builtin_nontemporal_load(a.snap + 2 * a.snap_stride + f);
+    gacc(a.grad + f, a.kap * (exx + ezz) * (sxx + szz));
+    gacc(a.grad + a.grad_stride + f, 2.f * a.kap * (exx * sxx + ezz * szz));
+    gacc(a.grad + 2 * a.grad_stride + f, a.kap * exz * sxz);
     float e1 = txx, e2 = tzz, e3 = txz, e4 = txz;
     if (c.layer) {
         float q;
@@ -204,8 +214,8 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
     a.a[E_VZ][f] = vz;
     const float fxb = a.kap * a.m[M_BX][c.mo + c.f] * vx;
     const float fzb = a.kap * a.m[M_BZ][c.mo + c.f] * vz;
-    a.grad[3 * a.grad_stride + f] += a.kap * a.snap[3 * a.snap_stride + f] * vx;
-    a.grad[4 * a.grad_stride + f] += a.kap * a.snap[4 * a.snap_stride + f] * vz;
+    gacc(a.grad + 3 * a.grad_stride + f, a.kap * __builtin_nontemporal_load(a.snap + 3 * a.snap_stride + f) * vx);
+    gacc(a.grad + 4 * a.grad_stride + f, a.kap * __builtin_nontemporal_load(a.snap + 4 * a.snap_stride + f) * vz);
     float d1 = fxb, d2 = fxb, d3 = fzb, d4 = fzb;
     if (c.layer) {
         float q;
