@@ -61,6 +61,44 @@ def test_3d_forward_and_gradient_parity():
     assert e3 <= GRAD_TOL and e4 <= GRAD_TOL
 
 
+def test_3d_interior_tiles_two_chunks_parity():
+    """A grid with xy tiles beyond the stencil reach of the layer (the tile
+    passes' second launch, hx = hy = 0) and two z chunks (64 + 16 planes),
+    sources and receivers inside those tiles on interior and slab planes."""
+    nx, ny, nz, P, nt, dt = 100, 44, 60, 10, 150, 1e-3     # padded 120 x 64 x 80
+    NX, NY = nx + 2 * P, ny + 2 * P
+    interior = [(x0, y0) for x0 in range(0, NX, 32) for y0 in range(0, NY, 16)
+                if x0 - 4 >= P and x0 + 36 <= P + nx and y0 - 4 >= P and y0 + 20 <= P + ny]
+    assert len(interior) >= 4
+    c = 1600.0 + 1200.0 * synth.smooth_random(22, (nz, ny, nx), 3.0, 0.0, 1.0)
+    c0 = synth.smooth(c, 4.0)
+    src = np.array([[50, 22, 2], [60, 20, 40]], dtype=np.int32)
+    xs, ys = np.meshgrid(np.arange(0, nx, 4), np.arange(0, ny, 4), indexing="xy")
+    surf = np.stack([xs.ravel(), ys.ravel(), np.zeros(xs.size, dtype=int)], -1)
+    deep = np.stack([np.arange(30, 80, 2), np.full(25, 24), np.full(25, 30)], -1)
+    r = np.concatenate([surf, deep])
+    rec = np.stack([r, r]).astype(np.int32)
+    d = _desc3(nx, ny, nz, P, nt, dt)
+    wav = torch.stack([S.ricker(f, t, dt, nt) for f, t in ((20.0, 0.05), (25.0, 0.04))])
+    sh = S.Shots(src, rec, wav)
+    obs = S.Model(d, dev(c), 2, rec.shape[1], 14).forward(sh, save_ckpt=False)
+    m0 = S.Model(d, dev(c0), 2, rec.shape[1], 14)
+    pred = m0.forward(sh)
+    J, r_ = m0.misfit(pred, obs)
+    g = m0.gradient(sh, r_).cpu().numpy()[0]
+    go = _grid3(nx, ny, nz, P, nt, dt)
+    wo = np.stack([O.ricker(f, t, dt, nt) for f, t in ((20.0, 0.05), (25.0, 0.04))])
+    oo = O.ac3_forward(go, c, src, wo, rec)
+    op = O.ac3_forward(go, c0, src, wo, rec)
+    _, ro = O.misfit(op, oo)
+    og, _ = O.ac3_gradient(go, c0, src, wo, rec, ro, ckpt=14)
+    e1, e2 = rel_l2(obs.cpu().numpy()[:, 0], oo), rel_l2(pred.cpu().numpy()[:, 0], op)
+    e3 = rel_l2(g, og)
+    print(f"3-D interior tiles ({len(interior)}), two chunks: seis {e1:.2e} {e2:.2e} grad {e3:.2e}")
+    assert e1 <= SEIS_TOL and e2 <= SEIS_TOL
+    assert e3 <= GRAD_TOL
+
+
 def test_3d_checkpointed_equals_store_all_and_dot_identity():
     (nx, ny, nz, P, nt, dt), c, c0, src, rec = _small_case()
     nt = 120
