@@ -77,11 +77,6 @@ __device__ __forceinline__ int xcd_work_id(int nblocks)
     return x * per + min(x, rem) + j;
 }
 
-__device__ __forceinline__ bool tile_near_xy(const Grid3 &g, int x0, int y0)
-{
-    return g.P > 0 && (x0 - 4 < g.P || x0 + TX3 + 4 > g.P + g.nx || y0 - 4 < g.P || y0 + TY3 + 4 > g.P + g.ny);
-}
-
 __device__ __forceinline__ bool plane_near_z(const Grid3 &g, int z)
 {
     return g.P > 0 && (z - 4 < g.P || z + 4 >= g.P + g.nz);
@@ -111,11 +106,6 @@ constexpr int RING3 = 8 * (TX3 + 8) + 8 * TY3;
 // psi^k planes with a 4-cell ring in LDS, register windows along z, the
 // operands of the next plane loaded one plane ahead into rings (the scheme of
 // pass B below).  phi is updated at the layer cells only.
-__device__ __forceinline__ bool layer3(const Grid3 &g, int ix, int iy, int iz)
-{
-    return ix < g.P || ix >= g.P + g.nx || iy < g.P || iy >= g.P + g.ny || iz < g.P || iz >= g.P + g.nz;
-}
-
 __device__ __forceinline__ float d8w(const float *q)
 {
     return D1 * (q[5] - q[3]) + D2 * (q[6] - q[2]) + D3 * (q[7] - q[1]) + D4 * (q[8] - q[0]);
