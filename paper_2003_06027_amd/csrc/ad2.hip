@@ -27,8 +27,9 @@
 //   dJ/dchat_i += 1/2 (qb S' at the two half nodes beside node i, per axis),
 //   S' of forward step k being a snapshot
 // Y and Z alternate between two buffers like psi'.
-// Cache policy: u^{k-1} (lambda^{k+2}) and its overwrite, the snapshot
-// stores and the gradient accumulator are streamed (non-temporal); the
+// Cache policy: u^{k-1} (lambda^{k+2}) and its overwrite, the xi' memories,
+// the snapshot stores and the gradient accumulator are streamed
+// (non-temporal); the
 // snapshot loads of the adjoint stay cached, since the half-node averages
 // read each of them from two rows (streaming them cost 16 % of the adjoint).
 #include <algorithm>
@@ -217,10 +218,10 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
             const long long f = fr(g, iz, ix);
             float inc = Hx + hz[j];
             if constexpr (NEAR) {
-                const float xx = fmaf(a.t.b0x[ix], a.xix[so + f], a.t.a0x[ix] * Hx);
-                const float xz = fmaf(a.t.b0z[iz], a.xiz[so + f], a.t.a0z[iz] * hz[j]);
-                a.xix[so + f] = xx;
-                a.xiz[so + f] = xz;
+                const float xx = fmaf(a.t.b0x[ix], __builtin_nontemporal_load(a.xix + so + f), a.t.a0x[ix] * Hx);
+                const float xz = fmaf(a.t.b0z[iz], __builtin_nontemporal_load(a.xiz + so + f), a.t.a0z[iz] * hz[j]);
+                __builtin_nontemporal_store(xx, a.xix + so + f);
+                __builtin_nontemporal_store(xz, a.xiz + so + f);
                 inc += xx + xz;
             }
             inc += uc[j] - um[j];

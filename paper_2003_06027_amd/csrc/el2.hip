@@ -22,9 +22,10 @@
 // velocity adjoints, then forms the adjoints d1..d4 of the stress
 // differences (and the bx/bz gradients from the stored divergences); pass 3
 // applies those transposes to the stress adjoints.
-// Cache policy: the snapshots and the gradient accumulators, which only their
-// own cell touches, are loaded and stored non-temporally; the fields that the
-// stencils share stay cached.
+// Cache policy: the snapshots, the gradient accumulators and the adjoint CPML
+// memories, which only their own cell touches, are loaded and stored
+// non-temporally; the fields that the stencils share stay cached.  (The
+// forward CPML memories stay cached: streaming them slowed the forward.)
 #include "el2_internal.h"
 
 namespace sg {
@@ -187,10 +188,10 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
     float e1 = txx, e2 = tzz, e3 = txz, e4 = txz;
     if (c.layer) {
         float q;
-        q = txx + a.a[E_MVXX][f]; a.a[E_MVXX][f] = a.t.bx[0][c.ix] * q; e1 = txx + a.t.ax[0][c.ix] * q;
-        q = tzz + a.a[E_MVZZ][f]; a.a[E_MVZZ][f] = a.t.bz[0][c.iz] * q; e2 = tzz + a.t.az[0][c.iz] * q;
-        q = txz + a.a[E_MVXZ][f]; a.a[E_MVXZ][f] = a.t.bz[1][c.iz] * q; e3 = txz + a.t.az[1][c.iz] * q;
-        q = txz + a.a[E_MVZX][f]; a.a[E_MVZX][f] = a.t.bx[1][c.ix] * q; e4 = txz + a.t.ax[1][c.ix] * q;
+        q = txx + __builtin_nontemporal_load(a.a[E_MVXX] + f); __builtin_nontemporal_store(a.t.bx[0][c.ix] * q, a.a[E_MVXX] + f); e1 = txx + a.t.ax[0][c.ix] * q;
+        q = tzz + __builtin_nontemporal_load(a.a[E_MVZZ] + f); __builtin_nontemporal_store(a.t.bz[0][c.iz] * q, a.a[E_MVZZ] + f); e2 = tzz + a.t.az[0][c.iz] * q;
+        q = txz + __builtin_nontemporal_load(a.a[E_MVXZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MVXZ] + f); e3 = txz + a.t.az[1][c.iz] * q;
+        q = txz + __builtin_nontemporal_load(a.a[E_MVZX] + f); __builtin_nontemporal_store(a.t.bx[1][c.ix] * q, a.a[E_MVZX] + f); e4 = txz + a.t.ax[1][c.ix] * q;
     }
     a.tmp[0][f] = e1;
     a.tmp[1][f] = e2;
@@ -219,10 +220,10 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
     float d1 = fxb, d2 = fxb, d3 = fzb, d4 = fzb;
     if (c.layer) {
         float q;
-        q = fxb + a.a[E_MSXXX][f]; a.a[E_MSXXX][f] = a.t.bx[1][c.ix] * q; d1 = fxb + a.t.ax[1][c.ix] * q;
-        q = fxb + a.a[E_MSXZZ][f]; a.a[E_MSXZZ][f] = a.t.bz[0][c.iz] * q; d2 = fxb + a.t.az[0][c.iz] * q;
-        q = fzb + a.a[E_MSXZX][f]; a.a[E_MSXZX][f] = a.t.bx[0][c.ix] * q; d3 = fzb + a.t.ax[0][c.ix] * q;
-        q = fzb + a.a[E_MSZZZ][f]; a.a[E_MSZZZ][f] = a.t.bz[1][c.iz] * q; d4 = fzb + a.t.az[1][c.iz] * q;
+        q = fxb + __builtin_nontemporal_load(a.a[E_MSXXX] + f); __builtin_nontemporal_store(a.t.bx[1][c.ix] * q, a.a[E_MSXXX] + f); d1 = fxb + a.t.ax[1][c.ix] * q;
+        q = fxb + __builtin_nontemporal_load(a.a[E_MSXZZ] + f); __builtin_nontemporal_store(a.t.bz[0][c.iz] * q, a.a[E_MSXZZ] + f); d2 = fxb + a.t.az[0][c.iz] * q;
+        q = fzb + __builtin_nontemporal_load(a.a[E_MSXZX] + f); __builtin_nontemporal_store(a.t.bx[0][c.ix] * q, a.a[E_MSXZX] + f); d3 = fzb + a.t.ax[0][c.ix] * q;
+        q = fzb + __builtin_nontemporal_load(a.a[E_MSZZZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MSZZZ] + f); d4 = fzb + a.t.az[1][c.iz] * q;
     }
     a.tmp[4][f] = d1;
     a.tmp[5][f] = d2;
