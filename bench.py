@@ -68,13 +68,20 @@ def bytes_per_cell_step_div(pml_fraction):
     return {"forward": f, "recompute": f + 8.0, "adjoint": 32.0 + 32.0 * pml_fraction}
 
 
-def measured_traffic(phase, divergence=False):
+TRAFFIC_FILES = {   # workload -> committed counter summary, the kernel sources it was taken with
+    "c2": ("ac2_c2_hbm_traffic.txt", ("ac2.hip", "sg_internal.h")),
+    "div": ("ad2_c2_hbm_traffic.txt", ("ad2.hip", "ad2_internal.h", "sg_internal.h")),
+    "c3": ("el2_c3_hbm_traffic.txt", ("el2.hip", "el2_internal.h", "sg_internal.h")),
+    "c4": ("ac3_c4_hbm_traffic.txt", ("ac3.hip", "ac3_internal.h", "sg_internal.h")),
+}
+
+
+def measured_traffic(phase, workload="c2"):
     """HBM bytes per step of `phase` from the committed FETCH_SIZE/WRITE_SIZE
     summary (counters scaled by a plain copy of known size), or None when the
     kernels' source has changed since the counters were taken."""
     import hashlib
-    name, files = (("ad2_c2_hbm_traffic.txt", ("ad2.hip", "ad2_internal.h", "sg_internal.h")) if divergence
-                   else ("ac2_c2_hbm_traffic.txt", ("ac2.hip", "sg_internal.h")))
+    name, files = TRAFFIC_FILES[workload]
     path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2003_06027_amd", "csrc")
     try:
@@ -322,7 +329,7 @@ def main():
                     "alg_bytes_per_cell": round(bpc[name], 3), "gbs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     dom = max(ph, key=lambda k: phases[k][0])
-    traffic = measured_traffic(dom, div) if wl == "c2" else None   # HBM bytes per step (all launches)
+    traffic = measured_traffic(dom, "div" if div else wl)   # HBM bytes per step (all launches)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
