@@ -100,26 +100,12 @@ __device__ __forceinline__ void ring_rc(int i, int &r, int &c)
 }
 constexpr int RING3 = 8 * (TX3 + 8) + 8 * TY3;
 
-// ------------------------------------------------------------ forward pass A
-// z-marching over the layer work items (every plane of the tiles that touch
-// the layer in x or y, the z slabs of the others), like pass B: u^k and
-// psi^k planes with a 4-cell ring in LDS, register windows along z, the
-// operands of the next plane loaded one plane ahead into rings (the scheme of
-// pass B below).  phi is updated at the layer cells only.
 __device__ __forceinline__ float d8w(const float *q)
 {
     return D1 * (q[5] - q[3]) + D2 * (q[6] - q[2]) + D3 * (q[7] - q[1]) + D4 * (q[8] - q[0]);
 }
 
-
-// ------------------------------------------------------------ forward pass B
-// Two launches over (xy tile, z chunk, shot): the tiles within 4 cells of the
-// layer in x or y (LAYER: every plane takes the layer terms) and the others
-// (only the z slabs do; their cells are interior in x and y, hx = hy = 0).
-// In LAYER tiles the layer auxiliaries are staged like u: phi_x with its x
-// halo and phi_y with its y halo in LDS planes, phi_z in a register window;
-// the other tiles read the few stencil points of their slab planes directly.
-//
+// ------------------------------------------------------------ marching scheme
 // Every per-plane operand is loaded PD planes ahead into registers that the
 // planes in between do not use: the z windows are rings of ZR registers (9
 // in use, the next PD receiving planes z + 5 ..), the other operands rings of
@@ -127,8 +113,9 @@ __device__ __forceinline__ float d8w(const float *q)
 // compile-time constants.  The prefetch loads are unconditional (addresses
 // stay inside the frame; unused values are dropped) and so are the stores
 // that follow them, so that the memory counter waits are exact and do not
-// wait for the loads just issued; the conditional psi store of a plane is
-// issued at the start of the next one, before its prefetch.  Addresses are
+// wait for the loads just issued; a conditional store of a plane (psi, phi,
+// e on layer cells) is issued at the start of the next one, before its
+// prefetch.  Streaming operands use non-temporal loads and stores.  Addresses are
 // 32-bit byte offsets from per-block bases at the chunk's first window plane
 // (the host bounds (TZC + 8) planes below 4 GiB).
 constexpr int PD = 1, NB = PD + 1, ZR = 10;
@@ -177,7 +164,13 @@ __device__ __forceinline__ float d8b(const float *b, unsigned o, unsigned sb)
          + D3 * (ldb(b, o + 3 * sb) - ldb(b, o - 3 * sb)) + D4 * (ldb(b, o + 4 * sb) - ldb(b, o - 4 * sb));
 }
 
-// forward pass A (described above): phi~_j^k = p_j phi~_j^{k-1} + q_j D~_j u^k + r_j D~_j psi^k
+// ------------------------------------------------------------ forward pass A
+// z-marching over the layer work items (every plane of the tiles that touch
+// the layer in x or y, the z slabs of the others), like pass B: u^k and
+// psi^k planes with a 4-cell ring in LDS, register windows along z, the
+// operands of the next plane loaded one plane ahead into rings (the marching
+// scheme above).  phi is updated at the layer cells only, and loaded only
+// there (elsewhere every lane reads one shared line).
 constexpr int LPD = 1, LNB = LPD + 1, LZR = 10;
 static_assert(LZR % LNB == 0 && 8 + LPD < LZR, "ring sizes");
 
@@ -301,6 +294,13 @@ void ac3_phi_kernel(Ac3PhiArgs a)
     }
 }
 
+// ------------------------------------------------------------ forward pass B
+// Two launches over (xy tile, z chunk, shot): the tiles within 4 cells of the
+// layer in x or y (LAYER: every plane takes the layer terms) and the others
+// (only the z slabs do; their cells are interior in x and y, hx = hy = 0).
+// In LAYER tiles the layer auxiliaries are staged like u: phi_x with its x
+// halo and phi_y with its y halo in LDS planes, phi_z in a register window;
+// the other tiles read the few stencil points of their slab planes directly.
 template <bool SNAP, bool REC, bool LAYER>
 __global__ __launch_bounds__(NTH3) __attribute__((amdgpu_waves_per_eu(LAYER ? 4 : 8)))
 void ac3_fwd_kernel(Ac3FwdArgs a)
