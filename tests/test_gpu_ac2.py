@@ -126,6 +126,24 @@ def test_ragged_multishot_multimodel_parity():
         assert e1 <= SEIS_TOL and e2 <= SEIS_TOL and e3 <= GRAD_TOL
 
 
+def test_no_layer_rigid_box_parity():
+    """npml = 0: no layer pass, rigid walls at the grid edge, the blocked
+    tiles reaching to within 8 cells of the edge; reflections within the
+    window (sources next to two walls)."""
+    cfg = synth.C1.replace(nx=200, nz=120, npml=0, nt=300, dt=1e-3)
+    c = 1700.0 + 800.0 * synth.smooth_random(5, (cfg.nz, cfg.nx), 4.0, 0.0, 1.0)
+    c0 = synth.smooth(c, 3.0)
+    src = np.array([[3, 2], [190, 110]], dtype=np.int32)
+    xs = np.arange(0, cfg.nx, 3)
+    rec = np.stack([np.stack([xs, np.zeros_like(xs)], -1), np.stack([xs, np.full_like(xs, 60)], -1)]).astype(np.int32)
+    f0s, t0s = [15.0, 18.0], [0.07, 0.06]
+    out = _run_case(cfg, c, c0, src, rec, f0s, t0s, 2500.0, ckpt=17)
+    ref = _oracle_case(cfg, c, c0, src, rec, f0s, t0s, 2500.0)
+    e1, e2, e3 = rel_l2(out["obs"], ref["obs"]), rel_l2(out["pred"], ref["pred"]), rel_l2(out["grad"][0], ref["grad"])
+    print(f"no layer: seis {e1:.2e} {e2:.2e} grad {e3:.2e}")
+    assert e1 <= SEIS_TOL and e2 <= SEIS_TOL and e3 <= GRAD_TOL
+
+
 def test_checkpointed_equals_store_all_bitwise_and_deterministic():
     cfg = synth.C1.replace(nt=200)
     ct = synth.layered_c1()

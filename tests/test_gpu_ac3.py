@@ -99,6 +99,37 @@ def test_3d_interior_tiles_two_chunks_parity():
     assert e3 <= GRAD_TOL
 
 
+def test_3d_no_layer_parity():
+    """npml = 0: no layer passes and no tile within reach of a layer (one
+    launch of the interior tile passes), rigid walls at the grid edge."""
+    nx, ny, nz, nt, dt = 70, 40, 36, 150, 1e-3
+    c = 1600.0 + 1000.0 * synth.smooth_random(23, (nz, ny, nx), 3.0, 0.0, 1.0)
+    c0 = synth.smooth(c, 4.0)
+    src = np.array([[3, 3, 2], [60, 30, 30]], dtype=np.int32)
+    xs, ys = np.meshgrid(np.arange(0, nx, 3), np.arange(0, ny, 3), indexing="xy")
+    r = np.stack([xs.ravel(), ys.ravel(), np.zeros(xs.size, dtype=int)], -1)
+    rec = np.stack([r, r]).astype(np.int32)
+    d = _desc3(nx, ny, nz, 0, nt, dt)
+    wav = torch.stack([S.ricker(f, t, dt, nt) for f, t in ((20.0, 0.05), (25.0, 0.04))])
+    sh = S.Shots(src, rec, wav)
+    obs = S.Model(d, dev(c), 2, rec.shape[1], 12).forward(sh, save_ckpt=False)
+    m0 = S.Model(d, dev(c0), 2, rec.shape[1], 12)
+    pred = m0.forward(sh)
+    J, r_ = m0.misfit(pred, obs)
+    g = m0.gradient(sh, r_).cpu().numpy()[0]
+    go = _grid3(nx, ny, nz, 0, nt, dt)
+    wo = np.stack([O.ricker(f, t, dt, nt) for f, t in ((20.0, 0.05), (25.0, 0.04))])
+    oo = O.ac3_forward(go, c, src, wo, rec)
+    op = O.ac3_forward(go, c0, src, wo, rec)
+    _, ro = O.misfit(op, oo)
+    og, _ = O.ac3_gradient(go, c0, src, wo, rec, ro, ckpt=12)
+    e1, e2 = rel_l2(obs.cpu().numpy()[:, 0], oo), rel_l2(pred.cpu().numpy()[:, 0], op)
+    e3 = rel_l2(g, og)
+    print(f"3-D no layer: seis {e1:.2e} {e2:.2e} grad {e3:.2e}")
+    assert e1 <= SEIS_TOL and e2 <= SEIS_TOL
+    assert e3 <= GRAD_TOL
+
+
 def test_3d_checkpointed_equals_store_all_and_dot_identity():
     (nx, ny, nz, P, nt, dt), c, c0, src, rec = _small_case()
     nt = 120
