@@ -72,6 +72,34 @@ def test_elastic_forward_and_gradient_parity():
     assert max(e_g) <= GRAD_TOL
 
 
+def test_elastic_no_layer_parity():
+    """npml = 0: no CPML memories touched, rigid walls at the grid edge,
+    sources next to two walls."""
+    c, vp, vs, rho, src, mt, rec = _case(nx=120, nz=70, P=0, nt=400)
+    src = np.array([[3, 2], [110, 60], [60, 35]], dtype=np.int32)
+    vp0, vs0, rho0 = (synth.smooth(a, 5.0) for a in (vp, vs, rho))
+    d = _desc(c)
+    f0s = [15.0, 12.0, 18.0]
+    wav = torch.stack([S.ricker(f, 1.0 / f, c["dt"], c["nt"]) for f in f0s])
+    sh = S.Shots(src, rec, wav, mt)
+    obs = _model(d, vp, vs, rho, 3, rec.shape[1], 21).forward(sh, save_ckpt=False)
+    m0 = _model(d, vp0, vs0, rho0, 3, rec.shape[1], 21)
+    pred = m0.forward(sh)
+    J, r = m0.misfit(pred, obs)
+    gv = [x.cpu().numpy()[0] for x in m0.gradient(sh, r)]
+    go = _grid(c)
+    wo = np.stack([O.ricker(f, 1.0 / f, c["dt"], c["nt"]) for f in f0s])
+    oo = O.el2_forward(go, vp, vs, rho, src, mt, wo, rec)
+    op = O.el2_forward(go, vp0, vs0, rho0, src, mt, wo, rec)
+    _, ro = O.misfit(op, oo)
+    og, _ = O.el2_gradient(go, vp0, vs0, rho0, src, mt, wo, rec, ro, ckpt=20)
+    e_obs, e_pred = rel_l2(obs.cpu().numpy(), oo), rel_l2(pred.cpu().numpy(), op)
+    e_g = [rel_l2(a, b) for a, b in zip(gv, og)]
+    print(f"elastic no layer: seis {e_obs:.2e} {e_pred:.2e}; grad vp/vs/rho {e_g[0]:.2e} {e_g[1]:.2e} {e_g[2]:.2e}")
+    assert e_obs <= SEIS_TOL and e_pred <= SEIS_TOL
+    assert max(e_g) <= GRAD_TOL
+
+
 def test_elastic_checkpointing_and_dot_identity():
     c, vp, vs, rho, src, mt, rec = _case(nt=300)
     d = _desc(c)
