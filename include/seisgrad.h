@@ -178,8 +178,10 @@ SG_API int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t s
 /* L2 misfit (display after Eq. (1)): resid = pred - obs (FP32) and
  * J = 1/2 sum resid^2 accumulated in FP64 in a fixed order (bitwise
  * reproducible).
- *   pred, obs: DEVICE FP32 [n]; J_dev: DEVICE double[1]; resid: DEVICE FP32
- *   [n] or NULL (may alias pred).  With a model the reduction runs over many
+ *   pred, obs: DEVICE FP32 [n] (may be NULL when n == 0, which gives J = 0);
+ *   J_dev: DEVICE double[1]; resid: DEVICE FP32 [n] or NULL (may alias
+ *   pred).  Errors: SG_EINVAL for n < 0, J_dev NULL, or pred/obs NULL with
+ *   n > 0.  With a model the reduction runs over many
  *   workgroups and keeps its partial sums in the model's workspace; with
  *   m == NULL it runs in one workgroup (slower, no workspace).
  * Non-finite inputs give a non-finite J; the call itself does not sync. */

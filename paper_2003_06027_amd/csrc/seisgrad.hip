@@ -1331,7 +1331,7 @@ int misfit(sg_model *m, const float *pred, const float *obs, int64_t n, double *
            float *resid, sg_stream_t stream)
 {
     g_err.clear();
-    if (!pred || !obs || !J_dev || n < 0) return fail(SG_EINVAL, "bad misfit arguments");
+    if (!J_dev || n < 0 || (n > 0 && (!pred || !obs))) return fail(SG_EINVAL, "bad misfit arguments");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     launch_misfit(pred, obs, n, resid, m ? m->partials : nullptr, m ? 4096 : 1, J_dev, s);
     HIPCHECK(hipGetLastError());

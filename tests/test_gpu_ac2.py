@@ -144,6 +144,47 @@ def test_no_layer_rigid_box_parity():
     assert e1 <= SEIS_TOL and e2 <= SEIS_TOL and e3 <= GRAD_TOL
 
 
+def test_degenerate_sizes():
+    """One and two time steps; a 5 x 3 grid without a layer (one tile, most of
+    it outside the grid); a shot without receivers (empty seismogram, J = 0,
+    zero gradient)."""
+    for nt in (1, 2):                                   # nt = 1: only the source term, zero gradient
+        cfg = synth.C1.replace(nx=30, nz=20, npml=10, nt=nt, dt=1e-3)
+        c = np.full((cfg.nz, cfg.nx), 2000.0)
+        c[8:12, 8:14] = 2300.0
+        src = np.array([[10, 9]], dtype=np.int32)
+        rec = np.array([[[10, 9], [11, 9], [12, 10]]], dtype=np.int32)
+        out = _run_case(cfg, c, synth.smooth(c, 2.0), src, rec, [15.0], [0.0], 2500.0)
+        ref = _oracle_case(cfg, c, synth.smooth(c, 2.0), src, rec, [15.0], [0.0], 2500.0)
+        assert rel_l2(out["obs"], ref["obs"]) <= SEIS_TOL and rel_l2(out["pred"], ref["pred"]) <= SEIS_TOL
+        if nt == 1:
+            assert np.all(ref["grad"] == 0.0) and np.all(out["grad"] == 0.0)
+        else:
+            assert np.abs(ref["grad"]).max() > 0 and rel_l2(out["grad"][0], ref["grad"]) <= GRAD_TOL
+    cfg = synth.C1.replace(nx=5, nz=3, npml=0, nt=50, dt=1e-3)
+    c = np.array([[2000.0, 2100, 2200, 2100, 2000]] * 3)
+    src = np.array([[2, 1]], dtype=np.int32)
+    rec = np.array([[[0, 0], [4, 2]]], dtype=np.int32)
+    out = _run_case(cfg, c, np.full_like(c, 2100.0), src, rec, [15.0], [0.07], 2500.0)
+    ref = _oracle_case(cfg, c, np.full_like(c, 2100.0), src, rec, [15.0], [0.07], 2500.0)
+    e = (rel_l2(out["obs"], ref["obs"]), rel_l2(out["pred"], ref["pred"]), rel_l2(out["grad"][0], ref["grad"]))
+    print(f"5 x 3 grid: seis {e[0]:.2e} {e[1]:.2e} grad {e[2]:.2e}")
+    assert e[0] <= SEIS_TOL and e[1] <= SEIS_TOL and e[2] <= GRAD_TOL
+    # no receivers
+    cfg = synth.C1.replace(nx=40, nz=30, npml=10, nt=60, dt=1e-3)
+    d = gpu_desc(cfg, 2500.0)
+    sh = S.Shots(np.array([[20, 5]], dtype=np.int32), np.zeros((1, 0, 2), dtype=np.int32),
+                 gpu_wavelets([15.0], [0.07], cfg.dt, cfg.nt))
+    m = S.Model(d, dev(np.full((cfg.nz, cfg.nx), 2000.0)), 1, 0)
+    seis = m.forward(sh)
+    assert seis.shape == (1, 1, cfg.nt, 0)
+    J, r = m.misfit(seis, seis)
+    g = m.gradient(sh, r)
+    torch.cuda.synchronize()
+    assert J.item() == 0.0 and torch.count_nonzero(g).item() == 0
+    m.close()
+
+
 def test_checkpointed_equals_store_all_bitwise_and_deterministic():
     cfg = synth.C1.replace(nt=200)
     ct = synth.layered_c1()
