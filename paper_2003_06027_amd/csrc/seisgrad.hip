@@ -1018,6 +1018,10 @@ size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int
         fail(SG_EINVAL, "max_shots >= 1, max_rec >= 0 and ckpt_every >= 0 required");
         return 0;
     }
+    if ((long long)max_rec >= (1LL << REC_ID_BITS)) {     // as init_model
+        fail(SG_EINVAL, "at most %d receivers per shot", (1 << REC_ID_BITS) - 1);
+        return 0;
+    }
     return make_layout(d, max_shots, max_rec, ckpt_every).total;
 }
 

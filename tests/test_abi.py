@@ -51,6 +51,27 @@ def test_workspace_bytes_validation_on_host():
         S.workspace_bytes(S.desc(ndim=4, nx=10, nz=10, ny=10), 1, 1)
 
 
+def test_size_limits_on_host():
+    """The largest grids the kernels' index arithmetic supports are accepted,
+    one step beyond is refused with a message (no GPU needed)."""
+    # 3-D: a z chunk and its window planes must stay below 4 GiB of byte offsets
+    ok = S.desc(ndim=3, nx=3500, ny=3500, nz=64, npml=0, nt=10)
+    assert S.workspace_bytes(ok, 1, 1) > 0
+    with pytest.raises(S.SeisError) as e:
+        S.workspace_bytes(S.desc(ndim=3, nx=4000, ny=4000, nz=64, npml=0, nt=10), 1, 1)
+    assert "planes" in str(e.value)        # workspace_bytes returns 0; the message names the limit
+    # 3-D: 12-bit plane field of the receiver sort key
+    assert S.workspace_bytes(S.desc(ndim=3, nx=8, ny=8, nz=4095, npml=0, nt=10), 1, 1) > 0
+    with pytest.raises(S.SeisError) as e:
+        S.workspace_bytes(S.desc(ndim=3, nx=8, ny=8, nz=4000, npml=48, nt=10), 1, 1)
+    assert "padded planes in z" in str(e.value)
+    # receivers per shot: 20-bit receiver ids
+    with pytest.raises(S.SeisError) as e:
+        S.workspace_bytes(S.desc(nx=100, nz=50, npml=10, nt=10), 1, 1 << 20)
+    assert "receivers" in str(e.value)
+    assert S.workspace_bytes(S.desc(nx=100, nz=50, npml=10, nt=10), 1, (1 << 20) - 1) > 0
+
+
 def test_init_model_rejects_null_arguments_without_gpu():
     d = S.desc(nx=100, nz=50, npml=10, nt=100)
     h = C.c_void_p()
