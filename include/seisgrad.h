@@ -132,8 +132,10 @@ typedef struct sg_model sg_model;
 
 /* Bytes of device workspace needed for up to max_shots shots of up to
  * max_rec receivers each, with wavefield checkpoints every ckpt_every steps
- * (0 -> ceil(sqrt(nt))).  Returns 0 on an invalid descriptor (see
- * last_error()). */
+ * (0 -> ceil(sqrt(nt))).  Returns 0 (reason in last_error()) on an invalid
+ * descriptor or a size beyond the build's limits: 2^20 - 1 receivers per
+ * shot; 3-D grids below 4096 padded planes in z, and 76 padded planes of
+ * the xy frame below 4 GiB. */
 SG_API size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int32_t ckpt_every);
 
 /* Bytes that one stored checkpoint segment of adjoint snapshots takes in the
