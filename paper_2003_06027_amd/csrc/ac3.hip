@@ -697,12 +697,18 @@ void ac3_adj_kernel(Ac3AdjArgs a)
         rob = (unsigned)((y0 - 4 + r + OY3) * g.sy + x0 - 4 + c + OX3) * 4u;
     }
     // q: chat s^{k+2} of planes z - 4 .. z + 4 (ring); wc, ws: the factors
-    // of plane z + 4 + APD; the other rings: planes z .. z + APD
-    float q[AZR], wc[ANB], ws[ANB], rc[ANB], rsv[ANB], srv[ANB], s3v[ANB], snv[ANB], gv[ANB];
+    // of plane z + 4 + APD; the other rings: planes z .. z + APD.  The
+    // pointwise terms need s^{k+2} at the centre: interior tiles keep it in a
+    // window beside q (sw), layer tiles, short of registers, load it again (srv).
+    constexpr bool SWIN = !LAYER;
+    float q[AZR], sw[SWIN ? AZR : 1], srv[SWIN ? 1 : ANB];
+    float wc[ANB], ws[ANB], rc[ANB], rsv[ANB], s3v[ANB], snv[ANB], gv[ANB];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const unsigned o = colb + pbc(z0 - 4 + m);
-        q[m] = ldb(chat, o) * ldb(s2, o);
+        const float sv = ldb(s2, o);
+        q[m] = ldb(chat, o) * sv;
+        if constexpr (SWIN) sw[m] = sv;
     }
 #pragma unroll
     for (int d = 0; d < APD; ++d) {
@@ -711,7 +717,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
         ws[d] = ldb(s2, ow);
         rc[d] = ldb(chat, rob + o);
         rsv[d] = ldb(s2, rob + o);
-        srv[d] = ldb(s2, colb + o);
+        if constexpr (!SWIN) srv[d] = ldb(s2, colb + o);
         s3v[d] = ldn(s3, colb + o);
         snv[d] = ldn(snap, colb + o);
         gv[d] = ldn(grad, colb + o);
@@ -766,6 +772,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
             if (esw) stb(ee, esf, esn);
             esw = false;
             q[(r + 8) % AZR] = wc[c] * ws[c];
+            if constexpr (SWIN) sw[(r + 8) % AZR] = ws[c];
             float *P = pl[z & 1];
             P[(ly + 4) * W + lx + 4] = q[(r + 4) % AZR];
             if (rs >= 0) P[rs] = rc[c] * rsv[c];
@@ -795,7 +802,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
                 }
                 wc[n] = ldb(chat, colb + dw);
                 ws[n] = ldb(s2, colb + dw);
-                srv[n] = ldb(s2, colb + d1);
+                if constexpr (!SWIN) srv[n] = ldb(s2, colb + d1);
                 s3v[n] = ldn(s3, colb + d1);
                 snv[n] = ldn(snap, colb + d1);
                 gv[n] = ldn(grad, colb + d1);
@@ -808,7 +815,10 @@ void ac3_adj_kernel(Ac3AdjArgs a)
 #pragma unroll
             for (int m = 0; m < 9; ++m) qw[m] = q[(r + m) % AZR];
             const float *cc = P + (ly + 4) * W + lx + 4;
-            const float sraw = srv[c], s3f = s3v[c];
+            float sraw;
+            if constexpr (SWIN) sraw = sw[(r + 4) % AZR];
+            else sraw = srv[c];
+            const float s3f = s3v[c];
             float v = lap3(cc, W, qw);
             bool nearz = false;
             float hs = 0.f;
