@@ -418,7 +418,9 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
     }
 }
 
-__global__ __launch_bounds__(NTH) void ac2_adj_kernel(Ac2AdjArgs a)
+// (8 waves per SIMD: 64 VGPRs, no spill; measured 2 % faster than the
+// compiler's choice of 70.  The forward's one-step variants are slower at 8.)
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8))) void ac2_adj_kernel(Ac2AdjArgs a)
 {
     __shared__ float sc[(TZ + 8) * (TX + 8)];
     const int ntl = a.tiles ? a.ntl : a.g.ntx * a.g.ntz;
