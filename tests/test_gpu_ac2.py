@@ -185,6 +185,44 @@ def test_degenerate_sizes():
     m.close()
 
 
+def test_c2_full_grid_short_window_parity():
+    """The 1000 x 500 (+32-cell layer) launch configuration as timed: all 64
+    shots in one launch, two steps per launch on the blocked tiles,
+    checkpoints every 64 steps (here over a 250-step window).  Seismograms of
+    two sampled shots against the oracle; the gradient driven by those two
+    shots' residuals (zero residual for the others, which then add nothing)
+    against the oracle's gradient for them."""
+    cfg = synth.C2
+    nt = 250
+    true = synth.dipping_layers_anomalies(2003, cfg.nx, cfg.nz, cfg.dx)
+    c0 = synth.smooth(true, 10.0)
+    src, rec = synth.c2_geometry(cfg.nshots, cfg.nx)
+    vmax = 4500.0
+    d = S.desc(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+               pml_R=cfg.pml_R, pml_vmax=vmax)
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)[None].repeat(cfg.nshots, 1).contiguous()
+    sh = S.Shots(src, rec, wav)
+    m = S.Model(d, dev(c0), cfg.nshots, rec.shape[1], 64)
+    m.set_time_blocking(2)
+    seis = m.forward(sh)
+    sel = [5, 40]
+    go = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt,
+                pml_R=cfg.pml_R, pml_vmax=vmax)
+    wo = np.stack([O.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)] * len(sel))
+    op = O.ac2_forward(go, c0, src[sel], wo, rec[sel])
+    oo = O.ac2_forward(go, true, src[sel], wo, rec[sel])
+    _, ro = O.misfit(op, oo)
+    dJ = torch.zeros_like(seis)
+    dJ[sel, 0] = dev(ro)
+    g = m.gradient(sh, dJ).cpu().numpy()[0]
+    og, _ = O.ac2_gradient(go, c0, src[sel], wo, rec[sel], ro, ckpt=16)
+    e1, e2 = rel_l2(seis.cpu().numpy()[sel, 0], op), rel_l2(g, og)
+    print(f"C2 full grid, {nt} steps, shots {sel}: seis rel-L2 {e1:.2e}, grad rel-L2 {e2:.2e}")
+    assert np.abs(op).max() > 0 and np.abs(og).max() > 0
+    assert e1 <= SEIS_TOL and e2 <= GRAD_TOL
+    m.close()
+
+
 def test_checkpointed_equals_store_all_bitwise_and_deterministic():
     cfg = synth.C1.replace(nt=200)
     ct = synth.layered_c1()
