@@ -172,6 +172,40 @@ def test_full_grid_short_window():
     assert es <= SEIS_TOL and eg <= GRAD_TOL
 
 
+def test_c2_configuration_sampled_shots():
+    """The divergence form in the benchmark's launch configuration (1000 x 500
+    + 32-cell CPML, all 64 point-source shots in one launch, checkpoints every
+    64 steps) over a 250-step window: seismograms of two sampled shots, and
+    the gradient driven by their residuals alone, against the oracle."""
+    cfg = synth.C2
+    nt = 250
+    true = synth.dipping_layers_anomalies(2003, cfg.nx, cfg.nz, cfg.dx)
+    c0 = synth.smooth(true, 10.0)
+    src, rec = synth.c2_geometry(cfg.nshots, cfg.nx)
+    vmax = 4500.0
+    d = S.desc(ndim=2, physics=S.SG_ACOUSTIC_DIV, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx,
+               dt=cfg.dt, pml_R=cfg.pml_R, pml_vmax=vmax, f0_pml=cfg.f0)
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)[None].repeat(cfg.nshots, 1).contiguous()
+    sh = S.Shots(src, rec, wav)
+    m = S.Model(d, dev(c0), cfg.nshots, rec.shape[1], 64)
+    seis = m.forward(sh)
+    sel = [5, 40]
+    g = O.grid(ndim=2, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, dx=cfg.dx, dt=cfg.dt, pml_R=cfg.pml_R,
+               pml_vmax=vmax, f0_pml=cfg.f0)
+    w = np.stack([O.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)] * len(sel))
+    pred = O.ad2_forward(g, c0, src[sel], w, rec[sel])
+    obs = O.ad2_forward(g, true, src[sel], w, rec[sel])
+    dJ = torch.zeros_like(seis)
+    dJ[sel, 0] = dev(pred - obs)
+    gg = m.gradient(sh, dJ).cpu().numpy()[0]
+    og, _, _ = O.ad2_gradient(g, c0, src[sel], w, rec[sel], pred - obs)
+    es, eg = rel_l2(seis.cpu().numpy()[sel, 0], pred), rel_l2(gg, og)
+    print(f"C2 divergence form, {nt} steps, shots {sel}: seis {es:.2e} grad {eg:.2e}")
+    assert np.abs(pred).max() > 0 and np.abs(og).max() > 0
+    assert es <= SEIS_TOL and eg <= GRAD_TOL
+    m.close()
+
+
 def test_layered_model_plane_wave_inversion():
     nx, nz, P, nt, dx, dt = 160, 80, 16, 900, 20.0, 2e-3
     c_true, c0, src, wav, rec, _ = _plane_wave_case(nx, nz, dx, dt, nt)
