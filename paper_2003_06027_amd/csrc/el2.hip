@@ -33,7 +33,10 @@ namespace {
 
 constexpr float C1 = (float)(9.0 / 8.0);
 constexpr float C2 = (float)(-1.0 / 24.0);
-constexpr int EBX = 64, EBZ = 4;   // cell block
+// Cell blocks of 256 threads, EBX x (256 / EBX) cells: 256 x 1 for the
+// forward passes, 128 x 2 for the adjoint passes (measured best of 64 x 4,
+// 32 x 8, 128 x 2 and 256 x 1 for each).
+constexpr int EBX_FWD = 256, EBX_ADJ = 128;
 
 __device__ __forceinline__ float Dp(const float *f, long long i, long long s)
 {
@@ -56,8 +59,10 @@ struct Cell {
     long long f, so, mo;   // frame index, shot and model offsets
 };
 
+template <int EBX>
 __device__ __forceinline__ Cell cell_of(const Grid2 &g, int spm)
 {
+    constexpr int EBZ = 256 / EBX;
     Cell c;
     const int ntxe = (g.NX + EBX - 1) / EBX;
     const int bx = blockIdx.x % ntxe, bz = blockIdx.x / ntxe;
@@ -72,15 +77,17 @@ __device__ __forceinline__ Cell cell_of(const Grid2 &g, int spm)
     return c;
 }
 
+template <int EBX>
 dim3 cell_grid(const Grid2 &g, int nshots)
 {
+    constexpr int EBZ = 256 / EBX;
     return dim3(((g.NX + EBX - 1) / EBX) * ((g.NZ + EBZ - 1) / EBZ), nshots);
 }
 
 __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_FWD>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     float d1 = Dp(a.f[E_SXX], f, 1), d2 = Dm(a.f[E_SXZ], f, SX);
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
 __global__ __launch_bounds__(256) void el2_str_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_FWD>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     float e1 = Dm(a.f[E_VX], f, 1), e2 = Dm(a.f[E_VZ], f, SX);
@@ -172,7 +179,7 @@ __global__ void el2_inject_kernel(El2RecArgs a)
 __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f;
     const float sxx = a.a[E_SXX][f], szz = a.a[E_SZZ][f], sxz = a.a[E_SXZ][f];
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
 __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     // transposes of the velocity differences: Dm^T = -Dp, Dp^T = -Dm
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
 __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     a.a[E_SXX][f] -= Dm(a.tmp[4], f, 1);
@@ -377,11 +384,11 @@ int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 6
 
 } // namespace
 
-void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { el2_adj1_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { el2_adj2_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid<EBX_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid<EBX_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { el2_adj1_kernel<<<cell_grid<EBX_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { el2_adj2_kernel<<<cell_grid<EBX_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid<EBX_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
 
 void launch_el2_record(const El2RecArgs &a, hipStream_t s)
 {
