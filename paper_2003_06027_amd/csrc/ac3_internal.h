@@ -7,11 +7,16 @@ namespace sg {
 
 // ---------------------------------------------------------------- 3-D
 // Tile of the 3-D kernels: TX3 x TY3 columns (one thread each), marching in
-// z over chunks of TZC planes with register windows along z.
+// z over chunks of planes with register windows along z. The forward passes
+// and the layer work items take shorter chunks than the adjoint, whose longer
+// march re-reads fewer window planes; the adjoint's is the longest.
 constexpr int TX3 = 32;
 constexpr int TY3 = 16;
 constexpr int NTH3 = TX3 * TY3;
-constexpr int TZC = 64;
+constexpr int TZC = 64;    // the adjoint tile passes
+constexpr int TZCF = 32;   // the forward tile passes
+constexpr int TZCI = 32;   // the layer work items
+static_assert(TZCF <= TZC && TZCI <= TZC, "TZC bounds every chunk's 32-bit plane offsets");
 constexpr int OX3 = 32;  // x offset (128-byte aligned rows)
 constexpr int OY3 = 4;
 constexpr int OZ3 = 4;
@@ -23,7 +28,7 @@ struct Grid3 {
     int P, nx, ny, nz;
     int SX, SY, SZ;
     long long sy, sz, plane;   // strides: sy = SX, sz = SX*SY, plane = sz*SZ
-    int ntx, nty, nzc;         // tiles in x, y; z chunks
+    int ntx, nty, nzc;         // tiles in x, y; adjoint z chunks
 };
 
 struct Ac3Tabs {               // per-axis damping tables, h = zeta dt / 2

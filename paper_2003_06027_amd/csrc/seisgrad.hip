@@ -195,7 +195,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_soff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
     L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
-    L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * (L.g3.nzc + 2) : 0);
+    L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * ((L.g3.NZ + TZCI - 1) / TZCI + 2) : 0);
     L.total = o;
     return L;
 }
@@ -1235,12 +1235,16 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
             const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
             const bool xy = x0 < g.P || x0 + TX3 > g.P + g.nx || y0 < g.P || y0 + TY3 > g.P + g.ny;
             auto add = [&](int za, int zb) {
-                for (int z = za; z < zb; z += TZC) m->h_items3.push_back(make_int4(t, z, std::min(z + TZC, zb), 0));
+                for (int z = za; z < zb; z += TZCI) m->h_items3.push_back(make_int4(t, z, std::min(z + TZCI, zb), 0));
             };
             if (xy) add(0, g.NZ);
             else { add(0, g.P); add(g.P + g.nz, g.NZ); }
         }
         m->n_items3 = (int)m->h_items3.size();
+        if ((size_t)m->n_items3 > (size_t)L.ntiles * ((g.NZ + TZCI - 1) / TZCI + 2)) {
+            delete m;
+            return fail(SG_EINVAL, "layer work list overflows its buffer");
+        }
     }
     hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m->n_items3 > 0)
