@@ -35,8 +35,11 @@ constexpr float C1 = (float)(9.0 / 8.0);
 constexpr float C2 = (float)(-1.0 / 24.0);
 // Cell blocks of 256 threads, EBX x (256 / EBX) cells: 256 x 1 for the
 // forward passes, 128 x 2 for the adjoint passes (measured best of 64 x 4,
-// 32 x 8, 128 x 2 and 256 x 1 for each).
+// 32 x 8, 128 x 2 and 256 x 1 for each). The forward passes take their
+// blocks in XCD order; the adjoint passes ran slower that way with every
+// block shape and keep the hardware order.
 constexpr int EBX_FWD = 256, EBX_ADJ = 128;
+constexpr bool XCD_FWD = true, XCD_ADJ = false;
 
 __device__ __forceinline__ float Dp(const float *f, long long i, long long s)
 {
@@ -59,16 +62,40 @@ struct Cell {
     long long f, so, mo;   // frame index, shot and model offsets
 };
 
-template <int EBX>
+// Work id of this workgroup with consecutive ids on one XCD: the hardware
+// hands workgroups to the 8 XCDs round-robin, so id b runs on XCD b % 8; the
+// remap gives each XCD a contiguous range of (block, shot) work, so the rows
+// that a block's z stencil shares with the blocks above and below it are
+// fetched into one L2.
+__device__ __forceinline__ int xcd_work_id(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks / NXCD, rem = nblocks % NXCD;
+    const int x = b % NXCD, j = b / NXCD;
+    return x * per + min(x, rem) + j;
+}
+
+// Cell of this thread in a grid of EBX x (256 / EBX) cell blocks. XCD =
+// true: a 1-D grid over (block, shot) taken in xcd_work_id order; false: a
+// 2-D grid, blockIdx.y the shot.
+template <int EBX, bool XCD>
 __device__ __forceinline__ Cell cell_of(const Grid2 &g, int spm)
 {
     constexpr int EBZ = 256 / EBX;
     Cell c;
-    const int ntxe = (g.NX + EBX - 1) / EBX;
-    const int bx = blockIdx.x % ntxe, bz = blockIdx.x / ntxe;
+    const int ntxe = (g.NX + EBX - 1) / EBX, nblk = ntxe * ((g.NZ + EBZ - 1) / EBZ);
+    int r;
+    if (XCD) {
+        const int w = xcd_work_id((int)gridDim.x);
+        c.shot = w / nblk;
+        r = w - c.shot * nblk;
+    } else {
+        c.shot = blockIdx.y;
+        r = blockIdx.x;
+    }
+    const int bz = r / ntxe, bx = r - bz * ntxe;
     c.ix = bx * EBX + (int)(threadIdx.x % EBX);
     c.iz = bz * EBZ + (int)(threadIdx.x / EBX);
-    c.shot = blockIdx.y;
     c.valid = c.ix < g.NX && c.iz < g.NZ;
     c.layer = g.P > 0 && (c.ix < g.P || c.ix >= g.P + g.nx - 1 || c.iz < g.P || c.iz >= g.P + g.nz - 1);
     c.f = (long long)(c.iz + OZ) * g.SX + c.ix + OX;
@@ -77,17 +104,18 @@ __device__ __forceinline__ Cell cell_of(const Grid2 &g, int spm)
     return c;
 }
 
-template <int EBX>
+template <int EBX, bool XCD>
 dim3 cell_grid(const Grid2 &g, int nshots)
 {
     constexpr int EBZ = 256 / EBX;
-    return dim3(((g.NX + EBX - 1) / EBX) * ((g.NZ + EBZ - 1) / EBZ), nshots);
+    const int nblk = ((g.NX + EBX - 1) / EBX) * ((g.NZ + EBZ - 1) / EBZ);
+    return XCD ? dim3(nblk * nshots) : dim3(nblk, nshots);
 }
 
 __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_FWD>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     float d1 = Dp(a.f[E_SXX], f, 1), d2 = Dm(a.f[E_SXZ], f, SX);
@@ -111,7 +139,7 @@ __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
 __global__ __launch_bounds__(256) void el2_str_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_FWD>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     float e1 = Dm(a.f[E_VX], f, 1), e2 = Dm(a.f[E_VZ], f, SX);
@@ -179,7 +207,7 @@ __global__ void el2_inject_kernel(El2RecArgs a)
 __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f;
     const float sxx = a.a[E_SXX][f], szz = a.a[E_SZZ][f], sxz = a.a[E_SXZ][f];
@@ -212,7 +240,7 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
 __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     // transposes of the velocity differences: Dm^T = -Dp, Dp^T = -Dm
@@ -241,7 +269,7 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
 __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     a.a[E_SXX][f] -= Dm(a.tmp[4], f, 1);
@@ -384,11 +412,11 @@ int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 6
 
 } // namespace
 
-void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid<EBX_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid<EBX_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { el2_adj1_kernel<<<cell_grid<EBX_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { el2_adj2_kernel<<<cell_grid<EBX_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid<EBX_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { el2_adj1_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { el2_adj2_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
 
 void launch_el2_record(const El2RecArgs &a, hipStream_t s)
 {

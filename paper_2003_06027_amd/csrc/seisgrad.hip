@@ -107,6 +107,18 @@ int check_desc(const sg_desc *d)
     return SG_OK;
 }
 
+// Shot-count limits of the launches: the elastic adjoint passes take the shot
+// as the grid's y index (at most 65535), the forward passes number their
+// 256 x 1 cell blocks over all shots with an int.
+int check_shots(const sg_desc *d, int max_shots)
+{
+    if (d->physics != SG_ELASTIC) return SG_OK;
+    const long long NX = d->nx + 2LL * d->npml, NZ = d->nz + 2LL * d->npml;
+    if (max_shots > 65535 || (NX + 255) / 256 * NZ * max_shots >= (1LL << 31))
+        return fail(SG_EINVAL, "too many elastic shots (%d) for a %lld x %lld grid", max_shots, NX, NZ);
+    return SG_OK;
+}
+
 Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
 {
     Layout L{};
@@ -1022,6 +1034,7 @@ size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int
         fail(SG_EINVAL, "at most %d receivers per shot", (1 << REC_ID_BITS) - 1);
         return 0;
     }
+    if (check_shots(d, max_shots) != SG_OK) return 0;
     return make_layout(d, max_shots, max_rec, ckpt_every).total;
 }
 
@@ -1054,6 +1067,7 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         return fail(SG_EINVAL, "max_shots >= 1, max_rec >= 0 and ckpt_every >= 0 required");
     if (max_shots % d->nmodels) return fail(SG_EINVAL, "max_shots must be a multiple of nmodels");
     if ((long long)max_rec >= (1LL << REC_ID_BITS)) return fail(SG_EINVAL, "at most %d receivers per shot", (1 << REC_ID_BITS) - 1);
+    if (const int e = check_shots(d, max_shots)) return e;
     if (d->ndim == 3 && d->nz + 2 * d->npml >= (1 << 12)) return fail(SG_EINVAL, "3-D grids are limited to 4095 padded planes in z");
     const Layout L = make_layout(d, max_shots, max_rec, ckpt_every);
     if (ws_bytes < L.total) return fail(SG_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
