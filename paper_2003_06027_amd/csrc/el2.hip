@@ -56,6 +56,39 @@ __device__ __forceinline__ void gacc(float *p, float v)
     __builtin_nontemporal_store(__builtin_nontemporal_load(p) + v, p);
 }
 
+// Is (ix, iz) a CPML cell? (The cells that update memory variables; frame
+// padding beyond the grid counts as layer when there is a layer.)
+__device__ __forceinline__ bool in_layer(const Grid2 &g, int ix, int iz)
+{
+    return g.P > 0 && (ix < g.P || ix >= g.P + g.nx - 1 || iz < g.P || iz >= g.P + g.nz - 1);
+}
+
+// Staggered differences of a field that the adjoint passes store in two
+// arrays: `lay` holds it on CPML cells, `inn` elsewhere, where it equals the
+// field `inn` holds. Point k of the stencil along axis AX (0: x, 1: z) reads
+// the array its cell belongs to.
+template <int AX>
+__device__ __forceinline__ float at_sel(const Grid2 &g, const float *lay, const float *inn, long long i, long long s,
+                                        int ix, int iz, int k)
+{
+    const bool l = AX == 0 ? in_layer(g, ix + k, iz) : in_layer(g, ix, iz + k);
+    return (l ? lay : inn)[i + k * s];
+}
+template <int AX>
+__device__ __forceinline__ float Dp_sel(const Grid2 &g, const float *lay, const float *inn, long long i, long long s,
+                                        int ix, int iz)
+{
+    return C1 * (at_sel<AX>(g, lay, inn, i, s, ix, iz, 1) - at_sel<AX>(g, lay, inn, i, s, ix, iz, 0)) +
+           C2 * (at_sel<AX>(g, lay, inn, i, s, ix, iz, 2) - at_sel<AX>(g, lay, inn, i, s, ix, iz, -1));
+}
+template <int AX>
+__device__ __forceinline__ float Dm_sel(const Grid2 &g, const float *lay, const float *inn, long long i, long long s,
+                                        int ix, int iz)
+{
+    return C1 * (at_sel<AX>(g, lay, inn, i, s, ix, iz, 0) - at_sel<AX>(g, lay, inn, i, s, ix, iz, -1)) +
+           C2 * (at_sel<AX>(g, lay, inn, i, s, ix, iz, 1) - at_sel<AX>(g, lay, inn, i, s, ix, iz, -2));
+}
+
 struct Cell {
     int ix, iz, shot;
     bool valid, layer;
@@ -97,7 +130,7 @@ __device__ __forceinline__ Cell cell_of(const Grid2 &g, int spm)
     c.ix = bx * EBX + (int)(threadIdx.x % EBX);
     c.iz = bz * EBZ + (int)(threadIdx.x / EBX);
     c.valid = c.ix < g.NX && c.iz < g.NZ;
-    c.layer = g.P > 0 && (c.ix < g.P || c.ix >= g.P + g.nx - 1 || c.iz < g.P || c.iz >= g.P + g.nz - 1);
+    c.layer = in_layer(g, c.ix, c.iz);
     c.f = (long long)(c.iz + OZ) * g.SX + c.ix + OX;
     c.so = (long long)c.shot * g.plane;
     c.mo = (long long)(c.shot / spm) * g.plane;
@@ -231,7 +264,7 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
     a.tmp[0][f] = e1;
     a.tmp[1][f] = e2;
     a.tmp[2][f] = e3;
-    a.tmp[3][f] = e4;
+    if (c.layer) a.tmp[3][f] = e4;   // e4 = e3 off the layer
     if (a.gwav && c.f == a.src_f[c.shot])
         a.gwav[(long long)c.shot * a.nt + a.k] =
             a.src_scale * (a.mt[3 * c.shot] * sxx + a.mt[3 * c.shot + 1] * szz + a.mt[3 * c.shot + 2] * sxz);
@@ -245,7 +278,7 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
     const long long f = c.so + c.f, SX = g.SX;
     // transposes of the velocity differences: Dm^T = -Dp, Dp^T = -Dm
     const float vx = a.a[E_VX][f] - (Dp(a.tmp[0], f, 1) + Dm(a.tmp[2], f, SX));
-    const float vz = a.a[E_VZ][f] - (Dp(a.tmp[1], f, SX) + Dm(a.tmp[3], f, 1));
+    const float vz = a.a[E_VZ][f] - (Dp(a.tmp[1], f, SX) + Dm_sel<0>(g, a.tmp[3], a.tmp[2], f, 1, c.ix, c.iz));
     a.a[E_VX][f] = vx;
     a.a[E_VZ][f] = vz;
     const float fxb = a.kap * a.m[M_BX][c.mo + c.f] * vx;
@@ -261,9 +294,11 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
         q = fzb + __builtin_nontemporal_load(a.a[E_MSZZZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MSZZZ] + f); d4 = fzb + a.t.az[1][c.iz] * q;
     }
     a.tmp[4][f] = d1;
-    a.tmp[5][f] = d2;
     a.tmp[6][f] = d3;
-    a.tmp[7][f] = d4;
+    if (c.layer) {   // d2 = d1 and d4 = d3 off the layer
+        a.tmp[5][f] = d2;
+        a.tmp[7][f] = d4;
+    }
 }
 
 __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
@@ -273,8 +308,8 @@ __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     a.a[E_SXX][f] -= Dm(a.tmp[4], f, 1);
-    a.a[E_SXZ][f] -= Dp(a.tmp[5], f, SX) + Dp(a.tmp[6], f, 1);
-    a.a[E_SZZ][f] -= Dm(a.tmp[7], f, SX);
+    a.a[E_SXZ][f] -= Dp_sel<1>(g, a.tmp[5], a.tmp[4], f, SX, c.ix, c.iz) + Dp(a.tmp[6], f, 1);
+    a.a[E_SZZ][f] -= Dm_sel<1>(g, a.tmp[7], a.tmp[6], f, SX, c.ix, c.iz);
 }
 
 // Model fields on the frame (FP64 arithmetic, rounded once) and padded
