@@ -237,68 +237,96 @@ __global__ void el2_inject_kernel(El2RecArgs a)
     a.az[f] += sz;
 }
 
+// Shots per thread in the adjoint passes that accumulate gradients: the
+// shots of a group belong to one model, so a thread reads the model fields
+// once and adds the group's summed contribution to one accumulator slot per
+// group (slots [group][plane]), where one slot per shot would cost a read and
+// a write of each accumulator per shot.
+__host__ __device__ constexpr int el2_group(int spm) { return spm % 4 == 0 ? 4 : spm % 2 == 0 ? 2 : 1; }
+
+template <int GSH>
 __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
-    const long long f = c.so + c.f;
-    const float sxx = a.a[E_SXX][f], szz = a.a[E_SZZ][f], sxz = a.a[E_SXZ][f];
-    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f];
-    const float txx = a.kap * ((lam + 2.f * mu) * sxx + lam * szz);
-    const float tzz = a.kap * (lam * sxx + (lam + 2.f * mu) * szz);
-    const float txz = a.kap * a.m[M_MUXZ][c.mo + c.f] * sxz;
-    const float exx = __builtin_nontemporal_load(a.snap + f), ezz = __builtin_nontemporal_load(a.snap + a.snap_stride + f),
-                exz = __builtin_nontemporal_load(a.snap + 2 * a.snap_stride + f);
-    gacc(a.grad + f, a.kap * (exx + ezz) * (sxx + szz));
-    gacc(a.grad + a.grad_stride + f, 2.f * a.kap * (exx * sxx + ezz * szz));
-    gacc(a.grad + 2 * a.grad_stride + f, a.kap * exz * sxz);
-    float e1 = txx, e2 = tzz, e3 = txz, e4 = txz;
-    if (c.layer) {
-        float q;
-        q = txx + __builtin_nontemporal_load(a.a[E_MVXX] + f); __builtin_nontemporal_store(a.t.bx[0][c.ix] * q, a.a[E_MVXX] + f); e1 = txx + a.t.ax[0][c.ix] * q;
-        q = tzz + __builtin_nontemporal_load(a.a[E_MVZZ] + f); __builtin_nontemporal_store(a.t.bz[0][c.iz] * q, a.a[E_MVZZ] + f); e2 = tzz + a.t.az[0][c.iz] * q;
-        q = txz + __builtin_nontemporal_load(a.a[E_MVXZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MVXZ] + f); e3 = txz + a.t.az[1][c.iz] * q;
-        q = txz + __builtin_nontemporal_load(a.a[E_MVZX] + f); __builtin_nontemporal_store(a.t.bx[1][c.ix] * q, a.a[E_MVZX] + f); e4 = txz + a.t.ax[1][c.ix] * q;
+    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < GSH; ++j) {
+        const int shot = c.shot * GSH + j;
+        const long long f = (long long)shot * g.plane + c.f;
+        const float sxx = a.a[E_SXX][f], szz = a.a[E_SZZ][f], sxz = a.a[E_SXZ][f];
+        const float txx = a.kap * ((lam + 2.f * mu) * sxx + lam * szz);
+        const float tzz = a.kap * (lam * sxx + (lam + 2.f * mu) * szz);
+        const float txz = a.kap * muxz * sxz;
+        const float exx = __builtin_nontemporal_load(a.snap + f),
+                    ezz = __builtin_nontemporal_load(a.snap + a.snap_stride + f),
+                    exz = __builtin_nontemporal_load(a.snap + 2 * a.snap_stride + f);
+        g0 += a.kap * (exx + ezz) * (sxx + szz);
+        g1 += 2.f * a.kap * (exx * sxx + ezz * szz);
+        g2 += a.kap * exz * sxz;
+        float e1 = txx, e2 = tzz, e3 = txz, e4 = txz;
+        if (c.layer) {
+            float q;
+            q = txx + __builtin_nontemporal_load(a.a[E_MVXX] + f); __builtin_nontemporal_store(a.t.bx[0][c.ix] * q, a.a[E_MVXX] + f); e1 = txx + a.t.ax[0][c.ix] * q;
+            q = tzz + __builtin_nontemporal_load(a.a[E_MVZZ] + f); __builtin_nontemporal_store(a.t.bz[0][c.iz] * q, a.a[E_MVZZ] + f); e2 = tzz + a.t.az[0][c.iz] * q;
+            q = txz + __builtin_nontemporal_load(a.a[E_MVXZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MVXZ] + f); e3 = txz + a.t.az[1][c.iz] * q;
+            q = txz + __builtin_nontemporal_load(a.a[E_MVZX] + f); __builtin_nontemporal_store(a.t.bx[1][c.ix] * q, a.a[E_MVZX] + f); e4 = txz + a.t.ax[1][c.ix] * q;
+        }
+        a.tmp[0][f] = e1;
+        a.tmp[1][f] = e2;
+        a.tmp[2][f] = e3;
+        if (c.layer) a.tmp[3][f] = e4;   // e4 = e3 off the layer
+        if (a.gwav && c.f == a.src_f[shot])
+            a.gwav[(long long)shot * a.nt + a.k] =
+                a.src_scale * (a.mt[3 * shot] * sxx + a.mt[3 * shot + 1] * szz + a.mt[3 * shot + 2] * sxz);
     }
-    a.tmp[0][f] = e1;
-    a.tmp[1][f] = e2;
-    a.tmp[2][f] = e3;
-    if (c.layer) a.tmp[3][f] = e4;   // e4 = e3 off the layer
-    if (a.gwav && c.f == a.src_f[c.shot])
-        a.gwav[(long long)c.shot * a.nt + a.k] =
-            a.src_scale * (a.mt[3 * c.shot] * sxx + a.mt[3 * c.shot + 1] * szz + a.mt[3 * c.shot + 2] * sxz);
+    const long long gf = c.so + c.f;
+    gacc(a.grad + gf, g0);
+    gacc(a.grad + a.grad_stride + gf, g1);
+    gacc(a.grad + 2 * a.grad_stride + gf, g2);
 }
 
+template <int GSH>
 __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
-    const long long f = c.so + c.f, SX = g.SX;
-    // transposes of the velocity differences: Dm^T = -Dp, Dp^T = -Dm
-    const float vx = a.a[E_VX][f] - (Dp(a.tmp[0], f, 1) + Dm(a.tmp[2], f, SX));
-    const float vz = a.a[E_VZ][f] - (Dp(a.tmp[1], f, SX) + Dm_sel<0>(g, a.tmp[3], a.tmp[2], f, 1, c.ix, c.iz));
-    a.a[E_VX][f] = vx;
-    a.a[E_VZ][f] = vz;
-    const float fxb = a.kap * a.m[M_BX][c.mo + c.f] * vx;
-    const float fzb = a.kap * a.m[M_BZ][c.mo + c.f] * vz;
-    gacc(a.grad + 3 * a.grad_stride + f, a.kap * __builtin_nontemporal_load(a.snap + 3 * a.snap_stride + f) * vx);
-    gacc(a.grad + 4 * a.grad_stride + f, a.kap * __builtin_nontemporal_load(a.snap + 4 * a.snap_stride + f) * vz);
-    float d1 = fxb, d2 = fxb, d3 = fzb, d4 = fzb;
-    if (c.layer) {
-        float q;
-        q = fxb + __builtin_nontemporal_load(a.a[E_MSXXX] + f); __builtin_nontemporal_store(a.t.bx[1][c.ix] * q, a.a[E_MSXXX] + f); d1 = fxb + a.t.ax[1][c.ix] * q;
-        q = fxb + __builtin_nontemporal_load(a.a[E_MSXZZ] + f); __builtin_nontemporal_store(a.t.bz[0][c.iz] * q, a.a[E_MSXZZ] + f); d2 = fxb + a.t.az[0][c.iz] * q;
-        q = fzb + __builtin_nontemporal_load(a.a[E_MSXZX] + f); __builtin_nontemporal_store(a.t.bx[0][c.ix] * q, a.a[E_MSXZX] + f); d3 = fzb + a.t.ax[0][c.ix] * q;
-        q = fzb + __builtin_nontemporal_load(a.a[E_MSZZZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MSZZZ] + f); d4 = fzb + a.t.az[1][c.iz] * q;
+    const long long SX = g.SX;
+    const float bxm = a.m[M_BX][c.mo + c.f], bzm = a.m[M_BZ][c.mo + c.f];
+    float g3 = 0.f, g4 = 0.f;
+#pragma unroll
+    for (int j = 0; j < GSH; ++j) {
+        const long long f = (long long)(c.shot * GSH + j) * g.plane + c.f;
+        // transposes of the velocity differences: Dm^T = -Dp, Dp^T = -Dm
+        const float vx = a.a[E_VX][f] - (Dp(a.tmp[0], f, 1) + Dm(a.tmp[2], f, SX));
+        const float vz = a.a[E_VZ][f] - (Dp(a.tmp[1], f, SX) + Dm_sel<0>(g, a.tmp[3], a.tmp[2], f, 1, c.ix, c.iz));
+        a.a[E_VX][f] = vx;
+        a.a[E_VZ][f] = vz;
+        const float fxb = a.kap * bxm * vx;
+        const float fzb = a.kap * bzm * vz;
+        g3 += a.kap * __builtin_nontemporal_load(a.snap + 3 * a.snap_stride + f) * vx;
+        g4 += a.kap * __builtin_nontemporal_load(a.snap + 4 * a.snap_stride + f) * vz;
+        float d1 = fxb, d2 = fxb, d3 = fzb, d4 = fzb;
+        if (c.layer) {
+            float q;
+            q = fxb + __builtin_nontemporal_load(a.a[E_MSXXX] + f); __builtin_nontemporal_store(a.t.bx[1][c.ix] * q, a.a[E_MSXXX] + f); d1 = fxb + a.t.ax[1][c.ix] * q;
+            q = fxb + __builtin_nontemporal_load(a.a[E_MSXZZ] + f); __builtin_nontemporal_store(a.t.bz[0][c.iz] * q, a.a[E_MSXZZ] + f); d2 = fxb + a.t.az[0][c.iz] * q;
+            q = fzb + __builtin_nontemporal_load(a.a[E_MSXZX] + f); __builtin_nontemporal_store(a.t.bx[0][c.ix] * q, a.a[E_MSXZX] + f); d3 = fzb + a.t.ax[0][c.ix] * q;
+            q = fzb + __builtin_nontemporal_load(a.a[E_MSZZZ] + f); __builtin_nontemporal_store(a.t.bz[1][c.iz] * q, a.a[E_MSZZZ] + f); d4 = fzb + a.t.az[1][c.iz] * q;
+        }
+        a.tmp[4][f] = d1;
+        a.tmp[6][f] = d3;
+        if (c.layer) {   // d2 = d1 and d4 = d3 off the layer
+            a.tmp[5][f] = d2;
+            a.tmp[7][f] = d4;
+        }
     }
-    a.tmp[4][f] = d1;
-    a.tmp[6][f] = d3;
-    if (c.layer) {   // d2 = d1 and d4 = d3 off the layer
-        a.tmp[5][f] = d2;
-        a.tmp[7][f] = d4;
-    }
+    const long long gf = c.so + c.f;
+    gacc(a.grad + 3 * a.grad_stride + gf, g3);
+    gacc(a.grad + 4 * a.grad_stride + gf, g4);
 }
 
 __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
@@ -349,7 +377,8 @@ __global__ void el2_prep_kernel(Grid2 g, int nmodels, const float *vp, const flo
     }
 }
 
-__global__ void el2_sum_shots_kernel(Grid2 g, int nmodels, int spm, const float *grad, long long gs, float *acc)
+// Sum of the accumulator slots (shot groups) of each model, in slot order.
+__global__ void el2_sum_shots_kernel(Grid2 g, int nmodels, int slots, const float *grad, long long gs, float *acc)
 {
     const long long n = (long long)nmodels * g.plane;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -357,7 +386,7 @@ __global__ void el2_sum_shots_kernel(Grid2 g, int nmodels, int spm, const float 
         const long long m = i / g.plane, f = i - m * g.plane;
         for (int q = 0; q < 5; ++q) {
             float v = 0.f;
-            for (int s = 0; s < spm; ++s) v += grad[q * gs + (m * spm + s) * g.plane + f];
+            for (int s = 0; s < slots; ++s) v += grad[q * gs + (m * slots + s) * g.plane + f];
             acc[q * n + i] = v;
         }
     }
@@ -449,8 +478,22 @@ int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 6
 
 void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
 void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { el2_adj1_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { el2_adj2_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s)
+{
+    const int gs = el2_group(a.shots_per_model);
+    const dim3 grid = cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots / gs);
+    if (gs == 4) el2_adj1_kernel<4><<<grid, 256, 0, s>>>(a);
+    else if (gs == 2) el2_adj1_kernel<2><<<grid, 256, 0, s>>>(a);
+    else el2_adj1_kernel<1><<<grid, 256, 0, s>>>(a);
+}
+void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s)
+{
+    const int gs = el2_group(a.shots_per_model);
+    const dim3 grid = cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots / gs);
+    if (gs == 4) el2_adj2_kernel<4><<<grid, 256, 0, s>>>(a);
+    else if (gs == 2) el2_adj2_kernel<2><<<grid, 256, 0, s>>>(a);
+    else el2_adj2_kernel<1><<<grid, 256, 0, s>>>(a);
+}
 void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
 
 void launch_el2_record(const El2RecArgs &a, hipStream_t s)
@@ -479,7 +522,8 @@ void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, const float *grad
 {
     const long long n = (long long)nmodels * g.plane;
     float *pad = acc + 5 * n;
-    el2_sum_shots_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, spm, grad, grad_stride, acc);
+    // one accumulator slot per shot group
+    el2_sum_shots_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, spm / el2_group(spm), grad, grad_stride, acc);
     el2_chain_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, acc, model[2], model[1], model[3], model[4],
                                                     phys_pad[0], phys_pad[1], phys_pad[2], pad);
     el2_fold_kernel<<<blocks_for((long long)nmodels * g.nz * g.nx), 256, 0, s>>>(g, nmodels, pad, g_vp, g_vs,

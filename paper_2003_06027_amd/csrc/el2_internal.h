@@ -44,7 +44,7 @@ struct El2AdjArgs {
     float kap;
     const float *snap;
     long long snap_stride;
-    float *grad;               // 5 accumulators [5][shot][plane]
+    float *grad;               // 5 accumulators [5][shot group][plane]
     long long grad_stride;
     const long long *src_f;
     const float *mt;

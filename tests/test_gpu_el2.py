@@ -72,6 +72,46 @@ def test_elastic_forward_and_gradient_parity():
     assert max(e_g) <= GRAD_TOL
 
 
+def test_elastic_gradient_shot_groups_parity():
+    """The adjoint passes accumulate gradients over groups of the shots of a
+    model (4 when the shots per model divide by 4, else 2, else 1): one model
+    with 4 shots (groups of 4) and 2 models with 2 shots each (groups of 2),
+    each on the oracle's residual, against the oracle's gradients."""
+    c, vp, vs, rho, _, _, rec3 = _case(nx=100, nz=56, P=12, nt=380)
+    src = np.array([[30, 5], [80, 40], [55, 25], [15, 45]], dtype=np.int32)
+    mt = np.array([[1.0, 1.0, 0.0], [-0.5, 0.5, 0.86], [0.3, -0.3, 0.95], [0.7, 0.2, -0.4]])
+    rec = np.stack([rec3[0]] * 4)
+    f0s = [15.0, 12.0, 18.0, 14.0]
+    wav = torch.stack([S.ricker(f, 1.0 / f, c["dt"], c["nt"]) for f in f0s])
+    wo = np.stack([O.ricker(f, 1.0 / f, c["dt"], c["nt"]) for f in f0s])
+    sh = S.Shots(src, rec, wav, mt)
+    go = _grid(c)
+    A = [vp, vs, rho]
+    B = [a[::-1].copy() for a in A]
+    A0 = [synth.smooth(a, 5.0) for a in A]
+    B0 = [synth.smooth(a, 5.0) for a in B]
+    for label, models, models0, spm in (("1 model x 4 shots", [A], [A0], 4),
+                                        ("2 models x 2 shots", [A, B], [A0, B0], 2)):
+        ro, og = [], []
+        for mi, (t, t0) in enumerate(zip(models, models0)):
+            sl = slice(mi * spm, (mi + 1) * spm)
+            oo = O.el2_forward(go, *t, src[sl], mt[sl], wo[sl], rec[sl])
+            op = O.el2_forward(go, *t0, src[sl], mt[sl], wo[sl], rec[sl])
+            r = O.misfit(op, oo)[1]
+            ro.append(r)
+            og.append(O.el2_gradient(go, *t0, src[sl], mt[sl], wo[sl], rec[sl], r, ckpt=30)[0])
+        d = S.desc(ndim=2, physics=S.SG_ELASTIC, nx=c["nx"], nz=c["nz"], npml=c["P"], nt=c["nt"], dx=c["dx"],
+                   dt=c["dt"], pml_vmax=4000.0, f0_pml=15.0, nmodels=len(models))
+        m0 = S.Model(d, dev(np.stack([t[0] for t in models0])), 4, rec.shape[1], 29,
+                     vs=dev(np.stack([t[1] for t in models0])), rho=dev(np.stack([t[2] for t in models0])))
+        m0.forward(sh)
+        ga = [x.cpu().numpy() for x in m0.gradient(sh, dev(np.concatenate(ro)))]
+        for mi in range(len(models)):
+            e = [rel_l2(ga[q][mi], og[mi][q]) for q in range(3)]
+            print(f"{label}, model {mi}: grad vp/vs/rho {e[0]:.2e} {e[1]:.2e} {e[2]:.2e}")
+            assert max(e) <= GRAD_TOL
+
+
 def test_elastic_no_layer_parity():
     """npml = 0: no CPML memories touched, rigid walls at the grid edge,
     sources next to two walls."""
