@@ -104,7 +104,11 @@ def bytes_per_cell_step_el2(pml_fraction):
     cells read and write the eight CPML memory variables (+64 B).  recompute:
     + five snapshot fields (+20 B).  adjoint: read the five adjoint fields,
     the model fields and the snapshots, read+write five gradient
-    accumulators, write five adjoint fields = 120 B (+64 B on layer cells)."""
+    accumulators, write five adjoint fields = 120 B (+64 B on layer cells).
+    The count is per shot. The adjoint kernels read the model fields and
+    update the accumulators once per group of up to 4 shots of a model, so
+    they move less than this. The adjoint figure is the rate of the per-shot
+    work, not a byte rate."""
     return {"forward": 60.0 + 64.0 * pml_fraction, "recompute": 80.0 + 64.0 * pml_fraction,
             "adjoint": 120.0 + 64.0 * pml_fraction}
 
