@@ -105,10 +105,10 @@ def bytes_per_cell_step_el2(pml_fraction):
     + five snapshot fields (+20 B).  adjoint: read the five adjoint fields,
     the model fields and the snapshots, read+write five gradient
     accumulators, write five adjoint fields = 120 B (+64 B on layer cells).
-    The count is per shot. The adjoint kernels read the model fields and
-    update the accumulators once per group of up to 4 shots of a model, so
-    they move less than this. The adjoint figure is the rate of the per-shot
-    work, not a byte rate."""
+    The counts are per shot. The kernels read the model fields, and the
+    adjoint kernels update the accumulators, once per group of up to 4 shots
+    of a model, so they move less than this. The figures are rates of
+    per-shot work, not byte rates."""
     return {"forward": 60.0 + 64.0 * pml_fraction, "recompute": 80.0 + 64.0 * pml_fraction,
             "adjoint": 120.0 + 64.0 * pml_fraction}
 

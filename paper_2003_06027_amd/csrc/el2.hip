@@ -145,63 +145,82 @@ dim3 cell_grid(const Grid2 &g, int nshots)
     return XCD ? dim3(nblk * nshots) : dim3(nblk, nshots);
 }
 
+// Shots per thread in the step passes: the shots of a group belong to one
+// model, so a thread reads the model fields once per group. The adjoint
+// passes that accumulate gradients also add the group's summed contribution
+// to one accumulator slot per group (slots [group][plane]), where one slot
+// per shot would cost a read and a write of each accumulator per shot.
+__host__ __device__ constexpr int el2_group(int spm) { return spm % 4 == 0 ? 4 : spm % 2 == 0 ? 2 : 1; }
+
+template <int GSH>
 __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
-    const long long f = c.so + c.f, SX = g.SX;
-    float d1 = Dp(a.f[E_SXX], f, 1), d2 = Dm(a.f[E_SXZ], f, SX);
-    float d3 = Dm(a.f[E_SXZ], f, 1), d4 = Dp(a.f[E_SZZ], f, SX);
-    if (c.layer) {
-        float m;
-        m = a.t.bx[1][c.ix] * a.f[E_MSXXX][f] + a.t.ax[1][c.ix] * d1; a.f[E_MSXXX][f] = m; d1 += m;
-        m = a.t.bz[0][c.iz] * a.f[E_MSXZZ][f] + a.t.az[0][c.iz] * d2; a.f[E_MSXZZ][f] = m; d2 += m;
-        m = a.t.bx[0][c.ix] * a.f[E_MSXZX][f] + a.t.ax[0][c.ix] * d3; a.f[E_MSXZX][f] = m; d3 += m;
-        m = a.t.bz[1][c.iz] * a.f[E_MSZZZ][f] + a.t.az[1][c.iz] * d4; a.f[E_MSZZZ][f] = m; d4 += m;
-    }
-    const float fx = d1 + d2, fz = d3 + d4;
-    a.f[E_VX][f] += a.kap * a.m[M_BX][c.mo + c.f] * fx;
-    a.f[E_VZ][f] += a.kap * a.m[M_BZ][c.mo + c.f] * fz;
-    if (a.snap) {
-        __builtin_nontemporal_store(fx, a.snap + 3 * a.snap_stride + f);
-        __builtin_nontemporal_store(fz, a.snap + 4 * a.snap_stride + f);
+    const long long SX = g.SX;
+    const float kbx = a.kap * a.m[M_BX][c.mo + c.f], kbz = a.kap * a.m[M_BZ][c.mo + c.f];
+#pragma unroll
+    for (int j = 0; j < GSH; ++j) {
+        const long long f = (long long)(c.shot * GSH + j) * g.plane + c.f;
+        float d1 = Dp(a.f[E_SXX], f, 1), d2 = Dm(a.f[E_SXZ], f, SX);
+        float d3 = Dm(a.f[E_SXZ], f, 1), d4 = Dp(a.f[E_SZZ], f, SX);
+        if (c.layer) {
+            float m;
+            m = a.t.bx[1][c.ix] * a.f[E_MSXXX][f] + a.t.ax[1][c.ix] * d1; a.f[E_MSXXX][f] = m; d1 += m;
+            m = a.t.bz[0][c.iz] * a.f[E_MSXZZ][f] + a.t.az[0][c.iz] * d2; a.f[E_MSXZZ][f] = m; d2 += m;
+            m = a.t.bx[0][c.ix] * a.f[E_MSXZX][f] + a.t.ax[0][c.ix] * d3; a.f[E_MSXZX][f] = m; d3 += m;
+            m = a.t.bz[1][c.iz] * a.f[E_MSZZZ][f] + a.t.az[1][c.iz] * d4; a.f[E_MSZZZ][f] = m; d4 += m;
+        }
+        const float fx = d1 + d2, fz = d3 + d4;
+        a.f[E_VX][f] += kbx * fx;
+        a.f[E_VZ][f] += kbz * fz;
+        if (a.snap) {
+            __builtin_nontemporal_store(fx, a.snap + 3 * a.snap_stride + f);
+            __builtin_nontemporal_store(fz, a.snap + 4 * a.snap_stride + f);
+        }
     }
 }
 
+template <int GSH>
 __global__ __launch_bounds__(256) void el2_str_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
-    const long long f = c.so + c.f, SX = g.SX;
-    float e1 = Dm(a.f[E_VX], f, 1), e2 = Dm(a.f[E_VZ], f, SX);
-    float e3 = Dp(a.f[E_VX], f, SX), e4 = Dp(a.f[E_VZ], f, 1);
-    if (c.layer) {
-        float m;
-        m = a.t.bx[0][c.ix] * a.f[E_MVXX][f] + a.t.ax[0][c.ix] * e1; a.f[E_MVXX][f] = m; e1 += m;
-        m = a.t.bz[0][c.iz] * a.f[E_MVZZ][f] + a.t.az[0][c.iz] * e2; a.f[E_MVZZ][f] = m; e2 += m;
-        m = a.t.bz[1][c.iz] * a.f[E_MVXZ][f] + a.t.az[1][c.iz] * e3; a.f[E_MVXZ][f] = m; e3 += m;
-        m = a.t.bx[1][c.ix] * a.f[E_MVZX][f] + a.t.ax[1][c.ix] * e4; a.f[E_MVZX][f] = m; e4 += m;
-    }
-    const float exz = e3 + e4;
-    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f];
-    float sxx = a.f[E_SXX][f] + a.kap * ((lam + 2.f * mu) * e1 + lam * e2);
-    float szz = a.f[E_SZZ][f] + a.kap * (lam * e1 + (lam + 2.f * mu) * e2);
-    float sxz = a.f[E_SXZ][f] + a.kap * a.m[M_MUXZ][c.mo + c.f] * exz;
-    if (c.f == a.src_f[c.shot]) {
-        const float s = a.src_scale * a.wav[(long long)c.shot * a.nt + a.k];
-        sxx += s * a.mt[3 * c.shot];
-        szz += s * a.mt[3 * c.shot + 1];
-        sxz += s * a.mt[3 * c.shot + 2];
-    }
-    a.f[E_SXX][f] = sxx;
-    a.f[E_SZZ][f] = szz;
-    a.f[E_SXZ][f] = sxz;
-    if (a.snap) {
-        __builtin_nontemporal_store(e1, a.snap + f);
-        __builtin_nontemporal_store(e2, a.snap + a.snap_stride + f);
-        __builtin_nontemporal_store(exz, a.snap + 2 * a.snap_stride + f);
+    const long long SX = g.SX;
+    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
+#pragma unroll
+    for (int j = 0; j < GSH; ++j) {
+        const int shot = c.shot * GSH + j;
+        const long long f = (long long)shot * g.plane + c.f;
+        float e1 = Dm(a.f[E_VX], f, 1), e2 = Dm(a.f[E_VZ], f, SX);
+        float e3 = Dp(a.f[E_VX], f, SX), e4 = Dp(a.f[E_VZ], f, 1);
+        if (c.layer) {
+            float m;
+            m = a.t.bx[0][c.ix] * a.f[E_MVXX][f] + a.t.ax[0][c.ix] * e1; a.f[E_MVXX][f] = m; e1 += m;
+            m = a.t.bz[0][c.iz] * a.f[E_MVZZ][f] + a.t.az[0][c.iz] * e2; a.f[E_MVZZ][f] = m; e2 += m;
+            m = a.t.bz[1][c.iz] * a.f[E_MVXZ][f] + a.t.az[1][c.iz] * e3; a.f[E_MVXZ][f] = m; e3 += m;
+            m = a.t.bx[1][c.ix] * a.f[E_MVZX][f] + a.t.ax[1][c.ix] * e4; a.f[E_MVZX][f] = m; e4 += m;
+        }
+        const float exz = e3 + e4;
+        float sxx = a.f[E_SXX][f] + a.kap * ((lam + 2.f * mu) * e1 + lam * e2);
+        float szz = a.f[E_SZZ][f] + a.kap * (lam * e1 + (lam + 2.f * mu) * e2);
+        float sxz = a.f[E_SXZ][f] + a.kap * muxz * exz;
+        if (c.f == a.src_f[shot]) {
+            const float s = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
+            sxx += s * a.mt[3 * shot];
+            szz += s * a.mt[3 * shot + 1];
+            sxz += s * a.mt[3 * shot + 2];
+        }
+        a.f[E_SXX][f] = sxx;
+        a.f[E_SZZ][f] = szz;
+        a.f[E_SXZ][f] = sxz;
+        if (a.snap) {
+            __builtin_nontemporal_store(e1, a.snap + f);
+            __builtin_nontemporal_store(e2, a.snap + a.snap_stride + f);
+            __builtin_nontemporal_store(exz, a.snap + 2 * a.snap_stride + f);
+        }
     }
 }
 
@@ -237,12 +256,6 @@ __global__ void el2_inject_kernel(El2RecArgs a)
     a.az[f] += sz;
 }
 
-// Shots per thread in the adjoint passes that accumulate gradients: the
-// shots of a group belong to one model, so a thread reads the model fields
-// once and adds the group's summed contribution to one accumulator slot per
-// group (slots [group][plane]), where one slot per shot would cost a read and
-// a write of each accumulator per shot.
-__host__ __device__ constexpr int el2_group(int spm) { return spm % 4 == 0 ? 4 : spm % 2 == 0 ? 2 : 1; }
 
 template <int GSH>
 __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
@@ -476,8 +489,22 @@ int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 6
 
 } // namespace
 
-void launch_el2_vel(const El2Args &a, hipStream_t s) { el2_vel_kernel<<<cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
-void launch_el2_str(const El2Args &a, hipStream_t s) { el2_str_kernel<<<cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots), 256, 0, s>>>(a); }
+void launch_el2_vel(const El2Args &a, hipStream_t s)
+{
+    const int gs = el2_group(a.shots_per_model);
+    const dim3 grid = cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots / gs);
+    if (gs == 4) el2_vel_kernel<4><<<grid, 256, 0, s>>>(a);
+    else if (gs == 2) el2_vel_kernel<2><<<grid, 256, 0, s>>>(a);
+    else el2_vel_kernel<1><<<grid, 256, 0, s>>>(a);
+}
+void launch_el2_str(const El2Args &a, hipStream_t s)
+{
+    const int gs = el2_group(a.shots_per_model);
+    const dim3 grid = cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots / gs);
+    if (gs == 4) el2_str_kernel<4><<<grid, 256, 0, s>>>(a);
+    else if (gs == 2) el2_str_kernel<2><<<grid, 256, 0, s>>>(a);
+    else el2_str_kernel<1><<<grid, 256, 0, s>>>(a);
+}
 void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s)
 {
     const int gs = el2_group(a.shots_per_model);
