@@ -33,12 +33,11 @@ namespace {
 
 constexpr float C1 = (float)(9.0 / 8.0);
 constexpr float C2 = (float)(-1.0 / 24.0);
-// Cell blocks of 256 threads, EBX x (256 / EBX) cells. The forward passes
-// take 32 x 8 blocks in XCD order; the adjoint passes 128 x 2 blocks in the
-// hardware order (they ran slower in XCD order with every block shape).
-// Each is the measured best of 16 x 16 (forward), 32 x 8, 64 x 4, 128 x 2
-// and 256 x 1.
-constexpr int EBX_FWD = 32, EBX_ADJ = 128;
+// Cell blocks of 256 threads, EBX x (256 / EBX) cells: 32 x 8 in both
+// passes, the forward's in XCD order, the adjoint's in the hardware order
+// (they ran slower in XCD order with every block shape). Each is the
+// measured best of 16 x 16 (forward), 32 x 8, 64 x 4, 128 x 2 and 256 x 1.
+constexpr int EBX_FWD = 32, EBX_ADJ = 32;
 constexpr bool XCD_FWD = true, XCD_ADJ = false;
 
 __device__ __forceinline__ float Dp(const float *f, long long i, long long s)
