@@ -5,10 +5,10 @@
  * Seismic Inversion with Automatic Differentiation"):
  *   - the explicit recursion U_k = A(theta) U_{k-1} + F_{k-1}
  *     (Method, "Relationship to the Adjoint Method", Eq. (1)) for the
- *     acoustic wave equation (Implementation, Eq. (11), constant-density form
+ *     acoustic wave equation (Implementation, Eq. (12), constant-density form
  *     u_tt = c^2 lap(u) + f, 2nd order in time, 8th order in space) with an
  *     auxiliary-field absorbing layer (PML) padded outside the model; and the
- *     same equation in the divergence form printed in Eq. (11),
+ *     same equation in the divergence form printed in Eq. (12),
  *     u_tt = div(c^2 grad u) + f (physics SG_ACOUSTIC_DIV, 2-D): the
  *     staggered grid with a convolutional PML of the Implementation section,
  *     4th order in space, flux coefficients c^2 averaged onto the half nodes
@@ -145,7 +145,7 @@ SG_API size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_r
 SG_API size_t snapshot_segment_bytes(const sg_desc *d, int32_t max_shots, int32_t ckpt_every);
 
 /* Prepare a model (paper: the parameter theta of A(theta), Eq. (1); here the
- * velocity c of Eq. (11)): validate the descriptor, check stability
+ * velocity c of Eq. (12)): validate the descriptor, check stability
  * (8th-order leapfrog limit c dt/dx <= 2/sqrt(6.5016 ndim); staggered 4th
  * order, elastic and SG_ACOUSTIC_DIV: c dt/dx <= 1/(sqrt(ndim) (9/8 + 1/24));
  * rejected above 0.95 of the limit), pad the velocity by edge replication,

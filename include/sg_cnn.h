@@ -1,7 +1,9 @@
 /* sg_cnn.h -- C ABI of the learned gradient preconditioner in libseisgrad.
  *
- * The paper has no network: its Conclusions name deep-learning priors in the
- * inversion loop as future work.  What this part preconditions is the
+ * The paper has no network.  Its Limitations section calls ill-conditioning
+ * intrinsic to the inversion and notes that conditioning techniques can be
+ * applied within the framework; this part is one such technique, of the
+ * project's own design.  What it preconditions is the
  * gradient of the paper's method (Method section: the misfit after Eq. (1),
  * its gradient by the adjoint Eqs. (4)-(5)), used by plain gradient-descent
  * inversion.  The network is fixed:

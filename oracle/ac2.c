@@ -10,7 +10,7 @@
  *   - adjoint recursion lambda_k = A^T lambda_{k+1} + residual, Eq. (4);
  *   - gradient sum_k lambda_k^T (dA/dtheta) U_{k-1}, Eq. (5) (equal to the
  *     reverse-mode result of Eq. (9) by the Theorem);
- *   - the PDE, Implementation, Eq. (11), read in its constant-density form
+ *   - the PDE, Implementation, Eq. (12), read in its constant-density form
  *     c^2 lap(u); the PML is the complex-coordinate-stretched auxiliary-field
  *     family the paper cites (Grote & Sim 2010):
  *         u_tt + (zx+zz) u_t + zx zz u = c^2 (lap u + d_x phix + d_z phiz) + f

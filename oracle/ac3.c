@@ -2,7 +2,7 @@
  * u_tt = c^2 lap(u) + f with an auxiliary-field PML, and its exact adjoint.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Same paper anchors as the 2-D oracle (Eqs. (1), (4), (5), (11)).  The
+ * Same paper anchors as the 2-D oracle (Eqs. (1), (4), (5), (12)).  The
  * absorbing layer follows from complex coordinate stretching
  * d_j -> s/(s+zeta_j) d_j of s^2 u = c^2 lap u, multiplied through by
  * (s+zx)(s+zy)(s+zz)/s^3:

@@ -3,7 +3,7 @@
  * adjoint.  TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
  * Paper anchors: the acoustic equation of the Implementation section,
- * Eq. (11), as printed (divergence form); the staggered-grid finite
+ * Eq. (12), as printed (divergence form); the staggered-grid finite
  * differences with a convolutional PML named in the same paragraph (Roden &
  * Gedney; Komatitsch & Martin); the explicit recursion Eq. (1), the misfit
  * after it, the adjoint recursion Eq. (4) and the gradient Eq. (5).

@@ -2,9 +2,11 @@
 (TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU
 baseline of the benchmark use this module; the product path never does).
 
-The paper has no network (its Conclusions name deep-learning priors for the
-inversion as future work).  The preconditioner here is the concrete one the
-project fixes, written as plainly as possible with torch FP64 CPU ops:
+The paper has no network.  Its Limitations section calls ill-conditioning
+intrinsic to the inversion and notes that techniques which improve the
+conditioning can be applied within the framework; this preconditioner is one
+such technique, of the project's own design, written as plainly as possible
+with torch FP64 CPU ops:
 
 * six 3x3 convolutions with zero padding: c1 (1->32), c2..c5 (32->32) in two
   residual blocks, c6 (32->1);

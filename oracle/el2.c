@@ -2,7 +2,7 @@
  * staggered grid with CPML, and their exact adjoint.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Paper anchors: the elastic equations, Implementation, Eq. (12)
+ * Paper anchors: the elastic equations, Implementation, Eq. (13)
  * (rho v_i,t = sigma_ij,j + rho f_i;  sigma_ij,t = lambda delta_ij v_k,k +
  * mu (v_i,j + v_j,i), the Kronecker delta being implied), the explicit
  * recursion Eq. (1), the misfit after Eq. (1), the adjoint recursion and

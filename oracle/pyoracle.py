@@ -314,6 +314,20 @@ def greens3d_ricker(r, c, t, f0, t0):
 
 
 # ---------------------------------------------------------------- elastic 2-D
+def cpml_profile(g, n, half):
+    """CPML (a, b) of the oracle at every padded position i + half/2 of an axis
+    with n physical cells (half = 0: integer nodes, 1: half nodes)."""
+    P = g.npml
+    a, b = np.zeros(n + 2 * P), np.zeros(n + 2 * P)
+    fa, fb = C.c_double(0.0), C.c_double(0.0)
+    f = lib().or_cpml_at
+    f.argtypes = [C.POINTER(OrGrid), C.c_int, C.c_double, _dp, _dp]
+    for i in range(n + 2 * P):
+        f(C.byref(g), n, i + 0.5 * half, C.byref(fa), C.byref(fb))
+        a[i], b[i] = fa.value, fb.value
+    return a, b
+
+
 EL2_FIELDS = ("vx", "vz", "sxx", "szz", "sxz", "m_vx_x", "m_vx_z", "m_vz_x", "m_vz_z",
               "m_sxx_x", "m_sxz_z", "m_sxz_x", "m_szz_z")
 

@@ -1,6 +1,6 @@
 // ac2.hip -- gfx950 kernels of the 2-D acoustic recursion and its adjoint.
 //
-// Forward step k (paper: U_{k+1} = A(theta) U_k + F_k, Eq. (1); PDE Eq. (11)
+// Forward step k (paper: U_{k+1} = A(theta) U_k + F_k, Eq. (1); PDE Eq. (12)
 // in the constant-density form u_tt = c^2 lap(u) + f with an auxiliary-field
 // absorbing layer).  In scaled variables (chat = dt^2 c^2/dx^2, phi~ = dx*phi,
 // h = zeta dt/2, L~ and D~ the 8th-order stencils without the 1/dx factors):

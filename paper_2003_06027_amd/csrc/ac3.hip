@@ -1,6 +1,6 @@
 // ac3.hip -- gfx950 kernels of the 3-D acoustic recursion and its adjoint.
 //
-// Paper: U_{k+1} = A(theta) U_k + F_k (Eq. (1)), PDE Eq. (11) in the
+// Paper: U_{k+1} = A(theta) U_k + F_k (Eq. (1)), PDE Eq. (12) in the
 // constant-density form u_tt = c^2 lap(u) + f, adjoint Eqs. (4)-(5).  The
 // absorbing layer is the auxiliary-field form obtained by complex coordinate
 // stretching, with psi = integral of u in time:

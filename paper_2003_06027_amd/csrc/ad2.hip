@@ -1,5 +1,5 @@
 // ad2.hip -- gfx950 kernels of the 2-D acoustic equation in divergence form,
-// u_tt = div(c^2 grad u) + f (Eq. (11) as printed), on a staggered grid with
+// u_tt = div(c^2 grad u) + f (Eq. (12) as printed), on a staggered grid with
 // a convolutional PML, and its adjoint (Eqs. (4)-(5)).
 //
 // Scaled variables: chat = dt^2 c^2 / dx^2 at the nodes, khat = (chat_i +

@@ -1,5 +1,5 @@
 // el2.hip -- gfx950 kernels of the 2-D elastic velocity-stress scheme
-// (paper: Implementation, Eq. (12), with the explicit recursion Eq. (1)) and
+// (paper: Implementation, Eq. (13), with the explicit recursion Eq. (1)) and
 // its exact adjoint (Eqs. (4)-(5)), gradients with respect to vp, vs, rho.
 //
 // Staggered grid, all fields [iz][ix] on the padded grid, the index naming

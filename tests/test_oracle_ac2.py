@@ -351,3 +351,19 @@ def test_invalid_geometry_rejected(oracle):
     bad[0, 0] = g.nx
     with pytest.raises(ValueError):
         oracle.ac2_forward(g, c, bad, wav, rec)
+
+
+def test_damping_profile_follows_definition(oracle):
+    """zeta(d) = zeta_max (d/P)^2 with zeta_max = 3 vmax ln(1/R) / (2 P dx): d
+    is 1 on the first layer cell and P on the outermost, 0 on physical cells;
+    the profile uses the reference velocity, not the model."""
+    g = oracle.grid(ndim=2, nx=13, nz=8, npml=5, nt=1, dx=7.5, dt=1e-3, pml_vmax=2600.0, pml_R=1e-3)
+    c = np.full((8, 13), 1500.0)
+    c[3, 4] = 4000.0
+    _, zx, zz = oracle.ac2_pad(g, c)
+    zmax = 3.0 * 2600.0 * np.log(1e3) / (2.0 * 5 * 7.5)
+    for z, n in ((zx, 13), (zz, 8)):
+        i = np.arange(n + 10)
+        depth = np.where(i < 5, 5 - i, np.where(i >= 5 + n, i - (4 + n), 0))
+        assert np.allclose(z, zmax * (depth / 5.0) ** 2, rtol=1e-15, atol=0)
+    assert zx[4] == pytest.approx(zmax / 25.0, rel=1e-15) and zx[5] == 0.0

@@ -1,5 +1,5 @@
 """Pins of the FP64 oracle of the divergence-form acoustic equation
-u_tt = div(c^2 grad u) + f (Eq. (11) as printed; staggered 4th-order grid
+u_tt = div(c^2 grad u) + f (Eq. (12) as printed; staggered 4th-order grid
 with CPML) against facts fixed outside the oracle:
 
 * the discrete symbol of Dm Dp on a plane wave (closed form);

@@ -245,3 +245,153 @@ def test_cpml_absorbs(oracle):
     refl = small[:, :tmax] - big[:, :tmax]
     ratio = np.sqrt(np.mean(refl ** 2)) / np.sqrt(np.mean(big[:, :tmax] ** 2))
     assert ratio < 2e-2, ratio
+
+
+def _radial_second_derivatives(oracle, X, Z, c, t, f0, t0, h=1.0):
+    """d2U/dx2, d2U/dz2, d2U/dxdz at offset (X, Z) of the radial solution
+    U(r, t) of U_tt = c^2 lap U + delta(x) r(t) (closed-form quadrature),
+    from 4th-order differences in r."""
+    r = np.hypot(X, Z)
+    U = [oracle.greens2d_ricker(r + k * h, c, t, f0, t0, nq=200) for k in (-2, -1, 0, 1, 2)]
+    Ur = (U[0] - 8 * U[1] + 8 * U[3] - U[4]) / (12 * h)
+    Urr = (-U[0] + 16 * U[1] - 30 * U[2] + 16 * U[3] - U[4]) / (12 * h * h)
+    return (Urr * X * X / r ** 2 + Ur * Z * Z / r ** 3, Urr * Z * Z / r ** 2 + Ur * X * X / r ** 3,
+            X * Z / r ** 2 * (Urr - Ur / r))
+
+
+def test_moment_tensor_source_divergence_and_curl_closed_form(oracle):
+    """Stress-rate source sigma_t += M r(t) delta in a homogeneous medium is
+    the body force F_i = r(t) M_ij d_j delta in the velocity equation
+    rho v_tt = (lam + 2 mu) grad div v - mu curl curl v + F.  Its divergence
+    theta = div v and rotation omega = dz vx - dx vz then obey scalar wave
+    equations with point sources:
+        theta = (1/rho) M_ij d_i d_j U_vp,
+        omega = (1/rho) [(Mxx - Mzz) dx dz + Mxz (dz^2 - dx^2)] U_vs,
+    U_c the 2-D point-source solution at speed c.  theta is formed from the
+    recorded velocities with the 4th-order staggered difference at a node,
+    omega at a half node.  Mxx and Mzz act at the source node, Mxz at the
+    sigma_xz node half a cell down and right of it.  Shot 0 is a pure Mxz
+    double couple, shot 1 has Mxx = 1, Mzz = -0.4: every component, its node,
+    sign and scale, and the S speed sqrt(mu/rho) through mu_xz are pinned
+    (measured <= 1.5e-3; an Mxz injection half a cell off gives 0.5, twice
+    the scale 1.0, the opposite sign 2.0; a one-sample slip 4e-2)."""
+    vp0, vs0, rho0, dx, dt, f0 = 2000.0, 1155.0, 2000.0, 5.0, 0.5e-3, 10.0
+    t0 = 1.5 / f0           # the wavelet's onset is 1e-8 of its peak
+    n, nt = 261, 900        # no wall return before the window ends
+    g = oracle.grid(ndim=2, nx=n, nz=n, npml=0, nt=nt, dx=dx, dt=dt, pml_vmax=vp0)
+    m = n // 2
+    pts = [(36, 21), (-21, 36)]            # observation nodes relative to the source cell
+    blocks = [[m + a + p, m + b + q] for (a, b) in pts for q in range(-2, 3) for p in range(-2, 3)]
+    mt = np.array([[0.0, 0.0, 1.0], [1.0, -0.4, 0.0]])
+    s = oracle.el2_forward(g, np.full((n, n), vp0), np.full((n, n), vs0), np.full((n, n), rho0),
+                           np.array([[m, m]] * 2, dtype=np.int32), mt,
+                           np.stack([oracle.ricker(f0, t0, dt, nt)] * 2), np.array([blocks] * 2, dtype=np.int32))
+    t = np.arange(nt) * dt       # sample n is the solution at t = n dt
+    S1, S2 = 9.0 / 8.0, -1.0 / 24.0
+    errs, slips = [], []
+    for shot in range(2):
+        Mxx, Mzz, Mxz = mt[shot]
+        sh = 0.5 if Mxz != 0 else 0.0          # source position in cells beyond the node
+        for ip, (a, b) in enumerate(pts):
+            blk = s[shot, :, :, 25 * ip:25 * (ip + 1)].reshape(2, nt, 5, 5)
+
+            def vx(p, q):
+                return blk[0, :, q + 2, p + 2]     # at ((i + p + 1/2) dx, (j + q) dx)
+
+            def vz(p, q):
+                return blk[1, :, q + 2, p + 2]     # at ((i + p) dx, (j + q + 1/2) dx)
+
+            theta = (S1 * (vx(0, 0) - vx(-1, 0)) + S2 * (vx(1, 0) - vx(-2, 0))
+                     + S1 * (vz(0, 0) - vz(0, -1)) + S2 * (vz(0, 1) - vz(0, -2))) / dx
+            omega = (S1 * (vx(0, 1) - vx(0, 0)) + S2 * (vx(0, 2) - vx(0, -1))
+                     - S1 * (vz(1, 0) - vz(0, 0)) - S2 * (vz(2, 0) - vz(-1, 0))) / dx
+            pxx, pzz, pxz = _radial_second_derivatives(oracle, (a - sh) * dx, (b - sh) * dx, vp0, t, f0, t0)
+            qxx, qzz, qxz = _radial_second_derivatives(oracle, (a + 0.5 - sh) * dx, (b + 0.5 - sh) * dx, vs0, t,
+                                                       f0, t0)
+            for v, ref in ((theta, (Mxx * pxx + Mzz * pzz + 2 * Mxz * pxz) / rho0),
+                           (omega, ((Mxx - Mzz) * qxz + Mxz * (qzz - qxx)) / rho0)):
+                errs.append(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+                slips.append(np.linalg.norm(v[1:] - ref[:-1]) / np.linalg.norm(ref))
+    assert max(errs) < 3e-3, errs
+    assert min(slips) > 2e-2, slips
+
+
+def test_transposition_symmetry_heterogeneous_with_cpml(oracle):
+    """Swapping x and z maps the staggered grid onto itself (vx <-> vz,
+    sxx <-> szz, sxz -> sxz, bx <-> bz, the 4-node mu_xz onto itself, the
+    x CPML profiles onto the z ones when nx = nz).  So the run on the
+    transposed model, with Mxx and Mzz swapped and the source and receivers
+    transposed, records vz where the first run records vx (to rounding).  An
+    x average of rho taken across the wrong neighbour breaks it (1.7e-2)."""
+    n, P, nt = 36, 10, 300
+    g = oracle.grid(ndim=2, nx=n, nz=n, npml=P, nt=nt, dx=5.0, dt=0.4e-3, pml_vmax=3500.0, f0_pml=20.0)
+    vp = 2200.0 + 600.0 * synth.smooth_random(11, (n, n), 2.0, 0.0, 1.0)
+    vs = vp / 1.73 * (1.0 + 0.1 * synth.smooth_random(12, (n, n), 2.0, -1.0, 1.0))
+    rho = 310.0 * vp ** 0.25 * (1.0 + 0.1 * synth.smooth_random(13, (n, n), 2.0, -1.0, 1.0))
+    wav = oracle.ricker(25.0, 0.05, 0.4e-3, nt)[None]
+    rr = [[x, z] for x in range(0, n, 5) for z in range(0, n, 7)]
+    a = oracle.el2_forward(g, vp, vs, rho, np.array([[9, 23]], dtype=np.int32), np.array([[0.7, -0.3, 0.5]]), wav,
+                           np.array([rr], dtype=np.int32))[0]
+    b = oracle.el2_forward(g, vp.T, vs.T, rho.T, np.array([[23, 9]], dtype=np.int32), np.array([[-0.3, 0.7, 0.5]]),
+                           wav, np.array([[[z, x] for x, z in rr]], dtype=np.int32))[0]
+    scale = np.abs(a).max()
+    assert scale > 0
+    assert np.abs(a[0] - b[1]).max() <= 1e-12 * scale and np.abs(a[1] - b[0]).max() <= 1e-12 * scale
+
+
+def test_model_fields_follow_definitions(oracle):
+    """lam = rho (vp^2 - 2 vs^2), mu = rho vs^2 at the nodes; mu_xz = 4 / sum
+    of 1/mu over the four nodes around the sigma_xz node; bx = 2 / (rho_i +
+    rho_{i+1}), bz = 2 / (rho_j + rho_{j+1}); the padded grid continues the
+    edge values, and a neighbour beyond it is the edge value again."""
+    nz, nx, P = 7, 9, 3
+    g = oracle.grid(ndim=2, nx=nx, nz=nz, npml=P, nt=1, dx=5.0, dt=0.4e-3, pml_vmax=3000.0)
+    rng = np.random.default_rng(21)
+    vp = rng.uniform(1800.0, 4000.0, (nz, nx))
+    vs = vp / 1.73 * rng.uniform(0.9, 1.1, (nz, nx))
+    rho = rng.uniform(1900.0, 2600.0, (nz, nx))
+    lam, mu, muxz, bx, bz = oracle.el2_pad(g, vp, vs, rho)
+    NZ, NX = nz + 2 * P, nx + 2 * P
+    for iz in range(NZ):
+        for ix in range(NX):
+            def at(f, z, x):
+                return f[min(max(z - P, 0), nz - 1), min(max(x - P, 0), nx - 1)]
+
+            r, a, b = at(rho, iz, ix), at(vp, iz, ix), at(vs, iz, ix)
+            assert lam[iz, ix] == pytest.approx(r * (a * a - 2 * b * b), rel=1e-14)
+            assert mu[iz, ix] == pytest.approx(r * b * b, rel=1e-14)
+            x1, z1 = min(ix + 1, NX - 1), min(iz + 1, NZ - 1)
+            m4 = [at(rho, z, x) * at(vs, z, x) ** 2 for z, x in ((iz, ix), (iz, x1), (z1, ix), (z1, x1))]
+            assert muxz[iz, ix] == pytest.approx(4.0 / sum(1.0 / q for q in m4), rel=1e-14)
+            assert bx[iz, ix] == pytest.approx(2.0 / (r + at(rho, iz, x1)), rel=1e-14)
+            assert bz[iz, ix] == pytest.approx(2.0 / (r + at(rho, z1, ix)), rel=1e-14)
+
+
+def test_cpml_profiles_follow_definition(oracle):
+    """CPML coefficients at integer and half nodes against the definition
+    b = exp(-(d + al) dt), a = d (b - 1) / (d + al), d = d0 (x/L)^2,
+    al = pi f0 (1 - x/L), d0 = 3 vmax ln(1/R) / (2L), x the distance into
+    the layer from the physical edge node at the node's own position;
+    a = 0, b = 1 off the layer; 0 < b < 1 and a < 0 on it, d growing and
+    al shrinking outwards."""
+    g = oracle.grid(ndim=2, nx=11, nz=6, npml=7, nt=1, dx=4.0, dt=0.3e-3, pml_vmax=3700.0, pml_R=1e-4,
+                    f0_pml=17.0)
+    ref = _cpml_tables(g, g.nx, g.nz)
+    got = [oracle.cpml_profile(g, g.nx, 0), oracle.cpml_profile(g, g.nx, 1),
+           oracle.cpml_profile(g, g.nz, 0), oracle.cpml_profile(g, g.nz, 1)]
+    for (ar, br), (ag, bg) in zip(ref, got):
+        assert np.allclose(ag, ar, rtol=1e-14, atol=0) and np.allclose(bg, br, rtol=1e-14, atol=0)
+        inl = bg < 1.0
+        assert np.all(ag[~inl] == 0.0) and np.all(ag[inl] < 0.0) and np.all(bg > 0.0)
+    # spot values by hand: the outermost integer node of x sits P cells out
+    L = 7 * 4.0
+    d0 = 3.0 * 3700.0 * np.log(1e4) / (2.0 * L)
+    bb = np.exp(-d0 * 0.3e-3)
+    assert got[0][1][0] == pytest.approx(bb, rel=1e-14)
+    assert got[0][0][0] == pytest.approx(d0 * (bb - 1.0) / d0, rel=1e-14)
+    # half node just outside the last physical node: x = 1/2 cell
+    r = 0.5 / 7
+    d, al = d0 * r * r, np.pi * 17.0 * (1 - r)
+    b1 = np.exp(-(d + al) * 0.3e-3)
+    assert got[1][1][7 + 11 - 1] == pytest.approx(b1, rel=1e-14)
+    assert got[1][0][7 + 11 - 1] == pytest.approx(d * (b1 - 1.0) / (d + al), rel=1e-14)
