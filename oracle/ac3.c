@@ -65,6 +65,7 @@ static inline double d1(const ac3_ctx *c, const double *a, long i, int dir)
 
 static void clear_ghosts(const ac3_ctx *c, double *a)
 {
+    #pragma omp parallel for schedule(static)
     for (int z = 0; z < c->SZ; ++z)
         for (int y = 0; y < c->SY; ++y)
             for (int x = 0; x < c->SX; ++x)
@@ -72,31 +73,43 @@ static void clear_ghosts(const ac3_ctx *c, double *a)
                     a[(long)z * c->sz + (long)y * c->sy + x] = 0.0;
 }
 
+/* The transposes scatter from plane iz into planes iz-4 .. iz+4.  Planes nine
+ * apart reach disjoint planes, so they are taken in nine phases (iz mod 9),
+ * the planes of one phase in parallel: no cell is written by two threads, and
+ * the order in which a cell receives its terms does not depend on the thread
+ * count. */
 static void lap_T(const ac3_ctx *c, const double *in, double *out)
 {
     const double h2 = c->dx * c->dx;
-    for (int iz = 0; iz < c->NZ; ++iz)
-        for (int iy = 0; iy < c->NY; ++iy)
-            for (int ix = 0; ix < c->NX; ++ix) {
-                long i = fi(c, iz, iy, ix);
-                double v = in[i] / h2;
-                out[i] += 3.0 * OR_L8[0] * v;
-                for (int m = 1; m <= 4; ++m) {
-                    out[i + m] += OR_L8[m] * v;
-                    out[i - m] += OR_L8[m] * v;
-                    out[i + m * c->sy] += OR_L8[m] * v;
-                    out[i - m * c->sy] += OR_L8[m] * v;
-                    out[i + m * c->sz] += OR_L8[m] * v;
-                    out[i - m * c->sz] += OR_L8[m] * v;
+    for (int ph = 0; ph < 9; ++ph) {
+        #pragma omp parallel for schedule(static)
+        for (int iz = ph; iz < c->NZ; iz += 9)
+            for (int iy = 0; iy < c->NY; ++iy)
+                for (int ix = 0; ix < c->NX; ++ix) {
+                    long i = fi(c, iz, iy, ix);
+                    double v = in[i] / h2;
+                    out[i] += 3.0 * OR_L8[0] * v;
+                    for (int m = 1; m <= 4; ++m) {
+                        out[i + m] += OR_L8[m] * v;
+                        out[i - m] += OR_L8[m] * v;
+                        out[i + m * c->sy] += OR_L8[m] * v;
+                        out[i - m * c->sy] += OR_L8[m] * v;
+                        out[i + m * c->sz] += OR_L8[m] * v;
+                        out[i - m * c->sz] += OR_L8[m] * v;
+                    }
                 }
-            }
+    }
     clear_ghosts(c, out);
 }
 
+/* x and y scatters stay in their plane (one phase); z needs nine. */
 static void d1_T(const ac3_ctx *c, const double *in, double *out, int dir)
 {
     const long s = dir == 0 ? 1 : (dir == 1 ? c->sy : c->sz);
-    for (int iz = 0; iz < c->NZ; ++iz)
+    const int period = dir == 2 ? 9 : 1;
+    for (int ph = 0; ph < period; ++ph) {
+    #pragma omp parallel for schedule(static)
+    for (int iz = ph; iz < c->NZ; iz += period)
         for (int iy = 0; iy < c->NY; ++iy)
             for (int ix = 0; ix < c->NX; ++ix) {
                 long i = fi(c, iz, iy, ix);
@@ -106,6 +119,7 @@ static void d1_T(const ac3_ctx *c, const double *in, double *out, int dir)
                     out[i - m * s] -= a;
                 }
             }
+    }
     clear_ghosts(c, out);
 }
 
@@ -220,6 +234,7 @@ static void step_T(const ac3_ctx *c, const double *cf, double *const *X, double 
     for (int j = 0; j < 3; ++j) {
         memset(q, 0, sizeof(double) * c->N);
         memset(r, 0, sizeof(double) * c->N);
+        #pragma omp parallel for schedule(static)
         for (int iz = 0; iz < c->NZ; ++iz)
             for (int iy = 0; iy < c->NY; ++iy)
                 for (int ix = 0; ix < c->NX; ++ix) {
@@ -236,10 +251,12 @@ static void step_T(const ac3_ctx *c, const double *cf, double *const *X, double 
     }
     free(q); free(r);
     /* psi^{k+1} = psi^k + dt u^{k+1} */
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < c->N; ++i) { aX[5][i] += apsin[i]; aun[i] += dt * apsin[i]; }
     /* u^{k+1} = alpha (beta u^k - gamma u^{k-1} - dt^2 s3 psi^k + C w^k + ...) */
     double *Ct = c->t2;   /* apsin no longer needed */
     memset(Ct, 0, sizeof(double) * c->N);
+    #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < c->NZ; ++iz)
         for (int iy = 0; iy < c->NY; ++iy)
             for (int ix = 0; ix < c->NX; ++ix) {

@@ -68,26 +68,38 @@ static inline double Dm(const el_ctx *c, const double *f, long i, long s)
 {
     return (OR_S4[0] * (f[i] - f[i - s]) + OR_S4[1] * (f[i + s] - f[i - 2 * s])) / c->dx;
 }
-/* transposes as literal scatters: out[j] += weight * in[i] */
+/* transposes as literal scatters: out[j] += weight * in[i].  A z scatter
+ * from row iz reaches four consecutive rows, so rows four apart write
+ * disjoint rows: they run in four phases (iz mod 4), the rows of a phase in
+ * parallel; an x scatter stays in its row (one phase).  No cell is written by
+ * two threads and its terms arrive in an order fixed by the phases alone. */
 static void Dp_T(const el_ctx *c, const double *in, double *out, long s)
 {
-    for (int iz = 0; iz < c->NZ; ++iz)
-        for (int ix = 0; ix < c->NX; ++ix) {
-            long i = fi(c, iz, ix);
-            double v = in[i] / c->dx;
-            out[i + s] += OR_S4[0] * v; out[i] -= OR_S4[0] * v;
-            out[i + 2 * s] += OR_S4[1] * v; out[i - s] -= OR_S4[1] * v;
-        }
+    const int period = s == 1 ? 1 : 4;
+    for (int ph = 0; ph < period; ++ph) {
+        #pragma omp parallel for schedule(static)
+        for (int iz = ph; iz < c->NZ; iz += period)
+            for (int ix = 0; ix < c->NX; ++ix) {
+                long i = fi(c, iz, ix);
+                double v = in[i] / c->dx;
+                out[i + s] += OR_S4[0] * v; out[i] -= OR_S4[0] * v;
+                out[i + 2 * s] += OR_S4[1] * v; out[i - s] -= OR_S4[1] * v;
+            }
+    }
 }
 static void Dm_T(const el_ctx *c, const double *in, double *out, long s)
 {
-    for (int iz = 0; iz < c->NZ; ++iz)
-        for (int ix = 0; ix < c->NX; ++ix) {
-            long i = fi(c, iz, ix);
-            double v = in[i] / c->dx;
-            out[i] += OR_S4[0] * v; out[i - s] -= OR_S4[0] * v;
-            out[i + s] += OR_S4[1] * v; out[i - 2 * s] -= OR_S4[1] * v;
-        }
+    const int period = s == 1 ? 1 : 4;
+    for (int ph = 0; ph < period; ++ph) {
+        #pragma omp parallel for schedule(static)
+        for (int iz = ph; iz < c->NZ; iz += period)
+            for (int ix = 0; ix < c->NX; ++ix) {
+                long i = fi(c, iz, ix);
+                double v = in[i] / c->dx;
+                out[i] += OR_S4[0] * v; out[i - s] -= OR_S4[0] * v;
+                out[i + s] += OR_S4[1] * v; out[i - 2 * s] -= OR_S4[1] * v;
+            }
+    }
 }
 static void clear_ghosts(const el_ctx *c, double *a)
 {
@@ -218,6 +230,7 @@ static void step_T(const el_ctx *c, double *const *M, double *const *X, double *
     /* ---- stress step, reversed ---- */
     double *t_exx = calloc(c->N, sizeof(double)), *t_ezz = calloc(c->N, sizeof(double)),
            *t_exz = calloc(c->N, sizeof(double));
+    #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < c->NZ; ++iz)
         for (int ix = 0; ix < c->NX; ++ix) {
             long i = fi(c, iz, ix);
@@ -241,6 +254,7 @@ static void step_T(const el_ctx *c, double *const *M, double *const *X, double *
     /* memory variables m^new = b m^old + a D v: adjoint to m^old and to D v */
     double *dvxx_b = calloc(c->N, sizeof(double)), *dvzz_b = calloc(c->N, sizeof(double)),
            *dvxz_b = calloc(c->N, sizeof(double)), *dvzx_b = calloc(c->N, sizeof(double));
+    #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < c->NZ; ++iz)
         for (int ix = 0; ix < c->NX; ++ix) {
             long i = fi(c, iz, ix);
@@ -262,6 +276,7 @@ static void step_T(const el_ctx *c, double *const *M, double *const *X, double *
     clear_ghosts(c, A[VZ]);
     /* ---- velocity step, reversed ---- */
     double *fx_b = t_exx, *fz_b = t_ezz;   /* reuse */
+    #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < c->NZ; ++iz)
         for (int ix = 0; ix < c->NX; ++ix) {
             long i = fi(c, iz, ix);
