@@ -83,7 +83,10 @@ enum {
     SG_ENOMEM = -3,      /* workspace smaller than workspace_bytes() */
     SG_ESTATE = -4,      /* adjoint without a matching checkpointed forward */
     SG_EDEVICE = -5,     /* a HIP runtime call failed */
-    SG_EUNSUPPORTED = -6 /* a physics / dimension combination this build does not provide */
+    SG_EUNSUPPORTED = -6,/* a physics / dimension combination this build does not provide */
+    SG_ENUMERIC = -7     /* a misfit on this model came out non-finite (NaN or Inf in the
+                            seismograms); reported by numeric_status(), the next call that
+                            synchronises with the stream */
 };
 
 /* SG_ACOUSTIC: u_tt = c^2 lap(u) + f (2-D, 3-D); SG_ELASTIC: velocity-stress
@@ -187,7 +190,9 @@ SG_API int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t s
  *   n > 0.  With a model the reduction runs over many
  *   workgroups and keeps its partial sums in the model's workspace; with
  *   m == NULL it runs in one workgroup (slower, no workspace).
- * Non-finite inputs give a non-finite J; the call itself does not sync. */
+ * Non-finite inputs give a non-finite J; the call itself does not sync.  With
+ * a model, a non-finite J also sets the model's numeric flag, which
+ * numeric_status() reports as SG_ENUMERIC. */
 SG_API int misfit(sg_model *m, const float *pred, const float *obs, int64_t n,
            double *J_dev, float *resid, sg_stream_t stream);
 
@@ -208,6 +213,17 @@ SG_API int misfit(sg_model *m, const float *pred, const float *obs, int64_t n,
 SG_API int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd,
                      float *g_vp, float *g_vs, float *g_rho, float *g_wavelet,
                      sg_stream_t stream);
+
+/* Numeric state of the model's misfits: waits for `stream`, then returns
+ * SG_ENUMERIC if any misfit() on this model since the previous
+ * numeric_status() (or since init_model) produced a non-finite J -- a NaN or
+ * Inf in the predicted or observed seismograms, or an overflow of the sum --
+ * and SG_OK otherwise.  Reading the flag clears it.  The flag is one int in
+ * the model's workspace, set by the misfit's final reduction on the device,
+ * so a failing misfit itself returns SG_OK (it does not synchronise) and the
+ * failure surfaces here.  Not for use inside a captured graph (it
+ * synchronises).  Errors: SG_EINVAL for a NULL model, SG_EDEVICE. */
+SG_API int numeric_status(sg_model *m, sg_stream_t stream);
 
 /* Optional device timing of the step loops.  With profiling on, the
  * library records one pair of HIP events on the call's stream around every

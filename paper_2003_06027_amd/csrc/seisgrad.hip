@@ -71,7 +71,7 @@ struct Layout {
     int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
         off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt,
-        off_tiles, off_soff, off_sent, off_nodef, off_items, total;
+        off_tiles, off_soff, off_sent, off_nodef, off_items, off_flag, total;
 };
 
 int check_desc(const sg_desc *d)
@@ -208,6 +208,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
     L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
     L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * ((L.g3.NZ + TZCI - 1) / TZCI + 2) : 0);
+    L.off_flag = take(sizeof(int));
     L.total = o;
     return L;
 }
@@ -266,6 +267,7 @@ struct sg_model {
     int *rec_off;
     void *rec_ent;
     double *partials;
+    int *numeric_flag;            // set on the device by a non-finite misfit
     std::vector<float> h_tab;
     std::vector<long long> h_src;
     std::vector<int> h_off, h_ent;
@@ -511,9 +513,29 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
     return SG_OK;
 }
 
+// The runtime's view of where p lives, when it has one: the attribute query
+// fails on plain pageable host memory on some runtimes; that failure is
+// cleared so later launch checks do not report it, and the pointer is then
+// taken as host memory.
+hipMemoryType memory_type(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (!p || hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return hipMemoryTypeUnregistered;
+    }
+    return a.type;
+}
+
 int check_shots(const sg_model *m, const sg_shots *sh)
 {
     if (!sh) return fail(SG_EINVAL, "shots is NULL");
+    // src, rec and mt are read by the host while the geometry is uploaded: a
+    // device address there would fault the host process, so it is refused
+    if (memory_type(sh->src) == hipMemoryTypeDevice || memory_type(sh->rec) == hipMemoryTypeDevice ||
+        memory_type(sh->mt) == hipMemoryTypeDevice)
+        return fail(SG_EINVAL, "src, rec and mt are HOST arrays; a device pointer was passed");
+    if (m->L.elastic && !sh->mt) return fail(SG_EINVAL, "elastic shots need moment tensors (mt)");
     if (sh->nshots < 1 || sh->nshots > m->max_shots)
         return fail(SG_EINVAL, "nshots %d outside [1, %d]", sh->nshots, m->max_shots);
     if (sh->nshots % m->d.nmodels)
@@ -1155,6 +1177,7 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     m->rec_off = reinterpret_cast<int *>(m->ws + L.off_recoff);
     m->rec_ent = m->ws + L.off_recent;
     m->partials = reinterpret_cast<double *>(m->ws + L.off_part);
+    m->numeric_flag = reinterpret_cast<int *>(m->ws + L.off_flag);
     for (int i = 0; i < 8; ++i) {
         m->model[i] = reinterpret_cast<float *>(m->ws + L.off_chat) + (size_t)i * d->nmodels * L.plane;
         m->tmp[i] = L.elastic ? reinterpret_cast<float *>(m->ws + L.off_tmp) + i * L.field : nullptr;
@@ -1260,6 +1283,8 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
             return fail(SG_EINVAL, "layer work list overflows its buffer");
         }
     }
+    // the numeric flag starts clear (a fill kernel: the int 0 is the float 0.f)
+    launch_fill(reinterpret_cast<float *>(m->numeric_flag), 1, 0.f, s);
     hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m->n_items3 > 0)
         e = hipMemcpyAsync(m->items3, m->h_items3.data(), sizeof(int4) * m->n_items3, hipMemcpyHostToDevice, s);
@@ -1355,7 +1380,8 @@ int misfit(sg_model *m, const float *pred, const float *obs, int64_t n, double *
     g_err.clear();
     if (!J_dev || n < 0 || (n > 0 && (!pred || !obs))) return fail(SG_EINVAL, "bad misfit arguments");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    launch_misfit(pred, obs, n, resid, m ? m->partials : nullptr, m ? 4096 : 1, J_dev, s);
+    launch_misfit(pred, obs, n, resid, m ? m->partials : nullptr, m ? 4096 : 1, J_dev,
+                  m ? m->numeric_flag : nullptr, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }
@@ -1447,6 +1473,20 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         launch_ac3_finalize(L.g3, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
+}
+
+int numeric_status(sg_model *m, sg_stream_t stream)
+{
+    g_err.clear();
+    if (!m) return fail(SG_EINVAL, "model is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHECK(hipStreamSynchronize(s));
+    int flag = 0;
+    HIPCHECK(hipMemcpy(&flag, m->numeric_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (!flag) return SG_OK;
+    const int zero = 0;
+    HIPCHECK(hipMemcpy(m->numeric_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return fail(SG_ENUMERIC, "a misfit on this model was not finite (NaN or Inf in the seismograms)");
 }
 
 int set_time_blocking(sg_model *m, int32_t steps)

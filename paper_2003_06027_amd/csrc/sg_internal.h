@@ -162,8 +162,9 @@ void launch_ac2_finalize(const Grid2 &g, int nmodels, int shots_per_model, const
                          float *acc, const float *cpad, double dt, double dx, float *g_vp,
                          hipStream_t s);
 void launch_fill(float *p, long long n, float v, hipStream_t s);
+// flag (nullable): set to 1 when J comes out non-finite, left alone otherwise.
 void launch_misfit(const float *pred, const float *obs, long long n, float *resid,
-                   double *partials, int nparts, double *J, hipStream_t s);
+                   double *partials, int nparts, double *J, int *flag, hipStream_t s);
 void launch_dot(const float *x, const float *y, long long n, double *out, hipStream_t s);
 void launch_ricker(double f0, double t0, double dt, int nt, float *out, hipStream_t s);
 

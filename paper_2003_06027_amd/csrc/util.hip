@@ -66,16 +66,21 @@ __global__ __launch_bounds__(256) void misfit_kernel(const float *pred, const fl
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void sum_partials_kernel(const double *partial, int np, double *out)
+// The final sum; a non-finite result also raises *flag (when given), which
+// the host reads at its next synchronising status query.
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double *partial, int np, double *out, int *flag)
 {
     double acc = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
     const double s = block_sum(acc);
-    if (threadIdx.x == 0) *out = s;
+    if (threadIdx.x == 0) {
+        *out = s;
+        if (flag && !isfinite(s)) *flag = 1;
+    }
 }
 
 void launch_misfit(const float *pred, const float *obs, long long n, float *resid,
-                   double *partials, int nparts, double *J, hipStream_t s)
+                   double *partials, int nparts, double *J, int *flag, hipStream_t s)
 {
     if (nparts <= 1 || partials == nullptr) {
         misfit_kernel<<<1, 256, 0, s>>>(pred, obs, n, n > 0 ? n : 1, resid, J);
@@ -89,7 +94,7 @@ void launch_misfit(const float *pred, const float *obs, long long n, float *resi
         return;
     }
     misfit_kernel<<<nb, 256, 0, s>>>(pred, obs, n, chunk, resid, partials);
-    sum_partials_kernel<<<1, 256, 0, s>>>(partials, nb, J);
+    sum_partials_kernel<<<1, 256, 0, s>>>(partials, nb, J, flag);
 }
 
 __global__ __launch_bounds__(1024) void dot_kernel(const float *x, const float *y, long long n, double *out)

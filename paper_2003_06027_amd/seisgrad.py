@@ -16,14 +16,16 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libseisgrad.so")
 
-SG_OK, SG_EINVAL, SG_EUNSTABLE, SG_ENOMEM, SG_ESTATE, SG_EDEVICE, SG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+SG_OK, SG_EINVAL, SG_EUNSTABLE, SG_ENOMEM, SG_ESTATE, SG_EDEVICE, SG_EUNSUPPORTED, SG_ENUMERIC = \
+    0, -1, -2, -3, -4, -5, -6, -7
 SG_ACOUSTIC, SG_ELASTIC, SG_ACOUSTIC_DIV = 0, 1, 2
 _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_ENOMEM",
-          SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED"}
+          SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED",
+          SG_ENUMERIC: "SG_ENUMERIC"}
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
-           "set_time_blocking", "snapshot_segment_bytes", "lbfgs_push", "lbfgs_direction",
+           "set_time_blocking", "snapshot_segment_bytes", "numeric_status", "lbfgs_push", "lbfgs_direction",
            "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad",
            "source_plane_wave")
 
@@ -73,6 +75,7 @@ def lib():
         L.dot_f64.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.set_profiling.argtypes = [C.c_void_p, C.c_int32]
         L.set_time_blocking.argtypes = [C.c_void_p, C.c_int32]
+        L.numeric_status.argtypes = [C.c_void_p, C.c_void_p]
         v = C.c_void_p
         L.lbfgs_push.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v, v, v]
         L.lbfgs_direction.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v]
@@ -212,6 +215,11 @@ class Model:
         _check(lib().adjoint_gradient(self.handle, C.byref(st), _ptr(dJdd.contiguous()), _ptr(g_vp), _ptr(g_vs),
                                       _ptr(g_rho), _ptr(g_wavelet), _stream(stream)))
         return (g_vp, g_vs, g_rho) if self.elastic else g_vp
+
+    def check_numeric(self, stream=None):
+        """Wait for the stream; raise SeisError(SG_ENUMERIC) if a misfit on this
+        model since the last check was not finite (the flag is then cleared)."""
+        _check(lib().numeric_status(self.handle, _stream(stream)))
 
     def set_time_blocking(self, steps):
         """Steps per launch of the 2-D acoustic blocked tiles (1 or 2)."""

@@ -87,10 +87,105 @@ def test_batched_gd_decreases_misfit_and_matches_single_runs():
     rel = res.J[-1] / res.J[0]
     print("batched GD J/J0 after 6 iterations:", rel)
     assert np.all(np.diff(res.J, axis=0) <= 0)           # never increases (steps are only accepted if J drops)
-    assert np.all(rel < 1.0) and res.accepted.any(axis=0).all()
+    # measured [0.995, 0.984, 0.748]: every model moves, one by a quarter;
+    # plain descent from a 10-cell blur is slow on the other two (the
+    # learned preconditioner and L-BFGS exist for that)
+    assert np.all(rel < 0.999) and np.median(rel) < 0.99 and rel.min() < 0.85
+    assert res.accepted.any(axis=0).all()
     # model 1 alone follows the same trajectory bit for bit
     d1 = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, nmodels=1, dx=cfg.dx, dt=cfg.dt, pml_vmax=3500.0)
     p1 = fwi.Propagator(d1, S.Shots(src[1:2], rec[1:2], wav[1:2].contiguous()))
     r1 = fwi.batched_gd(p1, dev(init[1:2]), obs[1:2].contiguous(), fwi.GDConfig(iters=6))
     assert np.array_equal(r1.J[:, 0], res.J[:, 1])
     assert torch.equal(r1.models[0], res.models[1])
+
+
+class _Ascent:
+    """A preconditioner whose every direction is the ascent direction +g/rms(g):
+    the untrained network (zero last layer gives p = -g/rms(g)) with its
+    output negated, so the real network kernels run."""
+
+    def __init__(self):
+        from paper_2003_06027_amd import cnn as N
+        self.pre = N.Preconditioner(8, seed=0)
+
+    def direction(self, g):
+        return -self.pre.direction(g)
+
+
+def test_safeguard_rejects_every_bad_direction_and_matches_plain_gd():
+    """Every learned direction offered is an ascent direction: the safeguard
+    must reject all of them (the descent test <p, g> < 0 fails) and take the
+    plain step instead, so the trajectory is plain descent bit for bit; after
+    two consecutive rejections a model stops asking the network."""
+    from paper_2003_06027_amd import ttm
+    B = 3
+    cfg = synth.C1.replace(nt=400)
+    true = np.stack([synth.random_layered(200 + b) for b in range(B)])
+    init = np.stack([synth.smooth(t, 10.0) for t in true])
+    src = np.array([[50, 2]] * B, dtype=np.int32)
+    rec = synth.surface_receivers_2d(B, cfg.nx)
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, cfg.nt)[None].repeat(B, 1).contiguous()
+    d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, nmodels=B, dx=cfg.dx, dt=cfg.dt, pml_vmax=3500.0)
+    prop = fwi.Propagator(d, S.Shots(src, rec, wav))
+    obs = prop.forward(dev(true), save_ckpt=False).clone()
+    plain = fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=5))
+    ld = ttm.LearnedDirection(_Ascent(), max_rejects=2)
+    guarded = fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=5), direction=ld)
+    print("offered", guarded.guarded.astype(int).tolist(), "rejected", guarded.rejected.astype(int).tolist())
+    assert np.array_equal(guarded.guarded[:2], np.ones((2, B), dtype=bool))      # offered twice ...
+    assert not guarded.guarded[2:].any()                                        # ... then switched off
+    assert np.array_equal(guarded.rejected, guarded.guarded)                    # every offer rejected
+    assert ld.off.all()
+    assert np.array_equal(guarded.J, plain.J)
+    assert torch.equal(guarded.models, plain.models)
+
+
+def test_gradient_taylor_expansion_on_the_gpu():
+    """Finite differences of J along the gradient direction against <g, delta>
+    of the autograd form's gradient (the hand-written adjoint), J in FP64 on
+    the device.  The central differences D(e) converge to <g, delta> as e^2
+    (the error falls 4x per halving of e) and their Richardson extrapolation
+    (4 D(e) - D(2e)) / 3 matches <g, delta> to 1e-3; the first-order
+    remainder J(m + e d) - J(m) - e <g, d> grows as e^2.  The model is an FP32
+    array: the base model is taken in FP32, delta in multiples of 2^-12 and
+    e >= 1 a power of 2, so every perturbed model m + e delta is exact in FP32
+    and the perturbation applied is exactly e delta."""
+    cfg, d, _ = _c1(nt=400)
+    ct = synth.layered_c1()
+    c0 = synth.smooth(ct, 10.0).astype(np.float32).astype(np.float64)
+    src, rec = synth.c1_geometry()
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, cfg.nt)[None]
+    prop = fwi.Propagator(d, S.Shots(src, rec, wav))
+    obs = prop.forward(dev(ct), save_ckpt=False).clone()
+    vp = dev(c0).requires_grad_(True)
+    seis = fwi.seis_forward(prop, vp)
+    (0.5 * ((seis - obs) ** 2).sum()).backward()
+    g = vp.grad.double().cpu().numpy().reshape(c0.shape)
+    delta = -np.round(4096.0 * g / np.abs(g).max()) / 4096.0   # the descent direction, |delta| <= 1 m/s
+    gd = float(np.sum(g * delta))
+
+    def J(eps):
+        m = c0 + eps * delta
+        assert np.array_equal(m.astype(np.float32).astype(np.float64), m)
+        pred = prop.forward(dev(m), save_ckpt=False)
+        Jd, _ = prop.model.misfit(pred, obs)
+        return Jd.item()
+
+    J0 = J(0.0)
+    eps = [1.0, 2.0, 4.0, 8.0, 16.0]
+    Jp = {e: J(e) for e in eps}
+    Jm = {e: J(-e) for e in eps}
+    D = [(Jp[e] - Jm[e]) / (2 * e) for e in eps]
+    err = [(v - gd) / abs(gd) for v in D]
+    rich = [((4 * D[i] - D[i + 1]) / 3 - gd) / abs(gd) for i in range(len(eps) - 1)]
+    rem = [abs(Jp[e] - J0 - e * gd) for e in eps]
+    print("<g, delta>", gd, "J0", J0)
+    print("central-difference signed rel. errors", ["%.3e" % v for v in err])
+    print("Richardson rel. errors", ["%.3e" % v for v in rich])
+    print("first-order remainders", ["%.3e" % v for v in rem])
+    r_err = [err[i + 1] / err[i] for i in range(len(eps) - 1)]
+    r_rem = [rem[i + 1] / rem[i] for i in range(len(eps) - 1)]
+    print("error ratios per doubling", r_err, "remainder ratios", r_rem)
+    assert abs(rich[0]) <= 1e-3 and abs(rich[1]) <= 1e-3, rich
+    assert all(3.0 < r < 5.0 for r in r_err[1:]) and all(3.0 < r < 5.0 for r in r_rem), (r_err, r_rem)
