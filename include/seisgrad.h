@@ -214,6 +214,26 @@ SG_API int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd,
                      float *g_vp, float *g_vs, float *g_rho, float *g_wavelet,
                      sg_stream_t stream);
 
+/* misfit() for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the reduction a model's misfit runs -- 4096 workgroup partial sums in
+ * FP64, added in a fixed order -- with the partial sums in a static device
+ * array of the library instead of a model's workspace, so J_dev and resid
+ * are bitwise those of misfit(m, ...).  The array holds 4096 doubles
+ * (32 KiB) per device and stays allocated until the process ends; its
+ * address is taken once per device on the first call there.  The call
+ * allocates nothing and does not synchronise.  Every call on one device
+ * shares that device's array: calls that overlap on one device (streams not
+ * ordered with each other) race on it and must be serialised by the caller.
+ * No model is involved, so no numeric flag is set: a non-finite J is visible
+ * in J_dev itself.
+ *   pred, obs: DEVICE FP32 [n] (may be NULL when n == 0, which gives J = 0);
+ *   J_dev: DEVICE double[1]; resid: DEVICE FP32 [n] or NULL (may alias pred).
+ * Errors: SG_EINVAL for n < 0, n above 2^40, J_dev NULL, or pred/obs NULL with
+ * n > 0; SG_EDEVICE if the runtime gives no address for the array. */
+SG_API int misfit_noalloc(const float *pred, const float *obs, int64_t n, double *J_dev, float *resid,
+                          sg_stream_t stream);
+
 /* Numeric state of the model's misfits: waits for `stream`, then returns
  * SG_ENUMERIC if any misfit() on this model since the previous
  * numeric_status() (or since init_model) produced a non-finite J -- a NaN or

@@ -197,7 +197,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_src = take(sizeof(long long) * max_shots);
     L.off_recoff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_recent = take(std::max(sizeof(int2), sizeof(long long)) * std::max<size_t>(1, (size_t)max_shots * max_rec));
-    L.off_part = take(sizeof(double) * 4096);
+    L.off_part = take(sizeof(double) * NOALLOC_PARTS);
     L.off_tmp = take(L.elastic ? sizeof(float) * 8 * L.field : 0);
     L.off_acc = take(sizeof(float) * 8 * (size_t)d->nmodels * L.plane);
     L.off_uoff = take(sizeof(int) * (size_t)max_shots * (max_rec + 1));
@@ -1380,7 +1380,7 @@ int misfit(sg_model *m, const float *pred, const float *obs, int64_t n, double *
     g_err.clear();
     if (!J_dev || n < 0 || (n > 0 && (!pred || !obs))) return fail(SG_EINVAL, "bad misfit arguments");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    launch_misfit(pred, obs, n, resid, m ? m->partials : nullptr, m ? 4096 : 1, J_dev,
+    launch_misfit(pred, obs, n, resid, m ? m->partials : nullptr, m ? NOALLOC_PARTS : 1, J_dev,
                   m ? m->numeric_flag : nullptr, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
@@ -1471,6 +1471,20 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         launch_ac2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
     else
         launch_ac3_finalize(L.g3, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx, g_vp, s);
+    HIPCHECK(hipGetLastError());
+    return SG_OK;
+}
+
+int misfit_noalloc(const float *pred, const float *obs, int64_t n, double *J_dev, float *resid,
+                   sg_stream_t stream)
+{
+    g_err.clear();
+    if (!J_dev || n < 0 || (n > 0 && (!pred || !obs))) return fail(SG_EINVAL, "bad misfit arguments");
+    if (n > (int64_t(1) << 40)) return fail(SG_EINVAL, "n = %lld above the limit 2^40", (long long)n);
+    double *partials = nullptr;
+    if (noalloc_scratch(&partials)) return fail(SG_EDEVICE, "no address for the static partial-sum array");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    launch_misfit(pred, obs, n, resid, partials, NOALLOC_PARTS, J_dev, nullptr, s);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }

@@ -162,6 +162,12 @@ void launch_ac2_finalize(const Grid2 &g, int nmodels, int shots_per_model, const
                          float *acc, const float *cpad, double dt, double dx, float *g_vp,
                          hipStream_t s);
 void launch_fill(float *p, long long n, float v, hipStream_t s);
+// Partial sums of the misfit reduction (a model's workspace slot, or the
+// static array of the allocation-free entry point).
+constexpr int NOALLOC_PARTS = 4096;
+// The device address of this device's static partial-sum array (taken once
+// per device); 0 on success, -1 if the runtime cannot give it.
+int noalloc_scratch(double **out);
 // flag (nullable): set to 1 when J comes out non-finite, left alone otherwise.
 void launch_misfit(const float *pred, const float *obs, long long n, float *resid,
                    double *partials, int nparts, double *J, int *flag, hipStream_t s);

@@ -2,6 +2,8 @@
 // reductions (fixed reduction order, so results are bitwise reproducible).
 #include "sg_internal.h"
 
+#include <mutex>
+
 namespace sg {
 
 __global__ void fill_kernel(float *p, long long n, float v)
@@ -108,6 +110,31 @@ __global__ __launch_bounds__(1024) void dot_kernel(const float *x, const float *
 void launch_dot(const float *x, const float *y, long long n, double *out, hipStream_t s)
 {
     dot_kernel<<<1, 1024, 0, s>>>(x, y, n, out);
+}
+
+// Partial sums of the allocation-free misfit: a static device array, one per
+// device, held until the process ends.  Host code never passes `scratch`
+// itself (on the host it names a stand-in, not the device address): the
+// address is taken once per device with hipGetSymbolAddress and kept.
+static __device__ __align__(256) double scratch[NOALLOC_PARTS];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[256] = {};
+} // namespace
+
+int noalloc_scratch(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 256) return -1;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
 }
 
 } // namespace sg

@@ -25,7 +25,7 @@ _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_E
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
-           "set_time_blocking", "snapshot_segment_bytes", "numeric_status", "lbfgs_push", "lbfgs_direction",
+           "set_time_blocking", "snapshot_segment_bytes", "numeric_status", "misfit_noalloc", "lbfgs_push", "lbfgs_direction",
            "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad",
            "source_plane_wave")
 
@@ -76,6 +76,7 @@ def lib():
         L.set_profiling.argtypes = [C.c_void_p, C.c_int32]
         L.set_time_blocking.argtypes = [C.c_void_p, C.c_int32]
         L.numeric_status.argtypes = [C.c_void_p, C.c_void_p]
+        L.misfit_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         v = C.c_void_p
         L.lbfgs_push.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v, v, v]
         L.lbfgs_direction.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v]
