@@ -98,19 +98,25 @@ def measured_traffic(phase, workload="c2"):
     return int(m.group(1)) if m else None
 
 
-def bytes_per_cell_step_el2(pml_fraction):
-    """2-D elastic: forward reads vx, vz, sxx, szz, sxz and the five model
-    fields (lam, mu, muxz, bx, bz) and writes the five fields = 60 B; layer
-    cells read and write the eight CPML memory variables (+64 B).  recompute:
-    + five snapshot fields (+20 B).  adjoint: read the five adjoint fields,
-    the model fields and the snapshots, read+write five gradient
-    accumulators, write five adjoint fields = 120 B (+64 B on layer cells).
-    The counts are per shot. The kernels read the model fields, and the
-    adjoint kernels update the accumulators, once per group of up to 4 shots
-    of a model, so they move less than this. The figures are rates of
-    per-shot work, not byte rates."""
-    return {"forward": 60.0 + 64.0 * pml_fraction, "recompute": 80.0 + 64.0 * pml_fraction,
-            "adjoint": 120.0 + 64.0 * pml_fraction}
+def el2_group(shots_per_model):
+    """Shots of one model that the elastic passes take together (the
+    library's rule): 4 when the model's shots divide by 4, else 2, else 1."""
+    return 4 if shots_per_model % 4 == 0 else 2 if shots_per_model % 2 == 0 else 1
+
+
+def bytes_per_cell_step_el2(pml_fraction, group=1):
+    """2-D elastic, per shot and padded cell.  forward: read vx, vz, sxx, szz,
+    sxz and write them = 40 B, plus the five model fields (lam, mu, muxz, bx,
+    bz; 20 B) that a group of `group` shots reads once; layer cells read and
+    write the eight CPML memory variables (+64 B).  recompute: + five
+    snapshot fields (+20 B).  adjoint: read the five adjoint fields and the
+    five snapshots, write five adjoint fields = 60 B, plus the model fields
+    (20 B) and the five gradient accumulators read and written (40 B), once
+    per group; +64 B on layer cells."""
+    per_group = 20.0 / group
+    return {"forward": 40.0 + per_group + 64.0 * pml_fraction,
+            "recompute": 60.0 + per_group + 64.0 * pml_fraction,
+            "adjoint": 60.0 + (20.0 + 40.0) / group + 64.0 * pml_fraction}
 
 
 def bytes_per_cell_step_ac3(pml_fraction):
@@ -135,6 +141,32 @@ def copy_bandwidth(torch):
         best = max(best, 2.0 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
     del a, b
     return best
+
+
+def omp_threads(n):
+    """Thread count of the oracle's OpenMP loops (the process's libgomp)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    except OSError:
+        pass
+
+
+def host_cpu():
+    """The host CPU as lscpu reports it, and the CPUs this process may use."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                             "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    info["usable_cpus"] = len(os.sched_getaffinity(0))
+    return info
 
 
 def cpu_baseline_el2(cfg, m0, src, mt, rec, nshots, nt):
@@ -176,50 +208,20 @@ def cpu_baseline(cfg, c0, src, rec, nshots, nt, divergence=False):
     return 2.0 * cells * nshots * nt / t / 1e9, t
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nt", type=int, default=None, help="override time steps (profiling runs only)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-steps", type=int, default=400)
-    ap.add_argument("--no-ttm", action="store_true", help="skip the learned-preconditioner time-to-misfit leg")
-    ap.add_argument("--store-segments", type=int, default=None,
-                    help="checkpoint segments whose adjoint snapshots the forward keeps "
-                         "(default: as many as fit in free HBM)")
-    ap.add_argument("--time-blocking", type=int, default=None, choices=(1, 2),
-                    help="time steps per launch on the blocked tiles (results are identical); "
-                         "default: the autotuner's choice")
-    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
-                    help="c2: 2-D acoustic 1000x500, 64 shots (default); c3: 2-D elastic 800x400, 16 shots; "
-                         "c4: 3-D acoustic 400^3")
-    ap.add_argument("--physics", choices=("constant-density", "divergence"), default="constant-density",
-                    help="acoustic form: u_tt = c^2 lap(u) (the headline kernels) or u_tt = div(c^2 grad u) "
-                         "(staggered grid, CPML; same grid, shots and steps)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU shot sharding "
-              "is a design, not a build target.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2003_06027_amd import seisgrad as S
-    from paper_2003_06027_amd import synth
-
-    wl = args.workload
+def measure(a, S, synth, torch):
+    """Time K steps (fwd with checkpoints + misfit + adjoint) of workload
+    a.workload; returns the JSON record and what the CPU baseline needs."""
+    wl = a.workload
     cfg = {"c2": synth.C2, "c3": synth.C3, "c4": synth.C4}[wl]
-    nt = args.nt or cfg.nt
+    nt = a.nt or cfg.nt
     ckpt = int(math.ceil(math.sqrt(nt)))
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
-    div = args.physics == "divergence"
+    div = a.physics == "divergence"
     if div and wl != "c2":
         log("--physics divergence applies to the c2 workload")
         sys.exit(2)
     if div or wl != "c2":
-        args.no_ttm = True                    # the learned-preconditioner leg runs the headline form
+        a.no_ttm = True                    # the learned-preconditioner leg runs the headline form
     mt_ = None
     if wl == "c2":
         true_m = [synth.dipping_layers_anomalies(2003, cfg.nx, cfg.nz, cfg.dx)]
@@ -260,25 +262,25 @@ def main():
     # grid and shot batch, cached, outside the timed region)
     strategy = None
     if div or wl != "c2":
-        args.time_blocking = 1                # one step per launch (the setting is the 2-D acoustic form's)
-    if args.time_blocking is None:
+        a.time_blocking = 1                # one step per launch (the setting is the 2-D acoustic form's)
+    if a.time_blocking is None:
         from paper_2003_06027_amd import tune
         strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log)
-        args.time_blocking = strategy.time_blocking
+        a.time_blocking = strategy.time_blocking
         torch.cuda.empty_cache()
     # workspace beyond the minimum keeps the adjoint snapshots of the last
     # checkpoint segments (their recomputation is skipped); leave a margin
     # for the seismogram and residual buffers
     nseg = -(-nt // ckpt)
-    if args.store_segments is None:
+    if a.store_segments is None:
         free = torch.cuda.mem_get_info()[0]
         spare = free - S.workspace_bytes(d, ns, nrec, ckpt) - 16 * (1 << 30)
         nstore = int(max(0, min(nseg, spare // S.snapshot_segment_bytes(d, ns, ckpt))))
     else:
-        nstore = min(args.store_segments, nseg)
+        nstore = min(a.store_segments, nseg)
     m = model(init_m, store_segments=nstore)
     log(f"workspace {m.ws.numel() / 1e9:.1f} GB: {nstore} of {nseg} segments keep their snapshots")
-    m.set_time_blocking(args.time_blocking)
+    m.set_time_blocking(a.time_blocking)
     seis = torch.empty_like(obs)
     resid = torch.empty_like(obs)
     J = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -292,37 +294,40 @@ def main():
                                 S._ptr(resid), S._stream()))
         m.gradient(sh, resid, g_vp=g, g_vs=gx[0], g_rho=gx[1])
 
-    for i in range(args.warmup):
+    for i in range(a.warmup):
         step()
         torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done, J = {J.item():.6e}")
+        log(f"warmup {i + 1}/{a.warmup} done, J = {J.item():.6e}")
     m.set_profiling(True)
     m.phase_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(a.steps):
         step()
         torch.cuda.synchronize()
-        log(f"step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s")
+        log(f"step {i + 1}/{a.steps} done at {time.perf_counter() - t0:.2f} s")
     t1 = time.perf_counter()
     phases = m.phase_times()
     m.set_profiling(False)
-    if args.copy_probe:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.ones_like(a)
-        a.copy_(b)
+    if a.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.ones_like(x)
+        x.copy_(y)
         torch.cuda.synchronize()
-        del a, b
+        del x, y
     assert np.isfinite(J.item()) and np.isfinite(g.abs().max().item())
-    copy_gbs = None if args.copy_probe else copy_bandwidth(torch)
+    copy_gbs = None if a.copy_probe else copy_bandwidth(torch)
 
-    T = (t1 - t0) / args.steps
+    T = (t1 - t0) / a.steps
     cells = cfg.padded_cells
     updates = 2.0 * cells * ns * nt
     value = updates / T / 1e9
     pml_frac = 1.0 - cfg.nx * cfg.ny * cfg.nz / cells
-    bpc = (bytes_per_cell_step_div if div else bytes_per_cell_step_el2 if wl == "c3"
-           else bytes_per_cell_step_ac3 if wl == "c4" else bytes_per_cell_step)(pml_frac)
+    if wl == "c3":
+        bpc = bytes_per_cell_step_el2(pml_frac, el2_group(ns // d.nmodels))
+    else:
+        bpc = (bytes_per_cell_step_div if div else bytes_per_cell_step_ac3 if wl == "c4"
+               else bytes_per_cell_step)(pml_frac)
     ph = {}
     for name, (ms, steps) in phases.items():
         if steps == 0:
@@ -336,13 +341,13 @@ def main():
     traffic = measured_traffic(dom, "div" if div else wl)   # HBM bytes per step (all launches)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(T * 1e3, 3),
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(T * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": (cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}") + ("_divergence" if div else ""),
                    "grid_padded": list(cfg.padded),
                    "shots": ns, "nt": nt, "ckpt_every": ckpt, "stored_segments": nstore, "segments": nseg,
-                   "time_blocking": args.time_blocking,
+                   "time_blocking": a.time_blocking,
                    "tuned": None if strategy is None else {"time_blocking": strategy.time_blocking,
                                                            "graphs": strategy.graphs},
                    "launch": "eager (per-phase HIP events need eager launches)",
@@ -359,9 +364,60 @@ def main():
                      "frac_of_copy": None if copy_gbs is None else round(ph[dom]["gbs"] / copy_gbs, 4)},
         "phases": ph,
     }
+    ctx = dict(cfg=cfg, c0=c0, init_m=init_m, src=src, rec=rec, mt=mt_, ns=ns, div=div)
+    m.close()
+    return out, ctx
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=None, help="override time steps (profiling runs only)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--no-ttm", action="store_true", help="skip the learned-preconditioner time-to-misfit leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the short 3-D record of the default run")
+    ap.add_argument("--store-segments", type=int, default=None,
+                    help="checkpoint segments whose adjoint snapshots the forward keeps "
+                         "(default: as many as fit in free HBM)")
+    ap.add_argument("--time-blocking", type=int, default=None, choices=(1, 2),
+                    help="time steps per launch on the blocked tiles (results are identical); "
+                         "default: the autotuner's choice")
+    ap.add_argument("--workload", choices=("c2", "c3", "c4"), default="c2",
+                    help="c2: 2-D acoustic 1000x500, 64 shots (default); c3: 2-D elastic 800x400, 16 shots; "
+                         "c4: 3-D acoustic 400^3")
+    ap.add_argument("--physics", choices=("constant-density", "divergence"), default="constant-density",
+                    help="acoustic form: u_tt = c^2 lap(u) (the headline kernels) or u_tt = div(c^2 grad u) "
+                         "(staggered grid, CPML; same grid, shots and steps)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU shot sharding "
+              "is a design, not a build target.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_06027_amd import seisgrad as S
+    from paper_2003_06027_amd import synth
+
+    out, ctx = measure(args, S, synth, torch)
+    if args.workload == "c2" and args.physics == "constant-density" and not args.no_c4:
+        # a short 3-D record beside the headline: the full 400^3 grid, 40 steps
+        # (7-step checkpoints), one timed fwd+adjoint step after one warm-up
+        torch.cuda.empty_cache()
+        sub = argparse.Namespace(**vars(args))
+        sub.workload, sub.nt, sub.steps, sub.warmup = "c4", 40, 1, 1
+        sub.store_segments, sub.time_blocking, sub.copy_probe, sub.no_ttm = None, None, False, True
+        c4, _ = measure(sub, S, synth, torch)
+        out["c4"] = {k: c4[k] for k in ("value", "unit", "ms_per_step", "config", "roofline", "phases")}
+        torch.cuda.empty_cache()
+    cfg, c0, init_m, src, rec, mt_, ns, div = (ctx[k] for k in ("cfg", "c0", "init_m", "src", "rec", "mt", "ns",
+                                                               "div"))
+    wl = args.workload
     if not args.no_ttm:
-        m.close()
-        del m, seis, resid, obs
         torch.cuda.empty_cache()
         from paper_2003_06027_amd import ttm
         log("time-to-misfit: data generation, CNN training and evaluation")
@@ -390,22 +446,34 @@ def main():
         }
     if not args.no_cpu:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        if wl == "c2":
-            ncpu, steps = max(1, min(cores, ns)), args.cpu_steps
-            log(f"cpu baseline: oracle, {ncpu} shots x {steps} steps on {cores} threads")
-            rate, t = cpu_baseline(cfg, c0, src, rec, ncpu, steps, divergence=div)
-        elif wl == "c3":
-            ncpu, steps = 2, min(args.cpu_steps, 300)
-            log(f"cpu baseline: oracle, {ncpu} shots x {steps} steps on {cores} threads")
-            rate, t = cpu_baseline_el2(cfg, init_m, src, mt_, rec, ncpu, steps)
-        else:
-            ncpu, steps = 1, 2
-            log(f"cpu baseline: oracle, 1 shot x {steps} steps on {cores} threads")
-            rate, t = cpu_baseline_ac3(cfg, c0, src, rec, steps)
+        omp_threads(cores)
+
+        def sample(nshots, nsteps):
+            if wl == "c2":
+                return cpu_baseline(cfg, c0, src, rec, nshots, nsteps, divergence=div)
+            if wl == "c3":
+                return cpu_baseline_el2(cfg, init_m, src, mt_, rec, nshots, nsteps)
+            return cpu_baseline_ac3(cfg, c0, src, rec, nsteps)
+
+        # all host threads (the oracle runs shots in parallel in 2-D acoustic,
+        # rows / planes of every pass in the elastic and 3-D forms)
+        ncpu, steps = {"c2": (max(1, min(cores, ns)), args.cpu_steps), "c3": (2, min(args.cpu_steps, 300)),
+                       "c4": (1, 2)}[wl]
+        log(f"cpu baseline: oracle, {ncpu} shot(s) x {steps} steps on {cores} threads")
+        rate, t = sample(ncpu, steps)
+        # one thread, a smaller sample of the same grid
+        n1, s1 = {"c2": (1, max(1, steps // 2)), "c3": (1, max(1, steps // 10)), "c4": (1, 1)}[wl]
+        omp_threads(1)
+        log(f"cpu baseline: oracle, {n1} shot x {s1} steps on 1 thread")
+        rate1, t1 = sample(n1, s1)
+        omp_threads(cores)
         out["cpu_baseline"] = {"value": round(rate, 4), "unit": "Gcell-updates/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{ncpu} shot(s) x {steps} steps of the same grid, FP64 "
-                                         f"fwd+adjoint, {t:.1f} s"}
+                                         f"fwd+adjoint, {t:.1f} s",
+                               "single_thread": {"value": round(rate1, 5),
+                                                 "sample": f"{n1} shot x {s1} steps, {t1:.1f} s"},
+                               "host": host_cpu()}
     print(json.dumps(out), flush=True)
 
 

@@ -139,7 +139,7 @@ typedef struct sg_model sg_model;
  * descriptor or a size beyond the build's limits: 2^20 - 1 receivers per
  * shot; 3-D grids below 4096 padded planes in z, and 76 padded planes of
  * the xy frame below 4 GiB; elastic runs of at most 65535 shots, with
- * ceil(NX / 256) * NZ * max_shots below 2^31 (NX, NZ: padded). */
+ * ceil(NX / 32) * ceil(NZ / 8) * max_shots below 2^31 (NX, NZ: padded). */
 SG_API size_t workspace_bytes(const sg_desc *d, int32_t max_shots, int32_t max_rec, int32_t ckpt_every);
 
 /* Bytes that one stored checkpoint segment of adjoint snapshots takes in the

@@ -37,7 +37,6 @@ constexpr float C2 = (float)(-1.0 / 24.0);
 // passes, the forward's in XCD order, the adjoint's in the hardware order
 // (they ran slower in XCD order with every block shape). Each is the
 // measured best of 16 x 16 (forward), 32 x 8, 64 x 4, 128 x 2 and 256 x 1.
-constexpr int EBX_FWD = 32, EBX_ADJ = 32;
 constexpr bool XCD_FWD = true, XCD_ADJ = false;
 
 __device__ __forceinline__ float Dp(const float *f, long long i, long long s)

@@ -7,7 +7,16 @@ namespace sg {
 
 // ---------------------------------------------------------------- elastic 2-D
 // Staggered velocity-stress fields on a 2-D frame (same frame as the 2-D
-// acoustic fields); one thread per cell, 64 x 4 cell blocks.
+// acoustic fields); one thread per cell, EBX x (256 / EBX) = 32 x 8 cell
+// blocks in every pass.  The forward passes and the adjoint's first two
+// passes give each thread a group of el2_group(shots per model) shots of one
+// model; the forward passes number (cell block, shot group) in a 1-D grid,
+// the adjoint passes take the shot group as the grid's y index.
+constexpr int EBX_FWD = 32, EBX_ADJ = 32;
+constexpr long long el2_cell_blocks(int ebx, long long NX, long long NZ)
+{
+    return (NX + ebx - 1) / ebx * ((NZ + 256 / ebx - 1) / (256 / ebx));
+}
 constexpr int EL_NS = 13;      // vx vz sxx szz sxz + 8 CPML memory variables
 enum { E_VX, E_VZ, E_SXX, E_SZZ, E_SXZ, E_MVXX, E_MVXZ, E_MVZX, E_MVZZ,
        E_MSXXX, E_MSXZZ, E_MSXZX, E_MSZZZ };

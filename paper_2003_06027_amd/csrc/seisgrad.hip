@@ -107,14 +107,15 @@ int check_desc(const sg_desc *d)
     return SG_OK;
 }
 
-// Shot-count limits of the launches: the elastic adjoint passes take the shot
-// as the grid's y index (at most 65535), the forward passes number their
-// 256 x 1 cell blocks over all shots with an int.
+// Shot-count limits of the elastic launches: the adjoint passes take the shot
+// (group) as the grid's y index (at most 65535); the forward passes number
+// (cell block, shot group) in a 1-D grid of int work ids, at most
+// el2_cell_blocks * max_shots of them (shot groups of one).
 int check_shots(const sg_desc *d, int max_shots)
 {
     if (d->physics != SG_ELASTIC) return SG_OK;
     const long long NX = d->nx + 2LL * d->npml, NZ = d->nz + 2LL * d->npml;
-    if (max_shots > 65535 || (NX + 255) / 256 * NZ * max_shots >= (1LL << 31))
+    if (max_shots > 65535 || el2_cell_blocks(EBX_FWD, NX, NZ) * max_shots >= (1LL << 31))
         return fail(SG_EINVAL, "too many elastic shots (%d) for a %lld x %lld grid", max_shots, NX, NZ);
     return SG_OK;
 }
