@@ -258,15 +258,14 @@ def measure(a, S, synth, torch):
     torch.cuda.synchronize()
     mtrue.close()
     del mtrue
-    # strategy from the autotuner (timed on 4 checkpoint segments of this
-    # grid and shot batch, cached, outside the timed region)
-    strategy = None
-    if div or wl != "c2":
-        a.time_blocking = 1                # one step per launch (the setting is the 2-D acoustic form's)
-    if a.time_blocking is None:
-        from paper_2003_06027_amd import tune
-        strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log)
-        a.time_blocking = strategy.time_blocking
+    # launch strategy from the autotuner (timed on a few checkpoint segments
+    # of this grid and shot batch, cached, outside the timed region)
+    from paper_2003_06027_amd import tune
+    if a.time_blocking is not None:
+        strategy = tune.Strategy(time_blocking=a.time_blocking)
+    else:
+        extra = {} if len(init_m) == 1 else {"vs": dev(init_m[1]), "rho": dev(init_m[2])}
+        strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log, segments=2 if wl == "c4" else 4, **extra)
         torch.cuda.empty_cache()
     # workspace beyond the minimum keeps the adjoint snapshots of the last
     # checkpoint segments (their recomputation is skipped); leave a margin
@@ -280,7 +279,7 @@ def measure(a, S, synth, torch):
         nstore = min(a.store_segments, nseg)
     m = model(init_m, store_segments=nstore)
     log(f"workspace {m.ws.numel() / 1e9:.1f} GB: {nstore} of {nseg} segments keep their snapshots")
-    m.set_time_blocking(a.time_blocking)
+    strategy.apply(m)
     seis = torch.empty_like(obs)
     resid = torch.empty_like(obs)
     J = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -347,9 +346,7 @@ def measure(a, S, synth, torch):
         "config": {"workload": (cfg.name if nt == cfg.nt else f"{cfg.name}_nt{nt}") + ("_divergence" if div else ""),
                    "grid_padded": list(cfg.padded),
                    "shots": ns, "nt": nt, "ckpt_every": ckpt, "stored_segments": nstore, "segments": nseg,
-                   "time_blocking": a.time_blocking,
-                   "tuned": None if strategy is None else {"time_blocking": strategy.time_blocking,
-                                                           "graphs": strategy.graphs},
+                   "launch_settings": strategy.label(),
                    "launch": "eager (per-phase HIP events need eager launches)",
                    "receivers": nrec,
                    "cell_updates_per_step": updates},

@@ -312,14 +312,14 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
     __shared__ float sphy[LAYER ? 2 * (TY3 + 8) * WY : 1];
     __shared__ float xch[REC ? TX3 * TY3 : 1];
     const Grid3 &g = a.g;
-    const int nzf = (g.NZ + TZCF - 1) / TZCF;
+    const int nzf = (g.NZ + g.zcf - 1) / g.zcf;
     const int w = xcd_work_id(a.ntl * nzf * a.nshots);
     const int shot = w / (a.ntl * nzf);
     const int rem = w - shot * a.ntl * nzf;
     const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
     const int nxy = g.ntx * g.nty;
     const int ty = tile / g.ntx, tx = tile - ty * g.ntx;
-    const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * TZCF, z1 = min(z0 + TZCF, g.NZ);
+    const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * g.zcf, z1 = min(z0 + g.zcf, g.NZ);
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
     const int ix = x0 + lx, iy = y0 + ly;
     const bool valid_xy = ix < g.NX && iy < g.NY;
@@ -661,7 +661,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
     const int rem = w - shot * a.ntl * g.nzc;
     const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
     const int ty = tile / g.ntx, tx = tile - ty * g.ntx;
-    const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * TZC, z1 = min(z0 + TZC, g.NZ);
+    const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * g.zca, z1 = min(z0 + g.zca, g.NZ);
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
     const int ix = x0 + lx, iy = y0 + ly;
     const bool valid_xy = ix < g.NX && iy < g.NY;
@@ -977,7 +977,7 @@ void launch_ac3_fwd_part(Ac3FwdArgs a, int t0, int ntl, hipStream_t s)
 {
     a.t0 = t0;
     a.ntl = ntl;
-    const int nb = ntl * ((a.g.NZ + TZCF - 1) / TZCF) * a.nshots;
+    const int nb = ntl * ((a.g.NZ + a.g.zcf - 1) / a.g.zcf) * a.nshots;
     if (nb == 0) return;
     const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
     if (snap) { if (rec) ac3_fwd_kernel<true, true, LAYER><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<true, false, LAYER><<<nb, NTH3, 0, s>>>(a); }

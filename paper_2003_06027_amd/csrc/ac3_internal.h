@@ -7,16 +7,20 @@ namespace sg {
 
 // ---------------------------------------------------------------- 3-D
 // Tile of the 3-D kernels: TX3 x TY3 columns (one thread each), marching in
-// z over chunks of planes with register windows along z. The forward passes
-// and the layer work items take shorter chunks than the adjoint, whose longer
-// march re-reads fewer window planes; the adjoint's is the longest.
+// z over chunks of planes with register windows along z.  The chunk lengths
+// are run-time settings of a model (set_tuning; Grid3.zcf, zca and the
+// layer work list), between TZC_MIN and TZC planes; the defaults are below:
+// the forward passes and the layer work items take shorter chunks than the
+// adjoint, whose longer march re-reads fewer window planes.
 constexpr int TX3 = 32;
 constexpr int TY3 = 16;
 constexpr int NTH3 = TX3 * TY3;
-constexpr int TZC = 64;    // the adjoint tile passes
-constexpr int TZCF = 32;   // the forward tile passes
-constexpr int TZCI = 32;   // the layer work items
-static_assert(TZCF <= TZC && TZCI <= TZC, "TZC bounds every chunk's 32-bit plane offsets");
+constexpr int TZC = 64;    // the longest chunk (bounds every chunk's 32-bit plane offsets)
+constexpr int TZC_MIN = 16;
+constexpr int TZCA_DEF = 64;   // the adjoint tile passes
+constexpr int TZCF_DEF = 32;   // the forward tile passes
+constexpr int TZCI_DEF = 32;   // the layer work items
+static_assert(TZCF_DEF <= TZC && TZCI_DEF <= TZC && TZCA_DEF <= TZC && TZC_MIN <= TZCF_DEF, "chunk bounds");
 constexpr int OX3 = 32;  // x offset (128-byte aligned rows)
 constexpr int OY3 = 4;
 constexpr int OZ3 = 4;
@@ -29,6 +33,7 @@ struct Grid3 {
     int SX, SY, SZ;
     long long sy, sz, plane;   // strides: sy = SX, sz = SX*SY, plane = sz*SZ
     int ntx, nty, nzc;         // tiles in x, y; adjoint z chunks
+    int zcf, zca;              // planes per chunk: forward and adjoint tile passes
 };
 
 struct Ac3Tabs {               // per-axis damping tables, h = zeta dt / 2

@@ -148,13 +148,12 @@ dim3 cell_grid(const Grid2 &g, int nshots)
 // passes that accumulate gradients also add the group's summed contribution
 // to one accumulator slot per group (slots [group][plane]), where one slot
 // per shot would cost a read and a write of each accumulator per shot.
-__host__ __device__ constexpr int el2_group(int spm) { return spm % 4 == 0 ? 4 : spm % 2 == 0 ? 2 : 1; }
 
-template <int GSH>
+template <int GSH, int EBX>
 __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model / GSH);   // c.shot: the group
+    const Cell c = cell_of<EBX, XCD_FWD>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
     const long long SX = g.SX;
     const float kbx = a.kap * a.m[M_BX][c.mo + c.f], kbz = a.kap * a.m[M_BZ][c.mo + c.f];
@@ -180,11 +179,11 @@ __global__ __launch_bounds__(256) void el2_vel_kernel(El2Args a)
     }
 }
 
-template <int GSH>
+template <int GSH, int EBX>
 __global__ __launch_bounds__(256) void el2_str_kernel(El2Args a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_FWD, XCD_FWD>(g, a.shots_per_model / GSH);   // c.shot: the group
+    const Cell c = cell_of<EBX, XCD_FWD>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
     const long long SX = g.SX;
     const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
@@ -255,11 +254,11 @@ __global__ void el2_inject_kernel(El2RecArgs a)
 }
 
 
-template <int GSH>
+template <int GSH, int EBX>
 __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
+    const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
     const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
     float g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -299,11 +298,11 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
     gacc(a.grad + 2 * a.grad_stride + gf, g2);
 }
 
-template <int GSH>
+template <int GSH, int EBX>
 __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
+    const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
     if (!c.valid) return;
     const long long SX = g.SX;
     const float bxm = a.m[M_BX][c.mo + c.f], bzm = a.m[M_BZ][c.mo + c.f];
@@ -340,10 +339,11 @@ __global__ __launch_bounds__(256) void el2_adj2_kernel(El2AdjArgs a)
     gacc(a.grad + 4 * a.grad_stride + gf, g4);
 }
 
+template <int EBX>
 __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
 {
     const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX_ADJ, XCD_ADJ>(g, a.shots_per_model);
+    const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
     const long long f = c.so + c.f, SX = g.SX;
     a.a[E_SXX][f] -= Dm(a.tmp[4], f, 1);
@@ -487,39 +487,33 @@ int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 6
 
 } // namespace
 
-void launch_el2_vel(const El2Args &a, hipStream_t s)
+// Launch kernel K<GSH, EBX> for the args' group size and block width.
+#define EL2_DISPATCH(K, a, XCD, s)                                                                    \
+    do {                                                                                              \
+        const int gs_ = (a).gs, n_ = (a).nshots / gs_;                                                \
+        if ((a).ebx == 64) {                                                                          \
+            const dim3 grid_ = cell_grid<64, XCD>((a).g, n_);                                         \
+            if (gs_ == 4) K<4, 64><<<grid_, 256, 0, s>>>(a);                                          \
+            else if (gs_ == 2) K<2, 64><<<grid_, 256, 0, s>>>(a);                                     \
+            else K<1, 64><<<grid_, 256, 0, s>>>(a);                                                   \
+        } else {                                                                                      \
+            const dim3 grid_ = cell_grid<32, XCD>((a).g, n_);                                         \
+            if (gs_ == 4) K<4, 32><<<grid_, 256, 0, s>>>(a);                                          \
+            else if (gs_ == 2) K<2, 32><<<grid_, 256, 0, s>>>(a);                                     \
+            else K<1, 32><<<grid_, 256, 0, s>>>(a);                                                   \
+        }                                                                                             \
+    } while (0)
+
+void launch_el2_vel(const El2Args &a, hipStream_t s) { EL2_DISPATCH(el2_vel_kernel, a, XCD_FWD, s); }
+void launch_el2_str(const El2Args &a, hipStream_t s) { EL2_DISPATCH(el2_str_kernel, a, XCD_FWD, s); }
+void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { EL2_DISPATCH(el2_adj1_kernel, a, XCD_ADJ, s); }
+void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { EL2_DISPATCH(el2_adj2_kernel, a, XCD_ADJ, s); }
+void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s)
 {
-    const int gs = el2_group(a.shots_per_model);
-    const dim3 grid = cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots / gs);
-    if (gs == 4) el2_vel_kernel<4><<<grid, 256, 0, s>>>(a);
-    else if (gs == 2) el2_vel_kernel<2><<<grid, 256, 0, s>>>(a);
-    else el2_vel_kernel<1><<<grid, 256, 0, s>>>(a);
+    if (a.ebx == 64) el2_adj3_kernel<64><<<cell_grid<64, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a);
+    else el2_adj3_kernel<32><<<cell_grid<32, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a);
 }
-void launch_el2_str(const El2Args &a, hipStream_t s)
-{
-    const int gs = el2_group(a.shots_per_model);
-    const dim3 grid = cell_grid<EBX_FWD, XCD_FWD>(a.g, a.nshots / gs);
-    if (gs == 4) el2_str_kernel<4><<<grid, 256, 0, s>>>(a);
-    else if (gs == 2) el2_str_kernel<2><<<grid, 256, 0, s>>>(a);
-    else el2_str_kernel<1><<<grid, 256, 0, s>>>(a);
-}
-void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s)
-{
-    const int gs = el2_group(a.shots_per_model);
-    const dim3 grid = cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots / gs);
-    if (gs == 4) el2_adj1_kernel<4><<<grid, 256, 0, s>>>(a);
-    else if (gs == 2) el2_adj1_kernel<2><<<grid, 256, 0, s>>>(a);
-    else el2_adj1_kernel<1><<<grid, 256, 0, s>>>(a);
-}
-void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s)
-{
-    const int gs = el2_group(a.shots_per_model);
-    const dim3 grid = cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots / gs);
-    if (gs == 4) el2_adj2_kernel<4><<<grid, 256, 0, s>>>(a);
-    else if (gs == 2) el2_adj2_kernel<2><<<grid, 256, 0, s>>>(a);
-    else el2_adj2_kernel<1><<<grid, 256, 0, s>>>(a);
-}
-void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s) { el2_adj3_kernel<<<cell_grid<EBX_ADJ, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a); }
+#undef EL2_DISPATCH
 
 void launch_el2_record(const El2RecArgs &a, hipStream_t s)
 {
@@ -541,14 +535,14 @@ void launch_el2_prep(const Grid2 &g, int nmodels, const float *vp, const float *
         phys_pad[2]);
 }
 
-void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, const float *grad, long long grad_stride,
+void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, int gs, const float *grad, long long grad_stride,
                          float *acc, const float *const *model, const float *const *phys_pad,
                          float *g_vp, float *g_vs, float *g_rho, hipStream_t s)
 {
     const long long n = (long long)nmodels * g.plane;
     float *pad = acc + 5 * n;
     // one accumulator slot per shot group
-    el2_sum_shots_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, spm / el2_group(spm), grad, grad_stride, acc);
+    el2_sum_shots_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, spm / gs, grad, grad_stride, acc);
     el2_chain_kernel<<<blocks_for(n), 256, 0, s>>>(g, nmodels, acc, model[2], model[1], model[3], model[4],
                                                     phys_pad[0], phys_pad[1], phys_pad[2], pad);
     el2_fold_kernel<<<blocks_for((long long)nmodels * g.nz * g.nx), 256, 0, s>>>(g, nmodels, pad, g_vp, g_vs,

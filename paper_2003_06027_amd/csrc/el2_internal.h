@@ -7,12 +7,14 @@ namespace sg {
 
 // ---------------------------------------------------------------- elastic 2-D
 // Staggered velocity-stress fields on a 2-D frame (same frame as the 2-D
-// acoustic fields); one thread per cell, EBX x (256 / EBX) = 32 x 8 cell
-// blocks in every pass.  The forward passes and the adjoint's first two
-// passes give each thread a group of el2_group(shots per model) shots of one
-// model; the forward passes number (cell block, shot group) in a 1-D grid,
-// the adjoint passes take the shot group as the grid's y index.
-constexpr int EBX_FWD = 32, EBX_ADJ = 32;
+// acoustic fields); one thread per cell, cell blocks of EBX x (256 / EBX),
+// EBX = 32 (32 x 8, the default) or 64 (64 x 4), a run-time setting of a
+// model (set_tuning).  The forward passes and the adjoint's first two passes
+// give each thread a group of gs shots of one model (by default
+// el2_group(shots per model)); the forward passes number (cell block, shot
+// group) in a 1-D grid, the adjoint passes take the shot group as the grid's
+// y index.
+constexpr int EBX_DEF = 32;
 constexpr long long el2_cell_blocks(int ebx, long long NX, long long NZ)
 {
     return (NX + ebx - 1) / ebx * ((NZ + 256 / ebx - 1) / (256 / ebx));
@@ -26,9 +28,12 @@ struct El2Tabs {               // CPML a, b at integer (0) and half (1) position
     const float *ax[2], *bx[2], *az[2], *bz[2];
 };
 
+__host__ __device__ constexpr int el2_group(int spm) { return spm % 4 == 0 ? 4 : spm % 2 == 0 ? 2 : 1; }
+
 struct El2Args {
     Grid2 g;                   // NX, NZ, P, nx, nz, SX, SZ, plane (tiles unused)
     int nshots, shots_per_model;
+    int gs, ebx;               // shots per thread (divides shots_per_model); cell block width
     float *f[EL_NS];           // state fields [shot][plane]
     const float *m[5];         // model fields [model][plane]
     El2Tabs t;
@@ -46,6 +51,7 @@ struct El2Args {
 struct El2AdjArgs {
     Grid2 g;
     int nshots, shots_per_model;
+    int gs, ebx;               // as in El2Args
     float *a[EL_NS];           // adjoint state
     float *tmp[8];             // e1..e4 then d1..d4
     const float *m[5];
@@ -85,7 +91,7 @@ void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s);
 void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s);
 void launch_el2_prep(const Grid2 &g, int nmodels, const float *vp, const float *vs, const float *rho,
                      float *const *model, float *const *phys_pad, hipStream_t s);
-void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, const float *grad, long long grad_stride,
+void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, int gs, const float *grad, long long grad_stride,
                          float *acc, const float *const *model, const float *const *phys_pad,
                          float *g_vp, float *g_vs, float *g_rho, hipStream_t s);
 

@@ -110,12 +110,13 @@ int check_desc(const sg_desc *d)
 // Shot-count limits of the elastic launches: the adjoint passes take the shot
 // (group) as the grid's y index (at most 65535); the forward passes number
 // (cell block, shot group) in a 1-D grid of int work ids, at most
-// el2_cell_blocks * max_shots of them (shot groups of one).
+// el2_cell_blocks * max_shots of them (shot groups of one, either block width).
 int check_shots(const sg_desc *d, int max_shots)
 {
     if (d->physics != SG_ELASTIC) return SG_OK;
     const long long NX = d->nx + 2LL * d->npml, NZ = d->nz + 2LL * d->npml;
-    if (max_shots > 65535 || el2_cell_blocks(EBX_FWD, NX, NZ) * max_shots >= (1LL << 31))
+    const long long nblk = std::max(el2_cell_blocks(32, NX, NZ), el2_cell_blocks(64, NX, NZ));
+    if (max_shots > 65535 || nblk * max_shots >= (1LL << 31))
         return fail(SG_EINVAL, "too many elastic shots (%d) for a %lld x %lld grid", max_shots, NX, NZ);
     return SG_OK;
 }
@@ -169,7 +170,10 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
         Grid3 &g = L.g3;
         g.P = P; g.nx = d->nx; g.ny = d->ny; g.nz = d->nz;
         g.NX = d->nx + 2 * P; g.NY = d->ny + 2 * P; g.NZ = d->nz + 2 * P;
-        g.ntx = (g.NX + TX3 - 1) / TX3; g.nty = (g.NY + TY3 - 1) / TY3; g.nzc = (g.NZ + TZC - 1) / TZC;
+        g.ntx = (g.NX + TX3 - 1) / TX3; g.nty = (g.NY + TY3 - 1) / TY3;
+        g.zcf = TZCF_DEF;
+        g.zca = TZCA_DEF;
+        g.nzc = (g.NZ + g.zca - 1) / g.zca;
         g.SX = OX3 + g.ntx * TX3 + 32;
         g.SY = OY3 + g.nty * TY3 + 4;
         g.SZ = OZ3 + g.NZ + 4;
@@ -208,7 +212,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_soff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
     L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
-    L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * ((L.g3.NZ + TZCI - 1) / TZCI + 2) : 0);
+    L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * ((L.g3.NZ + TZC_MIN - 1) / TZC_MIN + 2) : 0);
     L.off_flag = take(sizeof(int));
     L.total = o;
     return L;
@@ -244,6 +248,12 @@ struct sg_model {
     // 3-D acoustic layer pass: (xy tile, first plane, end plane) work items
     int4 *items3 = nullptr;
     int n_items3 = 0;
+    int zci = 0;                  // planes per layer work item
+    // elastic launch settings: shots per thread (0: el2_group of the shots per
+    // model) and cell block width
+    int el_gs = 0, el_ebx = EBX_DEF;
+    // 2-D acoustic: forward and recompute segments in the CU-resident kernel
+    bool resident = false;
     std::vector<int4> h_items3;
     // 3-D xy tiles, those within the stencil reach of the layer in x or y first
     int *tiles3 = nullptr;
@@ -302,6 +312,36 @@ bool same_geometry(const sg_model *m, const sg_shots *sh)
     return m->geom_nshots == ns && m->geom_nrec == sh->nrec && m->geom_nsrc == nsrc &&
            std::equal(sh->src, sh->src + (size_t)nd * ns * nsrc, m->geom_src.begin()) &&
            (sh->nrec == 0 || std::equal(sh->rec, sh->rec + (size_t)nd * ns * sh->nrec, m->geom_rec.begin()));
+}
+
+// The 3-D layer pass's work list (host copy): every plane of the xy tiles
+// that touch the layer in x or y, the two z slabs of the others, in items of
+// at most zci planes.  Returns nonzero if it would overflow its workspace
+// slot (sized for TZC_MIN-plane items).
+int build_items3(sg_model *m, int zci)
+{
+    const Layout &L = m->L;
+    const Grid3 &g = L.g3;
+    m->h_items3.clear();
+    for (int t = 0; t < L.ntiles; ++t) {
+        const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
+        const bool xy = x0 < g.P || x0 + TX3 > g.P + g.nx || y0 < g.P || y0 + TY3 > g.P + g.ny;
+        auto add = [&](int za, int zb) {
+            for (int z = za; z < zb; z += zci) m->h_items3.push_back(make_int4(t, z, std::min(z + zci, zb), 0));
+        };
+        if (xy) add(0, g.NZ);
+        else { add(0, g.P); add(g.P + g.nz, g.NZ); }
+    }
+    m->n_items3 = (int)m->h_items3.size();
+    m->zci = zci;
+    return (size_t)m->n_items3 > (size_t)L.ntiles * ((g.NZ + TZC_MIN - 1) / TZC_MIN + 2);
+}
+
+// Shots per thread of the elastic passes for spm shots per model: the
+// model's setting if it divides spm, else el2_group(spm).
+int el_group(const sg_model *m, int spm)
+{
+    return m->el_gs > 0 && spm % m->el_gs == 0 ? m->el_gs : el2_group(spm);
 }
 
 int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
@@ -611,6 +651,8 @@ void el_fwd_step(const sg_model *m, int ns, const float *wav, int k, float *seis
     a.g = m->L.g2;
     a.nshots = ns;
     a.shots_per_model = ns / m->d.nmodels;
+    a.gs = el_group(m, a.shots_per_model);
+    a.ebx = m->el_ebx;
     for (int i = 0; i < EL_NS; ++i) a.f[i] = m->fwd[i];
     for (int i = 0; i < 5; ++i) a.m[i] = m->model[i];
     a.t = el_tabs(m);
@@ -642,6 +684,8 @@ void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwa
     a.g = m->L.g2;
     a.nshots = ns;
     a.shots_per_model = ns / m->d.nmodels;
+    a.gs = el_group(m, a.shots_per_model);
+    a.ebx = m->el_ebx;
     for (int i = 0; i < EL_NS; ++i) a.a[i] = m->adj[i];
     for (int i = 0; i < 8; ++i) a.tmp[i] = m->tmp[i];
     for (int i = 0; i < 5; ++i) a.m[i] = m->model[i];
@@ -1265,21 +1309,8 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
         m->h_tiles3.insert(m->h_tiles3.end(), rest.begin(), rest.end());
     }
     if (d->ndim == 3 && d->npml > 0) {
-        // every plane of the xy tiles that touch the layer in x or y; the two
-        // z slabs of the others
-        const Grid3 &g = L.g3;
         m->items3 = reinterpret_cast<int4 *>(m->ws + L.off_items);
-        for (int t = 0; t < L.ntiles; ++t) {
-            const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
-            const bool xy = x0 < g.P || x0 + TX3 > g.P + g.nx || y0 < g.P || y0 + TY3 > g.P + g.ny;
-            auto add = [&](int za, int zb) {
-                for (int z = za; z < zb; z += TZCI) m->h_items3.push_back(make_int4(t, z, std::min(z + TZCI, zb), 0));
-            };
-            if (xy) add(0, g.NZ);
-            else { add(0, g.P); add(g.P + g.nz, g.NZ); }
-        }
-        m->n_items3 = (int)m->h_items3.size();
-        if ((size_t)m->n_items3 > (size_t)L.ntiles * ((g.NZ + TZCI - 1) / TZCI + 2)) {
+        if (build_items3(m, TZCI_DEF)) {
             delete m;
             return fail(SG_EINVAL, "layer work list overflows its buffer");
         }
@@ -1308,6 +1339,40 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     }
     *out = m;
     return SG_OK;
+}
+
+// Steps [k0, k1) of a 2-D acoustic batch in the CU-resident kernel (one
+// workgroup per shot), from the state in the slots of u^{k0}, u^{k0-1} to
+// the slots of u^{k1}, u^{k1-1}; snapshots (if any) from snap, one step
+// every nsnap fields.
+void ac2_resident(const sg_model *m, int ns, const float *wav, int k0, int k1, float *seis, float *snap,
+                  hipStream_t s)
+{
+    Ac2ResArgs a{};
+    a.g = m->L.g2;
+    a.nshots = ns;
+    a.shots_per_model = ns / m->d.nmodels;
+    a.u0 = m->u4[k0 & 3];
+    a.um0 = m->u4[(k0 + 3) & 3];
+    a.u1 = m->u4[k1 & 3];
+    a.um1 = m->u4[(k1 + 3) & 3];
+    a.chat = m->chat;
+    a.phx = m->fwd[2];
+    a.phz = m->fwd[3];
+    a.hx = m->h[0]; a.hz = m->h[2]; a.px = m->p[0]; a.pz = m->p[2]; a.ihx = m->ih[0]; a.ihz = m->ih[2];
+    a.src_f = m->src_f;
+    a.wav = wav;
+    a.nt = m->d.nt;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.src_scale = src_scale(m);
+    a.rec_off = m->rec_off;
+    a.rec_ent = static_cast<const int *>(m->rec_ent);
+    a.seis = seis;
+    a.nrec = m->geom_nrec;
+    a.snap = snap;
+    a.snap_step = (long long)m->L.nsnap * m->L.field;
+    launch_ac2_resident(a, s);
 }
 
 int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckpt, sg_stream_t stream)
@@ -1354,7 +1419,12 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
             }
             span = span_begin(m, 0, std::min(K, nt - k), s);
         }
-        if (ac2) {
+        if (ac2 && m->resident && m->geom_nsrc == 1) {
+            // the whole segment in one launch, one workgroup per shot
+            const int k1 = std::min((k / K + 1) * K, nt);
+            ac2_resident(m, ns, sh->wavelet, k, k1, sp, stored(k), s);
+            k = k1;
+        } else if (ac2) {
             // two steps per launch on the blocked tiles, within one checkpoint segment
             const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < std::min((k / K + 1) * K, nt);
             ac2_forward(m, ns, sh->wavelet, k, two, sp, stored(k), two ? stored(k + 1) : nullptr, s);
@@ -1430,7 +1500,10 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
             int cu = 0;
             span = span_begin(m, 1, k1 - k0, s);
             for (int k = k0; k < k1;) {
-                if (ac2) {
+                if (ac2 && m->resident && m->geom_nsrc == 1) {
+                    ac2_resident(m, ns, sh->wavelet, k0, k1, nullptr, snap(k0), s);
+                    k = k1;
+                } else if (ac2) {
                     const bool two = blk && k + 1 < k1;
                     ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
                     k += two ? 2 : 1;
@@ -1463,7 +1536,8 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         span_end(m, span, s);
     }
     if (L.elastic)
-        launch_el2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, L.field, m->acc, m->model,
+        launch_el2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, el_group(m, ns / m->d.nmodels), m->grad,
+                            L.field, m->acc, m->model,
                             m->model + 5, g_vp, g_vs, g_rho, s);
     else if (ad2)
         launch_ad2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, m->grad, m->acc, m->cpad, m->d.dt, m->d.dx,
@@ -1502,6 +1576,62 @@ int numeric_status(sg_model *m, sg_stream_t stream)
     const int zero = 0;
     HIPCHECK(hipMemcpy(m->numeric_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
     return fail(SG_ENUMERIC, "a misfit on this model was not finite (NaN or Inf in the seismograms)");
+}
+
+int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream)
+{
+    g_err.clear();
+    if (!m) return fail(SG_EINVAL, "model is NULL");
+    const bool three = !m->L.elastic && m->d.ndim == 3;
+    switch (key) {
+    case SG_TUNE_TIME_BLOCKING:
+        return set_time_blocking(m, value);
+    case SG_TUNE_CHUNK_FWD3:
+    case SG_TUNE_CHUNK_ADJ3:
+    case SG_TUNE_CHUNK_LAYER3: {
+        if (!three) return fail(SG_EINVAL, "3-D chunk lengths apply to 3-D acoustic models");
+        if (value < TZC_MIN || value > TZC || value % 8)
+            return fail(SG_EINVAL, "chunk of %d planes outside [%d, %d] or not a multiple of 8", value, TZC_MIN, TZC);
+        Grid3 &g = m->L.g3;
+        if (key == SG_TUNE_CHUNK_FWD3) g.zcf = value;
+        if (key == SG_TUNE_CHUNK_ADJ3) {
+            g.zca = value;
+            g.nzc = (g.NZ + value - 1) / value;
+        }
+        if (key == SG_TUNE_CHUNK_LAYER3 && m->items3 && value != m->zci) {
+            if (build_items3(m, value)) return fail(SG_EINVAL, "layer work list overflows its buffer");
+            // the list is read by launches already enqueued: wait for them first
+            hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+            HIPCHECK(hipStreamSynchronize(s));
+            HIPCHECK(hipMemcpyAsync(m->items3, m->h_items3.data(), sizeof(int4) * m->n_items3,
+                                    hipMemcpyHostToDevice, s));
+            HIPCHECK(hipStreamSynchronize(s));
+        }
+        return SG_OK;
+    }
+    case SG_TUNE_SHOT_GROUP:
+        if (!m->L.elastic) return fail(SG_EINVAL, "shot groups apply to elastic models");
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return fail(SG_EINVAL, "shot group %d: 0 (automatic), 1, 2 or 4", value);
+        m->el_gs = value;
+        return SG_OK;
+    case SG_TUNE_RESIDENT:
+        if (m->L.elastic || m->L.ad2 || m->d.ndim != 2)
+            return fail(SG_EINVAL, "the CU-resident forward applies to the 2-D constant-density acoustic form");
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "resident: 0 or 1");
+        if (value && !resident_fits(m->L.g2))
+            return fail(SG_EINVAL, "a %d x %d padded grid does not fit one CU (at most %d cells, %d LDS floats)",
+                        m->L.g2.NX, m->L.g2.NZ, RES_NTH * RES_NPT, RES_LDS);
+        m->resident = value != 0;
+        return SG_OK;
+    case SG_TUNE_BLOCK_X:
+        if (!m->L.elastic) return fail(SG_EINVAL, "cell block width applies to elastic models");
+        if (value != 32 && value != 64) return fail(SG_EINVAL, "cell block width %d: 32 or 64", value);
+        m->el_ebx = value;
+        return SG_OK;
+    default:
+        return fail(SG_EINVAL, "unknown tuning key %d", key);
+    }
 }
 
 int set_time_blocking(sg_model *m, int32_t steps)

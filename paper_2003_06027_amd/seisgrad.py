@@ -19,13 +19,15 @@ LIB_PATH = os.path.join(HERE, "libseisgrad.so")
 SG_OK, SG_EINVAL, SG_EUNSTABLE, SG_ENOMEM, SG_ESTATE, SG_EDEVICE, SG_EUNSUPPORTED, SG_ENUMERIC = \
     0, -1, -2, -3, -4, -5, -6, -7
 SG_ACOUSTIC, SG_ELASTIC, SG_ACOUSTIC_DIV = 0, 1, 2
+SG_TUNE_TIME_BLOCKING, SG_TUNE_CHUNK_FWD3, SG_TUNE_CHUNK_ADJ3, SG_TUNE_CHUNK_LAYER3, SG_TUNE_SHOT_GROUP, \
+    SG_TUNE_BLOCK_X, SG_TUNE_RESIDENT = 0, 1, 2, 3, 4, 5, 6
 _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_ENOMEM",
           SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED",
           SG_ENUMERIC: "SG_ENUMERIC"}
 
 EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
-           "set_time_blocking", "snapshot_segment_bytes", "numeric_status", "misfit_noalloc", "lbfgs_push", "lbfgs_direction",
+           "set_time_blocking", "set_tuning", "snapshot_segment_bytes", "numeric_status", "misfit_noalloc", "lbfgs_push", "lbfgs_direction",
            "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad",
            "source_plane_wave")
 
@@ -76,6 +78,7 @@ def lib():
         L.set_profiling.argtypes = [C.c_void_p, C.c_int32]
         L.set_time_blocking.argtypes = [C.c_void_p, C.c_int32]
         L.numeric_status.argtypes = [C.c_void_p, C.c_void_p]
+        L.set_tuning.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
         L.misfit_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         v = C.c_void_p
         L.lbfgs_push.argtypes = [C.c_int32, C.c_int64, C.c_int32, v, v, v, v, v, v, v, v, v]
@@ -225,6 +228,12 @@ class Model:
     def set_time_blocking(self, steps):
         """Steps per launch of the 2-D acoustic blocked tiles (1 or 2)."""
         _check(lib().set_time_blocking(self.handle, int(steps)))
+
+    def set_tuning(self, key, value, stream=None):
+        """A launch setting (SG_TUNE_*): 3-D chunk lengths, elastic shot group
+        and cell block width, time blocking.  Results do not depend on it
+        (the elastic shot group only fixes the gradient's summation order)."""
+        _check(lib().set_tuning(self.handle, int(key), int(value), _stream(stream)))
 
     def set_profiling(self, on=True):
         _check(lib().set_profiling(self.handle, int(on)))

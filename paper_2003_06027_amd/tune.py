@@ -1,12 +1,20 @@
-"""Autotuner of the sweep strategy for one workload (grid, shot batch,
+"""Autotuner of the launch strategy for one workload (grid, shot batch,
 physics), with a JSON cache.
 
-Candidates:
-* time blocking, 2-D acoustic only: 1 or 2 steps per launch on the blocked
-  tiles (results are bitwise identical, traffic and launch count differ);
-* launch mode: eager launches, or one hipGraph holding the whole
-  checkpointed forward, misfit and adjoint of the batch, replayed (useful
-  where per-launch overhead dominates: small grids, many short steps).
+Candidates (none changes what is computed; see set_tuning in the C ABI):
+* 2-D acoustic: 1 or 2 steps per launch on the blocked tiles (results are
+  bitwise identical, traffic and launch count differ), each eager or as one
+  hipGraph holding the whole checkpointed forward, misfit and adjoint of the
+  batch, replayed (useful where per-launch overhead dominates: small grids,
+  many short steps); on grids that fit one CU, also the CU-resident forward
+  (a whole checkpoint segment per launch, one workgroup per shot);
+* 3-D acoustic: the z-chunk lengths of the forward tile passes (16-64
+  planes), of the adjoint tile passes (32-64) and of the layer work items
+  (16-64), searched one at a time from the defaults (each moves different
+  kernels);
+* 2-D elastic: shots of one model per thread (4, 2 or 1, those dividing the
+  shots per model) and cell blocks of 32 x 8 or 64 x 4;
+* every physics: eager launches or graph replay.
 
 Each candidate is timed on a shortened run of the same grid and shots (a
 few checkpoint segments; the cost per step does not depend on nt) and the
@@ -34,8 +42,32 @@ GRAPH_MARGIN = 0.02
 
 @dataclasses.dataclass(frozen=True)
 class Strategy:
-    time_blocking: int = 2
+    time_blocking: int = 2     # 2-D acoustic
     graphs: bool = False
+    chunk_fwd3: int = 32       # 3-D acoustic
+    chunk_adj3: int = 64
+    chunk_layer3: int = 32
+    shot_group: int = 0        # elastic (0: the library's rule)
+    block_x: int = 32
+    resident: bool = False     # 2-D acoustic, small grids
+
+    def apply(self, m):
+        """Set the strategy's launch settings on model m (those its physics has)."""
+        d = m.d
+        if d.physics == S.SG_ACOUSTIC and d.ndim == 2:
+            m.set_tuning(S.SG_TUNE_TIME_BLOCKING, self.time_blocking)
+            m.set_tuning(S.SG_TUNE_RESIDENT, int(self.resident))
+        elif d.physics == S.SG_ACOUSTIC and d.ndim == 3:
+            m.set_tuning(S.SG_TUNE_CHUNK_FWD3, self.chunk_fwd3)
+            m.set_tuning(S.SG_TUNE_CHUNK_ADJ3, self.chunk_adj3)
+            m.set_tuning(S.SG_TUNE_CHUNK_LAYER3, self.chunk_layer3)
+        elif d.physics == S.SG_ELASTIC:
+            m.set_tuning(S.SG_TUNE_SHOT_GROUP, self.shot_group)
+            m.set_tuning(S.SG_TUNE_BLOCK_X, self.block_x)
+
+    def label(self):
+        return ",".join(f"{k}={v}" for k, v in dataclasses.asdict(self).items()
+                        if v != getattr(Strategy, k))  or "default"
 
 
 def cache_path():
@@ -51,9 +83,33 @@ def workload_key(d, nshots, nrec):
     return hashlib.sha1(repr(fields).encode()).hexdigest()[:16]
 
 
-def candidates(d):
-    tbs = (2, 1) if (d.ndim == 2 and d.physics == S.SG_ACOUSTIC) else (2,)
-    return [Strategy(tb, g) for tb in tbs for g in (False, True)]
+def candidates(d, nshots=1):
+    """The first round of candidates; 3-D continues with coordinate search."""
+    if d.ndim == 2 and d.physics == S.SG_ACOUSTIC:
+        out = [Strategy(time_blocking=tb, graphs=g) for tb in (2, 1) for g in (False, True)]
+        if resident_fits(d):
+            out += [Strategy(resident=True, graphs=g) for g in (False, True)]
+        return out
+    if d.physics == S.SG_ELASTIC:
+        spm = nshots // d.nmodels
+        groups = [gs for gs in (4, 2, 1) if spm % gs == 0]
+        return [Strategy(shot_group=gs, block_x=bx) for gs in groups for bx in (32, 64)] + [Strategy(graphs=True)]
+    if d.ndim == 3:
+        return [Strategy(chunk_fwd3=c) for c in (16, 32, 48, 64)]
+    return [Strategy(), Strategy(graphs=True)]
+
+
+def resident_fits(d):
+    """The padded 2-D grid fits the CU-resident forward (the limits of
+    set_tuning's resident key: 1024 threads x 24 cells, the field and a
+    4-cell frame in 40960 LDS floats)."""
+    NX, NZ = d.nx + 2 * d.npml, d.nz + 2 * d.npml
+    return NX * NZ <= 1024 * 24 and (NX + 8) * (NZ + 8) <= 40960
+
+
+# 3-D coordinate search after the forward chunk: the adjoint chunk, then the layer items
+CHUNKS_ADJ3 = (32, 48, 64)
+CHUNKS_LAYER3 = (16, 32, 64)
 
 
 class Runner:
@@ -63,7 +119,7 @@ class Runner:
     def __init__(self, d, shots, vp, obs, strategy: Strategy, ckpt=0, vs=None, rho=None):
         self.shots = shots
         self.m = S.Model(d, vp, shots.nshots, shots.nrec, ckpt, vs=vs, rho=rho)
-        self.m.set_time_blocking(strategy.time_blocking)
+        strategy.apply(self.m)
         self.obs = obs
         self.seis = torch.empty_like(obs)
         self.resid = torch.empty_like(obs)
@@ -140,17 +196,34 @@ def tune(d, shots, vp, vs=None, rho=None, ckpt=0, segments=4, cache=None, log=No
     obs = (ref.forward(sh, save_ckpt=False) * 0.9).contiguous()   # any data of the right shape
     ref.close()
     times = {}
-    for c in candidates(d):
-        times[c] = measure(dt, sh, vp, obs, c, ckpt=K, vs=vs, rho=rho)
-        if log:
-            log(f"tune {key}: {c} {times[c] * 1e3:.2f} ms for {nt} steps")
+
+    def run(c):
+        if c not in times:
+            times[c] = measure(dt, sh, vp, obs, c, ckpt=K, vs=vs, rho=rho)
+            if log:
+                log(f"tune {key}: {c.label()} {times[c] * 1e3:.2f} ms for {nt} steps")
+        return times[c]
+
+    for c in candidates(d, shots.nshots):
+        try:
+            run(c)
+        except S.SeisError as e:            # a setting this workload cannot take
+            if log:
+                log(f"tune {key}: {c.label()} skipped ({e})")
+    if d.ndim == 3 and d.physics == S.SG_ACOUSTIC:
+        best = min(times, key=times.get)
+        for field, values in (("chunk_adj3", CHUNKS_ADJ3), ("chunk_layer3", CHUNKS_LAYER3)):
+            for v in values:
+                run(dataclasses.replace(best, **{field: v}))
+            best = min(times, key=times.get)
+        run(dataclasses.replace(best, graphs=True))
     # graph replay only where it beats the best eager candidate by more than 2%
     eager = min((c for c in times if not c.graphs), key=times.get)
     best = min(times, key=times.get)
     if best.graphs and times[best] > (1.0 - GRAPH_MARGIN) * times[eager]:
         best = eager
     table[key] = {"strategy": dataclasses.asdict(best), "nt_measured": nt,
-                  "ms": {f"tb{c.time_blocking}_graphs{int(c.graphs)}": round(t * 1e3, 3) for c, t in times.items()}}
+                  "ms": {c.label(): round(t * 1e3, 3) for c, t in times.items()}}
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     with open(cache + ".tmp", "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)

@@ -71,16 +71,17 @@ def test_size_limits_on_host():
     assert "receivers" in str(e.value)
     assert S.workspace_bytes(S.desc(nx=100, nz=50, npml=10, nt=10), 1, (1 << 20) - 1) > 0
     # elastic: the adjoint passes take the shot as the grid's y index, the
-    # forward passes number their 32 x 8 cell blocks over all shots with an int
+    # forward passes number their cell blocks over all shots with an int
     el = S.desc(physics=S.SG_ELASTIC, nx=100, nz=50, npml=10, nt=10)
     assert S.workspace_bytes(el, 65535, 1) > 0
     with pytest.raises(S.SeisError) as e:
         S.workspace_bytes(el, 65536, 1)
     assert "too many elastic shots" in str(e.value)
-    big = S.desc(physics=S.SG_ELASTIC, nx=20000, nz=20000, nt=10)   # 625 x 2500 blocks per shot
-    assert S.workspace_bytes(big, 1374, 1) > 0
+    # 625 x 2500 blocks of 32 x 8 or 313 x 5000 blocks of 64 x 4 per shot: the larger count bounds
+    big = S.desc(physics=S.SG_ELASTIC, nx=20000, nz=20000, nt=10)
+    assert S.workspace_bytes(big, 1372, 1) > 0
     with pytest.raises(S.SeisError) as e:
-        S.workspace_bytes(big, 1375, 1)
+        S.workspace_bytes(big, 1373, 1)
     assert "too many elastic shots" in str(e.value)
 
 
