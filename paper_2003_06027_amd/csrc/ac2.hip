@@ -692,137 +692,6 @@ void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s)
     ac2_phi_adj_kernel<<<a.ntl * nshots, NTH, 0, s>>>(a);
 }
 
-// ------------------------------------------------------------ CU-resident forward
-// One workgroup per shot marches a run of steps.  Thread t owns the cells
-// t + j RES_NTH (row-major over the padded grid).  Per step: the layer pass
-// on the owned layer cells (phi~^k from u^k in LDS), a barrier, the update of
-// every owned cell (L~ u^k from LDS, the phi terms from global memory on
-// cells of near tiles), a barrier, u^{k+1} into LDS, a barrier, receivers
-// from LDS.  The expressions are those of ac2_phi_kernel and fwd_tile.
-template <bool SNAP>
-__global__ __launch_bounds__(RES_NTH) void ac2_resident_kernel(Ac2ResArgs a)
-{
-    __shared__ float lu[RES_LDS];
-    const Grid2 &g = a.g;
-    const int shot = blockIdx.x, tid = threadIdx.x;
-    const int LW = g.NX + 8, NXg = g.NX;
-    const long long so = (long long)shot * g.plane;
-    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int ncell = g.NX * g.NZ;
-    // c / NX for c < RES_NTH * RES_NPT: multiply-high by ceil(2^32 / NX) is exact there
-    const unsigned magic = (unsigned)((0xffffffffull + NXg) / NXg);
-    auto cell = [&](int j, int &iz, int &ix) {
-        int c = tid + j * RES_NTH;
-        asm volatile("" : "+v"(c));          // recomputed where used, not held across the time loop
-        iz = (int)__umulhi((unsigned)c, magic);
-        ix = c - iz * NXg;
-        return c < ncell;
-    };
-    // zero frame of the LDS field (4 cells around the grid)
-    for (int i = tid; i < LW * (g.NZ + 8); i += RES_NTH) lu[i] = 0.f;
-    __syncthreads();
-    // which owned cells are layer cells and which lie in near tiles (bit j)
-    unsigned lay = 0u, nea = 0u;
-    float um[RES_NPT], un[RES_NPT];
-#pragma unroll
-    for (int j = 0; j < RES_NPT; ++j) {
-        int iz, ix;
-        um[j] = 0.f;
-        if (!cell(j, iz, ix)) continue;
-        if (g.P > 0 && layer_cell_at(g, iz, ix)) lay |= 1u << j;
-        if (near_layer(g, ix / TX * TX, iz / TZ * TZ)) nea |= 1u << j;
-        const long long f = fidx(g, iz, ix);
-        lu[(iz + 4) * LW + ix + 4] = a.u0[so + f];
-        um[j] = a.um0[so + f];
-    }
-    const long long src = a.src_f[shot];
-    const int ntiles = g.ntx * g.ntz;
-    const int *roff = a.rec_off + (long long)shot * (ntiles + 1);
-    float *phx = a.phx + so, *phz = a.phz + so;
-    __syncthreads();
-    for (int k = a.k0; k < a.k1; ++k) {
-        // pass A: phi~^k on the owned layer cells
-        if (lay) {
-#pragma unroll
-            for (int j = 0; j < RES_NPT; ++j) {
-                int iz, ix;
-                if (!(lay >> j & 1u)) continue;
-                cell(j, iz, ix);
-                const long long f = fidx(g, iz, ix);
-                const float *ul = lu + (iz + 4) * LW + ix + 4;
-                const float hx = a.hx[ix], hz = a.hz[iz];
-                const float qx = 2.f * (hz - hx) * a.ihx[ix], qz = 2.f * (hx - hz) * a.ihz[iz];
-                phx[f] = a.px[ix] * phx[f] + qx * d8(ul, 1);
-                phz[f] = a.pz[iz] * phz[f] + qz * d8(ul, (long long)LW);
-            }
-        }
-        if (g.P > 0) __syncthreads();
-        // pass B: u^{k+1} of every owned cell
-        const float sval = a.src_scale * a.wav[(long long)shot * a.nt + k];
-#pragma unroll
-        for (int j = 0; j < RES_NPT; ++j) {
-            int iz, ix;
-            un[j] = 0.f;
-            if (!cell(j, iz, ix)) continue;
-            const long long f = fidx(g, iz, ix);
-            const float *ul = lu + (iz + 4) * LW + ix + 4;
-            const float uc = ul[0];
-            float w = lap8(ul, LW);
-            float v;
-            if (nea >> j & 1u) {
-                w += d8(phx + f, 1) + d8(phz + f, (long long)g.SX);
-                const float hx = a.hx[ix], hz = a.hz[iz];
-                const float alpha = 1.f / (1.f + hx + hz);
-                const float umf = um[j];
-                float inc = (uc - umf) + ((hx + hz) * umf - 4.f * hx * hz * uc) + chat[f] * w;
-                if (f == src) inc += sval;
-                v = alpha * (uc + inc);
-            } else {
-                float inc = fmaf(chat[f], w, uc - um[j]);
-                if (f == src) inc += sval;
-                v = uc + inc;
-            }
-            un[j] = v;
-            um[j] = uc;
-            if constexpr (SNAP) __builtin_nontemporal_store(w, a.snap + (long long)(k - a.k0) * a.snap_step + so + f);
-        }
-        __syncthreads();                      // every read of u^k done
-#pragma unroll
-        for (int j = 0; j < RES_NPT; ++j) {
-            int iz, ix;
-            if (cell(j, iz, ix)) lu[(iz + 4) * LW + ix + 4] = un[j];
-        }
-        __syncthreads();
-        if (a.seis) {
-            float *sk = a.seis + ((long long)shot * a.nt + k) * a.nrec;
-            for (int t = 0; t < ntiles; ++t) {
-                const int tz = t / g.ntx, tx = t - tz * g.ntx;
-                for (int e = roff[t] + tid; e < roff[t + 1]; e += RES_NTH) {
-                    const int ent = a.rec_ent[e], rc = rec_cell(ent);
-                    const int r = rc / TX, cc = rc - r * TX;
-                    sk[rec_id(ent)] = lu[(tz * TZ + r + 4) * LW + tx * TX + cc + 4];
-                }
-            }
-        }
-    }
-    // the state at the end of the run: u^{k1}, u^{k1-1}
-#pragma unroll
-    for (int j = 0; j < RES_NPT; ++j) {
-        int iz, ix;
-        if (!cell(j, iz, ix)) continue;
-        const long long f = so + fidx(g, iz, ix);
-        a.u1[f] = lu[(iz + 4) * LW + ix + 4];
-        a.um1[f] = um[j];
-    }
-}
-
-void launch_ac2_resident(const Ac2ResArgs &a, hipStream_t s)
-{
-    if (a.nshots == 0 || a.k1 <= a.k0) return;
-    if (a.snap) ac2_resident_kernel<true><<<a.nshots, RES_NTH, 0, s>>>(a);
-    else ac2_resident_kernel<false><<<a.nshots, RES_NTH, 0, s>>>(a);
-}
-
 void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s)
 {
     const int nb = (a.tiles ? a.ntl : a.g.ntx * a.g.ntz) * a.nshots;

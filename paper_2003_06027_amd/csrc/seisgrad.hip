@@ -252,8 +252,6 @@ struct sg_model {
     // elastic launch settings: shots per thread (0: el2_group of the shots per
     // model) and cell block width
     int el_gs = 0, el_ebx = EBX_DEF;
-    // 2-D acoustic: forward and recompute segments in the CU-resident kernel
-    bool resident = false;
     std::vector<int4> h_items3;
     // 3-D xy tiles, those within the stencil reach of the layer in x or y first
     int *tiles3 = nullptr;
@@ -1341,40 +1339,6 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     return SG_OK;
 }
 
-// Steps [k0, k1) of a 2-D acoustic batch in the CU-resident kernel (one
-// workgroup per shot), from the state in the slots of u^{k0}, u^{k0-1} to
-// the slots of u^{k1}, u^{k1-1}; snapshots (if any) from snap, one step
-// every nsnap fields.
-void ac2_resident(const sg_model *m, int ns, const float *wav, int k0, int k1, float *seis, float *snap,
-                  hipStream_t s)
-{
-    Ac2ResArgs a{};
-    a.g = m->L.g2;
-    a.nshots = ns;
-    a.shots_per_model = ns / m->d.nmodels;
-    a.u0 = m->u4[k0 & 3];
-    a.um0 = m->u4[(k0 + 3) & 3];
-    a.u1 = m->u4[k1 & 3];
-    a.um1 = m->u4[(k1 + 3) & 3];
-    a.chat = m->chat;
-    a.phx = m->fwd[2];
-    a.phz = m->fwd[3];
-    a.hx = m->h[0]; a.hz = m->h[2]; a.px = m->p[0]; a.pz = m->p[2]; a.ihx = m->ih[0]; a.ihz = m->ih[2];
-    a.src_f = m->src_f;
-    a.wav = wav;
-    a.nt = m->d.nt;
-    a.k0 = k0;
-    a.k1 = k1;
-    a.src_scale = src_scale(m);
-    a.rec_off = m->rec_off;
-    a.rec_ent = static_cast<const int *>(m->rec_ent);
-    a.seis = seis;
-    a.nrec = m->geom_nrec;
-    a.snap = snap;
-    a.snap_step = (long long)m->L.nsnap * m->L.field;
-    launch_ac2_resident(a, s);
-}
-
 int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckpt, sg_stream_t stream)
 {
     g_err.clear();
@@ -1419,12 +1383,7 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
             }
             span = span_begin(m, 0, std::min(K, nt - k), s);
         }
-        if (ac2 && m->resident && m->geom_nsrc == 1) {
-            // the whole segment in one launch, one workgroup per shot
-            const int k1 = std::min((k / K + 1) * K, nt);
-            ac2_resident(m, ns, sh->wavelet, k, k1, sp, stored(k), s);
-            k = k1;
-        } else if (ac2) {
+        if (ac2) {
             // two steps per launch on the blocked tiles, within one checkpoint segment
             const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < std::min((k / K + 1) * K, nt);
             ac2_forward(m, ns, sh->wavelet, k, two, sp, stored(k), two ? stored(k + 1) : nullptr, s);
@@ -1500,10 +1459,7 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
             int cu = 0;
             span = span_begin(m, 1, k1 - k0, s);
             for (int k = k0; k < k1;) {
-                if (ac2 && m->resident && m->geom_nsrc == 1) {
-                    ac2_resident(m, ns, sh->wavelet, k0, k1, nullptr, snap(k0), s);
-                    k = k1;
-                } else if (ac2) {
+                if (ac2) {
                     const bool two = blk && k + 1 < k1;
                     ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
                     k += two ? 2 : 1;
@@ -1614,15 +1570,6 @@ int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream)
         if (value != 0 && value != 1 && value != 2 && value != 4)
             return fail(SG_EINVAL, "shot group %d: 0 (automatic), 1, 2 or 4", value);
         m->el_gs = value;
-        return SG_OK;
-    case SG_TUNE_RESIDENT:
-        if (m->L.elastic || m->L.ad2 || m->d.ndim != 2)
-            return fail(SG_EINVAL, "the CU-resident forward applies to the 2-D constant-density acoustic form");
-        if (value != 0 && value != 1) return fail(SG_EINVAL, "resident: 0 or 1");
-        if (value && !resident_fits(m->L.g2))
-            return fail(SG_EINVAL, "a %d x %d padded grid does not fit one CU (at most %d cells, %d LDS floats)",
-                        m->L.g2.NX, m->L.g2.NZ, RES_NTH * RES_NPT, RES_LDS);
-        m->resident = value != 0;
         return SG_OK;
     case SG_TUNE_BLOCK_X:
         if (!m->L.elastic) return fail(SG_EINVAL, "cell block width applies to elastic models");

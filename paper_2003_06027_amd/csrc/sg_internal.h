@@ -155,41 +155,6 @@ void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s);
 void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s);
 void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s);
 void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s);
-
-// CU-resident forward of small 2-D grids: one workgroup of RES_NTH threads
-// per shot runs the steps [k0, k1) of one checkpoint segment with u^k in LDS
-// and each thread's cells' u^{k-1} and chat in registers; the layer
-// auxiliaries stay in global memory (L2-resident at these sizes).  Every
-// cell gets the arithmetic of the one-step kernels (layer pass, then the
-// near-tile or interior formula of its 64 x 32 tile), so results are those of
-// the batched sweep.
-constexpr int RES_NTH = 1024;
-constexpr int RES_NPT = 24;                 // cells per thread at most
-constexpr int RES_LDS = 40960;              // floats of LDS (160 KiB): (NZ + 8) x (NX + 8)
-__host__ __device__ inline bool resident_fits(const Grid2 &g)
-{
-    return (long long)g.NX * g.NZ <= (long long)RES_NTH * RES_NPT &&
-           (long long)(g.NX + 8) * (g.NZ + 8) <= RES_LDS;
-}
-struct Ac2ResArgs {
-    Grid2 g;
-    int nshots, shots_per_model;
-    const float *u0, *um0;      // u^{k0}, u^{k0-1} [shot][plane]
-    float *u1, *um1;            // out: u^{k1}, u^{k1-1}
-    const float *chat;
-    float *phx, *phz;           // layer auxiliaries, updated in place
-    const float *hx, *hz, *px, *pz, *ihx, *ihz;
-    const long long *src_f;
-    const float *wav;
-    int nt, k0, k1;
-    float src_scale;
-    const int *rec_off, *rec_ent;   // per-tile CSR, as the tile kernels
-    float *seis;                // or null
-    int nrec;
-    float *snap;                // w~ of step k0 (then + snap_step per step), or null
-    long long snap_step;
-};
-void launch_ac2_resident(const Ac2ResArgs &a, hipStream_t s);
 void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s);
 void launch_ac2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx,
                      float *chat, float *cpad, hipStream_t s);

@@ -6,8 +6,7 @@ Candidates (none changes what is computed; see set_tuning in the C ABI):
   bitwise identical, traffic and launch count differ), each eager or as one
   hipGraph holding the whole checkpointed forward, misfit and adjoint of the
   batch, replayed (useful where per-launch overhead dominates: small grids,
-  many short steps); on grids that fit one CU, also the CU-resident forward
-  (a whole checkpoint segment per launch, one workgroup per shot);
+  many short steps);
 * 3-D acoustic: the z-chunk lengths of the forward tile passes (16-64
   planes), of the adjoint tile passes (32-64) and of the layer work items
   (16-64), searched one at a time from the defaults (each moves different
@@ -49,14 +48,12 @@ class Strategy:
     chunk_layer3: int = 32
     shot_group: int = 0        # elastic (0: the library's rule)
     block_x: int = 32
-    resident: bool = False     # 2-D acoustic, small grids
 
     def apply(self, m):
         """Set the strategy's launch settings on model m (those its physics has)."""
         d = m.d
         if d.physics == S.SG_ACOUSTIC and d.ndim == 2:
             m.set_tuning(S.SG_TUNE_TIME_BLOCKING, self.time_blocking)
-            m.set_tuning(S.SG_TUNE_RESIDENT, int(self.resident))
         elif d.physics == S.SG_ACOUSTIC and d.ndim == 3:
             m.set_tuning(S.SG_TUNE_CHUNK_FWD3, self.chunk_fwd3)
             m.set_tuning(S.SG_TUNE_CHUNK_ADJ3, self.chunk_adj3)
@@ -86,10 +83,7 @@ def workload_key(d, nshots, nrec):
 def candidates(d, nshots=1):
     """The first round of candidates; 3-D continues with coordinate search."""
     if d.ndim == 2 and d.physics == S.SG_ACOUSTIC:
-        out = [Strategy(time_blocking=tb, graphs=g) for tb in (2, 1) for g in (False, True)]
-        if resident_fits(d):
-            out += [Strategy(resident=True, graphs=g) for g in (False, True)]
-        return out
+        return [Strategy(time_blocking=tb, graphs=g) for tb in (2, 1) for g in (False, True)]
     if d.physics == S.SG_ELASTIC:
         spm = nshots // d.nmodels
         groups = [gs for gs in (4, 2, 1) if spm % gs == 0]
@@ -97,14 +91,6 @@ def candidates(d, nshots=1):
     if d.ndim == 3:
         return [Strategy(chunk_fwd3=c) for c in (16, 32, 48, 64)]
     return [Strategy(), Strategy(graphs=True)]
-
-
-def resident_fits(d):
-    """The padded 2-D grid fits the CU-resident forward (the limits of
-    set_tuning's resident key: 1024 threads x 24 cells, the field and a
-    4-cell frame in 40960 LDS floats)."""
-    NX, NZ = d.nx + 2 * d.npml, d.nz + 2 * d.npml
-    return NX * NZ <= 1024 * 24 and (NX + 8) * (NZ + 8) <= 40960
 
 
 # 3-D coordinate search after the forward chunk: the adjoint chunk, then the layer items

@@ -56,7 +56,7 @@ def test_tuner_measures_once_then_reads_its_cache(tmp_path, monkeypatch):
     table = json.load(open(cache))
     (entry,) = table.values()
     assert entry["strategy"] == dataclasses.asdict(best)
-    assert len(entry["ms"]) == 6           # 1 or 2 steps per launch, or resident; eager or graph
+    assert len(entry["ms"]) == 4           # 1 or 2 steps per launch, eager or graph
     monkeypatch.setattr(tune, "measure", lambda *a, **k: (_ for _ in ()).throw(AssertionError("re-measured")))
     assert tune.tune(d, sh, vp, cache=cache) == best
 
