@@ -12,10 +12,15 @@
 //     u^{k+1} = alpha (beta u^k - gamma u^{k-1} + chat w~^k + dt^2 f^k)
 // with alpha = 1/(1+h_x+h_z), beta = 2 - 4 h_x h_z, gamma = 1 - h_x - h_z
 // (1, 2, 1 in the interior).  The stored state after step k is
-// (u^{k+1}, u^k, phi~^k).  Pass A reads phi~^{k-1} only at its own cell, so
-// phi is updated in place; outside the layer phi~ stays exactly zero.
-// Pass B tiles more than 4 cells from the layer skip the phi terms and the
-// damping coefficients ("interior" tiles); the others ("near" tiles) add them.
+// (u^{k+1}, u^k, phi~^k); outside the layer phi~ stays exactly zero.
+// Tiles more than 4 cells from the layer ("interior" tiles) skip the phi
+// terms and the damping coefficients.  The others ("near" tiles) run pass A
+// themselves on the tile + 4, from u^k on the tile + 8 in LDS, then pass B
+// from LDS: phi~^k of a cell is then computed by its own tile and by the
+// neighbours whose ring covers it (the same expression, the same value),
+// and written by its own tile only, into the other buffer of a pair
+// (phi~^{k-1} and phi~^k live in different buffers, so a neighbour that
+// still reads phi~^{k-1} of the cell is not disturbed).
 //
 // Adjoint step k (Eq. (4): lambda_k = A^T lambda_{k+1} + residual; Eq. (5)
 // for the gradient), in the alpha-scaled variable s = alpha * dJ/du and the
@@ -27,7 +32,9 @@
 //     a^{k+1} = R^T dJ/dd^{k+1} - D~_x c_x^{k+1} - D~_z c_z^{k+1}
 //               + beta s^{k+2} + L~(chat s^{k+2}) - gamma s^{k+3}
 //     s^{k+1} = alpha a^{k+1};   dJ/dchat += s^{k+1} w~^k
-// using L~^T = L~ and D~^T = -D~ (zero cells beyond the grid).
+// using L~^T = L~ and D~^T = -D~ (zero cells beyond the grid).  Near tiles
+// fold pass A in as in the forward step (chat s^{k+2} on the tile + 8 in
+// LDS; c^{k+2} and c^{k+1} in the two buffers of a pair).
 //
 // Cache policy: an operand that only its own cell reads or writes in a step
 // (u^{k-1} and s^{k+3} in the one-step kernels, the new wavefields, the
@@ -123,47 +130,6 @@ __device__ __forceinline__ void load_halo(const Grid2 &g, float *lds, int x0, in
     }
 }
 
-// Map linear index i over the layer cells of one shot to (iz, ix): the top
-// strip (P full rows), the bottom strip, then the left/right strips of the
-// physical rows, each traversed row by row.
-__device__ __forceinline__ void layer_cell(const Grid2 &g, long long i, int &iz, int &ix)
-{
-    const long long strip = (long long)g.P * g.NX;
-    if (i < 2 * strip) {
-        const int top = i < strip;
-        const long long j = top ? i : i - strip;
-        iz = (int)(j / g.NX);
-        ix = (int)(j - (long long)iz * g.NX);
-        if (!top) iz += g.P + g.nz;
-    } else {
-        const long long j = i - 2 * strip;
-        const int row = (int)(j / (2 * g.P)), col = (int)(j - (long long)row * 2 * g.P);
-        iz = g.P + row;
-        ix = col < g.P ? col : col + g.nx;
-    }
-}
-
-// ------------------------------------------------------------ forward pass A
-// Strip order over the layer cells, one thread per cell, stencil points read
-// directly (measured faster than staging tiles for this one-operand pass).
-__global__ __launch_bounds__(256) void ac2_phi_kernel(Ac2PhiArgs a)
-{
-    const Grid2 &g = a.g;
-    const int shot = blockIdx.y;
-    const long long so = (long long)shot * g.plane;
-    const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
-    const float *u = a.u + so;
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < ncell; i += (long long)gridDim.x * 256) {
-        int iz, ix;
-        layer_cell(g, i, iz, ix);
-        const long long f = fidx(g, iz, ix);
-        const float hx = a.hx[ix], hz = a.hz[iz];
-        const float qx = 2.f * (hz - hx) * a.ihx[ix], qz = 2.f * (hx - hz) * a.ihz[iz];
-        a.phx[so + f] = a.px[ix] * a.phx[so + f] + qx * d8(u + f, 1);
-        a.phz[so + f] = a.pz[iz] * a.phz[so + f] + qz * d8(u + f, (long long)g.SX);
-    }
-}
-
 // A layer cell of the padded grid.
 __device__ __forceinline__ bool layer_cell_at(const Grid2 &g, int iz, int ix)
 {
@@ -203,7 +169,8 @@ void launch_ac2_src_gather(int nshots, int nsrc, long long plane, const long lon
 }
 
 // ------------------------------------------------------------ forward pass B
-template <bool NEAR, bool SNAP, bool REC>
+// A tile away from the layer (the interior update), u^k with a 4-cell halo in LDS.
+template <bool SNAP, bool REC>
 __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int tile, int shot)
 {
     constexpr int H = 4, W = TX + 2 * H;
@@ -238,25 +205,11 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
         float w = lap8(su + (r + H) * W + lx + H, W);
         un[j] = 0.f;
         if (iz < g.NZ && ix < g.NX) {
-            float v;
-            if constexpr (NEAR) {
-                w += d8(a.phx + so + f, 1) + d8(a.phz + so + f, (long long)g.SX);
-                const float hx = a.hx[ix], hz = a.hz[iz];
-                // alpha (beta u - gamma um + chat w + src) with
-                // beta u - gamma um = u + (u - um) + (hx + hz) um - 4 hx hz u
-                const float alpha = 1.f / (1.f + hx + hz);
-                const float umf = __builtin_nontemporal_load(um + f);
-                float inc = (uc[j] - umf) + ((hx + hz) * umf - 4.f * hx * hz * uc[j]) + chat[f] * w;
-                if (f == src) inc += sval;
-                if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
-                v = alpha * (uc[j] + inc);
-            } else {
-                // 2u - um + chat w = u + ((u - um) + chat w)
-                float inc = fmaf(chat[f], w, uc[j] - __builtin_nontemporal_load(um + f));
-                if (f == src) inc += sval;
-                if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
-                v = uc[j] + inc;
-            }
+            // 2u - um + chat w = u + ((u - um) + chat w)
+            float inc = fmaf(chat[f], w, uc[j] - __builtin_nontemporal_load(um + f));
+            if (f == src) inc += sval;
+            if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
+            const float v = uc[j] + inc;
             __builtin_nontemporal_store(v, uo + f);
             un[j] = v;
             if constexpr (SNAP) __builtin_nontemporal_store(w, a.snap + so + f);
@@ -282,59 +235,18 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
     }
 }
 
+// One forward step on a list of tiles away from the layer.
 template <bool SNAP, bool REC>
 __global__ __launch_bounds__(NTH) void ac2_fwd_kernel(Ac2FwdArgs a)
 {
     __shared__ float su[(TZ + 8) * (TX + 8)];
-    const int ntl = a.tiles ? a.ntl : a.g.ntx * a.g.ntz;
-    const int w = xcd_work_id(ntl * a.nshots);
-    const int shot = w / ntl, ti = w - shot * ntl;
-    const int tile = a.tiles ? a.tiles[ti] : ti;
-    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
-    if (near_layer(a.g, tx * TX, tz * TZ)) fwd_tile<true, SNAP, REC>(a, su, tile, shot);
-    else                                    fwd_tile<false, SNAP, REC>(a, su, tile, shot);
-}
-
-// ------------------------------------------------------------ adjoint pass A
-// Over the tiles that hold layer cells: chat s^{k+2} with a 4-cell halo in
-// LDS (two operands per stencil point make direct reads twice as costly as
-// in the forward pass), then the layer adjoint at the tile's layer cells.
-__global__ __launch_bounds__(NTH) void ac2_phi_adj_kernel(Ac2PhiAdjArgs a)
-{
-    constexpr int H = 4, W = TX + 2 * H;
-    __shared__ float sc[(TZ + 8) * (TX + 8)];
-    const Grid2 &g = a.g;
-    const int w = xcd_work_id((int)gridDim.x);
-    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
-    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
-    const int x0 = tx * TX, z0 = tz * TZ;
-    const long long so = (long long)shot * g.plane;
-    const float *s2 = a.s2 + so;
-    const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, ix = x0 + lx;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j;
-        const long long f = fidx(g, z0 + r, ix);
-        sc[(r + H) * W + lx + H] = chat[f] * s2[f];
-    }
-    load_halo(g, sc, x0, z0, [&](long long f) { return chat[f] * s2[f]; });
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j, iz = z0 + r;
-        if (iz >= g.NZ || ix >= g.NX || !layer_cell_at(g, iz, ix)) continue;
-        const long long f = so + fidx(g, iz, ix);
-        const float *c = sc + (r + H) * W + lx + H;
-        const float hx = a.hx[ix], hz = a.hz[iz];
-        const float qx = 2.f * (hz - hx) * a.ihx[ix], qz = 2.f * (hx - hz) * a.ihz[iz];
-        a.cx[f] = a.px[ix] * a.cx[f] - qx * d8(c, 1);
-        a.cz[f] = a.pz[iz] * a.cz[f] - qz * d8(c, (long long)W);
-    }
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl;
+    fwd_tile<SNAP, REC>(a, su, a.tiles[w - shot * a.ntl], shot);
 }
 
 // ------------------------------------------------------------ adjoint pass B
-template <bool NEAR>
+// A tile away from the layer, chat s^{k+2} with a 4-cell halo in LDS.
 __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int tile, int shot)
 {
     constexpr int H = 4, W = TX + 2 * H;
@@ -367,14 +279,7 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
         float v = lap8(sc + (r + H) * W + lx + H, W);
         if (iz < g.NZ && ix < g.NX) {
             const long long f = fidx(g, iz, ix);
-            if constexpr (NEAR) {
-                v -= d8(a.cx + so + f, 1) + d8(a.cz + so + f, (long long)g.SX);
-                const float hx = a.hx[ix], hz = a.hz[iz];
-                const float s3f = __builtin_nontemporal_load(s3 + f);
-                v += sc2[j] + ((sc2[j] - s3f) + ((hx + hz) * s3f - 4.f * hx * hz * sc2[j]));
-            } else {
-                v += sc2[j] + (sc2[j] - __builtin_nontemporal_load(s3 + f));
-            }
+            v += sc2[j] + (sc2[j] - __builtin_nontemporal_load(s3 + f));
         }
         av[j] = v;
     }
@@ -409,8 +314,7 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
         const int r = ly * RPT + j, iz = z0 + r;
         if (iz < g.NZ && ix < g.NX) {
             const long long f = fidx(g, iz, ix);
-            float s1 = av[j];
-            if constexpr (NEAR) s1 = s1 / (1.f + a.hx[ix] + a.hz[iz]);
+            const float s1 = av[j];
             __builtin_nontemporal_store(s1, s1o + f);
             __builtin_nontemporal_store(fmaf(s1, __builtin_nontemporal_load(a.snap + so + f), __builtin_nontemporal_load(a.grad + so + f)), a.grad + so + f);
             if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
@@ -423,13 +327,9 @@ __device__ __forceinline__ void adj_tile(const Ac2AdjArgs &a, float *sc, int til
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8))) void ac2_adj_kernel(Ac2AdjArgs a)
 {
     __shared__ float sc[(TZ + 8) * (TX + 8)];
-    const int ntl = a.tiles ? a.ntl : a.g.ntx * a.g.ntz;
-    const int w = xcd_work_id(ntl * a.nshots);
-    const int shot = w / ntl, ti = w - shot * ntl;
-    const int tile = a.tiles ? a.tiles[ti] : ti;
-    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
-    if (near_layer(a.g, tx * TX, tz * TZ)) adj_tile<true>(a, sc, tile, shot);
-    else                                    adj_tile<false>(a, sc, tile, shot);
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl;
+    adj_tile(a, sc, a.tiles[w - shot * a.ntl], shot);
 }
 
 // ---------------------------------------------------------- two-step kernels
@@ -659,6 +559,373 @@ __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
     }
 }
 
+// ---------------------------------------------------------------- near tiles
+// The tiles of the one-step list (near the layer, or holding receivers or
+// several-node sources) with pass A folded in.  LDS: the stepped field on
+// the tile + 8 (as the blocked kernels stage it), the x auxiliary on the
+// tile's rows x the tile + 4 columns, the z auxiliary on the tile + 4 rows x
+// the tile's columns.  Tiles of the list that are not near the layer take
+// the interior update on the first part of the field array.  Every value is
+// formed by the same expression as in separate passes, so results do not
+// depend on which tile computes a ring cell.
+constexpr int WPX = TX + 8;      // x auxiliary: columns x0 - 4 .. x0 + TX + 3
+constexpr int RPZ = TZ + 8;      // z auxiliary: rows z0 - 4 .. z0 + TZ + 3
+constexpr int NU = R0 * W0;      // the field on the tile + 8
+static_assert(NU >= (TZ + 8) * (TX + 8), "the interior update fits the field array");
+
+// Halo cells of the auxiliaries' LDS arrays: the 4 + 4 columns of the x
+// array beside the tile (TZ x 8, one per thread) and the 4 + 4 rows of the z
+// array above and below it (8 x TX, two per thread).
+constexpr int NHX = TZ * 8, NHZ = 8 * TX;
+static_assert(NHX == NTH && NHZ == 2 * NTH, "one x and two z halo cells per thread");
+
+__device__ __forceinline__ void halo_x_cell(int i, int &r, int &c)
+{
+    r = i >> 3;
+    const int cc = i & 7;
+    c = cc < 4 ? cc : cc + TX;           // column of the x array (x0 - 4 + c)
+}
+
+__device__ __forceinline__ void halo_z_cell(int i, int &r, int &c)
+{
+    const int rr = i / TX;
+    c = i - rr * TX;
+    r = rr < 4 ? rr : rr + TZ;           // row of the z array (z0 - 4 + r)
+}
+
+template <bool SNAP, bool REC>
+__device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, float *sx, float *sz, int tile,
+                                              int shot)
+{
+    const Grid2 &g = a.g;
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
+    const long long so = (long long)shot * g.plane;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int ix = x0 + lx;
+    const bool inx = ix < g.NX;
+    const float *__restrict__ chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const float *__restrict__ um = a.um + so;
+    const float *__restrict__ phx0 = a.phx0 + so;
+    const float *__restrict__ phz0 = a.phz0 + so;
+    float *__restrict__ phx = a.phx + so;
+    float *__restrict__ phz = a.phz + so;
+
+    // operands of the own cells and of the halo cells first (none depends on LDS)
+    const float hxc = inx ? a.hx[ix] : 0.f, pxc = inx ? a.px[ix] : 0.f, ihxc = inx ? a.ihx[ix] : 0.f;
+    float ch[RPT], pm[RPT], hzr[RPT], fx[RPT], fz[RPT];
+    unsigned lay = 0u;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int iz = z0 + ly * RPT + j;
+        const long long f = fidx(g, iz, ix);
+        ch[j] = pm[j] = hzr[j] = fx[j] = fz[j] = 0.f;
+        if (iz < g.NZ && inx) {
+            ch[j] = chat[f];
+            pm[j] = __builtin_nontemporal_load(um + f);
+            hzr[j] = a.hz[iz];
+            if (layer_cell_at(g, iz, ix)) {
+                lay |= 1u << j;
+                fx[j] = phx0[f];
+                fz[j] = phz0[f];
+            }
+        }
+    }
+    // x halo: one cell per thread
+    int hr, hc;
+    halo_x_cell(tid, hr, hc);
+    const int hxz = z0 + hr, hxx = x0 - 4 + hc;
+    const bool hxl = hxz < g.NZ && hxx >= 0 && hxx < g.NX && layer_cell_at(g, hxz, hxx);
+    float hx_h = 0.f, hz_h = 0.f, p_h = 0.f, ih_h = 0.f, f_h = 0.f;
+    if (hxl) {
+        hx_h = a.hx[hxx]; hz_h = a.hz[hxz]; p_h = a.px[hxx]; ih_h = a.ihx[hxx];
+        f_h = phx0[fidx(g, hxz, hxx)];
+    }
+    // z halo: two cells per thread
+    float zhx[2], zhz[2], zp[2], zih[2], zf[2];
+    bool zl[2];
+    int zr[2], zc[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        halo_z_cell(tid + it * NTH, zr[it], zc[it]);
+        const int iz = z0 - 4 + zr[it], jx = x0 + zc[it];
+        zl[it] = iz >= 0 && iz < g.NZ && jx < g.NX && layer_cell_at(g, iz, jx);
+        zhx[it] = zhz[it] = zp[it] = zih[it] = zf[it] = 0.f;
+        if (zl[it]) {
+            zhx[it] = a.hx[jx]; zhz[it] = a.hz[iz]; zp[it] = a.pz[iz]; zih[it] = a.ihz[iz];
+            zf[it] = phz0[fidx(g, iz, jx)];
+        }
+    }
+    load_tile8(g, a.u + so, nullptr, su, x0, z0);      // u^k on the tile + 8
+    __syncthreads();
+
+    // pass A: phi~^k on the own layer cells (written out) and the halo cells
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        float vx = 0.f, vz = 0.f;
+        if (lay >> j & 1u) {
+            const int iz = z0 + r;
+            const long long f = fidx(g, iz, ix);
+            const float *cu = su + (r + H2) * W0 + lx + H2;
+            const float qx = 2.f * (hzr[j] - hxc) * ihxc;
+            const float qz = 2.f * (hxc - hzr[j]) * a.ihz[iz];
+            vx = pxc * fx[j] + qx * d8(cu, 1);
+            vz = a.pz[iz] * fz[j] + qz * d8(cu, (long long)W0);
+            phx[f] = vx;
+            phz[f] = vz;
+        }
+        sx[r * WPX + lx + 4] = vx;
+        sz[(r + 4) * TX + lx] = vz;
+    }
+    {
+        float v = 0.f;
+        if (hxl) {
+            const float qx = 2.f * (hz_h - hx_h) * ih_h;
+            v = p_h * f_h + qx * d8(su + (hr + H2) * W0 + hc + 4, 1);
+        }
+        sx[hr * WPX + hc] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        float v = 0.f;
+        if (zl[it]) {
+            const float qz = 2.f * (zhx[it] - zhz[it]) * zih[it];
+            v = zp[it] * zf[it] + qz * d8(su + (zr[it] + 4) * W0 + zc[it] + H2, (long long)W0);
+        }
+        sz[zr[it] * TX + zc[it]] = v;
+    }
+    __syncthreads();
+
+    // pass B on the tile
+    float *uo = a.un + so;
+    const long long src = a.src_f[shot];
+    const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
+    float un[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j, iz = z0 + r;
+        const float *cu = su + (r + H2) * W0 + lx + H2;
+        const float uc = cu[0];
+        float w = lap8(cu, W0);
+        un[j] = 0.f;
+        if (iz < g.NZ && inx) {
+            const long long f = fidx(g, iz, ix);
+            w += d8(sx + r * WPX + lx + 4, 1) + d8(sz + (r + 4) * TX + lx, (long long)TX);
+            const float hx = hxc, hz = hzr[j];
+            // alpha (beta u - gamma um + chat w + src) with
+            // beta u - gamma um = u + (u - um) + (hx + hz) um - 4 hx hz u
+            const float alpha = 1.f / (1.f + hx + hz);
+            const float umf = pm[j];
+            float inc = (uc - umf) + ((hx + hz) * umf - 4.f * hx * hz * uc) + ch[j] * w;
+            if (f == src) inc += sval;
+            if (a.nsrc > 1) inc += node_sources(a, tile, shot, r * TX + lx);
+            const float v = alpha * (uc + inc);
+            __builtin_nontemporal_store(v, uo + f);
+            un[j] = v;
+            if constexpr (SNAP) __builtin_nontemporal_store(w, a.snap + so + f);
+        }
+    }
+
+    if constexpr (REC) {
+        const int ntiles = g.ntx * g.ntz;
+        const int *off = a.rec_off + (long long)shot * (ntiles + 1);
+        const int b = off[tile], e = off[tile + 1];
+        if (b < e) {                      // uniform over the block
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) su[(ly * RPT + j + H2) * W0 + lx + H2] = un[j];
+            __syncthreads();
+            for (int i = b + tid; i < e; i += NTH) {
+                const int ent = a.rec_ent[i];
+                const int cell = rec_cell(ent);
+                const int r = cell / TX, c = cell - r * TX;
+                a.seis[((long long)shot * a.nt + a.k) * a.nrec + rec_id(ent)] = su[(r + H2) * W0 + c + H2];
+            }
+        }
+    }
+}
+
+template <bool SNAP, bool REC>
+__global__ __launch_bounds__(NTH) void ac2_near_kernel(Ac2FwdArgs a)
+{
+    __shared__ float su[NU];
+    __shared__ float sx[TZ * WPX];
+    __shared__ float sz[RPZ * TX];
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
+    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
+    if (near_layer(a.g, tx * TX, tz * TZ)) fwd_near_tile<SNAP, REC>(a, su, sx, sz, tile, shot);
+    else                                    fwd_tile<SNAP, REC>(a, su, tile, shot);
+}
+
+__device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, float *sx, float *sz, int tile,
+                                              int shot)
+{
+    const Grid2 &g = a.g;
+    const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
+    const int x0 = tx * TX, z0 = tz * TZ;
+    const long long so = (long long)shot * g.plane;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int ix = x0 + lx;
+    const bool inx = ix < g.NX;
+    const float *__restrict__ s2 = a.s2 + so;
+    const float *__restrict__ s3 = a.s3 + so;
+    const float *__restrict__ chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
+    const float *__restrict__ cx0 = a.cx0 + so;
+    const float *__restrict__ cz0 = a.cz0 + so;
+    float *__restrict__ cxo = a.cx + so;
+    float *__restrict__ czo = a.cz + so;
+
+    const float hxc = inx ? a.hx[ix] : 0.f, pxc = inx ? a.px[ix] : 0.f, ihxc = inx ? a.ihx[ix] : 0.f;
+    float sc2[RPT], q3[RPT], hzr[RPT], fx[RPT], fz[RPT];
+    unsigned lay = 0u;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int iz = z0 + ly * RPT + j;
+        const long long f = fidx(g, iz, ix);
+        sc2[j] = s2[f];
+        q3[j] = hzr[j] = fx[j] = fz[j] = 0.f;
+        if (iz < g.NZ && inx) {
+            q3[j] = __builtin_nontemporal_load(s3 + f);
+            hzr[j] = a.hz[iz];
+            if (layer_cell_at(g, iz, ix)) {
+                lay |= 1u << j;
+                fx[j] = cx0[f];
+                fz[j] = cz0[f];
+            }
+        }
+    }
+    int hr, hc;
+    halo_x_cell(tid, hr, hc);
+    const int hxz = z0 + hr, hxx = x0 - 4 + hc;
+    const bool hxl = hxz < g.NZ && hxx >= 0 && hxx < g.NX && layer_cell_at(g, hxz, hxx);
+    float hx_h = 0.f, hz_h = 0.f, p_h = 0.f, ih_h = 0.f, f_h = 0.f;
+    if (hxl) {
+        hx_h = a.hx[hxx]; hz_h = a.hz[hxz]; p_h = a.px[hxx]; ih_h = a.ihx[hxx];
+        f_h = cx0[fidx(g, hxz, hxx)];
+    }
+    float zhx[2], zhz[2], zp[2], zih[2], zf[2];
+    bool zl[2];
+    int zr[2], zc[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        halo_z_cell(tid + it * NTH, zr[it], zc[it]);
+        const int iz = z0 - 4 + zr[it], jx = x0 + zc[it];
+        zl[it] = iz >= 0 && iz < g.NZ && jx < g.NX && layer_cell_at(g, iz, jx);
+        zhx[it] = zhz[it] = zp[it] = zih[it] = zf[it] = 0.f;
+        if (zl[it]) {
+            zhx[it] = a.hx[jx]; zhz[it] = a.hz[iz]; zp[it] = a.pz[iz]; zih[it] = a.ihz[iz];
+            zf[it] = cz0[fidx(g, iz, jx)];
+        }
+    }
+    load_tile8(g, s2, chat, sc, x0, z0);      // chat s^{k+2} on the tile + 8
+    __syncthreads();
+
+    // pass A: c^{k+1} on the own layer cells (written out) and the halo cells
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j;
+        float vx = 0.f, vz = 0.f;
+        if (lay >> j & 1u) {
+            const int iz = z0 + r;
+            const long long f = fidx(g, iz, ix);
+            const float *cc = sc + (r + H2) * W0 + lx + H2;
+            const float qx = 2.f * (hzr[j] - hxc) * ihxc;
+            const float qz = 2.f * (hxc - hzr[j]) * a.ihz[iz];
+            vx = pxc * fx[j] - qx * d8(cc, 1);
+            vz = a.pz[iz] * fz[j] - qz * d8(cc, (long long)W0);
+            cxo[f] = vx;
+            czo[f] = vz;
+        }
+        sx[r * WPX + lx + 4] = vx;
+        sz[(r + 4) * TX + lx] = vz;
+    }
+    {
+        float v = 0.f;
+        if (hxl) {
+            const float qx = 2.f * (hz_h - hx_h) * ih_h;
+            v = p_h * f_h - qx * d8(sc + (hr + H2) * W0 + hc + 4, 1);
+        }
+        sx[hr * WPX + hc] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        float v = 0.f;
+        if (zl[it]) {
+            const float qz = 2.f * (zhx[it] - zhz[it]) * zih[it];
+            v = zp[it] * zf[it] - qz * d8(sc + (zr[it] + 4) * W0 + zc[it] + H2, (long long)W0);
+        }
+        sz[zr[it] * TX + zc[it]] = v;
+    }
+    __syncthreads();
+
+    // pass B on the tile
+    float *s1o = a.s1 + so;
+    float av[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j, iz = z0 + r;
+        float v = lap8(sc + (r + H2) * W0 + lx + H2, W0);
+        if (iz < g.NZ && inx) {
+            v -= d8(sx + r * WPX + lx + 4, 1) + d8(sz + (r + 4) * TX + lx, (long long)TX);
+            const float hx = hxc, hz = hzr[j];
+            const float s3f = q3[j];
+            v += sc2[j] + ((sc2[j] - s3f) + ((hx + hz) * s3f - 4.f * hx * hz * sc2[j]));
+        }
+        av[j] = v;
+    }
+
+    {   // receiver residual injection R^T dJ/dd^{k+1}, deterministic per cell
+        const int ntiles = g.ntx * g.ntz;
+        const int *off = a.rec_off + (long long)shot * (ntiles + 1);
+        const int b = off[tile], e = off[tile + 1];
+        if (b < e) {
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) sc[(ly * RPT + j + H2) * W0 + lx + H2] = av[j];
+            __syncthreads();
+            const float *d = a.dJdd + ((long long)shot * a.nt + a.k) * a.nrec;
+            for (int i = b + tid; i < e; i += NTH) {
+                const int cell = rec_cell(a.rec_ent[i]);
+                if (i > b && rec_cell(a.rec_ent[i - 1]) == cell) continue;  // not first of its cell
+                float sum = 0.f;
+                for (int m = i; m < e && rec_cell(a.rec_ent[m]) == cell; ++m) sum += d[rec_id(a.rec_ent[m])];
+                const int r = cell / TX, c = cell - r * TX;
+                sc[(r + H2) * W0 + c + H2] += sum;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) av[j] = sc[(ly * RPT + j + H2) * W0 + lx + H2];
+        }
+    }
+
+    const long long src = a.src_f[shot];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = ly * RPT + j, iz = z0 + r;
+        if (iz < g.NZ && inx) {
+            const long long f = fidx(g, iz, ix);
+            const float s1 = av[j] / (1.f + hxc + hzr[j]);
+            __builtin_nontemporal_store(s1, s1o + f);
+            __builtin_nontemporal_store(fmaf(s1, __builtin_nontemporal_load(a.snap + so + f), __builtin_nontemporal_load(a.grad + so + f)), a.grad + so + f);
+            if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
+        }
+    }
+}
+
+__global__ __launch_bounds__(NTH) void ac2_adj_near_kernel(Ac2AdjArgs a)
+{
+    __shared__ float sc[NU];
+    __shared__ float sx[TZ * WPX];
+    __shared__ float sz[RPZ * TX];
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
+    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
+    if (near_layer(a.g, tx * TX, tz * TZ)) adj_near_tile(a, sc, sx, sz, tile, shot);
+    else                                    adj_tile(a, sc, tile, shot);
+}
+
 // ------------------------------------------------------------------ launchers
 void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s)
 {
@@ -674,38 +941,26 @@ void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s)
     ac2_adj2_kernel<<<nb, NTH, 0, s>>>(a);
 }
 
-static int layer_blocks(const Grid2 &g)
+void launch_ac2_fwd(const Ac2FwdArgs &a, bool near, hipStream_t s)
 {
-    const long long ncell = (long long)g.NX * g.NZ - (long long)g.nx * g.nz;
-    return (int)std::min<long long>(std::max<long long>((ncell + 255) / 256, 1), 4096);
-}
-
-void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s)
-{
-    if (a.g.P == 0 || nshots == 0) return;
-    ac2_phi_kernel<<<dim3(layer_blocks(a.g), nshots), 256, 0, s>>>(a);
-}
-
-void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s)
-{
-    if (a.g.P == 0 || nshots == 0 || a.ntl == 0) return;
-    ac2_phi_adj_kernel<<<a.ntl * nshots, NTH, 0, s>>>(a);
-}
-
-void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s)
-{
-    const int nb = (a.tiles ? a.ntl : a.g.ntx * a.g.ntz) * a.nshots;
+    const int nb = a.ntl * a.nshots;
     if (nb == 0) return;
     const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
-    if (snap) { if (rec) ac2_fwd_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
-    else      { if (rec) ac2_fwd_kernel<false, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<false, false><<<nb, NTH, 0, s>>>(a); }
+    if (near) {
+        if (snap) { if (rec) ac2_near_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_near_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
+        else      { if (rec) ac2_near_kernel<false, true><<<nb, NTH, 0, s>>>(a); else ac2_near_kernel<false, false><<<nb, NTH, 0, s>>>(a); }
+    } else {
+        if (snap) { if (rec) ac2_fwd_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
+        else      { if (rec) ac2_fwd_kernel<false, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<false, false><<<nb, NTH, 0, s>>>(a); }
+    }
 }
 
-void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s)
+void launch_ac2_adj(const Ac2AdjArgs &a, bool near, hipStream_t s)
 {
-    const int nb = (a.tiles ? a.ntl : a.g.ntx * a.g.ntz) * a.nshots;
+    const int nb = a.ntl * a.nshots;
     if (nb == 0) return;
-    ac2_adj_kernel<<<nb, NTH, 0, s>>>(a);
+    if (near) ac2_adj_near_kernel<<<nb, NTH, 0, s>>>(a);
+    else      ac2_adj_kernel<<<nb, NTH, 0, s>>>(a);
 }
 
 // ---------------------------------------------------------------- model prep

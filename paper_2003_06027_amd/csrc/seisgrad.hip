@@ -68,7 +68,8 @@ struct Layout {
     bool elastic;
     bool ad2;          // 2-D acoustic in divergence form (staggered grid, CPML)
     int nsnap, ngrad, nmod; // snapshot fields per step, gradient accumulators, model fields
-    int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots)
+    int nxs;           // extra wavefield slots (2-D acoustic: u and s rotate over 4 slots, the layer
+                       // auxiliaries over 2 pairs)
     size_t off_chat, off_cpad, off_tab, off_fwd, off_adj, off_ckpt, off_snap,
         off_grad, off_src, off_recoff, off_recent, off_part, off_tmp, off_acc, off_uoff, off_uid, off_mt,
         off_tiles, off_soff, off_sent, off_nodef, off_items, off_flag, total;
@@ -157,7 +158,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
         L.plane = g.plane;
         L.ntiles = g.ntx * g.ntz;
         L.nf = 4;
-        L.nxs = 2;
+        L.nxs = 4;
         if (L.ad2) {
             // state u^k, u^{k-1}, psi'x, psi'z, xi'x, xi'z; the second psi' buffers
             // (forward) and the adjoint's 10 fields use the extra slots
@@ -812,36 +813,34 @@ void ad2_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gw
 // 2-D acoustic: u^t is slot u4[t % 4] and s^t is slot s4[t % 4], so one
 // launch can write u^{k+1} and u^{k+2} while another still reads u^k and
 // u^{k-1} (the one- and two-step launches of a double step never touch a
-// slot another one reads).
-void ac2_phi(const sg_model *m, int ns, int k, hipStream_t s)
+// slot another one reads).  The layer auxiliaries alternate over two pairs
+// of fields: phi~^t (forward) and c^t (adjoint) in fields 2, 3 for even t
+// and 6, 7 for odd t, so a step reads one pair and writes the other.
+inline float *ac2_aux(float *const *f, int t, int j)
 {
-    Ac2PhiArgs p{};
-    p.g = m->L.g2;
-    p.u = m->u4[k & 3];
-    p.phx = m->fwd[2];
-    p.phz = m->fwd[3];
-    p.hx = m->h[0]; p.hz = m->h[2]; p.px = m->p[0]; p.pz = m->p[2]; p.ihx = m->ih[0]; p.ihz = m->ih[2];
-    launch_ac2_phi(p, ns, s);
+    return f[((t & 1) ? 6 : 2) + j];
 }
 
-// Pass B of forward step k on a tile list (null: every tile).
-void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, const int *tiles, int ntl, float *seis,
-               float *snap, hipStream_t s)
+// Forward step k on the one-step tile list (near: pass A folded into its
+// near tiles) or on the blocked tiles.
+void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, bool near, float *seis, float *snap,
+               hipStream_t s)
 {
     Ac2FwdArgs a{};
     a.g = m->L.g2;
     a.nshots = ns;
-    a.tiles = tiles;
-    a.ntl = ntl;
+    a.tiles = near ? m->tiles_near : m->tiles_blk;
+    a.ntl = near ? m->n_near : m->n_blk;
     a.u = m->u4[k & 3];
     a.um = m->u4[(k + 3) & 3];
     a.un = m->u4[(k + 1) & 3];
     a.chat = m->chat;
     a.shots_per_model = ns / m->d.nmodels;
-    a.phx = m->fwd[2];
-    a.phz = m->fwd[3];
-    a.hx = m->h[0];
-    a.hz = m->h[2];
+    a.phx0 = ac2_aux(m->fwd, k - 1, 0);
+    a.phz0 = ac2_aux(m->fwd, k - 1, 1);
+    a.phx = ac2_aux(m->fwd, k, 0);
+    a.phz = ac2_aux(m->fwd, k, 1);
+    a.hx = m->h[0]; a.hz = m->h[2]; a.px = m->p[0]; a.pz = m->p[2]; a.ihx = m->ih[0]; a.ihz = m->ih[2];
     a.src_f = m->src_f;
     a.wav = wav;
     a.nt = m->d.nt;
@@ -855,22 +854,21 @@ void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, const int *ti
     a.nsrc = m->geom_nsrc;
     a.src_off = m->src_off;
     a.src_ent = m->src_ent;
-    launch_ac2_fwd(a, s);
+    launch_ac2_fwd(a, near, s);
 }
 
-// Forward step k, or steps k and k+1 when `two`: near tiles step by step,
-// blocked tiles both steps in one launch (between the two near launches,
-// whose second step reads the blocked tiles' u^{k+1} in its halo).
+// Forward step k, or steps k and k+1 when `two`: the one-step list step by
+// step, blocked tiles both steps in one launch (between the two one-step
+// launches, whose second step reads the blocked tiles' u^{k+1} in its halo).
 void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, float *seis, float *snap0,
                  float *snap1, hipStream_t s)
 {
     if (!two) {
-        ac2_phi(m, ns, k, s);
-        ac2_tiles(m, ns, wav, k, nullptr, 0, seis, snap0, s);
+        ac2_tiles(m, ns, wav, k, true, seis, snap0, s);
+        ac2_tiles(m, ns, wav, k, false, seis, snap0, s);
         return;
     }
-    ac2_phi(m, ns, k, s);
-    ac2_tiles(m, ns, wav, k, m->tiles_near, m->n_near, seis, snap0, s);
+    ac2_tiles(m, ns, wav, k, true, seis, snap0, s);
     Ac2Fwd2Args b{};
     b.g = m->L.g2;
     b.nshots = ns;
@@ -890,8 +888,7 @@ void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, f
     b.snap0 = snap0;
     b.snap1 = snap1;
     launch_ac2_fwd2(b, s);
-    ac2_phi(m, ns, k + 1, s);
-    ac2_tiles(m, ns, wav, k + 1, m->tiles_near, m->n_near, seis, snap1, s);
+    ac2_tiles(m, ns, wav, k + 1, true, seis, snap1, s);
 }
 
 // One forward step of the 3-D acoustic or 2-D elastic recursion.
@@ -942,39 +939,26 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
     }
 }
 
-void ac2_phi_adj(const sg_model *m, int ns, int k, hipStream_t s)
-{
-    Ac2PhiAdjArgs pa{};
-    pa.g = m->L.g2;
-    pa.tiles = m->tiles_layer;
-    pa.ntl = m->n_layer;
-    pa.s2 = m->s4[(k + 2) & 3];
-    pa.chat = m->chat;
-    pa.shots_per_model = ns / m->d.nmodels;
-    pa.cx = m->adj[2];
-    pa.cz = m->adj[3];
-    pa.hx = m->h[0]; pa.hz = m->h[2]; pa.px = m->p[0]; pa.pz = m->p[2]; pa.ihx = m->ih[0]; pa.ihz = m->ih[2];
-    launch_ac2_phi_adj(pa, ns, s);
-}
-
-// Pass B of adjoint step k (s^{k+1} from s^{k+2}, s^{k+3}) on a tile list.
-void ac2_adj_tiles(const sg_model *m, int ns, int k, const int *tiles, int ntl, const float *dJdd, float *gwav,
+// Adjoint step k (s^{k+1} from s^{k+2}, s^{k+3}) on the one-step tile list
+// (near: pass A folded into its near tiles) or on the blocked tiles.
+void ac2_adj_tiles(const sg_model *m, int ns, int k, bool near, const float *dJdd, float *gwav,
                    const float *snap, hipStream_t s)
 {
     Ac2AdjArgs b{};
     b.g = m->L.g2;
     b.nshots = ns;
-    b.tiles = tiles;
-    b.ntl = ntl;
+    b.tiles = near ? m->tiles_near : m->tiles_blk;
+    b.ntl = near ? m->n_near : m->n_blk;
     b.s2 = m->s4[(k + 2) & 3];
     b.s3 = m->s4[(k + 3) & 3];
     b.s1 = m->s4[(k + 1) & 3];
     b.chat = m->chat;
     b.shots_per_model = ns / m->d.nmodels;
-    b.cx = m->adj[2];
-    b.cz = m->adj[3];
-    b.hx = m->h[0];
-    b.hz = m->h[2];
+    b.cx0 = ac2_aux(m->adj, k + 2, 0);
+    b.cz0 = ac2_aux(m->adj, k + 2, 1);
+    b.cx = ac2_aux(m->adj, k + 1, 0);
+    b.cz = ac2_aux(m->adj, k + 1, 1);
+    b.hx = m->h[0]; b.hz = m->h[2]; b.px = m->p[0]; b.pz = m->p[2]; b.ihx = m->ih[0]; b.ihz = m->ih[2];
     b.src_f = m->src_f;
     b.gwav = gwav;
     b.nt = m->d.nt;
@@ -986,7 +970,7 @@ void ac2_adj_tiles(const sg_model *m, int ns, int k, const int *tiles, int ntl, 
     b.nrec = m->geom_nrec;
     b.snap = snap;
     b.grad = m->grad;
-    launch_ac2_adj(b, s);
+    launch_ac2_adj(b, near, s);
 }
 
 // Adjoint step k, or steps k and k-1 when `two` (snap1 = w~^k, snap0 = w~^{k-1}).
@@ -999,13 +983,12 @@ void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, 
                               src_scale(m), s);
     };
     if (!two) {
-        ac2_phi_adj(m, ns, k, s);
-        ac2_adj_tiles(m, ns, k, nullptr, 0, dJdd, gwav, snap1, s);
+        ac2_adj_tiles(m, ns, k, true, dJdd, gwav, snap1, s);
+        ac2_adj_tiles(m, ns, k, false, dJdd, gwav, snap1, s);
         if (nodes) gather(k);
         return;
     }
-    ac2_phi_adj(m, ns, k, s);
-    ac2_adj_tiles(m, ns, k, m->tiles_near, m->n_near, dJdd, gwav, snap1, s);
+    ac2_adj_tiles(m, ns, k, true, dJdd, gwav, snap1, s);
     if (nodes) gather(k);
     Ac2Adj2Args b{};
     b.g = m->L.g2;
@@ -1027,8 +1010,7 @@ void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, 
     b.snap0 = snap0;
     b.grad = m->grad;
     launch_ac2_adj2(b, s);
-    ac2_phi_adj(m, ns, k - 1, s);
-    ac2_adj_tiles(m, ns, k - 1, m->tiles_near, m->n_near, dJdd, gwav, snap0, s);
+    ac2_adj_tiles(m, ns, k - 1, true, dJdd, gwav, snap0, s);
     if (nodes) gather(k - 1);
 }
 
@@ -1181,14 +1163,14 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     m->ws = static_cast<char *>(ws);
     m->chat = reinterpret_cast<float *>(m->ws + L.off_chat);
     m->cpad = reinterpret_cast<float *>(m->ws + L.off_cpad);
-    for (int i = 0; i < (L.ad2 ? L.nf + L.nxs : L.nf); ++i) {
+    for (int i = 0; i < L.nf + L.nxs; ++i) {
         m->fwd[i] = reinterpret_cast<float *>(m->ws + L.off_fwd) + i * L.field;
         m->adj[i] = reinterpret_cast<float *>(m->ws + L.off_adj) + i * L.field;
     }
     if (!L.elastic && d->ndim == 2) {
         if (!L.ad2) {
             float *fb = reinterpret_cast<float *>(m->ws + L.off_fwd), *ab = reinterpret_cast<float *>(m->ws + L.off_adj);
-            const int slot[4] = {0, 1, 4, 5};   // fields 2, 3 hold the layer auxiliaries
+            const int slot[4] = {0, 1, 4, 5};   // fields 2, 3 and 6, 7 hold the layer auxiliaries
             for (int i = 0; i < 4; ++i) {
                 m->u4[i] = fb + slot[i] * L.field;
                 m->s4[i] = ab + slot[i] * L.field;
@@ -1354,8 +1336,7 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     const long long fs = (long long)ns * L.plane;  // floats of one field over the batch
     const bool ad2 = L.ad2;
     const bool ac2 = !L.elastic && !ad2 && m->d.ndim == 2;
-    for (int i = 0; i < (ad2 ? nf + L.nxs : nf); ++i) launch_fill(m->fwd[i], fs, 0.f, s);
-    if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->u4[i], fs, 0.f, s);
+    for (int i = 0; i < (ad2 || ac2 ? nf + L.nxs : nf); ++i) launch_fill(m->fwd[i], fs, 0.f, s);
     float *sp = sh->nrec > 0 ? seis : nullptr;
     // segments >= seg0 keep their adjoint snapshots (checkpointed forwards only)
     const int seg0 = save_ckpt ? L.nseg - m->n_store : L.nseg;
@@ -1375,8 +1356,8 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
                 float *ck = m->ckpt + (size_t)(k / K) * nf * L.field;
                 for (int i = 0; i < nf; ++i) {
                     const float *src = ad2 ? ad2_state(m, k, i)
+                                     : ac2 ? (i < 2 ? m->u4[(k + 4 - i) & 3] : ac2_aux(m->fwd, k - 1, i - 2))
                                      : L.elastic || i >= 2 ? m->fwd[i]
-                                     : ac2 ? m->u4[(k + 4 - i) & 3]
                                            : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
                     HIPCHECK(hipMemcpyAsync(ck + i * L.field, src, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
                 }
@@ -1435,8 +1416,7 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     const long long fs = (long long)ns * L.plane;
     const bool ad2 = L.ad2;
     const bool ac2 = !L.elastic && !ad2 && m->d.ndim == 2;
-    for (int i = 0; i < (ad2 ? nf + L.nxs : nf); ++i) launch_fill(m->adj[i], fs, 0.f, s);
-    if (ac2) for (int i = 2; i < 4; ++i) launch_fill(m->s4[i], fs, 0.f, s);
+    for (int i = 0; i < (ad2 || ac2 ? nf + L.nxs : nf); ++i) launch_fill(m->adj[i], fs, 0.f, s);
     for (int q = 0; q < L.ngrad; ++q) launch_fill(m->grad + q * L.field, fs, 0.f, s);
     if (L.elastic)
         for (int i = 0; i < 8; ++i) launch_fill(m->tmp[i], fs, 0.f, s);
@@ -1453,7 +1433,9 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
         if (!kept) {
             const float *ck = m->ckpt + (size_t)seg * nf * L.field;
             for (int i = 0; i < nf; ++i) {
-                float *dst = ad2 ? ad2_state(m, k0, i) : ac2 && i < 2 ? m->u4[(k0 + 4 - i) & 3] : m->fwd[i];
+                float *dst = ad2 ? ad2_state(m, k0, i)
+                           : ac2 ? (i < 2 ? m->u4[(k0 + 4 - i) & 3] : ac2_aux(m->fwd, k0 - 1, i - 2))
+                                 : m->fwd[i];
                 HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
             }
             int cu = 0;

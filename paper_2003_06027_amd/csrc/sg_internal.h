@@ -30,28 +30,23 @@ struct Grid2 {
     int ntx, ntz;    // tiles
 };
 
-// Forward pass A: phi~^k = p phi~^{k-1} + q D~ u^k on the layer cells.
-struct Ac2PhiArgs {
-    Grid2 g;
-    const float *u;                   // u^k [shot][plane]
-    float *phx, *phz;                 // phi~ in place
-    const float *hx, *hz;             // h = zeta dt / 2 on the padded grid
-    const float *px, *pz, *ihx, *ihz; // (1-h)/(1+h) and 1/(1+h)
-};
-
-// Forward pass B over (tile, shot) pairs.
+// One forward step over (tile, shot) pairs: tiles away from the layer, or
+// the one-step list, whose near tiles also run pass A
+// (phi~^k = p phi~^{k-1} + q D~ u^k on the layer cells of the tile + 4).
 struct Ac2FwdArgs {
     Grid2 g;
     int nshots;
-    const int *tiles;       // tile indices to update, or null for all tiles
+    const int *tiles;       // tile indices to update
     int ntl;                // number of entries in tiles
     const float *u;         // u^k       [shot][plane]
     const float *um;        // u^{k-1}
     float *un;              // u^{k+1} out (may alias um: each cell reads um before writing)
     const float *chat;      // dt^2 c^2 / dx^2  [model][plane]
     int shots_per_model;
-    const float *phx, *phz; // phi~^k
-    const float *hx, *hz;
+    const float *phx0, *phz0; // phi~^{k-1} (near tiles: read on the layer cells of the tile + 4)
+    float *phx, *phz;       // phi~^k out (near tiles: their own layer cells; a different buffer)
+    const float *hx, *hz;   // h = zeta dt / 2 on the padded grid
+    const float *px, *pz, *ihx, *ihz; // (1-h)/(1+h) and 1/(1+h)
     const long long *src_f; // [shot] frame index of the source node
     const float *wav;       // [shot][nt]
     int nt, k;
@@ -68,30 +63,21 @@ struct Ac2FwdArgs {
     const int *src_ent;
 };
 
-// Adjoint pass A: c^{k+1} = p c^{k+2} - q D~(chat s^{k+2}) on the layer cells.
-struct Ac2PhiAdjArgs {
-    Grid2 g;
-    const int *tiles;       // tiles holding layer cells
-    int ntl;
-    const float *s2;        // s^{k+2}
-    const float *chat;
-    int shots_per_model;
-    float *cx, *cz;         // q-scaled adjoint of phi~, in place
-    const float *hx, *hz, *px, *pz, *ihx, *ihz;
-};
-
+// One adjoint step over (tile, shot) pairs; near tiles also run pass A
+// (c^{k+1} = p c^{k+2} - q D~(chat s^{k+2}) on the layer cells of the tile + 4).
 struct Ac2AdjArgs {
     Grid2 g;
     int nshots;
-    const int *tiles;       // tile indices to update, or null for all tiles
+    const int *tiles;       // tile indices to update
     int ntl;
     const float *s2;        // s^{k+2}  (alpha-scaled adjoint), read with halo
     const float *s3;        // s^{k+3}
     float *s1;              // s^{k+1} out (may alias s3)
     const float *chat;
     int shots_per_model;
-    const float *cx, *cz;   // c^{k+1}
-    const float *hx, *hz;
+    const float *cx0, *cz0; // c^{k+2} (near tiles, q-scaled layer adjoint)
+    float *cx, *cz;         // c^{k+1} out (near tiles: their own layer cells; a different buffer)
+    const float *hx, *hz, *px, *pz, *ihx, *ihz;
     const long long *src_f;
     float *gwav;            // [shot][nt] or null
     int nt, k;
@@ -150,12 +136,11 @@ constexpr int BLK_HALO = 8;
 // Adjoint of several source nodes: gw[shot][j][k] = scale * s^{k+1}[node j].
 void launch_ac2_src_gather(int nshots, int nsrc, long long plane, const long long *node_f, const float *s1,
                            float *gw, int nt, int k, float scale, hipStream_t s);
-void launch_ac2_phi(const Ac2PhiArgs &a, int nshots, hipStream_t s);
 void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s);
 void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s);
-void launch_ac2_phi_adj(const Ac2PhiAdjArgs &a, int nshots, hipStream_t s);
-void launch_ac2_fwd(const Ac2FwdArgs &a, hipStream_t s);
-void launch_ac2_adj(const Ac2AdjArgs &a, hipStream_t s);
+// near: the one-step list (pass A folded into its near tiles); else tiles away from the layer
+void launch_ac2_fwd(const Ac2FwdArgs &a, bool near, hipStream_t s);
+void launch_ac2_adj(const Ac2AdjArgs &a, bool near, hipStream_t s);
 void launch_ac2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx,
                      float *chat, float *cpad, hipStream_t s);
 void launch_ac2_finalize(const Grid2 &g, int nmodels, int shots_per_model, const float *grad,
