@@ -21,6 +21,8 @@ bookkeeping.
 from __future__ import annotations
 
 import dataclasses
+import json
+import os
 import time
 
 import numpy as np
@@ -132,8 +134,28 @@ def per_model_misfit(prop, pred, obs, nmodels):
     return J, resid
 
 
+def save_gd_state(path, it, m, alpha, Js, times, acc, offered, rej, direction=None):
+    """The inversion state after iteration `it` (numpy arrays only, written
+    atomically): models, step lengths, the misfit history and flags, and the
+    direction object's state if it has one."""
+    st = {"it": np.array(it), "models": m.detach().cpu().numpy(), "alpha": alpha.numpy(),
+          "J": np.array(Js), "times": np.array(times), "accepted": np.array(acc),
+          "guarded": np.array(offered), "rejected": np.array(rej)}
+    if direction is not None and hasattr(direction, "state"):
+        st.update({"dir_" + k: v for k, v in direction.state().items()})
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **st)
+    os.replace(tmp, path)
+
+
+def load_gd_state(path):
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
 def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDConfig = GDConfig(),
-               direction=None, target=None, log=None) -> GDResult:
+               direction=None, target=None, log=None, state_path=None, resume=False,
+               jsonl=None) -> GDResult:
     """Gradient descent on B models at once.  Per iteration and model: fwd +
     misfit + adjoint gradient g_b; direction p_b = -g_b, or
     direction(g, models, it) if given (which returns p and a mask of models
@@ -143,20 +165,39 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
     decrease J on its first trial is replaced by -g for that model and
     iteration; a direction object with a ``report(it, rejected)`` method is
     told which models that happened to.  Stops early when every model
-    reaches J/J0 <= target."""
+    reaches J/J0 <= target.
+
+    state_path: the state is saved there after every iteration; with
+    resume=True and an existing file the run continues from it (the models
+    are restored bit for bit, the misfit and residual recomputed from them,
+    so the continued trajectory equals an uninterrupted one).  jsonl: one
+    JSON line per iteration appended there (relative misfit, accepted and
+    rejected steps, step lengths, seconds)."""
     B = prop.d.nmodels
     m = m0.clone().contiguous()
     alpha = torch.full((B,), cfg.alpha0, dtype=torch.float64)
     Js, times, acc, offered, rej = [], [], [], [], []
+    start, t_prev = 0, 0.0
+    if resume and state_path and os.path.exists(state_path):
+        st = load_gd_state(state_path)
+        m = torch.as_tensor(st["models"], device=m0.device).contiguous()
+        alpha = torch.as_tensor(st["alpha"], dtype=torch.float64)
+        Js = list(st["J"])
+        times = list(st["times"])
+        acc, offered, rej = list(st["accepted"]), list(st["guarded"]), list(st["rejected"])
+        start, t_prev = int(st["it"]) + 1, float(st["times"][-1])
+        if direction is not None and hasattr(direction, "load_state"):
+            direction.load_state({k[4:]: v for k, v in st.items() if k.startswith("dir_")})
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    t0 = time.perf_counter() - t_prev
     pred = prop.forward(m, save_ckpt=True)
     J, r = per_model_misfit(prop, pred, obs, B)
-    J0 = J.cpu().numpy().copy()
-    Js.append(J0.copy())
-    torch.cuda.synchronize()
-    times.append(time.perf_counter() - t0)
-    for it in range(cfg.iters):
+    if start == 0:
+        Js.append(J.cpu().numpy().copy())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    J0 = Js[0]
+    for it in range(start, cfg.iters):
         g = prop.model.gradient(prop.shots, r)
         gflat = g.reshape(B, -1)
         p = -g
@@ -224,6 +265,13 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
         times.append(time.perf_counter() - t0)
         if log:
             log(it, Js[-1] / J0, done)
+        if jsonl:
+            with open(jsonl, "a") as f:
+                f.write(json.dumps({"it": it, "seconds": times[-1], "J": Js[-1].tolist(),
+                                    "J_rel": (Js[-1] / J0).tolist(), "accepted": done.tolist(),
+                                    "rejected": rejected.tolist(), "alpha": alpha.tolist()}) + "\n")
+        if state_path:
+            save_gd_state(state_path, it, m, alpha, Js, times, acc, offered, rej, direction)
         if target is not None and np.all(Js[-1] / J0 <= target):
             break
     return GDResult(models=m, J=np.array(Js), times=np.array(times), accepted=np.array(acc),

@@ -123,6 +123,14 @@ class LearnedDirection:
         self.consec = np.where(rejected, self.consec + 1, np.where(self.off, self.consec, 0))
         self.off |= self.consec >= self.max_rejects
 
+    def state(self):
+        """Switch-off bookkeeping, saved with the inversion state."""
+        return {} if self.off is None else {"off": self.off.copy(), "consec": self.consec.copy()}
+
+    def load_state(self, st):
+        if st:
+            self.off, self.consec = st["off"].astype(bool), st["consec"].astype(int)
+
 
 def generate_pairs(prob: Problem, iters: int, frame=128, seed=0):
     """Run the plain inversion and pack its (g, m_true - m) pairs into

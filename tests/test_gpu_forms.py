@@ -189,3 +189,45 @@ def test_gradient_taylor_expansion_on_the_gpu():
     print("error ratios per doubling", r_err, "remainder ratios", r_rem)
     assert abs(rich[0]) <= 1e-3 and abs(rich[1]) <= 1e-3, rich
     assert all(3.0 < r < 5.0 for r in r_err[1:]) and all(3.0 < r < 5.0 for r in r_rem), (r_err, r_rem)
+
+
+def test_gd_resumes_bit_for_bit_from_saved_state(tmp_path):
+    """An inversion stopped after 3 iterations and resumed from its saved
+    state (a new direction object too) ends where an uninterrupted 6-iteration
+    run ends, bit for bit; the JSON-lines log has one record per iteration."""
+    import json
+    from paper_2003_06027_amd import ttm
+    B = 2
+    cfg = synth.C1.replace(nt=300)
+    true = np.stack([synth.random_layered(300 + b) for b in range(B)])
+    init = np.stack([synth.smooth(t, 10.0) for t in true])
+    src = np.array([[50, 2]] * B, dtype=np.int32)
+    rec = synth.surface_receivers_2d(B, cfg.nx)
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, cfg.nt)[None].repeat(B, 1).contiguous()
+    d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, nmodels=B, dx=cfg.dx, dt=cfg.dt, pml_vmax=3500.0)
+    prop = fwi.Propagator(d, S.Shots(src, rec, wav))
+    obs = prop.forward(dev(true), save_ckpt=False).clone()
+    log = str(tmp_path / "gd.jsonl")
+    whole = fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=6), jsonl=log)
+    lines = [json.loads(x) for x in open(log)]
+    assert [x["it"] for x in lines] == list(range(6))
+    assert np.allclose([x["J_rel"] for x in lines], whole.J[1:] / whole.J[0], rtol=0, atol=0)
+    st = str(tmp_path / "gd_state.npz")
+    fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=3), state_path=st)
+    resumed = fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=6), state_path=st, resume=True)
+    assert np.array_equal(resumed.J, whole.J)
+    assert np.array_equal(resumed.accepted, whole.accepted)
+    assert torch.equal(resumed.models, whole.models)
+    # with the learned direction's switch-off state (the ascent network is
+    # switched off after two rejections, i.e. before the interruption)
+    g_whole = fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=5),
+                             direction=ttm.LearnedDirection(_Ascent(), max_rejects=2))
+    st2 = str(tmp_path / "gd_state2.npz")
+    fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=3), state_path=st2,
+                   direction=ttm.LearnedDirection(_Ascent(), max_rejects=2))
+    ld = ttm.LearnedDirection(_Ascent(), max_rejects=2)
+    g_res = fwi.batched_gd(prop, dev(init), obs, fwi.GDConfig(iters=5), state_path=st2, resume=True, direction=ld)
+    assert ld.off.all()
+    assert np.array_equal(g_res.guarded, g_whole.guarded) and np.array_equal(g_res.rejected, g_whole.rejected)
+    assert np.array_equal(g_res.J, g_whole.J) and torch.equal(g_res.models, g_whole.models)
+    prop.close()
