@@ -349,13 +349,14 @@ constexpr int RING_IT = (NRING + NTH - 1) / NTH;
 // Load the tile + 8 of a field into LDS with 16-byte loads (rows start
 // 32-byte aligned: x0 - 8 + OX is a multiple of 8), optionally multiplied
 // cell by cell by a second field.
+template <int NT = NTH>
 __device__ __forceinline__ void load_tile8(const Grid2 &g, const float *u, const float *mul, float *lds,
                                            int x0, int z0)
 {
     constexpr int Q = W0 / 4, N4 = R0 * Q;
 #pragma unroll
-    for (int it = 0; it < (N4 + NTH - 1) / NTH; ++it) {
-        const int q = threadIdx.x + it * NTH;
+    for (int it = 0; it < (N4 + NT - 1) / NT; ++it) {
+        const int q = threadIdx.x + it * NT;
         if (q < N4) {
             const int r = q / Q, c = (q - r * Q) * 4;
             const long long f = fidx(g, z0 - H2 + r, x0 - H2 + c);
@@ -560,24 +561,26 @@ __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
 }
 
 // ---------------------------------------------------------------- near tiles
-// The tiles of the one-step list (near the layer, or holding receivers or
-// several-node sources) with pass A folded in.  LDS: the stepped field on
+// The tiles within 4 cells of the layer, with pass A folded in.  LDS: the stepped field on
 // the tile + 8 (as the blocked kernels stage it), the x auxiliary on the
 // tile's rows x the tile + 4 columns, the z auxiliary on the tile + 4 rows x
-// the tile's columns.  Tiles of the list that are not near the layer take
-// the interior update on the first part of the field array.  Every value is
-// formed by the same expression as in separate passes, so results do not
-// depend on which tile computes a ring cell.
+// the tile's columns.
+// Every value is formed by the same expression as in separate passes, so
+// results do not depend on which tile computes a ring cell.  NTN threads per
+// tile (RN rows each): the LDS arrays cap the workgroups per CU, so a
+// larger workgroup keeps more waves resident.
 constexpr int WPX = TX + 8;      // x auxiliary: columns x0 - 4 .. x0 + TX + 3
 constexpr int RPZ = TZ + 8;      // z auxiliary: rows z0 - 4 .. z0 + TZ + 3
 constexpr int NU = R0 * W0;      // the field on the tile + 8
-static_assert(NU >= (TZ + 8) * (TX + 8), "the interior update fits the field array");
+constexpr int NTN = 512;         // threads of a near tile
+constexpr int RN = TZ * TX / NTN;
+static_assert(RN * NTN == TZ * TX && NTN % TX == 0, "whole rows per thread");
 
 // Halo cells of the auxiliaries' LDS arrays: the 4 + 4 columns of the x
 // array beside the tile (TZ x 8, one per thread) and the 4 + 4 rows of the z
 // array above and below it (8 x TX, two per thread).
 constexpr int NHX = TZ * 8, NHZ = 8 * TX;
-static_assert(NHX == NTH && NHZ == 2 * NTH, "one x and two z halo cells per thread");
+constexpr int HXI = (NHX + NTN - 1) / NTN, HZI = (NHZ + NTN - 1) / NTN;   // halo cells per thread
 
 __device__ __forceinline__ void halo_x_cell(int i, int &r, int &c)
 {
@@ -613,11 +616,11 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
 
     // operands of the own cells and of the halo cells first (none depends on LDS)
     const float hxc = inx ? a.hx[ix] : 0.f, pxc = inx ? a.px[ix] : 0.f, ihxc = inx ? a.ihx[ix] : 0.f;
-    float ch[RPT], pm[RPT], hzr[RPT], fx[RPT], fz[RPT];
+    float ch[RN], pm[RN], hzr[RN], fx[RN], fz[RN];
     unsigned lay = 0u;
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int iz = z0 + ly * RPT + j;
+    for (int j = 0; j < RN; ++j) {
+        const int iz = z0 + ly * RN + j;
         const long long f = fidx(g, iz, ix);
         ch[j] = pm[j] = hzr[j] = fx[j] = fz[j] = 0.f;
         if (iz < g.NZ && inx) {
@@ -631,38 +634,44 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
             }
         }
     }
-    // x halo: one cell per thread
-    int hr, hc;
-    halo_x_cell(tid, hr, hc);
-    const int hxz = z0 + hr, hxx = x0 - 4 + hc;
-    const bool hxl = hxz < g.NZ && hxx >= 0 && hxx < g.NX && layer_cell_at(g, hxz, hxx);
-    float hx_h = 0.f, hz_h = 0.f, p_h = 0.f, ih_h = 0.f, f_h = 0.f;
-    if (hxl) {
-        hx_h = a.hx[hxx]; hz_h = a.hz[hxz]; p_h = a.px[hxx]; ih_h = a.ihx[hxx];
-        f_h = phx0[fidx(g, hxz, hxx)];
-    }
-    // z halo: two cells per thread
-    float zhx[2], zhz[2], zp[2], zih[2], zf[2];
-    bool zl[2];
-    int zr[2], zc[2];
+    // halo cells of the x and z arrays
+    float xhx[HXI], xhz[HXI], xp[HXI], xih[HXI], xf[HXI];
+    bool xl[HXI];
+    int xr[HXI], xc[HXI];
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        halo_z_cell(tid + it * NTH, zr[it], zc[it]);
+    for (int it = 0; it < HXI; ++it) {
+        const int i = tid + it * NTN;
+        halo_x_cell(i < NHX ? i : 0, xr[it], xc[it]);
+        const int iz = z0 + xr[it], jx = x0 - 4 + xc[it];
+        xl[it] = i < NHX && iz < g.NZ && jx >= 0 && jx < g.NX && layer_cell_at(g, iz, jx);
+        xhx[it] = xhz[it] = xp[it] = xih[it] = xf[it] = 0.f;
+        if (xl[it]) {
+            xhx[it] = a.hx[jx]; xhz[it] = a.hz[iz]; xp[it] = a.px[jx]; xih[it] = a.ihx[jx];
+            xf[it] = phx0[fidx(g, iz, jx)];
+        }
+    }
+    float zhx[HZI], zhz[HZI], zp[HZI], zih[HZI], zf[HZI];
+    bool zl[HZI];
+    int zr[HZI], zc[HZI];
+#pragma unroll
+    for (int it = 0; it < HZI; ++it) {
+        const int i = tid + it * NTN;
+        halo_z_cell(i < NHZ ? i : 0, zr[it], zc[it]);
         const int iz = z0 - 4 + zr[it], jx = x0 + zc[it];
-        zl[it] = iz >= 0 && iz < g.NZ && jx < g.NX && layer_cell_at(g, iz, jx);
+        zl[it] = i < NHZ && iz >= 0 && iz < g.NZ && jx < g.NX && layer_cell_at(g, iz, jx);
         zhx[it] = zhz[it] = zp[it] = zih[it] = zf[it] = 0.f;
         if (zl[it]) {
             zhx[it] = a.hx[jx]; zhz[it] = a.hz[iz]; zp[it] = a.pz[iz]; zih[it] = a.ihz[iz];
             zf[it] = phz0[fidx(g, iz, jx)];
         }
     }
-    load_tile8(g, a.u + so, nullptr, su, x0, z0);      // u^k on the tile + 8
+    load_tile8<NTN>(g, a.u + so, nullptr, su, x0, z0);      // u^k on the tile + 8
     __syncthreads();
 
     // pass A: phi~^k on the own layer cells (written out) and the halo cells
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j;
+    for (int j = 0; j < RN; ++j) {
+        const int r = ly * RN + j;
         float vx = 0.f, vz = 0.f;
         if (lay >> j & 1u) {
             const int iz = z0 + r;
@@ -678,16 +687,19 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
         sx[r * WPX + lx + 4] = vx;
         sz[(r + 4) * TX + lx] = vz;
     }
-    {
+#pragma unroll
+    for (int it = 0; it < HXI; ++it) {
+        if (tid + it * NTN >= NHX) continue;
         float v = 0.f;
-        if (hxl) {
-            const float qx = 2.f * (hz_h - hx_h) * ih_h;
-            v = p_h * f_h + qx * d8(su + (hr + H2) * W0 + hc + 4, 1);
+        if (xl[it]) {
+            const float qx = 2.f * (xhz[it] - xhx[it]) * xih[it];
+            v = xp[it] * xf[it] + qx * d8(su + (xr[it] + H2) * W0 + xc[it] + 4, 1);
         }
-        sx[hr * WPX + hc] = v;
+        sx[xr[it] * WPX + xc[it]] = v;
     }
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < HZI; ++it) {
+        if (tid + it * NTN >= NHZ) continue;
         float v = 0.f;
         if (zl[it]) {
             const float qz = 2.f * (zhx[it] - zhz[it]) * zih[it];
@@ -701,10 +713,10 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
     float *uo = a.un + so;
     const long long src = a.src_f[shot];
     const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
-    float un[RPT];
+    float un[RN];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j, iz = z0 + r;
+    for (int j = 0; j < RN; ++j) {
+        const int r = ly * RN + j, iz = z0 + r;
         const float *cu = su + (r + H2) * W0 + lx + H2;
         const float uc = cu[0];
         float w = lap8(cu, W0);
@@ -734,9 +746,9 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
         if (b < e) {                      // uniform over the block
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) su[(ly * RPT + j + H2) * W0 + lx + H2] = un[j];
+            for (int j = 0; j < RN; ++j) su[(ly * RN + j + H2) * W0 + lx + H2] = un[j];
             __syncthreads();
-            for (int i = b + tid; i < e; i += NTH) {
+            for (int i = b + tid; i < e; i += NTN) {
                 const int ent = a.rec_ent[i];
                 const int cell = rec_cell(ent);
                 const int r = cell / TX, c = cell - r * TX;
@@ -746,17 +758,20 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
     }
 }
 
+// 34.8 KB of LDS per tile allow 4 tiles per CU: 8 waves per SIMD at 512
+// threads, which the forward reaches in 64 VGPRs without spills (256-thread
+// tiles held 4 waves per SIMD and ran the C2 near tiles 16 % slower).  The
+// adjoint keeps 76 VGPRs and 6 waves: limited to 64 it spills and runs 9 %
+// slower.
 template <bool SNAP, bool REC>
-__global__ __launch_bounds__(NTH) void ac2_near_kernel(Ac2FwdArgs a)
+__global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(8))) void ac2_near_kernel(Ac2FwdArgs a)
 {
     __shared__ float su[NU];
     __shared__ float sx[TZ * WPX];
     __shared__ float sz[RPZ * TX];
     const int w = xcd_work_id(a.ntl * a.nshots);
     const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
-    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
-    if (near_layer(a.g, tx * TX, tz * TZ)) fwd_near_tile<SNAP, REC>(a, su, sx, sz, tile, shot);
-    else                                    fwd_tile<SNAP, REC>(a, su, tile, shot);
+    fwd_near_tile<SNAP, REC>(a, su, sx, sz, tile, shot);
 }
 
 __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, float *sx, float *sz, int tile,
@@ -778,11 +793,11 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
     float *__restrict__ czo = a.cz + so;
 
     const float hxc = inx ? a.hx[ix] : 0.f, pxc = inx ? a.px[ix] : 0.f, ihxc = inx ? a.ihx[ix] : 0.f;
-    float sc2[RPT], q3[RPT], hzr[RPT], fx[RPT], fz[RPT];
+    float sc2[RN], q3[RN], hzr[RN], fx[RN], fz[RN];
     unsigned lay = 0u;
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int iz = z0 + ly * RPT + j;
+    for (int j = 0; j < RN; ++j) {
+        const int iz = z0 + ly * RN + j;
         const long long f = fidx(g, iz, ix);
         sc2[j] = s2[f];
         q3[j] = hzr[j] = fx[j] = fz[j] = 0.f;
@@ -796,36 +811,44 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
             }
         }
     }
-    int hr, hc;
-    halo_x_cell(tid, hr, hc);
-    const int hxz = z0 + hr, hxx = x0 - 4 + hc;
-    const bool hxl = hxz < g.NZ && hxx >= 0 && hxx < g.NX && layer_cell_at(g, hxz, hxx);
-    float hx_h = 0.f, hz_h = 0.f, p_h = 0.f, ih_h = 0.f, f_h = 0.f;
-    if (hxl) {
-        hx_h = a.hx[hxx]; hz_h = a.hz[hxz]; p_h = a.px[hxx]; ih_h = a.ihx[hxx];
-        f_h = cx0[fidx(g, hxz, hxx)];
-    }
-    float zhx[2], zhz[2], zp[2], zih[2], zf[2];
-    bool zl[2];
-    int zr[2], zc[2];
+    // halo cells of the x and z arrays
+    float xhx[HXI], xhz[HXI], xp[HXI], xih[HXI], xf[HXI];
+    bool xl[HXI];
+    int xr[HXI], xc[HXI];
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        halo_z_cell(tid + it * NTH, zr[it], zc[it]);
+    for (int it = 0; it < HXI; ++it) {
+        const int i = tid + it * NTN;
+        halo_x_cell(i < NHX ? i : 0, xr[it], xc[it]);
+        const int iz = z0 + xr[it], jx = x0 - 4 + xc[it];
+        xl[it] = i < NHX && iz < g.NZ && jx >= 0 && jx < g.NX && layer_cell_at(g, iz, jx);
+        xhx[it] = xhz[it] = xp[it] = xih[it] = xf[it] = 0.f;
+        if (xl[it]) {
+            xhx[it] = a.hx[jx]; xhz[it] = a.hz[iz]; xp[it] = a.px[jx]; xih[it] = a.ihx[jx];
+            xf[it] = cx0[fidx(g, iz, jx)];
+        }
+    }
+    float zhx[HZI], zhz[HZI], zp[HZI], zih[HZI], zf[HZI];
+    bool zl[HZI];
+    int zr[HZI], zc[HZI];
+#pragma unroll
+    for (int it = 0; it < HZI; ++it) {
+        const int i = tid + it * NTN;
+        halo_z_cell(i < NHZ ? i : 0, zr[it], zc[it]);
         const int iz = z0 - 4 + zr[it], jx = x0 + zc[it];
-        zl[it] = iz >= 0 && iz < g.NZ && jx < g.NX && layer_cell_at(g, iz, jx);
+        zl[it] = i < NHZ && iz >= 0 && iz < g.NZ && jx < g.NX && layer_cell_at(g, iz, jx);
         zhx[it] = zhz[it] = zp[it] = zih[it] = zf[it] = 0.f;
         if (zl[it]) {
             zhx[it] = a.hx[jx]; zhz[it] = a.hz[iz]; zp[it] = a.pz[iz]; zih[it] = a.ihz[iz];
             zf[it] = cz0[fidx(g, iz, jx)];
         }
     }
-    load_tile8(g, s2, chat, sc, x0, z0);      // chat s^{k+2} on the tile + 8
+    load_tile8<NTN>(g, s2, chat, sc, x0, z0);      // chat s^{k+2} on the tile + 8
     __syncthreads();
 
     // pass A: c^{k+1} on the own layer cells (written out) and the halo cells
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j;
+    for (int j = 0; j < RN; ++j) {
+        const int r = ly * RN + j;
         float vx = 0.f, vz = 0.f;
         if (lay >> j & 1u) {
             const int iz = z0 + r;
@@ -841,16 +864,19 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
         sx[r * WPX + lx + 4] = vx;
         sz[(r + 4) * TX + lx] = vz;
     }
-    {
+#pragma unroll
+    for (int it = 0; it < HXI; ++it) {
+        if (tid + it * NTN >= NHX) continue;
         float v = 0.f;
-        if (hxl) {
-            const float qx = 2.f * (hz_h - hx_h) * ih_h;
-            v = p_h * f_h - qx * d8(sc + (hr + H2) * W0 + hc + 4, 1);
+        if (xl[it]) {
+            const float qx = 2.f * (xhz[it] - xhx[it]) * xih[it];
+            v = xp[it] * xf[it] - qx * d8(sc + (xr[it] + H2) * W0 + xc[it] + 4, 1);
         }
-        sx[hr * WPX + hc] = v;
+        sx[xr[it] * WPX + xc[it]] = v;
     }
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < HZI; ++it) {
+        if (tid + it * NTN >= NHZ) continue;
         float v = 0.f;
         if (zl[it]) {
             const float qz = 2.f * (zhx[it] - zhz[it]) * zih[it];
@@ -862,10 +888,10 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
 
     // pass B on the tile
     float *s1o = a.s1 + so;
-    float av[RPT];
+    float av[RN];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j, iz = z0 + r;
+    for (int j = 0; j < RN; ++j) {
+        const int r = ly * RN + j, iz = z0 + r;
         float v = lap8(sc + (r + H2) * W0 + lx + H2, W0);
         if (iz < g.NZ && inx) {
             v -= d8(sx + r * WPX + lx + 4, 1) + d8(sz + (r + 4) * TX + lx, (long long)TX);
@@ -883,10 +909,10 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
         if (b < e) {
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) sc[(ly * RPT + j + H2) * W0 + lx + H2] = av[j];
+            for (int j = 0; j < RN; ++j) sc[(ly * RN + j + H2) * W0 + lx + H2] = av[j];
             __syncthreads();
             const float *d = a.dJdd + ((long long)shot * a.nt + a.k) * a.nrec;
-            for (int i = b + tid; i < e; i += NTH) {
+            for (int i = b + tid; i < e; i += NTN) {
                 const int cell = rec_cell(a.rec_ent[i]);
                 if (i > b && rec_cell(a.rec_ent[i - 1]) == cell) continue;  // not first of its cell
                 float sum = 0.f;
@@ -896,14 +922,14 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
             }
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) av[j] = sc[(ly * RPT + j + H2) * W0 + lx + H2];
+            for (int j = 0; j < RN; ++j) av[j] = sc[(ly * RN + j + H2) * W0 + lx + H2];
         }
     }
 
     const long long src = a.src_f[shot];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j, iz = z0 + r;
+    for (int j = 0; j < RN; ++j) {
+        const int r = ly * RN + j, iz = z0 + r;
         if (iz < g.NZ && inx) {
             const long long f = fidx(g, iz, ix);
             const float s1 = av[j] / (1.f + hxc + hzr[j]);
@@ -914,16 +940,14 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
     }
 }
 
-__global__ __launch_bounds__(NTH) void ac2_adj_near_kernel(Ac2AdjArgs a)
+__global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(6))) void ac2_adj_near_kernel(Ac2AdjArgs a)
 {
     __shared__ float sc[NU];
     __shared__ float sx[TZ * WPX];
     __shared__ float sz[RPZ * TX];
     const int w = xcd_work_id(a.ntl * a.nshots);
     const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
-    const int tz = tile / a.g.ntx, tx = tile - tz * a.g.ntx;
-    if (near_layer(a.g, tx * TX, tz * TZ)) adj_near_tile(a, sc, sx, sz, tile, shot);
-    else                                    adj_tile(a, sc, tile, shot);
+    adj_near_tile(a, sc, sx, sz, tile, shot);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -947,8 +971,8 @@ void launch_ac2_fwd(const Ac2FwdArgs &a, bool near, hipStream_t s)
     if (nb == 0) return;
     const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
     if (near) {
-        if (snap) { if (rec) ac2_near_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_near_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
-        else      { if (rec) ac2_near_kernel<false, true><<<nb, NTH, 0, s>>>(a); else ac2_near_kernel<false, false><<<nb, NTH, 0, s>>>(a); }
+        if (snap) { if (rec) ac2_near_kernel<true, true><<<nb, NTN, 0, s>>>(a); else ac2_near_kernel<true, false><<<nb, NTN, 0, s>>>(a); }
+        else      { if (rec) ac2_near_kernel<false, true><<<nb, NTN, 0, s>>>(a); else ac2_near_kernel<false, false><<<nb, NTN, 0, s>>>(a); }
     } else {
         if (snap) { if (rec) ac2_fwd_kernel<true, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<true, false><<<nb, NTH, 0, s>>>(a); }
         else      { if (rec) ac2_fwd_kernel<false, true><<<nb, NTH, 0, s>>>(a); else ac2_fwd_kernel<false, false><<<nb, NTH, 0, s>>>(a); }
@@ -959,7 +983,7 @@ void launch_ac2_adj(const Ac2AdjArgs &a, bool near, hipStream_t s)
 {
     const int nb = a.ntl * a.nshots;
     if (nb == 0) return;
-    if (near) ac2_adj_near_kernel<<<nb, NTH, 0, s>>>(a);
+    if (near) ac2_adj_near_kernel<<<nb, NTN, 0, s>>>(a);
     else      ac2_adj_kernel<<<nb, NTH, 0, s>>>(a);
 }
 

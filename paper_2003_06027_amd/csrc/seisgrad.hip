@@ -240,7 +240,8 @@ struct sg_model {
     int geom_nsrc = 1;
     std::vector<int> h_soff, h_sent;
     std::vector<long long> h_nodef;
-    int n_near = 0, n_blk = 0;
+    int n_near = 0, n_blk = 0;      // one-step tiles (the first n_layer_near by the layer), blocked tiles
+    int n_layer_near = 0;
     std::vector<int> h_tiles;
     // tiles holding layer cells (the layer pass of the constant-density form)
     int *tiles_layer = nullptr;
@@ -523,16 +524,22 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
                         if (px >= tx * TX - 4 && px < tx * TX + TX + 4 && pz >= tz * TZ - 4 && pz < tz * TZ + TZ + 4)
                             rec_near[tz * g.ntx + tx] = 1;
             }
-        std::vector<int> near, blk;
+        // one-step tiles: those within 4 cells of the layer (their kernel folds
+        // the layer pass in) first, then the others; then the blocked tiles
+        std::vector<int> near, other, blk;
         for (int t = 0; t < ntiles; ++t) {
             const int x0 = (t % g.ntx) * TX, z0 = (t / g.ntx) * TZ;
             const bool inner = x0 - BLK_HALO >= P && x0 + TX + BLK_HALO <= P + g.nx &&
                                z0 - BLK_HALO >= P && z0 + TZ + BLK_HALO <= P + g.nz;
-            (inner && !rec_near[t] ? blk : near).push_back(t);
+            const bool by_layer = P > 0 && (x0 - 4 < P || x0 + TX + 4 > P + g.nx ||
+                                            z0 - 4 < P || z0 + TZ + 4 > P + g.nz);
+            (by_layer ? near : inner && !rec_near[t] ? blk : other).push_back(t);
         }
-        m->n_near = (int)near.size();
+        m->n_layer_near = (int)near.size();
+        m->n_near = (int)(near.size() + other.size());
         m->n_blk = (int)blk.size();
         m->h_tiles = near;
+        m->h_tiles.insert(m->h_tiles.end(), other.begin(), other.end());
         m->h_tiles.insert(m->h_tiles.end(), blk.begin(), blk.end());
         HIPCHECK(hipMemcpyAsync(m->tiles_near, m->h_tiles.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice, s));
         m->tiles_blk = m->tiles_near + m->n_near;
@@ -821,16 +828,23 @@ inline float *ac2_aux(float *const *f, int t, int j)
     return f[((t & 1) ? 6 : 2) + j];
 }
 
-// Forward step k on the one-step tile list (near: pass A folded into its
-// near tiles) or on the blocked tiles.
-void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, bool near, float *seis, float *snap,
+// The tile lists of a step: the one-step tiles within 4 cells of the layer
+// (pass A folded in), the other one-step tiles, the blocked tiles.
+enum TileSet { TS_LAYER, TS_OTHER, TS_BLOCKED };
+inline const int *tile_set(const sg_model *m, TileSet t, int &n)
+{
+    n = t == TS_LAYER ? m->n_layer_near : t == TS_OTHER ? m->n_near - m->n_layer_near : m->n_blk;
+    return t == TS_LAYER ? m->tiles_near : t == TS_OTHER ? m->tiles_near + m->n_layer_near : m->tiles_blk;
+}
+
+// One forward step k on a tile set.
+void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, TileSet ts, float *seis, float *snap,
                hipStream_t s)
 {
     Ac2FwdArgs a{};
     a.g = m->L.g2;
     a.nshots = ns;
-    a.tiles = near ? m->tiles_near : m->tiles_blk;
-    a.ntl = near ? m->n_near : m->n_blk;
+    a.tiles = tile_set(m, ts, a.ntl);
     a.u = m->u4[k & 3];
     a.um = m->u4[(k + 3) & 3];
     a.un = m->u4[(k + 1) & 3];
@@ -854,7 +868,7 @@ void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, bool near, fl
     a.nsrc = m->geom_nsrc;
     a.src_off = m->src_off;
     a.src_ent = m->src_ent;
-    launch_ac2_fwd(a, near, s);
+    launch_ac2_fwd(a, ts == TS_LAYER, s);
 }
 
 // Forward step k, or steps k and k+1 when `two`: the one-step list step by
@@ -864,11 +878,11 @@ void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, f
                  float *snap1, hipStream_t s)
 {
     if (!two) {
-        ac2_tiles(m, ns, wav, k, true, seis, snap0, s);
-        ac2_tiles(m, ns, wav, k, false, seis, snap0, s);
+        for (TileSet ts : {TS_LAYER, TS_OTHER, TS_BLOCKED}) ac2_tiles(m, ns, wav, k, ts, seis, snap0, s);
         return;
     }
-    ac2_tiles(m, ns, wav, k, true, seis, snap0, s);
+    ac2_tiles(m, ns, wav, k, TS_LAYER, seis, snap0, s);
+    ac2_tiles(m, ns, wav, k, TS_OTHER, seis, snap0, s);
     Ac2Fwd2Args b{};
     b.g = m->L.g2;
     b.nshots = ns;
@@ -888,7 +902,8 @@ void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, f
     b.snap0 = snap0;
     b.snap1 = snap1;
     launch_ac2_fwd2(b, s);
-    ac2_tiles(m, ns, wav, k + 1, true, seis, snap1, s);
+    ac2_tiles(m, ns, wav, k + 1, TS_LAYER, seis, snap1, s);
+    ac2_tiles(m, ns, wav, k + 1, TS_OTHER, seis, snap1, s);
 }
 
 // One forward step of the 3-D acoustic or 2-D elastic recursion.
@@ -939,16 +954,14 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
     }
 }
 
-// Adjoint step k (s^{k+1} from s^{k+2}, s^{k+3}) on the one-step tile list
-// (near: pass A folded into its near tiles) or on the blocked tiles.
-void ac2_adj_tiles(const sg_model *m, int ns, int k, bool near, const float *dJdd, float *gwav,
+// One adjoint step k (s^{k+1} from s^{k+2}, s^{k+3}) on a tile set.
+void ac2_adj_tiles(const sg_model *m, int ns, int k, TileSet ts, const float *dJdd, float *gwav,
                    const float *snap, hipStream_t s)
 {
     Ac2AdjArgs b{};
     b.g = m->L.g2;
     b.nshots = ns;
-    b.tiles = near ? m->tiles_near : m->tiles_blk;
-    b.ntl = near ? m->n_near : m->n_blk;
+    b.tiles = tile_set(m, ts, b.ntl);
     b.s2 = m->s4[(k + 2) & 3];
     b.s3 = m->s4[(k + 3) & 3];
     b.s1 = m->s4[(k + 1) & 3];
@@ -970,7 +983,7 @@ void ac2_adj_tiles(const sg_model *m, int ns, int k, bool near, const float *dJd
     b.nrec = m->geom_nrec;
     b.snap = snap;
     b.grad = m->grad;
-    launch_ac2_adj(b, near, s);
+    launch_ac2_adj(b, ts == TS_LAYER, s);
 }
 
 // Adjoint step k, or steps k and k-1 when `two` (snap1 = w~^k, snap0 = w~^{k-1}).
@@ -983,12 +996,12 @@ void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, 
                               src_scale(m), s);
     };
     if (!two) {
-        ac2_adj_tiles(m, ns, k, true, dJdd, gwav, snap1, s);
-        ac2_adj_tiles(m, ns, k, false, dJdd, gwav, snap1, s);
+        for (TileSet ts : {TS_LAYER, TS_OTHER, TS_BLOCKED}) ac2_adj_tiles(m, ns, k, ts, dJdd, gwav, snap1, s);
         if (nodes) gather(k);
         return;
     }
-    ac2_adj_tiles(m, ns, k, true, dJdd, gwav, snap1, s);
+    ac2_adj_tiles(m, ns, k, TS_LAYER, dJdd, gwav, snap1, s);
+    ac2_adj_tiles(m, ns, k, TS_OTHER, dJdd, gwav, snap1, s);
     if (nodes) gather(k);
     Ac2Adj2Args b{};
     b.g = m->L.g2;
@@ -1010,7 +1023,8 @@ void ac2_adjoint(const sg_model *m, int ns, int k, bool two, const float *dJdd, 
     b.snap0 = snap0;
     b.grad = m->grad;
     launch_ac2_adj2(b, s);
-    ac2_adj_tiles(m, ns, k - 1, true, dJdd, gwav, snap0, s);
+    ac2_adj_tiles(m, ns, k - 1, TS_LAYER, dJdd, gwav, snap0, s);
+    ac2_adj_tiles(m, ns, k - 1, TS_OTHER, dJdd, gwav, snap0, s);
     if (nodes) gather(k - 1);
 }
 
