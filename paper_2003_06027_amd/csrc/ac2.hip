@@ -130,6 +130,15 @@ __device__ __forceinline__ void load_halo(const Grid2 &g, float *lds, int x0, in
     }
 }
 
+// The source term dt^2 f^k of one node: a separately rounded product, so
+// that no kernel fuses it into the addition that injects it (whether the
+// compiler would fuse depends on the kernel's shape; every kernel injecting
+// a source must round identically for the one- and two-step paths to agree).
+__device__ __forceinline__ float src_value(float scale, float w)
+{
+    return __fmul_rn(scale, w);
+}
+
 // A layer cell of the padded grid.
 __device__ __forceinline__ bool layer_cell_at(const Grid2 &g, int iz, int ix)
 {
@@ -196,7 +205,7 @@ __device__ __forceinline__ void fwd_tile(const Ac2FwdArgs &a, float *su, int til
     const float *um = a.um + so;
     float *uo = a.un + so;
     const long long src = a.src_f[shot];
-    const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
+    const float sval = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k]);
     float un[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -344,7 +353,14 @@ constexpr int H2 = 8;                       // u^k halo of a blocked tile
 constexpr int W0 = TX + 2 * H2, R0 = TZ + 2 * H2;
 constexpr int W1 = TX + 8, R1 = TZ + 8;
 constexpr int NRING = R1 * W1 - TZ * TX;    // the 4-cell ring around the tile
+// The forward blocked tiles take NTB threads (RB rows each): 8 waves per
+// SIMD in 55 VGPRs against 5 at 256 threads (C2: 141 -> 136 us per launch).
+// The adjoint keeps 256 threads (512 ran 2 % slower).
 constexpr int RING_IT = (NRING + NTH - 1) / NTH;
+constexpr int NTB = 512;
+constexpr int RB = TZ * TX / NTB;
+constexpr int RING_ITB = (NRING + NTB - 1) / NTB;
+static_assert(RB * NTB == TZ * TX && NTB % TX == 0, "whole rows per thread");
 
 // Load the tile + 8 of a field into LDS with 16-byte loads (rows start
 // 32-byte aligned: x0 - 8 + OX is a multiple of 8), optionally multiplied
@@ -386,7 +402,7 @@ __device__ __forceinline__ void ring_cell(int i, int &r, int &c)
     }
 }
 
-__global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
+__global__ __launch_bounds__(NTB) void ac2_fwd2_kernel(Ac2Fwd2Args a)
 {
     __shared__ float s0[R0 * W0];   // u^k on the tile + 8
     __shared__ float s1[R1 * W1];   // u^{k+1} on the tile + 4
@@ -399,24 +415,24 @@ __global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
     const float *um = a.um + so;
     const float *chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
     const long long src = a.src_f[shot];
-    const float sv0 = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
-    const float sv1 = a.src_scale * a.wav[(long long)shot * a.nt + a.k + 1];
+    const float sv0 = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k]);
+    const float sv1 = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k + 1]);
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
 
-    // own cells: column lx, rows ly*RPT .. +RPT-1; their chat and u^{k-1} first
-    float ch[RPT], pm[RPT];
+    // own cells: column lx, rows ly*RB .. +RB-1; their chat and u^{k-1} first
+    float ch[RB], pm[RB];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const long long f = fidx(g, z0 + ly * RPT + j, x0 + lx);
+    for (int j = 0; j < RB; ++j) {
+        const long long f = fidx(g, z0 + ly * RB + j, x0 + lx);
         ch[j] = chat[f];
         pm[j] = um[f];
     }
     // ring cells of the tile + 4
-    float rch[RING_IT], rpm[RING_IT];
-    long long rf[RING_IT];
+    float rch[RING_ITB], rpm[RING_ITB];
+    long long rf[RING_ITB];
 #pragma unroll
-    for (int it = 0; it < RING_IT; ++it) {
-        const int i = threadIdx.x + it * NTH;
+    for (int it = 0; it < RING_ITB; ++it) {
+        const int i = threadIdx.x + it * NTB;
         rf[it] = -1;
         if (i < NRING) {
             int r, c;
@@ -426,14 +442,14 @@ __global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
             rpm[it] = um[rf[it]];
         }
     }
-    load_tile8(g, a.u0 + so, nullptr, s0, x0, z0);
+    load_tile8<NTB>(g, a.u0 + so, nullptr, s0, x0, z0);
     __syncthreads();
 
     // step k: u^{k+1} on the tile + 4 (own cells, then the ring)
-    float uk[RPT], u1[RPT];
+    float uk[RB], u1[RB];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j;
+    for (int j = 0; j < RB; ++j) {
+        const int r = ly * RB + j;
         const long long f = fidx(g, z0 + r, x0 + lx);
         const float *cc = s0 + (r + H2) * W0 + lx + H2;
         const float wk = lap8(cc, W0);
@@ -446,8 +462,8 @@ __global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
         if (a.snap0) __builtin_nontemporal_store(wk, a.snap0 + so + f);
     }
 #pragma unroll
-    for (int it = 0; it < RING_IT; ++it) {
-        const int i = threadIdx.x + it * NTH;
+    for (int it = 0; it < RING_ITB; ++it) {
+        const int i = threadIdx.x + it * NTB;
         if (i < NRING) {
             int r, c;
             ring_cell(i, r, c);
@@ -463,8 +479,8 @@ __global__ __launch_bounds__(NTH) void ac2_fwd2_kernel(Ac2Fwd2Args a)
 
     // step k+1 on the tile
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = ly * RPT + j;
+    for (int j = 0; j < RB; ++j) {
+        const int r = ly * RB + j;
         const long long f = fidx(g, z0 + r, x0 + lx);
         const float wk = lap8(s1 + (r + 4) * W1 + lx + 4, W1);
         float inc = fmaf(ch[j], wk, u1[j] - uk[j]);
@@ -712,7 +728,7 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
     // pass B on the tile
     float *uo = a.un + so;
     const long long src = a.src_f[shot];
-    const float sval = a.src_scale * a.wav[(long long)shot * a.nt + a.k];
+    const float sval = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k]);
     float un[RN];
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
@@ -955,7 +971,7 @@ void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s)
 {
     const int nb = a.ntl * a.nshots;
     if (nb == 0) return;
-    ac2_fwd2_kernel<<<nb, NTH, 0, s>>>(a);
+    ac2_fwd2_kernel<<<nb, NTB, 0, s>>>(a);
 }
 
 void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s)
