@@ -267,6 +267,8 @@ def measure(a, S, synth, torch):
         extra = {} if len(init_m) == 1 else {"vs": dev(init_m[1]), "rho": dev(init_m[2])}
         strategy = tune.tune(d, sh, dev(c0), ckpt=ckpt, log=log, segments=2 if wl == "c4" else 4, **extra)
         torch.cuda.empty_cache()
+    # the timed run records per-phase HIP events, which need eager launches
+    strategy = tune.dataclasses.replace(strategy, graphs=False)
     # workspace beyond the minimum keeps the adjoint snapshots of the last
     # checkpoint segments (their recomputation is skipped); leave a margin
     # for the seismogram and residual buffers

@@ -278,8 +278,20 @@ SG_API int set_time_blocking(sg_model *m, int32_t steps);
  *                          shots per model falls back to that rule);
  *   SG_TUNE_BLOCK_X        elastic: cell blocks of 32 x 8 (32, the default)
  *                          or 64 x 4 (64) cells;
- * Chunks and block widths compute every value with the same operations, so
- * results do not change; the shot
+ *   SG_TUNE_GRAPHS         every physics: 1 runs each checkpoint segment of
+ *                          forward_shots (the checkpoint copies and K steps)
+ *                          and of adjoint_gradient (restore, recompute, K
+ *                          adjoint steps) as one HIP graph, captured on a
+ *                          stream of the model at the first call and
+ *                          replayed on `stream` by later calls with the same
+ *                          arguments (seismogram, wavelet, residual and
+ *                          wavelet-gradient pointers, shot counts, settings,
+ *                          geometry); other arguments re-capture the
+ *                          segments.  0 (the default): launches per step.
+ *                          Per-phase timing (set_profiling) is not recorded
+ *                          in graph mode.
+ * Chunks, block widths and graphs compute every value with the same
+ * operations, so results do not change; the shot
  * group changes the order in which the elastic gradient sums over shots
  * (fixed for a given setting, so results stay reproducible).  Changing the
  * layer chunk rebuilds and uploads the work list: the call waits for
@@ -287,7 +299,7 @@ SG_API int set_time_blocking(sg_model *m, int32_t steps);
  * after the upload.  Call between sweeps.  Errors: SG_EINVAL for an unknown
  * key, a value out of range, or a key that does not apply to the model. */
 enum { SG_TUNE_TIME_BLOCKING = 0, SG_TUNE_CHUNK_FWD3 = 1, SG_TUNE_CHUNK_ADJ3 = 2, SG_TUNE_CHUNK_LAYER3 = 3,
-       SG_TUNE_SHOT_GROUP = 4, SG_TUNE_BLOCK_X = 5 };
+       SG_TUNE_SHOT_GROUP = 4, SG_TUNE_BLOCK_X = 5, SG_TUNE_GRAPHS = 6 };
 SG_API int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream);
 
 /* Limited-memory BFGS helpers of the outer inversion loop (the paper's

@@ -18,6 +18,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -291,10 +292,22 @@ struct sg_model {
     bool profiling = false;
     std::vector<Span> spans;
     std::vector<hipEvent_t> pool;
+    // graph mode: one executable graph per checkpoint segment and sweep
+    // (forward; restore + recompute + adjoint), captured on a stream of the
+    // model and replayed on the caller's while the arguments they hold match
+    struct SegGraph { uint64_t key = 0; hipGraphExec_t exec = nullptr; };
+    bool graphs = false;
+    hipStream_t cap = nullptr;
+    std::vector<SegGraph> gfwd, gadj;
+    uint64_t epoch = 1;           // bumped by every change of launch settings or geometry
     ~sg_model()
     {
         for (auto &sp : spans) { pool.push_back(sp.a); pool.push_back(sp.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
+        for (auto *v : {&gfwd, &gadj})
+            for (auto &g : *v)
+                if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
@@ -368,6 +381,7 @@ int upload_geometry(sg_model *m, const sg_shots *sh, hipStream_t s)
                 return fail(SG_EINVAL, "shot %d receiver %d outside the grid", i, r);
     }
     if (same_geometry(m, sh)) return SG_OK;
+    ++m->epoch;                       // captured segment graphs hold the old lists and counts
     // the previous upload may still be reading the host vectors
     HIPCHECK(hipStreamSynchronize(s));
     if (L.elastic) {
@@ -1078,6 +1092,54 @@ void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float
     }
 }
 
+// FNV-1a over the arguments a segment's launches hold
+struct KeyHash {
+    uint64_t h = 1469598103934665603ull;
+    template <class T> KeyHash &add(T v)
+    {
+        uint64_t x = 0;
+        static_assert(sizeof(T) <= sizeof(x), "scalar key parts");
+        std::memcpy(&x, &v, sizeof(T));
+        for (int i = 0; i < 8; ++i) { h ^= (x >> (8 * i)) & 0xff; h *= 1099511628211ull; }
+        return *this;
+    }
+};
+
+// Issues one segment's work on s, or in graph mode launches the segment's
+// cached executable graph on s, capturing it first (on the model's capture
+// stream, so that the caller's stream may be the null stream) when there is
+// none or it was made for other arguments.
+template <class F>
+int run_segment(sg_model *m, std::vector<sg_model::SegGraph> &cache, int seg, uint64_t key, hipStream_t s,
+                F &&issue)
+{
+    if (!m->graphs) return issue(s);
+    if ((int)cache.size() <= seg) cache.resize(seg + 1);
+    sg_model::SegGraph &slot = cache[seg];
+    if (!slot.exec || slot.key != key) {
+        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+        slot.exec = nullptr;
+        if (!m->cap) HIPCHECK(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
+        HIPCHECK(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = issue(m->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(m->cap, &g);
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : fail(SG_EDEVICE, "segment capture failed: %s", hipGetErrorString(e));
+        }
+        const hipError_t e2 = hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            slot.exec = nullptr;
+            return fail(SG_EDEVICE, "segment graph instantiation failed: %s", hipGetErrorString(e2));
+        }
+        slot.key = key;
+    }
+    HIPCHECK(hipGraphLaunch(slot.exec, s));
+    return SG_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -1359,40 +1421,48 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
         if (seg < seg0) return nullptr;
         return m->store + ((size_t)(seg - seg0) * K + (k - seg * K)) * L.nsnap * L.field;
     };
-    int cu = 0;
-    int span = -1;
-    for (int k = 0; k < nt;) {
-        if (k % K == 0) {
-            span_end(m, span, s);
-            if (save_ckpt) {
-                // state at the start of step k: u^k, u^{k-1}, then the layer fields
-                // (acoustic: u^k, u^{k-1} first; elastic: the fields in order)
-                float *ck = m->ckpt + (size_t)(k / K) * nf * L.field;
-                for (int i = 0; i < nf; ++i) {
-                    const float *src = ad2 ? ad2_state(m, k, i)
-                                     : ac2 ? (i < 2 ? m->u4[(k + 4 - i) & 3] : ac2_aux(m->fwd, k - 1, i - 2))
-                                     : L.elastic || i >= 2 ? m->fwd[i]
-                                           : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
-                    HIPCHECK(hipMemcpyAsync(ck + i * L.field, src, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
-                }
+    // one checkpoint segment: the checkpoint of its first state, then its steps
+    auto issue = [&](int seg, hipStream_t st) -> int {
+        const int k0 = seg * K, k1 = std::min(k0 + K, nt);
+        int cu = k0 & 1;                  // 3-D / elastic: u^k in fwd[cu]
+        if (save_ckpt) {
+            // state at the start of step k0: u^k, u^{k-1}, then the layer fields
+            // (acoustic: u^k, u^{k-1} first; elastic: the fields in order)
+            float *ck = m->ckpt + (size_t)seg * nf * L.field;
+            for (int i = 0; i < nf; ++i) {
+                const float *src = ad2 ? ad2_state(m, k0, i)
+                                 : ac2 ? (i < 2 ? m->u4[(k0 + 4 - i) & 3] : ac2_aux(m->fwd, k0 - 1, i - 2))
+                                 : L.elastic || i >= 2 ? m->fwd[i]
+                                       : (i == 0 ? m->fwd[cu] : m->fwd[1 - cu]);
+                HIPCHECK(hipMemcpyAsync(ck + i * L.field, src, sizeof(float) * fs, hipMemcpyDeviceToDevice, st));
             }
-            span = span_begin(m, 0, std::min(K, nt - k), s);
         }
-        if (ac2) {
-            // two steps per launch on the blocked tiles, within one checkpoint segment
-            const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < std::min((k / K + 1) * K, nt);
-            ac2_forward(m, ns, sh->wavelet, k, two, sp, stored(k), two ? stored(k + 1) : nullptr, s);
-            k += two ? 2 : 1;
-        } else if (ad2) {
-            ad2_fwd_step(m, ns, sh->wavelet, k, sp, stored(k), s);
-            ++k;
-        } else {
-            fwd_step(m, ns, sh->wavelet, cu, k, sp, stored(k), s);
-            cu = 1 - cu;
-            ++k;
+        for (int k = k0; k < k1;) {
+            if (ac2) {
+                // two steps per launch on the blocked tiles, within one checkpoint segment
+                const bool two = m->steps_per_launch == 2 && m->n_blk > 0 && k + 1 < k1;
+                ac2_forward(m, ns, sh->wavelet, k, two, sp, stored(k), two ? stored(k + 1) : nullptr, st);
+                k += two ? 2 : 1;
+            } else if (ad2) {
+                ad2_fwd_step(m, ns, sh->wavelet, k, sp, stored(k), st);
+                ++k;
+            } else {
+                fwd_step(m, ns, sh->wavelet, cu, k, sp, stored(k), st);
+                cu = 1 - cu;
+                ++k;
+            }
         }
+        return SG_OK;
+    };
+    const uint64_t key = KeyHash().add(m->epoch).add(sp).add(sh->wavelet).add(save_ckpt).add(seg0).add(ns)
+                             .add(sh->nrec).h;
+    for (int seg = 0; seg < L.nseg; ++seg) {
+        const int steps = std::min(K, nt - seg * K);
+        const int span = m->graphs ? -1 : span_begin(m, 0, steps, s);
+        rc = run_segment(m, m->gfwd, seg, key, s, [&](hipStream_t st) { return issue(seg, st); });
+        if (rc) return rc;
+        span_end(m, span, s);
     }
-    span_end(m, span, s);
     HIPCHECK(hipGetLastError());
     m->have_ckpt = save_ckpt != 0;
     m->have_store = save_ckpt != 0 && m->n_store > 0;
@@ -1435,14 +1505,16 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
     if (L.elastic)
         for (int i = 0; i < 8; ++i) launch_fill(m->tmp[i], fs, 0.f, s);
     if (ad2) ad2_adj_step(m, ns, nt, dJ_dd, nullptr, nullptr, s);   // lambda^nt
-    int ca = 0;
     const int seg0 = m->have_store ? L.nseg - m->n_store : L.nseg;
-    for (int seg = L.nseg - 1; seg >= 0; --seg) {
+    const bool blk = ac2 && m->steps_per_launch == 2 && m->n_blk > 0;
+    // one checkpoint segment: restore and recompute its snapshots (unless the
+    // forward kept them), then its adjoint steps; with `spans` (eager runs)
+    // the recompute and adjoint loops are timed apart
+    auto issue = [&](int seg, hipStream_t st, bool spans) -> int {
         const int k0 = seg * K, k1 = std::min(k0 + K, nt);
         const bool kept = seg >= seg0;   // snapshots written by the forward
         float *sbase = kept ? m->store + (size_t)(seg - seg0) * K * L.nsnap * L.field : m->snap;
         auto snap = [&](int k) { return sbase + (size_t)(k - k0) * L.nsnap * L.field; };
-        const bool blk = ac2 && m->steps_per_launch == 2 && m->n_blk > 0;
         int span = -1;
         if (!kept) {
             const float *ck = m->ckpt + (size_t)seg * nf * L.field;
@@ -1450,42 +1522,50 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
                 float *dst = ad2 ? ad2_state(m, k0, i)
                            : ac2 ? (i < 2 ? m->u4[(k0 + 4 - i) & 3] : ac2_aux(m->fwd, k0 - 1, i - 2))
                                  : m->fwd[i];
-                HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, s));
+                HIPCHECK(hipMemcpyAsync(dst, ck + i * L.field, sizeof(float) * fs, hipMemcpyDeviceToDevice, st));
             }
             int cu = 0;
-            span = span_begin(m, 1, k1 - k0, s);
+            if (spans) span = span_begin(m, 1, k1 - k0, st);
             for (int k = k0; k < k1;) {
                 if (ac2) {
                     const bool two = blk && k + 1 < k1;
-                    ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, s);
+                    ac2_forward(m, ns, sh->wavelet, k, two, nullptr, snap(k), two ? snap(k + 1) : nullptr, st);
                     k += two ? 2 : 1;
                 } else if (ad2) {
-                    ad2_fwd_step(m, ns, sh->wavelet, k, nullptr, snap(k), s);
+                    ad2_fwd_step(m, ns, sh->wavelet, k, nullptr, snap(k), st);
                     ++k;
                 } else {
-                    fwd_step(m, ns, sh->wavelet, cu, k, nullptr, snap(k), s);
+                    fwd_step(m, ns, sh->wavelet, cu, k, nullptr, snap(k), st);
                     cu = 1 - cu;
                     ++k;
                 }
             }
-            span_end(m, span, s);
+            span_end(m, span, st);
         }
-        span = span_begin(m, 2, k1 - k0, s);
+        int ca = (nt - k1) & 1;          // 3-D / elastic: s^{k+2} in adj[ca]
+        span = spans ? span_begin(m, 2, k1 - k0, st) : -1;
         for (int k = k1 - 1; k >= k0;) {
             if (ac2) {
                 const bool two = blk && k - 1 >= k0;
-                ac2_adjoint(m, ns, k, two, dJ_dd, g_wavelet, snap(k), two ? snap(k - 1) : nullptr, s);
+                ac2_adjoint(m, ns, k, two, dJ_dd, g_wavelet, snap(k), two ? snap(k - 1) : nullptr, st);
                 k -= two ? 2 : 1;
             } else if (ad2) {
-                ad2_adj_step(m, ns, k, dJ_dd, g_wavelet, snap(k), s);
+                ad2_adj_step(m, ns, k, dJ_dd, g_wavelet, snap(k), st);
                 --k;
             } else {
-                adj_step(m, ns, ca, k, dJ_dd, g_wavelet, snap(k), s);
+                adj_step(m, ns, ca, k, dJ_dd, g_wavelet, snap(k), st);
                 ca = 1 - ca;
                 --k;
             }
         }
-        span_end(m, span, s);
+        span_end(m, span, st);
+        return SG_OK;
+    };
+    const uint64_t key = KeyHash().add(m->epoch).add(dJ_dd).add(g_wavelet).add(sh->wavelet).add(seg0).add(ns)
+                             .add(sh->nrec).h;
+    for (int seg = L.nseg - 1; seg >= 0; --seg) {
+        rc = run_segment(m, m->gadj, seg, key, s, [&](hipStream_t st) { return issue(seg, st, !m->graphs); });
+        if (rc) return rc;
     }
     if (L.elastic)
         launch_el2_finalize(L.g2, m->d.nmodels, ns / m->d.nmodels, el_group(m, ns / m->d.nmodels), m->grad,
@@ -1535,9 +1615,14 @@ int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream)
     g_err.clear();
     if (!m) return fail(SG_EINVAL, "model is NULL");
     const bool three = !m->L.elastic && m->d.ndim == 3;
+    ++m->epoch;                       // segment graphs captured under the old settings are stale
     switch (key) {
     case SG_TUNE_TIME_BLOCKING:
         return set_time_blocking(m, value);
+    case SG_TUNE_GRAPHS:
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "graphs: 0 or 1");
+        m->graphs = value != 0;
+        return SG_OK;
     case SG_TUNE_CHUNK_FWD3:
     case SG_TUNE_CHUNK_ADJ3:
     case SG_TUNE_CHUNK_LAYER3: {
@@ -1583,6 +1668,7 @@ int set_time_blocking(sg_model *m, int32_t steps)
     if (!m) return fail(SG_EINVAL, "model is NULL");
     if (steps != 1 && steps != 2) return fail(SG_EINVAL, "steps per launch must be 1 or 2, got %d", steps);
     m->steps_per_launch = steps;
+    ++m->epoch;
     return SG_OK;
 }
 

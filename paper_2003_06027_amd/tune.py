@@ -3,10 +3,9 @@ physics), with a JSON cache.
 
 Candidates (none changes what is computed; see set_tuning in the C ABI):
 * 2-D acoustic: 1 or 2 steps per launch on the blocked tiles (results are
-  bitwise identical, traffic and launch count differ), each eager or as one
-  hipGraph holding the whole checkpointed forward, misfit and adjoint of the
-  batch, replayed (useful where per-launch overhead dominates: small grids,
-  many short steps);
+  bitwise identical, traffic and launch count differ), each eager or with
+  the library's segment graphs (one HIP graph per checkpoint segment of the
+  forward and of the adjoint sweep, captured once and replayed);
 * 3-D acoustic: the z-chunk lengths of the forward tile passes (16-64
   planes), of the adjoint tile passes (32-64) and of the layer work items
   (16-64), searched one at a time from the defaults (each moves different
@@ -52,6 +51,7 @@ class Strategy:
     def apply(self, m):
         """Set the strategy's launch settings on model m (those its physics has)."""
         d = m.d
+        m.set_tuning(S.SG_TUNE_GRAPHS, int(self.graphs))
         if d.physics == S.SG_ACOUSTIC and d.ndim == 2:
             m.set_tuning(S.SG_TUNE_TIME_BLOCKING, self.time_blocking)
         elif d.physics == S.SG_ACOUSTIC and d.ndim == 3:
@@ -99,8 +99,9 @@ CHUNKS_LAYER3 = (16, 32, 64)
 
 
 class Runner:
-    """One checkpointed forward + misfit + adjoint of a shot batch, launched
-    eagerly or replayed from a captured graph, with fixed buffers."""
+    """One checkpointed forward + misfit + adjoint of a shot batch with fixed
+    buffers (so that the library's segment graphs, when the strategy has
+    them, are captured by the first step and replayed by the next)."""
 
     def __init__(self, d, shots, vp, obs, strategy: Strategy, ckpt=0, vs=None, rho=None):
         self.shots = shots
@@ -109,18 +110,7 @@ class Runner:
         self.obs = obs
         self.seis = torch.empty_like(obs)
         self.resid = torch.empty_like(obs)
-        self.graph = None
         self.out = None
-        if strategy.graphs:
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                self._eager()                 # geometry upload and first touch outside the capture
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            self.graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(self.graph):
-                self._eager()
 
     def _eager(self):
         self.m.forward(self.shots, seis=self.seis, save_ckpt=True)
@@ -135,13 +125,9 @@ class Runner:
         return self.out
 
     def step(self):
-        if self.graph is not None:
-            self.graph.replay()
-            return self.out
         return self._eager()
 
     def close(self):
-        self.graph = None
         self.m.close()
 
 

@@ -1,0 +1,150 @@
+"""The library's segment graphs (set_tuning SG_TUNE_GRAPHS): each checkpoint
+segment of the forward and of the adjoint sweep captured once as a HIP graph
+(checkpoint copies, restore copies and every step's launches) and replayed.
+Every replay is compared bit for bit with the eager launches, with other
+eager GPU work and synchronisations between replays; new buffers or new
+launch settings re-capture the segments."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import S, synth, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _sweep(m, sh, obs, seis, resid, gw=None, g=None):
+    m.forward(sh, seis=seis, save_ckpt=True)
+    m.misfit(seis, obs, resid=resid)
+    kw = {"g_wavelet": gw} if gw is not None else {}
+    if g is not None:
+        outs = g if isinstance(g, tuple) else (g,)
+        kw.update({"g_vp": outs[0]})
+        if len(outs) > 1:
+            kw.update({"g_vs": outs[1], "g_rho": outs[2]})
+    out = m.gradient(sh, resid, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def _check(label, make_model, sh, obs, with_gw=False, reps=3):
+    gw0 = torch.zeros_like(sh.wavelet) if with_gw else None
+    m0 = make_model()
+    seis0, r0 = torch.empty_like(obs), torch.empty_like(obs)
+    g0 = _sweep(m0, sh, obs, seis0, r0, gw0)
+    g0 = tuple(t.clone() for t in (g0 if isinstance(g0, tuple) else (g0,)))
+    m = make_model()
+    m.set_tuning(S.SG_TUNE_GRAPHS, 1)
+    seis, r = torch.empty_like(obs), torch.empty_like(obs)
+    gw = torch.zeros_like(sh.wavelet) if with_gw else None
+    g = None
+    for rep in range(reps):
+        seis.zero_()
+        if gw is not None:
+            gw.zero_()
+        g = _sweep(m, sh, obs, seis, r, gw, g)
+        gg = g if isinstance(g, tuple) else (g,)
+        assert torch.equal(seis, seis0), (label, rep)
+        assert all(torch.equal(a, b) for a, b in zip(gg, g0)), (label, rep)
+        if gw is not None:
+            assert torch.equal(gw, gw0), (label, rep)
+        _sweep(m0, sh, obs, seis0.clone(), r0.clone(), None)   # unrelated eager work between replays
+    # new seismogram and residual buffers: the segments are captured again
+    seis2, r2 = torch.empty_like(obs), torch.empty_like(obs)
+    g2 = _sweep(m, sh, obs, seis2, r2, gw)
+    g2 = g2 if isinstance(g2, tuple) else (g2,)
+    assert torch.equal(seis2, seis0) and all(torch.equal(a, b) for a, b in zip(g2, g0)), label
+    print(f"{label}: {reps} replays and one re-capture equal the eager launches bit for bit")
+    m.close()
+    m0.close()
+    return m
+
+
+def test_segment_graphs_2d_acoustic_stored_segments_and_time_blocking():
+    cfg = synth.C1.replace(nx=300, nz=140, npml=16, nt=230)
+    c = 1600.0 + 1200.0 * synth.smooth_random(8, (cfg.nz, cfg.nx), 8.0, 0.0, 1.0)
+    src = np.array([[150, 70], [20, 3]], dtype=np.int32)
+    rec = np.stack([np.stack([np.arange(0, 300, 3), np.full(100, 2)], -1)] * 2).astype(np.int32)
+    d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, dx=cfg.dx, dt=cfg.dt, pml_vmax=2800.0)
+    wav = torch.stack([S.ricker(15.0, 0.07, cfg.dt, cfg.nt), S.ricker(12.0, 0.08, cfg.dt, cfg.nt)])
+    sh = S.Shots(src, rec, wav)
+    mt = S.Model(d, dev(c), 2, rec.shape[1], 17)
+    obs = mt.forward(sh, save_ckpt=False).clone()
+    mt.close()
+    c0 = dev(synth.smooth(c, 6.0))
+    _check("2-D, stored segments", lambda: S.Model(d, c0, 2, rec.shape[1], 17, store_segments=4), sh, obs)
+
+    def one_step():
+        m = S.Model(d, c0, 2, rec.shape[1], 17)
+        m.set_time_blocking(1)
+        return m
+    _check("2-D, one step per launch", one_step, sh, obs)
+
+
+def test_segment_graphs_with_source_nodes_and_wavelet_gradient():
+    cfg = synth.C1.replace(nx=160, nz=120, npml=12, nt=200)
+    c = 1500.0 + 1000.0 * synth.smooth_random(4, (cfg.nz, cfg.nx), 6.0, 0.0, 1.0)
+    nodes = np.array([[[60, 50], [61, 50], [100, 80]]], dtype=np.int32)
+    rec = np.stack([np.stack([np.arange(0, 160, 2), np.full(80, 2)], -1)]).astype(np.int32)
+    d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, dx=cfg.dx, dt=cfg.dt, pml_vmax=2600.0)
+    w = torch.stack([S.ricker(15.0, 0.07, cfg.dt, cfg.nt), -0.5 * S.ricker(12.0, 0.08, cfg.dt, cfg.nt),
+                     S.ricker(10.0, 0.1, cfg.dt, cfg.nt)])[None].contiguous()
+    sh = S.Shots(nodes, rec, w)
+    mt = S.Model(d, dev(c), 1, rec.shape[1], 15)
+    obs = mt.forward(sh, save_ckpt=False).clone()
+    mt.close()
+    c0 = dev(synth.smooth(c, 5.0))
+    _check("2-D, several source nodes", lambda: S.Model(d, c0, 1, rec.shape[1], 15), sh, obs, with_gw=True)
+
+
+def test_segment_graphs_3d_and_elastic():
+    nx, ny, nz, P, nt = 40, 36, 44, 12, 60
+    c = 1600.0 + 1200.0 * synth.smooth_random(21, (nz, ny, nx), 3.0, 0.0, 1.0)
+    d = S.desc(ndim=3, nx=nx, ny=ny, nz=nz, npml=P, nt=nt, dx=10.0, dt=1e-3, pml_vmax=2800.0)
+    src = np.array([[20, 18, 2]], dtype=np.int32)
+    xs, ys = np.meshgrid(np.arange(0, nx, 4), np.arange(0, ny, 4), indexing="xy")
+    rec = np.stack([xs.ravel(), ys.ravel(), np.zeros(xs.size, dtype=int)], -1)[None].astype(np.int32)
+    sh = S.Shots(src, rec, S.ricker(20.0, 0.05, 1e-3, nt)[None].contiguous())
+    mt = S.Model(d, dev(c), 1, rec.shape[1], 9)
+    obs = mt.forward(sh, save_ckpt=False).clone()
+    mt.close()
+    c0 = dev(synth.smooth(c, 2.0))
+    _check("3-D", lambda: S.Model(d, c0, 1, rec.shape[1], 9), sh, obs, reps=2)
+
+    nx, nz, P, nt = 70, 50, 10, 160
+    vp = 1800.0 + 2200.0 * synth.smooth_random(6027, (nz, nx), 8.0, 0.0, 1.0)
+    vs, rho = vp / 1.75, 310.0 * vp ** 0.25
+    d = S.desc(ndim=2, physics=S.SG_ELASTIC, nx=nx, nz=nz, npml=P, nt=nt, dx=5.0, dt=0.5e-3, pml_vmax=4000.0,
+               f0_pml=15.0)
+    src = np.array([[20, 5], [45, 20]], dtype=np.int32)
+    mt_ = np.array([[1.0, 1.0, 0.0], [-0.5, 0.5, 0.86]])
+    rec = np.stack([np.stack([np.arange(0, nx, 3), np.zeros(24)], -1)] * 2).astype(np.int32)
+    sh = S.Shots(src, rec, S.ricker(20.0, 0.05, 0.5e-3, nt)[None].repeat(2, 1).contiguous(), mt=mt_)
+    mo = S.Model(d, dev(vp), 2, rec.shape[1], 13, vs=dev(vs), rho=dev(rho))
+    obs = mo.forward(sh, save_ckpt=False).clone()
+    mo.close()
+    m0 = [dev(synth.smooth(a, 4.0)) for a in (vp, vs, rho)]
+    _check("elastic", lambda: S.Model(d, m0[0], 2, rec.shape[1], 13, vs=m0[1], rho=m0[2]), sh, obs, reps=2)
+
+
+def test_segment_graphs_follow_new_settings():
+    """A launch setting changed between calls re-captures the segments."""
+    cfg = synth.C1.replace(nx=200, nz=120, npml=10, nt=150)
+    c = 1600.0 + 900.0 * synth.smooth_random(2, (cfg.nz, cfg.nx), 6.0, 0.0, 1.0)
+    src = np.array([[100, 60]], dtype=np.int32)
+    rec = np.stack([np.stack([np.arange(0, 200, 4), np.full(50, 3)], -1)]).astype(np.int32)
+    d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, dx=cfg.dx, dt=cfg.dt, pml_vmax=2500.0)
+    sh = S.Shots(src, rec, S.ricker(15.0, 0.07, cfg.dt, cfg.nt)[None].contiguous())
+    m = S.Model(d, dev(c), 1, rec.shape[1], 12)
+    m.set_tuning(S.SG_TUNE_GRAPHS, 1)
+    seis = torch.empty((1, 1, cfg.nt, rec.shape[1]), dtype=torch.float32, device="cuda")
+    m.forward(sh, seis=seis, save_ckpt=False)
+    a = seis.clone()
+    m.set_time_blocking(1)
+    seis.zero_()
+    m.forward(sh, seis=seis, save_ckpt=False)
+    torch.cuda.synchronize()
+    assert torch.equal(seis, a)
+    with pytest.raises(S.SeisError):
+        m.set_tuning(S.SG_TUNE_GRAPHS, 2)
+    m.close()
