@@ -69,12 +69,15 @@ __device__ __forceinline__ float lap3(const float *cc, int W, const float *q)
     return fmaf(A0X3, q[4], s);
 }
 
-__device__ __forceinline__ int xcd_work_id(int nblocks)
+// Work item of this workgroup: the hardware order, which deals consecutive
+// items (neighbouring tiles of one z chunk) to the 8 XCDs in turn, so that
+// all XCDs march the same chunks at once.  Giving each XCD a contiguous
+// range of items instead, as the 2-D kernels do, was measured slower at
+// 448^3: interior forward 465 -> 359 us, interior adjoint 736 -> 669 us,
+// forward step 1088 -> 963 us in hardware order.
+__device__ __forceinline__ int work_id()
 {
-    const int b = blockIdx.x;
-    const int per = nblocks / NXCD, rem = nblocks % NXCD;
-    const int x = b % NXCD, j = b / NXCD;
-    return x * per + min(x, rem) + j;
+    return (int)blockIdx.x;
 }
 
 __device__ __forceinline__ bool plane_near_z(const Grid3 &g, int z)
@@ -181,7 +184,7 @@ void ac3_phi_kernel(Ac3PhiArgs a)
     __shared__ float pu[2][(TY3 + 8) * W];
     __shared__ float pp[2][(TY3 + 8) * W];
     const Grid3 &g = a.g;
-    const int w = xcd_work_id((int)gridDim.x);
+    const int w = work_id();
     const int shot = w / a.nitems;
     const int4 it = a.items[w - shot * a.nitems];
     const int ty = it.x / g.ntx, tx = it.x - ty * g.ntx;
@@ -313,7 +316,7 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
     __shared__ float xch[REC ? TX3 * TY3 : 1];
     const Grid3 &g = a.g;
     const int nzf = (g.NZ + g.zcf - 1) / g.zcf;
-    const int w = xcd_work_id(a.ntl * nzf * a.nshots);
+    const int w = work_id();
     const int shot = w / (a.ntl * nzf);
     const int rem = w - shot * a.ntl * nzf;
     const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
@@ -527,7 +530,7 @@ void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
     constexpr int W = TX3 + 8;
     __shared__ float pc[2][(TY3 + 8) * W];
     const Grid3 &g = a.g;
-    const int w = xcd_work_id((int)gridDim.x);
+    const int w = work_id();
     const int shot = w / a.nitems;
     const int4 it = a.items[w - shot * a.nitems];
     const int ty = it.x / g.ntx, tx = it.x - ty * g.ntx;
@@ -656,7 +659,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
     __shared__ float xch[TX3 * TY3];
     const Grid3 &g = a.g;
     const int nxy = g.ntx * g.nty;
-    const int w = xcd_work_id(a.ntl * g.nzc * a.nshots);
+    const int w = work_id();
     const int shot = w / (a.ntl * g.nzc);
     const int rem = w - shot * a.ntl * g.nzc;
     const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
