@@ -38,6 +38,13 @@
 namespace sg {
 namespace {
 
+// 512 threads per 64 x 32 tile, 4 rows each: 61-65 VGPRs and 8 waves per
+// SIMD, against 84-96 VGPRs and 5 waves with 256 threads of 8 rows (C2 grid:
+// forward 391 -> 347 us, adjoint 480 -> 450 us per step).  The rarely used
+// variants without seismograms or snapshots spill one register at 8 waves.
+constexpr int NTA = 512;
+constexpr int RPA = TZ * TX / NTA;
+static_assert(RPA * NTA == TZ * TX && NTA % TX == 0, "whole rows per thread");
 constexpr int AH = 3;              // halo of the composite stencil Dm' khat Dp'
 constexpr int AW = TX + 2 * AH;    // node tile with halo: AR rows of AW
 constexpr int AR = TZ + 2 * AH;
@@ -81,9 +88,9 @@ __device__ __forceinline__ bool near_edge(const Grid2 &g, int x0, int z0)
 template <class CellOf, class ValOf>
 __device__ __forceinline__ void gather_entries(float *acc, const int *ent, int b, int e, CellOf cell_of, ValOf val_of)
 {
-    for (int i = threadIdx.x; i < TX * TZ; i += NTH) acc[i] = 0.f;
+    for (int i = threadIdx.x; i < TX * TZ; i += NTA) acc[i] = 0.f;
     __syncthreads();
-    for (int i = b + (int)threadIdx.x; i < e; i += NTH) {
+    for (int i = b + (int)threadIdx.x; i < e; i += NTA) {
         const int c = cell_of(ent[i]);
         if (i > b && cell_of(ent[i - 1]) == c) continue;
         float v = 0.f;
@@ -95,7 +102,7 @@ __device__ __forceinline__ void gather_entries(float *acc, const int *ent, int b
 
 // ------------------------------------------------------------------ forward
 // Work split of a tile: thread (lx, ly) owns column x0 + lx and rows
-// r0 = ly*RPT .. r0+RPT-1.  The z fluxes of its column (its own half rows and
+// r0 = ly*RPA .. r0+RPA-1.  The z fluxes of its column (its own half rows and
 // the three around them that its Dm' needs) are computed in registers from
 // its column of the u tile; the x fluxes go through LDS (own half column by
 // every thread, the three extra columns x0-2, x0-1, x0+TX by the first 3*TZ
@@ -137,35 +144,35 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     const long long so = (long long)shot * g.plane;
     const float *u = a.u + so;
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPT, ix = x0 + lx;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPA, ix = x0 + lx;
 
-    for (int i = tid; i < AR * AW; i += NTH) {
+    for (int i = tid; i < AR * AW; i += NTA) {
         const int r = i / AW, c = i - r * AW;
         su[i] = u[fr(g, z0 - AH + r, x0 - AH + c)];
     }
-    float cz[RPT + 4];                    // chat of rows z0+r0-2 .. z0+r0+RPT+1
+    float cz[RPA + 4];                    // chat of rows z0+r0-2 .. z0+r0+RPA+1
 #pragma unroll
-    for (int m = 0; m < RPT + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
-    float um[RPT];                        // u^{k-1} of the own rows, loaded early
+    for (int m = 0; m < RPA + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
+    float um[RPA];                        // u^{k-1} of the own rows, loaded early
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) um[j] = __builtin_nontemporal_load(a.um + so + fr(g, z0 + r0 + j, ix));
+    for (int j = 0; j < RPA; ++j) um[j] = __builtin_nontemporal_load(a.um + so + fr(g, z0 + r0 + j, ix));
     __syncthreads();
 
-    // z fluxes of the own column at half rows z0+r0-2+m, m = 0 .. RPT+2
-    float uc[RPT], hz[RPT];
+    // z fluxes of the own column at half rows z0+r0-2+m, m = 0 .. RPA+2
+    float uc[RPA], hz[RPA];
     {
-        float uz[RPT + 6];
+        float uz[RPA + 6];
 #pragma unroll
-        for (int m = 0; m < RPT + 6; ++m) uz[m] = su[(r0 + m) * AW + lx + AH];
-        float qz[RPT + 3];
+        for (int m = 0; m < RPA + 6; ++m) uz[m] = su[(r0 + m) * AW + lx + AH];
+        float qz[RPA + 3];
 #pragma unroll
-        for (int m = 0; m < RPT + 3; ++m) {
+        for (int m = 0; m < RPA + 3; ++m) {
             const int iz = z0 + r0 - 2 + m;
             const float G = d4(uz[m], uz[m + 1], uz[m + 2], uz[m + 3]);
             float q = 0.f;
             if (!NEAR || (iz >= 0 && iz < g.NZ)) {
                 const long long f = fr(g, iz, ix);
-                const bool own = m >= 2 && m < RPT + 2 && ix < g.NX;
+                const bool own = m >= 2 && m < RPA + 2 && ix < g.NX;
                 float S = G;
                 if constexpr (NEAR) {
                     const float p = fmaf(a.t.bhz[iz], a.psz[so + f], a.t.ahz[iz] * G);
@@ -180,13 +187,13 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
             qz[m] = q;
         }
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
+        for (int j = 0; j < RPA; ++j) {
             uc[j] = uz[j + 3];
             hz[j] = d4(qz[j], qz[j + 1], qz[j + 2], qz[j + 3]);
         }
     }
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
+    for (int j = 0; j < RPA; ++j) {
         const float c0 = cz[j + 2];
         float c1 = __shfl_down(c0, 1, TX);
         if (lx == TX - 1) c1 = ch[fr(g, z0 + r0 + j, ix + 1)];
@@ -207,9 +214,9 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
         gather_entries(su, a.src_ent, sb, se, [](int e) { return src_cell(e); },
                        [&](int e) { return a.src_scale * w[(long long)src_node(e) * a.nt]; });
     }
-    float un[RPT];
+    float un[RPA];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
+    for (int j = 0; j < RPA; ++j) {
         const int r = r0 + j, iz = z0 + r;
         const float *qa = qx + r * QXW + lx;
         const float Hx = d4(qa[0], qa[1], qa[2], qa[3]);
@@ -237,9 +244,9 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
         if (b < e) {                      // uniform over the block
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) su[(r0 + j) * TX + lx] = un[j];
+            for (int j = 0; j < RPA; ++j) su[(r0 + j) * TX + lx] = un[j];
             __syncthreads();
-            for (int i = b + tid; i < e; i += NTH) {
+            for (int i = b + tid; i < e; i += NTA) {
                 const int ent = a.rec_ent[i];
                 a.seis[((long long)shot * a.nt + a.k) * a.nrec + rec_id(ent)] = su[rec_cell(ent)];
             }
@@ -248,7 +255,7 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
 }
 
 template <bool SNAP, bool REC>
-__global__ __launch_bounds__(NTH) void ad2_fwd_kernel(Ad2FwdArgs a)
+__global__ __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(8))) void ad2_fwd_kernel(Ad2FwdArgs a)
 {
     __shared__ float su[AR * AW];
     __shared__ float qx[TZ * QXW];
@@ -304,10 +311,10 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
     const long long so = (long long)shot * g.plane;
     const float *l1 = a.l1 + so;
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPT, ix = x0 + lx;
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPA, ix = x0 + lx;
 
     // Hb = lambda^{k+1} + Y^{k+1} per axis on the tile and its halo
-    for (int i = tid; i < AR * AW; i += NTH) {
+    for (int i = tid; i < AR * AW; i += NTA) {
         const int r = i / AW, c = i - r * AW;
         const int iz = z0 - AH + r, jx = x0 - AH + c;
         const long long f = fr(g, iz, jx);
@@ -330,30 +337,30 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             hx[i] = l;
         }
     }
-    float cz[RPT + 4];
+    float cz[RPA + 4];
 #pragma unroll
-    for (int m = 0; m < RPT + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
-    float l2[RPT];                        // lambda^{k+2} of the own rows, loaded early
+    for (int m = 0; m < RPA + 4; ++m) cz[m] = ch[fr(g, z0 + r0 - 2 + m, ix)];
+    float l2[RPA];                        // lambda^{k+2} of the own rows, loaded early
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) l2[j] = __builtin_nontemporal_load(a.l2 + so + fr(g, z0 + r0 + j, ix));
+    for (int j = 0; j < RPA; ++j) l2[j] = __builtin_nontemporal_load(a.l2 + so + fr(g, z0 + r0 + j, ix));
     __syncthreads();
     const float *hzz = NEAR ? hz : hx;
 
-    float lam[RPT], dz[RPT], gnz[RPT];   // lambda^{k+1}, Dm' Gb_z and the z gradient of the own rows
+    float lam[RPA], dz[RPA], gnz[RPA];   // lambda^{k+1}, Dm' Gb_z and the z gradient of the own rows
     {
-        float hc[RPT + 6];
+        float hc[RPA + 6];
 #pragma unroll
-        for (int m = 0; m < RPT + 6; ++m) hc[m] = hzz[(r0 + m) * AW + lx + AH];
-        float gz[RPT + 3], pz[RPT + 3];
+        for (int m = 0; m < RPA + 6; ++m) hc[m] = hzz[(r0 + m) * AW + lx + AH];
+        float gz[RPA + 3], pz[RPA + 3];
 #pragma unroll
-        for (int m = 0; m < RPT + 3; ++m) {
+        for (int m = 0; m < RPA + 3; ++m) {
             const int iz = z0 + r0 - 2 + m;
             const float qb = -d4(hc[m], hc[m + 1], hc[m + 2], hc[m + 3]);
             float Gb = 0.f;
             pz[m] = 0.f;
             if (!NEAR || (iz >= 0 && iz < g.NZ)) {
                 const long long f = fr(g, iz, ix);
-                const bool own = m >= 2 && m < RPT + 2 && ix < g.NX;
+                const bool own = m >= 2 && m < RPA + 2 && ix < g.NX;
                 const float Sb = 0.5f * (cz[m] + cz[m + 1]) * qb;
                 Gb = Sb;
                 if constexpr (NEAR) {
@@ -362,13 +369,13 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
                     if (own) a.zzn[so + f] = z;
                 }
                 if constexpr (GRAD) {
-                    if (m >= 1 && m < RPT + 2) pz[m] = qb * a.snz[so + f];
+                    if (m >= 1 && m < RPA + 2) pz[m] = qb * a.snz[so + f];
                 }
             }
             gz[m] = Gb;
         }
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
+        for (int j = 0; j < RPA; ++j) {
             const int iz = z0 + r0 + j;
             lam[j] = NEAR ? 0.f : hc[j + 3];
             dz[j] = d4(gz[j], gz[j + 1], gz[j + 2], gz[j + 3]);
@@ -376,9 +383,9 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             if (iz == g.NZ - 1) gnz[j] += 0.5f * pz[j + 2];
         }
     }
-    float px[RPT];                        // x products at the own half column
+    float px[RPA];                        // x products at the own half column
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
+    for (int j = 0; j < RPA; ++j) {
         const float c0 = cz[j + 2];
         float c1 = __shfl_down(c0, 1, TX);
         if (lx == TX - 1) c1 = ch[fr(g, z0 + r0 + j, ix + 1)];
@@ -405,7 +412,7 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
                        [&](int en) { return d[rec_id(en)]; });
     }
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
+    for (int j = 0; j < RPA; ++j) {
         const int r = r0 + j, iz = z0 + r;
         const float *ga = qx + r * QXW + lx;
         const float Dx = d4(ga[0], ga[1], ga[2], ga[3]);
@@ -428,7 +435,7 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(NTH) void ad2_adj_kernel(Ad2AdjArgs a)
+__global__ __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(8))) void ad2_adj_kernel(Ad2AdjArgs a)
 {
     __shared__ float hx[AR * AW];
     __shared__ float hz[AR * AW];
@@ -506,19 +513,19 @@ void launch_ad2_fwd(const Ad2FwdArgs &a, hipStream_t s)
     const int n = a.g.ntx * a.g.ntz * a.nshots;
     const bool rec = a.seis && a.nrec > 0;
     if (a.snx) {
-        if (rec) ad2_fwd_kernel<true, true><<<n, NTH, 0, s>>>(a);
-        else     ad2_fwd_kernel<true, false><<<n, NTH, 0, s>>>(a);
+        if (rec) ad2_fwd_kernel<true, true><<<n, NTA, 0, s>>>(a);
+        else     ad2_fwd_kernel<true, false><<<n, NTA, 0, s>>>(a);
     } else {
-        if (rec) ad2_fwd_kernel<false, true><<<n, NTH, 0, s>>>(a);
-        else     ad2_fwd_kernel<false, false><<<n, NTH, 0, s>>>(a);
+        if (rec) ad2_fwd_kernel<false, true><<<n, NTA, 0, s>>>(a);
+        else     ad2_fwd_kernel<false, false><<<n, NTA, 0, s>>>(a);
     }
 }
 
 void launch_ad2_adj(const Ad2AdjArgs &a, hipStream_t s)
 {
     const int n = a.g.ntx * a.g.ntz * a.nshots;
-    if (a.snx) ad2_adj_kernel<true><<<n, NTH, 0, s>>>(a);
-    else       ad2_adj_kernel<false><<<n, NTH, 0, s>>>(a);
+    if (a.snx) ad2_adj_kernel<true><<<n, NTA, 0, s>>>(a);
+    else       ad2_adj_kernel<false><<<n, NTA, 0, s>>>(a);
 }
 
 void launch_ad2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx, float *chat, float *cpad,
