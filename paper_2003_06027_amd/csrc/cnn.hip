@@ -167,19 +167,15 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         }
 }
 
-// Weight gradient, K = pixels.  Wavefront w owns the taps w, w + 4, w + 8
-// (those below 9) over all four tile rows (K-blocks of 32 pixels), so that
-// it keeps the accumulators of at most three taps; wavefront 0 also forms
-// the bias gradient.  K index 8g + e of a lane maps to pixel 4e + g of the
-// block, the same for both operands, so that the eight 2-byte LDS reads of
-// a fragment hit distinct banks across the lane groups.
+// Weight gradient, K = pixels.  Each wavefront owns one tile row (two
+// K-blocks of 32 pixels); K index 8g + e of a lane maps to pixel 4e + g of
+// the block, the same for both operands, so that the eight 2-byte LDS reads
+// of a fragment hit distinct banks across the lane groups.
 struct WgradArgs {
     const u16 *dy, *x;
     float *part;  // [gridDim.x][PMID]
     int N, H, W, tx, ty, ntiles;
 };
-
-constexpr int WTAPS = 3;   // taps per wavefront at most
 
 __global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
 {
@@ -189,11 +185,11 @@ __global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
     const int r = lane & 15, g = lane >> 4;
     const bf16x8 ones = __builtin_bit_cast(bf16x8, u16x8{0x3f80, 0x3f80, 0x3f80, 0x3f80,
                                                          0x3f80, 0x3f80, 0x3f80, 0x3f80});
-    f32x4 acc[WTAPS][2][2];
+    f32x4 acc[9][2][2];
     f32x4 accb[2];
 #pragma unroll
-    for (int i = 0; i < WTAPS; ++i)
-        acc[i][0][0] = acc[i][0][1] = acc[i][1][0] = acc[i][1][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t)
+        acc[t][0][0] = acc[t][0][1] = acc[t][1][0] = acc[t][1][1] = f32x4{0.f, 0.f, 0.f, 0.f};
     accb[0] = accb[1] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -204,64 +200,65 @@ __global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
         stage_halo(a.x, n, a.H, a.W, y0, x0, lx);
         stage_plain(a.dy, n, a.H, a.W, y0, x0, lg);
         __syncthreads();
-#pragma unroll 1
-        for (int row = 0; row < TH; ++row) {
 #pragma unroll
-            for (int kb = 0; kb < 2; ++kb) {
-                u16x8 ga0, ga1;
+        for (int kb = 0; kb < 2; ++kb) {
+            u16x8 ga0, ga1;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const u16 *p = lg + (row * TW + kb * 32 + 4 * e + g) * PS + r;
-                    ga0[e] = p[0];
-                    ga1[e] = p[16];
-                }
-                const bf16x8 A0 = __builtin_bit_cast(bf16x8, ga0), A1 = __builtin_bit_cast(bf16x8, ga1);
-                if (wv == 0) {
-                    accb[0] = mfma(A0, ones, accb[0]);
-                    accb[1] = mfma(A1, ones, accb[1]);
-                }
+            for (int e = 0; e < 8; ++e) {
+                const u16 *p = lg + (wv * TW + kb * 32 + 4 * e + g) * PS + r;
+                ga0[e] = p[0];
+                ga1[e] = p[16];
+            }
+            const bf16x8 A0 = __builtin_bit_cast(bf16x8, ga0), A1 = __builtin_bit_cast(bf16x8, ga1);
+            accb[0] = mfma(A0, ones, accb[0]);
+            accb[1] = mfma(A1, ones, accb[1]);
 #pragma unroll
-                for (int i = 0; i < WTAPS; ++i) {
-                    const int t = wv + 4 * i;
-                    if (t >= 9) continue;                  // uniform per wavefront
-                    const int ky = t / 3, kx = t - 3 * (t / 3);
+            for (int t = 0; t < 9; ++t) {
+                const int ky = t / 3, kx = t - 3 * (t / 3);
 #pragma unroll
-                    for (int ib = 0; ib < 2; ++ib) {
-                        u16x8 xb;
+                for (int ib = 0; ib < 2; ++ib) {
+                    u16x8 xb;
 #pragma unroll
-                        for (int e = 0; e < 8; ++e)
-                            xb[e] = lx[((row + ky) * LW + kb * 32 + 4 * e + g + kx) * PS + 16 * ib + r];
-                        const bf16x8 B = __builtin_bit_cast(bf16x8, xb);
-                        acc[i][0][ib] = mfma(A0, B, acc[i][0][ib]);
-                        acc[i][1][ib] = mfma(A1, B, acc[i][1][ib]);
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        xb[e] = lx[((wv + ky) * LW + kb * 32 + 4 * e + g + kx) * PS + 16 * ib + r];
+                    const bf16x8 B = __builtin_bit_cast(bf16x8, xb);
+                    acc[t][0][ib] = mfma(A0, B, acc[t][0][ib]);
+                    acc[t][1][ib] = mfma(A1, B, acc[t][1][ib]);
                 }
             }
         }
     }
 
-    // each tap's sums belong to one wavefront: written straight to the
-    // workgroup's partial row (the bias by wavefront 0)
-    float *out = a.part + (long long)blockIdx.x * PMID;
+    // fixed-order sum over the four wavefronts in LDS, then one partial row
+    float *red = reinterpret_cast<float *>(smem);
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wv == w) {
 #pragma unroll
-    for (int i = 0; i < WTAPS; ++i) {
-        const int t = wv + 4 * i;
-        if (t >= 9) continue;
+            for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+                for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int ib = 0; ib < 2; ++ib)
+                    for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int co = 16 * cb + 4 * g + j, ci = 16 * ib + r;
-                    out[(co * 9 + t) * CH + ci] = acc[i][cb][ib][j];
-                }
+                        for (int j = 0; j < 4; ++j) {
+                            const int co = 16 * cb + 4 * g + j, ci = 16 * ib + r;
+                            const int idx = (co * 9 + t) * CH + ci;
+                            red[idx] = (w == 0 ? 0.f : red[idx]) + acc[t][cb][ib][j];
+                        }
+            if (r == 0)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int idx = WMID + 16 * cb + 4 * g + j;
+                        red[idx] = (w == 0 ? 0.f : red[idx]) + accb[cb][j];
+                    }
+        }
     }
-    if (wv == 0 && r == 0)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) out[WMID + 16 * cb + 4 * g + j] = accb[cb][j];
+    __syncthreads();
+    float *out = a.part + (long long)blockIdx.x * PMID;
+    for (int i = threadIdx.x; i < PMID; i += NT) out[i] = red[i];
 }
 
 // out[i] = sum over b of part[b][i] in FP64, in a fixed order: lane l of
