@@ -70,14 +70,31 @@ __device__ __forceinline__ float lap3(const float *cc, int W, const float *q)
 }
 
 // Work item of this workgroup: the hardware order, which deals consecutive
-// items (neighbouring tiles of one z chunk) to the 8 XCDs in turn, so that
-// all XCDs march the same chunks at once.  Giving each XCD a contiguous
-// range of items instead, as the 2-D kernels do, was measured slower at
-// 448^3: interior forward 465 -> 359 us, interior adjoint 736 -> 669 us,
-// forward step 1088 -> 963 us in hardware order.
+// items to the 8 XCDs in turn, so that all XCDs march the same chunks at
+// once.  Giving each XCD a contiguous range of items instead, as the 2-D
+// kernels do, was measured slower at 448^3: interior forward 465 -> 359 us,
+// interior adjoint 736 -> 669 us, forward step 1088 -> 963 us in hardware
+// order.
 __device__ __forceinline__ int work_id()
 {
     return (int)blockIdx.x;
+}
+
+// Work item of a tile pass over a list of ntl xy tiles: the (shot, z chunk)
+// pair cs and the tile's position t in the list.  Workgroups still go to
+// the XCDs in turn and all XCDs march the same chunk, but each XCD takes a
+// contiguous run of the list (whole rows of tiles), so the halo rings a tile
+// reads were mostly brought into the same XCD's L2 by its neighbours.  The
+// grid holds band_blocks(ntl) workgroups per (shot, chunk); those past the
+// list return at once.
+__host__ __device__ __forceinline__ int band_per(int ntl) { return (ntl + NXCD - 1) / NXCD; }
+__device__ __forceinline__ bool band_item(int ntl, int &cs, int &t)
+{
+    const int per = band_per(ntl);
+    const int b = (int)blockIdx.x, x = b % NXCD, s = b / NXCD;
+    cs = s / per;
+    t = x * per + (s - cs * per);
+    return t < ntl;
 }
 
 __device__ __forceinline__ bool plane_near_z(const Grid3 &g, int z)
@@ -316,10 +333,9 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
     __shared__ float xch[REC ? TX3 * TY3 : 1];
     const Grid3 &g = a.g;
     const int nzf = (g.NZ + g.zcf - 1) / g.zcf;
-    const int w = work_id();
-    const int shot = w / (a.ntl * nzf);
-    const int rem = w - shot * a.ntl * nzf;
-    const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
+    int cs, ti;
+    if (!band_item(a.ntl, cs, ti)) return;
+    const int shot = cs / nzf, zc = cs - shot * nzf, tile = a.tiles[a.t0 + ti];
     const int nxy = g.ntx * g.nty;
     const int ty = tile / g.ntx, tx = tile - ty * g.ntx;
     const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * g.zcf, z1 = min(z0 + g.zcf, g.NZ);
@@ -659,10 +675,9 @@ void ac3_adj_kernel(Ac3AdjArgs a)
     __shared__ float xch[TX3 * TY3];
     const Grid3 &g = a.g;
     const int nxy = g.ntx * g.nty;
-    const int w = work_id();
-    const int shot = w / (a.ntl * g.nzc);
-    const int rem = w - shot * a.ntl * g.nzc;
-    const int zc = rem / a.ntl, tile = a.tiles[a.t0 + rem - zc * a.ntl];
+    int cs, ti;
+    if (!band_item(a.ntl, cs, ti)) return;
+    const int shot = cs / g.nzc, zc = cs - shot * g.nzc, tile = a.tiles[a.t0 + ti];
     const int ty = tile / g.ntx, tx = tile - ty * g.ntx;
     const int x0 = tx * TX3, y0 = ty * TY3, z0 = zc * g.zca, z1 = min(z0 + g.zca, g.NZ);
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
@@ -980,8 +995,8 @@ void launch_ac3_fwd_part(Ac3FwdArgs a, int t0, int ntl, hipStream_t s)
 {
     a.t0 = t0;
     a.ntl = ntl;
-    const int nb = ntl * ((a.g.NZ + a.g.zcf - 1) / a.g.zcf) * a.nshots;
-    if (nb == 0) return;
+    if (ntl == 0 || a.nshots == 0) return;
+    const int nb = band_per(ntl) * NXCD * ((a.g.NZ + a.g.zcf - 1) / a.g.zcf) * a.nshots;
     const bool snap = a.snap != nullptr, rec = a.seis != nullptr;
     if (snap) { if (rec) ac3_fwd_kernel<true, true, LAYER><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<true, false, LAYER><<<nb, NTH3, 0, s>>>(a); }
     else      { if (rec) ac3_fwd_kernel<false, true, LAYER><<<nb, NTH3, 0, s>>>(a); else ac3_fwd_kernel<false, false, LAYER><<<nb, NTH3, 0, s>>>(a); }
@@ -1001,8 +1016,8 @@ void launch_ac3_adj(const Ac3AdjArgs &a, hipStream_t s)
         Ac3AdjArgs b = a;
         b.t0 = part ? a.nnear : 0;
         b.ntl = part ? nxy - a.nnear : a.nnear;
-        const int nb = b.ntl * a.g.nzc * a.nshots;
-        if (nb == 0) continue;
+        if (b.ntl == 0 || a.nshots == 0) continue;
+        const int nb = band_per(b.ntl) * NXCD * a.g.nzc * a.nshots;
         if (part) ac3_adj_kernel<false><<<nb, NTH3, 0, s>>>(b);
         else ac3_adj_kernel<true><<<nb, NTH3, 0, s>>>(b);
     }
