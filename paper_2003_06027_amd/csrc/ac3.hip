@@ -204,6 +204,7 @@ void ac3_phi_kernel(Ac3PhiArgs a)
     const int w = work_id();
     const int shot = w / a.nitems;
     const int4 it = a.items[w - shot * a.nitems];
+    if (it.x < 0) return;                  // padding of the launch order
     const int ty = it.x / g.ntx, tx = it.x - ty * g.ntx;
     const int x0 = tx * TX3, y0 = ty * TY3, z0 = it.y, z1 = it.z;
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;
@@ -549,6 +550,7 @@ void ac3_phi_adj_kernel(Ac3PhiAdjArgs a)
     const int w = work_id();
     const int shot = w / a.nitems;
     const int4 it = a.items[w - shot * a.nitems];
+    if (it.x < 0) return;                  // padding of the launch order
     const int ty = it.x / g.ntx, tx = it.x - ty * g.ntx;
     const int x0 = tx * TX3, y0 = ty * TY3, z0 = it.y, z1 = it.z;
     const int tid = threadIdx.x, lx = tid % TX3, ly = tid / TX3;

@@ -123,6 +123,15 @@ int check_shots(const sg_desc *d, int max_shots)
     return SG_OK;
 }
 
+// Entries of the 3-D layer pass's work list: at most two items per TZC_MIN
+// planes of every xy tile, and the padding of at most two groups per
+// TZC_MIN planes (see build_items3).
+size_t items3_cap(int ntiles, int NZ)
+{
+    const size_t per_col = (size_t)(NZ + TZC_MIN - 1) / TZC_MIN + 2;
+    return (size_t)ntiles * per_col + 2 * per_col * (NXCD - 1);
+}
+
 Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
 {
     Layout L{};
@@ -214,7 +223,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_soff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
     L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
-    L.off_items = take(L.ndim == 3 ? sizeof(int4) * (size_t)L.ntiles * ((L.g3.NZ + TZC_MIN - 1) / TZC_MIN + 2) : 0);
+    L.off_items = take(L.ndim == 3 ? sizeof(int4) * items3_cap(L.ntiles, L.g3.NZ) : 0);
     L.off_flag = take(sizeof(int));
     L.total = o;
     return L;
@@ -329,25 +338,45 @@ bool same_geometry(const sg_model *m, const sg_shots *sh)
 
 // The 3-D layer pass's work list (host copy): every plane of the xy tiles
 // that touch the layer in x or y, the two z slabs of the others, in items of
-// at most zci planes.  Returns nonzero if it would overflow its workspace
-// slot (sized for TZC_MIN-plane items).
+// at most zci planes.  The items are grouped by their first plane, and each
+// group is laid out in launch order: the hardware deals consecutive
+// workgroups to the XCDs in turn, so the group's n items are padded to a
+// multiple of NXCD (entries with tile -1, which return at once) and placed
+// so that XCD x takes the contiguous run x * per .. x * per + per - 1 of
+// them (per = ceil(n / NXCD)).  All XCDs then work on the same planes, each
+// on neighbouring tiles.  Returns nonzero, leaving the model's list as it
+// was, if the list would overflow its workspace slot.
 int build_items3(sg_model *m, int zci)
 {
     const Layout &L = m->L;
     const Grid3 &g = L.g3;
-    m->h_items3.clear();
+    std::vector<int4> raw;
     for (int t = 0; t < L.ntiles; ++t) {
         const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
         const bool xy = x0 < g.P || x0 + TX3 > g.P + g.nx || y0 < g.P || y0 + TY3 > g.P + g.ny;
         auto add = [&](int za, int zb) {
-            for (int z = za; z < zb; z += zci) m->h_items3.push_back(make_int4(t, z, std::min(z + zci, zb), 0));
+            for (int z = za; z < zb; z += zci) raw.push_back(make_int4(t, z, std::min(z + zci, zb), 0));
         };
         if (xy) add(0, g.NZ);
         else { add(0, g.P); add(g.P + g.nz, g.NZ); }
     }
+    std::stable_sort(raw.begin(), raw.end(), [](const int4 &a, const int4 &b) { return a.y < b.y; });
+    std::vector<int4> out;
+    for (size_t b = 0; b < raw.size();) {
+        size_t e = b;
+        while (e < raw.size() && raw[e].y == raw[b].y) ++e;
+        const size_t n = e - b, per = (n + NXCD - 1) / NXCD;
+        for (size_t sl = 0; sl < per * NXCD; ++sl) {
+            const size_t i = (sl % NXCD) * per + sl / NXCD;
+            out.push_back(i < n ? raw[b + i] : make_int4(-1, 0, 0, 0));
+        }
+        b = e;
+    }
+    if (out.size() > items3_cap(L.ntiles, g.NZ)) return 1;    // the model keeps its list
+    m->h_items3.swap(out);
     m->n_items3 = (int)m->h_items3.size();
     m->zci = zci;
-    return (size_t)m->n_items3 > (size_t)L.ntiles * ((g.NZ + TZC_MIN - 1) / TZC_MIN + 2);
+    return 0;
 }
 
 // Shots per thread of the elastic passes for spm shots per model: the
