@@ -682,6 +682,8 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
         }
     }
     load_tile8<NTN>(g, a.u + so, nullptr, su, x0, z0);      // u^k on the tile + 8
+    const long long src = a.src_f[shot];
+    const float sval = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k]);
     __syncthreads();
 
     // pass A: phi~^k on the own layer cells (written out) and the halo cells
@@ -727,8 +729,6 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
 
     // pass B on the tile
     float *uo = a.un + so;
-    const long long src = a.src_f[shot];
-    const float sval = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k]);
     float un[RN];
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
@@ -902,6 +902,21 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
     }
     __syncthreads();
 
+    // the snapshot and the gradient accumulator of the own cells, loaded
+    // here so that their latency overlaps pass B (loaded with the other
+    // operands before pass A, they would spill)
+    float snv[RN], grv[RN];
+#pragma unroll
+    for (int j = 0; j < RN; ++j) {
+        const int iz = z0 + ly * RN + j;
+        snv[j] = grv[j] = 0.f;
+        if (iz < g.NZ && inx) {
+            const long long f = fidx(g, iz, ix);
+            snv[j] = __builtin_nontemporal_load(a.snap + so + f);
+            grv[j] = __builtin_nontemporal_load(a.grad + so + f);
+        }
+    }
+
     // pass B on the tile
     float *s1o = a.s1 + so;
     float av[RN];
@@ -950,7 +965,7 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
             const long long f = fidx(g, iz, ix);
             const float s1 = av[j] / (1.f + hxc + hzr[j]);
             __builtin_nontemporal_store(s1, s1o + f);
-            __builtin_nontemporal_store(fmaf(s1, __builtin_nontemporal_load(a.snap + so + f), __builtin_nontemporal_load(a.grad + so + f)), a.grad + so + f);
+            __builtin_nontemporal_store(fmaf(s1, snv[j], grv[j]), a.grad + so + f);
             if (a.gwav && f == src) a.gwav[(long long)shot * a.nt + a.k] = s1 * a.src_scale;
         }
     }
