@@ -620,7 +620,8 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
     const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
     const int x0 = tx * TX, z0 = tz * TZ;
     const long long so = (long long)shot * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    // ly is uniform over a wavefront (TX lanes): rows and their tables in scalar registers
+    const int tid = threadIdx.x, lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX);
     const int ix = x0 + lx;
     const bool inx = ix < g.NX;
     const float *__restrict__ chat = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
@@ -632,13 +633,15 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
 
     // operands of the own cells and of the halo cells first (none depends on LDS)
     const float hxc = inx ? a.hx[ix] : 0.f, pxc = inx ? a.px[ix] : 0.f, ihxc = inx ? a.ihx[ix] : 0.f;
-    float ch[RN], pm[RN], hzr[RN], fx[RN], fz[RN];
+    float ch[RN], pm[RN], hzr[RN], fx[RN], fz[RN], pzr[RN], ihzr[RN];
     unsigned lay = 0u;
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
         const int iz = z0 + ly * RN + j;
         const long long f = fidx(g, iz, ix);
         ch[j] = pm[j] = hzr[j] = fx[j] = fz[j] = 0.f;
+        pzr[j] = iz < g.NZ ? a.pz[iz] : 0.f;
+        ihzr[j] = iz < g.NZ ? a.ihz[iz] : 0.f;
         if (iz < g.NZ && inx) {
             ch[j] = chat[f];
             pm[j] = __builtin_nontemporal_load(um + f);
@@ -696,9 +699,9 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
             const long long f = fidx(g, iz, ix);
             const float *cu = su + (r + H2) * W0 + lx + H2;
             const float qx = 2.f * (hzr[j] - hxc) * ihxc;
-            const float qz = 2.f * (hxc - hzr[j]) * a.ihz[iz];
+            const float qz = 2.f * (hxc - hzr[j]) * ihzr[j];
             vx = pxc * fx[j] + qx * d8(cu, 1);
-            vz = a.pz[iz] * fz[j] + qz * d8(cu, (long long)W0);
+            vz = pzr[j] * fz[j] + qz * d8(cu, (long long)W0);
             phx[f] = vx;
             phz[f] = vz;
         }
@@ -775,10 +778,11 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
 }
 
 // 34.8 KB of LDS per tile allow 4 tiles per CU: 8 waves per SIMD at 512
-// threads, which the forward reaches in 64 VGPRs without spills (256-thread
+// threads, which the forward reaches in 56 VGPRs without spills (256-thread
 // tiles held 4 waves per SIMD and ran the C2 near tiles 16 % slower).  The
-// adjoint keeps 76 VGPRs and 6 waves: limited to 64 it spills and runs 9 %
-// slower.
+// adjoint keeps 66 VGPRs and 7 waves: limited to 64 it spills and runs 4 %
+// slower.  Taking the row index through readfirstlane puts the rows' z
+// tables in scalar registers (forward 62 -> 56, adjoint 78 -> 66 VGPRs).
 template <bool SNAP, bool REC>
 __global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(8))) void ac2_near_kernel(Ac2FwdArgs a)
 {
@@ -797,7 +801,8 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
     const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
     const int x0 = tx * TX, z0 = tz * TZ;
     const long long so = (long long)shot * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    // ly is uniform over a wavefront (TX lanes): rows and their tables in scalar registers
+    const int tid = threadIdx.x, lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX);
     const int ix = x0 + lx;
     const bool inx = ix < g.NX;
     const float *__restrict__ s2 = a.s2 + so;
@@ -809,7 +814,7 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
     float *__restrict__ czo = a.cz + so;
 
     const float hxc = inx ? a.hx[ix] : 0.f, pxc = inx ? a.px[ix] : 0.f, ihxc = inx ? a.ihx[ix] : 0.f;
-    float sc2[RN], q3[RN], hzr[RN], fx[RN], fz[RN];
+    float sc2[RN], q3[RN], hzr[RN], fx[RN], fz[RN], pzr[RN], ihzr[RN];
     unsigned lay = 0u;
 #pragma unroll
     for (int j = 0; j < RN; ++j) {
@@ -817,6 +822,8 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
         const long long f = fidx(g, iz, ix);
         sc2[j] = s2[f];
         q3[j] = hzr[j] = fx[j] = fz[j] = 0.f;
+        pzr[j] = iz < g.NZ ? a.pz[iz] : 0.f;
+        ihzr[j] = iz < g.NZ ? a.ihz[iz] : 0.f;
         if (iz < g.NZ && inx) {
             q3[j] = __builtin_nontemporal_load(s3 + f);
             hzr[j] = a.hz[iz];
@@ -871,9 +878,9 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
             const long long f = fidx(g, iz, ix);
             const float *cc = sc + (r + H2) * W0 + lx + H2;
             const float qx = 2.f * (hzr[j] - hxc) * ihxc;
-            const float qz = 2.f * (hxc - hzr[j]) * a.ihz[iz];
+            const float qz = 2.f * (hxc - hzr[j]) * ihzr[j];
             vx = pxc * fx[j] - qx * d8(cc, 1);
-            vz = a.pz[iz] * fz[j] - qz * d8(cc, (long long)W0);
+            vz = pzr[j] * fz[j] - qz * d8(cc, (long long)W0);
             cxo[f] = vx;
             czo[f] = vz;
         }
