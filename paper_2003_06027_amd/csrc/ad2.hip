@@ -38,10 +38,13 @@
 namespace sg {
 namespace {
 
-// 512 threads per 64 x 32 tile, 4 rows each: 61-65 VGPRs and 8 waves per
-// SIMD, against 84-96 VGPRs and 5 waves with 256 threads of 8 rows (C2 grid:
-// forward 391 -> 347 us, adjoint 480 -> 450 us per step).  The rarely used
-// variants without seismograms or snapshots spill one register at 8 waves.
+// 512 threads per 64 x 32 tile, 4 rows each: 8 waves per SIMD, against 5
+// with 256 threads of 8 rows (C2 grid: forward 391 -> 347 us, adjoint 480 ->
+// 450 us per step).  A thread's rows are uniform over its wavefront (TX
+// lanes); taken through readfirstlane, they put the z tables in scalar
+// registers (46-62 VGPRs against 61-65, with a spill, before), which leaves
+// room to load the adjoint's gradient accumulator with the other operands
+// before the first barrier (adjoint 457 -> 413 us per step).
 constexpr int NTA = 512;
 constexpr int RPA = TZ * TX / NTA;
 static_assert(RPA * NTA == TZ * TX && NTA % TX == 0, "whole rows per thread");
@@ -144,7 +147,7 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     const long long so = (long long)shot * g.plane;
     const float *u = a.u + so;
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPA, ix = x0 + lx;
+    const int tid = threadIdx.x, lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX), r0 = ly * RPA, ix = x0 + lx;
 
     for (int i = tid; i < AR * AW; i += NTA) {
         const int r = i / AW, c = i - r * AW;
@@ -311,7 +314,7 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
     const long long so = (long long)shot * g.plane;
     const float *l1 = a.l1 + so;
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX, r0 = ly * RPA, ix = x0 + lx;
+    const int tid = threadIdx.x, lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX), r0 = ly * RPA, ix = x0 + lx;
 
     // Hb = lambda^{k+1} + Y^{k+1} per axis on the tile and its halo
     for (int i = tid; i < AR * AW; i += NTA) {
@@ -343,6 +346,14 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
     float l2[RPA];                        // lambda^{k+2} of the own rows, loaded early
 #pragma unroll
     for (int j = 0; j < RPA; ++j) l2[j] = __builtin_nontemporal_load(a.l2 + so + fr(g, z0 + r0 + j, ix));
+    float gacc[RPA];                      // the gradient accumulator of the own rows, loaded early
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int j = 0; j < RPA; ++j) {
+            const int iz = z0 + r0 + j;
+            gacc[j] = iz < g.NZ && ix < g.NX ? __builtin_nontemporal_load(a.gn + so + fr(g, iz, ix)) : 0.f;
+        }
+    }
     __syncthreads();
     const float *hzz = NEAR ? hz : hx;
 
@@ -429,7 +440,7 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             float v = lc + ((lc - l2[j]) - (Dx + dz[j]));
             if (inj) v += hx[r * TX + lx];
             __builtin_nontemporal_store(v, a.l0 + so + f);
-            if constexpr (GRAD) __builtin_nontemporal_store(__builtin_nontemporal_load(a.gn + so + f) + gn, a.gn + so + f);
+            if constexpr (GRAD) __builtin_nontemporal_store(gacc[j] + gn, a.gn + so + f);
         }
     }
 }
