@@ -172,6 +172,20 @@ SG_API int init_model(const sg_desc *d, const float *vp, const float *vs, const 
                int32_t max_shots, int32_t max_rec, int32_t ckpt_every, void *ws,
                size_t ws_bytes, sg_stream_t stream, sg_model **out);
 
+/* New parameters for a prepared model (paper: a new theta in A(theta),
+ * Eq. (1), as each iteration of an inversion makes it): the same checks and
+ * preparation as init_model, on the model's grid, shots and workspace; the
+ * geometry, work lists, tables and captured segment graphs are kept.
+ *   vp, vs, rho: DEVICE FP32 as in init_model (vs, rho NULL for acoustic
+ *                models); copied, may be freed afterwards.
+ * Synchronises `stream` once (the stability check).  The checkpoints and
+ * stored snapshots of an earlier forward belong to the old parameters:
+ * adjoint_gradient returns SG_ESTATE until a checkpointed forward runs.
+ * Errors: SG_EINVAL (NULL model or vp, vs/rho given for acoustic or missing
+ * for elastic models, non-positive or non-finite values), SG_EUNSTABLE; the
+ * model keeps its old parameters on an error before preparation. */
+SG_API int update_model(sg_model *m, const float *vp, const float *vs, const float *rho, sg_stream_t stream);
+
 /* Forward modelling of a batch of shots (Eq. (1) with the source term F_k):
  * runs all nt steps and writes the seismograms.
  *   seis: DEVICE FP32 [nshots][1][nt][nrec], overwritten;

@@ -307,13 +307,13 @@ struct sg_model {
     struct SegGraph { uint64_t key = 0; hipGraphExec_t exec = nullptr; };
     bool graphs = false;
     hipStream_t cap = nullptr;
-    std::vector<SegGraph> gfwd, gadj;
+    std::vector<SegGraph> gfwd[2], gadj;   // forward: without / with checkpoints
     uint64_t epoch = 1;           // bumped by every change of launch settings or geometry
     ~sg_model()
     {
         for (auto &sp : spans) { pool.push_back(sp.a); pool.push_back(sp.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
-        for (auto *v : {&gfwd, &gadj})
+        for (auto *v : {&gfwd[0], &gfwd[1], &gadj})
             for (auto &g : *v)
                 if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (cap) (void)hipStreamDestroy(cap);
@@ -1202,30 +1202,14 @@ size_t snapshot_segment_bytes(const sg_desc *d, int32_t max_shots, int32_t ckpt_
     return sizeof(float) * (size_t)L.K * L.nsnap * L.field;
 }
 
-int init_model(const sg_desc *d, const float *vp, const float *vs, const float *rho,
-               int32_t max_shots, int32_t max_rec, int32_t ckpt_every, void *ws, size_t ws_bytes,
-               sg_stream_t stream, sg_model **out)
+// Stability of the velocities (read back from the device; one
+// synchronisation of s): positive and finite, 0 < vs < vp and rho > 0 for
+// elastic models, the leapfrog limit of the scheme with a 5 % margin, and
+// the damping limit of the acoustic layer.
+int check_velocities(const sg_desc *d, const Layout &L, const float *vp, const float *vs, const float *rho,
+                     hipStream_t s)
 {
-    g_err.clear();
-    if (!out) return fail(SG_EINVAL, "out is NULL");
-    *out = nullptr;
-    int rc = check_desc(d);
-    if (rc) return rc;
     const bool elastic = d->physics == SG_ELASTIC;
-    if (!elastic && (vs || rho)) return fail(SG_EINVAL, "vs and rho must be NULL for acoustic models");
-    if (elastic && (!vs || !rho)) return fail(SG_EINVAL, "elastic models need vs and rho");
-    if (!vp || !ws) return fail(SG_EINVAL, "vp and ws must be device pointers");
-    if (max_shots < 1 || max_rec < 0 || ckpt_every < 0)
-        return fail(SG_EINVAL, "max_shots >= 1, max_rec >= 0 and ckpt_every >= 0 required");
-    if (max_shots % d->nmodels) return fail(SG_EINVAL, "max_shots must be a multiple of nmodels");
-    if ((long long)max_rec >= (1LL << REC_ID_BITS)) return fail(SG_EINVAL, "at most %d receivers per shot", (1 << REC_ID_BITS) - 1);
-    if (const int e = check_shots(d, max_shots)) return e;
-    if (d->ndim == 3 && d->nz + 2 * d->npml >= (1 << 12)) return fail(SG_EINVAL, "3-D grids are limited to 4095 padded planes in z");
-    const Layout L = make_layout(d, max_shots, max_rec, ckpt_every);
-    if (ws_bytes < L.total) return fail(SG_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
-    if ((uintptr_t)ws % ALIGN) return fail(SG_EINVAL, "workspace must be %zu-byte aligned", ALIGN);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-
     // stability: velocity range from the device copy
     const size_t nphys = (size_t)d->nmodels * d->nx * (d->ndim == 3 ? d->ny : 1) * d->nz;
     std::vector<float> hv(nphys);
@@ -1258,6 +1242,35 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     }
     const double zmax = d->npml > 0 ? 3.0 * d->pml_vmax * std::log(1.0 / d->pml_R) / (2.0 * d->npml * d->dx) : 0.0;
     if (!elastic && !L.ad2 && zmax * d->dt > 0.3) return fail(SG_EUNSTABLE, "zeta_max*dt = %.3f above 0.3", zmax * d->dt);
+    return SG_OK;
+}
+
+int init_model(const sg_desc *d, const float *vp, const float *vs, const float *rho,
+               int32_t max_shots, int32_t max_rec, int32_t ckpt_every, void *ws, size_t ws_bytes,
+               sg_stream_t stream, sg_model **out)
+{
+    g_err.clear();
+    if (!out) return fail(SG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_desc(d);
+    if (rc) return rc;
+    const bool elastic = d->physics == SG_ELASTIC;
+    if (!elastic && (vs || rho)) return fail(SG_EINVAL, "vs and rho must be NULL for acoustic models");
+    if (elastic && (!vs || !rho)) return fail(SG_EINVAL, "elastic models need vs and rho");
+    if (!vp || !ws) return fail(SG_EINVAL, "vp and ws must be device pointers");
+    if (max_shots < 1 || max_rec < 0 || ckpt_every < 0)
+        return fail(SG_EINVAL, "max_shots >= 1, max_rec >= 0 and ckpt_every >= 0 required");
+    if (max_shots % d->nmodels) return fail(SG_EINVAL, "max_shots must be a multiple of nmodels");
+    if ((long long)max_rec >= (1LL << REC_ID_BITS)) return fail(SG_EINVAL, "at most %d receivers per shot", (1 << REC_ID_BITS) - 1);
+    if (const int e = check_shots(d, max_shots)) return e;
+    if (d->ndim == 3 && d->nz + 2 * d->npml >= (1 << 12)) return fail(SG_EINVAL, "3-D grids are limited to 4095 padded planes in z");
+    const Layout L = make_layout(d, max_shots, max_rec, ckpt_every);
+    if (ws_bytes < L.total) return fail(SG_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    if ((uintptr_t)ws % ALIGN) return fail(SG_EINVAL, "workspace must be %zu-byte aligned", ALIGN);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    if (const int e = check_velocities(d, L, vp, vs, rho, s)) return e;
+    const double zmax = d->npml > 0 ? 3.0 * d->pml_vmax * std::log(1.0 / d->pml_R) / (2.0 * d->npml * d->dx) : 0.0;
 
     sg_model *m = new sg_model();
     m->d = *d;
@@ -1426,6 +1439,30 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     return SG_OK;
 }
 
+int update_model(sg_model *m, const float *vp, const float *vs, const float *rho, sg_stream_t stream)
+{
+    g_err.clear();
+    if (!m) return fail(SG_EINVAL, "model is NULL");
+    const sg_desc *d = &m->d;
+    const Layout &L = m->L;
+    const bool elastic = L.elastic;
+    if (!elastic && (vs || rho)) return fail(SG_EINVAL, "vs and rho must be NULL for acoustic models");
+    if (elastic && (!vs || !rho)) return fail(SG_EINVAL, "elastic models need vs and rho");
+    if (!vp) return fail(SG_EINVAL, "vp must be a device pointer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (const int e = check_velocities(d, L, vp, vs, rho, s)) return e;
+    if (elastic) launch_el2_prep(L.g2, d->nmodels, vp, vs, rho, m->model, m->model + 5, s);
+    else if (L.ad2) launch_ad2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
+    else if (d->ndim == 2) launch_ac2_prep(L.g2, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
+    else launch_ac3_prep(L.g3, d->nmodels, vp, d->dt, d->dx, m->chat, m->cpad, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SG_EDEVICE, "model preparation failed: %s", hipGetErrorString(e));
+    // the checkpoints and stored snapshots belong to the old parameters
+    m->have_ckpt = false;
+    m->have_store = false;
+    return SG_OK;
+}
+
 int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckpt, sg_stream_t stream)
 {
     g_err.clear();
@@ -1488,7 +1525,7 @@ int forward_shots(sg_model *m, const sg_shots *sh, float *seis, int32_t save_ckp
     for (int seg = 0; seg < L.nseg; ++seg) {
         const int steps = std::min(K, nt - seg * K);
         const int span = m->graphs ? -1 : span_begin(m, 0, steps, s);
-        rc = run_segment(m, m->gfwd, seg, key, s, [&](hipStream_t st) { return issue(seg, st); });
+        rc = run_segment(m, m->gfwd[save_ckpt != 0], seg, key, s, [&](hipStream_t st) { return issue(seg, st); });
         if (rc) return rc;
         span_end(m, span, s);
     }

@@ -34,11 +34,21 @@ from . import seisgrad as S
 class Propagator:
     """Workspace + model for a fixed grid, shot batch and checkpoint interval."""
 
-    def __init__(self, desc, shots: "S.Shots", ckpt_every: int = 0, device="cuda", store_segments: int = 0):
+    def __init__(self, desc, shots: "S.Shots", ckpt_every: int = 0, device="cuda", store_segments: int = 0,
+                 graphs: bool = False):
         """store_segments: checkpoint segments whose adjoint snapshots the
         checkpointed forward keeps in the workspace (-1: all of them), so the
-        adjoint does not recompute them."""
+        adjoint does not recompute them.  graphs: run every checkpoint
+        segment as a replayed HIP graph (the library's segment graphs; the
+        same results bit for bit, without the per-launch host cost).  The
+        model is prepared once and its parameters replaced in place by later
+        calls, so that the captured graphs stay valid while the forwards and
+        misfits of the inversion loops write into the propagator's own
+        seismogram and residual buffers (keep=True)."""
         self.d = desc
+        self.graphs = graphs
+        self._seis = {}            # save_ckpt -> the kept seismogram buffer
+        self.resid = None          # the kept residual buffer
         self.shots = shots
         self.ckpt = ckpt_every
         self.elastic = desc.physics == S.SG_ELASTIC
@@ -53,18 +63,33 @@ class Propagator:
         self.generation = 0
 
     def set_model(self, vp, vs=None, rho=None):
-        """(Re)initialise the model on the same workspace."""
-        if self.model is not None:
-            self.model.close()
-        self.model = S.Model(self.d, vp.detach(), self.shots.nshots, self.shots.nrec, self.ckpt,
-                             vs=None if vs is None else vs.detach(), rho=None if rho is None else rho.detach(),
-                             ws=self.ws)
+        """Prepare the model on the workspace (the first call), or give it
+        new parameters (later calls: update_model keeps its lists, tables
+        and graphs)."""
+        vs = None if vs is None else vs.detach()
+        rho = None if rho is None else rho.detach()
+        if self.model is None:
+            self.model = S.Model(self.d, vp.detach(), self.shots.nshots, self.shots.nrec, self.ckpt,
+                                 vs=vs, rho=rho, ws=self.ws)
+            if self.graphs:
+                self.model.set_tuning(S.SG_TUNE_GRAPHS, 1)
+        else:
+            self.model.update(vp.detach(), vs, rho)
         self.generation += 1
         return self.model
 
-    def forward(self, vp, vs=None, rho=None, save_ckpt=True):
+    def forward(self, vp, vs=None, rho=None, save_ckpt=True, keep=False):
+        """Seismograms of the shots for these parameters.  keep: into the
+        propagator's buffer for this checkpoint mode, which the next kept
+        forward of the same mode overwrites."""
         self.set_model(vp, vs, rho)
-        return self.model.forward(self.shots, save_ckpt=save_ckpt)
+        seis = None
+        if keep:
+            seis = self._seis.get(bool(save_ckpt))
+            if seis is None:
+                shape = (self.shots.nshots, 2 if self.elastic else 1, self.d.nt, self.shots.nrec)
+                seis = self._seis[bool(save_ckpt)] = torch.empty(shape, dtype=torch.float32, device=self.ws.device)
+        return self.model.forward(self.shots, seis=seis, save_ckpt=save_ckpt)
 
     def close(self):
         if self.model is not None:
@@ -121,10 +146,16 @@ class GDResult:
     rejected: np.ndarray = None       # [iters, B] ... and replaced by the plain direction
 
 
-def per_model_misfit(prop, pred, obs, nmodels):
+def per_model_misfit(prop, pred, obs, nmodels, keep=False):
     """J_b = 1/2 sum over model b's samples (FP64 on the device), and the
-    residual (FP32)."""
-    resid = torch.empty_like(pred)
+    residual (FP32); keep: into the propagator's residual buffer, which the
+    next kept misfit overwrites."""
+    if keep:
+        if prop.resid is None or prop.resid.shape != pred.shape:
+            prop.resid = torch.empty_like(pred)
+        resid = prop.resid
+    else:
+        resid = torch.empty_like(pred)
     J = torch.empty(nmodels, dtype=torch.float64, device=pred.device)
     per = pred.numel() // nmodels
     pv, ov, rv = pred.reshape(nmodels, per), obs.reshape(nmodels, per), resid.reshape(nmodels, per)
@@ -190,8 +221,8 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
             direction.load_state({k[4:]: v for k, v in st.items() if k.startswith("dir_")})
     torch.cuda.synchronize()
     t0 = time.perf_counter() - t_prev
-    pred = prop.forward(m, save_ckpt=True)
-    J, r = per_model_misfit(prop, pred, obs, B)
+    pred = prop.forward(m, save_ckpt=True, keep=True)
+    J, r = per_model_misfit(prop, pred, obs, B, keep=True)
     if start == 0:
         Js.append(J.cpu().numpy().copy())
         torch.cuda.synchronize()
@@ -224,8 +255,8 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
         for bt in range(cfg.max_backtracks + 1):
             trial = (m.reshape(B, -1) + (a.to(m.device, torch.float32) / scale)[:, None] * pflat).reshape(m.shape)
             trial = trial.clamp(cfg.vmin, cfg.vmax)
-            tp = prop.forward(trial, save_ckpt=False)
-            Jt, _ = per_model_misfit(prop, tp, obs, B)
+            tp = prop.forward(trial, save_ckpt=False, keep=True)
+            Jt, _ = per_model_misfit(prop, tp, obs, B, keep=True)
             Jt = Jt.cpu().numpy()
             ok = (~done) & (Jt < Jc)
             if ok.any():
@@ -258,8 +289,8 @@ def batched_gd(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: GDCon
         if direction is not None and hasattr(direction, "report"):
             direction.report(it, rejected)
         m = newm
-        pred = prop.forward(m, save_ckpt=True)
-        J, r = per_model_misfit(prop, pred, obs, B)
+        pred = prop.forward(m, save_ckpt=True, keep=True)
+        J, r = per_model_misfit(prop, pred, obs, B, keep=True)
         Js.append(J.cpu().numpy().copy())
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
@@ -316,8 +347,8 @@ def batched_lbfgs(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: LB
     Js, times, acc = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pred = prop.forward(m, save_ckpt=True)
-    J, r = per_model_misfit(prop, pred, obs, B)
+    pred = prop.forward(m, save_ckpt=True, keep=True)
+    J, r = per_model_misfit(prop, pred, obs, B, keep=True)
     J0 = J.cpu().numpy().copy()
     Js.append(J0.copy())
     torch.cuda.synchronize()
@@ -345,7 +376,7 @@ def batched_lbfgs(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: LB
         a = torch.ones(B, device=dev)
         for bt in range(cfg.max_backtracks + 1):
             trial = (m.reshape(B, -1) + (a * scale)[:, None] * pf).reshape(m.shape).clamp(cfg.vmin, cfg.vmax)
-            Jt, _ = per_model_misfit(prop, prop.forward(trial, save_ckpt=False), obs, B)
+            Jt, _ = per_model_misfit(prop, prop.forward(trial, save_ckpt=False, keep=True), obs, B, keep=True)
             Jt = Jt.cpu().numpy()
             ok = (~done) & (Jt < Jc)
             if ok.any():
@@ -366,8 +397,8 @@ def batched_lbfgs(prop: Propagator, m0: torch.Tensor, obs: torch.Tensor, cfg: LB
         acc.append(done.copy())
         m_old, g_old = m, g
         m = newm
-        pred = prop.forward(m, save_ckpt=True)
-        J, r = per_model_misfit(prop, pred, obs, B)
+        pred = prop.forward(m, save_ckpt=True, keep=True)
+        J, r = per_model_misfit(prop, pred, obs, B, keep=True)
         g = prop.model.gradient(prop.shots, r).contiguous()
         # store (s, y) of the models that moved
         slot = np.where(done, (newest + 1) % cfg.mem, -1).astype(np.int32)

@@ -25,7 +25,7 @@ _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_E
           SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED",
           SG_ENUMERIC: "SG_ENUMERIC"}
 
-EXPORTS = ("workspace_bytes", "init_model", "forward_shots", "misfit", "adjoint_gradient",
+EXPORTS = ("workspace_bytes", "init_model", "update_model", "forward_shots", "misfit", "adjoint_gradient",
            "free_model", "last_error", "ricker", "dot_f64", "set_profiling", "phase_times",
            "set_time_blocking", "set_tuning", "snapshot_segment_bytes", "numeric_status", "misfit_noalloc", "lbfgs_push", "lbfgs_direction",
            "source_gaussian", "source_gaussian_grad", "source_rupture", "source_rupture_grad",
@@ -67,6 +67,7 @@ def lib():
         L.init_model.argtypes = [C.POINTER(SgDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                  C.POINTER(C.c_void_p)]
+        L.update_model.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.forward_shots.argtypes = [C.c_void_p, C.POINTER(SgShots), C.c_void_p, C.c_int32, C.c_void_p]
         L.misfit.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.adjoint_gradient.argtypes = [C.c_void_p, C.POINTER(SgShots), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -188,6 +189,15 @@ class Model:
         self.rho = None if rho is None else rho.contiguous()
         _check(lib().init_model(C.byref(d), _ptr(self.vp), _ptr(self.vs), _ptr(self.rho), max_shots, max_rec,
                                 ckpt_every, _ptr(self.ws), self.ws.numel(), _stream(stream), C.byref(self.handle)))
+
+    def update(self, vp, vs=None, rho=None, stream=None):
+        """New parameters on the same grid, shots and workspace (the model's
+        lists, tables and segment graphs are kept)."""
+        vp = vp.contiguous()
+        vs = None if vs is None else vs.contiguous()
+        rho = None if rho is None else rho.contiguous()
+        _check(lib().update_model(self.handle, _ptr(vp), _ptr(vs), _ptr(rho), _stream(stream)))
+        self.vp, self.vs, self.rho = vp, vs, rho
 
     def forward(self, shots, seis=None, save_ckpt=True, stream=None):
         if seis is None:

@@ -69,8 +69,10 @@ class Problem:
     obs: torch.Tensor
 
 
-def c1_problem(seeds, nt=500) -> Problem:
-    """B random three-layer models, one shot each, batched in one launch."""
+def c1_problem(seeds, nt=500, graphs=True) -> Problem:
+    """B random three-layer models, one shot each, batched in one launch; the
+    propagator replays its checkpoint segments as HIP graphs unless graphs is
+    False (these small grids are bound by the launches otherwise)."""
     cfg = synth.C1.replace(nt=nt)
     B = len(seeds)
     true = np.stack([synth.random_layered(s, cfg.nx, cfg.nz) for s in seeds])
@@ -80,10 +82,10 @@ def c1_problem(seeds, nt=500) -> Problem:
     d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, nmodels=B, dx=cfg.dx, dt=cfg.dt,
                pml_R=cfg.pml_R, pml_vmax=3500.0)
     wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)[None].repeat(B, 1).contiguous()
-    prop = fwi.Propagator(d, S.Shots(src, rec, wav), store_segments=-1)
+    prop = fwi.Propagator(d, S.Shots(src, rec, wav), store_segments=-1, graphs=graphs)
     dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
     t_d, i_d = dev(true), dev(init)
-    obs = prop.forward(t_d, save_ckpt=False).clone()
+    obs = prop.forward(t_d, save_ckpt=False, keep=True).clone()
     return Problem(prop, t_d, i_d, obs)
 
 

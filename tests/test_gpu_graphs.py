@@ -148,3 +148,62 @@ def test_segment_graphs_follow_new_settings():
     with pytest.raises(S.SeisError):
         m.set_tuning(S.SG_TUNE_GRAPHS, 2)
     m.close()
+
+
+def test_update_model_equals_a_fresh_model_and_keeps_graphs():
+    """update_model gives the seismograms and gradient of a model prepared
+    from scratch with the new velocity, bit for bit, with the segment graphs
+    captured for the old velocity replayed; the adjoint is refused until a
+    checkpointed forward of the new parameters, and a rejected update leaves
+    the old parameters in place."""
+    nt = 300
+    cfg = synth.C1.replace(nt=nt)
+    B = 2
+    true = np.stack([synth.random_layered(s) for s in (3, 4)])
+    v1 = np.stack([synth.smooth(t, 10.0) for t in true])
+    v2 = np.stack([synth.smooth(t, 4.0) for t in true])
+    d = S.desc(nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=nt, nmodels=B, dx=cfg.dx, dt=cfg.dt, pml_vmax=3500.0)
+    wav = S.ricker(cfg.f0, cfg.ricker_t0, cfg.dt, nt)[None].repeat(B, 1).contiguous()
+    sh = S.Shots(np.array([[50, 2]] * B, dtype=np.int32), synth.surface_receivers_2d(B, cfg.nx), wav)
+    mt = S.Model(d, dev(true), B, cfg.nx, store_segments=2)
+    obs = mt.forward(sh, save_ckpt=False).clone()
+    mt.close()
+    fresh = S.Model(d, dev(v2), B, cfg.nx, store_segments=2)
+    s_ref, r_ref = torch.empty_like(obs), torch.empty_like(obs)
+    g_ref = _sweep(fresh, sh, obs, s_ref, r_ref).clone()
+    fresh.close()
+    m = S.Model(d, dev(v1), B, cfg.nx, store_segments=2)
+    m.set_tuning(S.SG_TUNE_GRAPHS, 1)
+    seis, r = torch.empty_like(obs), torch.empty_like(obs)
+    _sweep(m, sh, obs, seis, r)                     # captures the segments for v1
+    m.update(dev(v2))
+    with pytest.raises(S.SeisError):
+        m.gradient(sh, r)                           # checkpoints of v1 are stale
+    g = _sweep(m, sh, obs, seis, r)
+    assert torch.equal(seis, s_ref) and torch.equal(g, g_ref)
+    bad = dev(v2).clone()
+    bad[0, 5, 5] = -1.0
+    with pytest.raises(S.SeisError):
+        m.update(bad)
+    g = _sweep(m, sh, obs, seis, r)                 # still v2
+    assert torch.equal(seis, s_ref) and torch.equal(g, g_ref)
+    m.close()
+
+
+def test_inversion_loops_with_graphs_equal_eager_runs():
+    """Plain and L-BFGS batched inversion on a propagator that replays its
+    segments as graphs (parameters replaced in place, kept buffers) give the
+    eager propagator's models and misfits bit for bit."""
+    from paper_2003_06027_amd import fwi, ttm
+    res = {}
+    for graphs in (False, True):
+        pr = ttm.c1_problem([7, 8, 9], nt=300, graphs=graphs)
+        gd = fwi.batched_gd(pr.prop, pr.init, pr.obs, fwi.GDConfig(iters=4))
+        lb = fwi.batched_lbfgs(pr.prop, pr.init, pr.obs, fwi.LBFGSConfig(iters=4))
+        torch.cuda.synchronize()
+        res[graphs] = (gd.models.clone(), gd.J.copy(), lb.models.clone(), lb.J.copy())
+        pr.prop.close()
+    (m0, j0, l0, k0), (m1, j1, l1, k1) = res[False], res[True]
+    assert torch.equal(m0, m1) and np.array_equal(j0, j1)
+    assert torch.equal(l0, l1) and np.array_equal(k0, k1)
+    assert np.all(j1[-1] < j1[0]) and np.all(k1[-1] < k1[0])
