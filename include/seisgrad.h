@@ -286,6 +286,11 @@ SG_API int set_time_blocking(sg_model *m, int32_t steps);
  *   SG_TUNE_CHUNK_LAYER3   planes per work item of the 3-D layer passes
  *                          (3-D chunks: 16 to 64, multiples of 8; defaults
  *                          32, 64, 32);
+ *   SG_TUNE_PAIR           2-D acoustic with time blocking: 1 (the default)
+ *                          launches the step of the tiles by the layer with
+ *                          the two-step launch of the blocked tiles as one
+ *                          grid in sweeps that record no seismograms (the
+ *                          recompute), 0 apart;
  *   SG_TUNE_SHOT_GROUP     elastic: shots of one model per thread, 1, 2 or 4
  *                          (0: 4 if the shots per model divide by 4, else 2
  *                          if even, else 1; a value that does not divide the
@@ -313,7 +318,7 @@ SG_API int set_time_blocking(sg_model *m, int32_t steps);
  * after the upload.  Call between sweeps.  Errors: SG_EINVAL for an unknown
  * key, a value out of range, or a key that does not apply to the model. */
 enum { SG_TUNE_TIME_BLOCKING = 0, SG_TUNE_CHUNK_FWD3 = 1, SG_TUNE_CHUNK_ADJ3 = 2, SG_TUNE_CHUNK_LAYER3 = 3,
-       SG_TUNE_SHOT_GROUP = 4, SG_TUNE_BLOCK_X = 5, SG_TUNE_GRAPHS = 6 };
+       SG_TUNE_SHOT_GROUP = 4, SG_TUNE_BLOCK_X = 5, SG_TUNE_GRAPHS = 6, SG_TUNE_PAIR = 7 };
 SG_API int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream);
 
 /* Limited-memory BFGS helpers of the outer inversion loop (the paper's

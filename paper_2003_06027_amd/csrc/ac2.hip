@@ -402,13 +402,10 @@ __device__ __forceinline__ void ring_cell(int i, int &r, int &c)
     }
 }
 
-__global__ __launch_bounds__(NTB) void ac2_fwd2_kernel(Ac2Fwd2Args a)
+// s0: u^k on the tile + 8 (R0 x W0), s1: u^{k+1} on the tile + 4 (R1 x W1)
+__device__ __forceinline__ void fwd2_tile(const Ac2Fwd2Args &a, float *s0, float *s1, int tile, int shot)
 {
-    __shared__ float s0[R0 * W0];   // u^k on the tile + 8
-    __shared__ float s1[R1 * W1];   // u^{k+1} on the tile + 4
     const Grid2 &g = a.g;
-    const int w = xcd_work_id(a.ntl * a.nshots);
-    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
     const int tz = tile / g.ntx, tx = tile - tz * g.ntx;
     const int x0 = tx * TX, z0 = tz * TZ;
     const long long so = (long long)shot * g.plane;
@@ -488,6 +485,15 @@ __global__ __launch_bounds__(NTB) void ac2_fwd2_kernel(Ac2Fwd2Args a)
         __builtin_nontemporal_store(u1[j] + inc, a.u2 + so + f);
         if (a.snap1) __builtin_nontemporal_store(wk, a.snap1 + so + f);
     }
+}
+
+__global__ __launch_bounds__(NTB) void ac2_fwd2_kernel(Ac2Fwd2Args a)
+{
+    __shared__ float s0[R0 * W0];
+    __shared__ float s1[R1 * W1];
+    const int w = xcd_work_id(a.ntl * a.nshots);
+    const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
+    fwd2_tile(a, s0, s1, tile, shot);
 }
 
 // Adjoint steps k and k-1 on blocked tiles (no receivers within 4 cells):
@@ -794,6 +800,32 @@ __global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(8))) void a
     fwd_near_tile<SNAP, REC>(a, su, sx, sz, tile, shot);
 }
 
+// Step k of the tiles by the layer and steps k, k+1 of the blocked tiles in
+// one launch.  The two read only u^k, u^{k-1} (and phi~^{k-1}) and write
+// disjoint cells of u^{k+1} (and u^{k+2}, phi~^k, the seismograms), so they
+// need no order; one grid lets the near tiles fill the blocked launch's last
+// round instead of waiting for it.  The blocked tiles come first in the grid;
+// the two share one LDS buffer.
+constexpr int NPAIR_LDS = NU + TZ * WPX + RPZ * TX > R0 * W0 + R1 * W1 ? NU + TZ * WPX + RPZ * TX
+                                                                      : R0 * W0 + R1 * W1;
+static_assert(NTN == NTB, "one block size for the pair");
+template <bool SNAP, bool REC>
+__global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(8)))
+void ac2_fwd_pair_kernel(Ac2FwdArgs a, Ac2Fwd2Args b)
+{
+    __shared__ float lds[NPAIR_LDS];
+    const int nb = b.ntl * b.nshots;
+    int w = xcd_work_id(nb + a.ntl * a.nshots);
+    if (w < nb) {
+        const int shot = w / b.ntl;
+        fwd2_tile(b, lds, lds + R0 * W0, b.tiles[w - shot * b.ntl], shot);
+    } else {
+        w -= nb;
+        const int shot = w / a.ntl;
+        fwd_near_tile<SNAP, REC>(a, lds, lds + NU, lds + NU + TZ * WPX, a.tiles[w - shot * a.ntl], shot);
+    }
+}
+
 __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, float *sx, float *sz, int tile,
                                               int shot)
 {
@@ -1001,6 +1033,15 @@ void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s)
     const int nb = a.ntl * a.nshots;
     if (nb == 0) return;
     ac2_adj2_kernel<<<nb, NTH, 0, s>>>(a);
+}
+
+void launch_ac2_fwd_pair(const Ac2FwdArgs &a, const Ac2Fwd2Args &b, hipStream_t s)
+{
+    const int nb = a.ntl * a.nshots + b.ntl * b.nshots;
+    if (nb == 0) return;
+    if (a.seis) { ac2_fwd_pair_kernel<false, true><<<nb, NTN, 0, s>>>(a, b); return; }
+    if (a.snap) ac2_fwd_pair_kernel<true, false><<<nb, NTN, 0, s>>>(a, b);
+    else ac2_fwd_pair_kernel<false, false><<<nb, NTN, 0, s>>>(a, b);
 }
 
 void launch_ac2_fwd(const Ac2FwdArgs &a, bool near, hipStream_t s)

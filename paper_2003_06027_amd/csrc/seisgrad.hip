@@ -270,6 +270,7 @@ struct sg_model {
     int n_near3 = 0;
     std::vector<int> h_tiles3;
     int steps_per_launch = 2;
+    bool pair = true;             // 2-D: near step k and blocked steps k, k+1 in one launch
     // snapshots of the last n_store checkpoint segments, written by a
     // checkpointed forward into the workspace beyond its minimum size
     float *store = nullptr;
@@ -881,8 +882,7 @@ inline const int *tile_set(const sg_model *m, TileSet t, int &n)
 }
 
 // One forward step k on a tile set.
-void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, TileSet ts, float *seis, float *snap,
-               hipStream_t s)
+Ac2FwdArgs ac2_args(const sg_model *m, int ns, const float *wav, int k, TileSet ts, float *seis, float *snap)
 {
     Ac2FwdArgs a{};
     a.g = m->L.g2;
@@ -911,7 +911,13 @@ void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, TileSet ts, f
     a.nsrc = m->geom_nsrc;
     a.src_off = m->src_off;
     a.src_ent = m->src_ent;
-    launch_ac2_fwd(a, ts == TS_LAYER, s);
+    return a;
+}
+
+void ac2_tiles(const sg_model *m, int ns, const float *wav, int k, TileSet ts, float *seis, float *snap,
+               hipStream_t s)
+{
+    launch_ac2_fwd(ac2_args(m, ns, wav, k, ts, seis, snap), ts == TS_LAYER, s);
 }
 
 // Forward step k, or steps k and k+1 when `two`: the one-step list step by
@@ -924,8 +930,6 @@ void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, f
         for (TileSet ts : {TS_LAYER, TS_OTHER, TS_BLOCKED}) ac2_tiles(m, ns, wav, k, ts, seis, snap0, s);
         return;
     }
-    ac2_tiles(m, ns, wav, k, TS_LAYER, seis, snap0, s);
-    ac2_tiles(m, ns, wav, k, TS_OTHER, seis, snap0, s);
     Ac2Fwd2Args b{};
     b.g = m->L.g2;
     b.nshots = ns;
@@ -944,7 +948,18 @@ void ac2_forward(const sg_model *m, int ns, const float *wav, int k, bool two, f
     b.src_scale = src_scale(m);
     b.snap0 = snap0;
     b.snap1 = snap1;
-    launch_ac2_fwd2(b, s);
+    int n_other = 0;
+    (void)tile_set(m, TS_OTHER, n_other);
+    if (m->pair && n_other == 0 && (!seis || m->geom_nrec == 0)) {
+        // the near tiles' step k and the blocked tiles' double step in one
+        // grid (sweeps that record seismograms keep them apart: paired, the
+        // C2 forward ran 2 % slower while the recompute gained 4 %)
+        launch_ac2_fwd_pair(ac2_args(m, ns, wav, k, TS_LAYER, seis, snap0), b, s);
+    } else {
+        ac2_tiles(m, ns, wav, k, TS_LAYER, seis, snap0, s);
+        ac2_tiles(m, ns, wav, k, TS_OTHER, seis, snap0, s);
+        launch_ac2_fwd2(b, s);
+    }
     ac2_tiles(m, ns, wav, k + 1, TS_LAYER, seis, snap1, s);
     ac2_tiles(m, ns, wav, k + 1, TS_OTHER, seis, snap1, s);
 }
@@ -1712,6 +1727,11 @@ int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream)
         }
         return SG_OK;
     }
+    case SG_TUNE_PAIR:
+        if (m->L.elastic || m->L.ad2 || m->d.ndim != 2) return fail(SG_EINVAL, "launch pairing applies to 2-D acoustic models");
+        if (value != 0 && value != 1) return fail(SG_EINVAL, "launch pairing: 0 or 1");
+        m->pair = value != 0;
+        return SG_OK;
     case SG_TUNE_SHOT_GROUP:
         if (!m->L.elastic) return fail(SG_EINVAL, "shot groups apply to elastic models");
         if (value != 0 && value != 1 && value != 2 && value != 4)

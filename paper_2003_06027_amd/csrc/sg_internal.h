@@ -140,6 +140,8 @@ void launch_ac2_fwd2(const Ac2Fwd2Args &a, hipStream_t s);
 void launch_ac2_adj2(const Ac2Adj2Args &a, hipStream_t s);
 // near: the one-step list (pass A folded into its near tiles); else tiles away from the layer
 void launch_ac2_fwd(const Ac2FwdArgs &a, bool near, hipStream_t s);
+// the near tiles' step k (a) and the blocked tiles' steps k, k+1 (b) in one launch
+void launch_ac2_fwd_pair(const Ac2FwdArgs &a, const Ac2Fwd2Args &b, hipStream_t s);
 void launch_ac2_adj(const Ac2AdjArgs &a, bool near, hipStream_t s);
 void launch_ac2_prep(const Grid2 &g, int nmodels, const float *vp, double dt, double dx,
                      float *chat, float *cpad, hipStream_t s);

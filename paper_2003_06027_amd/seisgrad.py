@@ -20,7 +20,7 @@ SG_OK, SG_EINVAL, SG_EUNSTABLE, SG_ENOMEM, SG_ESTATE, SG_EDEVICE, SG_EUNSUPPORTE
     0, -1, -2, -3, -4, -5, -6, -7
 SG_ACOUSTIC, SG_ELASTIC, SG_ACOUSTIC_DIV = 0, 1, 2
 SG_TUNE_TIME_BLOCKING, SG_TUNE_CHUNK_FWD3, SG_TUNE_CHUNK_ADJ3, SG_TUNE_CHUNK_LAYER3, SG_TUNE_SHOT_GROUP, \
-    SG_TUNE_BLOCK_X, SG_TUNE_GRAPHS = 0, 1, 2, 3, 4, 5, 6
+    SG_TUNE_BLOCK_X, SG_TUNE_GRAPHS, SG_TUNE_PAIR = 0, 1, 2, 3, 4, 5, 6, 7
 _NAMES = {SG_EINVAL: "SG_EINVAL", SG_EUNSTABLE: "SG_EUNSTABLE", SG_ENOMEM: "SG_ENOMEM",
           SG_ESTATE: "SG_ESTATE", SG_EDEVICE: "SG_EDEVICE", SG_EUNSUPPORTED: "SG_EUNSUPPORTED",
           SG_ENUMERIC: "SG_ENUMERIC"}

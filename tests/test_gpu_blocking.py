@@ -33,14 +33,16 @@ def blocked_tiles(nx, nz, P, rec):
     return n
 
 
-def _run(d, c_true, c0, src, rec, wav, ckpt, steps):
+def _run(d, c_true, c0, src, rec, wav, ckpt, steps, pair=1):
     ns = src.shape[0]
     sh = S.Shots(src, rec, wav)
     mt = S.Model(d, dev(c_true), ns, rec.shape[1], ckpt)
     mt.set_time_blocking(steps)
+    mt.set_tuning(S.SG_TUNE_PAIR, pair)
     obs = mt.forward(sh, save_ckpt=False)
     m = S.Model(d, dev(c0), ns, rec.shape[1], ckpt)
     m.set_time_blocking(steps)
+    m.set_tuning(S.SG_TUNE_PAIR, pair)
     pred = m.forward(sh, save_ckpt=True)
     J, resid = m.misfit(pred, obs)
     gw = torch.zeros_like(wav)
@@ -69,6 +71,30 @@ def test_blocked_and_single_step_sweeps_are_bitwise_equal(ckpt, nt):
             assert x == y, name
         else:
             assert torch.equal(x, y), name
+    assert torch.count_nonzero(a[3]) > 0 and torch.count_nonzero(a[4][0]) > 0
+
+
+@pytest.mark.parametrize("ckpt,nt", [(0, 250), (7, 251)])
+def test_paired_launches_are_bitwise_equal(ckpt, nt):
+    """With surface receivers only (no one-step tiles away from the layer),
+    the near tiles' step and the blocked tiles' double step run as one grid
+    by default; paired, apart and unblocked runs agree bit for bit."""
+    nx, nz, P = 300, 180, 16
+    ct = synth.smooth_random(5, (nz, nx), 8.0, 1600.0, 3200.0)
+    c0 = synth.smooth(ct, 6.0)
+    src = np.array([[150, 90], [40, 5], [242, 100]], dtype=np.int32)
+    rec = np.stack([synth.surface_receivers_2d(1, nx)[0]] * 3)
+    assert blocked_tiles(nx, nz, P, rec) >= 4
+    d = S.desc(nx=nx, nz=nz, npml=P, nt=nt, dx=10.0, dt=1e-3, pml_vmax=3200.0)
+    wav = torch.stack([S.ricker(f, 1.0 / f, 1e-3, nt) for f in (12.0, 10.0, 15.0)])
+    a = _run(d, ct, c0, src, rec, wav, ckpt, 2, pair=1)
+    b = _run(d, ct, c0, src, rec, wav, ckpt, 2, pair=0)
+    c = _run(d, ct, c0, src, rec, wav, ckpt, 1)
+    for x, y, z, name in zip(a, b, c, ("obs", "pred", "J", "grad", "g_wavelet")):
+        if isinstance(x, float):
+            assert x == y == z, name
+        else:
+            assert torch.equal(x, y) and torch.equal(x, z), name
     assert torch.count_nonzero(a[3]) > 0 and torch.count_nonzero(a[4][0]) > 0
 
 
