@@ -190,16 +190,21 @@ __device__ __forceinline__ float d8b(const float *b, unsigned o, unsigned sb)
 // psi^k planes with a 4-cell ring in LDS, register windows along z, the
 // operands of the next plane loaded one plane ahead into rings (the marching
 // scheme above).  phi is updated at the layer cells only, and loaded only
-// there (elsewhere every lane reads one shared line).
+// there (elsewhere every lane reads one shared line).  The psi terms of
+// axis j carry the damping of the other two axes, h_a h_b: items where no
+// cell has two axes in the layer (PSI = false: a tile in the layer in x or
+// y only, off the z slabs; the z slabs of the other tiles) leave psi out,
+// which adds an exact zero in the other items.
 constexpr int LPD = 1, LNB = LPD + 1, LZR = 10;
 static_assert(LZR % LNB == 0 && 8 + LPD < LZR, "ring sizes");
 
+template <bool PSI>
 __global__ __launch_bounds__(NTH3) __attribute__((amdgpu_waves_per_eu(8)))
 void ac3_phi_kernel(Ac3PhiArgs a)
 {
     constexpr int W = TX3 + 8;
     __shared__ float pu[2][(TY3 + 8) * W];
-    __shared__ float pp[2][(TY3 + 8) * W];
+    __shared__ float pp[PSI ? 2 : 1][PSI ? (TY3 + 8) * W : 1];
     const Grid3 &g = a.g;
     const int w = work_id();
     const int shot = w / a.nitems;
@@ -226,18 +231,18 @@ void ac3_phi_kernel(Ac3PhiArgs a)
         rs = tid < RING3 ? r * W + c : -1;
         rob = (unsigned)((y0 - 4 + r + OY3) * g.sy + x0 - 4 + c + OX3) * 4u;
     }
-    float qu[LZR], qp[LZR], ru[LNB], rp[LNB], f0[LNB], f1[LNB], f2[LNB];
+    float qu[LZR], qp[PSI ? LZR : 1], ru[LNB], rp[PSI ? LNB : 1], f0[LNB], f1[LNB], f2[LNB];
 #pragma unroll
     for (int m = 0; m < 8 + LPD; ++m) {
         const unsigned o = colb + pbc(z0 - 4 + m);
         qu[m] = ldb(u, o);
-        qp[m] = ldb(psi, o);
+        if constexpr (PSI) qp[m] = ldb(psi, o);
     }
 #pragma unroll
     for (int d = 0; d < LPD; ++d) {
         const unsigned o = pbc(z0 + d);
         ru[d] = ldb(u, rob + o);
-        rp[d] = ldb(psi, rob + o);
+        if constexpr (PSI) rp[d] = ldb(psi, rob + o);
         f0[d] = ldb(ph0, colb + o);
         f1[d] = ldb(ph1, colb + o);
         f2[d] = ldb(ph2, colb + o);
@@ -267,22 +272,22 @@ void ac3_phi_kernel(Ac3PhiArgs a)
                 stb(ph2, ff, fn2);
             }
             fw = false;
-            float *P = pu[z & 1], *Q = pp[z & 1];
+            float *P = pu[z & 1], *Q = pp[PSI ? (z & 1) : 0];
             const int ctr = (ly + 4) * W + lx + 4;
             P[ctr] = qu[(r + 4) % LZR];
-            Q[ctr] = qp[(r + 4) % LZR];
+            if constexpr (PSI) Q[ctr] = qp[(r + 4) % LZR];
             if (rs >= 0) {
                 P[rs] = ru[c];
-                Q[rs] = rp[c];
+                if constexpr (PSI) Q[rs] = rp[c];
             }
             const unsigned fb = colb + pb(z);
             __syncthreads();
             {
                 const unsigned d1 = pbc(z + LPD), dw = colb + pbc(z + 4 + LPD);
                 ru[n] = ldb(u, rob + d1);
-                rp[n] = ldb(psi, rob + d1);
+                if constexpr (PSI) rp[n] = ldb(psi, rob + d1);
                 qu[(r + 8 + LPD) % LZR] = ldb(u, dw);
-                qp[(r + 8 + LPD) % LZR] = ldb(psi, dw);
+                if constexpr (PSI) qp[(r + 8 + LPD) % LZR] = ldb(psi, dw);
                 // phi only where it is updated; elsewhere one shared line
                 const unsigned fo = layer_xy || z + LPD < g.P || z + LPD >= g.P + g.nz ? colb + d1 : 0u;
                 f0[n] = ldb(ph0, fo);
@@ -294,14 +299,19 @@ void ac3_phi_kernel(Ac3PhiArgs a)
 #pragma unroll
                 for (int m = 0; m < 9; ++m) {
                     wu[m] = qu[(r + m) % LZR];
-                    wp[m] = qp[(r + m) % LZR];
+                    if constexpr (PSI) wp[m] = qp[(r + m) % LZR];
                 }
                 const float hz = a.t.h[2][z], ihz = a.t.ih[2][z], pz = a.t.p[2][z];
                 const float hs = hx + hy + hz;
-                const float k4 = 4.f * a.inv_dt;
-                fn0 = px * f0[c] + 2.f * (hs - 2.f * hx) * ihx * d8(P + ctr, 1) + k4 * hy * hz * ihx * d8(Q + ctr, 1);
-                fn1 = py * f1[c] + 2.f * (hs - 2.f * hy) * ihy * d8(P + ctr, W) + k4 * hz * hx * ihy * d8(Q + ctr, W);
-                fn2 = pz * f2[c] + 2.f * (hs - 2.f * hz) * ihz * d8w(wu) + k4 * hx * hy * ihz * d8w(wp);
+                fn0 = px * f0[c] + 2.f * (hs - 2.f * hx) * ihx * d8(P + ctr, 1);
+                fn1 = py * f1[c] + 2.f * (hs - 2.f * hy) * ihy * d8(P + ctr, W);
+                fn2 = pz * f2[c] + 2.f * (hs - 2.f * hz) * ihz * d8w(wu);
+                if constexpr (PSI) {
+                    const float k4 = 4.f * a.inv_dt;
+                    fn0 += k4 * hy * hz * ihx * d8(Q + ctr, 1);
+                    fn1 += k4 * hz * hx * ihy * d8(Q + ctr, W);
+                    fn2 += k4 * hx * hy * ihz * d8w(wp);
+                }
                 fw = true;
                 ff = fb;
             }
@@ -983,7 +993,12 @@ __global__ void ac3_finalize_kernel(Grid3 g, int nmodels, const float *acc, cons
 void launch_ac3_phi(const Ac3PhiArgs &a, int nshots, hipStream_t s)
 {
     if (a.g.P == 0 || nshots == 0 || a.nitems == 0) return;
-    ac3_phi_kernel<<<a.nitems * nshots, NTH3, 0, s>>>(a);
+    Ac3PhiArgs b = a;
+    b.nitems = a.nfree;
+    if (b.nitems > 0) ac3_phi_kernel<false><<<b.nitems * nshots, NTH3, 0, s>>>(b);
+    b.items = a.items + a.nfree;
+    b.nitems = a.nitems - a.nfree;
+    if (b.nitems > 0) ac3_phi_kernel<true><<<b.nitems * nshots, NTH3, 0, s>>>(b);
 }
 
 void launch_ac3_phi_adj(const Ac3PhiAdjArgs &a, int nshots, hipStream_t s)

@@ -69,6 +69,7 @@ struct Ac3PhiArgs {
     Grid3 g;
     const int4 *items;         // (xy tile, first plane, end plane) of the layer work
     int nitems;
+    int nfree;                 // the first nfree items have no cell with two axes in the layer
     const float *u, *psi;      // u^k, psi^k
     float *ph[3];              // in place
     Ac3Tabs t;

@@ -123,12 +123,13 @@ int check_shots(const sg_desc *d, int max_shots)
     return SG_OK;
 }
 
-// Entries of the 3-D layer pass's work list: at most two items per TZC_MIN
-// planes of every xy tile, and the padding of at most two groups per
-// TZC_MIN planes (see build_items3).
+// Entries of the 3-D layer pass's work list: per xy tile at most one item
+// per TZC_MIN planes plus one for each of the three z ranges (slab, interior,
+// slab) an item may not straddle, and, in each of the list's two parts, the
+// padding of one group per distinct first plane (see build_items3).
 size_t items3_cap(int ntiles, int NZ)
 {
-    const size_t per_col = (size_t)(NZ + TZC_MIN - 1) / TZC_MIN + 2;
+    const size_t per_col = (size_t)(NZ + TZC_MIN - 1) / TZC_MIN + 3;
     return (size_t)ntiles * per_col + 2 * per_col * (NXCD - 1);
 }
 
@@ -223,7 +224,7 @@ Layout make_layout(const sg_desc *d, int max_shots, int max_rec, int ckpt)
     L.off_soff = take(sizeof(int) * (size_t)max_shots * (L.ntiles + 1));
     L.off_sent = take(sizeof(int) * (size_t)max_shots * SG_MAX_SRC);
     L.off_nodef = take(sizeof(long long) * (size_t)max_shots * SG_MAX_SRC);
-    L.off_items = take(L.ndim == 3 ? sizeof(int4) * items3_cap(L.ntiles, L.g3.NZ) : 0);
+    L.off_items = take(L.ndim == 3 ? sizeof(int4) * 2 * items3_cap(L.ntiles, L.g3.NZ) : 0);
     L.off_flag = take(sizeof(int));
     L.total = o;
     return L;
@@ -260,6 +261,10 @@ struct sg_model {
     // 3-D acoustic layer pass: (xy tile, first plane, end plane) work items
     int4 *items3 = nullptr;
     int n_items3 = 0;
+    int n_items3_free = 0;        // the leading items whose cells have at most one axis in the layer
+    int4 *items3a = nullptr;      // the adjoint's list
+    int n_items3a = 0;
+    std::vector<int4> h_items3a;
     int zci = 0;                  // planes per layer work item
     // elastic launch settings: shots per thread (0: el2_group of the shots per
     // model) and cell block width
@@ -345,37 +350,71 @@ bool same_geometry(const sg_model *m, const sg_shots *sh)
 // multiple of NXCD (entries with tile -1, which return at once) and placed
 // so that XCD x takes the contiguous run x * per .. x * per + per - 1 of
 // them (per = ceil(n / NXCD)).  All XCDs then work on the same planes, each
-// on neighbouring tiles.  Returns nonzero, leaving the model's list as it
-// was, if the list would overflow its workspace slot.
+// on neighbouring tiles.  Two lists: the forward's, in two parts (the items
+// without psi terms first, each part grouped as above; the tiles by the
+// layer split at the z-slab boundaries so that an item is wholly in one
+// part), and the adjoint's, one list as above.  Returns nonzero, leaving the
+// model's lists as they were, if a list would overflow its workspace slot.
 int build_items3(sg_model *m, int zci)
 {
     const Layout &L = m->L;
     const Grid3 &g = L.g3;
-    std::vector<int4> raw;
+    // forward: items whose cells have at most one axis in the layer (no psi
+    // term) first, then the others; adjoint (no psi): one list in which the
+    // tiles by the layer take whole columns
+    std::vector<int4> raw[2], rawa;
     for (int t = 0; t < L.ntiles; ++t) {
         const int x0 = (t % g.ntx) * TX3, y0 = (t / g.ntx) * TY3;
-        const bool xy = x0 < g.P || x0 + TX3 > g.P + g.nx || y0 < g.P || y0 + TY3 > g.P + g.ny;
+        const bool lx = x0 < g.P || x0 + TX3 > g.P + g.nx, ly = y0 < g.P || y0 + TY3 > g.P + g.ny;
         auto add = [&](int za, int zb) {
-            for (int z = za; z < zb; z += zci) raw.push_back(make_int4(t, z, std::min(z + zci, zb), 0));
+            for (int z = za; z < zb; z += zci) {
+                const int ze = std::min(z + zci, zb);
+                const bool lz = z < g.P || ze > g.P + g.nz;
+                const bool two = (lx && ly) || ((lx || ly) && lz);
+                raw[two].push_back(make_int4(t, z, ze, 0));
+            }
         };
-        if (xy) add(0, g.NZ);
-        else { add(0, g.P); add(g.P + g.nz, g.NZ); }
-    }
-    std::stable_sort(raw.begin(), raw.end(), [](const int4 &a, const int4 &b) { return a.y < b.y; });
-    std::vector<int4> out;
-    for (size_t b = 0; b < raw.size();) {
-        size_t e = b;
-        while (e < raw.size() && raw[e].y == raw[b].y) ++e;
-        const size_t n = e - b, per = (n + NXCD - 1) / NXCD;
-        for (size_t sl = 0; sl < per * NXCD; ++sl) {
-            const size_t i = (sl % NXCD) * per + sl / NXCD;
-            out.push_back(i < n ? raw[b + i] : make_int4(-1, 0, 0, 0));
+        auto adda = [&](int za, int zb) {
+            for (int z = za; z < zb; z += zci) rawa.push_back(make_int4(t, z, std::min(z + zci, zb), 0));
+        };
+        if (lx || ly) {
+            add(0, g.P);                 // items never straddle a z-slab boundary
+            add(g.P, g.P + g.nz);
+            add(g.P + g.nz, g.NZ);
+            adda(0, g.NZ);
+        } else {
+            add(0, g.P);
+            add(g.P + g.nz, g.NZ);
+            adda(0, g.P);
+            adda(g.P + g.nz, g.NZ);
         }
-        b = e;
     }
-    if (out.size() > items3_cap(L.ntiles, g.NZ)) return 1;    // the model keeps its list
+    // each list grouped by first plane, each group in launch order
+    auto order = [](std::vector<int4> &r, std::vector<int4> &out) {
+        std::stable_sort(r.begin(), r.end(), [](const int4 &a, const int4 &b) { return a.y < b.y; });
+        for (size_t b = 0; b < r.size();) {
+            size_t e = b;
+            while (e < r.size() && r[e].y == r[b].y) ++e;
+            const size_t n = e - b, per = (n + NXCD - 1) / NXCD;
+            for (size_t sl = 0; sl < per * NXCD; ++sl) {
+                const size_t i = (sl % NXCD) * per + sl / NXCD;
+                out.push_back(i < n ? r[b + i] : make_int4(-1, 0, 0, 0));
+            }
+            b = e;
+        }
+    };
+    std::vector<int4> out, outa;
+    order(raw[0], out);
+    const size_t nfree = out.size();
+    order(raw[1], out);
+    order(rawa, outa);
+    const size_t cap = items3_cap(L.ntiles, g.NZ);
+    if (out.size() > cap || outa.size() > cap) return 1;    // the model keeps its lists
     m->h_items3.swap(out);
     m->n_items3 = (int)m->h_items3.size();
+    m->n_items3_free = (int)nfree;
+    m->h_items3a.swap(outa);
+    m->n_items3a = (int)m->h_items3a.size();
     m->zci = zci;
     return 0;
 }
@@ -978,6 +1017,7 @@ void fwd_step(const sg_model *m, int ns, const float *wav, int cu, int k, float 
         p.g = m->L.g3;
         p.items = m->items3;
         p.nitems = m->n_items3;
+        p.nfree = m->n_items3_free;
         p.u = m->fwd[cu];
         p.psi = m->fwd[5];
         for (int j = 0; j < 3; ++j) p.ph[j] = m->fwd[2 + j];
@@ -1099,8 +1139,8 @@ void adj_step(const sg_model *m, int ns, int ca, int k, const float *dJdd, float
     } else {
         Ac3PhiAdjArgs pa{};
         pa.g = m->L.g3;
-        pa.items = m->items3;
-        pa.nitems = m->n_items3;
+        pa.items = m->items3a;
+        pa.nitems = m->n_items3a;
         pa.s2 = m->adj[ca];
         pa.chat = m->chat;
         pa.shots_per_model = spm;
@@ -1423,6 +1463,7 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     }
     if (d->ndim == 3 && d->npml > 0) {
         m->items3 = reinterpret_cast<int4 *>(m->ws + L.off_items);
+        m->items3a = m->items3 + items3_cap(L.ntiles, L.g3.NZ);
         if (build_items3(m, TZCI_DEF)) {
             delete m;
             return fail(SG_EINVAL, "layer work list overflows its buffer");
@@ -1433,6 +1474,8 @@ int init_model(const sg_desc *d, const float *vp, const float *vs, const float *
     hipError_t e = hipMemcpyAsync(dev_tab, m->h_tab.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m->n_items3 > 0)
         e = hipMemcpyAsync(m->items3, m->h_items3.data(), sizeof(int4) * m->n_items3, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && m->n_items3a > 0)
+        e = hipMemcpyAsync(m->items3a, m->h_items3a.data(), sizeof(int4) * m->n_items3a, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m->n_layer > 0)
         e = hipMemcpyAsync(m->tiles_layer, m->h_layer.data(), sizeof(int) * m->n_layer, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !m->h_tiles3.empty())
@@ -1722,6 +1765,8 @@ int set_tuning(sg_model *m, int32_t key, int32_t value, sg_stream_t stream)
             hipStream_t s = reinterpret_cast<hipStream_t>(stream);
             HIPCHECK(hipStreamSynchronize(s));
             HIPCHECK(hipMemcpyAsync(m->items3, m->h_items3.data(), sizeof(int4) * m->n_items3,
+                                    hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemcpyAsync(m->items3a, m->h_items3a.data(), sizeof(int4) * m->n_items3a,
                                     hipMemcpyHostToDevice, s));
             HIPCHECK(hipStreamSynchronize(s));
         }
