@@ -254,19 +254,14 @@ __global__ void el2_inject_kernel(El2RecArgs a)
 }
 
 
-template <int GSH, int EBX>
-__global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
+// Pass 1 at one cell of one shot, from its stress adjoints sxx, szz, sxz:
+// the adjoints e1..e4 of the velocity differences (with the CPML memories),
+// the lam/mu/muxz gradient terms (added to g0..g2) and the source gradient.
+__device__ __forceinline__ void adj1_cell(const El2AdjArgs &a, const Cell &c, int shot, long long f, float sxx,
+                                          float szz, float sxz, float lam, float mu, float muxz, float &g0,
+                                          float &g1, float &g2)
 {
-    const Grid2 &g = a.g;
-    const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
-    if (!c.valid) return;
-    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-#pragma unroll
-    for (int j = 0; j < GSH; ++j) {
-        const int shot = c.shot * GSH + j;
-        const long long f = (long long)shot * g.plane + c.f;
-        const float sxx = a.a[E_SXX][f], szz = a.a[E_SZZ][f], sxz = a.a[E_SXZ][f];
+    {
         const float txx = a.kap * ((lam + 2.f * mu) * sxx + lam * szz);
         const float tzz = a.kap * (lam * sxx + (lam + 2.f * mu) * szz);
         const float txz = a.kap * muxz * sxz;
@@ -291,6 +286,62 @@ __global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
         if (a.gwav && c.f == a.src_f[shot])
             a.gwav[(long long)shot * a.nt + a.k] =
                 a.src_scale * (a.mt[3 * shot] * sxx + a.mt[3 * shot + 1] * szz + a.mt[3 * shot + 2] * sxz);
+    }
+}
+
+// Pass 3 at one cell of one shot: the stress adjoints minus the transposed
+// differences of d1..d4; returns them through sxx, szz, sxz (stored).
+__device__ __forceinline__ void adj3_cell(const El2AdjArgs &a, const Grid2 &g, long long f, int ix, int iz,
+                                          float &sxx, float &szz, float &sxz)
+{
+    const long long SX = g.SX;
+    sxx = a.a[E_SXX][f] - Dm(a.tmp[4], f, 1);
+    sxz = a.a[E_SXZ][f] - (Dp_sel<1>(g, a.tmp[5], a.tmp[4], f, SX, ix, iz) + Dp(a.tmp[6], f, 1));
+    szz = a.a[E_SZZ][f] - Dm_sel<1>(g, a.tmp[7], a.tmp[6], f, SX, ix, iz);
+    a.a[E_SXX][f] = sxx;
+    a.a[E_SXZ][f] = sxz;
+    a.a[E_SZZ][f] = szz;
+}
+
+template <int GSH, int EBX>
+__global__ __launch_bounds__(256) void el2_adj1_kernel(El2AdjArgs a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
+    if (!c.valid) return;
+    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < GSH; ++j) {
+        const int shot = c.shot * GSH + j;
+        const long long f = (long long)shot * g.plane + c.f;
+        adj1_cell(a, c, shot, f, a.a[E_SXX][f], a.a[E_SZZ][f], a.a[E_SXZ][f], lam, mu, muxz, g0, g1, g2);
+    }
+    const long long gf = c.so + c.f;
+    gacc(a.grad + gf, g0);
+    gacc(a.grad + a.grad_stride + gf, g1);
+    gacc(a.grad + 2 * a.grad_stride + gf, g2);
+}
+
+// Pass 3 of step k and pass 1 of step k - 1 in one launch (a: the arguments
+// of step k - 1): pass 1 reads the stress adjoints of its own cell only,
+// which pass 3 has just formed there, so one read and write of them serve
+// both.
+template <int GSH, int EBX>
+__global__ __launch_bounds__(256) void el2_adj31_kernel(El2AdjArgs a)
+{
+    const Grid2 &g = a.g;
+    const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model / GSH);   // c.shot: the group
+    if (!c.valid) return;
+    const float lam = a.m[M_LAM][c.mo + c.f], mu = a.m[M_MU][c.mo + c.f], muxz = a.m[M_MUXZ][c.mo + c.f];
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < GSH; ++j) {
+        const int shot = c.shot * GSH + j;
+        const long long f = (long long)shot * g.plane + c.f;
+        float sxx, szz, sxz;
+        adj3_cell(a, g, f, c.ix, c.iz, sxx, szz, sxz);
+        adj1_cell(a, c, shot, f, sxx, szz, sxz, lam, mu, muxz, g0, g1, g2);
     }
     const long long gf = c.so + c.f;
     gacc(a.grad + gf, g0);
@@ -345,10 +396,8 @@ __global__ __launch_bounds__(256) void el2_adj3_kernel(El2AdjArgs a)
     const Grid2 &g = a.g;
     const Cell c = cell_of<EBX, XCD_ADJ>(g, a.shots_per_model);
     if (!c.valid) return;
-    const long long f = c.so + c.f, SX = g.SX;
-    a.a[E_SXX][f] -= Dm(a.tmp[4], f, 1);
-    a.a[E_SXZ][f] -= Dp_sel<1>(g, a.tmp[5], a.tmp[4], f, SX, c.ix, c.iz) + Dp(a.tmp[6], f, 1);
-    a.a[E_SZZ][f] -= Dm_sel<1>(g, a.tmp[7], a.tmp[6], f, SX, c.ix, c.iz);
+    float sxx, szz, sxz;
+    adj3_cell(a, g, c.so + c.f, c.ix, c.iz, sxx, szz, sxz);
 }
 
 // Model fields on the frame (FP64 arithmetic, rounded once) and padded
@@ -508,6 +557,7 @@ void launch_el2_vel(const El2Args &a, hipStream_t s) { EL2_DISPATCH(el2_vel_kern
 void launch_el2_str(const El2Args &a, hipStream_t s) { EL2_DISPATCH(el2_str_kernel, a, XCD_FWD, s); }
 void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s) { EL2_DISPATCH(el2_adj1_kernel, a, XCD_ADJ, s); }
 void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s) { EL2_DISPATCH(el2_adj2_kernel, a, XCD_ADJ, s); }
+void launch_el2_adj31(const El2AdjArgs &a, hipStream_t s) { EL2_DISPATCH(el2_adj31_kernel, a, XCD_ADJ, s); }
 void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s)
 {
     if (a.ebx == 64) el2_adj3_kernel<64><<<cell_grid<64, XCD_ADJ>(a.g, a.nshots), 256, 0, s>>>(a);

@@ -89,6 +89,8 @@ void launch_el2_inject(const El2RecArgs &a, hipStream_t s);
 void launch_el2_adj1(const El2AdjArgs &a, hipStream_t s);
 void launch_el2_adj2(const El2AdjArgs &a, hipStream_t s);
 void launch_el2_adj3(const El2AdjArgs &a, hipStream_t s);
+// pass 3 of step k with pass 1 of step k - 1 (a: the arguments of step k - 1)
+void launch_el2_adj31(const El2AdjArgs &a, hipStream_t s);
 void launch_el2_prep(const Grid2 &g, int nmodels, const float *vp, const float *vs, const float *rho,
                      float *const *model, float *const *phys_pad, hipStream_t s);
 void launch_el2_finalize(const Grid2 &g, int nmodels, int spm, int gs, const float *grad, long long grad_stride,

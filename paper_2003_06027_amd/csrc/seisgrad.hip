@@ -767,7 +767,12 @@ void el_fwd_step(const sg_model *m, int ns, const float *wav, int k, float *seis
     launch_el2_str(a, s);
 }
 
-void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwav, const float *snap, hipStream_t s)
+// Elastic adjoint step k: pass 1 (unless the previous launch ran it: first =
+// false), the receiver injection, pass 2, and pass 3 -- with the next step's
+// pass 1 when that step's snapshots are at hand (snap_next, step k - 1 of
+// the same segment).
+void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwav, const float *snap, hipStream_t s,
+                 bool first = true, const float *snap_next = nullptr)
 {
     El2AdjArgs a{};
     a.g = m->L.g2;
@@ -790,7 +795,7 @@ void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwa
     a.nt = m->d.nt;
     a.k = k;
     a.src_scale = (float)(m->d.dt / (m->d.dx * m->d.dx));
-    launch_el2_adj1(a, s);
+    if (first) launch_el2_adj1(a, s);
     if (m->geom_nrec > 0) {
         El2RecArgs r{};
         r.nshots = ns; r.nrec = m->geom_nrec; r.nt = m->d.nt; r.k = k;
@@ -802,7 +807,14 @@ void el_adj_step(const sg_model *m, int ns, int k, const float *dJdd, float *gwa
         launch_el2_inject(r, s);
     }
     launch_el2_adj2(a, s);
-    launch_el2_adj3(a, s);
+    if (snap_next) {
+        El2AdjArgs b = a;
+        b.k = k - 1;
+        b.snap = snap_next;
+        launch_el2_adj31(b, s);
+    } else {
+        launch_el2_adj3(a, s);
+    }
 }
 
 // 2-D divergence form.  Forward: u^k in fwd[k & 1] (u^{k+1} overwrites
@@ -1675,6 +1687,10 @@ int adjoint_gradient(sg_model *m, const sg_shots *sh, const float *dJ_dd, float 
                 k -= two ? 2 : 1;
             } else if (ad2) {
                 ad2_adj_step(m, ns, k, dJ_dd, g_wavelet, snap(k), st);
+                --k;
+            } else if (L.elastic) {
+                // pass 3 of step k and pass 1 of step k - 1 share a launch within the segment
+                el_adj_step(m, ns, k, dJ_dd, g_wavelet, snap(k), st, k == k1 - 1, k > k0 ? snap(k - 1) : nullptr);
                 --k;
             } else {
                 adj_step(m, ns, ca, k, dJ_dd, g_wavelet, snap(k), st);
