@@ -102,6 +102,28 @@ __device__ __forceinline__ bool plane_near_z(const Grid3 &g, int z)
     return g.P > 0 && (z - 4 < g.P || z + 4 >= g.P + g.nz);
 }
 
+// psi (forward) and its adjoint e enter the recursion only through terms
+// with the damping of two or three axes (s3 psi; h_a h_b D~_j psi, whose
+// stencil along j stays on cells with the same two damped axes), so they are
+// kept only on cells with at least two damped axes: elsewhere they stay
+// zero, and a tile plane without such cells reads them from one shared zero
+// line of the frame instead of its columns.  Planes of a tile that may hold
+// such cells: every plane if the tile meets the layer in x and in y, the z
+// slabs if it meets it in x or in y.
+struct TwoAxis {
+    bool xy, any;
+    __device__ bool plane(const Grid3 &g, int z) const { return xy || (any && (z < g.P || z >= g.P + g.nz)); }
+};
+__device__ __forceinline__ TwoAxis two_axis_tile(const Grid3 &g, int x0, int y0)
+{
+    const bool tx = x0 < g.P || x0 + TX3 > g.P + g.nx, ty = y0 < g.P || y0 + TY3 > g.P + g.ny;
+    return TwoAxis{tx && ty, tx || ty};
+}
+__device__ __forceinline__ bool two_axis_cell(float hx, float hy, float hz)
+{
+    return (hx > 0.f) + (hy > 0.f) + (hz > 0.f) >= 2;
+}
+
 // Halo ring of a (TY3+8) x (TX3+8) plane tile: rows 0-3 and TY3+4.. full
 // width, then 4 + 4 columns of the middle rows.
 __device__ __forceinline__ void ring_rc(int i, int &r, int &c)
@@ -406,6 +428,7 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
     // LAYER: the phi_z window, this column's phi_x, phi_y and psi, and one
     // halo cell: of phi_x (the first 8 TY3 threads) or of phi_y (the next 8 TX3)
     float pz[LAYER ? ZR : 1], pxv[NB], pyv[NB], hvv[NB], psv[NB];
+    const TwoAxis two = two_axis_tile(g, x0, y0);
     int hslot = -1;
     const float *hsrc = phx;
     unsigned hob = colb;
@@ -428,7 +451,7 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
             const unsigned o = pbc(z0 + d);
             pxv[d] = ldb(phx, colb + o);
             pyv[d] = ldb(phy, colb + o);
-            psv[d] = ldb(psi, colb + o);
+            psv[d] = ldb(psi, two.plane(g, z0 + d) ? colb + o : 0u);
             hvv[d] = ldb(hsrc, hob + o);
         }
         if (valid_xy) {
@@ -482,7 +505,7 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
                 chv[n] = ldn(chat, colb + d1);
                 if constexpr (LAYER) {
                     pz[(r + 8 + PD) % ZR] = ldb(phz, colb + dw);
-                    psv[n] = ldb(psi, colb + d1);
+                    psv[n] = ldb(psi, two.plane(g, z + PD) ? colb + d1 : 0u);
                 }
             }
             float qw[9];
@@ -507,7 +530,7 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
                         // copy of z (no strength-reduced stencil addresses)
                         const unsigned fo = colb + pb(__builtin_amdgcn_readfirstlane(z));
                         wv += d8b(phx, fo, 4u) + d8b(phy, fo, SYB) + d8b(phz, fo, SZB);
-                        ps = ldb(psi, fo);
+                        ps = 0.f;                  // only z damped here: psi is not kept
                     }
                     const float hz = a.t.h[2][z];
                     const float hs = hx + hy + hz;
@@ -515,7 +538,7 @@ void ac3_fwd_kernel(Ac3FwdArgs a)
                     if (hs > 0.f) inc -= 8.f * hx * hy * hz * a.inv_dt * ps;
                     if (at_src) inc += sval;
                     un = (c0 + inc) / (1.f + hs);
-                    if (hs > 0.f) {
+                    if (two_axis_cell(hx, hy, hz)) {
                         psw = true;
                         psn = ps + a.dt * un;
                         psf = fb;
@@ -756,6 +779,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
     // LAYER: b_z window, own b_x, b_y, e, one halo cell of b_x or b_y, and
     // the tables at the own column, row and halo cell
     float bzw[LAYER ? AZR : 1], bxv[ANB], byv[ANB], hbv[ANB], ev[ANB];
+    const TwoAxis two = two_axis_tile(g, x0, y0);
     float hxo = 0.f, ihxo = 1.f, hyo = 0.f, ihyo = 1.f, hho = 0.f, ihho = 1.f;
     int hslot = -1;
     const float *hsrc = bxp;
@@ -783,7 +807,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
             bxv[d] = ldb(bxp, colb + o);
             byv[d] = ldb(byp, colb + o);
             hbv[d] = ldb(hsrc, hob + o);
-            ev[d] = ldb(ee, colb + o);
+            ev[d] = ldb(ee, two.plane(g, z0 + d) ? colb + o : 0u);
         }
     }
     const float *tz = a.t.h[2], *iz = a.t.ih[2];
@@ -839,7 +863,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
                 gv[n] = ldn(grad, colb + d1);
                 if constexpr (LAYER) {
                     bzw[(r + 8 + APD) % AZR] = ldb(bzp, colb + dw);
-                    ev[n] = ldb(ee, colb + d1);
+                    ev[n] = ldb(ee, two.plane(g, z + APD) ? colb + d1 : 0u);
                 }
             }
             float qw[9];
@@ -872,7 +896,7 @@ void ac3_adj_kernel(Ac3AdjArgs a)
                     const float de = 4.f * a.inv_dt * (hyo * hz * drx + hz * hxo * dry + hxo * hyo * drz);
                     if (hs > 0.f) {
                         const float en = ev[c] - 8.f * hxo * hyo * hz * a.inv_dt * sraw - de;
-                        esw = true;
+                        esw = two_axis_cell(hxo, hyo, hz);
                         esn = en;
                         esf = fb;
                         v += a.dt * en;
@@ -890,7 +914,6 @@ void ac3_adj_kernel(Ac3AdjArgs a)
                         dq += dcoef(m) * (tz[zz - m] * iz[zz - m] * ldb(bzp, fo - m * SZB)
                                           - tz[zz + m] * iz[zz + m] * ldb(bzp, fo + m * SZB));
                     v -= 2.f * (hs * (d8b(bxp, fo, 4u) + d8b(byp, fo, SYB)) + dq);
-                    if (hs > 0.f) v += a.dt * ldb(ee, fo);
                     v += sraw + ((sraw - s3f) + hs * s3f);
                 } else {
                     v += sraw + (sraw - s3f);
