@@ -26,7 +26,8 @@
  * Conventions: all pointers are device pointers, 16-byte aligned where they
  * address BF16 activations; calls are asynchronous on `stream` (NULL = the
  * null stream); they return SG_OK or a negative SG_E* code (seisgrad.h) with
- * a message in last_error().  The library allocates nothing: scratch comes
+ * a message in last_error().  Image extents must be positive with n h w
+ * below 2^29 pixels (SG_EINVAL otherwise).  The library allocates nothing: scratch comes
  * from the caller's workspace.  Calls that share a workspace must not overlap.
  */
 #ifndef SG_CNN_H
@@ -89,7 +90,8 @@ SG_API int cnn_unpack(const float *patches, int32_t nfields, int32_t fh, int32_t
  * (may be NULL, BF16 like x); v = max(v, 0) if relu; v = 0 where gate <= 0
  * (gate may be NULL, BF16 like x).  y gets v in BF16, y32 (may be NULL) in
  * FP32.  This is the forward of c2..c5 and, with the weights flipped and
- * transposed, their input gradient. */
+ * transposed, their input gradient.  x, wgt, res, gate, y and y32 must be
+ * 16-byte aligned (SG_EINVAL otherwise). */
 SG_API int cnn_conv3x3(const uint16_t *x, int32_t n, int32_t h, int32_t w, const uint16_t *wgt,
                        const float *bias, const uint16_t *res, const uint16_t *gate, int32_t relu,
                        uint16_t *y, float *y32, sg_stream_t stream);

@@ -38,6 +38,7 @@ constexpr int NT = 256;                  // threads per workgroup (4 wavefronts)
 constexpr int WMID = CH * 9 * CH;        // weights of one 32 -> 32 layer
 constexpr int PMID = WMID + CH;          // ... with its biases
 constexpr int OFF_C1 = 0, OFF_C2 = 9 * CH + CH, OFF_C6 = OFF_C2 + 4 * PMID;
+constexpr int GC = 2, GW = 2, GT = 2;       // staging steps whose loads are issued together (conv, wgrad, thin wgrad)
 constexpr int MAX_WG_WGRAD = 512;        // workgroups (partials) of the MFMA weight gradient
 constexpr int MAX_WG_THIN = 1024;        // ... of the thin-layer weight gradients
 constexpr int THIN_STRIDE = 320;         // partial row of a thin layer (289 or 320 used)
@@ -66,33 +67,57 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 }
 
 // Stage pixels (y0-1 .. y0+TH, x0-1 .. x0+TW) of image n (zero outside) into
-// LDS, 16 bytes (8 channels) per thread and step.
+// LDS, 16 bytes (8 channels) per thread and step.  The loads of G steps are
+// issued before their LDS writes, so a tile costs ceil(steps / G) memory
+// latencies rather than one per step; G trades that against registers.
+template <int G>
 __device__ __forceinline__ void stage_halo(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
                                           u16 *lds)
 {
-    for (int i = threadIdx.x; i < LH * LW * 4; i += NT) {
-        const int pix = i >> 2, q = i & 3;
-        const int r = pix / LW, c = pix - r * LW;
-        const int y = y0 - 1 + r, xx = x0 - 1 + c;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (y >= 0 && y < H && xx >= 0 && xx < W)
-            v = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
-        *(u32x4 *)(lds + pix * PS + q * 8) = v;
+    constexpr int NV = LH * LW * 4, K = (NV + NT - 1) / NT;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += G) {
+        u32x4 v[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
+            const int r = pix / LW, c = pix - r * LW;
+            const int y = y0 - 1 + r, xx = x0 - 1 + c;
+            v[k] = u32x4{0u, 0u, 0u, 0u};
+            if (k0 + k < K && i < NV && y >= 0 && y < H && xx >= 0 && xx < W)
+                v[k] = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
+            if (k0 + k < K && i < NV) *(u32x4 *)(lds + pix * PS + q * 8) = v[k];
+        }
     }
 }
 
-// Stage pixels (y0 .. y0+TH-1, x0 .. x0+TW-1) without halo.
+// Stage pixels (y0 .. y0+TH-1, x0 .. x0+TW-1) without halo, G steps' loads at a time as above.
+template <int G>
 __device__ __forceinline__ void stage_plain(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
                                            u16 *lds)
 {
-    for (int i = threadIdx.x; i < TH * TW * 4; i += NT) {
-        const int pix = i >> 2, q = i & 3;
-        const int r = pix / TW, c = pix - r * TW;
-        const int y = y0 + r, xx = x0 + c;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (y < H && xx < W)
-            v = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
-        *(u32x4 *)(lds + pix * PS + q * 8) = v;
+    constexpr int NV = TH * TW * 4, K = NV / NT;
+    static_assert(NV % NT == 0 && K % G == 0, "whole steps");
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += G) {
+        u32x4 v[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
+            const int r = pix / TW, c = pix - r * TW;
+            const int y = y0 + r, xx = x0 + c;
+            v[k] = u32x4{0u, 0u, 0u, 0u};
+            if (y < H && xx < W) v[k] = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
+            *(u32x4 *)(lds + pix * PS + q * 8) = v[k];
+        }
     }
 }
 
@@ -109,10 +134,16 @@ struct ConvArgs {
 // grid (ceil(W/64), ceil(H/4), N).  Lane l of a wavefront: r = l % 16 is the
 // fragment row (a pixel for A, an output channel for B), g = l / 16 selects
 // the 8 channels 8g .. 8g+7 of the K-block; the accumulator holds output
-// pixels 4g .. 4g+3 of each 16-pixel block for output channel r.
+// pixels 4g .. 4g+3 of each 16-pixel block for output channel r.  The
+// accumulators go through LDS ([pixel][channel], FP32) so that the epilogue
+// reads and writes 8 channels of a pixel per lane in 16- and 32-byte
+// accesses instead of single 2- and 4-byte elements.
+constexpr int OS = CH + 4;                 // FP32 stride of an output pixel in LDS
+constexpr int CONV_LDS = LH * LW * PS * 2 > 4 * TW * OS * 4 ? LH * LW * PS * 2 : 4 * TW * OS * 4;
 __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
 {
-    __shared__ __attribute__((aligned(16))) u16 lds[LH * LW * PS];
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[CONV_LDS];
+    u16 *lds = reinterpret_cast<u16 *>(lds_raw);
     const int n = blockIdx.z, y0 = blockIdx.y * TH, x0 = blockIdx.x * TW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
@@ -124,7 +155,7 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         for (int nb = 0; nb < 2; ++nb)
             bw[t][nb] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(a.w + ((16 * nb + r) * 9 + t) * CH + 8 * g));
 
-    stage_halo(a.x, n, a.H, a.W, y0, x0, lds);
+    stage_halo<GC>(a.x, n, a.H, a.W, y0, x0, lds);
     __syncthreads();
 
     f32x4 acc[4][2];
@@ -143,28 +174,48 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         }
     }
 
+    __syncthreads();                       // every wavefront is done with the input tile
+    float *orow = reinterpret_cast<float *>(lds_raw) + wv * TW * OS;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) orow[(16 * mb + 4 * g + j) * OS + 16 * nb + r] = acc[mb][nb][j];
+    __syncthreads();
+
     const int y = y0 + wv;
     if (y >= a.H) return;
     const long long rowbase = ((long long)n * a.H + y) * a.W;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int it = 0; it < TW * 4 / 64; ++it) {
+        const int item = lane + 64 * it, px = item >> 2, q = item & 3;   // 8 channels 8q .. 8q+7 of pixel px
+        if (x0 + px >= a.W) continue;
+        const long long idx = (rowbase + x0 + px) * CH + 8 * q;
+        const f32x4 lo = *reinterpret_cast<const f32x4 *>(orow + px * OS + 8 * q);
+        const f32x4 hi = *reinterpret_cast<const f32x4 *>(orow + px * OS + 8 * q + 4);
+        const float acc8[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        u16x8 rv = {0, 0, 0, 0, 0, 0, 0, 0}, gv = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (a.res) rv = *reinterpret_cast<const u16x8 *>(a.res + idx);
+        if (a.gate) gv = *reinterpret_cast<const u16x8 *>(a.gate + idx);
+        float v8[8];
+        u16x8 o;
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            const int co = 16 * nb + r;
-            const float b = a.bias ? a.bias[co] : 0.f;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int px = x0 + 16 * mb + 4 * g + j;
-                if (px >= a.W) continue;
-                const long long idx = (rowbase + px) * CH + co;
-                float v = acc[mb][nb][j] + b;
-                if (a.res) v += bf2f(a.res[idx]);
-                if (a.relu) v = fmaxf(v, 0.f);
-                if (a.gate && !(bf2f(a.gate[idx]) > 0.f)) v = 0.f;
-                a.y[idx] = f2bf(v);
-                if (a.y32) a.y32[idx] = v;
-            }
+        for (int k = 0; k < 8; ++k) {
+            const float b = a.bias ? a.bias[8 * q + k] : 0.f;
+            float v = acc8[k] + b;
+            if (a.res) v += bf2f(rv[k]);
+            if (a.relu) v = fmaxf(v, 0.f);
+            if (a.gate && !(bf2f(gv[k]) > 0.f)) v = 0.f;
+            v8[k] = v;
+            o[k] = f2bf(v);
         }
+        *reinterpret_cast<u16x8 *>(a.y + idx) = o;
+        if (a.y32) {
+            *reinterpret_cast<f32x4 *>(a.y32 + idx) = f32x4{v8[0], v8[1], v8[2], v8[3]};
+            *reinterpret_cast<f32x4 *>(a.y32 + idx + 4) = f32x4{v8[4], v8[5], v8[6], v8[7]};
+        }
+    }
 }
 
 // Weight gradient, K = pixels.  Each wavefront owns one tile row (two
@@ -177,7 +228,7 @@ struct WgradArgs {
     int N, H, W, tx, ty, ntiles;
 };
 
-__global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void wgrad3x3_mfma_kernel(WgradArgs a)
 {
     __shared__ __attribute__((aligned(16))) u16 smem[LH * LW * PS + TH * TW * PS];
     u16 *lx = smem, *lg = smem + LH * LW * PS;
@@ -197,8 +248,8 @@ __global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
         const int n = tile / per, rem = tile - n * per;
         const int y0 = (rem / a.tx) * TH, x0 = (rem - (rem / a.tx) * a.tx) * TW;
         __syncthreads();
-        stage_halo(a.x, n, a.H, a.W, y0, x0, lx);
-        stage_plain(a.dy, n, a.H, a.W, y0, x0, lg);
+        stage_halo<GW>(a.x, n, a.H, a.W, y0, x0, lx);
+        stage_plain<GW>(a.dy, n, a.H, a.W, y0, x0, lg);
         __syncthreads();
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
@@ -263,16 +314,28 @@ __global__ __launch_bounds__(NT) void wgrad3x3_mfma_kernel(WgradArgs a)
 
 // out[i] = sum over b of part[b][i] in FP64, in a fixed order: lane l of
 // output i sums rows b = l, l + 16, ... in ascending order, then the 16 lane
-// sums are added in lane order.  256 threads = 16 outputs x 16 lanes.
+// sums are added in lane order.  256 threads = 16 outputs x 16 lanes.  A lane
+// issues the loads of 16 of its rows before adding them, so that a chain of
+// nb / 16 rows costs nb / 256 memory latencies.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const float *__restrict__ part, int nb, int stride,
                                                               int count, float *__restrict__ out)
 {
+    constexpr int U = 16;
     __shared__ double red[16][17];
     const int o = threadIdx.x & 15, l = threadIdx.x >> 4;
     const int i = blockIdx.x * 16 + o;
     double s = 0.0;
-    if (i < count)
-        for (int b = l; b < nb; b += 16) s += (double)part[(long long)b * stride + i];
+    if (i < count) {
+        int b = l;
+        for (; b + 16 * (U - 1) < nb; b += 16 * U) {
+            float v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) v[k] = part[(long long)(b + 16 * k) * stride + i];
+#pragma unroll
+            for (int k = 0; k < U; ++k) s += (double)v[k];
+        }
+        for (; b < nb; b += 16) s += (double)part[(long long)b * stride + i];
+    }
     red[l][o] = s;
     __syncthreads();
     if (l == 0 && i < count) {
@@ -369,7 +432,10 @@ __global__ __launch_bounds__(256) void dgrad_out_kernel(const float *__restrict_
                                                         const float *__restrict__ params, u16 *__restrict__ G,
                                                         int N, int H, int W)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // four threads per pixel (channels 8q .. 8q+7), whole-pixel 1 KiB
+    // accesses per wavefront instruction
+    const long long tq = (long long)blockIdx.x * blockDim.x + threadIdx.x, i = tq >> 2;
+    const int q = (int)(tq & 3);
     if (i >= (long long)N * H * W) return;
     int n, y, x;
     pixel_of(i, H, W, n, y, x);
@@ -380,23 +446,18 @@ __global__ __launch_bounds__(256) void dgrad_out_kernel(const float *__restrict_
         d[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? dp[((long long)n * H + yy) * W + xx] : 0.f;
     }
     const float *w = params + OFF_C6;
-    const u32x4 *gate = (const u32x4 *)(x3 + i * CH);
-    u32x4 *out = (u32x4 *)(G + i * CH);
+    const u32x4 gt = *(const u32x4 *)(x3 + i * CH + 8 * q);
+    float o[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const u32x4 gt = gate[q];
-        float o[8];
+    for (int e = 0; e < 8; ++e) {
+        const int ci = 8 * q + e;
+        float s = 0.f;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int ci = 8 * q + e;
-            float s = 0.f;
-#pragma unroll
-            for (int t = 0; t < 9; ++t) s = fmaf(w[t * CH + ci], d[t], s);
-            const unsigned gv = (e & 1) ? (gt[e >> 1] & 0xffff0000u) : (gt[e >> 1] << 16);
-            o[e] = __uint_as_float(gv) > 0.f ? s : 0.f;
-        }
-        out[q] = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+        for (int t = 0; t < 9; ++t) s = fmaf(w[t * CH + ci], d[t], s);
+        const unsigned gv = (e & 1) ? (gt[e >> 1] & 0xffff0000u) : (gt[e >> 1] << 16);
+        o[e] = __uint_as_float(gv) > 0.f ? s : 0.f;
     }
+    *(u32x4 *)(G + i * CH + 8 * q) = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
 }
 
 // Weight gradients of the thin layers, on the 4 x 64 pixel tiles of the
@@ -420,13 +481,13 @@ __global__ __launch_bounds__(NT) void wgrad_thin_kernel(const float *__restrict_
         const int y0 = (rem / tx) * TH, x0 = (rem - (rem / tx) * tx) * TW;
         __syncthreads();
         if (OUT) {
-            stage_halo(act, n, H, W, y0, x0, la);
+            stage_halo<GT>(act, n, H, W, y0, x0, la);
             for (int i = threadIdx.x; i < TH * TW; i += NT) {
                 const int y = y0 + i / TW, x = x0 + i % TW;
                 li[i] = (y < H && x < W) ? img[((long long)n * H + y) * W + x] : 0.f;
             }
         } else {
-            stage_plain(act, n, H, W, y0, x0, la);
+            stage_plain<GT>(act, n, H, W, y0, x0, la);
             for (int i = threadIdx.x; i < LH * LW; i += NT) {
                 const int y = y0 - 1 + i / LW, x = x0 - 1 + i % LW;
                 li[i] = (y >= 0 && y < H && x >= 0 && x < W) ? img[((long long)n * H + y) * W + x] : 0.f;
@@ -631,7 +692,7 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 int check_dims(int n, int h, int w)
 {
     if (n < 1 || h < 1 || w < 1) return fail(SG_EINVAL, "image extents must be positive (n=%d h=%d w=%d)", n, h, w);
-    if ((long long)n * h * w * CH >= (1LL << 40)) return fail(SG_EINVAL, "images too large");
+    if ((long long)n * h * w >= (1LL << 29)) return fail(SG_EINVAL, "images too large (n h w >= 2^29 pixels)");
     return SG_OK;
 }
 
@@ -741,7 +802,7 @@ int cnn_backward(const float *params, const float *g, const float *dp, int32_t n
     const long long pix = (long long)n * h * w;
 
     if (int e = launch_wgrad_thin<true>(dp, x3, n, h, w, part, grad + OFF_C6, s)) return e;
-    dgrad_out_kernel<<<blocks(pix), 256, 0, s>>>(dp, x3, params, G0, n, h, w);           // G0 = d pre(x3)
+    dgrad_out_kernel<<<blocks(4 * pix), 256, 0, s>>>(dp, x3, params, G0, n, h, w);           // G0 = d pre(x3)
     HIPCHECK(hipGetLastError());
     float *gm = grad + OFF_C2;
     if (int e = launch_wgrad(G0, a4, n, h, w, part, gm + 3 * PMID, s)) return e;
@@ -833,7 +894,8 @@ int cnn_conv3x3(const uint16_t *x, int32_t n, int32_t h, int32_t w, const uint16
 {
     if (int e = check_dims(n, h, w)) return e;
     if (!x || !wgt || !y) return fail(SG_EINVAL, "NULL pointer argument");
-    if (!aligned16(x) || !aligned16(wgt)) return fail(SG_EINVAL, "x and wgt must be 16-byte aligned");
+    if (!aligned16(x) || !aligned16(wgt) || !aligned16(res) || !aligned16(gate) || !aligned16(y) || !aligned16(y32))
+        return fail(SG_EINVAL, "x, wgt, res, gate, y and y32 must be 16-byte aligned");
     return launch_conv(x, n, h, w, wgt, bias, res, gate, relu, y, y32, (hipStream_t)stream);
 }
 
