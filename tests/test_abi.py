@@ -112,3 +112,11 @@ def test_cnn_entry_points_validate_on_host():
     assert L.cnn_pack(None, None, 1, None, 1, 5, 5, 4, 1, None, None, None, None) == S.SG_EINVAL
     assert L.cnn_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == S.SG_EINVAL
     assert L.cnn_conv3x3(None, 1, 4, 4, None, None, None, None, 0, None, None, None) == S.SG_EINVAL
+    # the epilogue's 16-byte accesses: a misaligned output, residual or gate is refused before any launch
+    # (the addresses below are never dereferenced)
+    for res, gate, y, y32 in ((None, None, 4096 + 2, None), (4096 + 8, None, 4096, None),
+                              (None, 4096 + 4, 4096, None), (None, None, 4096, 4096 + 12)):
+        assert L.cnn_conv3x3(4096, 1, 4, 4, 4096, None, res, gate, 0, y, y32, None) == S.SG_EINVAL
+        assert b"16-byte aligned" in L.last_error()
+    assert L.cnn_conv3x3(4096, 1, 1 << 15, 1 << 14, 4096, None, None, None, 0, 4096, None, None) == S.SG_EINVAL
+    assert b"too large" in L.last_error()

@@ -62,8 +62,11 @@ def test_conv3x3_layer_matches_oracle(shape):
                            None if gg is None else gd, relu, want_fp32=True)
         e = rel_l2(y32.cpu().numpy(), ref) if np.any(ref) else float(np.abs(y32.cpu().numpy()).max())
         assert e <= 1e-5, (shape, args[3], e)
-        # the BF16 output is the FP32 result rounded to nearest even
+        # the BF16 output is the FP32 result rounded to nearest even, with or without the FP32 copy
         assert torch.equal(y, y32.to(torch.bfloat16))
+        y_only = N.conv3x3(xd, wd, None if bb is None else dev(bb), None if rr is None else rd,
+                           None if gg is None else gd, relu)
+        assert torch.equal(y_only, y)
 
 
 @pytest.mark.parametrize("shape", [(2, 37, 70), (2, 256, 256), (1, 3, 5)])
