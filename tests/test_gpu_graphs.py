@@ -190,6 +190,69 @@ def test_update_model_equals_a_fresh_model_and_keeps_graphs():
     m.close()
 
 
+def _update_case(label, d, sh, make, old, new, ckpt):
+    """make(params) -> Model; compares an updated model (segment graphs on,
+    captured for `old`) with one prepared from scratch for `new`."""
+    mo = make(new)
+    seis_ref = mo.forward(sh, save_ckpt=False).clone()
+    obs = (0.9 * seis_ref).contiguous()
+    mo.close()
+    fresh = make(new)
+    s_ref, r_ref = torch.empty_like(obs), torch.empty_like(obs)
+    g_ref = _sweep(fresh, sh, obs, s_ref, r_ref)
+    g_ref = tuple(t.clone() for t in (g_ref if isinstance(g_ref, tuple) else (g_ref,)))
+    fresh.close()
+    m = make(old)
+    m.set_tuning(S.SG_TUNE_GRAPHS, 1)
+    seis, r = torch.empty_like(obs), torch.empty_like(obs)
+    _sweep(m, sh, obs, seis, r)                     # segments captured for the old parameters
+    m.update(*new)
+    with pytest.raises(S.SeisError):
+        m.gradient(sh, r)                           # the checkpoints are stale
+    g = _sweep(m, sh, obs, seis, r)
+    g = g if isinstance(g, tuple) else (g,)
+    assert torch.equal(seis, s_ref), label
+    assert all(torch.equal(a, b) for a, b in zip(g, g_ref)), label
+    assert all(torch.count_nonzero(a) > 0 for a in g), label
+    print(f"{label}: update_model equals a fresh model bit for bit")
+    m.close()
+
+
+def test_update_model_3d_elastic_and_divergence_form():
+    nx, ny, nz, P, nt = 40, 36, 44, 12, 60
+    c = 1600.0 + 1200.0 * synth.smooth_random(21, (nz, ny, nx), 3.0, 0.0, 1.0)
+    d = S.desc(ndim=3, nx=nx, ny=ny, nz=nz, npml=P, nt=nt, dx=10.0, dt=1e-3, pml_vmax=2800.0)
+    src = np.array([[20, 18, 2]], dtype=np.int32)
+    xs, ys = np.meshgrid(np.arange(0, nx, 4), np.arange(0, ny, 4), indexing="xy")
+    rec = np.stack([xs.ravel(), ys.ravel(), np.zeros(xs.size, dtype=int)], -1)[None].astype(np.int32)
+    sh = S.Shots(src, rec, S.ricker(20.0, 0.05, 1e-3, nt)[None].contiguous())
+    _update_case("3-D", d, sh, lambda p: S.Model(d, p[0], 1, rec.shape[1], 9),
+                 (dev(synth.smooth(c, 2.0)),), (dev(c),), 9)
+
+    nx, nz, P, nt = 70, 50, 10, 160
+    vp = 1800.0 + 2200.0 * synth.smooth_random(6027, (nz, nx), 8.0, 0.0, 1.0)
+    vs, rho = vp / 1.75, 310.0 * vp ** 0.25
+    d = S.desc(ndim=2, physics=S.SG_ELASTIC, nx=nx, nz=nz, npml=P, nt=nt, dx=5.0, dt=0.5e-3, pml_vmax=4000.0,
+               f0_pml=15.0)
+    src = np.array([[20, 5], [45, 20]], dtype=np.int32)
+    mt_ = np.array([[1.0, 1.0, 0.0], [-0.5, 0.5, 0.86]])
+    rec = np.stack([np.stack([np.arange(0, nx, 3), np.zeros(24)], -1)] * 2).astype(np.int32)
+    sh = S.Shots(src, rec, S.ricker(20.0, 0.05, 0.5e-3, nt)[None].repeat(2, 1).contiguous(), mt=mt_)
+    old = tuple(dev(synth.smooth(a, 4.0)) for a in (vp, vs, rho))
+    _update_case("elastic", d, sh, lambda p: S.Model(d, p[0], 2, rec.shape[1], 13, vs=p[1], rho=p[2]),
+                 old, (dev(vp), dev(vs), dev(rho)), 13)
+
+    cfg = synth.C1.replace(nx=160, nz=100, npml=12, nt=200)
+    c = 1600.0 + 1000.0 * synth.smooth_random(5, (cfg.nz, cfg.nx), 6.0, 0.0, 1.0)
+    d = S.desc(ndim=2, physics=S.SG_ACOUSTIC_DIV, nx=cfg.nx, nz=cfg.nz, npml=cfg.npml, nt=cfg.nt, dx=cfg.dx,
+               dt=cfg.dt, pml_vmax=2600.0)
+    src = np.array([[80, 3]], dtype=np.int32)
+    rec = np.stack([np.stack([np.arange(0, 160, 2), np.full(80, 2)], -1)]).astype(np.int32)
+    sh = S.Shots(src, rec, S.ricker(15.0, 0.07, cfg.dt, cfg.nt)[None].contiguous())
+    _update_case("divergence form", d, sh, lambda p: S.Model(d, p[0], 1, rec.shape[1], 15),
+                 (dev(synth.smooth(c, 5.0)),), (dev(c),), 15)
+
+
 def test_inversion_loops_with_graphs_equal_eager_runs():
     """Plain and L-BFGS batched inversion on a propagator that replays its
     segments as graphs (parameters replaced in place, kept buffers) give the
