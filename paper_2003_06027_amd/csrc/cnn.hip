@@ -38,7 +38,7 @@ constexpr int NT = 256;                  // threads per workgroup (4 wavefronts)
 constexpr int WMID = CH * 9 * CH;        // weights of one 32 -> 32 layer
 constexpr int PMID = WMID + CH;          // ... with its biases
 constexpr int OFF_C1 = 0, OFF_C2 = 9 * CH + CH, OFF_C6 = OFF_C2 + 4 * PMID;
-constexpr int GC = 2, GW = 2, GT = 2;       // staging steps whose loads are issued together (conv, wgrad, thin wgrad)
+constexpr int GW = 2, GT = 2;               // staging steps whose loads are issued together (wgrad, thin wgrad)
 constexpr int MAX_WG_WGRAD = 512;        // workgroups (partials) of the MFMA weight gradient
 constexpr int MAX_WG_THIN = 1024;        // ... of the thin-layer weight gradients
 constexpr int THIN_STRIDE = 320;         // partial row of a thin layer (289 or 320 used)
@@ -139,7 +139,7 @@ struct ConvArgs {
 // reads and writes 8 channels of a pixel per lane in 16- and 32-byte
 // accesses instead of single 2- and 4-byte elements.
 constexpr int OS = CH + 4;                 // FP32 stride of an output pixel in LDS
-constexpr int CONV_LDS = LH * LW * PS * 2 > 4 * TW * OS * 4 ? LH * LW * PS * 2 : 4 * TW * OS * 4;
+constexpr int CONV_LDS = LH * LW * 64 > 4 * TW * OS * 4 ? LH * LW * 64 : 4 * TW * OS * 4;
 __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
 {
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[CONV_LDS];
@@ -155,7 +155,30 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         for (int nb = 0; nb < 2; ++nb)
             bw[t][nb] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(a.w + ((16 * nb + r) * 9 + t) * CH + 8 * g));
 
-    stage_halo<GC>(a.x, n, a.H, a.W, y0, x0, lds);
+    // The 6 x 66 halo tile goes straight from global memory to LDS, 16 bytes
+    // (8 channels) per lane and load: item i = (pixel i / 4, slot i % 4) fills
+    // 16-byte slot i, which holds chunk (i % 4) ^ sw(pixel) of the pixel.  The
+    // swizzle sw(p) = (p / 4) % 4 makes the 16 consecutive pixels of an
+    // A-fragment read land on 16 distinct 16-byte bank groups.  Pixels outside
+    // the image get zeros from a plain LDS store of their own slots.
+    {
+        constexpr int NV = LH * LW * 4, K = (NV + NT - 1) / NT;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i >= NV) continue;
+            const int pix = i >> 2, q = (i & 3) ^ ((pix >> 2) & 3);
+            const int rr = pix / LW, c = pix - rr * LW;
+            const int y = y0 - 1 + rr, xx = x0 - 1 + c;
+            if (y >= 0 && y < a.H && xx >= 0 && xx < a.W)
+                __builtin_amdgcn_global_load_lds((const void *)(a.x + (((long long)n * a.H + y) * a.W + xx) * CH + q * 8),
+                                                 (void __attribute__((address_space(3))) *)(lds_raw + (k * NT + (threadIdx.x & ~63)) * 16),
+                                                 16, 0, 0);
+            else
+                *(u32x4 *)(lds + i * 8) = u32x4{0u, 0u, 0u, 0u};
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     __syncthreads();
 
     f32x4 acc[4][2];
@@ -167,7 +190,8 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         const int ky = t / 3, kx = t - 3 * (t / 3);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
-            const u16 *p = lds + ((wv + ky) * LW + 16 * mb + r + kx) * PS + 8 * g;
+            const int pix = (wv + ky) * LW + 16 * mb + r + kx;
+            const u16 *p = lds + (pix * 4 + (g ^ ((pix >> 2) & 3))) * 8;
             const bf16x8 av = __builtin_bit_cast(bf16x8, *(const u32x4 *)p);
             acc[mb][0] = mfma(av, bw[t][0], acc[mb][0]);
             acc[mb][1] = mfma(av, bw[t][1], acc[mb][1]);
