@@ -33,12 +33,10 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int CH = CNN_CHANNELS;
 constexpr int TH = 4, TW = 64;           // output tile: 4 rows x 64 columns
 constexpr int LH = TH + 2, LW = TW + 2;  // input tile with a one-pixel halo
-constexpr int PS = 40;                   // LDS pixel stride in u16 (32 channels + 8 pad)
 constexpr int NT = 256;                  // threads per workgroup (4 wavefronts)
 constexpr int WMID = CH * 9 * CH;        // weights of one 32 -> 32 layer
 constexpr int PMID = WMID + CH;          // ... with its biases
 constexpr int OFF_C1 = 0, OFF_C2 = 9 * CH + CH, OFF_C6 = OFF_C2 + 4 * PMID;
-constexpr int GW = 2, GT = 2;               // staging steps whose loads are issued together (wgrad, thin wgrad)
 constexpr int MAX_WG_WGRAD = 512;        // workgroups (partials) of the MFMA weight gradient
 constexpr int MAX_WG_THIN = 1024;        // ... of the thin-layer weight gradients
 constexpr int THIN_STRIDE = 320;         // partial row of a thin layer (289 or 320 used)
@@ -64,61 +62,6 @@ __device__ __forceinline__ unsigned pack2(float a, float b)
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// Stage pixels (y0-1 .. y0+TH, x0-1 .. x0+TW) of image n (zero outside) into
-// LDS, 16 bytes (8 channels) per thread and step.  The loads of G steps are
-// issued before their LDS writes, so a tile costs ceil(steps / G) memory
-// latencies rather than one per step; G trades that against registers.
-template <int G>
-__device__ __forceinline__ void stage_halo(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
-                                          u16 *lds)
-{
-    constexpr int NV = LH * LW * 4, K = (NV + NT - 1) / NT;
-#pragma unroll
-    for (int k0 = 0; k0 < K; k0 += G) {
-        u32x4 v[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
-            const int r = pix / LW, c = pix - r * LW;
-            const int y = y0 - 1 + r, xx = x0 - 1 + c;
-            v[k] = u32x4{0u, 0u, 0u, 0u};
-            if (k0 + k < K && i < NV && y >= 0 && y < H && xx >= 0 && xx < W)
-                v[k] = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
-        }
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
-            if (k0 + k < K && i < NV) *(u32x4 *)(lds + pix * PS + q * 8) = v[k];
-        }
-    }
-}
-
-// Stage pixels (y0 .. y0+TH-1, x0 .. x0+TW-1) without halo, G steps' loads at a time as above.
-template <int G>
-__device__ __forceinline__ void stage_plain(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
-                                           u16 *lds)
-{
-    constexpr int NV = TH * TW * 4, K = NV / NT;
-    static_assert(NV % NT == 0 && K % G == 0, "whole steps");
-#pragma unroll
-    for (int k0 = 0; k0 < K; k0 += G) {
-        u32x4 v[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
-            const int r = pix / TW, c = pix - r * TW;
-            const int y = y0 + r, xx = x0 + c;
-            v[k] = u32x4{0u, 0u, 0u, 0u};
-            if (y < H && xx < W) v[k] = *(const u32x4 *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8);
-        }
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const int i = threadIdx.x + (k0 + k) * NT, pix = i >> 2, q = i & 3;
-            *(u32x4 *)(lds + pix * PS + q * 8) = v[k];
-        }
-    }
 }
 
 // ------------------------------------------------------------ 32 -> 32 layer
@@ -242,6 +185,32 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
     }
 }
 
+// Stage an image tile of ROWS x COLS pixels starting at (y0 - HALO, x0 - HALO)
+// straight from global memory into LDS: 16 bytes (8 channels) per lane and
+// load into consecutive 16-byte slots, slot i = chunk i % 4 of tile pixel
+// i / 4 (a 64-byte pixel stride); pixels outside the image get zeros from
+// plain LDS stores.  The caller waits for the loads and synchronises.
+template <int ROWS, int COLS, int HALO>
+__device__ __forceinline__ void dma_tile(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
+                                         unsigned char *lds)
+{
+    constexpr int NV = ROWS * COLS * 4, K = (NV + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i >= NV) continue;
+        const int pix = i >> 2, q = i & 3;
+        const int rr = pix / COLS, c = pix - rr * COLS;
+        const int y = y0 - HALO + rr, xx = x0 - HALO + c;
+        if (y >= 0 && y < H && xx >= 0 && xx < W)
+            __builtin_amdgcn_global_load_lds((const void *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8),
+                                             (void __attribute__((address_space(3))) *)(lds + (k * NT + (threadIdx.x & ~63)) * 16),
+                                             16, 0, 0);
+        else
+            *(u32x4 *)(lds + i * 16) = u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
 // Weight gradient, K = pixels.  Each wavefront owns one tile row (two
 // K-blocks of 32 pixels); K index 8g + e of a lane maps to pixel 4e + g of
 // the block, the same for both operands, so that the eight 2-byte LDS reads
@@ -254,8 +223,10 @@ struct WgradArgs {
 
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void wgrad3x3_mfma_kernel(WgradArgs a)
 {
-    __shared__ __attribute__((aligned(16))) u16 smem[LH * LW * PS + TH * TW * PS];
-    u16 *lx = smem, *lg = smem + LH * LW * PS;
+    constexpr int PW = 32;                 // u16 stride of a staged pixel (the slots of dma_tile)
+    __shared__ __attribute__((aligned(16))) u16 smem[LH * LW * PW + TH * TW * PW];
+    static_assert((LH * LW * PW + TH * TW * PW) * 2 >= PMID * 4, "the reduction reuses the staging space");
+    u16 *lx = smem, *lg = smem + LH * LW * PW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
     const bf16x8 ones = __builtin_bit_cast(bf16x8, u16x8{0x3f80, 0x3f80, 0x3f80, 0x3f80,
@@ -272,15 +243,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         const int n = tile / per, rem = tile - n * per;
         const int y0 = (rem / a.tx) * TH, x0 = (rem - (rem / a.tx) * a.tx) * TW;
         __syncthreads();
-        stage_halo<GW>(a.x, n, a.H, a.W, y0, x0, lx);
-        stage_plain<GW>(a.dy, n, a.H, a.W, y0, x0, lg);
+        dma_tile<LH, LW, 1>(a.x, n, a.H, a.W, y0, x0, reinterpret_cast<unsigned char *>(lx));
+        dma_tile<TH, TW, 0>(a.dy, n, a.H, a.W, y0, x0, reinterpret_cast<unsigned char *>(lg));
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
             u16x8 ga0, ga1;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const u16 *p = lg + (wv * TW + kb * 32 + 4 * e + g) * PS + r;
+                const u16 *p = lg + (wv * TW + kb * 32 + 4 * e + g) * PW + r;
                 ga0[e] = p[0];
                 ga1[e] = p[16];
             }
@@ -295,7 +267,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                     u16x8 xb;
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
-                        xb[e] = lx[((wv + ky) * LW + kb * 32 + 4 * e + g + kx) * PS + 16 * ib + r];
+                        xb[e] = lx[((wv + ky) * LW + kb * 32 + 4 * e + g + kx) * PW + 16 * ib + r];
                     const bf16x8 B = __builtin_bit_cast(bf16x8, xb);
                     acc[t][0][ib] = mfma(A0, B, acc[t][0][ib]);
                     acc[t][1][ib] = mfma(A1, B, acc[t][1][ib]);
@@ -494,7 +466,8 @@ __global__ __launch_bounds__(NT) void wgrad_thin_kernel(const float *__restrict_
                                                         float *__restrict__ part, int H, int W, int tx, int ty,
                                                         int ntiles)
 {
-    __shared__ __attribute__((aligned(16))) u16 la[(OUT ? LH * LW : TH * TW) * PS];
+    constexpr int PW = 32;                 // u16 stride of a staged pixel (the slots of dma_tile)
+    __shared__ __attribute__((aligned(16))) u16 la[(OUT ? LH * LW : TH * TW) * PW];
     __shared__ float li[OUT ? TH * TW : LH * LW];
     constexpr int NOUT = OUT ? 9 * CH + 1 : 9 * CH + CH;
     float acc0 = 0.f, acc1 = 0.f;
@@ -505,18 +478,19 @@ __global__ __launch_bounds__(NT) void wgrad_thin_kernel(const float *__restrict_
         const int y0 = (rem / tx) * TH, x0 = (rem - (rem / tx) * tx) * TW;
         __syncthreads();
         if (OUT) {
-            stage_halo<GT>(act, n, H, W, y0, x0, la);
+            dma_tile<LH, LW, 1>(act, n, H, W, y0, x0, reinterpret_cast<unsigned char *>(la));
             for (int i = threadIdx.x; i < TH * TW; i += NT) {
                 const int y = y0 + i / TW, x = x0 + i % TW;
                 li[i] = (y < H && x < W) ? img[((long long)n * H + y) * W + x] : 0.f;
             }
         } else {
-            stage_plain<GT>(act, n, H, W, y0, x0, la);
+            dma_tile<TH, TW, 0>(act, n, H, W, y0, x0, reinterpret_cast<unsigned char *>(la));
             for (int i = threadIdx.x; i < LH * LW; i += NT) {
                 const int y = y0 - 1 + i / LW, x = x0 - 1 + i % LW;
                 li[i] = (y >= 0 && y < H && x >= 0 && x < W) ? img[((long long)n * H + y) * W + x] : 0.f;
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);     // this thread's direct loads have landed in LDS
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -528,7 +502,7 @@ __global__ __launch_bounds__(NT) void wgrad_thin_kernel(const float *__restrict_
                     const int t = o / CH, ci = o % CH, ky = t / 3, kx = t % 3;
                     for (int r = 0; r < TH; ++r)
                         for (int c = 0; c < TW; ++c)
-                            s = fmaf(li[r * TW + c], bf2f(la[((r + ky) * LW + c + kx) * PS + ci]), s);
+                            s = fmaf(li[r * TW + c], bf2f(la[((r + ky) * LW + c + kx) * PW + ci]), s);
                 } else {
                     for (int i = 0; i < TH * TW; ++i) s += li[i];
                 }
@@ -537,10 +511,10 @@ __global__ __launch_bounds__(NT) void wgrad_thin_kernel(const float *__restrict_
                     const int co = o / 9, t = o % 9, ky = t / 3, kx = t % 3;
                     for (int r = 0; r < TH; ++r)
                         for (int c = 0; c < TW; ++c)
-                            s = fmaf(bf2f(la[(r * TW + c) * PS + co]), li[(r + ky) * LW + c + kx], s);
+                            s = fmaf(bf2f(la[(r * TW + c) * PW + co]), li[(r + ky) * LW + c + kx], s);
                 } else {
                     const int co = o - 9 * CH;
-                    for (int i = 0; i < TH * TW; ++i) s += bf2f(la[i * PS + co]);
+                    for (int i = 0; i < TH * TW; ++i) s += bf2f(la[i * PW + co]);
                 }
             }
             if (q) acc1 += s; else acc0 += s;
