@@ -64,6 +64,35 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// The 6 x 66 halo tile (pixels y0-1 .. y0+4, x0-1 .. x0+64 of image n) straight
+// from global memory into LDS, 16 bytes (8 channels) per lane and load: item
+// i = (pixel i / 4, slot i % 4) fills 16-byte slot i, which holds chunk
+// (i % 4) ^ sw(pixel) of the pixel.  The swizzle sw(p) = (p / 4) % 4 puts the
+// same chunk of 16 consecutive pixels on 16 distinct 16-byte bank groups.
+// Pixels outside the image get zeros from a plain LDS store of their slots.
+// The caller waits for the loads and synchronises.
+__device__ __forceinline__ int halo_slot(int pix, int q) { return pix * 4 + (q ^ ((pix >> 2) & 3)); }
+
+__device__ __forceinline__ void dma_halo_swizzled(const u16 *__restrict__ x, int n, int H, int W, int y0, int x0,
+                                                  unsigned char *lds)
+{
+    constexpr int NV = LH * LW * 4, K = (NV + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i >= NV) continue;
+        const int pix = i >> 2, q = (i & 3) ^ ((pix >> 2) & 3);
+        const int rr = pix / LW, c = pix - rr * LW;
+        const int y = y0 - 1 + rr, xx = x0 - 1 + c;
+        if (y >= 0 && y < H && xx >= 0 && xx < W)
+            __builtin_amdgcn_global_load_lds((const void *)(x + (((long long)n * H + y) * W + xx) * CH + q * 8),
+                                             (void __attribute__((address_space(3))) *)(lds + (k * NT + (threadIdx.x & ~63)) * 16),
+                                             16, 0, 0);
+        else
+            *(u32x4 *)(lds + i * 16) = u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
 // ------------------------------------------------------------ 32 -> 32 layer
 struct ConvArgs {
     const u16 *x, *w;
@@ -98,30 +127,8 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         for (int nb = 0; nb < 2; ++nb)
             bw[t][nb] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(a.w + ((16 * nb + r) * 9 + t) * CH + 8 * g));
 
-    // The 6 x 66 halo tile goes straight from global memory to LDS, 16 bytes
-    // (8 channels) per lane and load: item i = (pixel i / 4, slot i % 4) fills
-    // 16-byte slot i, which holds chunk (i % 4) ^ sw(pixel) of the pixel.  The
-    // swizzle sw(p) = (p / 4) % 4 makes the 16 consecutive pixels of an
-    // A-fragment read land on 16 distinct 16-byte bank groups.  Pixels outside
-    // the image get zeros from a plain LDS store of their own slots.
-    {
-        constexpr int NV = LH * LW * 4, K = (NV + NT - 1) / NT;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * NT;
-            if (i >= NV) continue;
-            const int pix = i >> 2, q = (i & 3) ^ ((pix >> 2) & 3);
-            const int rr = pix / LW, c = pix - rr * LW;
-            const int y = y0 - 1 + rr, xx = x0 - 1 + c;
-            if (y >= 0 && y < a.H && xx >= 0 && xx < a.W)
-                __builtin_amdgcn_global_load_lds((const void *)(a.x + (((long long)n * a.H + y) * a.W + xx) * CH + q * 8),
-                                                 (void __attribute__((address_space(3))) *)(lds_raw + (k * NT + (threadIdx.x & ~63)) * 16),
-                                                 16, 0, 0);
-            else
-                *(u32x4 *)(lds + i * 8) = u32x4{0u, 0u, 0u, 0u};
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-    }
+    dma_halo_swizzled(a.x, n, a.H, a.W, y0, x0, lds_raw);
+    __builtin_amdgcn_s_waitcnt(0);         // this thread's direct loads have landed in LDS
     __syncthreads();
 
     f32x4 acc[4][2];
@@ -133,8 +140,7 @@ __global__ __launch_bounds__(NT) void conv3x3_mfma_kernel(ConvArgs a)
         const int ky = t / 3, kx = t - 3 * (t / 3);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
-            const int pix = (wv + ky) * LW + 16 * mb + r + kx;
-            const u16 *p = lds + (pix * 4 + (g ^ ((pix >> 2) & 3))) * 8;
+            const u16 *p = lds + halo_slot((wv + ky) * LW + 16 * mb + r + kx, g) * 8;
             const bf16x8 av = __builtin_bit_cast(bf16x8, *(const u32x4 *)p);
             acc[mb][0] = mfma(av, bw[t][0], acc[mb][0]);
             acc[mb][1] = mfma(av, bw[t][1], acc[mb][1]);
@@ -395,24 +401,30 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float *__restrict__ 
 }
 
 // c6 and the global residual: p = -g + b + sum_t sum_ci w[t][ci] x3[pix + off_t][ci].
-__global__ __launch_bounds__(256) void conv_out_kernel(const u16 *__restrict__ x3, const float *__restrict__ g,
-                                                       const float *__restrict__ params, float *__restrict__ p,
-                                                       int N, int H, int W)
+// On the 4 x 64 tiles of the 32 -> 32 layers, x3 with its halo staged in LDS
+// as for those layers; one thread per pixel, the sum in tap, channel order.
+__global__ __launch_bounds__(NT) void conv_out_kernel(const u16 *__restrict__ x3, const float *__restrict__ g,
+                                                      const float *__restrict__ params, float *__restrict__ p,
+                                                      int N, int H, int W)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)N * H * W) return;
-    int n, y, x;
-    pixel_of(i, H, W, n, y, x);
+    __shared__ __attribute__((aligned(16))) unsigned char lds[LH * LW * 64];
+    const int n = blockIdx.z, y0 = blockIdx.y * TH, x0 = blockIdx.x * TW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    dma_halo_swizzled(x3, n, H, W, y0, x0, lds);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int y = y0 + wv, x = x0 + lane;
+    if (y >= H || x >= W) return;
     const float *w = params + OFF_C6;
     float s = params[OFF_C6 + 9 * CH];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
         if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-        const u32x4 *src = (const u32x4 *)(x3 + (((long long)n * H + yy) * W + xx) * CH);
+        const int pix = (wv + t / 3) * LW + lane + t % 3;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const u32x4 u = src[q];
+            const u32x4 u = *(const u32x4 *)(lds + halo_slot(pix, q) * 16);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 s = fmaf(w[t * CH + 8 * q + 2 * e], __uint_as_float(u[e] << 16), s);
@@ -420,6 +432,7 @@ __global__ __launch_bounds__(256) void conv_out_kernel(const u16 *__restrict__ x
             }
         }
     }
+    const long long i = ((long long)n * H + y) * W + x;
     p[i] = s - g[i];
 }
 
@@ -777,7 +790,7 @@ int cnn_forward(const float *params, const float *g, int32_t n, int32_t h, int32
     if (int e = launch_conv(a2, n, h, w, wf + 1 * WMID, bias + 1 * PMID, x1, nullptr, 1, x2, nullptr, s)) return e;
     if (int e = launch_conv(x2, n, h, w, wf + 2 * WMID, bias + 2 * PMID, nullptr, nullptr, 1, a4, nullptr, s)) return e;
     if (int e = launch_conv(a4, n, h, w, wf + 3 * WMID, bias + 3 * PMID, x2, nullptr, 1, x3, nullptr, s)) return e;
-    conv_out_kernel<<<blocks(pix), 256, 0, s>>>(x3, g, params, p, n, h, w);
+    conv_out_kernel<<<dim3((w + TW - 1) / TW, (h + TH - 1) / TH, n), NT, 0, s>>>(x3, g, params, p, n, h, w);
     HIPCHECK(hipGetLastError());
     return SG_OK;
 }
