@@ -370,34 +370,53 @@ __device__ __forceinline__ void pixel_of(long long p, int H, int W, int &n, int 
 }
 
 // c1: x1 = relu(b + sum_t w[co][t] g[pix + off_t]) in FP32, stored BF16.
-__global__ __launch_bounds__(256) void conv_in_kernel(const float *__restrict__ g, const float *__restrict__ params,
-                                                      u16 *__restrict__ x1, int N, int H, int W)
+// The thin layers c1 and c6's input gradient work on runs of NT consecutive
+// pixels (flat n, y, x order), whose 32 channels are NT x 64 contiguous
+// bytes: a thread computes one pixel (the weights are then the same for every
+// lane), and the 64-byte pixels pass through LDS in the swizzled slots of
+// halo_slot, so that global memory sees whole 1 KiB runs per instruction.
+__device__ __forceinline__ void store_pixels(const unsigned char *lds, long long p0, long long total, u16 *dst)
 {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (long long)N * H * W) return;
-    int n, y, x;
-    pixel_of(p, H, W, n, y, x);
-    float v[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        v[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? g[((long long)n * H + yy) * W + xx] : 0.f;
+    for (int k = 0; k < 4; ++k) {
+        const int j = threadIdx.x + k * NT, pix = j >> 2, q = j & 3;
+        if (p0 + pix < total)
+            *(u32x4 *)(dst + (p0 + pix) * CH + q * 8) = *(const u32x4 *)(lds + halo_slot(pix, q) * 16);
     }
-    const float *w = params + OFF_C1, *b = params + OFF_C1 + 9 * CH;
-    u32x4 *out = (u32x4 *)(x1 + p * CH);
+}
+
+__global__ __launch_bounds__(NT) void conv_in_kernel(const float *__restrict__ g, const float *__restrict__ params,
+                                                     u16 *__restrict__ x1, int N, int H, int W)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char lds[NT * 64];
+    const long long total = (long long)N * H * W, p0 = (long long)blockIdx.x * NT, p = p0 + threadIdx.x;
+    if (p < total) {
+        int n, y, x;
+        pixel_of(p, H, W, n, y, x);
+        float v[9];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float o[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int co = 8 * q + e;
-            float s = b[co];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) s = fmaf(w[co * 9 + t], v[t], s);
-            o[e] = fmaxf(s, 0.f);
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            v[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? g[((long long)n * H + yy) * W + xx] : 0.f;
         }
-        out[q] = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+        const float *w = params + OFF_C1, *b = params + OFF_C1 + 9 * CH;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float o[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int co = 8 * q + e;
+                float s = b[co];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) s = fmaf(w[co * 9 + t], v[t], s);
+                o[e] = fmaxf(s, 0.f);
+            }
+            *(u32x4 *)(lds + halo_slot(threadIdx.x, q) * 16) =
+                u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+        }
     }
+    __syncthreads();
+    store_pixels(lds, p0, total, x1);
 }
 
 // c6 and the global residual: p = -g + b + sum_t sum_ci w[t][ci] x3[pix + off_t][ci].
@@ -437,36 +456,52 @@ __global__ __launch_bounds__(NT) void conv_out_kernel(const u16 *__restrict__ x3
 }
 
 // Input gradient of c6 gated by x3 > 0: G[pix][ci] = [x3 > 0] sum_t w[t][ci] dp[pix - off_t].
-__global__ __launch_bounds__(256) void dgrad_out_kernel(const float *__restrict__ dp, const u16 *__restrict__ x3,
-                                                        const float *__restrict__ params, u16 *__restrict__ G,
-                                                        int N, int H, int W)
+__global__ __launch_bounds__(NT) void dgrad_out_kernel(const float *__restrict__ dp, const u16 *__restrict__ x3,
+                                                       const float *__restrict__ params, u16 *__restrict__ G,
+                                                       int N, int H, int W)
 {
-    // four threads per pixel (channels 8q .. 8q+7), whole-pixel 1 KiB
-    // accesses per wavefront instruction
-    const long long tq = (long long)blockIdx.x * blockDim.x + threadIdx.x, i = tq >> 2;
-    const int q = (int)(tq & 3);
-    if (i >= (long long)N * H * W) return;
-    int n, y, x;
-    pixel_of(i, H, W, n, y, x);
-    float d[9];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[NT * 64];
+    const long long total = (long long)N * H * W, p0 = (long long)blockIdx.x * NT, p = p0 + threadIdx.x;
+    // the gates x3 of the run, straight into the swizzled slots (16 bytes per lane and load)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
-        d[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? dp[((long long)n * H + yy) * W + xx] : 0.f;
+    for (int k = 0; k < 4; ++k) {
+        const int j = threadIdx.x + k * NT, pix = j >> 2, q = (j & 3) ^ ((pix >> 2) & 3);
+        if (p0 + pix < total)
+            __builtin_amdgcn_global_load_lds((const void *)(x3 + (p0 + pix) * CH + q * 8),
+                                             (void __attribute__((address_space(3))) *)(lds + (k * NT + (threadIdx.x & ~63)) * 16),
+                                             16, 0, 0);
     }
-    const float *w = params + OFF_C6;
-    const u32x4 gt = *(const u32x4 *)(x3 + i * CH + 8 * q);
-    float o[8];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (p < total) {
+        int n, y, x;
+        pixel_of(p, H, W, n, y, x);
+        float d[9];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int ci = 8 * q + e;
-        float s = 0.f;
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+            d[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? dp[((long long)n * H + yy) * W + xx] : 0.f;
+        }
+        const float *w = params + OFF_C6;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) s = fmaf(w[t * CH + ci], d[t], s);
-        const unsigned gv = (e & 1) ? (gt[e >> 1] & 0xffff0000u) : (gt[e >> 1] << 16);
-        o[e] = __uint_as_float(gv) > 0.f ? s : 0.f;
+        for (int q = 0; q < 4; ++q) {
+            u32x4 *slot = (u32x4 *)(lds + halo_slot(threadIdx.x, q) * 16);
+            const u32x4 gt = *slot;
+            float o[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int ci = 8 * q + e;
+                float s = 0.f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) s = fmaf(w[t * CH + ci], d[t], s);
+                const unsigned gv = (e & 1) ? (gt[e >> 1] & 0xffff0000u) : (gt[e >> 1] << 16);
+                o[e] = __uint_as_float(gv) > 0.f ? s : 0.f;
+            }
+            *slot = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+        }
     }
-    *(u32x4 *)(G + i * CH + 8 * q) = u32x4{pack2(o[0], o[1]), pack2(o[2], o[3]), pack2(o[4], o[5]), pack2(o[6], o[7])};
+    __syncthreads();
+    store_pixels(lds, p0, total, G);
 }
 
 // Weight gradients of the thin layers, on the 4 x 64 pixel tiles of the
@@ -783,7 +818,7 @@ int cnn_forward(const float *params, const float *g, int32_t n, int32_t h, int32
     const long long pix = (long long)n * h * w;
     prep_weights_kernel<<<blocks(4 * WMID), 256, 0, s>>>(params, wf, wt);
     HIPCHECK(hipGetLastError());
-    conv_in_kernel<<<blocks(pix), 256, 0, s>>>(g, params, x1, n, h, w);
+    conv_in_kernel<<<blocks(pix, NT), NT, 0, s>>>(g, params, x1, n, h, w);
     HIPCHECK(hipGetLastError());
     const float *bias = params + OFF_C2 + WMID;
     if (int e = launch_conv(x1, n, h, w, wf + 0 * WMID, bias + 0 * PMID, nullptr, nullptr, 1, a2, nullptr, s)) return e;
@@ -813,7 +848,7 @@ int cnn_backward(const float *params, const float *g, const float *dp, int32_t n
     const long long pix = (long long)n * h * w;
 
     if (int e = launch_wgrad_thin<true>(dp, x3, n, h, w, part, grad + OFF_C6, s)) return e;
-    dgrad_out_kernel<<<blocks(4 * pix), 256, 0, s>>>(dp, x3, params, G0, n, h, w);           // G0 = d pre(x3)
+    dgrad_out_kernel<<<blocks(pix, NT), NT, 0, s>>>(dp, x3, params, G0, n, h, w);           // G0 = d pre(x3)
     HIPCHECK(hipGetLastError());
     float *gm = grad + OFF_C2;
     if (int e = launch_wgrad(G0, a4, n, h, w, part, gm + 3 * PMID, s)) return e;
