@@ -4,13 +4,15 @@
 // The 32 -> 32 channel 3x3 layers are implicit GEMMs on the matrix cores:
 // v_mfma_f32_16x16x32_bf16 with one 3x3 tap (32 input channels) per
 // K-block.  A workgroup of four wavefronts computes a 4 x 64 output tile,
-// one row per wavefront; the 6 x 66 input tile (one-pixel zero halo) is
-// staged once in LDS with an 80-byte pixel stride, which makes the 16-byte
-// fragment reads of 16 consecutive pixels bank-conflict free.  The weight
-// gradient uses the pixels as the K dimension and reduces per workgroup,
-// then over workgroups in a fixed order.  The thin layers c1 (1 -> 32) and
-// c6 (32 -> 1) are per-pixel FP32 kernels: as GEMMs they would have K = 9 or
-// N = 1, which matrix cores cannot fill.
+// one row per wavefront; the 6 x 66 input tile (one-pixel zero halo) goes
+// straight from global memory into LDS (direct 16-byte loads) in swizzled
+// slots, which makes the 16-byte fragment reads of 16 consecutive pixels
+// bank-conflict free.  The weight gradient uses the pixels as the K
+// dimension and reduces per workgroup, then over workgroups in a fixed
+// order.  The thin layers c1 (1 -> 32) and c6 (32 -> 1) are per-pixel FP32
+// kernels: as GEMMs they would have K = 9 or N = 1, which matrix cores
+// cannot fill.  Every reduction has a fixed order, so results are bitwise
+// reproducible from call to call.
 #include "../../include/seisgrad.h"
 #include "../../include/sg_cnn.h"
 #include "sg_error.h"
