@@ -387,6 +387,27 @@ __device__ __forceinline__ void load_tile8(const Grid2 &g, const float *u, const
     }
 }
 
+// The same tile + 8 of u (no factor) straight from global memory into LDS:
+// 16 bytes per lane and load, item q into the 16-byte slot q (the LDS rows
+// of W0 floats have no padding, so item order is slot order).  Every cell
+// lies inside the zero frame.  The caller waits for the loads
+// (s_waitcnt) before the barrier that publishes the tile.
+template <int NT>
+__device__ __forceinline__ void dma_tile8(const Grid2 &g, const float *u, float *lds, int x0, int z0)
+{
+    constexpr int Q = W0 / 4, N4 = R0 * Q;
+#pragma unroll
+    for (int it = 0; it < (N4 + NT - 1) / NT; ++it) {
+        const int q = threadIdx.x + it * NT;
+        if (q < N4) {
+            const int r = q / Q, c = (q - r * Q) * 4;
+            __builtin_amdgcn_global_load_lds((const void *)(u + fidx(g, z0 - H2 + r, x0 - H2 + c)),
+                                             (void __attribute__((address_space(3))) *)(lds + (it * NT + (threadIdx.x & ~63)) * 4),
+                                             16, 0, 0);
+        }
+    }
+}
+
 // Cell i of the ring (rows 0-3 and 36-39 of the tile + 4, then columns 0-3
 // and 68-71 of rows 4-35), as (row, column) of the tile + 4.
 __device__ __forceinline__ void ring_cell(int i, int &r, int &c)
@@ -439,7 +460,8 @@ __device__ __forceinline__ void fwd2_tile(const Ac2Fwd2Args &a, float *s0, float
             rpm[it] = um[rf[it]];
         }
     }
-    load_tile8<NTB>(g, a.u0 + so, nullptr, s0, x0, z0);
+    dma_tile8<NTB>(g, a.u0 + so, s0, x0, z0);
+    __builtin_amdgcn_s_waitcnt(0);       // the tile's direct loads have landed in LDS
     __syncthreads();
 
     // step k: u^{k+1} on the tile + 4 (own cells, then the ring)
@@ -489,7 +511,7 @@ __device__ __forceinline__ void fwd2_tile(const Ac2Fwd2Args &a, float *s0, float
 
 __global__ __launch_bounds__(NTB) void ac2_fwd2_kernel(Ac2Fwd2Args a)
 {
-    __shared__ float s0[R0 * W0];
+    __shared__ __attribute__((aligned(16))) float s0[R0 * W0];
     __shared__ float s1[R1 * W1];
     const int w = xcd_work_id(a.ntl * a.nshots);
     const int shot = w / a.ntl, tile = a.tiles[w - shot * a.ntl];
@@ -690,9 +712,10 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
             zf[it] = phz0[fidx(g, iz, jx)];
         }
     }
-    load_tile8<NTN>(g, a.u + so, nullptr, su, x0, z0);      // u^k on the tile + 8
+    dma_tile8<NTN>(g, a.u + so, su, x0, z0);               // u^k on the tile + 8
     const long long src = a.src_f[shot];
     const float sval = src_value(a.src_scale, a.wav[(long long)shot * a.nt + a.k]);
+    __builtin_amdgcn_s_waitcnt(0);       // the tile's direct loads have landed in LDS
     __syncthreads();
 
     // pass A: phi~^k on the own layer cells (written out) and the halo cells
@@ -792,7 +815,7 @@ __device__ __forceinline__ void fwd_near_tile(const Ac2FwdArgs &a, float *su, fl
 template <bool SNAP, bool REC>
 __global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(8))) void ac2_near_kernel(Ac2FwdArgs a)
 {
-    __shared__ float su[NU];
+    __shared__ __attribute__((aligned(16))) float su[NU];
     __shared__ float sx[TZ * WPX];
     __shared__ float sz[RPZ * TX];
     const int w = xcd_work_id(a.ntl * a.nshots);
@@ -813,7 +836,7 @@ template <bool SNAP, bool REC>
 __global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(8)))
 void ac2_fwd_pair_kernel(Ac2FwdArgs a, Ac2Fwd2Args b)
 {
-    __shared__ float lds[NPAIR_LDS];
+    __shared__ __attribute__((aligned(16))) float lds[NPAIR_LDS];
     const int nb = b.ntl * b.nshots;
     int w = xcd_work_id(nb + a.ntl * a.nshots);
     if (w < nb) {
