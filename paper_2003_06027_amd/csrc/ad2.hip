@@ -149,9 +149,21 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     const float *ch = a.chat + (long long)(shot / a.shots_per_model) * g.plane;
     const int tid = threadIdx.x, lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX), r0 = ly * RPA, ix = x0 + lx;
 
-    for (int i = tid; i < AR * AW; i += NTA) {
-        const int r = i / AW, c = i - r * AW;
-        su[i] = u[fr(g, z0 - AH + r, x0 - AH + c)];
+    // u^k on the tile + 3 straight from global memory into LDS: 4 bytes per
+    // lane and load into consecutive LDS words (item order is the row-major
+    // order of su); every cell lies inside the zero frame
+    {
+        constexpr int NV = AR * AW, K = (NV + NTA - 1) / NTA;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = tid + k * NTA;
+            if (i < NV) {
+                const int r = i / AW, c = i - r * AW;
+                __builtin_amdgcn_global_load_lds((const void *)(u + fr(g, z0 - AH + r, x0 - AH + c)),
+                                                 (void __attribute__((address_space(3))) *)(su + k * NTA + (tid & ~63)),
+                                                 4, 0, 0);
+            }
+        }
     }
     float cz[RPA + 4];                    // chat of rows z0+r0-2 .. z0+r0+RPA+1
 #pragma unroll
@@ -159,6 +171,7 @@ __device__ __forceinline__ void fwd_tile(const Ad2FwdArgs &a, float *su, float *
     float um[RPA];                        // u^{k-1} of the own rows, loaded early
 #pragma unroll
     for (int j = 0; j < RPA; ++j) um[j] = __builtin_nontemporal_load(a.um + so + fr(g, z0 + r0 + j, ix));
+    __builtin_amdgcn_s_waitcnt(0);       // the tile's direct loads have landed in LDS
     __syncthreads();
 
     // z fluxes of the own column at half rows z0+r0-2+m, m = 0 .. RPA+2
@@ -317,7 +330,23 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
     const int tid = threadIdx.x, lx = tid % TX, ly = __builtin_amdgcn_readfirstlane(tid / TX), r0 = ly * RPA, ix = x0 + lx;
 
     // Hb = lambda^{k+1} + Y^{k+1} per axis on the tile and its halo
-    for (int i = tid; i < AR * AW; i += NTA) {
+    if constexpr (!NEAR) {
+        // away from the layer the x and z arrays are both lambda^{k+1} itself:
+        // straight from global memory into LDS (4 bytes per lane and load,
+        // item order = the row-major order of hx; every cell inside the frame)
+        constexpr int NV = AR * AW, K = (NV + NTA - 1) / NTA;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = tid + k * NTA;
+            if (i < NV) {
+                const int r = i / AW, c = i - r * AW;
+                __builtin_amdgcn_global_load_lds((const void *)(l1 + fr(g, z0 - AH + r, x0 - AH + c)),
+                                                 (void __attribute__((address_space(3))) *)(hx + k * NTA + (tid & ~63)),
+                                                 4, 0, 0);
+            }
+        }
+    }
+    for (int i = tid; NEAR && i < AR * AW; i += NTA) {
         const int r = i / AW, c = i - r * AW;
         const int iz = z0 - AH + r, jx = x0 - AH + c;
         const long long f = fr(g, iz, jx);
@@ -336,8 +365,6 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             }
             hx[i] = bx;
             hz[i] = bz;
-        } else {
-            hx[i] = l;
         }
     }
     float cz[RPA + 4];
@@ -354,6 +381,7 @@ __device__ __forceinline__ void adj_tile(const Ad2AdjArgs &a, float *hx, float *
             gacc[j] = iz < g.NZ && ix < g.NX ? __builtin_nontemporal_load(a.gn + so + fr(g, iz, ix)) : 0.f;
         }
     }
+    if constexpr (!NEAR) __builtin_amdgcn_s_waitcnt(0);   // the tile's direct loads have landed in LDS
     __syncthreads();
     const float *hzz = NEAR ? hz : hx;
 
