@@ -362,32 +362,8 @@ constexpr int RB = TZ * TX / NTB;
 constexpr int RING_ITB = (NRING + NTB - 1) / NTB;
 static_assert(RB * NTB == TZ * TX && NTB % TX == 0, "whole rows per thread");
 
-// Load the tile + 8 of a field into LDS with 16-byte loads (rows start
-// 32-byte aligned: x0 - 8 + OX is a multiple of 8), optionally multiplied
-// cell by cell by a second field.
-template <int NT = NTH>
-__device__ __forceinline__ void load_tile8(const Grid2 &g, const float *u, const float *mul, float *lds,
-                                           int x0, int z0)
-{
-    constexpr int Q = W0 / 4, N4 = R0 * Q;
-#pragma unroll
-    for (int it = 0; it < (N4 + NT - 1) / NT; ++it) {
-        const int q = threadIdx.x + it * NT;
-        if (q < N4) {
-            const int r = q / Q, c = (q - r * Q) * 4;
-            const long long f = fidx(g, z0 - H2 + r, x0 - H2 + c);
-            float4 v = *reinterpret_cast<const float4 *>(u + f);
-            if (mul) {
-                const float4 m = *reinterpret_cast<const float4 *>(mul + f);
-                v.x = m.x * v.x; v.y = m.y * v.y; v.z = m.z * v.z; v.w = m.w * v.w;
-            }
-            float *d = lds + r * W0 + c;
-            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-        }
-    }
-}
-
-// The same tile + 8 of u (no factor) straight from global memory into LDS:
+// The tile + 8 of a field (rows start 32-byte aligned: x0 - 8 + OX is a
+// multiple of 8) straight from global memory into LDS:
 // 16 bytes per lane and load, item q into the 16-byte slot q (the LDS rows
 // of W0 floats have no padding, so item order is slot order).  Every cell
 // lies inside the zero frame.  The caller waits for the loads
@@ -404,6 +380,45 @@ __device__ __forceinline__ void dma_tile8(const Grid2 &g, const float *u, float 
             __builtin_amdgcn_global_load_lds((const void *)(u + fidx(g, z0 - H2 + r, x0 - H2 + c)),
                                              (void __attribute__((address_space(3))) *)(lds + (it * NT + (threadIdx.x & ~63)) * 4),
                                              16, 0, 0);
+        }
+    }
+}
+
+// The product chat * s on the tile + 8 in two phases: dma_product_load puts
+// s straight into LDS (as dma_tile8) and chat of the same 16-byte items into
+// registers; after the caller's wait and barrier, product_in_place multiplies
+// each thread's items in LDS (one FP32 product per cell, chat times s).  The
+// caller synchronises again before the tile is read.
+template <int NT>
+__device__ __forceinline__ void dma_product_load(const Grid2 &g, const float *s, const float *mul, float *lds,
+                                                 int x0, int z0, float4 (&m)[(R0 * (W0 / 4) + NT - 1) / NT])
+{
+    constexpr int Q = W0 / 4, N4 = R0 * Q;
+#pragma unroll
+    for (int it = 0; it < (N4 + NT - 1) / NT; ++it) {
+        const int q = threadIdx.x + it * NT;
+        if (q < N4) {
+            const int r = q / Q, c = (q - r * Q) * 4;
+            const long long f = fidx(g, z0 - H2 + r, x0 - H2 + c);
+            __builtin_amdgcn_global_load_lds((const void *)(s + f),
+                                             (void __attribute__((address_space(3))) *)(lds + (it * NT + (threadIdx.x & ~63)) * 4),
+                                             16, 0, 0);
+            m[it] = *reinterpret_cast<const float4 *>(mul + f);
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void product_in_place(float *lds, const float4 (&m)[(R0 * (W0 / 4) + NT - 1) / NT])
+{
+    constexpr int N4 = R0 * (W0 / 4);
+#pragma unroll
+    for (int it = 0; it < (N4 + NT - 1) / NT; ++it) {
+        const int q = threadIdx.x + it * NT;
+        if (q < N4) {
+            float4 v = *reinterpret_cast<const float4 *>(lds + 4 * q);
+            v.x = m[it].x * v.x; v.y = m[it].y * v.y; v.z = m[it].z * v.z; v.w = m[it].w * v.w;
+            *reinterpret_cast<float4 *>(lds + 4 * q) = v;
         }
     }
 }
@@ -524,7 +539,7 @@ __global__ __launch_bounds__(NTB) void ac2_fwd2_kernel(Ac2Fwd2Args a)
 // single steps.
 __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
 {
-    __shared__ float p0[R0 * W0];   // chat s^{k+2} on the tile + 8
+    __shared__ __attribute__((aligned(16))) float p0[R0 * W0];   // chat s^{k+2} on the tile + 8
     __shared__ float p1[R1 * W1];   // chat s^{k+1} on the tile + 4
     const Grid2 &g = a.g;
     const int w = xcd_work_id(a.ntl * a.nshots);
@@ -561,7 +576,11 @@ __global__ __launch_bounds__(NTH) void ac2_adj2_kernel(Ac2Adj2Args a)
             rq3[it] = s3[f];
         }
     }
-    load_tile8(g, s2, chat, p0, x0, z0);
+    float4 cm[(R0 * (W0 / 4) + NTH - 1) / NTH];
+    dma_product_load<NTH>(g, s2, chat, p0, x0, z0, cm);
+    __builtin_amdgcn_s_waitcnt(0);       // the tile's direct loads have landed in LDS
+    __syncthreads();
+    product_in_place<NTH>(p0, cm);
     __syncthreads();
 
     // step k: s^{k+1} on the tile + 4
@@ -920,7 +939,11 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
             zf[it] = cz0[fidx(g, iz, jx)];
         }
     }
-    load_tile8<NTN>(g, s2, chat, sc, x0, z0);      // chat s^{k+2} on the tile + 8
+    float4 cm[(R0 * (W0 / 4) + NTN - 1) / NTN];
+    dma_product_load<NTN>(g, s2, chat, sc, x0, z0, cm);     // chat s^{k+2} on the tile + 8
+    __builtin_amdgcn_s_waitcnt(0);       // the tile's direct loads have landed in LDS
+    __syncthreads();
+    product_in_place<NTN>(sc, cm);
     __syncthreads();
 
     // pass A: c^{k+1} on the own layer cells (written out) and the halo cells
@@ -1035,7 +1058,7 @@ __device__ __forceinline__ void adj_near_tile(const Ac2AdjArgs &a, float *sc, fl
 
 __global__ __launch_bounds__(NTN) __attribute__((amdgpu_waves_per_eu(6))) void ac2_adj_near_kernel(Ac2AdjArgs a)
 {
-    __shared__ float sc[NU];
+    __shared__ __attribute__((aligned(16))) float sc[NU];
     __shared__ float sx[TZ * WPX];
     __shared__ float sz[RPZ * TX];
     const int w = xcd_work_id(a.ntl * a.nshots);
